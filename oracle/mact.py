@@ -1,0 +1,109 @@
+"""FP64 evaluation of the MACT transforms (oracle; test infrastructure only).
+
+These are the transforms of Sec. 3.2-3.4 with the costly elementary functions
+replaced by the minimax approximations whose coefficients are passed in.  The
+steps are the paper's, in its order; the arithmetic is float64 throughout, so
+a GPU evaluating the same approximation in float32 differs from these values
+by float32 rounding only (the caller rounds the coefficients to float32 and
+passes them here promoted to float64 when it wants exactly the GPU's
+approximation).
+
+Inputs are (..., 3) arrays of R, G, B on the normalised scale [0, 1]; float
+inputs outside [0, 1] are clamped to it first (the approximations are fitted
+on the image of [0, 1] only).
+"""
+import numpy as np
+
+from . import colour
+
+
+def horner(c, x):
+    """Polynomial sum_k c[k] x^k by Horner's rule, float64."""
+    x = np.asarray(x, dtype=np.float64)
+    c = [float(v) for v in c]
+    acc = np.full_like(x, c[-1])
+    for a in reversed(c[:-1]):
+        acc = acc * x + a
+    return acc
+
+
+def clamp01(rgb):
+    return np.clip(np.asarray(rgb, dtype=np.float64), 0.0, 1.0)
+
+
+def mact_lab_f(t, p, q):
+    """The approximated CIELAB nonlinearity: p(t)/q(t) above 0.008856 (the
+    minimax rational standing in for the cube root, Sec. 3.2.2), the exact
+    linear segment at or below it."""
+    t = np.asarray(t, dtype=np.float64)
+    hi = t > colour.LAB_T0
+    ts = np.where(hi, t, 0.5)  # keep q away from any root on the unused branch
+    return np.where(hi, horner(p, ts) / horner(q, ts), colour.LAB_K * t + colour.LAB_C)
+
+
+def mact_lab(rgb, p, q, gamma="bt709", debug=False):
+    """RGB -> CIELAB with the cube root replaced by p/q (Sec. 3.2).
+
+    Steps: inverse gamma (BT.709 by default), RGB -> XYZ, divide by the D65
+    white, approximated f, then L*, a*, b*.  With ``debug`` the three values
+    f~(X/X0), f~(Y/Y0), f~(Z/Z0) are returned instead of L*a*b*.
+    """
+    t = colour.lab_t(clamp01(rgb), gamma)
+    f = mact_lab_f(t, p, q)
+    if debug:
+        return f
+    fx, fy, fz = f[..., 0], f[..., 1], f[..., 2]
+    return np.stack([116.0 * fy - 16.0, 500.0 * (fx - fy), 200.0 * (fy - fz)], axis=-1)
+
+
+def odd_poly(c, x):
+    """P approximates an odd function on [0, 1]; negative arguments use
+    arctan(-x) = -arctan(x) (Sec. 3.3.2): -P(-x) for x < 0, P(x) otherwise."""
+    x = np.asarray(x, dtype=np.float64)
+    v = horner(c, np.abs(x))
+    return np.where(x < 0, -v, v)
+
+
+def mact_hsi(rgb, c_atan):
+    """RGB -> HSI by Kender's form with arctan(sqrt(3) x) replaced by the
+    polynomial ``c_atan`` (Sec. 3.3.2).  H in [0, 2pi]; H = 0 on the red ray
+    and on the gray axis; S = 0 for black."""
+    rgb = clamp01(rgb)
+    _, case, x = colour.kender_hue(rgb)
+    base = np.where(case == 1, np.pi / 3.0, np.where(case == 2, np.pi, 5.0 * np.pi / 3.0))
+    active = (case >= 1) & (case <= 3)
+    H = np.where(active, base + odd_poly(c_atan, x), 0.0)
+    hsi = colour.rgb_to_hsi(rgb)
+    return np.stack([H, hsi[..., 1], hsi[..., 2]], axis=-1)
+
+
+def mact_sct(rgb, c_asin2, c_acos, c_atan, c_atanc):
+    """RGB -> SCT with the inverse trigonometric functions replaced by
+    polynomials (Sec. 3.4.2, 3.4.3).
+
+    angle A: for B/L >= 0.5 (tested as 3 B^2 >= R^2 + G^2) it is
+    2 arcsin(y / sqrt 2) with y = sqrt(1 - B/L) ("c_asin2"); below 0.5 it is
+    arccos(B/L) ("c_acos").  1 - B/L is formed as (R^2+G^2) / (L (L + B)),
+    the same quantity without the cancellation.
+    angle B: arctan(G/R) split at G = R: for G < R the polynomial f of G/R
+    ("c_atan"); for 0 < R <= G the polynomial of g, pi/2 - arctan(R/G)
+    ("c_atanc"); pi/2 for R = 0 < G; 0 for R = G = 0.
+    L = 0 gives (0, 0, 0).
+    """
+    rgb = clamp01(rgb)
+    R, G, B = rgb[..., 0], rgb[..., 1], rgb[..., 2]
+    rg2 = R * R + G * G
+    L = np.sqrt(rg2 + B * B)
+    pos = L > 0
+    Ls = np.where(pos, L, 1.0)
+    upper = 3.0 * B * B >= rg2
+    y = np.sqrt(rg2 / (Ls * (Ls + B)))
+    A = np.where(upper, horner(c_asin2, y), horner(c_acos, B / Ls))
+    A = np.where(pos, A, 0.0)
+    gr = G < R
+    r_pos = R > 0
+    g_pos = G > 0
+    Bf = horner(c_atan, G / np.where(r_pos, R, 1.0))
+    Bg = horner(c_atanc, R / np.where(g_pos, G, 1.0))
+    Bang = np.where(gr, Bf, np.where(r_pos, Bg, np.where(g_pos, 0.5 * np.pi, 0.0)))
+    return np.stack([L, A, Bang], axis=-1)

@@ -1,0 +1,174 @@
+"""Invariants of the oracle's LUT interpolators, checked against independent
+constructions (CPU only).  Table 12 is checked in test_oracle_paper.py."""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.interpolate
+
+import synth
+from oracle import lut
+
+METHODS = ["trilinear", "prism", "pyramidal", "tetrahedral"]
+
+
+def _affine_lut(N, A, c):
+    v = lut.node_inputs(N)
+    g = np.stack(np.meshgrid(v, v, v, indexing="ij"), axis=-1)
+    return g @ A.T + c
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_weights_partition_unity(method):
+    f = synth.rng(1).random((5000, 3))
+    ws = lut.corner_weights(method, f)
+    total = sum(w for _, w in ws)
+    np.testing.assert_allclose(total, 1.0, atol=1e-15)
+    if method != "pyramidal":
+        assert min(w.min() for _, w in ws) >= -1e-15
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("N", [9, 17, 33])
+def test_affine_precision(method, N):
+    g = synth.rng(N)
+    A = g.normal(size=(3, 3))
+    c = g.normal(size=3)
+    L = _affine_lut(N, A, c)
+    x = g.random((20000, 3))
+    out, _ = lut.interp(L, "lab", method, x=x)
+    np.testing.assert_allclose(out, x @ A.T + c, atol=1e-12)
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("xform", ["lab", "hsi", "sct"])
+def test_node_hits(method, xform):
+    N = 17
+    L = lut.build(xform, N)
+    idx = np.array(list(itertools.product(range(N), repeat=3)))
+    out, _ = lut.interp(L, xform, method, x=idx / (N - 1.0))
+    want = L[idx[:, 0], idx[:, 1], idx[:, 2]]
+    for ch, ang in enumerate(lut.ANGULAR[xform]):
+        if ang:
+            d = np.abs(np.angle(np.exp(1j * (out[:, ch] - want[:, ch]))))
+            assert d.max() < 1e-12
+        else:
+            np.testing.assert_allclose(out[:, ch], want[:, ch], atol=1e-12)
+
+
+def test_trilinear_equals_library_grid_interpolator():
+    N = 9
+    L = lut.build("lab", N)
+    x = synth.rng(5).random((10000, 3))
+    v = lut.node_inputs(N)
+    ref = scipy.interpolate.RegularGridInterpolator((v, v, v), L, method="linear")(x)
+    out, _ = lut.interp(L, "lab", "trilinear", x=x)
+    np.testing.assert_allclose(out, ref, atol=1e-11)
+
+
+def _barycentric(verts, p):
+    # solve p = sum l_k v_k with sum l_k = 1
+    M = np.vstack([np.asarray(verts, dtype=float).T, np.ones(len(verts))])
+    return np.linalg.solve(M, np.append(p, 1.0))
+
+
+def test_tetrahedral_is_barycentric_in_sorted_simplex():
+    # the cube splits into 6 tetrahedra {f_a >= f_b >= f_c}; inside one the value is the
+    # barycentric interpolation of its 4 vertices
+    N = 5
+    L = lut.build("lab", N)
+    g = synth.rng(6)
+    for _ in range(300):
+        x = g.random(3)
+        pos = x * (N - 1)
+        i = np.minimum(np.floor(pos).astype(int), N - 2)
+        f = pos - i
+        order = np.argsort(-f)
+        verts = [np.zeros(3)]
+        for k in order:
+            v = verts[-1].copy()
+            v[k] = 1
+            verts.append(v)
+        lam = _barycentric(verts, f)
+        want = sum(l * L[tuple(i + v.astype(int))] for l, v in zip(lam, verts))
+        out, _ = lut.interp(L, "lab", "tetrahedral", x=x[None])
+        np.testing.assert_allclose(out[0], want, atol=1e-11)
+
+
+def test_prism_is_triangle_barycentric_times_lerp_along_r():
+    N = 5
+    L = lut.build("lab", N)
+    g = synth.rng(7)
+    for _ in range(300):
+        x = g.random(3)
+        pos = x * (N - 1)
+        i = np.minimum(np.floor(pos).astype(int), N - 2)
+        f = pos - i
+        tri = [(0, 0), (1, 0), (1, 1)] if f[1] >= f[2] else [(0, 0), (0, 1), (1, 1)]
+        M = np.vstack([np.array(tri, dtype=float).T, np.ones(3)])
+        lam = np.linalg.solve(M, np.array([f[1], f[2], 1.0]))
+        want = 0
+        for dr, wr in ((0, 1 - f[0]), (1, f[0])):
+            for l, (dg, db) in zip(lam, tri):
+                want = want + wr * l * L[i[0] + dr, i[1] + dg, i[2] + db]
+        out, _ = lut.interp(L, "lab", "prism", x=x[None])
+        np.testing.assert_allclose(out[0], want, atol=1e-11)
+
+
+@pytest.mark.parametrize("method", ["trilinear", "prism", "tetrahedral"])
+def test_continuity_across_cell_faces(method):
+    # the pyramidal polynomial form is not continuous (neither across cell faces nor across
+    # its own pyramid boundaries), so it is held to node hits and affine precision only
+    N = 9
+    L = lut.build("lab", N)
+    g = synth.rng(8)
+    x = g.random((2000, 3))
+    ax = g.integers(0, 3, 2000)
+    face = g.integers(1, N - 1, 2000) / (N - 1.0)
+    x[np.arange(2000), ax] = face
+    d = 1e-10
+    lo, hi = x.copy(), x.copy()
+    lo[np.arange(2000), ax] -= d
+    hi[np.arange(2000), ax] += d
+    a, _ = lut.interp(L, "lab", method, x=lo)
+    b, _ = lut.interp(L, "lab", method, x=hi)
+    assert np.abs(a - b).max() < 1e-6
+
+
+def test_u8_extraction_matches_float_extraction():
+    v = np.arange(256)
+    for N in (9, 17, 33, 2, 256):
+        i8, f8 = lut.locate_u8(v, N)
+        i, f = lut.locate(v / 255.0, N)
+        np.testing.assert_array_equal(i8, i)
+        np.testing.assert_allclose(f8, f, atol=1e-13)
+        assert f8.min() >= 0 and f8.max() <= 1
+
+
+def test_angular_channels_wrap_and_constant():
+    N = 3
+    L = np.zeros((N, N, N, 3))
+    L[..., 0] = 0.7
+    x = synth.rng(9).random((1000, 3))
+    for m in METHODS:
+        out, r = lut.interp(L, "hsi", m, x=x)
+        np.testing.assert_allclose(out[:, 0], 0.7, atol=1e-12)
+        np.testing.assert_allclose(r[:, 0], 1.0, atol=1e-12)
+    # angles 0.1 and 2 pi - 0.1 meet at 0, not at pi
+    L[..., 0] = 0.1
+    L[1:, ..., 0] = 2 * np.pi - 0.1
+    out, _ = lut.interp(L, "hsi", "trilinear", x=np.array([[0.25, 0.0, 0.0]]))
+    assert np.angle(np.exp(1j * out[0, 0])) == pytest.approx(0.0, abs=1e-12)
+
+
+def test_pyramidal_form_is_discontinuous_at_pyramid_boundary():
+    # documents the reading: with only c010 = 1, the R-pyramid form gives f (1 - f_B) on
+    # the plane f_R = f_G while the G-pyramid form gives 0
+    L = np.zeros((2, 2, 2, 3))
+    L[0, 1, 0, :] = 1.0
+    f = 0.3
+    fb = 0.6
+    below, _ = lut.interp(L, "lab", "pyramidal", x=np.array([[f - 1e-12, f, fb]]))
+    above, _ = lut.interp(L, "lab", "pyramidal", x=np.array([[f, f - 1e-12, fb]]))
+    assert below[0, 0] == pytest.approx(f * (1 - fb), abs=1e-9)
+    assert above[0, 0] == pytest.approx(0.0, abs=1e-9)
