@@ -1,0 +1,334 @@
+/*
+ * mact.h -- C ABI of libmact, the MACT hot path for AMD Instinct MI355X (gfx950).
+ *
+ * MACT (Celebi, Kingravi & Celiker, "Fast Color Space Transformations Using
+ * Minimax Approximations") evaluates per-pixel RGB->CIELAB (Sec. 3.2), RGB->HSI
+ * (Sec. 3.3) and RGB->SCT (Sec. 3.4) with the costly elementary functions -- the
+ * cube root, and the arctan / arcsin / arccos terms -- replaced by minimax
+ * polynomials or rationals computed with the Remez exchange algorithm (Sec. 3.1).
+ * The 3-D LUT interpolators the paper compares with (trilinear, prism, pyramidal,
+ * tetrahedral; Sec. 3.5.3) are provided beside it.
+ *
+ * Conventions for every entry point:
+ *  - Return value: MACT_OK (0) or a negative mact_status.  Nothing throws,
+ *    aborts or prints.  mact_last_error() gives a thread-local detail string.
+ *  - Device calls are asynchronous on the hip stream passed as `void*`
+ *    (hipStream_t; NULL = the default stream of the current device) and run on
+ *    the current HIP device.  Arguments are validated before anything is
+ *    launched; an invalid call launches nothing.
+ *  - Ownership: the library never allocates, frees or retains caller buffers.
+ *    Parameter structs are copied at call time and may be freed on return.
+ *  - Reentrant: calls may come from several host threads.  Calls that write the
+ *    same output buffer, or that share a batch plan, must not overlap.
+ *  - Pixels: R, G, B on the normalised scale [0, 1].  8-bit values v enter as
+ *    v/255.  Float inputs outside [0, 1] are clamped to it (the approximations
+ *    are fitted on the image of [0, 1] only); NaN inputs give unspecified values.
+ */
+#ifndef MACT_H
+#define MACT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+
+typedef int32_t mact_status;
+enum {
+  MACT_OK = 0,
+  MACT_E_INVALID = -1,     /* an argument is out of range, NULL or inconsistent */
+  MACT_E_NOCONV = -2,      /* mact_fit did not converge; *out holds the best iterate */
+  MACT_E_DEVICE = -3,      /* a HIP runtime call failed (detail in mact_last_error) */
+  MACT_E_NOMEM = -4,       /* a library-owned allocation failed */
+  MACT_E_UNSUPPORTED = -5, /* a valid but unimplemented combination */
+  MACT_E_BUSY = -6         /* serving: the request cannot be admitted yet */
+};
+
+/* Static description of a status code. */
+const char* mact_status_str(mact_status s);
+/* Detail of the last failing call on this thread ("" if none).  Valid until
+   the next library call on the same thread. */
+const char* mact_last_error(void);
+/* Library version string. */
+const char* mact_version(void);
+
+/* ------------------------------------------------- minimax approximations */
+
+/* Functions the paper approximates (Sec. 3.2.2, 3.3.2, 3.4.2, 3.4.3). */
+enum {
+  MACT_FN_CBRT = 0,       /* t^(1/3): the CIELAB nonlinearity above 0.008856 */
+  MACT_FN_ATAN_SQRT3 = 1, /* arctan(sqrt(3) x): Kender's hue, odd extension */
+  MACT_FN_ASIN2 = 2,      /* 2 arcsin(y / sqrt 2) = arccos(1 - y^2): SCT angle A, B/L >= 0.5 */
+  MACT_FN_ACOS = 3,       /* arccos(x): SCT angle A, B/L < 0.5 */
+  MACT_FN_ATAN = 4,       /* arctan(x): SCT angle B for G < R (f of the split) */
+  MACT_FN_ATANC = 5,      /* pi/2 - arctan(t): SCT angle B for R <= G (g of the split) */
+  MACT_FN_COUNT = 6
+};
+
+#define MACT_MAX_DEGREE 7
+
+/* A minimax approximation p/q on [lo, hi] (Sec. 3.1).  Monomial coefficients,
+   lowest degree first, q[0] = 1 for fits made here (printed tables keep the
+   paper's scaling).  m = 0: polynomial (q = 1). */
+typedef struct mact_approx {
+  int32_t fn;        /* MACT_FN_* */
+  int32_t n, m;      /* degrees of p and q, 0..MACT_MAX_DEGREE */
+  int32_t iters;     /* Remez iterations used (0 for tabulated sets) */
+  double lo, hi;     /* fit interval */
+  double p[8];       /* numerator coefficients (entries > n are 0) */
+  double q[8];       /* denominator coefficients (entries > m are 0) */
+  double eps;        /* max |f - p/q| on [lo, hi] */
+  double alt[18];    /* final alternation points (n + m + 2 of them) */
+  int32_t n_alt;
+  int32_t converged; /* 1 if the levelled error met the tolerance */
+} mact_approx;
+
+/* Remez exchange fit of function `fn` by p/q with deg p = n, deg q = m on
+   [lo, hi] (Sec. 3.1; the paper names the algorithm and cites its details).
+   Host only, FP64.  Errors: MACT_E_INVALID for NULL out, degrees outside
+   0..7, n + m + 2 > 18, lo >= hi, or an interval outside the function's
+   domain; MACT_E_NOCONV when the levelled error does not reach the tolerance
+   in `max_iter` iterations (out holds the best iterate and its eps). */
+mact_status mact_fit(int32_t fn, int32_t n, int32_t m, double lo, double hi, mact_approx* out);
+mact_status mact_fit_ex(int32_t fn, int32_t n, int32_t m, double lo, double hi, int32_t max_iter,
+                        mact_approx* out);
+
+/* The library's default approximation of `fn` (its own Remez fits, made once
+   per process and cached): cube root (4,4) rational on [0.008856, 1] (Table 2's
+   degree); arctan(sqrt 3 x) degree 5 on [0, 1]; 2 arcsin(y/sqrt 2) degree 5 on
+   [0, 1/sqrt 2]; arccos degree 5 on [0, 0.5]; arctan and pi/2 - arctan degree 5
+   on [0, 1] (the full range of G/R and R/G for float inputs). */
+mact_status mact_default_approx(int32_t fn, mact_approx* out);
+
+/* The coefficients printed in the paper: Table 1 (fn CBRT, m = 0, n = 2..5),
+   Table 2 (CBRT, n, m in 2..4), Table 3 (ATAN_SQRT3, n = 2..5; the n = 2 row
+   with a2 = -0.7497879, the printed + sign being lost), Tables 4-7 (ASIN2,
+   ACOS, ATAN, ATANC, n = 4, 5).  eps is the printed eps^A_max.
+   MACT_E_INVALID if the paper has no such row. */
+mact_status mact_paper_approx(int32_t fn, int32_t n, int32_t m, mact_approx* out);
+
+/* ------------------------------------------------------------ images */
+
+enum { MACT_LAB = 0, MACT_HSI = 1, MACT_SCT = 2 };   /* transforms */
+enum { MACT_U8 = 0, MACT_F16 = 1, MACT_F32 = 2 };    /* element types */
+enum { MACT_HWC = 0, MACT_CHW = 1 };                 /* layouts */
+enum {                                              /* input transfer function (LAB) */
+  MACT_GAMMA_BT709 = 0, /* Sec. 3.2.1's inverse gamma (ITU-R BT.709); default */
+  MACT_GAMMA_SRGB = 1,  /* IEC 61966-2-1 curve */
+  MACT_GAMMA_NONE = 2   /* the input is linear RGB */
+};
+
+/* A device image or a batch of equally shaped images.  Element (n, y, x, c) is at
+     HWC: data + (n*batch_stride + y*row_stride + 3*x + c) * elem_size
+     CHW: data + (n*batch_stride + c*plane_stride + y*row_stride + x) * elem_size
+   Strides are in elements; 0 selects the packed value (HWC row_stride = 3 W;
+   CHW row_stride = W, plane_stride = H row_stride; batch_stride = H row_stride
+   (HWC) or 3 plane_stride (CHW)).  `gamma` applies to LAB inputs only. */
+typedef struct mact_image {
+  void* data;
+  int32_t dtype, layout;
+  int64_t width, height;
+  int64_t row_stride, plane_stride;
+  int64_t batch, batch_stride; /* batch 0 or 1: a single image */
+  int32_t gamma;
+  int32_t reserved;
+} mact_image;
+
+/* Which approximations a transform uses:
+     LAB: f[0] = cube root (polynomial or rational);
+     HSI: f[0] = arctan(sqrt 3 x) (polynomial);
+     SCT: f[0] = 2 arcsin(y/sqrt 2), f[1] = arccos, f[2] = arctan, f[3] = pi/2 - arctan
+          (polynomials).
+   out_mode 0: transform values.  out_mode 1 (LAB only): the three values of
+   the approximated nonlinearity f~(X/X0), f~(Y/Y0), f~(Z/Z0) instead of L*a*b*. */
+typedef struct mact_params {
+  int32_t xform;
+  int32_t out_mode;
+  mact_approx f[4];
+} mact_params;
+
+/* Fill *p with transform `xform` and the default approximations. */
+mact_status mact_params_default(int32_t xform, mact_params* p);
+
+/* ------------------------------------------------------------ transforms */
+
+/* Per-pixel MACT transform of `in` into `out` (Sec. 3.2-3.4):
+     LAB: inverse gamma (8-bit inputs through a 256-entry table of the exact
+          values), BT.709 RGB->XYZ, D65 white, f~ = p/q above t = 0.008856 and
+          the exact linear segment at or below it; L* = 116 fy - 16,
+          a* = 500 (fx - fy), b* = 200 (fy - fz).
+     HSI: Kender's branch form; H = base + P(x) for x >= 0, base - P(-x) for
+          x < 0 (arctan's odd symmetry); H = 0 on the red ray and the gray
+          axis; S = 1 - 3 min / (R+G+B) (0 for black); I = (R+G+B)/3.
+          H in [0, 2 pi] radians; S, I in [0, 1].
+     SCT: L = |RGB|; angle A = P_asin2(sqrt(1 - B/L)) if 3 B^2 >= R^2 + G^2
+          (B/L >= 0.5), else P_acos(B/L); angle B = P_atan(G/R) if G < R,
+          P_atanc(R/G) if 0 < R <= G, pi/2 if R = 0 < G, 0 if R = G = 0;
+          black gives (0, 0, 0).  Radians.
+   in: MACT_U8 / MACT_F16 / MACT_F32, HWC or CHW.  out: MACT_F32 or MACT_F16,
+   HWC or CHW, same width, height and batch as `in`.  Evaluation is float32 with
+   explicit fused multiply-adds; the result does not depend on the launch
+   configuration, so every form (plain, batched, served) gives identical bits.
+   Errors: MACT_E_INVALID (NULL pointers, sizes <= 0, strides too small,
+   mismatched shapes, gamma set for HSI/SCT, out_mode 1 for HSI/SCT, degrees
+   outside 0..7); MACT_E_UNSUPPORTED (rational approximations for HSI/SCT,
+   U8 output); MACT_E_DEVICE (launch failure). */
+mact_status mact_transform(const mact_params* params, const mact_image* in, const mact_image* out,
+                           void* hip_stream);
+
+/* Vector-Jacobian product of the LAB transform (chain rule through the
+   definition of Sec. 3.2 with f~ in place of the cube root; the paper does not
+   differentiate the transform):
+     g_f = (500 g_a, 116 g_L - 500 g_a + 200 g_b, -200 g_b),
+     g_t = g_f * f~'(t)   (f~' = (p' q - p q') / q^2 above 0.008856, 7.787 below),
+     dx  = (diag(1/white) M)^T g_t, zeroed for inputs outside [0, 1].
+   x: MACT_F32 linear RGB (gamma MACT_GAMMA_NONE); grad_out and grad_in: MACT_F32
+   with the same geometry as x (any layouts).  params->xform must be MACT_LAB.
+   Errors as mact_transform; MACT_E_UNSUPPORTED for non-F32 or gamma != NONE. */
+mact_status mact_transform_backward(const mact_params* params, const mact_image* x,
+                                    const mact_image* grad_out, const mact_image* grad_in,
+                                    void* hip_stream);
+
+/* ------------------------------------------------------------ 3-D LUTs */
+
+enum { MACT_TRILINEAR = 0, MACT_PRISM = 1, MACT_PYRAMIDAL = 2, MACT_TETRAHEDRAL = 3 };
+
+/* Bytes of a packed N x N x N LUT for `xform`: N^3 nodes of 4 floats (LAB:
+   L*, a*, b*, 0; HSI: cos H, sin H, S, I) or 8 floats (SCT: L, cos A, sin A,
+   cos B, sin B, 0, 0, 0).  Node (i, j, k) at index (i N + j) N + k holds the
+   exact transform of the input (i, j, k)/(N - 1) (Sec. 3.5.3's packing).
+   Returns 0 for invalid arguments. */
+size_t lut_bytes(int32_t xform, int32_t n);
+
+/* Packing (Sec. 3.5.3): evaluates the exact transform in FP64 on the host at
+   every node, rounds to float32 and copies the packed LUT to the device buffer
+   `dev_lut` (caller-owned, >= lut_bytes bytes) on `hip_stream`.  Returns after
+   the copy has completed.  n in 2..256.  gamma applies to LAB. */
+mact_status lut_build(int32_t xform, int32_t n, int32_t gamma, float* dev_lut, size_t bytes,
+                      void* hip_stream);
+
+/* Extraction + 3-D interpolation (Sec. 3.5.3) of every pixel of `in` in the
+   LUT: cell i = min(floor(x (N-1)), N-2) and fraction per channel (exact
+   integer arithmetic for 8-bit inputs), then
+     TRILINEAR   tensor-product weights on 8 corners;
+     PRISM       linear along R, triangle (0,0),(1,0),(1,1) of the (G,B) face if
+                 f_G >= f_B else (0,0),(0,1),(1,1): 6 corners;
+     PYRAMIDAL   apex corner 111, base the cell face through 000 normal to the
+                 axis of the smallest fraction, in Kang's polynomial form: 5 corners;
+     TETRAHEDRAL fractions sorted f1 >= f2 >= f3, path 000 -> 111 along the
+                 axes in that order, weights 1-f1, f1-f2, f2-f3, f3: 4 corners.
+   Angular channels (H; angles A and B) are interpolated as circular data: the
+   angle of the weighted sum of the nodes' unit vectors (H in [0, 2 pi), SCT
+   angles in (-pi, pi]).  Grids whose bytes fit the workgroup's LDS are staged
+   there; larger ones are read through the L2.  in/out as mact_transform.
+   Errors: MACT_E_INVALID (NULL, n outside 2..256, bad method, shapes). */
+mact_status lut_interp(const float* dev_lut, int32_t n, int32_t xform, int32_t method,
+                       const mact_image* in, const mact_image* out, void* hip_stream);
+
+/* ------------------------------------------------------------ batched form */
+
+/* Launch shape picked by the autotuner (or given by the caller). */
+typedef struct mact_tune {
+  int32_t block;      /* threads per workgroup: 64, 128, 256, 512, 1024 */
+  int32_t tile;       /* pixels per work tile: multiple of the block, >= block */
+  int32_t vec;        /* pixels per lane per step on the packed 8-bit path: 1, 2 or 4 */
+  int32_t waves_per_cu; /* persistent grid = CUs x this, capped by the tile count */
+} mact_tune;
+
+typedef struct mact_batch_plan mact_batch_plan;
+
+/* A persistent batched transform of `count` images of any sizes, element
+   types, layouts and transforms (image i uses params[i], in[i], out[i]) in one
+   launch: the images are cut into tiles of `tile` pixels, and a grid sized to
+   the GPU walks the tile list.  The per-pixel arithmetic is that of
+   mact_transform, so every output is bitwise equal to the plain call's.  The
+   plan copies the descriptors to device memory (library-owned), picks the
+   launch shape with the autotuner when `tune` is NULL (timings on `hip_stream`,
+   cached per GPU and shape class; a JSON cache file is read and written when the
+   MACT_AUTOTUNE_CACHE environment variable names one), and captures the launch
+   in a HIP graph.  The image buffers must stay valid while the plan is used.
+   Errors: as mact_transform for any image; MACT_E_NOMEM; MACT_E_DEVICE. */
+mact_status mact_batch_plan_create(const mact_params* params, const mact_image* in, const mact_image* out,
+                                   int32_t count, const mact_tune* tune, void* hip_stream,
+                                   mact_batch_plan** plan);
+/* Replays the captured graph on `hip_stream` (use_graph = 1) or launches the
+   persistent kernel directly (use_graph = 0). */
+mact_status mact_batch_plan_launch(mact_batch_plan* plan, int32_t use_graph, void* hip_stream);
+/* The launch shape the plan uses. */
+mact_status mact_batch_plan_tune(const mact_batch_plan* plan, mact_tune* tune);
+/* Waits for nothing: the caller synchronises its stream before destroying. */
+mact_status mact_batch_plan_destroy(mact_batch_plan* plan);
+/* Create + launch (graph) + stream synchronise + destroy. */
+mact_status mact_batch_run(const mact_params* params, const mact_image* in, const mact_image* out,
+                           int32_t count, const mact_tune* tune, void* hip_stream);
+
+/* ------------------------------------------------------------ serving */
+
+/* A continuous-batching engine on the current device.  Requests carry host
+   (pinned) input and output buffers.  A scheduler thread admits a request when
+   its device bytes fit in the engine's arena (size-class free lists carved from
+   one allocation), copies it in on a copy stream, and groups every request
+   whose input has arrived into one persistent batched launch on the next of
+   `compute_streams` streams; batches overlap on the device, and requests that
+   arrive while batches are in flight join the next one.  Outputs are copied back
+   and the request completes.  Coefficients stay resident in the engine. */
+typedef struct mact_server_config {
+  size_t arena_bytes;      /* device memory for request inputs and outputs */
+  int32_t max_batch;       /* most requests in one launch */
+  int32_t compute_streams; /* concurrent batches in flight (1..8) */
+  int32_t max_queue;       /* submitted but not admitted requests before MACT_E_BUSY */
+  int32_t reserved;
+  mact_params params[3];   /* per transform: LAB, HSI, SCT */
+} mact_server_config;
+
+typedef struct mact_request {
+  const void* host_in;     /* pinned host pixels, packed HWC */
+  void* host_out;          /* pinned host output, packed HWC */
+  int32_t in_dtype;        /* MACT_U8 or MACT_F16 */
+  int32_t out_dtype;       /* MACT_F32 or MACT_F16 */
+  int32_t xform;           /* MACT_LAB / MACT_HSI / MACT_SCT */
+  int32_t gamma;           /* LAB input transfer function */
+  int64_t width, height;
+} mact_request;
+
+typedef struct mact_server_stats {
+  int64_t submitted, completed, rejected, batches;
+  double p50_ms, p99_ms, mean_ms; /* submit -> output copied back, completed requests */
+  double mean_batch;              /* requests per launch */
+  double device_busy_ms;          /* sum of batch kernel times */
+} mact_server_stats;
+
+typedef struct mact_server mact_server;
+
+mact_status mact_server_create(const mact_server_config* cfg, mact_server** srv);
+/* Queue a request; *id receives its handle.  MACT_E_BUSY if max_queue requests
+   are already waiting (nothing is queued); MACT_E_INVALID if it could never fit
+   the arena or its fields are out of range. */
+mact_status mact_server_submit(mact_server* srv, const mact_request* req, int64_t* id);
+/* *done = 1 once request `id` has completed (its host_out is written). */
+mact_status mact_server_poll(mact_server* srv, int64_t id, int32_t* done);
+/* Block until request `id` completes or timeout_ms passes (MACT_E_BUSY). */
+mact_status mact_server_wait(mact_server* srv, int64_t id, int32_t timeout_ms);
+/* Latency of a completed request in milliseconds (submit -> output on host). */
+mact_status mact_server_latency(mact_server* srv, int64_t id, double* ms);
+mact_status mact_server_stats_get(mact_server* srv, mact_server_stats* st);
+/* Drains every queued request, stops the scheduler, frees the arena. */
+mact_status mact_server_destroy(mact_server* srv);
+
+/* ------------------------------------------------------------ reference kernels */
+
+/* The byte pattern of the packed 8-bit -> float32 transform with no
+   arithmetic: reads n_px * 3 bytes from src and writes n_px * 12 bytes to dst
+   (the bytes widened to floats).  It measures the practical HBM ceiling of the
+   hot path's access pattern. */
+mact_status mact_stream_u8_to_f32(const void* src, void* dst, int64_t n_px, void* hip_stream);
+/* Plain 16-byte-vector copy of `bytes` (a multiple of 16). */
+mact_status mact_copy(const void* src, void* dst, int64_t bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MACT_H */

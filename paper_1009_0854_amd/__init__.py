@@ -1,0 +1,315 @@
+"""MACT on MI355X: minimax-approximated colour-space transforms (Celebi,
+Kingravi & Celiker, "Fast Color Space Transformations Using Minimax
+Approximations") as hand-written HIP kernels for gfx950 behind a C ABI
+(include/mact.h, libmact.so).
+
+This module only marshals arguments: torch tensors supply device memory and
+streams, and every step of a transform runs in libmact's kernels.  If the
+library has not been built, every call raises.
+"""
+import ctypes
+
+from . import _abi as A
+from ._abi import (CHW, E_BUSY, E_NOCONV, F16, F32, FN_ACOS, FN_ASIN2, FN_ATAN, FN_ATAN_SQRT3, FN_ATANC, FN_CBRT,
+                   GAMMA_BT709, GAMMA_NONE, GAMMA_SRGB, HSI, HWC, LAB, PRISM, PYRAMIDAL, SCT, TETRAHEDRAL, TRILINEAR,
+                   U8, Approx, Image, MactError, Params, Request, ServerConfig, ServerStats, Tune, lib)
+
+__all__ = ["fit", "default_approx", "paper_approx", "default_params", "make_params", "image", "transform",
+           "transform_backward", "lut_bytes", "lut_build", "lut_interp", "BatchPlan", "batch_run", "Server",
+           "stream_u8_to_f32", "copy", "MactError", "MactLab"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _xf(x):
+    return A.XFORMS[x] if isinstance(x, str) else int(x)
+
+
+def _gm(g):
+    return A.GAMMAS[g] if isinstance(g, str) else int(g)
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------- approximations
+
+def fit(fn, n, m, lo, hi, max_iter=100, allow_noconv=False):
+    """mact_fit: Remez fit of function `fn` (FN_*) by p/q, degrees (n, m), on [lo, hi]."""
+    out = Approx()
+    st = lib().mact_fit_ex(int(fn), int(n), int(m), float(lo), float(hi), int(max_iter), ctypes.byref(out))
+    A.check(st, allow=(E_NOCONV,) if allow_noconv else ())
+    return out
+
+
+def default_approx(fn):
+    out = Approx()
+    A.check(lib().mact_default_approx(int(fn), ctypes.byref(out)))
+    return out
+
+
+def paper_approx(fn, n, m=0):
+    out = Approx()
+    A.check(lib().mact_paper_approx(int(fn), int(n), int(m), ctypes.byref(out)))
+    return out
+
+
+def default_params(xform):
+    p = Params()
+    A.check(lib().mact_params_default(_xf(xform), ctypes.byref(p)))
+    return p
+
+
+def make_params(xform, approxes, out_mode=0):
+    """Params for `xform` with the given approximations (LAB: [cbrt]; HSI:
+    [atan_sqrt3]; SCT: [asin2, acos, atan, atanc])."""
+    p = Params()
+    p.xform = _xf(xform)
+    p.out_mode = int(out_mode)
+    for i, a in enumerate(approxes):
+        p.f[i] = a
+    return p
+
+
+# ---------------------------------------------------------------- images
+
+def _dtype_code(t):
+    torch = _torch()
+    m = {torch.uint8: U8, torch.float16: F16, torch.float32: F32}
+    if t.dtype not in m:
+        raise TypeError("unsupported dtype %s" % t.dtype)
+    return m[t.dtype]
+
+
+def image(t, layout="hwc", gamma="bt709"):
+    """Describe a CUDA tensor as an mact_image: HWC (H, W, 3) or (N, H, W, 3);
+    CHW (3, H, W) or (N, 3, H, W).  Strides are taken from the tensor."""
+    if not t.is_cuda:
+        raise ValueError("image(): tensor must be on the GPU")
+    im = Image()
+    im.data = t.data_ptr()
+    im.dtype = _dtype_code(t)
+    im.gamma = _gm(gamma)
+    lay = HWC if layout in ("hwc", HWC) else CHW
+    im.layout = lay
+    s = t.stride()
+    if lay == HWC:
+        if t.dim() not in (3, 4) or t.shape[-1] != 3:
+            raise ValueError("HWC tensor must be (H, W, 3) or (N, H, W, 3), got %s" % (tuple(t.shape),))
+        if s[-1] != 1 or s[-2] != 3:
+            raise ValueError("HWC tensor needs channel stride 1 and pixel stride 3")
+        im.height, im.width = t.shape[-3], t.shape[-2]
+        im.row_stride = s[-3]
+        im.plane_stride = 0
+        im.batch = t.shape[0] if t.dim() == 4 else 1
+        im.batch_stride = s[0] if t.dim() == 4 else 0
+    else:
+        if t.dim() not in (3, 4) or t.shape[-3] != 3:
+            raise ValueError("CHW tensor must be (3, H, W) or (N, 3, H, W), got %s" % (tuple(t.shape),))
+        if s[-1] != 1:
+            raise ValueError("CHW tensor needs unit stride along W")
+        im.height, im.width = t.shape[-2], t.shape[-1]
+        im.row_stride = s[-2]
+        im.plane_stride = s[-3]
+        im.batch = t.shape[0] if t.dim() == 4 else 1
+        im.batch_stride = s[0] if t.dim() == 4 else 0
+    return im
+
+
+def _out_like(x, layout, out_dtype):
+    torch = _torch()
+    return torch.empty(x.shape, dtype=out_dtype, device=x.device)
+
+
+def transform(x, xform="lab", params=None, layout="hwc", gamma="bt709", out=None, out_layout=None,
+              out_dtype=None, stream=None):
+    """mact_transform of tensor x; returns the output tensor (same shape)."""
+    torch = _torch()
+    p = params if params is not None else default_params(xform)
+    out_layout = layout if out_layout is None else out_layout
+    if out is None:
+        out = _out_like(x, out_layout, out_dtype or torch.float32)
+    A.check(lib().mact_transform(ctypes.byref(p), ctypes.byref(image(x, layout, gamma)),
+                                 ctypes.byref(image(out, out_layout)), _stream(stream)))
+    return out
+
+
+def transform_backward(x, grad_out, params=None, layout="chw", grad_in=None, stream=None):
+    """mact_transform_backward: d(sum <grad_out, Lab(x)>)/dx for linear float32 x."""
+    torch = _torch()
+    p = params if params is not None else default_params("lab")
+    if grad_in is None:
+        grad_in = torch.empty_like(x)
+    A.check(lib().mact_transform_backward(ctypes.byref(p), ctypes.byref(image(x, layout, "none")),
+                                          ctypes.byref(image(grad_out, layout)),
+                                          ctypes.byref(image(grad_in, layout)), _stream(stream)))
+    return grad_in
+
+
+# ---------------------------------------------------------------- LUTs
+
+def lut_bytes(xform, n):
+    return int(lib().lut_bytes(_xf(xform), int(n)))
+
+
+def lut_build(xform, n, gamma="bt709", device="cuda", stream=None):
+    """Packed N^3 LUT as a float32 device tensor (lut_build)."""
+    torch = _torch()
+    nbytes = lut_bytes(xform, n)
+    if nbytes == 0:
+        raise MactError(A.E_INVALID, "lut_bytes: invalid xform/n")
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device=device)
+    A.check(lib().lut_build(_xf(xform), int(n), _gm(gamma), ctypes.c_void_p(buf.data_ptr()), nbytes, _stream(stream)))
+    return buf
+
+
+def lut_interp(lut, n, xform, method, x, layout="hwc", out=None, out_layout=None, out_dtype=None, stream=None):
+    torch = _torch()
+    out_layout = layout if out_layout is None else out_layout
+    if out is None:
+        out = _out_like(x, out_layout, out_dtype or torch.float32)
+    m = A.METHODS[method] if isinstance(method, str) else int(method)
+    A.check(lib().lut_interp(ctypes.c_void_p(lut.data_ptr()), int(n), _xf(xform), m,
+                             ctypes.byref(image(x, layout, "none")), ctypes.byref(image(out, out_layout)),
+                             _stream(stream)))
+    return out
+
+
+# ---------------------------------------------------------------- batched form
+
+def _arrays(params, ins, outs, layouts=None, gammas=None, out_layouts=None):
+    n = len(ins)
+    P = (Params * n)(*params)
+    layouts = layouts or ["hwc"] * n
+    out_layouts = out_layouts or layouts
+    gammas = gammas or ["bt709"] * n
+    I = (Image * n)(*[image(t, l, g) for t, l, g in zip(ins, layouts, gammas)])
+    O = (Image * n)(*[image(t, l) for t, l in zip(outs, out_layouts)])
+    return P, I, O
+
+
+class BatchPlan:
+    """A persistent, graph-captured batched transform of many images
+    (mact_batch_plan_*).  Keeps references to the tensors it reads and writes."""
+
+    def __init__(self, params, ins, outs, layouts=None, gammas=None, out_layouts=None, tune=None, stream=None):
+        self._keep = (list(ins), list(outs))
+        P, I, O = _arrays(params, ins, outs, layouts, gammas, out_layouts)
+        h = ctypes.c_void_p()
+        t = ctypes.byref(tune) if tune is not None else None
+        A.check(lib().mact_batch_plan_create(P, I, O, len(ins), t, _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, use_graph=True, stream=None):
+        A.check(lib().mact_batch_plan_launch(self._h, 1 if use_graph else 0, _stream(stream)))
+
+    @property
+    def tune(self):
+        t = Tune()
+        A.check(lib().mact_batch_plan_tune(self._h, ctypes.byref(t)))
+        return t
+
+    def close(self):
+        if self._h:
+            lib().mact_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_run(params, ins, outs, layouts=None, gammas=None, out_layouts=None, tune=None, stream=None):
+    P, I, O = _arrays(params, ins, outs, layouts, gammas, out_layouts)
+    t = ctypes.byref(tune) if tune is not None else None
+    A.check(lib().mact_batch_run(P, I, O, len(ins), t, _stream(stream)))
+
+
+# ---------------------------------------------------------------- serving
+
+class Server:
+    """Continuous-batching engine (mact_server_*)."""
+
+    def __init__(self, arena_bytes=1 << 30, max_batch=64, compute_streams=4, max_queue=1 << 16, params=None):
+        cfg = ServerConfig()
+        cfg.arena_bytes = int(arena_bytes)
+        cfg.max_batch = int(max_batch)
+        cfg.compute_streams = int(compute_streams)
+        cfg.max_queue = int(max_queue)
+        for i, x in enumerate(("lab", "hsi", "sct")):
+            cfg.params[i] = (params or {}).get(x) or default_params(x)
+        h = ctypes.c_void_p()
+        A.check(lib().mact_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, host_in, host_out, xform="lab", gamma="bt709"):
+        """Queue one packed HWC image held in pinned host tensors; returns its id."""
+        torch = _torch()
+        r = Request()
+        r.host_in = host_in.data_ptr()
+        r.host_out = host_out.data_ptr()
+        r.in_dtype = _dtype_code(host_in)
+        r.out_dtype = _dtype_code(host_out)
+        r.xform = _xf(xform)
+        r.gamma = _gm(gamma)
+        r.height, r.width = host_in.shape[0], host_in.shape[1]
+        i = ctypes.c_int64()
+        A.check(lib().mact_server_submit(self._h, ctypes.byref(r), ctypes.byref(i)))
+        self._keep[i.value] = (host_in, host_out)
+        del torch
+        return i.value
+
+    def poll(self, rid):
+        d = ctypes.c_int32()
+        A.check(lib().mact_server_poll(self._h, int(rid), ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, rid, timeout_ms=60000):
+        A.check(lib().mact_server_wait(self._h, int(rid), int(timeout_ms)))
+        self._keep.pop(rid, None)
+
+    def latency_ms(self, rid):
+        v = ctypes.c_double()
+        A.check(lib().mact_server_latency(self._h, int(rid), ctypes.byref(v)))
+        return v.value
+
+    def stats(self):
+        s = ServerStats()
+        A.check(lib().mact_server_stats_get(self._h, ctypes.byref(s)))
+        return s
+
+    def close(self):
+        if self._h:
+            A.check(lib().mact_server_destroy(self._h))
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- reference kernels
+
+def stream_u8_to_f32(src, dst, n_px, stream=None):
+    A.check(lib().mact_stream_u8_to_f32(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                        int(n_px), _stream(stream)))
+
+
+def copy(src, dst, nbytes, stream=None):
+    A.check(lib().mact_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), int(nbytes),
+                            _stream(stream)))
+
+
+from .autograd import MactLab  # noqa: E402

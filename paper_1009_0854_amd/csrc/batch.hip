@@ -1,0 +1,501 @@
+// Batched form: one persistent launch over many images of uneven sizes, mixed
+// element types, layouts and transforms.
+//
+// Every image is cut into tiles of `tile` pixels; tile t belongs to the image
+// i with tile_start[i] <= t < tile_start[i+1].  A grid sized to the GPU walks
+// the tile list (tile t, t + gridDim.x, ...); each workgroup finds its tile's
+// image by binary search (wave-uniform, scalar loads), then transforms the
+// tile's pixels with the same per-pixel functions as the plain kernels --
+// packed 8-bit HWC -> float32 HWC tiles through the 4-pixel LDS-transposed
+// path, everything else one pixel per lane -- so outputs are bitwise equal to
+// mact_transform's.  The plan captures the launch in a HIP graph.  The launch
+// shape (block, tile, vector path, waves per CU) comes from an autotuner that
+// times candidates on the actual batch and caches the winner per GPU and
+// shape class (optionally in a JSON file named by MACT_AUTOTUNE_CACHE).
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+
+namespace mact {
+
+#include "gamma_table.inc"
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bbyte_of(uint3 w, int i) {
+  const uint32_t word = i < 4 ? w.x : (i < 8 ? w.y : w.z);
+  return (word >> (8 * (i & 3))) & 0xffu;
+}
+
+template <int XF, int DEG>
+__device__ __forceinline__ void bpx4(const KCoef& k, const float* gtab, uint3 w, float o[12]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t r = bbyte_of(w, 3 * j), g = bbyte_of(w, 3 * j + 1), b = bbyte_of(w, 3 * j + 2);
+    if (XF == MACT_LAB) lab_px<DEG>(k, gtab[r], gtab[g], gtab[b], o + 3 * j);
+    else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o + 3 * j);
+    else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o + 3 * j);
+  }
+}
+
+template <int DEG, int VEC>
+__global__ __launch_bounds__(1024) void k_batch(const BDesc* __restrict__ descs, const KCoef* __restrict__ coefs,
+                                                const uint32_t* __restrict__ tile_start, int32_t count,
+                                                uint32_t total_tiles, uint32_t tile) {
+  __shared__ float gtab[3][256];
+  extern __shared__ f4 s_out[];  // VEC == 4: 192 float4 per wave
+  for (uint32_t i = threadIdx.x; i < 768u; i += blockDim.x) gtab[i >> 8][i & 255u] = k_gamma_table[i >> 8][i & 255u];
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (uint32_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+    int32_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (tile_start[mid] <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const BDesc& d = descs[lo];
+    const KCoef& k = coefs[d.coef];
+    const uint32_t p0 = (t - tile_start[lo]) * tile;
+    const uint32_t p1 = min(p0 + tile, d.n_px);
+    const float* g = gtab[d.gamma];
+    uint32_t pstart = p0;
+    if (VEC == 4 && d.fast) {
+      // full 256-pixel chunks of the tile, one per wave at a time (p0 is a multiple of 256)
+      const uint32_t nchunk = (p1 - p0) >> 8;
+      f4* s = s_out + wv * 192;
+      for (uint32_t c = wv; c < nchunk; c += nw) {
+        const uint32_t cp = p0 + (c << 8);
+        const uint3 w = reinterpret_cast<const uint3*>(d.src.ptr)[(cp >> 2) + lane];
+        float o[12];
+        if (k.xform == MACT_LAB) bpx4<MACT_LAB, DEG>(k, g, w, o);
+        else if (k.xform == MACT_HSI) bpx4<MACT_HSI, DEG>(k, g, w, o);
+        else bpx4<MACT_SCT, DEG>(k, g, w, o);
+        __builtin_amdgcn_wave_barrier();
+        s[3 * lane] = f4{o[0], o[1], o[2], o[3]};
+        s[3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
+        s[3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): every lane's LDS writes have landed
+        __builtin_amdgcn_wave_barrier();
+        f4* dst = reinterpret_cast<f4*>(d.dst.ptr) + (size_t)(cp >> 2) * 3;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(s[q * 64 + lane], dst + q * 64 + lane);
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+      }
+      pstart = p0 + (nchunk << 8);
+    }
+    const bool u8 = d.src.dtype == MACT_U8;
+    for (uint32_t p = pstart + threadIdx.x; p < p1; p += blockDim.x) {
+      float v[3], o[3];
+      load_px(d.src, p, v);
+      eval_px<DEG>(k, u8, d.gamma, g, v, o);
+      store_px(d.dst, p, o);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- host helpers
+
+mact_status make_batch_descs(const mact_params& p, const mact_image* in, const mact_image* out, int32_t coef,
+                             std::vector<BDesc>* descs, int* deg, const char* what) {
+  mact_status s = check_params(&p);
+  if (s != MACT_OK) return s;
+  HostImage hi, ho;
+  if ((s = resolve_image(in, false, what, &hi)) != MACT_OK) return s;
+  if ((s = resolve_image(out, true, what, &ho)) != MACT_OK) return s;
+  if ((s = check_same_shape(hi, ho, what)) != MACT_OK) return s;
+  KCoef k;
+  *deg = pack_coef(p, &k);
+  const int gamma = p.xform == MACT_LAB ? hi.gamma : MACT_GAMMA_NONE;
+  const bool fast = hi.dtype == MACT_U8 && hi.layout == MACT_HWC && hi.packed && ho.dtype == MACT_F32 &&
+                    ho.layout == MACT_HWC && ho.packed && ((uintptr_t)hi.data % 4 == 0) &&
+                    ((uintptr_t)ho.data % 16 == 0);
+  const int64_t per = images_per_launch(hi);
+  for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
+    const int64_t cnt = std::min(per, hi.N - n0);
+    BDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.src = kimage(hi, n0, cnt);
+    d.dst = kimage(ho, n0, cnt);
+    d.n_px = (uint32_t)(cnt * hi.W * hi.H);
+    d.coef = coef;
+    d.gamma = gamma;
+    d.fast = fast ? 1 : 0;
+    descs->push_back(d);
+  }
+  return MACT_OK;
+}
+
+uint32_t build_tiles(const std::vector<BDesc>& descs, uint32_t tile, std::vector<uint32_t>* tile_start) {
+  tile_start->assign(descs.size() + 1, 0);
+  uint64_t t = 0;
+  for (size_t i = 0; i < descs.size(); ++i) {
+    (*tile_start)[i] = (uint32_t)t;
+    t += (descs[i].n_px + tile - 1) / tile;
+  }
+  (*tile_start)[descs.size()] = (uint32_t)t;
+  return (uint32_t)t;
+}
+
+unsigned batch_grid(const mact_tune& tune, uint32_t total_tiles) {
+  const uint64_t per_cu = std::max<uint64_t>(1, (uint64_t)tune.waves_per_cu * 64 / tune.block);
+  const uint64_t cap = (uint64_t)device_cus() * per_cu;
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(total_tiles, cap));
+}
+
+hipError_t launch_batch_kernel(const BDesc* d_descs, const KCoef* d_coefs, const uint32_t* d_tiles, int32_t count,
+                               uint32_t total_tiles, const mact_tune& tune, int deg, hipStream_t st) {
+  if (total_tiles == 0) return hipSuccess;
+  const unsigned grid = batch_grid(tune, total_tiles);
+  const size_t shm = tune.vec == 4 ? (size_t)(tune.block / 64) * 192 * sizeof(f4) : 0;
+  const dim3 g(grid), b(tune.block);
+  const uint32_t tile = (uint32_t)tune.tile;
+  if (deg == 5) {
+    if (tune.vec == 4) hipLaunchKernelGGL((k_batch<5, 4>), g, b, shm, st, d_descs, d_coefs, d_tiles, count, total_tiles, tile);
+    else hipLaunchKernelGGL((k_batch<5, 1>), g, b, shm, st, d_descs, d_coefs, d_tiles, count, total_tiles, tile);
+  } else {
+    if (tune.vec == 4) hipLaunchKernelGGL((k_batch<7, 4>), g, b, shm, st, d_descs, d_coefs, d_tiles, count, total_tiles, tile);
+    else hipLaunchKernelGGL((k_batch<7, 1>), g, b, shm, st, d_descs, d_coefs, d_tiles, count, total_tiles, tile);
+  }
+  return hipGetLastError();
+}
+
+static mact_status check_tune(const mact_tune& t) {
+  if (t.block < 64 || t.block > 1024 || t.block % 64)
+    return fail(MACT_E_INVALID, "mact_tune: block %d not a multiple of 64 in 64..1024", t.block);
+  if (t.tile < 256 || t.tile % 256 || t.tile < t.block)
+    return fail(MACT_E_INVALID, "mact_tune: tile %d must be a multiple of 256 and >= block", t.tile);
+  if (t.vec != 1 && t.vec != 4) return fail(MACT_E_INVALID, "mact_tune: vec %d not 1 or 4", t.vec);
+  if (t.waves_per_cu < 1 || t.waves_per_cu > 64) return fail(MACT_E_INVALID, "mact_tune: waves_per_cu %d", t.waves_per_cu);
+  return MACT_OK;
+}
+
+// ---------------------------------------------------------------- autotune cache
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, mact_tune> g_tune_cache;
+bool g_tune_file_loaded = false;
+
+const char* cache_path() {
+  const char* p = std::getenv("MACT_AUTOTUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+// File format: one JSON object, "key": [block, tile, vec, waves_per_cu] entries.
+void load_cache_file_locked() {
+  if (g_tune_file_loaded) return;
+  g_tune_file_loaded = true;
+  const char* path = cache_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return;
+  std::string s;
+  char buf[4096];
+  size_t n;
+  while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, n);
+  std::fclose(f);
+  size_t pos = 0;
+  while ((pos = s.find('"', pos)) != std::string::npos) {
+    const size_t end = s.find('"', pos + 1);
+    if (end == std::string::npos) break;
+    const std::string key = s.substr(pos + 1, end - pos - 1);
+    const size_t lb = s.find('[', end), rb = s.find(']', end);
+    if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
+    mact_tune t;
+    if (std::sscanf(s.c_str() + lb + 1, "%d , %d , %d , %d", &t.block, &t.tile, &t.vec, &t.waves_per_cu) == 4 &&
+        check_tune(t) == MACT_OK)
+      g_tune_cache[key] = t;
+    pos = rb + 1;
+  }
+  clear_error();
+}
+
+void save_cache_file_locked() {
+  const char* path = cache_path();
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return;
+  std::fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : g_tune_cache) {
+    std::fprintf(f, "  \"%s\": [%d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second.block, kv.second.tile, kv.second.vec,
+                 kv.second.waves_per_cu, ++i == g_tune_cache.size() ? "" : ",");
+  }
+  std::fprintf(f, "}\n");
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+
+int log2_bucket(uint64_t v) {
+  int b = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+std::string shape_key(const std::vector<BDesc>& descs, int deg) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, current_device()) == hipSuccess) arch = prop.gcnArchName;
+  uint64_t px = 0, fast_px = 0;
+  for (const BDesc& d : descs) {
+    px += d.n_px;
+    if (d.fast) fast_px += d.n_px;
+  }
+  const int fast_frac = px ? (int)(4 * fast_px / px) : 0;  // quarters of pixels on the 4-pixel path
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s|cu%d|px2^%d|n2^%d|fast%d/4|deg%d", arch.c_str(), device_cus(), log2_bucket(px),
+                log2_bucket(descs.size()), fast_frac, deg);
+  return buf;
+}
+}  // namespace
+
+}  // namespace mact
+
+using namespace mact;
+
+struct mact_batch_plan {
+  int device = 0;
+  int32_t count = 0;  // descriptors
+  int deg = 5;
+  mact_tune tune{};
+  uint32_t total_tiles = 0;
+  BDesc* d_descs = nullptr;
+  KCoef* d_coefs = nullptr;
+  uint32_t* d_tiles = nullptr;
+  size_t tiles_cap = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<BDesc> descs;
+};
+
+static void plan_free(mact_batch_plan* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->d_descs) (void)hipFree(p->d_descs);
+  if (p->d_coefs) (void)hipFree(p->d_coefs);
+  if (p->d_tiles) (void)hipFree(p->d_tiles);
+  delete p;
+}
+
+// Upload the tile list for plan->tune.tile (synchronous on the capture stream).
+static mact_status plan_set_tiles(mact_batch_plan* p) {
+  std::vector<uint32_t> ts;
+  p->total_tiles = build_tiles(p->descs, (uint32_t)p->tune.tile, &ts);
+  const size_t bytes = ts.size() * sizeof(uint32_t);
+  mact_status s = hip_check(hipMemcpyAsync(p->d_tiles, ts.data(), bytes, hipMemcpyHostToDevice, p->cap_stream),
+                            "mact_batch_plan: tile upload");
+  if (s != MACT_OK) return s;
+  return hip_check(hipStreamSynchronize(p->cap_stream), "mact_batch_plan: tile upload");
+}
+
+static mact_status plan_time(mact_batch_plan* p, int reps, float* ms) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return fail(MACT_E_DEVICE, "mact_batch_plan: event");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(MACT_E_DEVICE, "mact_batch_plan: event");
+  }
+  mact_status s = MACT_OK;
+  float best = INFINITY;
+  for (int r = 0; r < reps && s == MACT_OK; ++r) {
+    (void)hipEventRecord(a, p->cap_stream);
+    s = hip_check(launch_batch_kernel(p->d_descs, p->d_coefs, p->d_tiles, p->count, p->total_tiles, p->tune, p->deg,
+                                      p->cap_stream),
+                  "mact_batch_plan: autotune launch");
+    (void)hipEventRecord(b, p->cap_stream);
+    if (s == MACT_OK) s = hip_check(hipEventSynchronize(b), "mact_batch_plan: autotune");
+    float t = 0.0f;
+    if (s == MACT_OK && hipEventElapsedTime(&t, a, b) == hipSuccess) best = std::min(best, t);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  *ms = best;
+  return s;
+}
+
+static mact_status plan_autotune(mact_batch_plan* p) {
+  const std::string key = shape_key(p->descs, p->deg);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    load_cache_file_locked();
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      p->tune = it->second;
+      return plan_set_tiles(p);
+    }
+  }
+  static const int blocks[] = {256, 512, 1024};
+  static const int tiles[] = {8192, 32768, 131072};
+  static const int vecs[] = {4, 1};
+  static const int waves[] = {16, 32};
+  mact_tune best{};
+  float best_ms = INFINITY;
+  for (int v : vecs)
+    for (int b : blocks)
+      for (int t : tiles)
+        for (int w : waves) {
+          p->tune = mact_tune{b, t, v, w};
+          mact_status s = plan_set_tiles(p);
+          if (s != MACT_OK) return s;
+          float ms = INFINITY;
+          if ((s = plan_time(p, 2, &ms)) != MACT_OK) return s;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = p->tune;
+          }
+        }
+  p->tune = best;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache[key] = best;
+    save_cache_file_locked();
+  }
+  return plan_set_tiles(p);
+}
+
+static mact_status plan_capture(mact_batch_plan* p) {
+  if (p->exec) {
+    (void)hipGraphExecDestroy(p->exec);
+    p->exec = nullptr;
+  }
+  if (p->graph) {
+    (void)hipGraphDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  mact_status s = hip_check(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal),
+                            "mact_batch_plan: begin capture");
+  if (s != MACT_OK) return s;
+  hipError_t le = launch_batch_kernel(p->d_descs, p->d_coefs, p->d_tiles, p->count, p->total_tiles, p->tune, p->deg,
+                                      p->cap_stream);
+  hipError_t ce = hipStreamEndCapture(p->cap_stream, &p->graph);
+  if ((s = hip_check(le, "mact_batch_plan: captured launch")) != MACT_OK) return s;
+  if ((s = hip_check(ce, "mact_batch_plan: end capture")) != MACT_OK) return s;
+  return hip_check(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0), "mact_batch_plan: instantiate");
+}
+
+extern "C" mact_status mact_batch_plan_create(const mact_params* params, const mact_image* in, const mact_image* out,
+                                              int32_t count, const mact_tune* tune, void* hip_stream,
+                                              mact_batch_plan** plan) {
+  clear_error();
+  if (!plan) return fail(MACT_E_INVALID, "mact_batch_plan_create: plan is NULL");
+  *plan = nullptr;
+  if (count <= 0) return fail(MACT_E_INVALID, "mact_batch_plan_create: count %d <= 0", count);
+  if (!params || !in || !out) return fail(MACT_E_INVALID, "mact_batch_plan_create: NULL array");
+  if (tune) {
+    mact_status s = check_tune(*tune);
+    if (s != MACT_OK) return s;
+  }
+  mact_batch_plan* p = new (std::nothrow) mact_batch_plan();
+  if (!p) return fail(MACT_E_NOMEM, "mact_batch_plan_create: host allocation");
+  p->device = current_device();
+  // coefficient table with duplicates folded
+  std::vector<KCoef> coefs;
+  for (int32_t i = 0; i < count; ++i) {
+    KCoef k;
+    mact_status s = check_params(&params[i]);
+    if (s != MACT_OK) {
+      plan_free(p);
+      return fail(s, "mact_batch_plan_create: image %d: %s", i, mact_last_error());
+    }
+    pack_coef(params[i], &k);
+    int32_t idx = -1;
+    for (size_t j = 0; j < coefs.size(); ++j)
+      if (std::memcmp(&coefs[j], &k, sizeof k) == 0) idx = (int32_t)j;
+    if (idx < 0) {
+      idx = (int32_t)coefs.size();
+      coefs.push_back(k);
+    }
+    int deg = 5;
+    char what[64];
+    std::snprintf(what, sizeof what, "mact_batch_plan_create: image %d", i);
+    if ((s = make_batch_descs(params[i], &in[i], &out[i], idx, &p->descs, &deg, what)) != MACT_OK) {
+      plan_free(p);
+      return s;
+    }
+    p->deg = std::max(p->deg, deg);
+  }
+  p->count = (int32_t)p->descs.size();
+  hipStream_t user = static_cast<hipStream_t>(hip_stream);
+  mact_status s = MACT_OK;
+  const size_t tiles_bytes = (p->descs.size() + 1) * sizeof(uint32_t);
+  if (hipMalloc(&p->d_descs, p->descs.size() * sizeof(BDesc)) != hipSuccess ||
+      hipMalloc(&p->d_coefs, coefs.size() * sizeof(KCoef)) != hipSuccess ||
+      hipMalloc(&p->d_tiles, tiles_bytes) != hipSuccess) {
+    plan_free(p);
+    return fail(MACT_E_NOMEM, "mact_batch_plan_create: device allocation");
+  }
+  if (s == MACT_OK) s = hip_check(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "mact_batch_plan_create: stream");
+  if (s == MACT_OK)
+    s = hip_check(hipMemcpyAsync(p->d_descs, p->descs.data(), p->descs.size() * sizeof(BDesc), hipMemcpyHostToDevice,
+                                 p->cap_stream), "mact_batch_plan_create: upload");
+  if (s == MACT_OK)
+    s = hip_check(hipMemcpyAsync(p->d_coefs, coefs.data(), coefs.size() * sizeof(KCoef), hipMemcpyHostToDevice,
+                                 p->cap_stream), "mact_batch_plan_create: upload");
+  // inputs written on the caller's stream must be complete before the autotuner runs
+  if (s == MACT_OK) s = hip_check(hipStreamSynchronize(user), "mact_batch_plan_create: caller stream");
+  if (s == MACT_OK) {
+    if (tune) {
+      p->tune = *tune;
+      s = plan_set_tiles(p);
+    } else {
+      s = plan_autotune(p);
+    }
+  }
+  if (s == MACT_OK) s = plan_capture(p);
+  if (s != MACT_OK) {
+    plan_free(p);
+    return s;
+  }
+  *plan = p;
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_batch_plan_launch(mact_batch_plan* p, int32_t use_graph, void* hip_stream) {
+  clear_error();
+  if (!p) return fail(MACT_E_INVALID, "mact_batch_plan_launch: plan is NULL");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (use_graph) return hip_check(hipGraphLaunch(p->exec, st), "mact_batch_plan_launch: graph launch");
+  return hip_check(launch_batch_kernel(p->d_descs, p->d_coefs, p->d_tiles, p->count, p->total_tiles, p->tune, p->deg, st),
+                   "mact_batch_plan_launch: launch");
+}
+
+extern "C" mact_status mact_batch_plan_tune(const mact_batch_plan* p, mact_tune* tune) {
+  clear_error();
+  if (!p || !tune) return fail(MACT_E_INVALID, "mact_batch_plan_tune: NULL argument");
+  *tune = p->tune;
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_batch_plan_destroy(mact_batch_plan* p) {
+  clear_error();
+  plan_free(p);
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_batch_run(const mact_params* params, const mact_image* in, const mact_image* out,
+                                      int32_t count, const mact_tune* tune, void* hip_stream) {
+  mact_batch_plan* p = nullptr;
+  mact_status s = mact_batch_plan_create(params, in, out, count, tune, hip_stream, &p);
+  if (s != MACT_OK) return s;
+  s = mact_batch_plan_launch(p, 1, hip_stream);
+  if (s == MACT_OK) s = hip_check(hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)), "mact_batch_run: synchronise");
+  plan_free(p);
+  return s;
+}

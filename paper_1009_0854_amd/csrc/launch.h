@@ -1,0 +1,69 @@
+// Host-side helpers for launching libmact kernels: image descriptor
+// resolution and validation, coefficient packing, device properties.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "pixel.h"
+
+namespace mact {
+
+// A validated caller image with every stride resolved.
+struct HostImage {
+  void* data = nullptr;
+  int dtype = 0, layout = 0, gamma = 0;
+  int64_t W = 0, H = 0, N = 1;
+  int64_t rs = 0, ps = 0, bs = 0;
+  bool packed = false;
+  size_t esize = 1;
+};
+
+FastDiv make_fastdiv(uint32_t d);
+
+// Validates *im (input images accept U8/F16/F32, outputs F16/F32).
+mact_status resolve_image(const mact_image* im, bool is_output, const char* what, HostImage* out);
+// Same width, height and batch.
+mact_status check_same_shape(const HostImage& a, const HostImage& b, const char* what);
+// Kernel view of images [n0, n0 + count) of a resolved image.
+KImage kimage(const HostImage& h, int64_t n0, int64_t count);
+// Images per launch so that a launch covers fewer than 2^31 pixels.
+int64_t images_per_launch(const HostImage& h);
+
+// Coefficients rounded to float32 and zero padded; returns the padded degree
+// (5 or 7) the kernels are instantiated for.
+int pack_coef(const mact_params& p, KCoef* k);
+
+// One image of a batched launch (device-side descriptor).
+struct BDesc {
+  KImage src, dst;
+  uint32_t n_px;  // pixels (N H W) of this descriptor, < 2^31
+  int32_t coef;   // index into the coefficient table
+  int32_t gamma;  // inverse-gamma row for 8-bit LAB inputs
+  int32_t fast;   // packed 8-bit HWC in, packed float32 HWC out, aligned: 4-pixel path
+};
+
+// Host preparation of one batch entry: validates (params, in, out) and appends
+// its descriptors (several if the image holds 2^31 pixels or more) to `descs`;
+// the coefficient index is set to `coef`.  *deg receives the padded degree.
+mact_status make_batch_descs(const mact_params& p, const mact_image* in, const mact_image* out, int32_t coef,
+                             std::vector<BDesc>* descs, int* deg, const char* what);
+// Launch of the persistent batched kernel.
+hipError_t launch_batch_kernel(const BDesc* d_descs, const KCoef* d_coefs, const uint32_t* d_tiles, int32_t count,
+                               uint32_t total_tiles, const mact_tune& tune, int deg, hipStream_t st);
+// Grid of the batched kernel for a tune and a tile count.
+unsigned batch_grid(const mact_tune& tune, uint32_t total_tiles);
+// Tile list: tile_start[i] = first tile of descriptor i; returns the total.
+uint32_t build_tiles(const std::vector<BDesc>& descs, uint32_t tile, std::vector<uint32_t>* tile_start);
+
+// Compute units of the current device (cached per device).
+int device_cus();
+int current_device();
+
+inline mact_status hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return MACT_OK;
+  return fail(MACT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace mact

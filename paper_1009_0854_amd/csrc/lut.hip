@@ -1,0 +1,306 @@
+// 3-D LUT packing and interpolation (Sec. 3.5.3): the comparison path.
+//
+// Packing runs on the host in FP64 (the exact transform at every node) and
+// uploads float32 nodes.  A node is one float4 (LAB: L*, a*, b*, 0; HSI:
+// cos H, sin H, S, I) or two (SCT: L, cos A, sin A, cos B | sin B, 0, 0, 0):
+// angular channels are stored as unit vectors so that circular interpolation
+// needs no trigonometry per corner.
+//
+// Interpolation: one pixel per lane step over a grid of a few workgroups per
+// CU.  When the packed grid fits the workgroup's LDS (17^3 x 16 B = 78.6 KB) it
+// is staged there once per workgroup and every corner gather is an LDS read;
+// larger grids (33^3 x 16 B = 575 KB) are gathered from global memory through
+// the L2.  Each method is a weighted sum of its 8, 6, 5 or 4 corners.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "launch.h"
+
+namespace mact {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+static int node_floats(int xform) { return xform == MACT_SCT ? 8 : 4; }
+
+// ---------------------------------------------------------------- device
+
+template <bool LDS>
+struct NodeSrc {
+  const f4* p;
+  __device__ __forceinline__ f4 at(uint32_t i) const { return p[i]; }
+};
+
+// Extraction: cell and fraction per channel.
+__device__ __forceinline__ void locate_u8(uint32_t v, uint32_t N, uint32_t& i, float& f) {
+  const uint32_t num = v * (N - 1);
+  i = min(num / 255u, N - 2);
+  f = (float)(num - 255u * i) * kInv255;
+}
+
+__device__ __forceinline__ void locate_f(float x, uint32_t N, uint32_t& i, float& f) {
+  const float pos = x * (float)(N - 1);
+  i = min((uint32_t)pos, N - 2);  // x >= 0 after clamping
+  f = pos - (float)i;
+}
+
+// Corner weights of each method, as (offset, weight) pairs; K = 8, 6, 5, 4.
+template <int METHOD>
+struct Corners;
+
+template <>
+struct Corners<MACT_TRILINEAR> {
+  static constexpr int K = 8;
+  __device__ __forceinline__ static void get(float fr, float fg, float fb, uint32_t sR, uint32_t sG, uint32_t off[8],
+                                             float w[8]) {
+    const float r0 = 1.0f - fr, g0 = 1.0f - fg, b0 = 1.0f - fb;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int dr = c >> 2, dg = (c >> 1) & 1, db = c & 1;
+      off[c] = dr * sR + dg * sG + db;
+      w[c] = (dr ? fr : r0) * (dg ? fg : g0) * (db ? fb : b0);
+    }
+  }
+};
+
+template <>
+struct Corners<MACT_TETRAHEDRAL> {
+  static constexpr int K = 4;
+  __device__ __forceinline__ static void get(float fr, float fg, float fb, uint32_t sR, uint32_t sG, uint32_t off[4],
+                                             float w[4]) {
+    // decreasing order of the fractions, ties R before G before B
+    float f1, f2, f3;
+    uint32_t s1, s2;
+    if (fr >= fg) {
+      if (fg >= fb) { f1 = fr; f2 = fg; f3 = fb; s1 = sR; s2 = sG; }
+      else if (fr >= fb) { f1 = fr; f2 = fb; f3 = fg; s1 = sR; s2 = 1; }
+      else { f1 = fb; f2 = fr; f3 = fg; s1 = 1; s2 = sR; }
+    } else {
+      if (fr >= fb) { f1 = fg; f2 = fr; f3 = fb; s1 = sG; s2 = sR; }
+      else if (fg >= fb) { f1 = fg; f2 = fb; f3 = fr; s1 = sG; s2 = 1; }
+      else { f1 = fb; f2 = fg; f3 = fr; s1 = 1; s2 = sG; }
+    }
+    off[0] = 0; w[0] = 1.0f - f1;
+    off[1] = s1; w[1] = f1 - f2;
+    off[2] = s1 + s2; w[2] = f2 - f3;
+    off[3] = sR + sG + 1; w[3] = f3;
+  }
+};
+
+template <>
+struct Corners<MACT_PRISM> {
+  static constexpr int K = 6;
+  __device__ __forceinline__ static void get(float fr, float fg, float fb, uint32_t sR, uint32_t sG, uint32_t off[6],
+                                             float w[6]) {
+    // linear along R; triangle of the (G, B) face chosen by f_G >= f_B
+    uint32_t t1;
+    float w0, w1, w2;
+    if (fg >= fb) { t1 = sG; w0 = 1.0f - fg; w1 = fg - fb; w2 = fb; }
+    else { t1 = 1; w0 = 1.0f - fb; w1 = fb - fg; w2 = fg; }
+    const float r0 = 1.0f - fr;
+    off[0] = 0; w[0] = r0 * w0;
+    off[1] = t1; w[1] = r0 * w1;
+    off[2] = sG + 1; w[2] = r0 * w2;
+    off[3] = sR; w[3] = fr * w0;
+    off[4] = sR + t1; w[4] = fr * w1;
+    off[5] = sR + sG + 1; w[5] = fr * w2;
+  }
+};
+
+template <>
+struct Corners<MACT_PYRAMIDAL> {
+  static constexpr int K = 5;
+  __device__ __forceinline__ static void get(float fr, float fg, float fb, uint32_t sR, uint32_t sG, uint32_t off[5],
+                                             float w[5]) {
+    // smallest fraction s (ties R before G before B); u, v the other two in R, G, B order
+    float fs, fu, fv;
+    uint32_t ss, su, sv;
+    if (fr <= fg && fr <= fb) { fs = fr; fu = fg; fv = fb; ss = sR; su = sG; sv = 1; }
+    else if (fg <= fb) { fs = fg; fu = fr; fv = fb; ss = sG; su = sR; sv = 1; }
+    else { fs = fb; fu = fr; fv = fg; ss = 1; su = sR; sv = sG; }
+    const float uv = fu * fv;
+    // c000 + (c111 - c0uv) fs + (c0u0 - c000) fu + (c00v - c000) fv + (c0uv - c00v - c0u0 + c000) fu fv
+    off[0] = 0; w[0] = ((1.0f - fu) - fv) + uv;
+    off[1] = ss + su + sv; w[1] = fs;
+    off[2] = su + sv; w[2] = uv - fs;
+    off[3] = su; w[3] = fu - uv;
+    off[4] = sv; w[4] = fv - uv;
+  }
+};
+
+template <int METHOD, int XF, bool LDS>
+__global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32_t N, KImage src, KImage dst,
+                                             uint32_t n_px) {
+  extern __shared__ f4 s_lut[];
+  const int NF = XF == MACT_SCT ? 2 : 1;  // float4 per node
+  const uint32_t n_nodes = N * N * N;
+  const f4* nodes = lut;
+  if (LDS) {
+    for (uint32_t i = threadIdx.x; i < n_nodes * NF; i += blockDim.x) s_lut[i] = lut[i];
+    __syncthreads();
+    nodes = s_lut;
+  }
+  const uint32_t sR = N * N, sG = N;
+  const bool u8 = src.dtype == MACT_U8;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n_px; p += stride) {
+    float v[3];
+    load_px(src, p, v);
+    uint32_t i[3];
+    float f[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (u8) locate_u8((uint32_t)v[c], N, i[c], f[c]);
+      else locate_f(v[c], N, i[c], f[c]);
+    }
+    const uint32_t base = (i[0] * N + i[1]) * N + i[2];
+    uint32_t off[8];
+    float w[8];
+    Corners<METHOD>::get(f[0], f[1], f[2], sR, sG, off, w);
+    f4 a0 = {0.0f, 0.0f, 0.0f, 0.0f}, a1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < Corners<METHOD>::K; ++c) {
+      const uint32_t n = (base + off[c]) * NF;
+      const f4 v0 = nodes[n];
+      a0.x = __builtin_fmaf(w[c], v0.x, a0.x);
+      a0.y = __builtin_fmaf(w[c], v0.y, a0.y);
+      a0.z = __builtin_fmaf(w[c], v0.z, a0.z);
+      a0.w = __builtin_fmaf(w[c], v0.w, a0.w);
+      if (NF == 2) a1.x = __builtin_fmaf(w[c], nodes[n + 1].x, a1.x);
+    }
+    float o[3];
+    if (XF == MACT_LAB) {
+      o[0] = a0.x; o[1] = a0.y; o[2] = a0.z;
+    } else if (XF == MACT_HSI) {
+      float h = atan2f(a0.y, a0.x);
+      if (h < 0.0f) h += kTwoPif;
+      o[0] = h; o[1] = a0.z; o[2] = a0.w;
+    } else {
+      o[0] = a0.x;
+      o[1] = atan2f(a0.z, a0.y);
+      o[2] = atan2f(a1.x, a0.w);
+    }
+    store_px(dst, p, o);
+  }
+}
+
+// ---------------------------------------------------------------- host
+
+int max_lds_bytes() {
+  static int cache[64] = {0};
+  const int d = current_device();
+  if (d >= 0 && d < 64 && cache[d]) return cache[d];
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, d) != hipSuccess || v <= 0) v = 65536;
+  if (d >= 0 && d < 64) cache[d] = v;
+  return v;
+}
+
+template <int METHOD, int XF>
+static hipError_t launch_lut(const f4* lut, uint32_t N, const KImage& s, const KImage& d, uint32_t n_px,
+                             hipStream_t st) {
+  const size_t bytes = (size_t)N * N * N * node_floats(XF) * sizeof(float);
+  const bool lds = bytes <= (size_t)max_lds_bytes();
+  // staging costs one grid read per workgroup: when staging, one long-lived
+  // 1024-thread workgroup per CU (two if two copies fit the CU's LDS)
+  const unsigned block = lds ? 1024 : 256;
+  const uint64_t need = (n_px + block - 1) / block;
+  const uint64_t per_cu = lds ? std::max<uint64_t>(1, (uint64_t)max_lds_bytes() / bytes) : 8;
+  const uint64_t cap = (uint64_t)device_cus() * std::min<uint64_t>(per_cu, 2);
+  const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(need, cap));
+  if (lds) {
+    auto k = k_lut<METHOD, XF, true>;
+    if (bytes > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3(grid), dim3(block), bytes, st, lut, N, s, d, n_px);
+  } else {
+    hipLaunchKernelGGL((k_lut<METHOD, XF, false>), dim3(grid), dim3(block), 0, st, lut, N, s, d, n_px);
+  }
+  return hipGetLastError();
+}
+
+template <int XF>
+static hipError_t launch_lut_m(int method, const f4* lut, uint32_t N, const KImage& s, const KImage& d, uint32_t n_px,
+                               hipStream_t st) {
+  switch (method) {
+    case MACT_TRILINEAR: return launch_lut<MACT_TRILINEAR, XF>(lut, N, s, d, n_px, st);
+    case MACT_PRISM: return launch_lut<MACT_PRISM, XF>(lut, N, s, d, n_px, st);
+    case MACT_PYRAMIDAL: return launch_lut<MACT_PYRAMIDAL, XF>(lut, N, s, d, n_px, st);
+    default: return launch_lut<MACT_TETRAHEDRAL, XF>(lut, N, s, d, n_px, st);
+  }
+}
+
+}  // namespace mact
+
+using namespace mact;
+
+extern "C" size_t lut_bytes(int32_t xform, int32_t n) {
+  if (xform < MACT_LAB || xform > MACT_SCT || n < 2 || n > 256) return 0;
+  return (size_t)n * n * n * node_floats(xform) * sizeof(float);
+}
+
+extern "C" mact_status lut_build(int32_t xform, int32_t n, int32_t gamma, float* dev_lut, size_t bytes,
+                                 void* hip_stream) {
+  clear_error();
+  const size_t need = lut_bytes(xform, n);
+  if (need == 0) return fail(MACT_E_INVALID, "lut_build: transform %d / size %d invalid (n in 2..256)", xform, n);
+  if (!dev_lut) return fail(MACT_E_INVALID, "lut_build: dev_lut is NULL");
+  if (bytes < need) return fail(MACT_E_INVALID, "lut_build: %zu bytes < %zu needed", bytes, need);
+  if (gamma < MACT_GAMMA_BT709 || gamma > MACT_GAMMA_NONE) return fail(MACT_E_INVALID, "lut_build: gamma %d", gamma);
+  const int nf = node_floats(xform);
+  std::vector<float> host((size_t)n * n * n * nf, 0.0f);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k) {
+        const double rgb[3] = {(double)i / (n - 1), (double)j / (n - 1), (double)k / (n - 1)};
+        double o[3];
+        float* dst = &host[((size_t)(i * n + j) * n + k) * nf];
+        if (xform == MACT_LAB) {
+          exact_lab(rgb, gamma, o);
+          dst[0] = (float)o[0]; dst[1] = (float)o[1]; dst[2] = (float)o[2];
+        } else if (xform == MACT_HSI) {
+          exact_hsi(rgb, o);
+          dst[0] = (float)std::cos(o[0]); dst[1] = (float)std::sin(o[0]); dst[2] = (float)o[1]; dst[3] = (float)o[2];
+        } else {
+          exact_sct(rgb, o);
+          dst[0] = (float)o[0];
+          dst[1] = (float)std::cos(o[1]); dst[2] = (float)std::sin(o[1]);
+          dst[3] = (float)std::cos(o[2]); dst[4] = (float)std::sin(o[2]);
+        }
+      }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  mact_status s = hip_check(hipMemcpyAsync(dev_lut, host.data(), need, hipMemcpyHostToDevice, st), "lut_build: copy");
+  if (s != MACT_OK) return s;
+  return hip_check(hipStreamSynchronize(st), "lut_build: synchronise");
+}
+
+extern "C" mact_status lut_interp(const float* dev_lut, int32_t n, int32_t xform, int32_t method, const mact_image* in,
+                                  const mact_image* out, void* hip_stream) {
+  clear_error();
+  if (!dev_lut) return fail(MACT_E_INVALID, "lut_interp: dev_lut is NULL");
+  if (lut_bytes(xform, n) == 0) return fail(MACT_E_INVALID, "lut_interp: transform %d / size %d invalid", xform, n);
+  if (method < MACT_TRILINEAR || method > MACT_TETRAHEDRAL) return fail(MACT_E_INVALID, "lut_interp: method %d", method);
+  if ((uintptr_t)dev_lut % 16) return fail(MACT_E_INVALID, "lut_interp: dev_lut not 16-byte aligned");
+  HostImage hi, ho;
+  mact_status s;
+  if ((s = resolve_image(in, false, "lut_interp: in", &hi)) != MACT_OK) return s;
+  if ((s = resolve_image(out, true, "lut_interp: out", &ho)) != MACT_OK) return s;
+  if ((s = check_same_shape(hi, ho, "lut_interp: out")) != MACT_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const f4* lut = reinterpret_cast<const f4*>(dev_lut);
+  const int64_t per = images_per_launch(hi);
+  for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
+    const int64_t cnt = std::min(per, hi.N - n0);
+    const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
+    const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
+    hipError_t e;
+    if (xform == MACT_LAB) e = launch_lut_m<MACT_LAB>(method, lut, n, ks, kd, n_px, st);
+    else if (xform == MACT_HSI) e = launch_lut_m<MACT_HSI>(method, lut, n, ks, kd, n_px, st);
+    else e = launch_lut_m<MACT_SCT>(method, lut, n, ks, kd, n_px, st);
+    if ((s = hip_check(e, "lut_interp: launch")) != MACT_OK) return s;
+  }
+  return MACT_OK;
+}

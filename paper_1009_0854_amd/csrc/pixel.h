@@ -1,0 +1,230 @@
+// Per-pixel MACT arithmetic and pixel addressing, shared by every kernel of
+// libmact (plain, batched, served).  One definition of the arithmetic is what
+// makes the three forms bitwise identical: every multiply-add that matters is
+// an explicit fmaf and the sources are compiled with -ffp-contract=off.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mact {
+
+// ---------------------------------------------------------------- constants
+
+// diag(1/white) * M, rounded once from the double values (Sec. 3.2.1).
+#define MW(r, c) static_cast<float>(kM[r][c] / kWhite[r])
+constexpr float kMw00 = MW(0, 0), kMw01 = MW(0, 1), kMw02 = MW(0, 2);
+constexpr float kMw10 = MW(1, 0), kMw11 = MW(1, 1), kMw12 = MW(1, 2);
+constexpr float kMw20 = MW(2, 0), kMw21 = MW(2, 1), kMw22 = MW(2, 2);
+#undef MW
+constexpr float kT0f = static_cast<float>(kLabT0);
+constexpr float kLabKf = static_cast<float>(kLabK);
+constexpr float kLabCf = static_cast<float>(kLabC);
+constexpr float kPi3f = static_cast<float>(kPi / 3.0);
+constexpr float kPif = static_cast<float>(kPi);
+constexpr float k5Pi3f = static_cast<float>(5.0 * kPi / 3.0);
+constexpr float kPi2f = static_cast<float>(kPi / 2.0);
+constexpr float kTwoPif = static_cast<float>(2.0 * kPi);
+constexpr float kInv255 = static_cast<float>(1.0 / 255.0);
+constexpr float kInv765 = static_cast<float>(1.0 / 765.0);
+constexpr float kInv3 = static_cast<float>(1.0 / 3.0);
+
+// ---------------------------------------------------------------- parameters
+
+// Coefficients of one transform, float32, zero-padded to degree 7.  Horner's
+// rule over zero leading coefficients is exact, so evaluating at a padded
+// degree gives the same bits as at the true degree.
+struct KCoef {
+  float p[4][8];  // numerators of f[0..3]
+  float q[8];     // denominator of f[0] (LAB); {1, 0, ...} otherwise
+  int32_t xform, out_mode;
+};
+
+// One image as the kernels see it.  Pixel index p in [0, N H W) of one launch
+// is 32-bit; the host splits larger launches.
+struct FastDiv {  // n / d for 32-bit n and a fixed d >= 1 (round-up multiplier method)
+  uint32_t d, m, s;
+  __device__ __forceinline__ uint32_t div(uint32_t n) const {
+    return (uint32_t)(((uint64_t)__umulhi(n, m) + n) >> s);
+  }
+};
+
+struct KImage {
+  void* ptr;
+  int32_t dtype, layout;
+  int64_t rs, ps, bs;  // row, plane, batch strides in elements (resolved)
+  uint32_t W, HW;      // width, pixels per image
+  uint32_t packed;     // HWC: element (p, c) at 3 p + c;  CHW: batch and planes packed
+  FastDiv div_w, div_hw;
+};
+
+// ---------------------------------------------------------------- polynomial
+
+template <int DEG>
+__device__ __forceinline__ float horner(const float* c, float x) {
+  float acc = c[DEG];
+#pragma unroll
+  for (int k = DEG - 1; k >= 0; --k) acc = __builtin_fmaf(acc, x, c[k]);
+  return acc;
+}
+
+// a / b through the hardware reciprocal (about one ulp) and one multiply.
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// ---------------------------------------------------------------- transforms
+
+// Linear RGB -> the three approximated nonlinearity values (Sec. 3.2).
+template <int DEG>
+__device__ __forceinline__ void lab_f3(const KCoef& k, float lr, float lg, float lb, float f[3]) {
+  const float t[3] = {
+      __builtin_fmaf(kMw00, lr, __builtin_fmaf(kMw01, lg, kMw02 * lb)),
+      __builtin_fmaf(kMw10, lr, __builtin_fmaf(kMw11, lg, kMw12 * lb)),
+      __builtin_fmaf(kMw20, lr, __builtin_fmaf(kMw21, lg, kMw22 * lb)),
+  };
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (t[c] > kT0f)
+      f[c] = fdiv(horner<DEG>(k.p[0], t[c]), horner<DEG>(k.q, t[c]));
+    else
+      f[c] = __builtin_fmaf(kLabKf, t[c], kLabCf);
+  }
+}
+
+template <int DEG>
+__device__ __forceinline__ void lab_px(const KCoef& k, float lr, float lg, float lb, float o[3]) {
+  float f[3];
+  lab_f3<DEG>(k, lr, lg, lb, f);
+  if (k.out_mode == 1) {
+    o[0] = f[0];
+    o[1] = f[1];
+    o[2] = f[2];
+    return;
+  }
+  o[0] = __builtin_fmaf(116.0f, f[1], -16.0f);
+  o[1] = 500.0f * (f[0] - f[1]);
+  o[2] = 200.0f * (f[1] - f[2]);
+}
+
+// HSI by Kender's branches with the arctan(sqrt 3 x) polynomial (Sec. 3.3).
+// R, G, B on any common scale; `iscale` maps (R+G+B) to I.
+template <int DEG>
+__device__ __forceinline__ void hsi_px(const KCoef& k, float R, float G, float B, float iscale, float o[3]) {
+  float num, den, base;
+  bool act = true;
+  if (R > B && G > B) {
+    num = G - R; den = (G - B) + (R - B); base = kPi3f;
+  } else if (G > R) {
+    num = B - G; den = (B - R) + (G - R); base = kPif;
+  } else if (B > G) {
+    num = R - B; den = (R - G) + (B - G); base = k5Pi3f;
+  } else {
+    num = 0.0f; den = 1.0f; base = 0.0f; act = false;
+  }
+  float H = 0.0f;
+  if (act) {
+    const float x = fdiv(num, den);
+    const float v = horner<DEG>(k.p[0], __builtin_fabsf(x));
+    H = base + (x < 0.0f ? -v : v);
+  }
+  const float sum = (R + G) + B;
+  const float mn = __builtin_fminf(R, __builtin_fminf(G, B));
+  o[0] = H;
+  o[1] = sum > 0.0f ? 1.0f - fdiv(3.0f * mn, sum) : 0.0f;
+  o[2] = sum * iscale;
+}
+
+// SCT with the arcsin/arccos/arctan polynomials (Sec. 3.4).  R, G, B on any
+// common scale; `lscale` maps the norm to L on the [0, 1] input scale.
+template <int DEG>
+__device__ __forceinline__ void sct_px(const KCoef& k, float R, float G, float B, float lscale, float o[3]) {
+  const float rg2 = __builtin_fmaf(R, R, G * G);
+  const float L2 = __builtin_fmaf(B, B, rg2);
+  if (!(L2 > 0.0f)) {
+    o[0] = 0.0f; o[1] = 0.0f; o[2] = 0.0f;
+    return;
+  }
+  const float L = __builtin_sqrtf(L2);
+  float A;
+  if (3.0f * (B * B) >= rg2) {  // B/L >= 0.5: arccos(B/L) = 2 arcsin(sqrt(1 - B/L) / sqrt 2)
+    const float y = __builtin_sqrtf(fdiv(rg2, L * (L + B)));
+    A = horner<DEG>(k.p[0], y);
+  } else {
+    A = horner<DEG>(k.p[1], fdiv(B, L));
+  }
+  float Bang;
+  if (G < R) Bang = horner<DEG>(k.p[2], fdiv(G, R));
+  else if (R > 0.0f) Bang = horner<DEG>(k.p[3], fdiv(R, G));
+  else if (G > 0.0f) Bang = kPi2f;
+  else Bang = 0.0f;
+  o[0] = L * lscale;
+  o[1] = A;
+  o[2] = Bang;
+}
+
+// ---------------------------------------------------------------- inputs
+
+__device__ __forceinline__ float clamp01(float v) { return __builtin_fminf(__builtin_fmaxf(v, 0.0f), 1.0f); }
+
+// Inverse transfer function of a float input already clamped to [0, 1].
+__device__ __forceinline__ float lin_float(float v, int gamma) {
+  if (gamma == MACT_GAMMA_BT709) return v < 0.081f ? v / 4.5f : __builtin_powf((v + 0.099f) / 1.099f, 1.0f / 0.45f);
+  if (gamma == MACT_GAMMA_SRGB) return v <= 0.04045f ? v / 12.92f : __builtin_powf((v + 0.055f) / 1.055f, 2.4f);
+  return v;
+}
+
+// Offset (elements) of channel c of pixel p in an image.
+__device__ __forceinline__ int64_t elem_off(const KImage& im, uint32_t p, int c) {
+  if (im.packed) {
+    if (im.layout == MACT_HWC) return 3 * (int64_t)p + c;
+    const uint32_t n = im.div_hw.div(p);
+    return (int64_t)n * im.bs + (int64_t)c * im.ps + (p - n * im.HW);
+  }
+  const uint32_t n = im.div_hw.div(p);
+  const uint32_t r = p - n * im.HW;
+  const uint32_t y = im.div_w.div(r);
+  const uint32_t x = r - y * im.W;
+  if (im.layout == MACT_HWC) return (int64_t)n * im.bs + (int64_t)y * im.rs + 3 * (int64_t)x + c;
+  return (int64_t)n * im.bs + (int64_t)c * im.ps + (int64_t)y * im.rs + x;
+}
+
+// Raw pixel: 8-bit codes as integer-valued floats, float inputs clamped to [0, 1].
+__device__ __forceinline__ void load_px(const KImage& im, uint32_t p, float v[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t o = elem_off(im, p, c);
+    if (im.dtype == MACT_U8) v[c] = (float)static_cast<const uint8_t*>(im.ptr)[o];
+    else if (im.dtype == MACT_F16) v[c] = clamp01(__half2float(static_cast<const __half*>(im.ptr)[o]));
+    else v[c] = clamp01(static_cast<const float*>(im.ptr)[o]);
+  }
+}
+
+__device__ __forceinline__ void store_px(const KImage& im, uint32_t p, const float o3[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t o = elem_off(im, p, c);
+    if (im.dtype == MACT_F16) static_cast<__half*>(im.ptr)[o] = __float2half_rn(o3[c]);
+    else static_cast<float*>(im.ptr)[o] = o3[c];
+  }
+}
+
+// One pixel of any transform from its raw value (as load_px returns it).
+// `gtab` is the 256-entry inverse gamma of the image's transfer function.
+template <int DEG>
+__device__ __forceinline__ void eval_px(const KCoef& k, bool u8, int gamma, const float* gtab, const float v[3],
+                                        float o[3]) {
+  if (k.xform == MACT_LAB) {
+    float l[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) l[c] = u8 ? gtab[(int)v[c]] : lin_float(v[c], gamma);
+    lab_px<DEG>(k, l[0], l[1], l[2], o);
+  } else if (k.xform == MACT_HSI) {
+    hsi_px<DEG>(k, v[0], v[1], v[2], u8 ? kInv765 : kInv3, o);
+  } else {
+    sct_px<DEG>(k, v[0], v[1], v[2], u8 ? kInv255 : 1.0f, o);
+  }
+}
+
+}  // namespace mact

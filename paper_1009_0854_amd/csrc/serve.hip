@@ -1,0 +1,446 @@
+// Serving form: a continuous-batching engine around the persistent batched
+// kernel.
+//
+// One scheduler thread owns every HIP call after creation.  Its loop:
+//   1. admission -- queued requests are admitted in arrival order while their
+//      input and output bytes fit the device arena (first-fit free list over a
+//      single allocation, 256-byte granules, neighbours merged on free); the
+//      input copy is issued on the copy stream and an event recorded;
+//   2. requests whose input copy has completed become ready;
+//   3. when a compute slot is free, every ready request (up to max_batch) is
+//      put into one batch: descriptors are staged in pinned memory, copied to
+//      the slot's device buffers, the batched kernel is launched on the slot's
+//      stream and each output is copied back on the same stream; batches in
+//      different slots overlap on the device, and requests that arrive while
+//      batches run join the next one;
+//   4. a finished batch completes its requests and returns their arena space.
+// The coefficient table of the three transforms stays resident.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "launch.h"
+
+using namespace mact;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr size_t kGranule = 256;
+
+// First-fit allocator over [0, size) with coalescing.
+class Arena {
+ public:
+  explicit Arena(size_t size) : size_(size) { free_[0] = size; }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = (bytes + kGranule - 1) / kGranule * kGranule;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t start = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        used_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (bytes + kGranule - 1) / kGranule * kGranule;
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t size() const { return size_; }
+
+ private:
+  size_t size_, used_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+struct Req {
+  int64_t id = 0;
+  mact_request r{};
+  size_t in_bytes = 0, out_bytes = 0, in_off = 0, out_off = 0;
+  hipEvent_t ev_in = nullptr;
+  Clock::time_point t_submit, t_done;
+  bool done = false;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_done = nullptr;
+  BDesc* d_descs = nullptr;
+  uint32_t* d_tiles = nullptr;
+  BDesc* h_descs = nullptr;  // pinned staging
+  uint32_t* h_tiles = nullptr;
+  std::vector<Req*> reqs;
+  bool busy = false;
+  Clock::time_point t_launch;
+  hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;
+};
+
+size_t esize(int dtype) { return dtype == MACT_U8 ? 1 : dtype == MACT_F16 ? 2 : 4; }
+
+}  // namespace
+
+struct mact_server {
+  int device = 0;
+  mact_server_config cfg{};
+  int deg = 5;
+  mact_tune tune{512, 32768, 4, 32};
+  std::unique_ptr<Arena> arena;
+  char* d_arena = nullptr;
+  KCoef* d_coefs = nullptr;
+  hipStream_t copy_stream = nullptr;
+  std::vector<Slot> slots;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Req*> queued;   // submitted, not admitted
+  std::vector<Req*> copying; // input copy in flight
+  std::vector<Req*> ready;   // input on the device
+  std::unordered_map<int64_t, std::unique_ptr<Req>> all;
+  std::vector<double> lat_ms;
+  int64_t next_id = 1, submitted = 0, completed = 0, rejected = 0, batches = 0, batched_reqs = 0;
+  double busy_ms = 0.0;
+  bool stop = false;
+  std::thread th;
+  mact_status thread_status = MACT_OK;
+
+  void loop();
+  bool admit_locked();
+  void poll_copies_locked();
+  bool launch_locked(Slot& s);
+  bool finish_slots_locked();
+};
+
+bool mact_server::admit_locked() {
+  bool any = false;
+  while (!queued.empty()) {
+    Req* q = queued.front();
+    size_t in_off, out_off;
+    if (!arena->alloc(q->in_bytes, &in_off)) break;
+    if (!arena->alloc(q->out_bytes, &out_off)) {
+      arena->release(in_off, q->in_bytes);
+      break;
+    }
+    queued.pop_front();
+    q->in_off = in_off;
+    q->out_off = out_off;
+    (void)hipEventCreateWithFlags(&q->ev_in, hipEventDisableTiming);
+    (void)hipMemcpyAsync(d_arena + in_off, q->r.host_in, q->in_bytes, hipMemcpyHostToDevice, copy_stream);
+    (void)hipEventRecord(q->ev_in, copy_stream);
+    copying.push_back(q);
+    any = true;
+  }
+  return any;
+}
+
+void mact_server::poll_copies_locked() {
+  for (size_t i = 0; i < copying.size();) {
+    if (hipEventQuery(copying[i]->ev_in) == hipSuccess) {
+      ready.push_back(copying[i]);
+      copying[i] = copying.back();
+      copying.pop_back();
+    } else {
+      ++i;
+    }
+  }
+}
+
+bool mact_server::launch_locked(Slot& s) {
+  if (ready.empty()) return false;
+  const size_t n = std::min<size_t>(ready.size(), (size_t)cfg.max_batch);
+  // oldest first
+  std::sort(ready.begin(), ready.end(), [](const Req* a, const Req* b) { return a->id < b->id; });
+  s.reqs.assign(ready.begin(), ready.begin() + n);
+  ready.erase(ready.begin(), ready.begin() + n);
+  std::vector<BDesc> descs;
+  descs.reserve(n);
+  for (Req* q : s.reqs) {
+    mact_image in{}, out{};
+    in.data = d_arena + q->in_off;
+    in.dtype = q->r.in_dtype;
+    in.layout = MACT_HWC;
+    in.width = q->r.width;
+    in.height = q->r.height;
+    in.gamma = q->r.gamma;
+    out.data = d_arena + q->out_off;
+    out.dtype = q->r.out_dtype;
+    out.layout = MACT_HWC;
+    out.width = q->r.width;
+    out.height = q->r.height;
+    int d = 5;
+    (void)make_batch_descs(cfg.params[q->r.xform], &in, &out, q->r.xform, &descs, &d, "mact_server");
+  }
+  std::vector<uint32_t> ts;
+  const uint32_t total = build_tiles(descs, (uint32_t)tune.tile, &ts);
+  std::memcpy(s.h_descs, descs.data(), descs.size() * sizeof(BDesc));
+  std::memcpy(s.h_tiles, ts.data(), ts.size() * sizeof(uint32_t));
+  (void)hipMemcpyAsync(s.d_descs, s.h_descs, descs.size() * sizeof(BDesc), hipMemcpyHostToDevice, s.stream);
+  (void)hipMemcpyAsync(s.d_tiles, s.h_tiles, ts.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s.stream);
+  (void)hipEventRecord(s.ev_k0, s.stream);
+  (void)launch_batch_kernel(s.d_descs, d_coefs, s.d_tiles, (int32_t)descs.size(), total, tune, deg, s.stream);
+  (void)hipEventRecord(s.ev_k1, s.stream);
+  for (Req* q : s.reqs)
+    (void)hipMemcpyAsync(q->r.host_out, d_arena + q->out_off, q->out_bytes, hipMemcpyDeviceToHost, s.stream);
+  (void)hipEventRecord(s.ev_done, s.stream);
+  s.busy = true;
+  s.t_launch = Clock::now();
+  ++batches;
+  batched_reqs += (int64_t)n;
+  return true;
+}
+
+bool mact_server::finish_slots_locked() {
+  bool any = false;
+  for (Slot& s : slots) {
+    if (!s.busy || hipEventQuery(s.ev_done) != hipSuccess) continue;
+    const auto now = Clock::now();
+    float kms = 0.0f;
+    if (hipEventElapsedTime(&kms, s.ev_k0, s.ev_k1) == hipSuccess) busy_ms += kms;
+    for (Req* q : s.reqs) {
+      q->t_done = now;
+      q->done = true;
+      arena->release(q->in_off, q->in_bytes);
+      arena->release(q->out_off, q->out_bytes);
+      (void)hipEventDestroy(q->ev_in);
+      q->ev_in = nullptr;
+      lat_ms.push_back(std::chrono::duration<double, std::milli>(q->t_done - q->t_submit).count());
+      ++completed;
+    }
+    s.reqs.clear();
+    s.busy = false;
+    any = true;
+  }
+  return any;
+}
+
+void mact_server::loop() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    bool progress = false;
+    progress |= finish_slots_locked();
+    progress |= admit_locked();
+    poll_copies_locked();
+    for (Slot& s : slots)
+      if (!s.busy) progress |= launch_locked(s);
+    if (progress) cv_done.notify_all();
+    const bool in_flight = !copying.empty() || std::any_of(slots.begin(), slots.end(), [](const Slot& s) { return s.busy; });
+    if (stop && queued.empty() && copying.empty() && ready.empty() && !in_flight) break;
+    if (progress) continue;
+    if (in_flight || !ready.empty()) {
+      // device work outstanding: poll its events again shortly
+      lk.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      lk.lock();
+    } else {
+      cv_work.wait_for(lk, std::chrono::milliseconds(50));
+    }
+  }
+  cv_done.notify_all();
+}
+
+static void server_free(mact_server* s) {
+  if (!s) return;
+  for (Slot& sl : s->slots) {
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.ev_done) (void)hipEventDestroy(sl.ev_done);
+    if (sl.ev_k0) (void)hipEventDestroy(sl.ev_k0);
+    if (sl.ev_k1) (void)hipEventDestroy(sl.ev_k1);
+    if (sl.d_descs) (void)hipFree(sl.d_descs);
+    if (sl.d_tiles) (void)hipFree(sl.d_tiles);
+    if (sl.h_descs) (void)hipHostFree(sl.h_descs);
+    if (sl.h_tiles) (void)hipHostFree(sl.h_tiles);
+  }
+  if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+  if (s->d_arena) (void)hipFree(s->d_arena);
+  if (s->d_coefs) (void)hipFree(s->d_coefs);
+  delete s;
+}
+
+extern "C" mact_status mact_server_create(const mact_server_config* cfg, mact_server** srv) {
+  clear_error();
+  if (!cfg || !srv) return fail(MACT_E_INVALID, "mact_server_create: NULL argument");
+  *srv = nullptr;
+  if (cfg->arena_bytes < (1u << 20)) return fail(MACT_E_INVALID, "mact_server_create: arena_bytes < 1 MiB");
+  if (cfg->max_batch < 1 || cfg->max_batch > 4096) return fail(MACT_E_INVALID, "mact_server_create: max_batch %d", cfg->max_batch);
+  if (cfg->compute_streams < 1 || cfg->compute_streams > 8)
+    return fail(MACT_E_INVALID, "mact_server_create: compute_streams %d outside 1..8", cfg->compute_streams);
+  if (cfg->max_queue < 1) return fail(MACT_E_INVALID, "mact_server_create: max_queue %d", cfg->max_queue);
+  for (int x = 0; x < 3; ++x) {
+    if (cfg->params[x].xform != x)
+      return fail(MACT_E_INVALID, "mact_server_create: params[%d].xform must be %d", x, x);
+    mact_status st = check_params(&cfg->params[x]);
+    if (st != MACT_OK) return st;
+  }
+  mact_server* s = new (std::nothrow) mact_server();
+  if (!s) return fail(MACT_E_NOMEM, "mact_server_create: host allocation");
+  s->cfg = *cfg;
+  s->device = current_device();
+  KCoef k[3];
+  for (int x = 0; x < 3; ++x) s->deg = std::max(s->deg, pack_coef(cfg->params[x], &k[x]));
+  s->arena.reset(new Arena(cfg->arena_bytes));
+  mact_status st = MACT_OK;
+  if (hipMalloc(&s->d_arena, cfg->arena_bytes) != hipSuccess || hipMalloc(&s->d_coefs, sizeof k) != hipSuccess) {
+    server_free(s);
+    return fail(MACT_E_NOMEM, "mact_server_create: device allocation of %zu bytes", cfg->arena_bytes);
+  }
+  st = hip_check(hipMemcpy(s->d_coefs, k, sizeof k, hipMemcpyHostToDevice), "mact_server_create: coefficients");
+  if (st == MACT_OK) st = hip_check(hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking), "mact_server_create: stream");
+  s->slots.resize(cfg->compute_streams);
+  // descriptors per slot: an image of 2^31 pixels or more splits, but requests are single images
+  const size_t nd = (size_t)cfg->max_batch;
+  for (Slot& sl : s->slots) {
+    if (st != MACT_OK) break;
+    st = hip_check(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking), "mact_server_create: stream");
+    if (st == MACT_OK) st = hip_check(hipEventCreateWithFlags(&sl.ev_done, hipEventDisableTiming), "mact_server_create: event");
+    if (st == MACT_OK) st = hip_check(hipEventCreate(&sl.ev_k0), "mact_server_create: event");
+    if (st == MACT_OK) st = hip_check(hipEventCreate(&sl.ev_k1), "mact_server_create: event");
+    if (st == MACT_OK && (hipMalloc(&sl.d_descs, nd * sizeof(BDesc)) != hipSuccess ||
+                          hipMalloc(&sl.d_tiles, (nd + 1) * sizeof(uint32_t)) != hipSuccess ||
+                          hipHostMalloc(&sl.h_descs, nd * sizeof(BDesc)) != hipSuccess ||
+                          hipHostMalloc(&sl.h_tiles, (nd + 1) * sizeof(uint32_t)) != hipSuccess))
+      st = fail(MACT_E_NOMEM, "mact_server_create: slot buffers");
+  }
+  if (st != MACT_OK) {
+    server_free(s);
+    return st;
+  }
+  s->th = std::thread([s] { s->loop(); });
+  *srv = s;
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_server_submit(mact_server* s, const mact_request* r, int64_t* id) {
+  clear_error();
+  if (!s || !r || !id) return fail(MACT_E_INVALID, "mact_server_submit: NULL argument");
+  if (!r->host_in || !r->host_out) return fail(MACT_E_INVALID, "mact_server_submit: NULL host buffer");
+  if (r->in_dtype != MACT_U8 && r->in_dtype != MACT_F16 && r->in_dtype != MACT_F32)
+    return fail(MACT_E_INVALID, "mact_server_submit: in_dtype %d", r->in_dtype);
+  if (r->out_dtype != MACT_F32 && r->out_dtype != MACT_F16) return fail(MACT_E_INVALID, "mact_server_submit: out_dtype %d", r->out_dtype);
+  if (r->xform < MACT_LAB || r->xform > MACT_SCT) return fail(MACT_E_INVALID, "mact_server_submit: xform %d", r->xform);
+  if (r->gamma < MACT_GAMMA_BT709 || r->gamma > MACT_GAMMA_NONE) return fail(MACT_E_INVALID, "mact_server_submit: gamma %d", r->gamma);
+  if (r->width <= 0 || r->height <= 0 || (uint64_t)r->width * (uint64_t)r->height >= (1ull << 31))
+    return fail(MACT_E_INVALID, "mact_server_submit: size %lld x %lld", (long long)r->width, (long long)r->height);
+  const size_t px = (size_t)r->width * (size_t)r->height;
+  const size_t in_b = px * 3 * esize(r->in_dtype), out_b = px * 3 * esize(r->out_dtype);
+  const size_t need = (in_b + kGranule - 1) / kGranule * kGranule + (out_b + kGranule - 1) / kGranule * kGranule;
+  if (need > s->cfg.arena_bytes) return fail(MACT_E_INVALID, "mact_server_submit: request needs %zu bytes, arena has %zu", need, s->cfg.arena_bytes);
+  std::lock_guard<std::mutex> g(s->mu);
+  if (s->stop) return fail(MACT_E_INVALID, "mact_server_submit: server is stopping");
+  if ((int64_t)s->queued.size() >= s->cfg.max_queue) {
+    ++s->rejected;
+    return fail(MACT_E_BUSY, "mact_server_submit: %d requests already waiting", s->cfg.max_queue);
+  }
+  std::unique_ptr<Req> q(new Req());
+  q->id = s->next_id++;
+  q->r = *r;
+  q->in_bytes = in_b;
+  q->out_bytes = out_b;
+  q->t_submit = Clock::now();
+  *id = q->id;
+  s->queued.push_back(q.get());
+  s->all[q->id] = std::move(q);
+  ++s->submitted;
+  s->cv_work.notify_one();
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_server_poll(mact_server* s, int64_t id, int32_t* done) {
+  clear_error();
+  if (!s || !done) return fail(MACT_E_INVALID, "mact_server_poll: NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return fail(MACT_E_INVALID, "mact_server_poll: unknown request %lld", (long long)id);
+  *done = it->second->done ? 1 : 0;
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_server_wait(mact_server* s, int64_t id, int32_t timeout_ms) {
+  clear_error();
+  if (!s) return fail(MACT_E_INVALID, "mact_server_wait: NULL server");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return fail(MACT_E_INVALID, "mact_server_wait: unknown request %lld", (long long)id);
+  Req* q = it->second.get();
+  if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), [q] { return q->done; }))
+    return fail(MACT_E_BUSY, "mact_server_wait: request %lld not done after %d ms", (long long)id, timeout_ms);
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_server_latency(mact_server* s, int64_t id, double* ms) {
+  clear_error();
+  if (!s || !ms) return fail(MACT_E_INVALID, "mact_server_latency: NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  auto it = s->all.find(id);
+  if (it == s->all.end()) return fail(MACT_E_INVALID, "mact_server_latency: unknown request %lld", (long long)id);
+  if (!it->second->done) return fail(MACT_E_BUSY, "mact_server_latency: request %lld not done", (long long)id);
+  *ms = std::chrono::duration<double, std::milli>(it->second->t_done - it->second->t_submit).count();
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_server_stats_get(mact_server* s, mact_server_stats* st) {
+  clear_error();
+  if (!s || !st) return fail(MACT_E_INVALID, "mact_server_stats_get: NULL argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  std::memset(st, 0, sizeof *st);
+  st->submitted = s->submitted;
+  st->completed = s->completed;
+  st->rejected = s->rejected;
+  st->batches = s->batches;
+  st->mean_batch = s->batches ? (double)s->batched_reqs / s->batches : 0.0;
+  st->device_busy_ms = s->busy_ms;
+  if (!s->lat_ms.empty()) {
+    std::vector<double> v = s->lat_ms;
+    std::sort(v.begin(), v.end());
+    auto q = [&v](double f) { return v[std::min(v.size() - 1, (size_t)(f * (v.size() - 1) + 0.5))]; };
+    st->p50_ms = q(0.50);
+    st->p99_ms = q(0.99);
+    double sum = 0.0;
+    for (double x : v) sum += x;
+    st->mean_ms = sum / v.size();
+  }
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_server_destroy(mact_server* s) {
+  clear_error();
+  if (!s) return MACT_OK;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->th.joinable()) s->th.join();
+  for (Slot& sl : s->slots)
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+  if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
+  server_free(s);
+  return MACT_OK;
+}

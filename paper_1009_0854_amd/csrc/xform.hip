@@ -1,0 +1,458 @@
+// Plain per-pixel MACT transforms (Sec. 3.2-3.4), the backward pass of the
+// CIELAB transform, and the reference streaming kernels.
+//
+// Two kernel shapes:
+//  * k_u8_hwc: the hot path, packed 8-bit HWC in and packed float32 HWC out,
+//    staged through LDS so that every global store is a contiguous 1 KB per
+//    wave (details at the kernel).
+//  * k_generic: any element type, layout and stride, one pixel per lane step.
+// Both call the same per-pixel functions (pixel.h), so they give identical bits.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+
+#include "launch.h"
+
+namespace mact {
+
+#include "gamma_table.inc"
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- host helpers
+
+FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  uint32_t l = 0;
+  while (l < 32 && (1ull << l) < d) ++l;
+  f.s = l;
+  f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  return f;
+}
+
+static size_t elem_size(int dtype) { return dtype == MACT_U8 ? 1 : dtype == MACT_F16 ? 2 : 4; }
+
+mact_status resolve_image(const mact_image* im, bool is_output, const char* what, HostImage* out) {
+  if (!im) return fail(MACT_E_INVALID, "%s: image is NULL", what);
+  if (!im->data) return fail(MACT_E_INVALID, "%s: data is NULL", what);
+  if (im->dtype < MACT_U8 || im->dtype > MACT_F32) return fail(MACT_E_INVALID, "%s: unknown dtype %d", what, im->dtype);
+  if (is_output && im->dtype == MACT_U8) return fail(MACT_E_UNSUPPORTED, "%s: 8-bit output is not supported", what);
+  if (im->layout != MACT_HWC && im->layout != MACT_CHW) return fail(MACT_E_INVALID, "%s: unknown layout %d", what, im->layout);
+  if (im->width <= 0 || im->height <= 0) return fail(MACT_E_INVALID, "%s: size %lld x %lld", what, (long long)im->width, (long long)im->height);
+  if (im->batch < 0) return fail(MACT_E_INVALID, "%s: batch %lld < 0", what, (long long)im->batch);
+  if (im->gamma < MACT_GAMMA_BT709 || im->gamma > MACT_GAMMA_NONE) return fail(MACT_E_INVALID, "%s: unknown gamma %d", what, im->gamma);
+  HostImage h;
+  h.data = im->data;
+  h.dtype = im->dtype;
+  h.layout = im->layout;
+  h.gamma = im->gamma;
+  h.W = im->width;
+  h.H = im->height;
+  h.N = im->batch > 1 ? im->batch : 1;
+  h.esize = elem_size(im->dtype);
+  if ((uint64_t)h.W * (uint64_t)h.H >= (1ull << 31)) return fail(MACT_E_UNSUPPORTED, "%s: image of 2^31 pixels or more", what);
+  if (h.layout == MACT_HWC) {
+    h.rs = im->row_stride ? im->row_stride : 3 * h.W;
+    if (h.rs < 3 * h.W) return fail(MACT_E_INVALID, "%s: row_stride %lld < 3 W", what, (long long)h.rs);
+    h.ps = 1;
+    h.bs = im->batch_stride ? im->batch_stride : h.H * h.rs;
+    if (h.N > 1 && h.bs < h.H * h.rs) return fail(MACT_E_INVALID, "%s: batch_stride too small", what);
+    h.packed = h.rs == 3 * h.W && (h.N == 1 || h.bs == h.H * h.rs);
+  } else {
+    h.rs = im->row_stride ? im->row_stride : h.W;
+    if (h.rs < h.W) return fail(MACT_E_INVALID, "%s: row_stride %lld < W", what, (long long)h.rs);
+    h.ps = im->plane_stride ? im->plane_stride : h.H * h.rs;
+    if (h.ps < h.H * h.rs) return fail(MACT_E_INVALID, "%s: plane_stride too small", what);
+    h.bs = im->batch_stride ? im->batch_stride : 3 * h.ps;
+    if (h.N > 1 && h.bs < 3 * h.ps) return fail(MACT_E_INVALID, "%s: batch_stride too small", what);
+    h.packed = h.rs == h.W && h.ps == h.H * h.W;
+  }
+  if (h.rs < 0 || h.ps < 0 || h.bs < 0) return fail(MACT_E_INVALID, "%s: negative stride", what);
+  *out = h;
+  return MACT_OK;
+}
+
+mact_status check_same_shape(const HostImage& a, const HostImage& b, const char* what) {
+  if (a.W != b.W || a.H != b.H || a.N != b.N)
+    return fail(MACT_E_INVALID, "%s: shape %lldx%lldx%lld does not match %lldx%lldx%lld", what, (long long)b.N,
+                (long long)b.H, (long long)b.W, (long long)a.N, (long long)a.H, (long long)a.W);
+  return MACT_OK;
+}
+
+KImage kimage(const HostImage& h, int64_t n0, int64_t count) {
+  KImage k;
+  k.ptr = static_cast<char*>(h.data) + (size_t)(n0 * h.bs) * h.esize;
+  k.dtype = h.dtype;
+  k.layout = h.layout;
+  k.rs = h.rs;
+  k.ps = h.ps;
+  k.bs = h.bs;
+  k.W = (uint32_t)h.W;
+  k.HW = (uint32_t)(h.W * h.H);
+  k.packed = h.packed ? 1u : 0u;
+  k.div_w = make_fastdiv(k.W);
+  k.div_hw = make_fastdiv(k.HW);
+  (void)count;
+  return k;
+}
+
+int64_t images_per_launch(const HostImage& h) {
+  const int64_t hw = h.W * h.H;
+  return std::max<int64_t>(1, ((1ll << 31) - 1) / hw);
+}
+
+int pack_coef(const mact_params& p, KCoef* k) {
+  std::memset(k, 0, sizeof *k);
+  k->xform = p.xform;
+  k->out_mode = p.out_mode;
+  const int nf = p.xform == MACT_SCT ? 4 : 1;
+  int deg = 0;
+  for (int i = 0; i < nf; ++i) {
+    for (int j = 0; j <= p.f[i].n; ++j) k->p[i][j] = (float)p.f[i].p[j];
+    deg = std::max(deg, p.f[i].n);
+  }
+  if (p.xform == MACT_LAB && p.f[0].m > 0) {
+    for (int j = 0; j <= p.f[0].m; ++j) k->q[j] = (float)p.f[0].q[j];
+    deg = std::max(deg, p.f[0].m);
+  } else {
+    k->q[0] = 1.0f;
+  }
+  return deg <= 5 ? 5 : 7;
+}
+
+int current_device() {
+  int d = 0;
+  (void)hipGetDevice(&d);
+  return d;
+}
+
+int device_cus() {
+  static std::mutex mu;
+  static int cache[64] = {0};
+  const int d = current_device();
+  std::lock_guard<std::mutex> g(mu);
+  if (d >= 0 && d < 64 && cache[d]) return cache[d];
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess || cus <= 0) cus = 256;
+  if (d >= 0 && d < 64) cache[d] = cus;
+  return cus;
+}
+
+static unsigned grid_for(uint64_t work_items, int block, int blocks_per_cu) {
+  const uint64_t need = (work_items + block - 1) / block;
+  const uint64_t cap = (uint64_t)device_cus() * blocks_per_cu;
+  return (unsigned)std::max<uint64_t>(1, std::min(need, cap));
+}
+
+// ---------------------------------------------------------------- kernels
+
+__device__ __forceinline__ uint32_t byte_of(uint3 w, int i) {
+  const uint32_t word = i < 4 ? w.x : (i < 8 ? w.y : w.z);
+  return (word >> (8 * (i & 3))) & 0xffu;
+}
+
+// Packed 8-bit HWC -> packed float32 HWC: the hot path.
+//
+// A wave owns chunks of 256 pixels (768 input bytes, 3 KB of output).  Each
+// lane loads 12 bytes (4 pixels) with one 12-byte load -- the wave's loads are
+// one contiguous 768-byte run -- and computes its 4 pixels.  The 48 bytes of
+// results go to the wave's slice of LDS, and the wave then writes the chunk
+// back as 16-byte stores in which lane l writes bytes 16 l .. 16 l + 15 of each
+// KB: every store instruction covers 1 KB of contiguous output.  Writing the
+// 48 bytes straight from the lane (a 48-byte stride across the wave) runs at
+// about a third of this bandwidth.  Each wave handles kChunksPerWave chunks
+// and the grid covers the image once (no grid-stride loop).  Requires `in`
+// 4-byte and `out` 16-byte aligned; blockDim.x == kHotBlock.
+constexpr int kHotBlock = 512;
+constexpr int kChunksPerWave = 2;
+constexpr int kHotWaves = kHotBlock / 64;
+
+template <int XF, int DEG>
+__device__ __forceinline__ void px4_u8(const KCoef& k, const float* gtab, uint3 w, float o[12]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t r = byte_of(w, 3 * j), g = byte_of(w, 3 * j + 1), b = byte_of(w, 3 * j + 2);
+    if (XF == MACT_LAB) lab_px<DEG>(k, gtab[r], gtab[g], gtab[b], o + 3 * j);
+    else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o + 3 * j);
+    else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o + 3 * j);
+  }
+}
+
+template <int DEG, int XF>
+__global__ __launch_bounds__(kHotBlock) void k_u8_hwc(const uint8_t* __restrict__ in, float* __restrict__ out,
+                                                       uint32_t n_px, KCoef k, int gamma) {
+  __shared__ f4 s_out[kHotWaves][kChunksPerWave * 192];
+  __shared__ float gtab[256];
+  if (XF == MACT_LAB) {
+    for (uint32_t i = threadIdx.x; i < 256u; i += kHotBlock) gtab[i] = k_gamma_table[gamma][i];
+    __syncthreads();
+  }
+  const uint32_t n_chunks = n_px >> 8;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t c0 = (blockIdx.x * kHotWaves + wv) * kChunksPerWave;
+  if (c0 < n_chunks) {
+    uint3 w[kChunksPerWave];
+#pragma unroll
+    for (int j = 0; j < kChunksPerWave; ++j)
+      if (c0 + j < n_chunks) w[j] = reinterpret_cast<const uint3*>(in)[(size_t)(c0 + j) * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < kChunksPerWave; ++j) {
+      if (c0 + j >= n_chunks) break;
+      float o[12];
+      px4_u8<XF, DEG>(k, gtab, w[j], o);
+      s_out[wv][j * 192 + 3 * lane] = f4{o[0], o[1], o[2], o[3]};
+      s_out[wv][j * 192 + 3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
+      s_out[wv][j * 192 + 3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+    }
+    // the LDS writes of every lane must land before any lane reads them back
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t n_valid = min((uint32_t)kChunksPerWave, n_chunks - c0) * 192u;
+    f4* dst = reinterpret_cast<f4*>(out) + (size_t)c0 * 192;
+#pragma unroll
+    for (int q = 0; q < 3 * kChunksPerWave; ++q) {
+      const uint32_t e = q * 64 + lane;
+      if (e < n_valid) __builtin_nontemporal_store(s_out[wv][e], dst + e);
+    }
+  }
+  // the last n_px % 256 pixels, one per lane of block 0
+  const uint32_t tail0 = n_chunks << 8;
+  if (blockIdx.x == 0 && threadIdx.x < n_px - tail0) {
+    const uint32_t p = tail0 + threadIdx.x;
+    const uint32_t r = in[3 * (size_t)p], g = in[3 * (size_t)p + 1], b = in[3 * (size_t)p + 2];
+    float o[3];
+    if (XF == MACT_LAB) lab_px<DEG>(k, gtab[r], gtab[g], gtab[b], o);
+    else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o);
+    else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o);
+    out[3 * (size_t)p] = o[0];
+    out[3 * (size_t)p + 1] = o[1];
+    out[3 * (size_t)p + 2] = o[2];
+  }
+}
+
+// Blocks of k_u8_hwc for n_px pixels: every full chunk covered once, and at
+// least one block for the tail.
+static unsigned hot_grid(uint32_t n_px) {
+  const uint32_t per_block = kHotWaves * kChunksPerWave;
+  return std::max<unsigned>(1, ((n_px >> 8) + per_block - 1) / per_block);
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_generic(KImage src, KImage dst, uint32_t n_px, KCoef k, int gamma) {
+  __shared__ float gtab[256];
+  gtab[threadIdx.x] = k_gamma_table[gamma][threadIdx.x];
+  __syncthreads();
+  const bool u8 = src.dtype == MACT_U8;
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < n_px; p += stride) {
+    float v[3], o[3];
+    load_px(src, p, v);
+    eval_px<DEG>(k, u8, gamma, gtab, v, o);
+    store_px(dst, p, o);
+  }
+}
+
+struct KGrad {
+  float dp[8], dq[8];  // derivative coefficients of the float32 p and q
+};
+
+// dx = (diag(1/white) M)^T (f~'(t) * (J^T g)), zero outside [0, 1].
+template <int DEG>
+__global__ __launch_bounds__(256) void k_lab_backward(KImage xs, KImage gs, KImage ds, uint32_t n_px, KCoef k,
+                                                      KGrad kg) {
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < n_px; p += stride) {
+    float x[3], g[3];
+    bool in[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float raw = static_cast<const float*>(xs.ptr)[elem_off(xs, p, c)];
+      in[c] = raw >= 0.0f && raw <= 1.0f;
+      x[c] = clamp01(raw);
+      g[c] = static_cast<const float*>(gs.ptr)[elem_off(gs, p, c)];
+    }
+    const float t[3] = {
+        __builtin_fmaf(kMw00, x[0], __builtin_fmaf(kMw01, x[1], kMw02 * x[2])),
+        __builtin_fmaf(kMw10, x[0], __builtin_fmaf(kMw11, x[1], kMw12 * x[2])),
+        __builtin_fmaf(kMw20, x[0], __builtin_fmaf(kMw21, x[1], kMw22 * x[2])),
+    };
+    const float gf[3] = {500.0f * g[1], __builtin_fmaf(116.0f, g[0], __builtin_fmaf(-500.0f, g[1], 200.0f * g[2])),
+                         -200.0f * g[2]};
+    float gt[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float d = kLabKf;
+      if (t[c] > kT0f) {
+        const float pv = horner<DEG>(k.p[0], t[c]), qv = horner<DEG>(k.q, t[c]);
+        const float dpv = horner<DEG>(kg.dp, t[c]), dqv = horner<DEG>(kg.dq, t[c]);
+        d = fdiv(__builtin_fmaf(dpv, qv, -(pv * dqv)), qv * qv);
+      }
+      gt[c] = gf[c] * d;
+    }
+    const float dx[3] = {
+        __builtin_fmaf(kMw00, gt[0], __builtin_fmaf(kMw10, gt[1], kMw20 * gt[2])),
+        __builtin_fmaf(kMw01, gt[0], __builtin_fmaf(kMw11, gt[1], kMw21 * gt[2])),
+        __builtin_fmaf(kMw02, gt[0], __builtin_fmaf(kMw12, gt[1], kMw22 * gt[2])),
+    };
+#pragma unroll
+    for (int c = 0; c < 3; ++c) static_cast<float*>(ds.ptr)[elem_off(ds, p, c)] = in[c] ? dx[c] : 0.0f;
+  }
+}
+
+// Widen packed bytes to floats with the access pattern of k_u8_hwc (no arithmetic).
+__global__ __launch_bounds__(kHotBlock) void k_stream_u8_f32(const uint8_t* __restrict__ in, float* __restrict__ out,
+                                                             uint32_t n_px) {
+  __shared__ f4 s_out[kHotWaves][kChunksPerWave * 192];
+  const uint32_t n_chunks = n_px >> 8;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t c0 = (blockIdx.x * kHotWaves + wv) * kChunksPerWave;
+  if (c0 < n_chunks) {
+    uint3 w[kChunksPerWave];
+#pragma unroll
+    for (int j = 0; j < kChunksPerWave; ++j)
+      if (c0 + j < n_chunks) w[j] = reinterpret_cast<const uint3*>(in)[(size_t)(c0 + j) * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < kChunksPerWave; ++j) {
+      if (c0 + j >= n_chunks) break;
+      float o[12];
+#pragma unroll
+      for (int q = 0; q < 12; ++q) o[q] = (float)byte_of(w[j], q);
+      s_out[wv][j * 192 + 3 * lane] = f4{o[0], o[1], o[2], o[3]};
+      s_out[wv][j * 192 + 3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
+      s_out[wv][j * 192 + 3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t n_valid = min((uint32_t)kChunksPerWave, n_chunks - c0) * 192u;
+    f4* dst = reinterpret_cast<f4*>(out) + (size_t)c0 * 192;
+#pragma unroll
+    for (int q = 0; q < 3 * kChunksPerWave; ++q) {
+      const uint32_t e = q * 64 + lane;
+      if (e < n_valid) __builtin_nontemporal_store(s_out[wv][e], dst + e);
+    }
+  }
+  const uint32_t tail0 = n_chunks << 8;
+  if (blockIdx.x == 0)
+    for (uint32_t e = threadIdx.x; e < 3 * (n_px - tail0); e += kHotBlock)
+      out[3 * (size_t)tail0 + e] = (float)in[3 * (size_t)tail0 + e];
+}
+
+__global__ __launch_bounds__(256) void k_copy16(const f4* __restrict__ in, f4* __restrict__ out, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256u;
+  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += stride) __builtin_nontemporal_store(in[i], out + i);
+}
+
+// ---------------------------------------------------------------- dispatch
+
+template <int DEG>
+static void launch_u8_hwc(int xform, const uint8_t* in, float* out, uint32_t n_px, const KCoef& k, int gamma,
+                          hipStream_t st) {
+  const unsigned grid = hot_grid(n_px);
+  const dim3 blk(kHotBlock);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_u8_hwc<DEG, MACT_LAB>), dim3(grid), blk, 0, st, in, out, n_px, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_u8_hwc<DEG, MACT_HSI>), dim3(grid), blk, 0, st, in, out, n_px, k, gamma);
+  else hipLaunchKernelGGL((k_u8_hwc<DEG, MACT_SCT>), dim3(grid), blk, 0, st, in, out, n_px, k, gamma);
+}
+
+}  // namespace mact
+
+using namespace mact;
+
+extern "C" mact_status mact_transform(const mact_params* params, const mact_image* in, const mact_image* out,
+                                      void* hip_stream) {
+  clear_error();
+  mact_status s = check_params(params);
+  if (s != MACT_OK) return s;
+  HostImage hi, ho;
+  if ((s = resolve_image(in, false, "mact_transform: in", &hi)) != MACT_OK) return s;
+  if ((s = resolve_image(out, true, "mact_transform: out", &ho)) != MACT_OK) return s;
+  if ((s = check_same_shape(hi, ho, "mact_transform: out")) != MACT_OK) return s;
+  KCoef k;
+  const int deg = pack_coef(*params, &k);
+  const int gamma = params->xform == MACT_LAB ? hi.gamma : MACT_GAMMA_NONE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const bool fast = hi.dtype == MACT_U8 && hi.layout == MACT_HWC && hi.packed && ho.dtype == MACT_F32 &&
+                    ho.layout == MACT_HWC && ho.packed && ((uintptr_t)hi.data % 4 == 0) && ((uintptr_t)ho.data % 16 == 0);
+  const int64_t per = images_per_launch(hi);
+  for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
+    const int64_t cnt = std::min(per, hi.N - n0);
+    const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
+    if (fast) {
+      const uint8_t* ip = static_cast<const uint8_t*>(hi.data) + (size_t)(n0 * hi.bs);
+      float* op = static_cast<float*>(ho.data) + (size_t)(n0 * ho.bs);
+      if (deg == 5) launch_u8_hwc<5>(params->xform, ip, op, n_px, k, gamma, st);
+      else launch_u8_hwc<7>(params->xform, ip, op, n_px, k, gamma, st);
+    } else {
+      const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
+      const unsigned grid = grid_for(n_px, 256, 8);
+      if (deg == 5) hipLaunchKernelGGL(k_generic<5>, dim3(grid), dim3(256), 0, st, ks, kd, n_px, k, gamma);
+      else hipLaunchKernelGGL(k_generic<7>, dim3(grid), dim3(256), 0, st, ks, kd, n_px, k, gamma);
+    }
+    if ((s = hip_check(hipGetLastError(), "mact_transform: launch")) != MACT_OK) return s;
+  }
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_transform_backward(const mact_params* params, const mact_image* x,
+                                               const mact_image* grad_out, const mact_image* grad_in,
+                                               void* hip_stream) {
+  clear_error();
+  mact_status s = check_params(params);
+  if (s != MACT_OK) return s;
+  if (params->xform != MACT_LAB) return fail(MACT_E_UNSUPPORTED, "mact_transform_backward: only MACT_LAB");
+  if (params->out_mode != 0) return fail(MACT_E_INVALID, "mact_transform_backward: out_mode must be 0");
+  HostImage hx, hg, hd;
+  if ((s = resolve_image(x, false, "mact_transform_backward: x", &hx)) != MACT_OK) return s;
+  if ((s = resolve_image(grad_out, false, "mact_transform_backward: grad_out", &hg)) != MACT_OK) return s;
+  if ((s = resolve_image(grad_in, true, "mact_transform_backward: grad_in", &hd)) != MACT_OK) return s;
+  if (hx.dtype != MACT_F32 || hg.dtype != MACT_F32 || hd.dtype != MACT_F32)
+    return fail(MACT_E_UNSUPPORTED, "mact_transform_backward: x, grad_out and grad_in must be MACT_F32");
+  if (hx.gamma != MACT_GAMMA_NONE) return fail(MACT_E_UNSUPPORTED, "mact_transform_backward: x must be linear (MACT_GAMMA_NONE)");
+  if ((s = check_same_shape(hx, hg, "mact_transform_backward: grad_out")) != MACT_OK) return s;
+  if ((s = check_same_shape(hx, hd, "mact_transform_backward: grad_in")) != MACT_OK) return s;
+  KCoef k;
+  const int deg = pack_coef(*params, &k);
+  KGrad kg;
+  std::memset(&kg, 0, sizeof kg);
+  for (int j = 1; j <= 7; ++j) {
+    kg.dp[j - 1] = (float)(j * (double)k.p[0][j]);
+    kg.dq[j - 1] = (float)(j * (double)k.q[j]);
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int64_t per = images_per_launch(hx);
+  for (int64_t n0 = 0; n0 < hx.N; n0 += per) {
+    const int64_t cnt = std::min(per, hx.N - n0);
+    const uint32_t n_px = (uint32_t)(cnt * hx.W * hx.H);
+    const KImage kx = kimage(hx, n0, cnt), kgo = kimage(hg, n0, cnt), kd = kimage(hd, n0, cnt);
+    const unsigned grid = grid_for(n_px, 256, 8);
+    if (deg == 5) hipLaunchKernelGGL(k_lab_backward<5>, dim3(grid), dim3(256), 0, st, kx, kgo, kd, n_px, k, kg);
+    else hipLaunchKernelGGL(k_lab_backward<7>, dim3(grid), dim3(256), 0, st, kx, kgo, kd, n_px, k, kg);
+    if ((s = hip_check(hipGetLastError(), "mact_transform_backward: launch")) != MACT_OK) return s;
+  }
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_stream_u8_to_f32(const void* src, void* dst, int64_t n_px, void* hip_stream) {
+  clear_error();
+  if (!src || !dst) return fail(MACT_E_INVALID, "mact_stream_u8_to_f32: NULL pointer");
+  if (n_px <= 0 || n_px >= (1ll << 31)) return fail(MACT_E_INVALID, "mact_stream_u8_to_f32: n_px %lld", (long long)n_px);
+  if ((uintptr_t)src % 4 || (uintptr_t)dst % 16) return fail(MACT_E_INVALID, "mact_stream_u8_to_f32: misaligned buffers");
+  hipLaunchKernelGGL(k_stream_u8_f32, dim3(hot_grid((uint32_t)n_px)), dim3(kHotBlock), 0, static_cast<hipStream_t>(hip_stream),
+                     static_cast<const uint8_t*>(src), static_cast<float*>(dst), (uint32_t)n_px);
+  return hip_check(hipGetLastError(), "mact_stream_u8_to_f32: launch");
+}
+
+extern "C" mact_status mact_copy(const void* src, void* dst, int64_t bytes, void* hip_stream) {
+  clear_error();
+  if (!src || !dst) return fail(MACT_E_INVALID, "mact_copy: NULL pointer");
+  if (bytes <= 0 || bytes % 16) return fail(MACT_E_INVALID, "mact_copy: bytes %lld not a positive multiple of 16", (long long)bytes);
+  if ((uintptr_t)src % 16 || (uintptr_t)dst % 16) return fail(MACT_E_INVALID, "mact_copy: misaligned buffers");
+  const uint64_t n = (uint64_t)bytes / 16;
+  const unsigned grid = grid_for(n, 256, 8);
+  hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                     static_cast<const f4*>(src), static_cast<f4*>(dst), n);
+  return hip_check(hipGetLastError(), "mact_copy: launch");
+}

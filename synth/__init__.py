@@ -56,20 +56,39 @@ def smooth_f32(h, w, seed):
         v = g.uniform(0.0, 3.0, 4)
         phi = g.uniform(0.0, 2.0 * np.pi, 4)
         gx, gy = g.uniform(-1.0, 1.0, 2)
-        acc = 127.5 + 60.0 * (gy * y[:, None] + gx * x[None, :])
+        # cos(a + b) = cos a cos b - sin a sin b keeps each wave a sum of outer products
+        cols = [np.full(w, 1.0), 60.0 * gx * x]
+        rows = [127.5 + 60.0 * gy * y, np.full(h, 1.0)]
         for k in range(4):
-            # cos(a + b) = cos a cos b - sin a sin b keeps each wave an outer product
             a = 2.0 * np.pi * u[k] * x + phi[k]
             b = 2.0 * np.pi * v[k] * y
-            acc = acc + A[k] * (np.cos(b)[:, None] * np.cos(a)[None, :] - np.sin(b)[:, None] * np.sin(a)[None, :])
-        out[..., c] = acc
+            cols += [A[k] * np.cos(a), -A[k] * np.sin(a)]
+            rows += [np.cos(b), np.sin(b)]
+        out[..., c] = (np.stack(rows, 1).astype(np.float32) @ np.stack(cols, 0).astype(np.float32))
     return out, g
 
 
 def smooth_u8(h, w, seed):
     base, g = smooth_f32(h, w, seed)
-    noise = g.standard_normal(size=base.shape, dtype=np.float32) * np.float32(8.0)
-    return np.clip(np.rint(base + noise), 0, 255).astype(np.uint8)
+    noise = g.standard_normal(size=base.shape, dtype=np.float32)
+    noise *= np.float32(8.0)
+    base += noise
+    np.rint(base, out=base)
+    np.clip(base, 0, 255, out=base)
+    return base.astype(np.uint8)
+
+
+def smooth_batch_u8(n, h, w, seed0, threads=8):
+    """n smooth images with seeds seed0 .. seed0 + n - 1, generated on threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    out = np.empty((n, h, w, 3), dtype=np.uint8)
+
+    def one(i):
+        out[i] = smooth_u8(h, w, seed0 + i)
+
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(one, range(n)))
+    return out
 
 
 def uniform_f32(shape, seed):

@@ -36,3 +36,22 @@ def mean_max(parts):
 def sum_max(d):
     d = np.asarray(d)
     return float(d.sum()), float(d.max())
+
+
+_SHARED = {}
+
+
+def cube_map_shared(fn, shared, *args):
+    """Like cube_map, with `shared` (e.g. large GPU results as numpy arrays)
+    inherited by the forked workers instead of pickled; fn(v8, start, shared, *args)."""
+    _SHARED["v"] = shared
+    ctx = mp.get_context("fork")
+    try:
+        with ctx.Pool(WORKERS) as pool:
+            return pool.starmap(_call_shared, [(fn, s, args) for s in range(0, 1 << 24, CHUNK)])
+    finally:
+        _SHARED.clear()
+
+
+def _call_shared(fn, start, args):
+    return fn(_slice(start), start, _SHARED["v"], *args)

@@ -1,0 +1,252 @@
+"""The C ABI on the CPU: the library loads and exports every symbol the
+header declares, struct layouts match, mact_fit agrees with the oracle's
+independent Remez, the printed tables match, and invalid calls return the
+documented status without touching a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mact.h")
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_1009_0854_amd as M
+    from paper_1009_0854_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_1009_0854_amd import build
+        build.build()
+    M.lib()
+    return M
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:mact_status|size_t|char\s*\*|const char\s*\*)\s*\**\s*(\w+)\s*\(", text, re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(M):
+    from paper_1009_0854_amd import _abi
+    names = declared_functions()
+    assert len(names) >= 25, names
+    L = ctypes.CDLL(_abi.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # the Python binding knows every declared function, and nothing else
+    assert sorted(_abi.SIGNATURES) == names
+
+
+def test_struct_layouts_match_the_header(M, tmp_path):
+    from paper_1009_0854_amd import _abi
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mact.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                   "sizeof(mact_approx), sizeof(mact_image), sizeof(mact_params), sizeof(mact_tune),"
+                   "sizeof(mact_server_config), sizeof(mact_request), sizeof(mact_server_stats),"
+                   "offsetof(mact_approx, eps), offsetof(mact_image, gamma), offsetof(mact_server_config, params));return 0;}\n")
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(_abi.Approx), ctypes.sizeof(_abi.Image), ctypes.sizeof(_abi.Params), ctypes.sizeof(_abi.Tune),
+            ctypes.sizeof(_abi.ServerConfig), ctypes.sizeof(_abi.Request), ctypes.sizeof(_abi.ServerStats),
+            _abi.Approx.eps.offset, _abi.Image.gamma.offset, _abi.ServerConfig.params.offset]
+    assert got == want
+
+
+def test_status_strings(M):
+    L = M.lib()
+    for s in range(0, -7, -1):
+        assert L.mact_status_str(s)
+    assert b"gfx950" in L.mact_version()
+
+
+FITS = [
+    (0, 4, 4, 0.008856, 1.0), (0, 2, 2, 0.008856, 1.0), (0, 3, 4, 0.008856, 1.0), (0, 5, 0, 0.0, 1.0),
+    (1, 5, 0, 0.0, 1.0), (1, 3, 0, 0.0, 254 / 256), (2, 5, 0, 0.0, 1 / np.sqrt(2)), (3, 4, 0, 0.0, 0.5),
+    (4, 5, 0, 0.0, 1.0), (5, 4, 0, 1 / 255, 1.0),
+]
+
+
+@pytest.mark.parametrize("fn,n,m,lo,hi", FITS)
+def test_mact_fit_agrees_with_oracle_remez(M, fn, n, m, lo, hi):
+    from numpy.polynomial import polynomial as Pm
+    from oracle import remez, tables as T
+    f = [T.f_cbrt, T.f_atan_sqrt3, T.f_asin2, T.f_acos, T.f_atan, T.f_atanc][fn]
+    a = M.fit(fn, n, m, lo, hi)
+    o = remez.remez(f, n, m, lo, hi)
+    assert a.converged == 1
+    assert a.eps == pytest.approx(o.eps, rel=1e-6)
+    x = np.linspace(lo, hi, 20001)
+    r_lib = Pm.polyval(x, a.p_list) / Pm.polyval(x, a.q_list)
+    assert np.max(np.abs(r_lib - o(x))) <= 1e-3 * o.eps
+    # the library's own alternation set levels the error at eps with alternating signs
+    alt = np.array(a.alt[:a.n_alt])
+    assert a.n_alt == n + m + 2
+    e = Pm.polyval(alt, a.p_list) / Pm.polyval(alt, a.q_list) - f(alt)
+    assert np.all(np.sign(e[1:]) == -np.sign(e[:-1]))
+    np.testing.assert_allclose(np.abs(e), a.eps, rtol=1e-5)
+
+
+def test_mact_fit_nonconvergence_and_invalid(M):
+    from paper_1009_0854_amd import _abi
+    a = M.fit(0, 4, 4, 0.008856, 1.0, max_iter=1, allow_noconv=True)
+    assert a.converged == 0 and a.eps > 0 and a.n == 4 and a.m == 4
+    with pytest.raises(_abi.MactError) as e:
+        M.fit(0, 4, 4, 0.008856, 1.0, max_iter=1)
+    assert e.value.status == _abi.E_NOCONV
+    L = M.lib()
+    out = _abi.Approx()
+    for args in [(0, 8, 0, 0.0, 1.0), (0, 2, 2, 1.0, 0.5), (3, 3, 0, -2.0, 0.5), (0, 2, 2, -1.0, 1.0), (9, 2, 0, 0.0, 1.0)]:
+        assert L.mact_fit(*args, ctypes.byref(out)) == _abi.E_INVALID, args
+    assert L.mact_fit(0, 2, 2, 0.1, 1.0, None) == _abi.E_INVALID
+    assert L.mact_last_error()
+
+
+def test_paper_tables_match_the_oracle_copy(M):
+    # the library and the oracle each carry a transcription of Tables 1-7; they must agree
+    from oracle import tables as T
+    rows = [(0, n, 0, T.T1_CBRT_POLY[n][0], T.T1_CBRT_POLY[n][1], [1.0]) for n in T.T1_CBRT_POLY]
+    rows += [(0, n, m, e, p, q) for (n, m), (e, p, q) in T.T2_CBRT_RAT.items()]
+    for fn, tab in ((1, T.T3_ATAN_SQRT3), (2, T.T4_ASIN2), (3, T.T5_ACOS), (4, T.T6_ATAN), (5, T.T7_ATANC)):
+        rows += [(fn, n, 0, e, c, [1.0]) for n, (e, c) in tab.items()]
+    for fn, n, m, e, p, q in rows:
+        a = M.paper_approx(fn, n, m)
+        assert a.eps == e
+        assert a.p_list == list(p)
+        assert a.q_list == list(q)
+    from paper_1009_0854_amd import _abi
+    with pytest.raises(_abi.MactError):
+        M.paper_approx(0, 5, 5)
+
+
+def test_default_params(M):
+    want = {0: [(0, 4, 4, 0.008856, 1.0)], 1: [(1, 5, 0, 0.0, 1.0)],
+            2: [(2, 5, 0, 0.0, 1 / np.sqrt(2)), (3, 5, 0, 0.0, 0.5), (4, 5, 0, 0.0, 1.0), (5, 5, 0, 0.0, 1.0)]}
+    for x, fs in want.items():
+        p = M.default_params(x)
+        assert p.xform == x and p.out_mode == 0
+        for i, (fn, n, m, lo, hi) in enumerate(fs):
+            a = p.f[i]
+            assert (a.fn, a.n, a.m) == (fn, n, m)
+            assert a.lo == pytest.approx(lo) and a.hi == pytest.approx(hi)
+            assert a.converged == 1 and 0 < a.eps < 2e-4
+
+
+def _img(data=1, dtype=0, layout=0, w=4, h=3, **kw):
+    from paper_1009_0854_amd import _abi
+    im = _abi.Image()
+    im.data, im.dtype, im.layout, im.width, im.height = data, dtype, layout, w, h
+    for k, v in kw.items():
+        setattr(im, k, v)
+    return im
+
+
+def test_transform_validation_without_gpu(M):
+    from paper_1009_0854_amd import _abi as A
+    L = M.lib()
+    p = M.default_params(0)
+    ok_in, ok_out = _img(0x1000, A.U8), _img(0x2000, A.F32)
+    cases = [
+        (None, ok_in, ok_out, A.E_INVALID),
+        (p, _img(0, A.U8), ok_out, A.E_INVALID),                 # NULL data
+        (p, _img(0x1000, A.U8, w=0), ok_out, A.E_INVALID),         # empty
+        (p, _img(0x1000, 7), ok_out, A.E_INVALID),                 # dtype
+        (p, _img(0x1000, A.U8, layout=3), ok_out, A.E_INVALID),    # layout
+        (p, ok_in, _img(0x2000, A.U8), A.E_UNSUPPORTED),           # 8-bit output
+        (p, ok_in, _img(0x2000, A.F32, w=5), A.E_INVALID),         # shape mismatch
+        (p, _img(0x1000, A.U8, row_stride=5), ok_out, A.E_INVALID),  # stride < 3 W
+        (p, _img(0x1000, A.U8, gamma=9), ok_out, A.E_INVALID),     # gamma
+    ]
+    for params, i, o, want in cases:
+        pp = ctypes.byref(params) if params is not None else None
+        assert L.mact_transform(pp, ctypes.byref(i), ctypes.byref(o), None) == want
+        assert L.mact_last_error()
+    bad = M.default_params(1)
+    bad.out_mode = 1
+    assert L.mact_transform(ctypes.byref(bad), ctypes.byref(ok_in), ctypes.byref(ok_out), None) == A.E_INVALID
+    bad = M.default_params(1)
+    bad.f[0].m = 2
+    assert L.mact_transform(ctypes.byref(bad), ctypes.byref(ok_in), ctypes.byref(ok_out), None) == A.E_UNSUPPORTED
+    bad = M.default_params(0)
+    bad.f[0].n = 8
+    assert L.mact_transform(ctypes.byref(bad), ctypes.byref(ok_in), ctypes.byref(ok_out), None) == A.E_INVALID
+    bad = M.default_params(0)
+    bad.xform = 5
+    assert L.mact_transform(ctypes.byref(bad), ctypes.byref(ok_in), ctypes.byref(ok_out), None) == A.E_INVALID
+    # backward: float32 linear only
+    x = _img(0x1000, A.F32, gamma=A.GAMMA_NONE)
+    assert L.mact_transform_backward(ctypes.byref(p), ctypes.byref(_img(0x1000, A.U8, gamma=A.GAMMA_NONE)),
+                                     ctypes.byref(x), ctypes.byref(x), None) == A.E_UNSUPPORTED
+    assert L.mact_transform_backward(ctypes.byref(p), ctypes.byref(_img(0x1000, A.F32)),
+                                     ctypes.byref(x), ctypes.byref(x), None) == A.E_UNSUPPORTED
+    hp = M.default_params(1)
+    assert L.mact_transform_backward(ctypes.byref(hp), ctypes.byref(x), ctypes.byref(x), ctypes.byref(x), None) == A.E_UNSUPPORTED
+
+
+def test_lut_validation_without_gpu(M):
+    from paper_1009_0854_amd import _abi as A
+    L = M.lib()
+    assert L.lut_bytes(0, 17) == 17 ** 3 * 16
+    assert L.lut_bytes(1, 33) == 33 ** 3 * 16
+    assert L.lut_bytes(2, 17) == 17 ** 3 * 32
+    assert L.lut_bytes(0, 1) == 0 and L.lut_bytes(3, 17) == 0 and L.lut_bytes(0, 257) == 0
+    assert L.lut_build(0, 1, 0, ctypes.c_void_p(0x1000), 1 << 20, None) == A.E_INVALID
+    assert L.lut_build(0, 17, 0, None, 1 << 20, None) == A.E_INVALID
+    assert L.lut_build(0, 17, 0, ctypes.c_void_p(0x1000), 100, None) == A.E_INVALID
+    i, o = _img(0x1000, A.U8), _img(0x2000, A.F32)
+    assert L.lut_interp(ctypes.c_void_p(0x1000), 17, 0, 7, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
+    assert L.lut_interp(ctypes.c_void_p(0x1004), 17, 0, 0, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
+    assert L.lut_interp(None, 17, 0, 0, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
+
+
+def test_batch_and_server_validation_without_gpu(M):
+    from paper_1009_0854_amd import _abi as A
+    L = M.lib()
+    p = (A.Params * 1)(M.default_params(0))
+    i = (A.Image * 1)(_img(0x1000, A.U8))
+    o = (A.Image * 1)(_img(0x2000, A.F32))
+    h = ctypes.c_void_p()
+    assert L.mact_batch_plan_create(p, i, o, 0, None, None, ctypes.byref(h)) == A.E_INVALID
+    t = A.Tune(100, 4096, 4, 32)
+    assert L.mact_batch_plan_create(p, i, o, 1, ctypes.byref(t), None, ctypes.byref(h)) == A.E_INVALID
+    t = A.Tune(256, 1000, 4, 32)
+    assert L.mact_batch_plan_create(p, i, o, 1, ctypes.byref(t), None, ctypes.byref(h)) == A.E_INVALID
+    t = A.Tune(256, 4096, 3, 32)
+    assert L.mact_batch_plan_create(p, i, o, 1, ctypes.byref(t), None, ctypes.byref(h)) == A.E_INVALID
+    cfg = A.ServerConfig()
+    cfg.arena_bytes, cfg.max_batch, cfg.compute_streams, cfg.max_queue = 1 << 30, 64, 2, 100
+    for x in range(3):
+        cfg.params[x] = M.default_params(x)
+    bad = A.ServerConfig.from_buffer_copy(cfg)
+    bad.compute_streams = 9
+    assert L.mact_server_create(ctypes.byref(bad), ctypes.byref(h)) == A.E_INVALID
+    bad = A.ServerConfig.from_buffer_copy(cfg)
+    bad.arena_bytes = 1000
+    assert L.mact_server_create(ctypes.byref(bad), ctypes.byref(h)) == A.E_INVALID
+    bad = A.ServerConfig.from_buffer_copy(cfg)
+    bad.params[1] = M.default_params(0)
+    assert L.mact_server_create(ctypes.byref(bad), ctypes.byref(h)) == A.E_INVALID
+
+
+def test_fast_division_method():
+    # the round-up multiplier division the kernels use for pixel coordinates
+    def make(d):
+        l = 0
+        while (1 << l) < d:
+            l += 1
+        return ((1 << 32) * ((1 << l) - d)) // d + 1, l
+
+    g = np.random.default_rng(0)
+    for d in [1, 2, 3, 5, 7, 255, 256, 1920, 1080 * 1920, 4096 * 4096, 2 ** 31 - 1]:
+        m, s = make(d)
+        n = np.concatenate([g.integers(0, 2 ** 32, 20000, dtype=np.uint64), np.arange(0, 5000, dtype=np.uint64),
+                            np.array([2 ** 32 - 1, d, d - 1, 2 * d, 2 * d - 1], dtype=np.uint64)])
+        n = n[n < 2 ** 32]
+        q = (((n * np.uint64(m)) >> np.uint64(32)) + n) >> np.uint64(s)
+        np.testing.assert_array_equal(q, n // np.uint64(d))

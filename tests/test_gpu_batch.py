@@ -1,0 +1,142 @@
+"""The batched form (mact_batch_plan_*): one persistent, graph-captured launch
+over uneven images of mixed element types, layouts and transforms gives the
+same bits as one plain mact_transform per image, for every launch shape; graph
+replays equal eager launches; sampled pixels match the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_1009_0854_amd as M
+    return M
+
+
+def _mixed_batch(M, n, seed, lo=17, hi=700):
+    """n images: sizes log-uniform in [lo, hi]; dtype/layout/transform drawn per image."""
+    sizes, g = synth.uneven_sizes(n, seed, lo, hi)
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    params, ins, outs, lays, gams, olays, xfs = [], [], [], [], [], [], []
+    for i, (h, w) in enumerate(sizes):
+        kind = int(g.integers(0, 5))
+        xf = int(g.integers(0, 3))
+        if kind in (0, 1):  # packed 8-bit HWC (the 4-pixel path)
+            x = torch.randint(0, 256, (h, w, 3), dtype=torch.uint8, device="cuda", generator=gen)
+            lay, gam = "hwc", "bt709"
+        elif kind == 2:  # float16 linear HWC
+            x = torch.rand((h, w, 3), device="cuda", generator=gen).half()
+            lay, gam = "hwc", "none"
+        elif kind == 3:  # float32 CHW, some values outside [0, 1]
+            x = torch.rand((3, h, w), device="cuda", generator=gen) * 1.1 - 0.05
+            lay, gam = "chw", "none"
+        else:  # row-strided 8-bit view
+            base = torch.randint(0, 256, (h, w + 5, 3), dtype=torch.uint8, device="cuda", generator=gen)
+            x = base[:, 2:2 + w, :]
+            lay, gam = "hwc", "srgb"
+        out = torch.empty(x.shape, dtype=torch.float32, device="cuda")
+        params.append(M.default_params(xf))
+        ins.append(x)
+        outs.append(out)
+        lays.append(lay)
+        gams.append(gam)
+        olays.append(lay)
+        xfs.append(xf)
+    return params, ins, outs, lays, gams, olays, xfs
+
+
+def _plain(M, params, ins, lays, gams):
+    return [M.transform(x, params=p, layout=l, gamma=gm) for p, x, l, gm in zip(params, ins, lays, gams)]
+
+
+TUNES = [None, (256, 4096, 4, 32), (1024, 16384, 4, 16), (256, 4096, 1, 32), (64, 256, 1, 8), (512, 65536, 4, 64)]
+
+
+@pytest.mark.parametrize("tune", TUNES, ids=["autotuned", "b256v4", "b1024v4", "b256v1", "b64t256", "b512big"])
+def test_batch_equals_plain_bitwise(M, tune):
+    params, ins, outs, lays, gams, olays, _ = _mixed_batch(M, 40, seed=3)
+    ref = _plain(M, params, ins, lays, gams)
+    t = M.Tune(*tune) if tune else None
+    plan = M.BatchPlan(params, ins, outs, lays, gams, olays, tune=t)
+    for use_graph in (True, False):
+        for o in outs:
+            o.fill_(float("nan"))
+        plan.launch(use_graph=use_graph)
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, ref)):
+            assert torch.equal(o, r), (i, use_graph)
+    tt = plan.tune
+    assert tt.block in (64, 128, 256, 512, 1024) and tt.vec in (1, 4)
+    plan.close()
+
+
+def test_graph_replays_with_eager_work_between(M):
+    params, ins, outs, lays, gams, olays, _ = _mixed_batch(M, 25, seed=4)
+    ref = _plain(M, params, ins, lays, gams)
+    plan = M.BatchPlan(params, ins, outs, lays, gams, olays)
+    side = torch.empty((300, 301, 3), dtype=torch.float32, device="cuda")
+    xin = torch.randint(0, 256, (300, 301, 3), dtype=torch.uint8, device="cuda")
+    for rep in range(4):
+        for o in outs:
+            o.zero_()
+        M.transform(xin, params=M.default_params(rep % 3), out=side)  # eager work between replays
+        plan.launch(use_graph=True)
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, ref)):
+            assert torch.equal(o, r), (rep, i)
+    plan.close()
+
+
+def test_config3_uneven_1000_images_against_plain_and_oracle(M):
+    # 1000 images, width and height log-uniform in 64..4096 (seed 3), 8-bit encoded or float16
+    # linear inputs, a transform per image: one persistent launch vs 1000 plain launches
+    sizes, g = synth.uneven_sizes(1000, 3, 64, 4096)
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    params, ins, outs, lays, gams = [], [], [], [], []
+    for (h, w) in sizes:
+        if g.random() < 0.5:
+            x = torch.randint(0, 256, (h, w, 3), dtype=torch.uint8, device="cuda", generator=gen)
+            gams.append("bt709")
+        else:
+            x = torch.rand((h, w, 3), device="cuda", generator=gen).half()
+            gams.append("none")
+        params.append(M.default_params(int(g.integers(0, 3))))
+        ins.append(x)
+        outs.append(torch.empty((h, w, 3), dtype=torch.float32, device="cuda"))
+        lays.append("hwc")
+    plan = M.BatchPlan(params, ins, outs, lays, gams)
+    plan.launch()
+    torch.cuda.synchronize()
+    for i in range(0, 1000, 1):
+        r = M.transform(ins[i], params=params[i], gamma=gams[i])
+        assert torch.equal(outs[i], r), i
+    # sampled pixels of a few images against the oracle
+    for i in range(0, 1000, 97):
+        x = ins[i].reshape(-1, 3)
+        k = g.integers(0, x.shape[0], 2000)
+        xv = x[torch.from_numpy(k).cuda()].float().cpu().numpy().astype(np.float64)
+        if ins[i].dtype == torch.uint8:
+            xv = xv / 255.0
+        gv = outs[i].reshape(-1, 3)[torch.from_numpy(k).cuda()].cpu().numpy()
+        ref = P.oracle(params[i].xform, xv, P.coeffs(params[i]), gamma=gams[i])
+        e = P.max_scaled_err(params[i].xform, gv, ref)
+        if params[i].xform == 2 and ins[i].dtype != torch.uint8:
+            # float SCT branch guard: allow pixels near the branch planes
+            R, G, B = xv[:, 0], xv[:, 1], xv[:, 2]
+            near = (np.abs(3 * B * B - (R * R + G * G)) <= 1e-6 * (xv * xv).sum(1)) | (np.abs(G - R) <= 1e-6)
+            e = P.max_scaled_err(2, gv[~near], ref[~near])
+        assert np.all(e <= P.REL), (i, e)
+    plan.close()
+
+
+def test_batch_run_convenience(M):
+    params, ins, outs, lays, gams, olays, _ = _mixed_batch(M, 7, seed=5)
+    ref = _plain(M, params, ins, lays, gams)
+    M.batch_run(params, ins, outs, lays, gams, olays, tune=M.Tune(256, 4096, 4, 32))
+    for o, r in zip(outs, ref):
+        assert torch.equal(o, r)

@@ -1,0 +1,128 @@
+"""GPU parity of lut_build / lut_interp against the oracle's LUT
+interpolators, node hits, and Table 12 reproduced from the GPU's own output."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import colour, lut as OL
+from tests import parity as P
+from tests.cubepool import cube_map_shared
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+METHODS = ["trilinear", "prism", "pyramidal", "tetrahedral"]
+XF = {"lab": 0, "hsi": 1, "sct": 2}
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_1009_0854_amd as M
+    return M
+
+
+def _interp(M, xform, N, method, x_np, layout="hwc"):
+    L = M.lut_build(xform, N)
+    x = torch.from_numpy(np.ascontiguousarray(x_np)).cuda()
+    y = M.lut_interp(L, N, xform, method, x, layout=layout)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.float64), L
+
+
+def _compare(xform, gpu, ref, rlen, mask=None):
+    """Linear channels: |gpu - ref| <= 2e-6 full scale.  Angular channels: the
+    wrapped angle difference times the resultant length (the angle of a short
+    resultant is ill-conditioned)."""
+    xf = XF[xform]
+    g = gpu.reshape(-1, 3)
+    r = ref.reshape(-1, 3)
+    rl = rlen.reshape(-1, 3)
+    if mask is not None:
+        g, r, rl = g[mask], r[mask], rl[mask]
+    for ch, ang in enumerate(OL.ANGULAR[xform]):
+        if ang:
+            d = colour.angle_diff(g[:, ch], r[:, ch]) * rl[:, ch]
+        else:
+            d = np.abs(g[:, ch] - r[:, ch])
+        worst = d.max() / P.SCALE[xf][ch]
+        assert worst <= P.REL, (xform, ch, worst)
+
+
+@pytest.mark.parametrize("N", [17, 33])
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("xform", ["lab", "hsi", "sct"])
+def test_u8_parity(M, xform, method, N):
+    img = synth.uniform_u8(129, 131, seed=N)
+    img.reshape(-1, 3)[:6] = [[0, 0, 0], [255, 255, 255], [128, 128, 128], [255, 0, 0], [0, 0, 255], [17, 17, 200]]
+    gpu, _ = _interp(M, xform, N, method, img)
+    ref, rlen = OL.interp(OL.build(xform, N), xform, method, v8=img)
+    _compare(xform, gpu, ref, rlen)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_float_inputs_and_chw(M, method):
+    g = synth.rng(31)
+    x = g.uniform(-0.05, 1.05, (3, 45, 47)).astype(np.float32)
+    gpu, _ = _interp(M, "lab", 17, method, x, layout="chw")
+    xc = np.moveaxis(x.astype(np.float64), 0, -1)
+    ref, rlen = OL.interp(OL.build("lab", 17), "lab", method, x=xc)
+    mask = None
+    if method == "pyramidal":
+        # the pyramidal form is discontinuous: skip inputs within float32 rounding of a
+        # cell face or of a pyramid boundary (two fractions equal)
+        pos = np.clip(xc.reshape(-1, 3), 0, 1) * 16
+        f = pos - np.minimum(np.floor(pos), 15)
+        near_face = (np.abs(pos - np.rint(pos)) < 1e-5).any(1)
+        near_tie = (np.abs(f[:, 0] - f[:, 1]) < 1e-5) | (np.abs(f[:, 0] - f[:, 2]) < 1e-5) | (np.abs(f[:, 1] - f[:, 2]) < 1e-5)
+        mask = ~(near_face | near_tie)
+    _compare("lab", np.moveaxis(gpu, 0, -1), ref, rlen, mask)
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("N", [9, 17, 33])
+def test_node_hits_are_exact(M, method, N):
+    # at the node inputs (exact binary fractions for N - 1 a power of two) the output is the
+    # stored float32 node, bit for bit
+    idx = np.stack(np.meshgrid(*[np.arange(N)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    x = (idx / (N - 1.0)).astype(np.float32).reshape(1, -1, 3)
+    gpu, L = _interp(M, "lab", N, method, x)
+    nodes = L.cpu().numpy().reshape(N, N, N, 4)[..., :3].reshape(-1, 3)
+    np.testing.assert_array_equal(gpu.reshape(-1, 3), nodes.astype(np.float64))
+    # and the stored nodes are the exact transform rounded once
+    ref = OL.build("lab", N).reshape(-1, 3)
+    assert np.max(np.abs(nodes - ref) / P.SCALE[0]) < 1e-7
+
+
+def _t12(v8, start, shared, key):
+    out = shared[key][start:start + len(v8)]
+    d = colour.delta_e(out, colour.rgb_to_lab(v8 / 255.0))
+    return float(d.sum()), float(d.max())
+
+
+def test_table12_from_gpu_output(M):
+    # all 2^24 colours through the GPU interpolators reproduce Table 12 (trilinear, prism,
+    # tetrahedral; the pyramidal row is unpinned) to the printed digits within float32 rounding
+    from oracle import tables as T
+    cube = torch.from_numpy(synth.cube_u8()).cuda()
+    outs = {}
+    for method in ("trilinear", "prism", "tetrahedral"):
+        for N in (17, 33):
+            L = M.lut_build("lab", N)
+            outs[(method, N)] = M.lut_interp(L, N, "lab", method, cube).reshape(-1, 3).double().cpu().numpy()
+    for key in list(outs):
+        parts = cube_map_shared(_t12, outs, key)
+        mean = sum(p[0] for p in parts) / float(1 << 24)
+        mx = max(p[1] for p in parts)
+        avg_p, max_p = T.T12_LUT_ERR[key]
+        assert mean == pytest.approx(avg_p, abs=2e-6), key
+        assert mx == pytest.approx(max_p, abs=2e-5), key
+
+
+def test_lut_33_goes_through_l2_and_17_sct_through_lds(M):
+    # sizes: 33^3 x 16 B does not fit 160 KB of LDS; 17^3 x 32 B (SCT) does
+    assert M.lut_bytes("lab", 33) > 163840 >= M.lut_bytes("sct", 17)
+    img = synth.uniform_u8(40, 41, seed=9)
+    for xform, N in (("sct", 17), ("sct", 33), ("hsi", 33)):
+        gpu, _ = _interp(M, xform, N, "tetrahedral", img)
+        ref, rlen = OL.interp(OL.build(xform, N), xform, "tetrahedral", v8=img)
+        _compare(xform, gpu, ref, rlen)

@@ -1,0 +1,93 @@
+"""The serving form (mact_server_*): requests of mixed sizes, element types
+and transforms admitted by device memory and run in overlapping batches;
+every result is bitwise the plain path's, alone and in the mix."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def M():
+    import paper_1009_0854_amd as M
+    return M
+
+
+def _requests(n, seed, lo=16, hi=600):
+    sizes, g = synth.uneven_sizes(n, seed, lo, hi)
+    reqs = []
+    for (h, w) in sizes:
+        xf = int(g.integers(0, 3))
+        if g.random() < 0.5:
+            x = torch.from_numpy(g.integers(0, 256, (h, w, 3), dtype=np.uint8)).pin_memory()
+            gamma = "bt709"
+        else:
+            x = torch.from_numpy(g.random((h, w, 3)).astype(np.float16)).pin_memory()
+            gamma = "none"
+        odt = torch.float32 if g.random() < 0.8 else torch.float16
+        y = torch.empty((h, w, 3), dtype=odt).pin_memory()
+        reqs.append((x, y, xf, gamma))
+    return reqs
+
+
+def _plain(M, x, xf, gamma, odt):
+    return M.transform(x.cuda(), xform=xf, gamma=gamma, out_dtype=odt).cpu()
+
+
+def test_mixed_requests_equal_plain(M):
+    reqs = _requests(120, seed=6)
+    srv = M.Server(arena_bytes=64 << 20, max_batch=16, compute_streams=3)
+    ids = [srv.submit(x, y, xf, gm) for x, y, xf, gm in reqs]
+    for i in ids:
+        srv.wait(i, 60000)
+    st = srv.stats()
+    assert st.completed == len(reqs) and st.submitted == len(reqs)
+    assert st.batches >= 1 and st.mean_batch >= 1.0
+    for (x, y, xf, gm), i in zip(reqs, ids):
+        assert torch.equal(y, _plain(M, x, xf, gm, y.dtype)), i
+        assert srv.latency_ms(i) > 0
+    srv.close()
+
+
+def test_alone_equals_in_the_mix(M):
+    reqs = _requests(40, seed=7)
+    srv = M.Server(arena_bytes=256 << 20, max_batch=64, compute_streams=4)
+    x0, y0, xf0, g0 = reqs[0]
+    i = srv.submit(x0, y0, xf0, g0)
+    srv.wait(i)
+    alone = y0.clone()
+    y0.zero_()
+    ids = [srv.submit(x, y, xf, gm) for x, y, xf, gm in reqs]
+    for j in ids:
+        srv.wait(j)
+    assert torch.equal(alone, y0)
+    assert srv.stats().mean_batch > 1.0  # the mix did batch requests together
+    srv.close()
+
+
+def test_admission_limits(M):
+    from paper_1009_0854_amd import _abi
+    srv = M.Server(arena_bytes=2 << 20, max_batch=4, compute_streams=2, max_queue=3)
+    big = torch.zeros((400, 400, 3), dtype=torch.uint8).pin_memory()  # 480 KB in + 1.9 MB out > 2 MiB
+    out = torch.empty((400, 400, 3), dtype=torch.float32).pin_memory()
+    with pytest.raises(_abi.MactError) as e:
+        srv.submit(big, out)
+    assert e.value.status == _abi.E_INVALID
+    # requests that fit only one at a time: every accepted one completes; refusals are MACT_E_BUSY
+    reqs = [(torch.full((300, 300, 3), k, dtype=torch.uint8).pin_memory(),
+             torch.empty((300, 300, 3), dtype=torch.float32).pin_memory()) for k in range(12)]
+    ids, busy = [], 0
+    for x, y in reqs:
+        try:
+            ids.append((srv.submit(x, y), x, y))
+        except _abi.MactError as err:
+            assert err.status == _abi.E_BUSY
+            busy += 1
+    for i, x, y in ids:
+        srv.wait(i)
+        assert torch.equal(y, _plain(M, x, 0, "bt709", torch.float32))
+    assert srv.stats().rejected == busy
+    srv.close()
