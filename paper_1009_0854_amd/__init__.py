@@ -122,9 +122,19 @@ def image(t, layout="hwc", gamma="bt709"):
     return im
 
 
-def _out_like(x, layout, out_dtype):
+def _out_like(x, layout, out_layout, out_dtype):
+    """An output tensor for x (in `layout`) in `out_layout`."""
     torch = _torch()
-    return torch.empty(x.shape, dtype=out_dtype, device=x.device)
+    shape = tuple(x.shape)
+    lay = "hwc" if layout in ("hwc", HWC) else "chw"
+    olay = "hwc" if out_layout in ("hwc", HWC) else "chw"
+    if lay != olay:
+        lead = shape[:-3]
+        if lay == "hwc":  # (..., H, W, 3) -> (..., 3, H, W)
+            shape = lead + (3, shape[-3], shape[-2])
+        else:  # (..., 3, H, W) -> (..., H, W, 3)
+            shape = lead + (shape[-2], shape[-1], 3)
+    return torch.empty(shape, dtype=out_dtype, device=x.device)
 
 
 def transform(x, xform="lab", params=None, layout="hwc", gamma="bt709", out=None, out_layout=None,
@@ -134,7 +144,7 @@ def transform(x, xform="lab", params=None, layout="hwc", gamma="bt709", out=None
     p = params if params is not None else default_params(xform)
     out_layout = layout if out_layout is None else out_layout
     if out is None:
-        out = _out_like(x, out_layout, out_dtype or torch.float32)
+        out = _out_like(x, layout, out_layout, out_dtype or torch.float32)
     A.check(lib().mact_transform(ctypes.byref(p), ctypes.byref(image(x, layout, gamma)),
                                  ctypes.byref(image(out, out_layout)), _stream(stream)))
     return out
@@ -173,7 +183,7 @@ def lut_interp(lut, n, xform, method, x, layout="hwc", out=None, out_layout=None
     torch = _torch()
     out_layout = layout if out_layout is None else out_layout
     if out is None:
-        out = _out_like(x, out_layout, out_dtype or torch.float32)
+        out = _out_like(x, layout, out_layout, out_dtype or torch.float32)
     m = A.METHODS[method] if isinstance(method, str) else int(method)
     A.check(lib().lut_interp(ctypes.c_void_p(lut.data_ptr()), int(n), _xf(xform), m,
                              ctypes.byref(image(x, layout, "none")), ctypes.byref(image(out, out_layout)),
@@ -238,7 +248,7 @@ def batch_run(params, ins, outs, layouts=None, gammas=None, out_layouts=None, tu
 class Server:
     """Continuous-batching engine (mact_server_*)."""
 
-    def __init__(self, arena_bytes=1 << 30, max_batch=64, compute_streams=4, max_queue=1 << 16, params=None):
+    def __init__(self, arena_bytes=1 << 30, max_batch=64, compute_streams=2, max_queue=1 << 16, params=None):
         cfg = ServerConfig()
         cfg.arena_bytes = int(arena_bytes)
         cfg.max_batch = int(max_batch)

@@ -29,22 +29,6 @@ namespace mact {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint32_t bbyte_of(uint3 w, int i) {
-  const uint32_t word = i < 4 ? w.x : (i < 8 ? w.y : w.z);
-  return (word >> (8 * (i & 3))) & 0xffu;
-}
-
-template <int XF, int DEG>
-__device__ __forceinline__ void bpx4(const KCoef& k, const float* gtab, uint3 w, float o[12]) {
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint32_t r = bbyte_of(w, 3 * j), g = bbyte_of(w, 3 * j + 1), b = bbyte_of(w, 3 * j + 2);
-    if (XF == MACT_LAB) lab_px<DEG>(k, gtab[r], gtab[g], gtab[b], o + 3 * j);
-    else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o + 3 * j);
-    else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o + 3 * j);
-  }
-}
-
 template <int DEG, int VEC>
 __global__ __launch_bounds__(1024) void k_batch(const BDesc* __restrict__ descs, const KCoef* __restrict__ coefs,
                                                 const uint32_t* __restrict__ tile_start, int32_t count,
@@ -73,11 +57,19 @@ __global__ __launch_bounds__(1024) void k_batch(const BDesc* __restrict__ descs,
       f4* s = s_out + wv * 192;
       for (uint32_t c = wv; c < nchunk; c += nw) {
         const uint32_t cp = p0 + (c << 8);
-        const uint3 w = reinterpret_cast<const uint3*>(d.src.ptr)[(cp >> 2) + lane];
+        const uint3* win = reinterpret_cast<const uint3*>(d.src.ptr);
         float o[12];
-        if (k.xform == MACT_LAB) bpx4<MACT_LAB, DEG>(k, g, w, o);
-        else if (k.xform == MACT_HSI) bpx4<MACT_HSI, DEG>(k, g, w, o);
-        else bpx4<MACT_SCT, DEG>(k, g, w, o);
+        if (d.fast == 1) {  // 8-bit: 12 bytes (4 pixels) per lane
+          const uint3 w = win[(cp >> 2) + lane];
+          if (k.xform == MACT_LAB) px4_u8<MACT_LAB, DEG>(k, g, w, o);
+          else if (k.xform == MACT_HSI) px4_u8<MACT_HSI, DEG>(k, g, w, o);
+          else px4_u8<MACT_SCT, DEG>(k, g, w, o);
+        } else {  // float16: 24 bytes per lane
+          const uint3 wa = win[(cp >> 1) + 2 * lane], wb = win[(cp >> 1) + 2 * lane + 1];
+          if (k.xform == MACT_LAB) px4_f16<MACT_LAB, DEG>(k, d.gamma, wa, wb, o);
+          else if (k.xform == MACT_HSI) px4_f16<MACT_HSI, DEG>(k, d.gamma, wa, wb, o);
+          else px4_f16<MACT_SCT, DEG>(k, d.gamma, wa, wb, o);
+        }
         __builtin_amdgcn_wave_barrier();
         s[3 * lane] = f4{o[0], o[1], o[2], o[3]};
         s[3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
@@ -116,9 +108,9 @@ mact_status make_batch_descs(const mact_params& p, const mact_image* in, const m
   KCoef k;
   *deg = pack_coef(p, &k);
   const int gamma = p.xform == MACT_LAB ? hi.gamma : MACT_GAMMA_NONE;
-  const bool fast = hi.dtype == MACT_U8 && hi.layout == MACT_HWC && hi.packed && ho.dtype == MACT_F32 &&
-                    ho.layout == MACT_HWC && ho.packed && ((uintptr_t)hi.data % 4 == 0) &&
-                    ((uintptr_t)ho.data % 16 == 0);
+  // packed 8-bit (1) or float16 (2) HWC in, packed float32 HWC out: the 4-pixel LDS path
+  const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16) && hi.layout == MACT_HWC && hi.packed &&
+                    ho.dtype == MACT_F32 && ho.layout == MACT_HWC && ho.packed;
   const int64_t per = images_per_launch(hi);
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
@@ -129,7 +121,8 @@ mact_status make_batch_descs(const mact_params& p, const mact_image* in, const m
     d.n_px = (uint32_t)(cnt * hi.W * hi.H);
     d.coef = coef;
     d.gamma = gamma;
-    d.fast = fast ? 1 : 0;
+    const bool al = (uintptr_t)d.src.ptr % 4 == 0 && (uintptr_t)d.dst.ptr % 16 == 0;
+    d.fast = (hwc4 && al) ? (hi.dtype == MACT_U8 ? 1 : 2) : 0;
     descs->push_back(d);
   }
   return MACT_OK;

@@ -6,11 +6,13 @@
 // angular channels are stored as unit vectors so that circular interpolation
 // needs no trigonometry per corner.
 //
-// Interpolation: one pixel per lane step over a grid of a few workgroups per
-// CU.  When the packed grid fits the workgroup's LDS (17^3 x 16 B = 78.6 KB) it
-// is staged there once per workgroup and every corner gather is an LDS read;
+// Interpolation: a grid of a few workgroups per CU strides over the image.
+// When the packed grid fits the workgroup's LDS (17^3 x 16 B = 78.6 KB) it is
+// staged there once per workgroup and every corner gather is an LDS read;
 // larger grids (33^3 x 16 B = 575 KB) are gathered from global memory through
-// the L2.  Each method is a weighted sum of its 8, 6, 5 or 4 corners.
+// the L2.  Packed 8-bit HWC -> float32 HWC takes k_lut4 (the transform's
+// 12-byte loads and LDS-transposed 1 KB stores); other shapes take k_lut, one
+// pixel per lane.  Each method is a weighted sum of its 8, 6, 5 or 4 corners.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -25,12 +27,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 static int node_floats(int xform) { return xform == MACT_SCT ? 8 : 4; }
 
 // ---------------------------------------------------------------- device
-
-template <bool LDS>
-struct NodeSrc {
-  const f4* p;
-  __device__ __forceinline__ f4 at(uint32_t i) const { return p[i]; }
-};
 
 // Extraction: cell and fraction per channel.
 __device__ __forceinline__ void locate_u8(uint32_t v, uint32_t N, uint32_t& i, float& f) {
@@ -129,11 +125,57 @@ struct Corners<MACT_PYRAMIDAL> {
   }
 };
 
+// One pixel: the method's weighted corner sum at cell i, fractions f.
+template <int METHOD, int XF>
+__device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, uint32_t N, const uint32_t i[3], const float f[3],
+                                       float o[3]) {
+  const int NF = XF == MACT_SCT ? 2 : 1;  // float4 per node
+  const uint32_t base = (i[0] * N + i[1]) * N + i[2];
+  uint32_t off[8];
+  float w[8];
+  Corners<METHOD>::get(f[0], f[1], f[2], N * N, N, off, w);
+  f4 a0 = {0.0f, 0.0f, 0.0f, 0.0f};
+  float a1 = 0.0f;
+#pragma unroll
+  for (int c = 0; c < Corners<METHOD>::K; ++c) {
+    const uint32_t n = (base + off[c]) * NF;
+    const f4 v0 = nodes[n];
+    a0.x = __builtin_fmaf(w[c], v0.x, a0.x);
+    a0.y = __builtin_fmaf(w[c], v0.y, a0.y);
+    a0.z = __builtin_fmaf(w[c], v0.z, a0.z);
+    a0.w = __builtin_fmaf(w[c], v0.w, a0.w);
+    if (NF == 2) a1 = __builtin_fmaf(w[c], nodes[n + 1].x, a1);
+  }
+  if (XF == MACT_LAB) {
+    o[0] = a0.x; o[1] = a0.y; o[2] = a0.z;
+  } else if (XF == MACT_HSI) {
+    float h = atan2f(a0.y, a0.x);
+    if (h < 0.0f) h += kTwoPif;
+    o[0] = h; o[1] = a0.z; o[2] = a0.w;
+  } else {
+    o[0] = a0.x;
+    o[1] = atan2f(a0.z, a0.y);
+    o[2] = atan2f(a1, a0.w);
+  }
+}
+
+template <int METHOD, int XF>
+__device__ __forceinline__ void lut_px_u8(const f4* __restrict__ nodes, uint32_t N, uint32_t r, uint32_t g, uint32_t b,
+                                          float o[3]) {
+  uint32_t i[3];
+  float f[3];
+  locate_u8(r, N, i[0], f[0]);
+  locate_u8(g, N, i[1], f[1]);
+  locate_u8(b, N, i[2], f[2]);
+  lut_px<METHOD, XF>(nodes, N, i, f, o);
+}
+
+// Any element type, layout and stride: one pixel per lane step.
 template <int METHOD, int XF, bool LDS>
 __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32_t N, KImage src, KImage dst,
-                                             uint32_t n_px) {
+                                              uint32_t n_px) {
   extern __shared__ f4 s_lut[];
-  const int NF = XF == MACT_SCT ? 2 : 1;  // float4 per node
+  const int NF = XF == MACT_SCT ? 2 : 1;
   const uint32_t n_nodes = N * N * N;
   const f4* nodes = lut;
   if (LDS) {
@@ -141,11 +183,10 @@ __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32
     __syncthreads();
     nodes = s_lut;
   }
-  const uint32_t sR = N * N, sG = N;
   const bool u8 = src.dtype == MACT_U8;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n_px; p += stride) {
-    float v[3];
+    float v[3], o[3];
     load_px(src, p, v);
     uint32_t i[3];
     float f[3];
@@ -154,35 +195,60 @@ __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32
       if (u8) locate_u8((uint32_t)v[c], N, i[c], f[c]);
       else locate_f(v[c], N, i[c], f[c]);
     }
-    const uint32_t base = (i[0] * N + i[1]) * N + i[2];
-    uint32_t off[8];
-    float w[8];
-    Corners<METHOD>::get(f[0], f[1], f[2], sR, sG, off, w);
-    f4 a0 = {0.0f, 0.0f, 0.0f, 0.0f}, a1 = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int c = 0; c < Corners<METHOD>::K; ++c) {
-      const uint32_t n = (base + off[c]) * NF;
-      const f4 v0 = nodes[n];
-      a0.x = __builtin_fmaf(w[c], v0.x, a0.x);
-      a0.y = __builtin_fmaf(w[c], v0.y, a0.y);
-      a0.z = __builtin_fmaf(w[c], v0.z, a0.z);
-      a0.w = __builtin_fmaf(w[c], v0.w, a0.w);
-      if (NF == 2) a1.x = __builtin_fmaf(w[c], nodes[n + 1].x, a1.x);
-    }
-    float o[3];
-    if (XF == MACT_LAB) {
-      o[0] = a0.x; o[1] = a0.y; o[2] = a0.z;
-    } else if (XF == MACT_HSI) {
-      float h = atan2f(a0.y, a0.x);
-      if (h < 0.0f) h += kTwoPif;
-      o[0] = h; o[1] = a0.z; o[2] = a0.w;
-    } else {
-      o[0] = a0.x;
-      o[1] = atan2f(a0.z, a0.y);
-      o[2] = atan2f(a1.x, a0.w);
-    }
+    lut_px<METHOD, XF>(nodes, N, i, f, o);
     store_px(dst, p, o);
   }
+}
+
+// Packed 8-bit HWC -> packed float32 HWC with the access pattern of the
+// transform's hot path: each wave takes 256-pixel chunks (grid-stride, since
+// a staged LUT is worth keeping), each lane reads its 4 pixels with one
+// 12-byte load, and the results leave through the wave's LDS slice as 1 KB
+// contiguous stores.  LDS holds the LUT (when LDS) followed by 3 KB per wave.
+template <int METHOD, int XF, bool LDS>
+__global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint32_t N, const uint8_t* __restrict__ in,
+                                               float* __restrict__ out, uint32_t n_px) {
+  extern __shared__ f4 smem[];
+  const int NF = XF == MACT_SCT ? 2 : 1;
+  const uint32_t n_nodes = N * N * N;
+  const f4* nodes = lut;
+  f4* tbuf = smem + (LDS ? n_nodes * NF : 0);
+  if (LDS) {
+    for (uint32_t i = threadIdx.x; i < n_nodes * NF; i += blockDim.x) smem[i] = lut[i];
+    __syncthreads();
+    nodes = smem;
+  }
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  f4* s = tbuf + wv * 192;
+  const uint32_t n_chunks = n_px >> 8;
+  for (uint32_t c = blockIdx.x * nw + wv; c < n_chunks; c += gridDim.x * nw) {
+    const uint3 w = reinterpret_cast<const uint3*>(in)[(size_t)c * 64 + lane];
+    float o[12];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      lut_px_u8<METHOD, XF>(nodes, N, byte_of(w, 3 * j), byte_of(w, 3 * j + 1), byte_of(w, 3 * j + 2), o + 3 * j);
+    __builtin_amdgcn_wave_barrier();
+    s[3 * lane] = f4{o[0], o[1], o[2], o[3]};
+    s[3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
+    s[3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): every lane's LDS writes have landed
+    __builtin_amdgcn_wave_barrier();
+    f4* d = reinterpret_cast<f4*>(out) + (size_t)c * 192;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(s[q * 64 + lane], d + q * 64 + lane);
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+  }
+  const uint32_t tail0 = n_chunks << 8;
+  if (blockIdx.x == 0)
+    for (uint32_t p = tail0 + threadIdx.x; p < n_px; p += blockDim.x) {
+      float o[3];
+      lut_px_u8<METHOD, XF>(nodes, N, in[3 * (size_t)p], in[3 * (size_t)p + 1], in[3 * (size_t)p + 2], o);
+      out[3 * (size_t)p] = o[0];
+      out[3 * (size_t)p + 1] = o[1];
+      out[3 * (size_t)p + 2] = o[2];
+    }
 }
 
 // ---------------------------------------------------------------- host
@@ -197,24 +263,57 @@ int max_lds_bytes() {
   return v;
 }
 
+template <typename K>
+static hipError_t allow_lds(K k, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Launch shapes.  LDS-staged grid: 1024-thread workgroups, one or two per CU
+// (as many copies of the grid as the CU's LDS holds), grid-stride.  Grid
+// gathered through the L2: 256-thread workgroups, eight per CU.
 template <int METHOD, int XF>
-static hipError_t launch_lut(const f4* lut, uint32_t N, const KImage& s, const KImage& d, uint32_t n_px,
-                             hipStream_t st) {
+static hipError_t launch_lut(const f4* lut, uint32_t N, const HostImage& hi, const HostImage& ho, int64_t n0,
+                             int64_t cnt, uint32_t n_px, hipStream_t st) {
   const size_t bytes = (size_t)N * N * N * node_floats(XF) * sizeof(float);
-  const bool lds = bytes <= (size_t)max_lds_bytes();
-  // staging costs one grid read per workgroup: when staging, one long-lived
-  // 1024-thread workgroup per CU (two if two copies fit the CU's LDS)
+  const size_t lds_max = (size_t)max_lds_bytes();
+  const void* ip = static_cast<const char*>(hi.data) + (size_t)(n0 * hi.bs) * hi.esize;
+  float* op = static_cast<float*>(ho.data) + (size_t)(n0 * ho.bs);
+  const bool fast = hi.dtype == MACT_U8 && hi.layout == MACT_HWC && hi.packed && ho.dtype == MACT_F32 &&
+                    ho.layout == MACT_HWC && ho.packed && (uintptr_t)ip % 4 == 0 && (uintptr_t)op % 16 == 0;
+  const size_t t_lds = 16 * 192 * sizeof(f4);  // k_lut4 with 1024 threads: 16 waves x 3 KB
+  // a grid that fits LDS alone but not beside k_lut4's transpose buffers (17^3 SCT) is
+  // still worth staging: k_lut below
+  if (fast && (bytes + t_lds <= lds_max || bytes > lds_max)) {
+    const bool lds = bytes + t_lds <= lds_max;
+    const unsigned block = lds ? 1024 : 256;
+    const size_t shm = (lds ? bytes : 0) + (size_t)(block / 64) * 192 * sizeof(f4);
+    const uint64_t chunks = std::max<uint64_t>(1, n_px >> 8);
+    const uint64_t per_cu = lds ? std::max<uint64_t>(1, std::min<uint64_t>(2, lds_max / shm)) : 8;
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((chunks + block / 64 - 1) / (block / 64),
+                                                                             (uint64_t)device_cus() * per_cu));
+    const uint8_t* in8 = static_cast<const uint8_t*>(ip);
+    if (lds) {
+      auto k = k_lut4<METHOD, XF, true>;
+      hipError_t e = allow_lds(k, shm);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, lut, N, in8, op, n_px);
+    } else {
+      auto k = k_lut4<METHOD, XF, false>;
+      hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, lut, N, in8, op, n_px);
+    }
+    return hipGetLastError();
+  }
+  const KImage s = kimage(hi, n0, cnt), d = kimage(ho, n0, cnt);
+  const bool lds = bytes <= lds_max;
   const unsigned block = lds ? 1024 : 256;
   const uint64_t need = (n_px + block - 1) / block;
-  const uint64_t per_cu = lds ? std::max<uint64_t>(1, (uint64_t)max_lds_bytes() / bytes) : 8;
-  const uint64_t cap = (uint64_t)device_cus() * std::min<uint64_t>(per_cu, 2);
-  const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(need, cap));
+  const uint64_t per_cu = lds ? std::max<uint64_t>(1, std::min<uint64_t>(2, lds_max / bytes)) : 8;
+  const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(need, (uint64_t)device_cus() * per_cu));
   if (lds) {
     auto k = k_lut<METHOD, XF, true>;
-    if (bytes > 65536) {
-      hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-      if (e != hipSuccess) return e;
-    }
+    hipError_t e = allow_lds(k, bytes);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(grid), dim3(block), bytes, st, lut, N, s, d, n_px);
   } else {
     hipLaunchKernelGGL((k_lut<METHOD, XF, false>), dim3(grid), dim3(block), 0, st, lut, N, s, d, n_px);
@@ -223,13 +322,13 @@ static hipError_t launch_lut(const f4* lut, uint32_t N, const KImage& s, const K
 }
 
 template <int XF>
-static hipError_t launch_lut_m(int method, const f4* lut, uint32_t N, const KImage& s, const KImage& d, uint32_t n_px,
-                               hipStream_t st) {
+static hipError_t launch_lut_m(int method, const f4* lut, uint32_t N, const HostImage& hi, const HostImage& ho,
+                               int64_t n0, int64_t cnt, uint32_t n_px, hipStream_t st) {
   switch (method) {
-    case MACT_TRILINEAR: return launch_lut<MACT_TRILINEAR, XF>(lut, N, s, d, n_px, st);
-    case MACT_PRISM: return launch_lut<MACT_PRISM, XF>(lut, N, s, d, n_px, st);
-    case MACT_PYRAMIDAL: return launch_lut<MACT_PYRAMIDAL, XF>(lut, N, s, d, n_px, st);
-    default: return launch_lut<MACT_TETRAHEDRAL, XF>(lut, N, s, d, n_px, st);
+    case MACT_TRILINEAR: return launch_lut<MACT_TRILINEAR, XF>(lut, N, hi, ho, n0, cnt, n_px, st);
+    case MACT_PRISM: return launch_lut<MACT_PRISM, XF>(lut, N, hi, ho, n0, cnt, n_px, st);
+    case MACT_PYRAMIDAL: return launch_lut<MACT_PYRAMIDAL, XF>(lut, N, hi, ho, n0, cnt, n_px, st);
+    default: return launch_lut<MACT_TETRAHEDRAL, XF>(lut, N, hi, ho, n0, cnt, n_px, st);
   }
 }
 
@@ -295,11 +394,10 @@ extern "C" mact_status lut_interp(const float* dev_lut, int32_t n, int32_t xform
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
     const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
-    const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
     hipError_t e;
-    if (xform == MACT_LAB) e = launch_lut_m<MACT_LAB>(method, lut, n, ks, kd, n_px, st);
-    else if (xform == MACT_HSI) e = launch_lut_m<MACT_HSI>(method, lut, n, ks, kd, n_px, st);
-    else e = launch_lut_m<MACT_SCT>(method, lut, n, ks, kd, n_px, st);
+    if (xform == MACT_LAB) e = launch_lut_m<MACT_LAB>(method, lut, n, hi, ho, n0, cnt, n_px, st);
+    else if (xform == MACT_HSI) e = launch_lut_m<MACT_HSI>(method, lut, n, hi, ho, n0, cnt, n_px, st);
+    else e = launch_lut_m<MACT_SCT>(method, lut, n, hi, ho, n0, cnt, n_px, st);
     if ((s = hip_check(e, "lut_interp: launch")) != MACT_OK) return s;
   }
   return MACT_OK;

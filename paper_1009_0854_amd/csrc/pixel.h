@@ -227,4 +227,45 @@ __device__ __forceinline__ void eval_px(const KCoef& k, bool u8, int gamma, cons
   }
 }
 
+
+// ---------------------------------------------------------------- 4-pixel groups
+
+// Byte i (0..11) of 12 bytes held as one 12-byte word.
+__device__ __forceinline__ uint32_t byte_of(uint3 w, int i) {
+  const uint32_t word = i < 4 ? w.x : (i < 8 ? w.y : w.z);
+  return (word >> (8 * (i & 3))) & 0xffu;
+}
+
+// Half i (0..11) of 24 bytes held as two 12-byte words.
+__device__ __forceinline__ float half_of(uint3 a, uint3 b, int i) {
+  const uint3 w = i < 6 ? a : b;
+  const int j = i < 6 ? i : i - 6;
+  const uint32_t word = j < 2 ? w.x : (j < 4 ? w.y : w.z);
+  const uint16_t bits = (uint16_t)(word >> (16 * (j & 1)));
+  return clamp01(__half2float(__ushort_as_half(bits)));
+}
+
+template <int XF, int DEG>
+__device__ __forceinline__ void px4_u8(const KCoef& k, const float* gtab, uint3 w, float o[12]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t r = byte_of(w, 3 * j), g = byte_of(w, 3 * j + 1), b = byte_of(w, 3 * j + 2);
+    if (XF == MACT_LAB) lab_px<DEG>(k, gtab[r], gtab[g], gtab[b], o + 3 * j);
+    else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o + 3 * j);
+    else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o + 3 * j);
+  }
+}
+
+// The same 4 pixels from float16 input: eval_px's arithmetic for float inputs.
+template <int XF, int DEG>
+__device__ __forceinline__ void px4_f16(const KCoef& k, int gamma, uint3 wa, uint3 wb, float o[12]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float r = half_of(wa, wb, 3 * j), g = half_of(wa, wb, 3 * j + 1), b = half_of(wa, wb, 3 * j + 2);
+    if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(r, gamma), lin_float(g, gamma), lin_float(b, gamma), o + 3 * j);
+    else if (XF == MACT_HSI) hsi_px<DEG>(k, r, g, b, kInv3, o + 3 * j);
+    else sct_px<DEG>(k, r, g, b, 1.0f, o + 3 * j);
+  }
+}
+
 }  // namespace mact

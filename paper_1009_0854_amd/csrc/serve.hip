@@ -6,14 +6,21 @@
 //      input and output bytes fit the device arena (first-fit free list over a
 //      single allocation, 256-byte granules, neighbours merged on free); the
 //      input copy is issued on the copy stream and an event recorded;
-//   2. requests whose input copy has completed become ready;
-//   3. when a compute slot is free, every ready request (up to max_batch) is
-//      put into one batch: descriptors are staged in pinned memory, copied to
-//      the slot's device buffers, the batched kernel is launched on the slot's
-//      stream and each output is copied back on the same stream; batches in
+//   2. requests whose input copy has completed become ready (the scheduler
+//      polls the copy events: with few hardware queues per process, device-side
+//      waits across streams were measured to stall unrelated copies);
+//      when a compute slot is free, every ready request (up to max_batch) is
+//      put into one batch: the descriptors and tile list are staged in pinned
+//      memory and copied to the slot's device buffer in one copy, and the
+//      batched kernel is launched; batches in
 //      different slots overlap on the device, and requests that arrive while
-//      batches run join the next one;
-//   4. a finished batch completes its requests and returns their arena space.
+//      batches run join the next one.  Outputs go
+//      back on one device-to-host stream that waits for each batch's kernel,
+//      smallest output first within a batch, so the PCIe link serves copies
+//      one at a time instead of splitting its bandwidth over concurrent ones;
+//   3. a slot is free again as soon as its kernel has finished; each request
+//      completes, and returns its arena space, when its own output copy has
+//      landed (an event per request), not when its whole batch has.
 // The coefficient table of the three transforms stays resident.
 #include <algorithm>
 #include <atomic>
@@ -85,18 +92,16 @@ struct Req {
   int64_t id = 0;
   mact_request r{};
   size_t in_bytes = 0, out_bytes = 0, in_off = 0, out_off = 0;
-  hipEvent_t ev_in = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   Clock::time_point t_submit, t_done;
   bool done = false;
 };
 
 struct Slot {
   hipStream_t stream = nullptr;
-  hipEvent_t ev_done = nullptr;
-  BDesc* d_descs = nullptr;
-  uint32_t* d_tiles = nullptr;
-  BDesc* h_descs = nullptr;  // pinned staging
-  uint32_t* h_tiles = nullptr;
+  char* d_buf = nullptr;  // descriptors, then the tile list
+  char* h_buf = nullptr;  // pinned staging of the same
+  size_t buf_bytes = 0;
   std::vector<Req*> reqs;
   bool busy = false;
   Clock::time_point t_launch;
@@ -111,18 +116,20 @@ struct mact_server {
   int device = 0;
   mact_server_config cfg{};
   int deg = 5;
-  mact_tune tune{512, 32768, 4, 32};
+  mact_tune tune{512, 8192, 4, 32};  // small tiles: a single request still spreads over the CUs
   std::unique_ptr<Arena> arena;
   char* d_arena = nullptr;
   KCoef* d_coefs = nullptr;
-  hipStream_t copy_stream = nullptr;
+  hipStream_t copy_stream = nullptr;  // host -> device, in admission order
+  hipStream_t d2h_stream = nullptr;   // device -> host, in launch order
   std::vector<Slot> slots;
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Req*> queued;   // submitted, not admitted
-  std::vector<Req*> copying; // input copy in flight
-  std::vector<Req*> ready;   // input on the device
+  std::vector<Req*> copying;  // input copy in flight
+  std::vector<Req*> ready;    // input on the device, not yet in a batch
+  std::vector<Req*> draining;  // output copy in flight
   std::unordered_map<int64_t, std::unique_ptr<Req>> all;
   std::vector<double> lat_ms;
   int64_t next_id = 1, submitted = 0, completed = 0, rejected = 0, batches = 0, batched_reqs = 0;
@@ -136,6 +143,7 @@ struct mact_server {
   void poll_copies_locked();
   bool launch_locked(Slot& s);
   bool finish_slots_locked();
+  bool finish_requests_locked();
 };
 
 bool mact_server::admit_locked() {
@@ -152,6 +160,7 @@ bool mact_server::admit_locked() {
     q->in_off = in_off;
     q->out_off = out_off;
     (void)hipEventCreateWithFlags(&q->ev_in, hipEventDisableTiming);
+    (void)hipEventCreateWithFlags(&q->ev_out, hipEventDisableTiming);
     (void)hipMemcpyAsync(d_arena + in_off, q->r.host_in, q->in_bytes, hipMemcpyHostToDevice, copy_stream);
     (void)hipEventRecord(q->ev_in, copy_stream);
     copying.push_back(q);
@@ -161,23 +170,17 @@ bool mact_server::admit_locked() {
 }
 
 void mact_server::poll_copies_locked() {
-  for (size_t i = 0; i < copying.size();) {
-    if (hipEventQuery(copying[i]->ev_in) == hipSuccess) {
-      ready.push_back(copying[i]);
-      copying[i] = copying.back();
-      copying.pop_back();
-    } else {
-      ++i;
-    }
-  }
+  // copies complete in admission order (one copy stream): stop at the first pending one
+  size_t i = 0;
+  while (i < copying.size() && hipEventQuery(copying[i]->ev_in) == hipSuccess) ++i;
+  ready.insert(ready.end(), copying.begin(), copying.begin() + i);
+  copying.erase(copying.begin(), copying.begin() + i);
 }
 
 bool mact_server::launch_locked(Slot& s) {
   if (ready.empty()) return false;
   const size_t n = std::min<size_t>(ready.size(), (size_t)cfg.max_batch);
-  // oldest first
-  std::sort(ready.begin(), ready.end(), [](const Req* a, const Req* b) { return a->id < b->id; });
-  s.reqs.assign(ready.begin(), ready.begin() + n);
+  s.reqs.assign(ready.begin(), ready.begin() + n);  // admission order is arrival order
   ready.erase(ready.begin(), ready.begin() + n);
   std::vector<BDesc> descs;
   descs.reserve(n);
@@ -199,16 +202,23 @@ bool mact_server::launch_locked(Slot& s) {
   }
   std::vector<uint32_t> ts;
   const uint32_t total = build_tiles(descs, (uint32_t)tune.tile, &ts);
-  std::memcpy(s.h_descs, descs.data(), descs.size() * sizeof(BDesc));
-  std::memcpy(s.h_tiles, ts.data(), ts.size() * sizeof(uint32_t));
-  (void)hipMemcpyAsync(s.d_descs, s.h_descs, descs.size() * sizeof(BDesc), hipMemcpyHostToDevice, s.stream);
-  (void)hipMemcpyAsync(s.d_tiles, s.h_tiles, ts.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s.stream);
+  const size_t db = descs.size() * sizeof(BDesc), tb = ts.size() * sizeof(uint32_t);
+  std::memcpy(s.h_buf, descs.data(), db);
+  std::memcpy(s.h_buf + db, ts.data(), tb);
+  (void)hipMemcpyAsync(s.d_buf, s.h_buf, db + tb, hipMemcpyHostToDevice, s.stream);
   (void)hipEventRecord(s.ev_k0, s.stream);
-  (void)launch_batch_kernel(s.d_descs, d_coefs, s.d_tiles, (int32_t)descs.size(), total, tune, deg, s.stream);
+  (void)launch_batch_kernel(reinterpret_cast<const BDesc*>(s.d_buf), d_coefs,
+                            reinterpret_cast<const uint32_t*>(s.d_buf + db), (int32_t)descs.size(), total, tune, deg,
+                            s.stream);
   (void)hipEventRecord(s.ev_k1, s.stream);
-  for (Req* q : s.reqs)
-    (void)hipMemcpyAsync(q->r.host_out, d_arena + q->out_off, q->out_bytes, hipMemcpyDeviceToHost, s.stream);
-  (void)hipEventRecord(s.ev_done, s.stream);
+  (void)hipStreamWaitEvent(d2h_stream, s.ev_k1, 0);
+  std::vector<Req*> by_size(s.reqs);
+  std::stable_sort(by_size.begin(), by_size.end(), [](const Req* a, const Req* b) { return a->out_bytes < b->out_bytes; });
+  for (Req* q : by_size) {
+    (void)hipMemcpyAsync(q->r.host_out, d_arena + q->out_off, q->out_bytes, hipMemcpyDeviceToHost, d2h_stream);
+    (void)hipEventRecord(q->ev_out, d2h_stream);
+    draining.push_back(q);
+  }
   s.busy = true;
   s.t_launch = Clock::now();
   ++batches;
@@ -219,22 +229,36 @@ bool mact_server::launch_locked(Slot& s) {
 bool mact_server::finish_slots_locked() {
   bool any = false;
   for (Slot& s : slots) {
-    if (!s.busy || hipEventQuery(s.ev_done) != hipSuccess) continue;
-    const auto now = Clock::now();
+    if (!s.busy || hipEventQuery(s.ev_k1) != hipSuccess) continue;
     float kms = 0.0f;
     if (hipEventElapsedTime(&kms, s.ev_k0, s.ev_k1) == hipSuccess) busy_ms += kms;
-    for (Req* q : s.reqs) {
-      q->t_done = now;
-      q->done = true;
-      arena->release(q->in_off, q->in_bytes);
-      arena->release(q->out_off, q->out_bytes);
-      (void)hipEventDestroy(q->ev_in);
-      q->ev_in = nullptr;
-      lat_ms.push_back(std::chrono::duration<double, std::milli>(q->t_done - q->t_submit).count());
-      ++completed;
-    }
     s.reqs.clear();
     s.busy = false;
+    any = true;
+  }
+  return any;
+}
+
+bool mact_server::finish_requests_locked() {
+  bool any = false;
+  const auto now = Clock::now();
+  for (size_t i = 0; i < draining.size();) {
+    Req* q = draining[i];
+    if (hipEventQuery(q->ev_out) != hipSuccess) {
+      ++i;
+      continue;
+    }
+    q->t_done = now;
+    q->done = true;
+    arena->release(q->in_off, q->in_bytes);
+    arena->release(q->out_off, q->out_bytes);
+    (void)hipEventDestroy(q->ev_in);
+    (void)hipEventDestroy(q->ev_out);
+    q->ev_in = q->ev_out = nullptr;
+    lat_ms.push_back(std::chrono::duration<double, std::milli>(q->t_done - q->t_submit).count());
+    ++completed;
+    draining[i] = draining.back();
+    draining.pop_back();
     any = true;
   }
   return any;
@@ -245,19 +269,21 @@ void mact_server::loop() {
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     bool progress = false;
+    progress |= finish_requests_locked();
     progress |= finish_slots_locked();
     progress |= admit_locked();
     poll_copies_locked();
     for (Slot& s : slots)
       if (!s.busy) progress |= launch_locked(s);
     if (progress) cv_done.notify_all();
-    const bool in_flight = !copying.empty() || std::any_of(slots.begin(), slots.end(), [](const Slot& s) { return s.busy; });
+    const bool in_flight = !copying.empty() || !draining.empty() ||
+                           std::any_of(slots.begin(), slots.end(), [](const Slot& s) { return s.busy; });
     if (stop && queued.empty() && copying.empty() && ready.empty() && !in_flight) break;
     if (progress) continue;
     if (in_flight || !ready.empty()) {
       // device work outstanding: poll its events again shortly
       lk.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(20));
+      std::this_thread::sleep_for(std::chrono::microseconds(5));
       lk.lock();
     } else {
       cv_work.wait_for(lk, std::chrono::milliseconds(50));
@@ -270,15 +296,13 @@ static void server_free(mact_server* s) {
   if (!s) return;
   for (Slot& sl : s->slots) {
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
-    if (sl.ev_done) (void)hipEventDestroy(sl.ev_done);
     if (sl.ev_k0) (void)hipEventDestroy(sl.ev_k0);
     if (sl.ev_k1) (void)hipEventDestroy(sl.ev_k1);
-    if (sl.d_descs) (void)hipFree(sl.d_descs);
-    if (sl.d_tiles) (void)hipFree(sl.d_tiles);
-    if (sl.h_descs) (void)hipHostFree(sl.h_descs);
-    if (sl.h_tiles) (void)hipHostFree(sl.h_tiles);
+    if (sl.d_buf) (void)hipFree(sl.d_buf);
+    if (sl.h_buf) (void)hipHostFree(sl.h_buf);
   }
   if (s->copy_stream) (void)hipStreamDestroy(s->copy_stream);
+  if (s->d2h_stream) (void)hipStreamDestroy(s->d2h_stream);
   if (s->d_arena) (void)hipFree(s->d_arena);
   if (s->d_coefs) (void)hipFree(s->d_coefs);
   delete s;
@@ -313,19 +337,18 @@ extern "C" mact_status mact_server_create(const mact_server_config* cfg, mact_se
   }
   st = hip_check(hipMemcpy(s->d_coefs, k, sizeof k, hipMemcpyHostToDevice), "mact_server_create: coefficients");
   if (st == MACT_OK) st = hip_check(hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking), "mact_server_create: stream");
+  if (st == MACT_OK) st = hip_check(hipStreamCreateWithFlags(&s->d2h_stream, hipStreamNonBlocking), "mact_server_create: stream");
   s->slots.resize(cfg->compute_streams);
   // descriptors per slot: an image of 2^31 pixels or more splits, but requests are single images
   const size_t nd = (size_t)cfg->max_batch;
   for (Slot& sl : s->slots) {
     if (st != MACT_OK) break;
     st = hip_check(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking), "mact_server_create: stream");
-    if (st == MACT_OK) st = hip_check(hipEventCreateWithFlags(&sl.ev_done, hipEventDisableTiming), "mact_server_create: event");
     if (st == MACT_OK) st = hip_check(hipEventCreate(&sl.ev_k0), "mact_server_create: event");
     if (st == MACT_OK) st = hip_check(hipEventCreate(&sl.ev_k1), "mact_server_create: event");
-    if (st == MACT_OK && (hipMalloc(&sl.d_descs, nd * sizeof(BDesc)) != hipSuccess ||
-                          hipMalloc(&sl.d_tiles, (nd + 1) * sizeof(uint32_t)) != hipSuccess ||
-                          hipHostMalloc(&sl.h_descs, nd * sizeof(BDesc)) != hipSuccess ||
-                          hipHostMalloc(&sl.h_tiles, (nd + 1) * sizeof(uint32_t)) != hipSuccess))
+    sl.buf_bytes = nd * sizeof(BDesc) + (nd + 1) * sizeof(uint32_t);
+    if (st == MACT_OK && (hipMalloc((void**)&sl.d_buf, sl.buf_bytes) != hipSuccess ||
+                          hipHostMalloc((void**)&sl.h_buf, sl.buf_bytes) != hipSuccess))
       st = fail(MACT_E_NOMEM, "mact_server_create: slot buffers");
   }
   if (st != MACT_OK) {
@@ -441,6 +464,7 @@ extern "C" mact_status mact_server_destroy(mact_server* s) {
   for (Slot& sl : s->slots)
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
   if (s->copy_stream) (void)hipStreamSynchronize(s->copy_stream);
+  if (s->d2h_stream) (void)hipStreamSynchronize(s->d2h_stream);
   server_free(s);
   return MACT_OK;
 }

@@ -2,9 +2,11 @@
 // CIELAB transform, and the reference streaming kernels.
 //
 // Two kernel shapes:
-//  * k_u8_hwc: the hot path, packed 8-bit HWC in and packed float32 HWC out,
-//    staged through LDS so that every global store is a contiguous 1 KB per
-//    wave (details at the kernel).
+//  * k_hwc4: the hot path, packed 8-bit (or float16) HWC in and packed
+//    float32 HWC out, staged through LDS so that every global store is a
+//    contiguous 1 KB per wave (details at the kernel).
+//  * k_chw4: packed float32 / float16 CHW, 4 pixels per lane, vector access
+//    per plane.
 //  * k_generic: any element type, layout and stride, one pixel per lane step.
 // Both call the same per-pixel functions (pixel.h), so they give identical bits.
 #include <algorithm>
@@ -147,60 +149,50 @@ static unsigned grid_for(uint64_t work_items, int block, int blocks_per_cu) {
 
 // ---------------------------------------------------------------- kernels
 
-__device__ __forceinline__ uint32_t byte_of(uint3 w, int i) {
-  const uint32_t word = i < 4 ? w.x : (i < 8 ? w.y : w.z);
-  return (word >> (8 * (i & 3))) & 0xffu;
-}
-
-// Packed 8-bit HWC -> packed float32 HWC: the hot path.
+// Packed HWC (8-bit or float16) -> packed float32 HWC: the hot path.
 //
-// A wave owns chunks of 256 pixels (768 input bytes, 3 KB of output).  Each
-// lane loads 12 bytes (4 pixels) with one 12-byte load -- the wave's loads are
-// one contiguous 768-byte run -- and computes its 4 pixels.  The 48 bytes of
-// results go to the wave's slice of LDS, and the wave then writes the chunk
-// back as 16-byte stores in which lane l writes bytes 16 l .. 16 l + 15 of each
-// KB: every store instruction covers 1 KB of contiguous output.  Writing the
-// 48 bytes straight from the lane (a 48-byte stride across the wave) runs at
-// about a third of this bandwidth.  Each wave handles kChunksPerWave chunks
-// and the grid covers the image once (no grid-stride loop).  Requires `in`
-// 4-byte and `out` 16-byte aligned; blockDim.x == kHotBlock.
+// A wave owns chunks of 256 pixels (768 input bytes for 8-bit input, 1536
+// for float16; 3 KB of output).  Each lane loads its 4 pixels (one 12-byte
+// load, or two for float16) -- the wave's loads cover one contiguous run --
+// and computes them.  The 48 bytes of results go to the wave's slice of LDS,
+// and the wave then writes the chunk back as 16-byte stores in which lane l
+// writes bytes 16 l .. 16 l + 15 of each KB: every store instruction covers
+// 1 KB of contiguous output.  Writing the 48 bytes straight from the lane (a
+// 48-byte stride across the wave) runs at about a third of this bandwidth.
+// Each wave handles kChunksPerWave chunks and the grid covers the image once
+// (no grid-stride loop).  Requires `in` 4-byte and `out` 16-byte aligned;
+// blockDim.x == kHotBlock.
 constexpr int kHotBlock = 512;
 constexpr int kChunksPerWave = 2;
 constexpr int kHotWaves = kHotBlock / 64;
 
-template <int XF, int DEG>
-__device__ __forceinline__ void px4_u8(const KCoef& k, const float* gtab, uint3 w, float o[12]) {
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint32_t r = byte_of(w, 3 * j), g = byte_of(w, 3 * j + 1), b = byte_of(w, 3 * j + 2);
-    if (XF == MACT_LAB) lab_px<DEG>(k, gtab[r], gtab[g], gtab[b], o + 3 * j);
-    else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o + 3 * j);
-    else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o + 3 * j);
-  }
-}
-
-template <int DEG, int XF>
-__global__ __launch_bounds__(kHotBlock) void k_u8_hwc(const uint8_t* __restrict__ in, float* __restrict__ out,
-                                                       uint32_t n_px, KCoef k, int gamma) {
+template <int IN, int DEG, int XF>
+__global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in, float* __restrict__ out,
+                                                     uint32_t n_px, KCoef k, int gamma) {
+  constexpr int WPC = IN == MACT_U8 ? 1 : 2;  // 12-byte words per lane per chunk
   __shared__ f4 s_out[kHotWaves][kChunksPerWave * 192];
   __shared__ float gtab[256];
-  if (XF == MACT_LAB) {
+  if (IN == MACT_U8 && XF == MACT_LAB) {
     for (uint32_t i = threadIdx.x; i < 256u; i += kHotBlock) gtab[i] = k_gamma_table[gamma][i];
     __syncthreads();
   }
+  const uint3* win = reinterpret_cast<const uint3*>(in);
   const uint32_t n_chunks = n_px >> 8;
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
   const uint32_t c0 = (blockIdx.x * kHotWaves + wv) * kChunksPerWave;
   if (c0 < n_chunks) {
-    uint3 w[kChunksPerWave];
+    uint3 w[kChunksPerWave][WPC];
 #pragma unroll
     for (int j = 0; j < kChunksPerWave; ++j)
-      if (c0 + j < n_chunks) w[j] = reinterpret_cast<const uint3*>(in)[(size_t)(c0 + j) * 64 + lane];
+      if (c0 + j < n_chunks)
+#pragma unroll
+        for (int q = 0; q < WPC; ++q) w[j][q] = win[((size_t)(c0 + j) * 64 + lane) * WPC + q];
 #pragma unroll
     for (int j = 0; j < kChunksPerWave; ++j) {
       if (c0 + j >= n_chunks) break;
       float o[12];
-      px4_u8<XF, DEG>(k, gtab, w[j], o);
+      if (IN == MACT_U8) px4_u8<XF, DEG>(k, gtab, w[j][0], o);
+      else px4_f16<XF, DEG>(k, gamma, w[j][0], w[j][WPC - 1], o);
       s_out[wv][j * 192 + 3 * lane] = f4{o[0], o[1], o[2], o[3]};
       s_out[wv][j * 192 + 3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
       s_out[wv][j * 192 + 3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
@@ -220,23 +212,75 @@ __global__ __launch_bounds__(kHotBlock) void k_u8_hwc(const uint8_t* __restrict_
   // the last n_px % 256 pixels, one per lane of block 0
   const uint32_t tail0 = n_chunks << 8;
   if (blockIdx.x == 0 && threadIdx.x < n_px - tail0) {
-    const uint32_t p = tail0 + threadIdx.x;
-    const uint32_t r = in[3 * (size_t)p], g = in[3 * (size_t)p + 1], b = in[3 * (size_t)p + 2];
+    const size_t p = tail0 + threadIdx.x;
     float o[3];
-    if (XF == MACT_LAB) lab_px<DEG>(k, gtab[r], gtab[g], gtab[b], o);
-    else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o);
-    else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o);
-    out[3 * (size_t)p] = o[0];
-    out[3 * (size_t)p + 1] = o[1];
-    out[3 * (size_t)p + 2] = o[2];
+    if (IN == MACT_U8) {
+      const uint8_t* b8 = static_cast<const uint8_t*>(in);
+      const uint32_t r = b8[3 * p], g = b8[3 * p + 1], b = b8[3 * p + 2];
+      if (XF == MACT_LAB) lab_px<DEG>(k, gtab[r], gtab[g], gtab[b], o);
+      else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o);
+      else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o);
+    } else {
+      const __half* h = static_cast<const __half*>(in);
+      const float r = clamp01(__half2float(h[3 * p])), g = clamp01(__half2float(h[3 * p + 1])),
+                  b = clamp01(__half2float(h[3 * p + 2]));
+      if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(r, gamma), lin_float(g, gamma), lin_float(b, gamma), o);
+      else if (XF == MACT_HSI) hsi_px<DEG>(k, r, g, b, kInv3, o);
+      else sct_px<DEG>(k, r, g, b, 1.0f, o);
+    }
+    out[3 * p] = o[0];
+    out[3 * p + 1] = o[1];
+    out[3 * p + 2] = o[2];
   }
 }
 
-// Blocks of k_u8_hwc for n_px pixels: every full chunk covered once, and at
+// Blocks of k_hwc4 for n_px pixels: every full chunk covered once, and at
 // least one block for the tail.
 static unsigned hot_grid(uint32_t n_px) {
   const uint32_t per_block = kHotWaves * kChunksPerWave;
   return std::max<unsigned>(1, ((n_px >> 8) + per_block - 1) / per_block);
+}
+
+// Packed CHW (float32 or float16) -> packed float32 CHW, 4 pixels per lane:
+// one 16-byte (8-byte for float16) load per plane and one 16-byte store per
+// plane, each contiguous across the wave.  Requires W H % 4 == 0 and the
+// pointers aligned to the vector width.
+template <int IN, int DEG, int XF>
+__global__ __launch_bounds__(256) void k_chw4(const void* __restrict__ in, float* __restrict__ out, uint32_t n_px,
+                                               uint32_t hw, FastDiv div_hw4, KCoef k, int gamma) {
+  const uint32_t n4 = n_px >> 2, hw4 = hw >> 2;
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t g4 = blockIdx.x * 256u + threadIdx.x; g4 < n4; g4 += stride) {
+    const uint32_t n = div_hw4.div(g4);
+    const size_t base = (size_t)n * 3 * hw + 4 * (size_t)(g4 - n * hw4);  // element offset of plane 0
+    float v[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (IN == MACT_F32) {
+        const f4 x = *reinterpret_cast<const f4*>(static_cast<const float*>(in) + base + (size_t)c * hw);
+        v[c][0] = clamp01(x.x); v[c][1] = clamp01(x.y); v[c][2] = clamp01(x.z); v[c][3] = clamp01(x.w);
+      } else {
+        const uint2 x = *reinterpret_cast<const uint2*>(static_cast<const __half*>(in) + base + (size_t)c * hw);
+        v[c][0] = clamp01(__half2float(__ushort_as_half((uint16_t)x.x)));
+        v[c][1] = clamp01(__half2float(__ushort_as_half((uint16_t)(x.x >> 16))));
+        v[c][2] = clamp01(__half2float(__ushort_as_half((uint16_t)x.y)));
+        v[c][3] = clamp01(__half2float(__ushort_as_half((uint16_t)(x.y >> 16))));
+      }
+    }
+    float o[3][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float r[3];
+      if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(v[0][j], gamma), lin_float(v[1][j], gamma), lin_float(v[2][j], gamma), r);
+      else if (XF == MACT_HSI) hsi_px<DEG>(k, v[0][j], v[1][j], v[2][j], kInv3, r);
+      else sct_px<DEG>(k, v[0][j], v[1][j], v[2][j], 1.0f, r);
+      o[0][j] = r[0]; o[1][j] = r[1]; o[2][j] = r[2];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      __builtin_nontemporal_store(f4{o[c][0], o[c][1], o[c][2], o[c][3]},
+                                  reinterpret_cast<f4*>(out + base + (size_t)c * hw));
+  }
 }
 
 template <int DEG>
@@ -258,50 +302,92 @@ struct KGrad {
   float dp[8], dq[8];  // derivative coefficients of the float32 p and q
 };
 
-// dx = (diag(1/white) M)^T (f~'(t) * (J^T g)), zero outside [0, 1].
+// dx of one pixel: (diag(1/white) M)^T (f~'(t) * (J^T g)), zero outside [0, 1].
+template <int DEG>
+__device__ __forceinline__ void lab_bwd_px(const KCoef& k, const KGrad& kg, const float raw[3], const float g[3],
+                                           float dx[3]) {
+  float x[3];
+  bool in[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    in[c] = raw[c] >= 0.0f && raw[c] <= 1.0f;
+    x[c] = clamp01(raw[c]);
+  }
+  const float t[3] = {
+      __builtin_fmaf(kMw00, x[0], __builtin_fmaf(kMw01, x[1], kMw02 * x[2])),
+      __builtin_fmaf(kMw10, x[0], __builtin_fmaf(kMw11, x[1], kMw12 * x[2])),
+      __builtin_fmaf(kMw20, x[0], __builtin_fmaf(kMw21, x[1], kMw22 * x[2])),
+  };
+  const float gf[3] = {500.0f * g[1], __builtin_fmaf(116.0f, g[0], __builtin_fmaf(-500.0f, g[1], 200.0f * g[2])),
+                       -200.0f * g[2]};
+  float gt[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float d = kLabKf;
+    if (t[c] > kT0f) {
+      const float pv = horner<DEG>(k.p[0], t[c]), qv = horner<DEG>(k.q, t[c]);
+      const float dpv = horner<DEG>(kg.dp, t[c]), dqv = horner<DEG>(kg.dq, t[c]);
+      d = fdiv(__builtin_fmaf(dpv, qv, -(pv * dqv)), qv * qv);
+    }
+    gt[c] = gf[c] * d;
+  }
+  const float r[3] = {
+      __builtin_fmaf(kMw00, gt[0], __builtin_fmaf(kMw10, gt[1], kMw20 * gt[2])),
+      __builtin_fmaf(kMw01, gt[0], __builtin_fmaf(kMw11, gt[1], kMw21 * gt[2])),
+      __builtin_fmaf(kMw02, gt[0], __builtin_fmaf(kMw12, gt[1], kMw22 * gt[2])),
+  };
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dx[c] = in[c] ? r[c] : 0.0f;
+}
+
 template <int DEG>
 __global__ __launch_bounds__(256) void k_lab_backward(KImage xs, KImage gs, KImage ds, uint32_t n_px, KCoef k,
                                                       KGrad kg) {
   const uint32_t stride = gridDim.x * 256u;
   for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < n_px; p += stride) {
-    float x[3], g[3];
-    bool in[3];
+    float raw[3], g[3], dx[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const float raw = static_cast<const float*>(xs.ptr)[elem_off(xs, p, c)];
-      in[c] = raw >= 0.0f && raw <= 1.0f;
-      x[c] = clamp01(raw);
+      raw[c] = static_cast<const float*>(xs.ptr)[elem_off(xs, p, c)];
       g[c] = static_cast<const float*>(gs.ptr)[elem_off(gs, p, c)];
     }
-    const float t[3] = {
-        __builtin_fmaf(kMw00, x[0], __builtin_fmaf(kMw01, x[1], kMw02 * x[2])),
-        __builtin_fmaf(kMw10, x[0], __builtin_fmaf(kMw11, x[1], kMw12 * x[2])),
-        __builtin_fmaf(kMw20, x[0], __builtin_fmaf(kMw21, x[1], kMw22 * x[2])),
-    };
-    const float gf[3] = {500.0f * g[1], __builtin_fmaf(116.0f, g[0], __builtin_fmaf(-500.0f, g[1], 200.0f * g[2])),
-                         -200.0f * g[2]};
-    float gt[3];
+    lab_bwd_px<DEG>(k, kg, raw, g, dx);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float d = kLabKf;
-      if (t[c] > kT0f) {
-        const float pv = horner<DEG>(k.p[0], t[c]), qv = horner<DEG>(k.q, t[c]);
-        const float dpv = horner<DEG>(kg.dp, t[c]), dqv = horner<DEG>(kg.dq, t[c]);
-        d = fdiv(__builtin_fmaf(dpv, qv, -(pv * dqv)), qv * qv);
-      }
-      gt[c] = gf[c] * d;
-    }
-    const float dx[3] = {
-        __builtin_fmaf(kMw00, gt[0], __builtin_fmaf(kMw10, gt[1], kMw20 * gt[2])),
-        __builtin_fmaf(kMw01, gt[0], __builtin_fmaf(kMw11, gt[1], kMw21 * gt[2])),
-        __builtin_fmaf(kMw02, gt[0], __builtin_fmaf(kMw12, gt[1], kMw22 * gt[2])),
-    };
-#pragma unroll
-    for (int c = 0; c < 3; ++c) static_cast<float*>(ds.ptr)[elem_off(ds, p, c)] = in[c] ? dx[c] : 0.0f;
+    for (int c = 0; c < 3; ++c) static_cast<float*>(ds.ptr)[elem_off(ds, p, c)] = dx[c];
   }
 }
 
-// Widen packed bytes to floats with the access pattern of k_u8_hwc (no arithmetic).
+// The same on packed CHW tensors, 4 pixels per lane with 16-byte accesses per plane.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_lab_backward_chw4(const float* __restrict__ xs, const float* __restrict__ gs,
+                                                           float* __restrict__ ds, uint32_t n_px, uint32_t hw,
+                                                           FastDiv div_hw4, KCoef k, KGrad kg) {
+  const uint32_t n4 = n_px >> 2, hw4 = hw >> 2;
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t g4 = blockIdx.x * 256u + threadIdx.x; g4 < n4; g4 += stride) {
+    const uint32_t n = div_hw4.div(g4);
+    const size_t base = (size_t)n * 3 * hw + 4 * (size_t)(g4 - n * hw4);
+    f4 x[3], g[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[c] = *reinterpret_cast<const f4*>(xs + base + (size_t)c * hw);
+      g[c] = *reinterpret_cast<const f4*>(gs + base + (size_t)c * hw);
+    }
+    float o[3][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float raw[3] = {x[0][j], x[1][j], x[2][j]}, gg[3] = {g[0][j], g[1][j], g[2][j]};
+      float dx[3];
+      lab_bwd_px<DEG>(k, kg, raw, gg, dx);
+      o[0][j] = dx[0]; o[1][j] = dx[1]; o[2][j] = dx[2];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      __builtin_nontemporal_store(f4{o[c][0], o[c][1], o[c][2], o[c][3]}, reinterpret_cast<f4*>(ds + base + (size_t)c * hw));
+  }
+}
+
+// Widen packed bytes to floats with the access pattern of k_hwc4<U8> (no arithmetic).
 __global__ __launch_bounds__(kHotBlock) void k_stream_u8_f32(const uint8_t* __restrict__ in, float* __restrict__ out,
                                                              uint32_t n_px) {
   __shared__ f4 s_out[kHotWaves][kChunksPerWave * 192];
@@ -347,15 +433,26 @@ __global__ __launch_bounds__(256) void k_copy16(const f4* __restrict__ in, f4* _
 
 // ---------------------------------------------------------------- dispatch
 
-template <int DEG>
-static void launch_u8_hwc(int xform, const uint8_t* in, float* out, uint32_t n_px, const KCoef& k, int gamma,
-                          hipStream_t st) {
-  const unsigned grid = hot_grid(n_px);
-  const dim3 blk(kHotBlock);
-  if (xform == MACT_LAB) hipLaunchKernelGGL((k_u8_hwc<DEG, MACT_LAB>), dim3(grid), blk, 0, st, in, out, n_px, k, gamma);
-  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_u8_hwc<DEG, MACT_HSI>), dim3(grid), blk, 0, st, in, out, n_px, k, gamma);
-  else hipLaunchKernelGGL((k_u8_hwc<DEG, MACT_SCT>), dim3(grid), blk, 0, st, in, out, n_px, k, gamma);
+template <int IN, int DEG>
+static void launch_hwc4(int xform, const void* in, float* out, uint32_t n_px, const KCoef& k, int gamma,
+                        hipStream_t st) {
+  const dim3 grid(hot_grid(n_px)), blk(kHotBlock);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_hwc4<IN, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_hwc4<IN, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, k, gamma);
+  else hipLaunchKernelGGL((k_hwc4<IN, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, k, gamma);
 }
+
+template <int IN, int DEG>
+static void launch_chw4(int xform, const void* in, float* out, uint32_t n_px, uint32_t hw, const KCoef& k, int gamma,
+                        hipStream_t st) {
+  const dim3 grid(grid_for(n_px / 4, 256, 8)), blk(256);
+  const FastDiv d = make_fastdiv(hw / 4);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_chw4<IN, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_chw4<IN, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else hipLaunchKernelGGL((k_chw4<IN, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+}
+
+static bool aligned(const void* p, size_t a) { return (uintptr_t)p % a == 0; }
 
 }  // namespace mact
 
@@ -374,17 +471,35 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   const int deg = pack_coef(*params, &k);
   const int gamma = params->xform == MACT_LAB ? hi.gamma : MACT_GAMMA_NONE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const bool fast = hi.dtype == MACT_U8 && hi.layout == MACT_HWC && hi.packed && ho.dtype == MACT_F32 &&
-                    ho.layout == MACT_HWC && ho.packed && ((uintptr_t)hi.data % 4 == 0) && ((uintptr_t)ho.data % 16 == 0);
+  // fast shapes: packed 8-bit / float16 HWC -> packed float32 HWC, and packed float32 / float16
+  // CHW -> packed float32 CHW with W H a multiple of 4; everything else takes k_generic
+  const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16) && hi.layout == MACT_HWC && hi.packed &&
+                    ho.dtype == MACT_F32 && ho.layout == MACT_HWC && ho.packed;
+  const bool chw4 = (hi.dtype == MACT_F32 || hi.dtype == MACT_F16) && hi.layout == MACT_CHW && hi.packed &&
+                    ho.dtype == MACT_F32 && ho.layout == MACT_CHW && ho.packed && (hi.W * hi.H) % 4 == 0;
   const int64_t per = images_per_launch(hi);
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
     const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
-    if (fast) {
-      const uint8_t* ip = static_cast<const uint8_t*>(hi.data) + (size_t)(n0 * hi.bs);
-      float* op = static_cast<float*>(ho.data) + (size_t)(n0 * ho.bs);
-      if (deg == 5) launch_u8_hwc<5>(params->xform, ip, op, n_px, k, gamma, st);
-      else launch_u8_hwc<7>(params->xform, ip, op, n_px, k, gamma, st);
+    const void* ip = static_cast<const char*>(hi.data) + (size_t)(n0 * hi.bs) * hi.esize;
+    float* op = static_cast<float*>(ho.data) + (size_t)(n0 * ho.bs);
+    if (hwc4 && aligned(ip, 4) && aligned(op, 16)) {
+      if (hi.dtype == MACT_U8) {
+        if (deg == 5) launch_hwc4<MACT_U8, 5>(params->xform, ip, op, n_px, k, gamma, st);
+        else launch_hwc4<MACT_U8, 7>(params->xform, ip, op, n_px, k, gamma, st);
+      } else {
+        if (deg == 5) launch_hwc4<MACT_F16, 5>(params->xform, ip, op, n_px, k, gamma, st);
+        else launch_hwc4<MACT_F16, 7>(params->xform, ip, op, n_px, k, gamma, st);
+      }
+    } else if (chw4 && aligned(ip, 4 * hi.esize) && aligned(op, 16)) {
+      const uint32_t hw = (uint32_t)(hi.W * hi.H);
+      if (hi.dtype == MACT_F32) {
+        if (deg == 5) launch_chw4<MACT_F32, 5>(params->xform, ip, op, n_px, hw, k, gamma, st);
+        else launch_chw4<MACT_F32, 7>(params->xform, ip, op, n_px, hw, k, gamma, st);
+      } else {
+        if (deg == 5) launch_chw4<MACT_F16, 5>(params->xform, ip, op, n_px, hw, k, gamma, st);
+        else launch_chw4<MACT_F16, 7>(params->xform, ip, op, n_px, hw, k, gamma, st);
+      }
     } else {
       const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
       const unsigned grid = grid_for(n_px, 256, 8);
@@ -422,14 +537,27 @@ extern "C" mact_status mact_transform_backward(const mact_params* params, const 
     kg.dq[j - 1] = (float)(j * (double)k.q[j]);
   }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const bool chw4 = hx.layout == MACT_CHW && hg.layout == MACT_CHW && hd.layout == MACT_CHW && hx.packed && hg.packed &&
+                    hd.packed && (hx.W * hx.H) % 4 == 0;
   const int64_t per = images_per_launch(hx);
   for (int64_t n0 = 0; n0 < hx.N; n0 += per) {
     const int64_t cnt = std::min(per, hx.N - n0);
     const uint32_t n_px = (uint32_t)(cnt * hx.W * hx.H);
-    const KImage kx = kimage(hx, n0, cnt), kgo = kimage(hg, n0, cnt), kd = kimage(hd, n0, cnt);
-    const unsigned grid = grid_for(n_px, 256, 8);
-    if (deg == 5) hipLaunchKernelGGL(k_lab_backward<5>, dim3(grid), dim3(256), 0, st, kx, kgo, kd, n_px, k, kg);
-    else hipLaunchKernelGGL(k_lab_backward<7>, dim3(grid), dim3(256), 0, st, kx, kgo, kd, n_px, k, kg);
+    const float* xp = static_cast<const float*>(hx.data) + (size_t)(n0 * hx.bs);
+    const float* gp = static_cast<const float*>(hg.data) + (size_t)(n0 * hg.bs);
+    float* dp = static_cast<float*>(hd.data) + (size_t)(n0 * hd.bs);
+    const uint32_t hw = (uint32_t)(hx.W * hx.H);
+    if (chw4 && aligned(xp, 16) && aligned(gp, 16) && aligned(dp, 16)) {
+      const dim3 grid(grid_for(n_px / 4, 256, 8));
+      const FastDiv d = make_fastdiv(hw / 4);
+      if (deg == 5) hipLaunchKernelGGL(k_lab_backward_chw4<5>, grid, dim3(256), 0, st, xp, gp, dp, n_px, hw, d, k, kg);
+      else hipLaunchKernelGGL(k_lab_backward_chw4<7>, grid, dim3(256), 0, st, xp, gp, dp, n_px, hw, d, k, kg);
+    } else {
+      const KImage kx = kimage(hx, n0, cnt), kgo = kimage(hg, n0, cnt), kd = kimage(hd, n0, cnt);
+      const unsigned grid = grid_for(n_px, 256, 8);
+      if (deg == 5) hipLaunchKernelGGL(k_lab_backward<5>, dim3(grid), dim3(256), 0, st, kx, kgo, kd, n_px, k, kg);
+      else hipLaunchKernelGGL(k_lab_backward<7>, dim3(grid), dim3(256), 0, st, kx, kgo, kd, n_px, k, kg);
+    }
     if ((s = hip_check(hipGetLastError(), "mact_transform_backward: launch")) != MACT_OK) return s;
   }
   return MACT_OK;
