@@ -162,7 +162,7 @@ static unsigned grid_for(uint64_t work_items, int block, int blocks_per_cu) {
 // Each wave handles kChunksPerWave chunks and the grid covers the image once
 // (no grid-stride loop).  Requires `in` 4-byte and `out` 16-byte aligned;
 // blockDim.x == kHotBlock.
-constexpr int kHotBlock = 512;
+constexpr int kHotBlock = 256;
 constexpr int kChunksPerWave = 2;
 constexpr int kHotWaves = kHotBlock / 64;
 
