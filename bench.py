@@ -116,11 +116,20 @@ def bench_lut(M, x, y, n_px, steps):
         for method in ("trilinear", "prism", "pyramidal", "tetrahedral"):
             ms, _ = time_kernel(lambda: M.lut_interp(L, N, "lab", method, x, out=y), steps)
             out["lab_%s_%d" % (method, N)] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15 * n_px / ms / 1e6, "ms": ms}
+        # the cell-major form: one pixel's corners in one contiguous run
+        C = M.lut_cells_build(L, N, "lab")
+        for method in ("trilinear", "prism", "pyramidal", "tetrahedral"):
+            ms, _ = time_kernel(lambda: M.lut_cells_interp(C, N, "lab", method, x, out=y), steps)
+            out["lab_cells_%s_%d" % (method, N)] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15 * n_px / ms / 1e6, "ms": ms}
+        del C
     for xf in ("hsi", "sct"):
         for N in (17, 33):
             L = M.lut_build(xf, N)
             ms, _ = time_kernel(lambda: M.lut_interp(L, N, xf, "trilinear", x, out=y), steps)
             out["%s_trilinear_%d" % (xf, N)] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15 * n_px / ms / 1e6, "ms": ms}
+            C = M.lut_cells_build(L, N, xf)
+            ms, _ = time_kernel(lambda: M.lut_cells_interp(C, N, xf, "trilinear", x, out=y), steps)
+            out["%s_cells_trilinear_%d" % (xf, N)] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15 * n_px / ms / 1e6, "ms": ms}
     return out
 
 
@@ -269,7 +278,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--forms", default="all", choices=["all", "none"])
+    ap.add_argument("--forms", default="all", choices=["all", "none", "lut"],
+                    help="all: every form; none: the headline and its ceilings only; lut: the headline and the LUTs")
     ap.add_argument("--cpu-px", type=int, default=1 << 25)
     ap.add_argument("--serve-requests", type=int, default=2000)
     a = ap.parse_args()
@@ -317,14 +327,21 @@ def main():
     forms["copy16"] = {"GBs": 2.0 * nb / (cc_ms * 1e-3) / 1e9, "ms": cc_ms, "bytes_each_way": nb}
 
     if a.forms == "all":
+        y16 = torch.empty((N_IMG, H, W, 3), dtype=torch.float16, device="cuda")
+        h_ms, h_med = time_kernel(lambda: M.transform(x, params=p_lab, out=y16), a.steps)
+        forms["lab_f16_out"] = {"Mpx_s": n_px / h_ms / 1e3, "GBs": 9.0 * n_px / h_ms / 1e6, "ms": h_ms,
+                                "ms_median": h_med, "what": "same batch, float16 output: 9 bytes per pixel"}
+        del y16
         log("4K batch")
         forms["lab_32x4k"] = bench_4k(M, p_lab, a.steps)
         for name, xf in (("hsi", 1), ("sct", 2)):
             p = M.default_params(xf)
             ms, _ = time_kernel(lambda: M.transform(x, params=p, out=y), a.steps)
             forms[name] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
+    if a.forms in ("all", "lut"):
         log("LUT interpolators")
         forms["lut"] = bench_lut(M, x, y, n_px, a.steps)
+    if a.forms == "all":
         log("backward")
         forms["differentiation"] = bench_backward(M, a.steps)
         log("batched form")
@@ -360,7 +377,7 @@ def main():
                    "images": N_IMG, "height": H, "width": W, "pixels_per_step": n_px,
                    "max_dE_exhaustive_cube": acc.get("exhaustive_cube_oracle", {}).get("lab", {}).get("max")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_hwc4<U8,5,LAB>",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_hwc4<U8,F32,5,LAB>",
                      "kernel_ms": k_ms, "kernel_ms_median": k_med, "algorithmic_bytes_per_px": 15,
                      "pixels_per_launch": n_px},
         "cpu_baseline": cpu,

@@ -228,6 +228,30 @@ mact_status lut_build(int32_t xform, int32_t n, int32_t gamma, float* dev_lut, s
 mact_status lut_interp(const float* dev_lut, int32_t n, int32_t xform, int32_t method,
                        const mact_image* in, const mact_image* out, void* hip_stream);
 
+/* Cell-major form of an N^3 LUT, the counterpart of the caching LUTs of
+   Sec. 3.5.3 (which store neighbour information in every node to save
+   per-pixel work): (N-1)^3 cells, cell (i, j, k) at index (i (N-1) + j) (N-1)
+   + k, each holding its 8 corner nodes in the order dR dG dB = 000, 001, 010,
+   011, 100, 101, 110, 111, nodes as in lut_bytes.  One pixel's corners are then
+   one contiguous 128-byte run (256 for SCT) rather than four runs N and N^2
+   nodes apart.  Returns the bytes, 0 for invalid arguments. */
+size_t lut_cells_bytes(int32_t xform, int32_t n);
+
+/* Fills `dev_cells` (caller-owned device buffer, >= lut_cells_bytes bytes,
+   16-byte aligned) with the cell-major form of the packed LUT `dev_lut` (as
+   lut_build writes it, on the device, 16-byte aligned); node values are copied
+   bit for bit.  Asynchronous on `hip_stream`.
+   Errors: MACT_E_INVALID (NULL, misaligned, n outside 2..256, short buffer). */
+mact_status lut_cells_build(const float* dev_lut, int32_t n, int32_t xform, float* dev_cells, size_t bytes,
+                            void* hip_stream);
+
+/* lut_interp on the cell-major form: the same extraction, methods, weights and
+   summation order, hence bitwise the same outputs; the cells are always read
+   through the L2 (they are 8x the packed grid's bytes).  Arguments and errors
+   as lut_interp. */
+mact_status lut_cells_interp(const float* dev_cells, int32_t n, int32_t xform, int32_t method,
+                             const mact_image* in, const mact_image* out, void* hip_stream);
+
 /* ------------------------------------------------------------ batched form */
 
 /* Launch shape picked by the autotuner (or given by the caller). */

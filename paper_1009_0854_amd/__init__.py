@@ -191,6 +191,36 @@ def lut_interp(lut, n, xform, method, x, layout="hwc", out=None, out_layout=None
     return out
 
 
+def lut_cells_bytes(xform, n):
+    return int(lib().lut_cells_bytes(_xf(xform), int(n)))
+
+
+def lut_cells_build(lut, n, xform, stream=None):
+    """Cell-major form (lut_cells_build) of a packed LUT from lut_build, as a
+    float32 device tensor on the LUT's device."""
+    torch = _torch()
+    nbytes = lut_cells_bytes(xform, n)
+    if nbytes == 0:
+        raise MactError(A.E_INVALID, "lut_cells_bytes: invalid xform/n")
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device=lut.device)
+    A.check(lib().lut_cells_build(ctypes.c_void_p(lut.data_ptr()), int(n), _xf(xform),
+                                  ctypes.c_void_p(buf.data_ptr()), nbytes, _stream(stream)))
+    return buf
+
+
+def lut_cells_interp(cells, n, xform, method, x, layout="hwc", out=None, out_layout=None, out_dtype=None,
+                     stream=None):
+    torch = _torch()
+    out_layout = layout if out_layout is None else out_layout
+    if out is None:
+        out = _out_like(x, layout, out_layout, out_dtype or torch.float32)
+    m = A.METHODS[method] if isinstance(method, str) else int(method)
+    A.check(lib().lut_cells_interp(ctypes.c_void_p(cells.data_ptr()), int(n), _xf(xform), m,
+                                   ctypes.byref(image(x, layout, "none")), ctypes.byref(image(out, out_layout)),
+                                   _stream(stream)))
+    return out
+
+
 # ---------------------------------------------------------------- batched form
 
 def _arrays(params, ins, outs, layouts=None, gammas=None, out_layouts=None):

@@ -84,6 +84,9 @@ SIGNATURES = {
     "lut_bytes": (c_size_t, [c_int32, c_int32]),
     "lut_build": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
     "lut_interp": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(Image), POINTER(Image), c_void_p]),
+    "lut_cells_bytes": (c_size_t, [c_int32, c_int32]),
+    "lut_cells_build": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
+    "lut_cells_interp": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(Image), POINTER(Image), c_void_p]),
     "mact_batch_plan_create": (c_int32, [POINTER(Params), POINTER(Image), POINTER(Image), c_int32, POINTER(Tune),
                                          c_void_p, POINTER(c_void_p)]),
     "mact_batch_plan_launch": (c_int32, [c_void_p, c_int32, c_void_p]),

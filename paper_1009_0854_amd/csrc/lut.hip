@@ -13,8 +13,18 @@
 // the L2.  Packed 8-bit HWC -> float32 HWC takes k_lut4 (the transform's
 // 12-byte loads and LDS-transposed 1 KB stores); other shapes take k_lut, one
 // pixel per lane.  Each method is a weighted sum of its 8, 6, 5 or 4 corners.
+//
+// Cell-major form: (N-1)^3 cells, each holding its 8 corner nodes in one
+// contiguous run (128 bytes; 256 for SCT), so that one pixel's corners are
+// one cache line instead of four lines N and N^2 nodes apart.  It plays the
+// part of the paper's caching LUTs, which store neighbour information in every
+// node to save per-pixel work; here what the stored neighbours save is memory
+// transactions.  Corner ids (dR dG dB as bits 2, 1, 0) stand in for the node
+// strides, so both forms sum the same values in the same order and give the
+// same bits.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -125,15 +135,16 @@ struct Corners<MACT_PYRAMIDAL> {
   }
 };
 
-// One pixel: the method's weighted corner sum at cell i, fractions f.
-template <int METHOD, int XF>
+// One pixel: the method's weighted corner sum at cell i, fractions f.  CELL:
+// `nodes` is the cell-major form.
+template <int METHOD, int XF, bool CELL>
 __device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, uint32_t N, const uint32_t i[3], const float f[3],
                                        float o[3]) {
   const int NF = XF == MACT_SCT ? 2 : 1;  // float4 per node
-  const uint32_t base = (i[0] * N + i[1]) * N + i[2];
+  const uint32_t base = CELL ? ((i[0] * (N - 1) + i[1]) * (N - 1) + i[2]) * 8u : (i[0] * N + i[1]) * N + i[2];
   uint32_t off[8];
   float w[8];
-  Corners<METHOD>::get(f[0], f[1], f[2], N * N, N, off, w);
+  Corners<METHOD>::get(f[0], f[1], f[2], CELL ? 4u : N * N, CELL ? 2u : N, off, w);
   f4 a0 = {0.0f, 0.0f, 0.0f, 0.0f};
   float a1 = 0.0f;
 #pragma unroll
@@ -159,7 +170,7 @@ __device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, uint32_t N,
   }
 }
 
-template <int METHOD, int XF>
+template <int METHOD, int XF, bool CELL>
 __device__ __forceinline__ void lut_px_u8(const f4* __restrict__ nodes, uint32_t N, uint32_t r, uint32_t g, uint32_t b,
                                           float o[3]) {
   uint32_t i[3];
@@ -167,11 +178,12 @@ __device__ __forceinline__ void lut_px_u8(const f4* __restrict__ nodes, uint32_t
   locate_u8(r, N, i[0], f[0]);
   locate_u8(g, N, i[1], f[1]);
   locate_u8(b, N, i[2], f[2]);
-  lut_px<METHOD, XF>(nodes, N, i, f, o);
+  lut_px<METHOD, XF, CELL>(nodes, N, i, f, o);
 }
 
-// Any element type, layout and stride: one pixel per lane step.
-template <int METHOD, int XF, bool LDS>
+// Any element type, layout and stride: one pixel per lane step.  LDS and
+// CELL are exclusive.
+template <int METHOD, int XF, bool LDS, bool CELL>
 __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32_t N, KImage src, KImage dst,
                                               uint32_t n_px) {
   extern __shared__ f4 s_lut[];
@@ -195,7 +207,7 @@ __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32
       if (u8) locate_u8((uint32_t)v[c], N, i[c], f[c]);
       else locate_f(v[c], N, i[c], f[c]);
     }
-    lut_px<METHOD, XF>(nodes, N, i, f, o);
+    lut_px<METHOD, XF, CELL>(nodes, N, i, f, o);
     store_px(dst, p, o);
   }
 }
@@ -205,7 +217,7 @@ __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32
 // a staged LUT is worth keeping), each lane reads its 4 pixels with one
 // 12-byte load, and the results leave through the wave's LDS slice as 1 KB
 // contiguous stores.  LDS holds the LUT (when LDS) followed by 3 KB per wave.
-template <int METHOD, int XF, bool LDS>
+template <int METHOD, int XF, bool LDS, bool CELL>
 __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint32_t N, const uint8_t* __restrict__ in,
                                                float* __restrict__ out, uint32_t n_px) {
   extern __shared__ f4 smem[];
@@ -226,7 +238,7 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
     float o[12];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      lut_px_u8<METHOD, XF>(nodes, N, byte_of(w, 3 * j), byte_of(w, 3 * j + 1), byte_of(w, 3 * j + 2), o + 3 * j);
+      lut_px_u8<METHOD, XF, CELL>(nodes, N, byte_of(w, 3 * j), byte_of(w, 3 * j + 1), byte_of(w, 3 * j + 2), o + 3 * j);
     __builtin_amdgcn_wave_barrier();
     s[3 * lane] = f4{o[0], o[1], o[2], o[3]};
     s[3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
@@ -244,11 +256,24 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
   if (blockIdx.x == 0)
     for (uint32_t p = tail0 + threadIdx.x; p < n_px; p += blockDim.x) {
       float o[3];
-      lut_px_u8<METHOD, XF>(nodes, N, in[3 * (size_t)p], in[3 * (size_t)p + 1], in[3 * (size_t)p + 2], o);
+      lut_px_u8<METHOD, XF, CELL>(nodes, N, in[3 * (size_t)p], in[3 * (size_t)p + 1], in[3 * (size_t)p + 2], o);
       out[3 * (size_t)p] = o[0];
       out[3 * (size_t)p + 1] = o[1];
       out[3 * (size_t)p + 2] = o[2];
     }
+}
+
+// Cell-major form from the packed grid: element t of the output is float4 q
+// of corner c of cell (i, j, k), t = ((cell 8) + c) NF + q.  A plain copy.
+__global__ __launch_bounds__(256) void k_lut_cells(const f4* __restrict__ nodes, uint32_t N, uint32_t NF,
+                                                   f4* __restrict__ cells, uint32_t n_elems) {
+  const uint32_t M = N - 1;
+  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n_elems; t += gridDim.x * 256u) {
+    const uint32_t q = t % NF, c = (t / NF) & 7u, cell = t / (8u * NF);
+    const uint32_t k = cell % M, j = (cell / M) % M, i = cell / (M * M);
+    const uint32_t node = ((i + (c >> 2)) * N + (j + ((c >> 1) & 1u))) * N + (k + (c & 1u));
+    cells[t] = nodes[node * NF + q];
+  }
 }
 
 // ---------------------------------------------------------------- host
@@ -271,8 +296,9 @@ static hipError_t allow_lds(K k, size_t bytes) {
 
 // Launch shapes.  LDS-staged grid: 1024-thread workgroups, one or two per CU
 // (as many copies of the grid as the CU's LDS holds), grid-stride.  Grid
-// gathered through the L2: 256-thread workgroups, eight per CU.
-template <int METHOD, int XF>
+// gathered through the L2 (and every cell-major grid): 256-thread
+// workgroups, eight per CU.
+template <int METHOD, int XF, bool CELL>
 static hipError_t launch_lut(const f4* lut, uint32_t N, const HostImage& hi, const HostImage& ho, int64_t n0,
                              int64_t cnt, uint32_t n_px, hipStream_t st) {
   const size_t bytes = (size_t)N * N * N * node_floats(XF) * sizeof(float);
@@ -284,8 +310,8 @@ static hipError_t launch_lut(const f4* lut, uint32_t N, const HostImage& hi, con
   const size_t t_lds = 16 * 192 * sizeof(f4);  // k_lut4 with 1024 threads: 16 waves x 3 KB
   // a grid that fits LDS alone but not beside k_lut4's transpose buffers (17^3 SCT) is
   // still worth staging: k_lut below
-  if (fast && (bytes + t_lds <= lds_max || bytes > lds_max)) {
-    const bool lds = bytes + t_lds <= lds_max;
+  if (fast && (CELL || bytes + t_lds <= lds_max || bytes > lds_max)) {
+    const bool lds = !CELL && bytes + t_lds <= lds_max;
     const unsigned block = lds ? 1024 : 256;
     const size_t shm = (lds ? bytes : 0) + (size_t)(block / 64) * 192 * sizeof(f4);
     const uint64_t chunks = std::max<uint64_t>(1, n_px >> 8);
@@ -294,42 +320,76 @@ static hipError_t launch_lut(const f4* lut, uint32_t N, const HostImage& hi, con
                                                                              (uint64_t)device_cus() * per_cu));
     const uint8_t* in8 = static_cast<const uint8_t*>(ip);
     if (lds) {
-      auto k = k_lut4<METHOD, XF, true>;
+      auto k = k_lut4<METHOD, XF, true, false>;
       hipError_t e = allow_lds(k, shm);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, lut, N, in8, op, n_px);
     } else {
-      auto k = k_lut4<METHOD, XF, false>;
+      auto k = k_lut4<METHOD, XF, false, CELL>;
       hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, lut, N, in8, op, n_px);
     }
     return hipGetLastError();
   }
   const KImage s = kimage(hi, n0, cnt), d = kimage(ho, n0, cnt);
-  const bool lds = bytes <= lds_max;
+  const bool lds = !CELL && bytes <= lds_max;
   const unsigned block = lds ? 1024 : 256;
   const uint64_t need = (n_px + block - 1) / block;
   const uint64_t per_cu = lds ? std::max<uint64_t>(1, std::min<uint64_t>(2, lds_max / bytes)) : 8;
   const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(need, (uint64_t)device_cus() * per_cu));
   if (lds) {
-    auto k = k_lut<METHOD, XF, true>;
+    auto k = k_lut<METHOD, XF, true, false>;
     hipError_t e = allow_lds(k, bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(grid), dim3(block), bytes, st, lut, N, s, d, n_px);
   } else {
-    hipLaunchKernelGGL((k_lut<METHOD, XF, false>), dim3(grid), dim3(block), 0, st, lut, N, s, d, n_px);
+    hipLaunchKernelGGL((k_lut<METHOD, XF, false, CELL>), dim3(grid), dim3(block), 0, st, lut, N, s, d, n_px);
   }
   return hipGetLastError();
 }
 
-template <int XF>
+template <int XF, bool CELL>
 static hipError_t launch_lut_m(int method, const f4* lut, uint32_t N, const HostImage& hi, const HostImage& ho,
                                int64_t n0, int64_t cnt, uint32_t n_px, hipStream_t st) {
   switch (method) {
-    case MACT_TRILINEAR: return launch_lut<MACT_TRILINEAR, XF>(lut, N, hi, ho, n0, cnt, n_px, st);
-    case MACT_PRISM: return launch_lut<MACT_PRISM, XF>(lut, N, hi, ho, n0, cnt, n_px, st);
-    case MACT_PYRAMIDAL: return launch_lut<MACT_PYRAMIDAL, XF>(lut, N, hi, ho, n0, cnt, n_px, st);
-    default: return launch_lut<MACT_TETRAHEDRAL, XF>(lut, N, hi, ho, n0, cnt, n_px, st);
+    case MACT_TRILINEAR: return launch_lut<MACT_TRILINEAR, XF, CELL>(lut, N, hi, ho, n0, cnt, n_px, st);
+    case MACT_PRISM: return launch_lut<MACT_PRISM, XF, CELL>(lut, N, hi, ho, n0, cnt, n_px, st);
+    case MACT_PYRAMIDAL: return launch_lut<MACT_PYRAMIDAL, XF, CELL>(lut, N, hi, ho, n0, cnt, n_px, st);
+    default: return launch_lut<MACT_TETRAHEDRAL, XF, CELL>(lut, N, hi, ho, n0, cnt, n_px, st);
   }
+}
+
+// lut_interp and lut_cells_interp: validation, then one launch per run of
+// images of fewer than 2^31 pixels.
+template <bool CELL>
+static mact_status interp_common(const char* what, const float* dev_lut, int32_t n, int32_t xform, int32_t method,
+                                 const mact_image* in, const mact_image* out, void* hip_stream) {
+  if (!dev_lut) return fail(MACT_E_INVALID, "%s: LUT pointer is NULL", what);
+  if (xform < MACT_LAB || xform > MACT_SCT || n < 2 || n > 256)
+    return fail(MACT_E_INVALID, "%s: transform %d / size %d invalid", what, xform, n);
+  if (method < MACT_TRILINEAR || method > MACT_TETRAHEDRAL) return fail(MACT_E_INVALID, "%s: method %d", what, method);
+  if ((uintptr_t)dev_lut % 16) return fail(MACT_E_INVALID, "%s: LUT not 16-byte aligned", what);
+  HostImage hi, ho;
+  mact_status s;
+  char nm[64];
+  std::snprintf(nm, sizeof nm, "%s: in", what);
+  if ((s = resolve_image(in, false, nm, &hi)) != MACT_OK) return s;
+  std::snprintf(nm, sizeof nm, "%s: out", what);
+  if ((s = resolve_image(out, true, nm, &ho)) != MACT_OK) return s;
+  if ((s = check_same_shape(hi, ho, nm)) != MACT_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const f4* lut = reinterpret_cast<const f4*>(dev_lut);
+  const int64_t per = images_per_launch(hi);
+  for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
+    const int64_t cnt = std::min(per, hi.N - n0);
+    const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
+    hipError_t e;
+    if (xform == MACT_LAB) e = launch_lut_m<MACT_LAB, CELL>(method, lut, n, hi, ho, n0, cnt, n_px, st);
+    else if (xform == MACT_HSI) e = launch_lut_m<MACT_HSI, CELL>(method, lut, n, hi, ho, n0, cnt, n_px, st);
+    else e = launch_lut_m<MACT_SCT, CELL>(method, lut, n, hi, ho, n0, cnt, n_px, st);
+    std::snprintf(nm, sizeof nm, "%s: launch", what);
+    if ((s = hip_check(e, nm)) != MACT_OK) return s;
+  }
+  return MACT_OK;
 }
 
 }  // namespace mact
@@ -379,26 +439,34 @@ extern "C" mact_status lut_build(int32_t xform, int32_t n, int32_t gamma, float*
 extern "C" mact_status lut_interp(const float* dev_lut, int32_t n, int32_t xform, int32_t method, const mact_image* in,
                                   const mact_image* out, void* hip_stream) {
   clear_error();
-  if (!dev_lut) return fail(MACT_E_INVALID, "lut_interp: dev_lut is NULL");
-  if (lut_bytes(xform, n) == 0) return fail(MACT_E_INVALID, "lut_interp: transform %d / size %d invalid", xform, n);
-  if (method < MACT_TRILINEAR || method > MACT_TETRAHEDRAL) return fail(MACT_E_INVALID, "lut_interp: method %d", method);
-  if ((uintptr_t)dev_lut % 16) return fail(MACT_E_INVALID, "lut_interp: dev_lut not 16-byte aligned");
-  HostImage hi, ho;
-  mact_status s;
-  if ((s = resolve_image(in, false, "lut_interp: in", &hi)) != MACT_OK) return s;
-  if ((s = resolve_image(out, true, "lut_interp: out", &ho)) != MACT_OK) return s;
-  if ((s = check_same_shape(hi, ho, "lut_interp: out")) != MACT_OK) return s;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const f4* lut = reinterpret_cast<const f4*>(dev_lut);
-  const int64_t per = images_per_launch(hi);
-  for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
-    const int64_t cnt = std::min(per, hi.N - n0);
-    const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
-    hipError_t e;
-    if (xform == MACT_LAB) e = launch_lut_m<MACT_LAB>(method, lut, n, hi, ho, n0, cnt, n_px, st);
-    else if (xform == MACT_HSI) e = launch_lut_m<MACT_HSI>(method, lut, n, hi, ho, n0, cnt, n_px, st);
-    else e = launch_lut_m<MACT_SCT>(method, lut, n, hi, ho, n0, cnt, n_px, st);
-    if ((s = hip_check(e, "lut_interp: launch")) != MACT_OK) return s;
-  }
-  return MACT_OK;
+  return interp_common<false>("lut_interp", dev_lut, n, xform, method, in, out, hip_stream);
+}
+
+extern "C" size_t lut_cells_bytes(int32_t xform, int32_t n) {
+  if (xform < MACT_LAB || xform > MACT_SCT || n < 2 || n > 256) return 0;
+  const size_t m = (size_t)(n - 1);
+  return m * m * m * 8 * node_floats(xform) * sizeof(float);
+}
+
+extern "C" mact_status lut_cells_build(const float* dev_lut, int32_t n, int32_t xform, float* dev_cells, size_t bytes,
+                                       void* hip_stream) {
+  clear_error();
+  const size_t need = lut_cells_bytes(xform, n);
+  if (need == 0) return fail(MACT_E_INVALID, "lut_cells_build: transform %d / size %d invalid (n in 2..256)", xform, n);
+  if (!dev_lut || !dev_cells) return fail(MACT_E_INVALID, "lut_cells_build: NULL LUT pointer");
+  if ((uintptr_t)dev_lut % 16 || (uintptr_t)dev_cells % 16)
+    return fail(MACT_E_INVALID, "lut_cells_build: LUT pointers must be 16-byte aligned");
+  if (bytes < need) return fail(MACT_E_INVALID, "lut_cells_build: %zu bytes < %zu needed", bytes, need);
+  const uint32_t nf4 = (uint32_t)(node_floats(xform) / 4);
+  const uint32_t n_elems = (uint32_t)(need / sizeof(f4));
+  const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n_elems + 255) / 256, (uint64_t)device_cus() * 8));
+  hipLaunchKernelGGL(k_lut_cells, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
+                     reinterpret_cast<const f4*>(dev_lut), (uint32_t)n, nf4, reinterpret_cast<f4*>(dev_cells), n_elems);
+  return hip_check(hipGetLastError(), "lut_cells_build: launch");
+}
+
+extern "C" mact_status lut_cells_interp(const float* dev_cells, int32_t n, int32_t xform, int32_t method,
+                                        const mact_image* in, const mact_image* out, void* hip_stream) {
+  clear_error();
+  return interp_common<true>("lut_cells_interp", dev_cells, n, xform, method, in, out, hip_stream);
 }

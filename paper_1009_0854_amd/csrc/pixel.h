@@ -201,11 +201,21 @@ __device__ __forceinline__ void load_px(const KImage& im, uint32_t p, float v[3]
   }
 }
 
+// float32 -> float16 of the float32 value, rounded to nearest even.  The
+// empty asm pins x as a float32 register value: without it the compiler may
+// fuse the conversion with the fma that produced x into one mixed-precision
+// instruction, which rounds the exact product-sum once, straight to float16,
+// and can differ in the last bit.
+__device__ __forceinline__ __half f2h_rn(float x) {
+  asm volatile("" : "+v"(x));
+  return __float2half_rn(x);
+}
+
 __device__ __forceinline__ void store_px(const KImage& im, uint32_t p, const float o3[3]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const int64_t o = elem_off(im, p, c);
-    if (im.dtype == MACT_F16) static_cast<__half*>(im.ptr)[o] = __float2half_rn(o3[c]);
+    if (im.dtype == MACT_F16) static_cast<__half*>(im.ptr)[o] = f2h_rn(o3[c]);
     else static_cast<float*>(im.ptr)[o] = o3[c];
   }
 }

@@ -1,14 +1,14 @@
 // Plain per-pixel MACT transforms (Sec. 3.2-3.4), the backward pass of the
 // CIELAB transform, and the reference streaming kernels.
 //
-// Two kernel shapes:
+// Three kernel shapes:
 //  * k_hwc4: the hot path, packed 8-bit (or float16) HWC in and packed
-//    float32 HWC out, staged through LDS so that every global store is a
-//    contiguous 1 KB per wave (details at the kernel).
+//    float32 (or float16) HWC out, staged through LDS so that every global
+//    store is a contiguous run of 1 KB per wave (details at the kernel).
 //  * k_chw4: packed float32 / float16 CHW, 4 pixels per lane, vector access
 //    per plane.
 //  * k_generic: any element type, layout and stride, one pixel per lane step.
-// Both call the same per-pixel functions (pixel.h), so they give identical bits.
+// All call the same per-pixel functions (pixel.h), so they give identical bits.
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -20,6 +20,7 @@ namespace mact {
 #include "gamma_table.inc"
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------- host helpers
 
@@ -149,15 +150,17 @@ static unsigned grid_for(uint64_t work_items, int block, int blocks_per_cu) {
 
 // ---------------------------------------------------------------- kernels
 
-// Packed HWC (8-bit or float16) -> packed float32 HWC: the hot path.
+// Packed HWC (8-bit or float16) -> packed HWC float32 (or float16): the hot
+// path.
 //
 // A wave owns chunks of 256 pixels (768 input bytes for 8-bit input, 1536
-// for float16; 3 KB of output).  Each lane loads its 4 pixels (one 12-byte
-// load, or two for float16) -- the wave's loads cover one contiguous run --
-// and computes them.  The 48 bytes of results go to the wave's slice of LDS,
-// and the wave then writes the chunk back as 16-byte stores in which lane l
+// for float16; 3 KB of float32 output, 1.5 KB of float16).  Each lane loads
+// its 4 pixels (one 12-byte load, or two for float16) -- the wave's loads
+// cover one contiguous run -- and computes them.  The 48 bytes of results
+// (24 for float16, rounded to nearest even) go to the wave's slice of LDS,
+// and the wave then writes its chunks back as 16-byte stores in which lane l
 // writes bytes 16 l .. 16 l + 15 of each KB: every store instruction covers
-// 1 KB of contiguous output.  Writing the 48 bytes straight from the lane (a
+// 1 KB of contiguous output.  Writing the results straight from the lane (a
 // 48-byte stride across the wave) runs at about a third of this bandwidth.
 // Each wave handles kChunksPerWave chunks and the grid covers the image once
 // (no grid-stride loop).  Requires `in` 4-byte and `out` 16-byte aligned;
@@ -166,10 +169,11 @@ constexpr int kHotBlock = 256;
 constexpr int kChunksPerWave = 2;
 constexpr int kHotWaves = kHotBlock / 64;
 
-template <int IN, int DEG, int XF>
-__global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in, float* __restrict__ out,
+template <int IN, int OUT, int DEG, int XF>
+__global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in, void* __restrict__ out,
                                                      uint32_t n_px, KCoef k, int gamma) {
-  constexpr int WPC = IN == MACT_U8 ? 1 : 2;  // 12-byte words per lane per chunk
+  constexpr int WPC = IN == MACT_U8 ? 1 : 2;      // 12-byte words per lane per chunk
+  constexpr uint32_t F4PC = OUT == MACT_F32 ? 192 : 96;  // 16-byte output words per chunk
   __shared__ f4 s_out[kHotWaves][kChunksPerWave * 192];
   __shared__ float gtab[256];
   if (IN == MACT_U8 && XF == MACT_LAB) {
@@ -193,18 +197,31 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
       float o[12];
       if (IN == MACT_U8) px4_u8<XF, DEG>(k, gtab, w[j][0], o);
       else px4_f16<XF, DEG>(k, gamma, w[j][0], w[j][WPC - 1], o);
-      s_out[wv][j * 192 + 3 * lane] = f4{o[0], o[1], o[2], o[3]};
-      s_out[wv][j * 192 + 3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
-      s_out[wv][j * 192 + 3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+      if (OUT == MACT_F32) {
+        s_out[wv][j * 192 + 3 * lane] = f4{o[0], o[1], o[2], o[3]};
+        s_out[wv][j * 192 + 3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
+        s_out[wv][j * 192 + 3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+      } else {
+        // 12 halves = three 8-byte words; chunk j starts at 8-byte word 192 j
+        f2* s2 = reinterpret_cast<f2*>(&s_out[wv][0]);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const uint32_t lo = (uint32_t)__half_as_ushort(f2h_rn(o[4 * t])) |
+                              ((uint32_t)__half_as_ushort(f2h_rn(o[4 * t + 1])) << 16);
+          const uint32_t hi = (uint32_t)__half_as_ushort(f2h_rn(o[4 * t + 2])) |
+                              ((uint32_t)__half_as_ushort(f2h_rn(o[4 * t + 3])) << 16);
+          s2[j * 192 + 3 * lane + t] = f2{__uint_as_float(lo), __uint_as_float(hi)};
+        }
+      }
     }
     // the LDS writes of every lane must land before any lane reads them back
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
     __builtin_amdgcn_wave_barrier();
-    const uint32_t n_valid = min((uint32_t)kChunksPerWave, n_chunks - c0) * 192u;
-    f4* dst = reinterpret_cast<f4*>(out) + (size_t)c0 * 192;
+    const uint32_t n_valid = min((uint32_t)kChunksPerWave, n_chunks - c0) * F4PC;
+    f4* dst = reinterpret_cast<f4*>(out) + (size_t)c0 * F4PC;
 #pragma unroll
-    for (int q = 0; q < 3 * kChunksPerWave; ++q) {
+    for (int q = 0; q < (int)(kChunksPerWave * F4PC / 64); ++q) {
       const uint32_t e = q * 64 + lane;
       if (e < n_valid) __builtin_nontemporal_store(s_out[wv][e], dst + e);
     }
@@ -228,9 +245,11 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
       else if (XF == MACT_HSI) hsi_px<DEG>(k, r, g, b, kInv3, o);
       else sct_px<DEG>(k, r, g, b, 1.0f, o);
     }
-    out[3 * p] = o[0];
-    out[3 * p + 1] = o[1];
-    out[3 * p + 2] = o[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (OUT == MACT_F32) static_cast<float*>(out)[3 * p + c] = o[c];
+      else static_cast<__half*>(out)[3 * p + c] = f2h_rn(o[c]);
+    }
   }
 }
 
@@ -433,13 +452,25 @@ __global__ __launch_bounds__(256) void k_copy16(const f4* __restrict__ in, f4* _
 
 // ---------------------------------------------------------------- dispatch
 
-template <int IN, int DEG>
-static void launch_hwc4(int xform, const void* in, float* out, uint32_t n_px, const KCoef& k, int gamma,
+template <int IN, int OUT, int DEG>
+static void launch_hwc4(int xform, const void* in, void* out, uint32_t n_px, const KCoef& k, int gamma,
                         hipStream_t st) {
   const dim3 grid(hot_grid(n_px)), blk(kHotBlock);
-  if (xform == MACT_LAB) hipLaunchKernelGGL((k_hwc4<IN, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, k, gamma);
-  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_hwc4<IN, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, k, gamma);
-  else hipLaunchKernelGGL((k_hwc4<IN, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, k, gamma);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_hwc4<IN, OUT, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_hwc4<IN, OUT, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, k, gamma);
+  else hipLaunchKernelGGL((k_hwc4<IN, OUT, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, k, gamma);
+}
+
+template <int IN>
+static void launch_hwc4_io(int xform, int out_dtype, int deg, const void* in, void* out, uint32_t n_px,
+                           const KCoef& k, int gamma, hipStream_t st) {
+  if (out_dtype == MACT_F32) {
+    if (deg == 5) launch_hwc4<IN, MACT_F32, 5>(xform, in, out, n_px, k, gamma, st);
+    else launch_hwc4<IN, MACT_F32, 7>(xform, in, out, n_px, k, gamma, st);
+  } else {
+    if (deg == 5) launch_hwc4<IN, MACT_F16, 5>(xform, in, out, n_px, k, gamma, st);
+    else launch_hwc4<IN, MACT_F16, 7>(xform, in, out, n_px, k, gamma, st);
+  }
 }
 
 template <int IN, int DEG>
@@ -471,10 +502,10 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   const int deg = pack_coef(*params, &k);
   const int gamma = params->xform == MACT_LAB ? hi.gamma : MACT_GAMMA_NONE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  // fast shapes: packed 8-bit / float16 HWC -> packed float32 HWC, and packed float32 / float16
-  // CHW -> packed float32 CHW with W H a multiple of 4; everything else takes k_generic
+  // fast shapes: packed 8-bit / float16 HWC -> packed float32 / float16 HWC, and packed float32 /
+  // float16 CHW -> packed float32 CHW with W H a multiple of 4; everything else takes k_generic
   const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16) && hi.layout == MACT_HWC && hi.packed &&
-                    ho.dtype == MACT_F32 && ho.layout == MACT_HWC && ho.packed;
+                    (ho.dtype == MACT_F32 || ho.dtype == MACT_F16) && ho.layout == MACT_HWC && ho.packed;
   const bool chw4 = (hi.dtype == MACT_F32 || hi.dtype == MACT_F16) && hi.layout == MACT_CHW && hi.packed &&
                     ho.dtype == MACT_F32 && ho.layout == MACT_CHW && ho.packed && (hi.W * hi.H) % 4 == 0;
   const int64_t per = images_per_launch(hi);
@@ -482,23 +513,18 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
     const int64_t cnt = std::min(per, hi.N - n0);
     const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
     const void* ip = static_cast<const char*>(hi.data) + (size_t)(n0 * hi.bs) * hi.esize;
-    float* op = static_cast<float*>(ho.data) + (size_t)(n0 * ho.bs);
+    void* op = static_cast<char*>(ho.data) + (size_t)(n0 * ho.bs) * ho.esize;
     if (hwc4 && aligned(ip, 4) && aligned(op, 16)) {
-      if (hi.dtype == MACT_U8) {
-        if (deg == 5) launch_hwc4<MACT_U8, 5>(params->xform, ip, op, n_px, k, gamma, st);
-        else launch_hwc4<MACT_U8, 7>(params->xform, ip, op, n_px, k, gamma, st);
-      } else {
-        if (deg == 5) launch_hwc4<MACT_F16, 5>(params->xform, ip, op, n_px, k, gamma, st);
-        else launch_hwc4<MACT_F16, 7>(params->xform, ip, op, n_px, k, gamma, st);
-      }
+      if (hi.dtype == MACT_U8) launch_hwc4_io<MACT_U8>(params->xform, ho.dtype, deg, ip, op, n_px, k, gamma, st);
+      else launch_hwc4_io<MACT_F16>(params->xform, ho.dtype, deg, ip, op, n_px, k, gamma, st);
     } else if (chw4 && aligned(ip, 4 * hi.esize) && aligned(op, 16)) {
       const uint32_t hw = (uint32_t)(hi.W * hi.H);
       if (hi.dtype == MACT_F32) {
-        if (deg == 5) launch_chw4<MACT_F32, 5>(params->xform, ip, op, n_px, hw, k, gamma, st);
-        else launch_chw4<MACT_F32, 7>(params->xform, ip, op, n_px, hw, k, gamma, st);
+        if (deg == 5) launch_chw4<MACT_F32, 5>(params->xform, ip, static_cast<float*>(op), n_px, hw, k, gamma, st);
+        else launch_chw4<MACT_F32, 7>(params->xform, ip, static_cast<float*>(op), n_px, hw, k, gamma, st);
       } else {
-        if (deg == 5) launch_chw4<MACT_F16, 5>(params->xform, ip, op, n_px, hw, k, gamma, st);
-        else launch_chw4<MACT_F16, 7>(params->xform, ip, op, n_px, hw, k, gamma, st);
+        if (deg == 5) launch_chw4<MACT_F16, 5>(params->xform, ip, static_cast<float*>(op), n_px, hw, k, gamma, st);
+        else launch_chw4<MACT_F16, 7>(params->xform, ip, static_cast<float*>(op), n_px, hw, k, gamma, st);
       }
     } else {
       const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);

@@ -203,6 +203,19 @@ def test_lut_validation_without_gpu(M):
     assert L.lut_interp(ctypes.c_void_p(0x1000), 17, 0, 7, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
     assert L.lut_interp(ctypes.c_void_p(0x1004), 17, 0, 0, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
     assert L.lut_interp(None, 17, 0, 0, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
+    # cell-major form: (N-1)^3 cells of 8 nodes
+    assert L.lut_cells_bytes(0, 17) == 16 ** 3 * 8 * 16
+    assert L.lut_cells_bytes(2, 33) == 32 ** 3 * 8 * 32
+    assert L.lut_cells_bytes(0, 2) == 8 * 16
+    assert L.lut_cells_bytes(0, 1) == 0 and L.lut_cells_bytes(3, 17) == 0 and L.lut_cells_bytes(1, 257) == 0
+    need = L.lut_cells_bytes(0, 17)
+    assert L.lut_cells_build(ctypes.c_void_p(0x1000), 17, 0, ctypes.c_void_p(0x2000), need - 1, None) == A.E_INVALID
+    assert L.lut_cells_build(None, 17, 0, ctypes.c_void_p(0x2000), need, None) == A.E_INVALID
+    assert L.lut_cells_build(ctypes.c_void_p(0x1000), 17, 0, ctypes.c_void_p(0x2008), need, None) == A.E_INVALID
+    assert L.lut_cells_build(ctypes.c_void_p(0x1000), 300, 0, ctypes.c_void_p(0x2000), need, None) == A.E_INVALID
+    assert L.lut_cells_interp(ctypes.c_void_p(0x1000), 17, 0, 9, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
+    assert L.lut_cells_interp(ctypes.c_void_p(0x1008), 17, 0, 0, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
+    assert L.lut_cells_interp(None, 17, 0, 0, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
 
 
 def test_batch_and_server_validation_without_gpu(M):

@@ -126,3 +126,54 @@ def test_lut_33_goes_through_l2_and_17_sct_through_lds(M):
         gpu, _ = _interp(M, xform, N, "tetrahedral", img)
         ref, rlen = OL.interp(OL.build(xform, N), xform, "tetrahedral", v8=img)
         _compare(xform, gpu, ref, rlen)
+
+
+@pytest.mark.parametrize("N", [2, 9, 17, 33])
+@pytest.mark.parametrize("xform", ["lab", "hsi", "sct"])
+def test_cells_hold_the_corner_nodes(M, xform, N):
+    # cell (i, j, k), corner (dR dG dB): the packed node (i + dR, j + dG, k + dB), bit for bit
+    L = M.lut_build(xform, N)
+    C = M.lut_cells_build(L, N, xform)
+    torch.cuda.synchronize()
+    nf = M.lut_bytes(xform, N) // 4 // N ** 3
+    nodes = L.view(N, N, N, nf)
+    cells = C.view(N - 1, N - 1, N - 1, 8, nf)
+    for c in range(8):
+        dr, dg, db = c >> 2, (c >> 1) & 1, c & 1
+        ref = nodes[dr:dr + N - 1, dg:dg + N - 1, db:db + N - 1]
+        assert torch.equal(cells[:, :, :, c], ref), c
+
+
+@pytest.mark.parametrize("N", [17, 33])
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("xform", ["lab", "hsi", "sct"])
+def test_cells_interp_equals_packed(M, xform, method, N):
+    # the cell-major form gives the packed form's bits: packed 8-bit HWC fast path (ragged
+    # tail included), the general kernel through a strided view, and float CHW input
+    g = torch.Generator(device="cuda").manual_seed(N + 3)
+    x = torch.randint(0, 256, (3, 67, 331, 3), dtype=torch.uint8, device="cuda", generator=g)
+    L = M.lut_build(xform, N)
+    C = M.lut_cells_build(L, N, xform)
+    a = M.lut_interp(L, N, xform, method, x)
+    b = M.lut_cells_interp(C, N, xform, method, x)
+    big = torch.zeros((3, 67, 334, 3), dtype=torch.uint8, device="cuda")
+    big[:, :, :331] = x
+    c = M.lut_cells_interp(C, N, xform, method, big[:, :, :331])
+    xf = (torch.rand((2, 3, 33, 47), device="cuda", generator=g) * 1.1 - 0.05)
+    d1 = M.lut_interp(L, N, xform, method, xf, layout="chw")
+    d2 = M.lut_cells_interp(C, N, xform, method, xf, layout="chw")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c) and torch.equal(d1, d2)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_cells_u8_parity_33(M, method):
+    # against the oracle directly, including the corner colours
+    img = synth.uniform_u8(129, 131, seed=5)
+    img.reshape(-1, 3)[:6] = [[0, 0, 0], [255, 255, 255], [128, 128, 128], [255, 0, 0], [0, 0, 255], [17, 17, 200]]
+    L = M.lut_build("lab", 33)
+    C = M.lut_cells_build(L, 33, "lab")
+    y = M.lut_cells_interp(C, 33, "lab", method, torch.from_numpy(img).cuda())
+    torch.cuda.synchronize()
+    ref, rlen = OL.interp(OL.build("lab", 33), "lab", method, v8=img)
+    _compare("lab", y.cpu().numpy().astype(np.float64), ref, rlen)

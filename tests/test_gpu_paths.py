@@ -65,6 +65,28 @@ def test_hwc_fast_equals_general(M, xform, dtype, shape):
         assert err.max() <= P.REL
 
 
+@pytest.mark.parametrize("shape", SHAPES + [(33, 31)])
+@pytest.mark.parametrize("dtype", ["u8", "f16"])
+@pytest.mark.parametrize("xform", [0, 1, 2])
+def test_hwc_f16_output_fast_equals_general(M, xform, dtype, shape):
+    # float16 output: the fast kernel rounds in the same place as the general one
+    g = torch.Generator(device="cuda").manual_seed(7 * sum(shape) + xform)
+    if dtype == "u8":
+        x = torch.randint(0, 256, (3,) + shape + (3,), dtype=torch.uint8, device="cuda", generator=g)
+        gm = "bt709" if xform == 0 else "none"
+    else:
+        x = (torch.rand((3,) + shape + (3,), device="cuda", generator=g) * 1.1 - 0.05).half()
+        gm = "none"
+    p = M.default_params(xform)
+    fast = M.transform(x, params=p, gamma=gm, out_dtype=torch.float16)
+    general = _padded_hwc(torch.zeros(x.shape, dtype=torch.float16, device="cuda"))
+    M.transform(x, params=p, gamma=gm, out=general)
+    f32 = M.transform(x, params=p, gamma=gm)
+    torch.cuda.synchronize()
+    assert torch.equal(fast, general)
+    assert torch.equal(fast, f32.half())  # round to nearest even of the float32 result
+
+
 @pytest.mark.parametrize("hw", [(4, 1), (16, 24), (64, 64), (129, 20)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
 @pytest.mark.parametrize("xform", [0, 1, 2])

@@ -109,6 +109,18 @@ def test_float_inputs_layouts_and_clamp(M, xform):
 
 
 @pytest.mark.parametrize("xform", [0, 1, 2], ids=["lab", "hsi", "sct"])
+def test_u8_input_f16_output(M, xform):
+    # C1 through the float16-output form of the hot kernel (9 bytes per pixel moved):
+    # the oracle value rounded to float16 within one half-unit of the float16 result
+    img = synth.uniform_u8(512, 512, seed=1)
+    p = M.default_params(xform)
+    gpu16 = _run(M, img, xform, p, out_dtype=torch.float16).astype(np.float64)
+    ref = P.oracle(xform, img.reshape(-1, 3) / 255.0, P.coeffs(p)).reshape(gpu16.shape)
+    tol = np.abs(ref) * 2.0 ** -11 + 2e-6 * np.asarray(P.SCALE[xform]) + 2.0 ** -25
+    assert np.all(np.abs(gpu16 - ref) <= tol)
+
+
+@pytest.mark.parametrize("xform", [0, 1, 2], ids=["lab", "hsi", "sct"])
 def test_f16_input_and_f16_output(M, xform):
     g = synth.rng(22)
     xh = g.random((40, 50, 3)).astype(np.float16)
@@ -166,3 +178,46 @@ def test_batch_of_1080p_sampled(M):
         gv = y.reshape(-1, 3)[torch.from_numpy(idx).cuda()].cpu().numpy()
         P.assert_parity(xform, gv, P.oracle(xform, flat / 255.0, P.coeffs(p)))
         del y
+
+
+def _sample_check(M, x, y, xform, p, n_sample, seed):
+    """Sampled pixels of a device batch against the oracle."""
+    n = x.numel() // 3
+    idx = torch.from_numpy(synth.rng(seed).integers(0, n, n_sample)).cuda()
+    xs = x.reshape(-1, 3)[idx].cpu().numpy()
+    gv = y.reshape(-1, 3)[idx].cpu().numpy()
+    P.assert_parity(xform, gv, P.oracle(xform, xs / 255.0, P.coeffs(p)))
+
+
+def test_batch_of_4k_sampled(M):
+    # 32 x 3840 x 2160 uint8 (i.i.d. uniform bytes from a seeded device generator), in the
+    # launch shape the benchmark's 4K form times; 200,000 sampled pixels per transform
+    g = torch.Generator(device="cuda").manual_seed(7)
+    x = torch.randint(0, 256, (32, 2160, 3840, 3), dtype=torch.uint8, device="cuda", generator=g)
+    y = torch.empty((32, 2160, 3840, 3), dtype=torch.float32, device="cuda")
+    for xform in (0, 1, 2):
+        p = M.default_params(xform)
+        M.transform(x, xform=xform, params=p, out=y)
+        torch.cuda.synchronize()
+        _sample_check(M, x, y, xform, p, 200000, 40 + xform)
+    del x, y
+    torch.cuda.empty_cache()
+
+
+def test_batch_spanning_two_launches(M):
+    # 2 x 32768 x 32768 = 2^31 pixels: one launch covers fewer than 2^31 pixels, so the batch
+    # goes out as two launches; pixels on both sides of the split and at both ends are checked
+    g = torch.Generator(device="cuda").manual_seed(11)
+    x = torch.randint(0, 256, (2, 32768, 32768, 3), dtype=torch.uint8, device="cuda", generator=g)
+    y = torch.empty((2, 32768, 32768, 3), dtype=torch.float32, device="cuda")
+    p = M.default_params(0)
+    M.transform(x, params=p, out=y)
+    torch.cuda.synchronize()
+    _sample_check(M, x, y, 0, p, 100000, 50)
+    n1 = 32768 * 32768
+    edge = torch.tensor([0, 1, n1 - 2, n1 - 1, n1, n1 + 1, 2 * n1 - 1], device="cuda")
+    xs = x.reshape(-1, 3)[edge].cpu().numpy()
+    gv = y.reshape(-1, 3)[edge].cpu().numpy()
+    P.assert_parity(0, gv, P.oracle(0, xs / 255.0, P.coeffs(p)))
+    del x, y
+    torch.cuda.empty_cache()
