@@ -225,31 +225,43 @@ def bench_serve(M, n_req=2000, pool=16):
     import torch
     reqs = _requests(n_req, 6, pool)
     px = sum(r[1].shape[0] * r[1].shape[1] for r in reqs)
-    # served: a submitter thread follows the arrival times; a slot is reused only after its
-    # previous request completed
+    # served: the submitter follows the arrival times; a pinned slot is reused only after its
+    # previous request completed.  The first 400 requests of the stream (0.2 s) run once untimed
+    # on the same server (steady state), then the whole stream is timed.
     srv = M.Server(arena_bytes=8 << 30, max_batch=64, compute_streams=2, max_queue=1 << 20)
-    ids = [None] * n_req
-    lag = [0.0] * n_req
-    t0 = time.perf_counter()
-    for i, (ta, x, y, xf, gm) in enumerate(reqs):
-        if i >= pool:
-            srv.wait(ids[i - pool], 120000)
-        now = time.perf_counter() - t0
-        if ta > now:
-            time.sleep(ta - now)
-        lag[i] = (time.perf_counter() - t0 - ta) * 1e3  # arrival -> submit
-        ids[i] = srv.submit(x, y, xf, gm)
-    for i in ids:
-        srv.wait(i, 120000)
-    wall = time.perf_counter() - t0
+
+    def run(rs):
+        ids = [None] * len(rs)
+        lag = [0.0] * len(rs)
+        t0 = time.perf_counter()
+        for i, (ta, x, y, xf, gm) in enumerate(rs):
+            if i >= pool:
+                srv.wait(ids[i - pool], 120000)
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            lag[i] = (time.perf_counter() - t0 - ta) * 1e3  # arrival -> submit
+            ids[i] = srv.submit(x, y, xf, gm)
+        for i in ids:
+            srv.wait(i, 120000)
+        wall = time.perf_counter() - t0
+        lib = np.array([srv.latency_ms(i) for i in ids])
+        return np.array(lag), lib, wall
+
+    run(reqs[:400])
+    st0 = srv.stats()
+    lag, lib, wall = run(reqs)
     st = srv.stats()
-    lat = np.sort(np.array([lag[k] + srv.latency_ms(ids[k]) for k in range(n_req)]))
-    served = {"requests": n_req, "Mpx_s": px / wall / 1e6, "p50_ms": float(np.percentile(lat, 50)),
-              "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
-              "p50_ms_from_submit": st.p50_ms, "p99_ms_from_submit": st.p99_ms,
-              "batches": st.batches, "mean_batch": st.mean_batch, "compute_streams": 2,
-              "device_busy_ms": st.device_busy_ms, "wall_s": wall, "offered_req_s": 2000.0}
     srv.close()
+    lat = lag + lib
+    nb = st.batches - st0.batches
+    served = {"requests": n_req, "Mpx_s": px / wall / 1e6, "p50_ms": float(np.percentile(lat, 50)),
+              "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()), "mean_ms": float(lat.mean()),
+              "p50_ms_from_submit": float(np.percentile(lib, 50)), "p99_ms_from_submit": float(np.percentile(lib, 99)),
+              "p99_arrival_to_submit_ms": float(np.percentile(lag, 99)),
+              "batches": nb, "mean_batch": n_req / max(1, nb), "compute_streams": 2,
+              "device_busy_ms": st.device_busy_ms - st0.device_busy_ms, "wall_s": wall, "offered_req_s": 2000.0,
+              "warmup_requests": 400}
     # plain per-request path: one stream, copy in, transform, copy out, synchronise, in arrival order
     lat = []
     s = torch.cuda.Stream()
@@ -377,7 +389,7 @@ def main():
                    "images": N_IMG, "height": H, "width": W, "pixels_per_step": n_px,
                    "max_dE_exhaustive_cube": acc.get("exhaustive_cube_oracle", {}).get("lab", {}).get("max")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_hwc4<U8,F32,5,LAB>",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_hwc4<U8,F32,4,LAB>",
                      "kernel_ms": k_ms, "kernel_ms_median": k_med, "algorithmic_bytes_per_px": 15,
                      "pixels_per_launch": n_px},
         "cpu_baseline": cpu,

@@ -292,13 +292,23 @@ mact_status mact_batch_run(const mact_params* params, const mact_image* in, cons
 /* ------------------------------------------------------------ serving */
 
 /* A continuous-batching engine on the current device.  Requests carry host
-   (pinned) input and output buffers.  A scheduler thread admits a request when
-   its device bytes fit in the engine's arena (size-class free lists carved from
-   one allocation), copies it in on a copy stream, and groups every request
-   whose input has arrived into one persistent batched launch on the next of
-   `compute_streams` streams; batches overlap on the device, and requests that
-   arrive while batches are in flight join the next one.  Outputs are copied back
-   and the request completes.  Coefficients stay resident in the engine. */
+   (pinned) input and output buffers.  A scheduler thread admits a request, in
+   arrival order, when its device bytes fit in the engine's arena (a first-fit
+   free list over one allocation, 256-byte granules), copies it in on a copy
+   stream, and groups every request whose input has arrived into one persistent
+   batched launch on the next free of `compute_streams` streams; batches overlap
+   on the device, and requests that arrive while batches are in flight join the
+   next one.  Outputs go back on one device-to-host stream, smallest first
+   within a batch, and each request completes when its own output has landed.
+   Coefficients stay resident in the engine.  The scheduler makes every HIP call
+   after creation, without holding the locks that submit / poll / wait take, so
+   those never wait on device work.
+
+   mact_server_create allocates the arena and per-stream buffers, clears the
+   arena once and runs one small request through every stream (so that first-use
+   costs fall on creation, not on the first requests), then starts the
+   scheduler.  Errors: MACT_E_INVALID (config out of range), MACT_E_NOMEM,
+   MACT_E_DEVICE. */
 typedef struct mact_server_config {
   size_t arena_bytes;      /* device memory for request inputs and outputs */
   int32_t max_batch;       /* most requests in one launch */

@@ -46,7 +46,8 @@ __global__ __launch_bounds__(1024) void k_batch(const BDesc* __restrict__ descs,
       else hi = mid - 1;
     }
     const BDesc& d = descs[lo];
-    const KCoef& k = coefs[d.coef];
+    KCoef k = coefs[d.coef];
+    pin_lead<DEG>(k);
     const uint32_t p0 = (t - tile_start[lo]) * tile;
     const uint32_t p1 = min(p0 + tile, d.n_px);
     const float* g = gtab[d.gamma];

@@ -32,8 +32,9 @@ KImage kimage(const HostImage& h, int64_t n0, int64_t count);
 int64_t images_per_launch(const HostImage& h);
 
 // Coefficients rounded to float32 and zero padded; returns the padded degree
-// (5 or 7) the kernels are instantiated for.
-int pack_coef(const mact_params& p, KCoef* k);
+// (5 or 7) the kernels are instantiated for, and the highest degree actually
+// used in *exact (the hot kernel also has a degree-4 instance).
+int pack_coef(const mact_params& p, KCoef* k, int* exact = nullptr);
 
 // One image of a batched launch (device-side descriptor).
 struct BDesc {

@@ -63,6 +63,17 @@ struct KImage {
 
 // ---------------------------------------------------------------- polynomial
 
+// Moves the leading coefficient of every polynomial into a vector register,
+// once per kernel.  A vector instruction may read one scalar register, so the
+// first Horner step, fma(c[DEG], x, c[DEG-1]), would otherwise need a copy at
+// every evaluation.  Values are unchanged.
+template <int DEG>
+__device__ __forceinline__ void pin_lead(KCoef& k) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(k.p[i][DEG]));
+  asm volatile("" : "+v"(k.q[DEG]));
+}
+
 template <int DEG>
 __device__ __forceinline__ float horner(const float* c, float x) {
   float acc = c[DEG];

@@ -22,6 +22,15 @@
 //      completes, and returns its arena space, when its own output copy has
 //      landed (an event per request), not when its whole batch has.
 // The coefficient table of the three transforms stays resident.
+//
+// Locking: the scheduler owns the request pipeline and makes its HIP calls
+// without holding any lock that callers take.  Callers meet it at three small
+// locks: `mu_in` (incoming requests and the id map), `mu_done` (completion
+// wake-ups; a request's done flag is atomic) and `mu_stats` (counters).  A
+// submit, poll or wait therefore never waits behind a run of HIP calls.
+// Events come from a pool owned by the scheduler, and creation warms every
+// stream and the batched kernel with one tiny request, so that the first real
+// requests pay no one-time costs.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -93,8 +102,8 @@ struct Req {
   mact_request r{};
   size_t in_bytes = 0, out_bytes = 0, in_off = 0, out_off = 0;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  Clock::time_point t_submit, t_done;
-  bool done = false;
+  Clock::time_point t_submit, t_done;  // t_done is written before done is set
+  std::atomic<bool> done{false};
 };
 
 struct Slot {
@@ -124,29 +133,59 @@ struct mact_server {
   hipStream_t d2h_stream = nullptr;   // device -> host, in launch order
   std::vector<Slot> slots;
 
-  std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  // shared with callers
+  std::mutex mu_in;  // incoming, all, next_id, submitted, rejected, stop
+  std::condition_variable cv_work;
+  std::deque<Req*> incoming;
+  std::unordered_map<int64_t, std::unique_ptr<Req>> all;
+  int64_t next_id = 1, submitted = 0, rejected = 0;
+  bool stop = false;
+  std::atomic<int64_t> waiting{0};  // submitted, not yet admitted to the arena
+  std::mutex mu_done;
+  std::condition_variable cv_done;
+  std::mutex mu_stats;  // lat_ms, completed, batches, batched_reqs, busy_ms
+  std::vector<double> lat_ms;
+  int64_t completed = 0, batches = 0, batched_reqs = 0;
+  double busy_ms = 0.0;
+
+  // the scheduler's own
   std::deque<Req*> queued;   // submitted, not admitted
   std::vector<Req*> copying;  // input copy in flight
   std::vector<Req*> ready;    // input on the device, not yet in a batch
   std::vector<Req*> draining;  // output copy in flight
-  std::unordered_map<int64_t, std::unique_ptr<Req>> all;
-  std::vector<double> lat_ms;
-  int64_t next_id = 1, submitted = 0, completed = 0, rejected = 0, batches = 0, batched_reqs = 0;
-  double busy_ms = 0.0;
-  bool stop = false;
+  std::vector<hipEvent_t> ev_pool;
   std::thread th;
-  mact_status thread_status = MACT_OK;
 
   void loop();
-  bool admit_locked();
-  void poll_copies_locked();
-  bool launch_locked(Slot& s);
-  bool finish_slots_locked();
-  bool finish_requests_locked();
+  hipEvent_t get_event();
+  bool take_incoming();
+  bool admit();
+  void poll_copies();
+  bool launch(Slot& s);
+  bool finish_slots();
+  bool finish_requests();
 };
 
-bool mact_server::admit_locked() {
+hipEvent_t mact_server::get_event() {
+  if (!ev_pool.empty()) {
+    hipEvent_t e = ev_pool.back();
+    ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+  return e;
+}
+
+bool mact_server::take_incoming() {
+  std::lock_guard<std::mutex> g(mu_in);
+  if (incoming.empty()) return false;
+  queued.insert(queued.end(), incoming.begin(), incoming.end());
+  incoming.clear();
+  return true;
+}
+
+bool mact_server::admit() {
   bool any = false;
   while (!queued.empty()) {
     Req* q = queued.front();
@@ -157,10 +196,11 @@ bool mact_server::admit_locked() {
       break;
     }
     queued.pop_front();
+    waiting.fetch_sub(1);
     q->in_off = in_off;
     q->out_off = out_off;
-    (void)hipEventCreateWithFlags(&q->ev_in, hipEventDisableTiming);
-    (void)hipEventCreateWithFlags(&q->ev_out, hipEventDisableTiming);
+    q->ev_in = get_event();
+    q->ev_out = get_event();
     (void)hipMemcpyAsync(d_arena + in_off, q->r.host_in, q->in_bytes, hipMemcpyHostToDevice, copy_stream);
     (void)hipEventRecord(q->ev_in, copy_stream);
     copying.push_back(q);
@@ -169,7 +209,7 @@ bool mact_server::admit_locked() {
   return any;
 }
 
-void mact_server::poll_copies_locked() {
+void mact_server::poll_copies() {
   // copies complete in admission order (one copy stream): stop at the first pending one
   size_t i = 0;
   while (i < copying.size() && hipEventQuery(copying[i]->ev_in) == hipSuccess) ++i;
@@ -177,7 +217,7 @@ void mact_server::poll_copies_locked() {
   copying.erase(copying.begin(), copying.begin() + i);
 }
 
-bool mact_server::launch_locked(Slot& s) {
+bool mact_server::launch(Slot& s) {
   if (ready.empty()) return false;
   const size_t n = std::min<size_t>(ready.size(), (size_t)cfg.max_batch);
   s.reqs.assign(ready.begin(), ready.begin() + n);  // admission order is arrival order
@@ -221,17 +261,21 @@ bool mact_server::launch_locked(Slot& s) {
   }
   s.busy = true;
   s.t_launch = Clock::now();
+  std::lock_guard<std::mutex> g(mu_stats);
   ++batches;
   batched_reqs += (int64_t)n;
   return true;
 }
 
-bool mact_server::finish_slots_locked() {
+bool mact_server::finish_slots() {
   bool any = false;
   for (Slot& s : slots) {
     if (!s.busy || hipEventQuery(s.ev_k1) != hipSuccess) continue;
     float kms = 0.0f;
-    if (hipEventElapsedTime(&kms, s.ev_k0, s.ev_k1) == hipSuccess) busy_ms += kms;
+    if (hipEventElapsedTime(&kms, s.ev_k0, s.ev_k1) == hipSuccess) {
+      std::lock_guard<std::mutex> g(mu_stats);
+      busy_ms += kms;
+    }
     s.reqs.clear();
     s.busy = false;
     any = true;
@@ -239,8 +283,8 @@ bool mact_server::finish_slots_locked() {
   return any;
 }
 
-bool mact_server::finish_requests_locked() {
-  bool any = false;
+bool mact_server::finish_requests() {
+  std::vector<double> lat;
   const auto now = Clock::now();
   for (size_t i = 0; i < draining.size();) {
     Req* q = draining[i];
@@ -248,52 +292,62 @@ bool mact_server::finish_requests_locked() {
       ++i;
       continue;
     }
-    q->t_done = now;
-    q->done = true;
     arena->release(q->in_off, q->in_bytes);
     arena->release(q->out_off, q->out_bytes);
-    (void)hipEventDestroy(q->ev_in);
-    (void)hipEventDestroy(q->ev_out);
+    ev_pool.push_back(q->ev_in);
+    ev_pool.push_back(q->ev_out);
     q->ev_in = q->ev_out = nullptr;
-    lat_ms.push_back(std::chrono::duration<double, std::milli>(q->t_done - q->t_submit).count());
-    ++completed;
+    q->t_done = now;
+    lat.push_back(std::chrono::duration<double, std::milli>(q->t_done - q->t_submit).count());
+    {
+      std::lock_guard<std::mutex> g(mu_done);  // a waiter checks done under this lock
+      q->done.store(true);
+    }
     draining[i] = draining.back();
     draining.pop_back();
-    any = true;
   }
-  return any;
+  if (lat.empty()) return false;
+  {
+    std::lock_guard<std::mutex> g(mu_stats);
+    lat_ms.insert(lat_ms.end(), lat.begin(), lat.end());
+    completed += (int64_t)lat.size();
+  }
+  cv_done.notify_all();
+  return true;
 }
 
 void mact_server::loop() {
   (void)hipSetDevice(device);
-  std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     bool progress = false;
-    progress |= finish_requests_locked();
-    progress |= finish_slots_locked();
-    progress |= admit_locked();
-    poll_copies_locked();
+    progress |= finish_requests();
+    progress |= finish_slots();
+    progress |= take_incoming();
+    progress |= admit();
+    poll_copies();
     for (Slot& s : slots)
-      if (!s.busy) progress |= launch_locked(s);
-    if (progress) cv_done.notify_all();
+      if (!s.busy) progress |= launch(s);
     const bool in_flight = !copying.empty() || !draining.empty() ||
                            std::any_of(slots.begin(), slots.end(), [](const Slot& s) { return s.busy; });
-    if (stop && queued.empty() && copying.empty() && ready.empty() && !in_flight) break;
     if (progress) continue;
     if (in_flight || !ready.empty()) {
       // device work outstanding: poll its events again shortly
-      lk.unlock();
       std::this_thread::sleep_for(std::chrono::microseconds(5));
-      lk.lock();
-    } else {
-      cv_work.wait_for(lk, std::chrono::milliseconds(50));
+      continue;
     }
+    std::unique_lock<std::mutex> lk(mu_in);
+    if (stop && incoming.empty() && queued.empty()) break;
+    if (incoming.empty() && queued.empty()) cv_work.wait_for(lk, std::chrono::milliseconds(50));
   }
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  ev_pool.clear();
   cv_done.notify_all();
 }
 
 static void server_free(mact_server* s) {
   if (!s) return;
+  for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
+  s->ev_pool.clear();
   for (Slot& sl : s->slots) {
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
     if (sl.ev_k0) (void)hipEventDestroy(sl.ev_k0);
@@ -306,6 +360,68 @@ static void server_free(mact_server* s) {
   if (s->d_arena) (void)hipFree(s->d_arena);
   if (s->d_coefs) (void)hipFree(s->d_coefs);
   delete s;
+}
+
+// The arena cleared once, one 16 x 16 8-bit CIELAB request through the copy
+// stream, every slot and the output stream, synchronously, and a stock of
+// events: first-use costs (page set-up, queue set-up, kernel loading, event
+// creation) are paid here rather than by the first requests.
+static mact_status warm_up(mact_server* s) {
+  const int64_t w = 16, h = 16;
+  const size_t in_b = (size_t)(w * h * 3), out_off = 4096, out_b = (size_t)(w * h * 12);
+  char* hs = nullptr;
+  if (hipHostMalloc((void**)&hs, out_b) != hipSuccess) return fail(MACT_E_NOMEM, "mact_server_create: warm-up buffer");
+  std::memset(hs, 0, out_b);
+  // touch the whole arena once, so that no request is the first to reach its pages
+  mact_status st = hip_check(hipMemsetAsync(s->d_arena, 0, s->cfg.arena_bytes, s->copy_stream),
+                             "mact_server_create: arena clear");
+  if (st == MACT_OK)
+    st = hip_check(hipMemcpyAsync(s->d_arena, hs, in_b, hipMemcpyHostToDevice, s->copy_stream),
+                   "mact_server_create: warm-up copy");
+  if (st == MACT_OK) st = hip_check(hipStreamSynchronize(s->copy_stream), "mact_server_create: warm-up copy");
+  for (Slot& sl : s->slots) {
+    if (st != MACT_OK) break;
+    mact_image in{}, out{};
+    in.data = s->d_arena;
+    in.dtype = MACT_U8;
+    in.layout = MACT_HWC;
+    in.width = w;
+    in.height = h;
+    in.gamma = MACT_GAMMA_BT709;
+    out.data = s->d_arena + out_off;
+    out.dtype = MACT_F32;
+    out.layout = MACT_HWC;
+    out.width = w;
+    out.height = h;
+    std::vector<BDesc> descs;
+    int d = 5;
+    st = make_batch_descs(s->cfg.params[MACT_LAB], &in, &out, MACT_LAB, &descs, &d, "mact_server_create");
+    if (st != MACT_OK) break;
+    std::vector<uint32_t> ts;
+    const uint32_t total = build_tiles(descs, (uint32_t)s->tune.tile, &ts);
+    const size_t db = descs.size() * sizeof(BDesc), tb = ts.size() * sizeof(uint32_t);
+    std::memcpy(sl.h_buf, descs.data(), db);
+    std::memcpy(sl.h_buf + db, ts.data(), tb);
+    st = hip_check(hipMemcpyAsync(sl.d_buf, sl.h_buf, db + tb, hipMemcpyHostToDevice, sl.stream), "mact_server_create: warm-up");
+    if (st == MACT_OK)
+      st = hip_check(launch_batch_kernel(reinterpret_cast<const BDesc*>(sl.d_buf), s->d_coefs,
+                                         reinterpret_cast<const uint32_t*>(sl.d_buf + db), (int32_t)descs.size(), total,
+                                         s->tune, s->deg, sl.stream),
+                     "mact_server_create: warm-up launch");
+    if (st == MACT_OK) st = hip_check(hipStreamSynchronize(sl.stream), "mact_server_create: warm-up");
+  }
+  if (st == MACT_OK)
+    st = hip_check(hipMemcpyAsync(hs, s->d_arena + out_off, out_b, hipMemcpyDeviceToHost, s->d2h_stream),
+                   "mact_server_create: warm-up copy");
+  if (st == MACT_OK) st = hip_check(hipStreamSynchronize(s->d2h_stream), "mact_server_create: warm-up copy");
+  (void)hipHostFree(hs);
+  const int n_ev = 2 * std::min(s->cfg.max_batch, 256) * (int)s->slots.size();
+  for (int i = 0; i < n_ev && st == MACT_OK; ++i) {
+    hipEvent_t e = nullptr;
+    st = hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "mact_server_create: event");
+    if (st == MACT_OK) s->ev_pool.push_back(e);
+  }
+  return st;
 }
 
 extern "C" mact_status mact_server_create(const mact_server_config* cfg, mact_server** srv) {
@@ -351,6 +467,7 @@ extern "C" mact_status mact_server_create(const mact_server_config* cfg, mact_se
                           hipHostMalloc((void**)&sl.h_buf, sl.buf_bytes) != hipSuccess))
       st = fail(MACT_E_NOMEM, "mact_server_create: slot buffers");
   }
+  if (st == MACT_OK) st = warm_up(s);
   if (st != MACT_OK) {
     server_free(s);
     return st;
@@ -375,44 +492,53 @@ extern "C" mact_status mact_server_submit(mact_server* s, const mact_request* r,
   const size_t in_b = px * 3 * esize(r->in_dtype), out_b = px * 3 * esize(r->out_dtype);
   const size_t need = (in_b + kGranule - 1) / kGranule * kGranule + (out_b + kGranule - 1) / kGranule * kGranule;
   if (need > s->cfg.arena_bytes) return fail(MACT_E_INVALID, "mact_server_submit: request needs %zu bytes, arena has %zu", need, s->cfg.arena_bytes);
-  std::lock_guard<std::mutex> g(s->mu);
-  if (s->stop) return fail(MACT_E_INVALID, "mact_server_submit: server is stopping");
-  if ((int64_t)s->queued.size() >= s->cfg.max_queue) {
-    ++s->rejected;
-    return fail(MACT_E_BUSY, "mact_server_submit: %d requests already waiting", s->cfg.max_queue);
-  }
-  std::unique_ptr<Req> q(new Req());
-  q->id = s->next_id++;
+  std::unique_ptr<Req> q(new (std::nothrow) Req());
+  if (!q) return fail(MACT_E_NOMEM, "mact_server_submit: host allocation");
   q->r = *r;
   q->in_bytes = in_b;
   q->out_bytes = out_b;
-  q->t_submit = Clock::now();
-  *id = q->id;
-  s->queued.push_back(q.get());
-  s->all[q->id] = std::move(q);
-  ++s->submitted;
+  {
+    std::lock_guard<std::mutex> g(s->mu_in);
+    if (s->stop) return fail(MACT_E_INVALID, "mact_server_submit: server is stopping");
+    if (s->waiting.load() >= s->cfg.max_queue) {
+      ++s->rejected;
+      return fail(MACT_E_BUSY, "mact_server_submit: %d requests already waiting", s->cfg.max_queue);
+    }
+    q->id = s->next_id++;
+    q->t_submit = Clock::now();
+    *id = q->id;
+    s->incoming.push_back(q.get());
+    s->all[q->id] = std::move(q);
+    ++s->submitted;
+    s->waiting.fetch_add(1);
+  }
   s->cv_work.notify_one();
   return MACT_OK;
+}
+
+// The request with handle `id`, or null.  Requests live until the server is destroyed.
+static Req* find_req(mact_server* s, int64_t id) {
+  std::lock_guard<std::mutex> g(s->mu_in);
+  auto it = s->all.find(id);
+  return it == s->all.end() ? nullptr : it->second.get();
 }
 
 extern "C" mact_status mact_server_poll(mact_server* s, int64_t id, int32_t* done) {
   clear_error();
   if (!s || !done) return fail(MACT_E_INVALID, "mact_server_poll: NULL argument");
-  std::lock_guard<std::mutex> g(s->mu);
-  auto it = s->all.find(id);
-  if (it == s->all.end()) return fail(MACT_E_INVALID, "mact_server_poll: unknown request %lld", (long long)id);
-  *done = it->second->done ? 1 : 0;
+  Req* q = find_req(s, id);
+  if (!q) return fail(MACT_E_INVALID, "mact_server_poll: unknown request %lld", (long long)id);
+  *done = q->done.load() ? 1 : 0;
   return MACT_OK;
 }
 
 extern "C" mact_status mact_server_wait(mact_server* s, int64_t id, int32_t timeout_ms) {
   clear_error();
   if (!s) return fail(MACT_E_INVALID, "mact_server_wait: NULL server");
-  std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->all.find(id);
-  if (it == s->all.end()) return fail(MACT_E_INVALID, "mact_server_wait: unknown request %lld", (long long)id);
-  Req* q = it->second.get();
-  if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), [q] { return q->done; }))
+  Req* q = find_req(s, id);
+  if (!q) return fail(MACT_E_INVALID, "mact_server_wait: unknown request %lld", (long long)id);
+  std::unique_lock<std::mutex> lk(s->mu_done);
+  if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), [q] { return q->done.load(); }))
     return fail(MACT_E_BUSY, "mact_server_wait: request %lld not done after %d ms", (long long)id, timeout_ms);
   return MACT_OK;
 }
@@ -420,22 +546,24 @@ extern "C" mact_status mact_server_wait(mact_server* s, int64_t id, int32_t time
 extern "C" mact_status mact_server_latency(mact_server* s, int64_t id, double* ms) {
   clear_error();
   if (!s || !ms) return fail(MACT_E_INVALID, "mact_server_latency: NULL argument");
-  std::lock_guard<std::mutex> g(s->mu);
-  auto it = s->all.find(id);
-  if (it == s->all.end()) return fail(MACT_E_INVALID, "mact_server_latency: unknown request %lld", (long long)id);
-  if (!it->second->done) return fail(MACT_E_BUSY, "mact_server_latency: request %lld not done", (long long)id);
-  *ms = std::chrono::duration<double, std::milli>(it->second->t_done - it->second->t_submit).count();
+  Req* q = find_req(s, id);
+  if (!q) return fail(MACT_E_INVALID, "mact_server_latency: unknown request %lld", (long long)id);
+  if (!q->done.load()) return fail(MACT_E_BUSY, "mact_server_latency: request %lld not done", (long long)id);
+  *ms = std::chrono::duration<double, std::milli>(q->t_done - q->t_submit).count();
   return MACT_OK;
 }
 
 extern "C" mact_status mact_server_stats_get(mact_server* s, mact_server_stats* st) {
   clear_error();
   if (!s || !st) return fail(MACT_E_INVALID, "mact_server_stats_get: NULL argument");
-  std::lock_guard<std::mutex> g(s->mu);
   std::memset(st, 0, sizeof *st);
-  st->submitted = s->submitted;
+  {
+    std::lock_guard<std::mutex> g(s->mu_in);
+    st->submitted = s->submitted;
+    st->rejected = s->rejected;
+  }
+  std::lock_guard<std::mutex> g(s->mu_stats);
   st->completed = s->completed;
-  st->rejected = s->rejected;
   st->batches = s->batches;
   st->mean_batch = s->batches ? (double)s->batched_reqs / s->batches : 0.0;
   st->device_busy_ms = s->busy_ms;
@@ -456,7 +584,7 @@ extern "C" mact_status mact_server_destroy(mact_server* s) {
   clear_error();
   if (!s) return MACT_OK;
   {
-    std::lock_guard<std::mutex> g(s->mu);
+    std::lock_guard<std::mutex> g(s->mu_in);
     s->stop = true;
   }
   s->cv_work.notify_all();

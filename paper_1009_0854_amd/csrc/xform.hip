@@ -105,7 +105,7 @@ int64_t images_per_launch(const HostImage& h) {
   return std::max<int64_t>(1, ((1ll << 31) - 1) / hw);
 }
 
-int pack_coef(const mact_params& p, KCoef* k) {
+int pack_coef(const mact_params& p, KCoef* k, int* exact) {
   std::memset(k, 0, sizeof *k);
   k->xform = p.xform;
   k->out_mode = p.out_mode;
@@ -121,6 +121,7 @@ int pack_coef(const mact_params& p, KCoef* k) {
   } else {
     k->q[0] = 1.0f;
   }
+  if (exact) *exact = deg;
   return deg <= 5 ? 5 : 7;
 }
 
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
     for (uint32_t i = threadIdx.x; i < 256u; i += kHotBlock) gtab[i] = k_gamma_table[gamma][i];
     __syncthreads();
   }
+  pin_lead<DEG>(k);
   const uint3* win = reinterpret_cast<const uint3*>(in);
   const uint32_t n_chunks = n_px >> 8;
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
@@ -461,14 +463,18 @@ static void launch_hwc4(int xform, const void* in, void* out, uint32_t n_px, con
   else hipLaunchKernelGGL((k_hwc4<IN, OUT, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, k, gamma);
 }
 
+// deg: the highest degree in use; the instance evaluates Horner from degree 4,
+// 5 or 7 (zero leading coefficients leave every bit unchanged).
 template <int IN>
 static void launch_hwc4_io(int xform, int out_dtype, int deg, const void* in, void* out, uint32_t n_px,
                            const KCoef& k, int gamma, hipStream_t st) {
   if (out_dtype == MACT_F32) {
-    if (deg == 5) launch_hwc4<IN, MACT_F32, 5>(xform, in, out, n_px, k, gamma, st);
+    if (deg <= 4) launch_hwc4<IN, MACT_F32, 4>(xform, in, out, n_px, k, gamma, st);
+    else if (deg == 5) launch_hwc4<IN, MACT_F32, 5>(xform, in, out, n_px, k, gamma, st);
     else launch_hwc4<IN, MACT_F32, 7>(xform, in, out, n_px, k, gamma, st);
   } else {
-    if (deg == 5) launch_hwc4<IN, MACT_F16, 5>(xform, in, out, n_px, k, gamma, st);
+    if (deg <= 4) launch_hwc4<IN, MACT_F16, 4>(xform, in, out, n_px, k, gamma, st);
+    else if (deg == 5) launch_hwc4<IN, MACT_F16, 5>(xform, in, out, n_px, k, gamma, st);
     else launch_hwc4<IN, MACT_F16, 7>(xform, in, out, n_px, k, gamma, st);
   }
 }
@@ -499,7 +505,8 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   if ((s = resolve_image(out, true, "mact_transform: out", &ho)) != MACT_OK) return s;
   if ((s = check_same_shape(hi, ho, "mact_transform: out")) != MACT_OK) return s;
   KCoef k;
-  const int deg = pack_coef(*params, &k);
+  int exact_deg = 7;
+  const int deg = pack_coef(*params, &k, &exact_deg);
   const int gamma = params->xform == MACT_LAB ? hi.gamma : MACT_GAMMA_NONE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   // fast shapes: packed 8-bit / float16 HWC -> packed float32 / float16 HWC, and packed float32 /
@@ -515,8 +522,8 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
     const void* ip = static_cast<const char*>(hi.data) + (size_t)(n0 * hi.bs) * hi.esize;
     void* op = static_cast<char*>(ho.data) + (size_t)(n0 * ho.bs) * ho.esize;
     if (hwc4 && aligned(ip, 4) && aligned(op, 16)) {
-      if (hi.dtype == MACT_U8) launch_hwc4_io<MACT_U8>(params->xform, ho.dtype, deg, ip, op, n_px, k, gamma, st);
-      else launch_hwc4_io<MACT_F16>(params->xform, ho.dtype, deg, ip, op, n_px, k, gamma, st);
+      if (hi.dtype == MACT_U8) launch_hwc4_io<MACT_U8>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
+      else launch_hwc4_io<MACT_F16>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
     } else if (chw4 && aligned(ip, 4 * hi.esize) && aligned(op, 16)) {
       const uint32_t hw = (uint32_t)(hi.W * hi.H);
       if (hi.dtype == MACT_F32) {

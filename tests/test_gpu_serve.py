@@ -91,3 +91,51 @@ def test_admission_limits(M):
         assert torch.equal(y, _plain(M, x, 0, "bt709", torch.float32))
     assert srv.stats().rejected == busy
     srv.close()
+
+
+def test_concurrent_submitters_and_waiters(M):
+    # four threads submit, poll and wait at once on one server: every request completes once,
+    # with the plain path's bits, and the counters add up
+    import threading
+    reqs = _requests(96, seed=8, lo=16, hi=300)
+    srv = M.Server(arena_bytes=32 << 20, max_batch=8, compute_streams=2)
+    ids = [None] * len(reqs)
+    errors = []
+
+    def worker(k):
+        try:
+            for j in range(k, len(reqs), 4):
+                x, y, xf, gm = reqs[j]
+                ids[j] = srv.submit(x, y, xf, gm)
+                if j % 3 == 0:
+                    srv.wait(ids[j], 60000)
+            for j in range(k, len(reqs), 4):
+                srv.wait(ids[j], 60000)
+                assert srv.poll(ids[j])
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(4)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    assert len(set(ids)) == len(reqs)
+    st = srv.stats()
+    assert st.submitted == len(reqs) and st.completed == len(reqs) and st.rejected == 0
+    for (x, y, xf, gm), i in zip(reqs, ids):
+        assert torch.equal(y, _plain(M, x, xf, gm, y.dtype)), i
+    srv.close()
+
+
+def test_destroy_drains_queued_requests(M):
+    # closing right after submitting completes every request first
+    reqs = _requests(24, seed=9, lo=64, hi=400)
+    srv = M.Server(arena_bytes=8 << 20, max_batch=4, compute_streams=1)
+    for x, y, xf, gm in reqs:
+        y.zero_()
+        srv.submit(x, y, xf, gm)
+    srv.close()
+    for x, y, xf, gm in reqs:
+        assert torch.equal(y, _plain(M, x, xf, gm, y.dtype))
