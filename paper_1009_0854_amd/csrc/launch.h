@@ -50,9 +50,12 @@ struct BDesc {
 // the coefficient index is set to `coef`.  *deg receives the padded degree.
 mact_status make_batch_descs(const mact_params& p, const mact_image* in, const mact_image* out, int32_t coef,
                              std::vector<BDesc>* descs, int* deg, const char* what);
-// Launch of the persistent batched kernel.
+// Launch of the persistent batched kernel.  d_tile_img (optional): the image
+// of every tile; without it each workgroup finds its tile's image by binary
+// search over d_tiles.
 hipError_t launch_batch_kernel(const BDesc* d_descs, const KCoef* d_coefs, const uint32_t* d_tiles, int32_t count,
-                               uint32_t total_tiles, const mact_tune& tune, int deg, hipStream_t st);
+                               uint32_t total_tiles, const mact_tune& tune, int deg, hipStream_t st,
+                               const uint32_t* d_tile_img = nullptr);
 // Grid of the batched kernel for a tune and a tile count.
 unsigned batch_grid(const mact_tune& tune, uint32_t total_tiles);
 // Tile list: tile_start[i] = first tile of descriptor i; returns the total.

@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "launch.h"
@@ -314,8 +315,10 @@ __global__ __launch_bounds__(256) void k_lut_cells(const f4* __restrict__ nodes,
 // ---------------------------------------------------------------- host
 
 int max_lds_bytes() {
+  static std::mutex mu;
   static int cache[64] = {0};
   const int d = current_device();
+  std::lock_guard<std::mutex> g(mu);
   if (d >= 0 && d < 64 && cache[d]) return cache[d];
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, d) != hipSuccess || v <= 0) v = 65536;

@@ -43,15 +43,18 @@ struct KCoef {
   int32_t xform, out_mode;
 };
 
-// One image as the kernels see it.  Pixel index p in [0, N H W) of one launch
-// is 32-bit; the host splits larger launches.
-struct FastDiv {  // n / d for 32-bit n and a fixed d >= 1 (round-up multiplier method)
+// n / d for 32-bit n and a fixed d >= 1: q = (umulhi(n, m) + n) >> s with the
+// round-up multiplier m = floor(2^32 (2^s - d) / d) + 1, 2^s >= d (exact for
+// every 32-bit n; the sum is formed in 64 bits).
+struct FastDiv {
   uint32_t d, m, s;
   __device__ __forceinline__ uint32_t div(uint32_t n) const {
     return (uint32_t)(((uint64_t)__umulhi(n, m) + n) >> s);
   }
 };
 
+// One image as the kernels see it.  Pixel index p in [0, N H W) of one launch
+// is 32-bit; the host splits larger launches.
 struct KImage {
   void* ptr;
   int32_t dtype, layout;
@@ -247,7 +250,6 @@ __device__ __forceinline__ void eval_px(const KCoef& k, bool u8, int gamma, cons
     sct_px<DEG>(k, v[0], v[1], v[2], u8 ? kInv255 : 1.0f, o);
   }
 }
-
 
 // ---------------------------------------------------------------- 4-pixel groups
 
