@@ -10,11 +10,15 @@ here imports the product.
 
 Modules
 -------
-colour   exact RGB->CIELAB / HSI / SCT transforms, the SCT inverse and the
-         error metrics (Sec. 3.2.1, 3.3.1, 3.4.1 and the metric of Sec. 3.4.1).
+colour   exact RGB->CIELAB / HSI / SCT transforms, their inverses (the
+         definitions solved for R, G, B; the SCT one is the paper's own) and
+         the error metrics (Sec. 3.2.1, 3.3.1, 3.4.1 and the metric of
+         Sec. 3.4.1).
 tables   the coefficient tables printed in the paper (Tables 1-7).
 mact     FP64 evaluation of the minimax-approximated transforms (Sec. 3.2.2,
-         3.3.2, 3.4.2-3.4.3) exactly as the GPU kernels evaluate them.
+         3.3.2, 3.4.2-3.4.3) exactly as the GPU kernels evaluate them, and of
+         the inverses with sine, cosine and the BT.709 encoding power replaced
+         by minimax approximations in the same way.
 remez    Remez exchange for minimax polynomials and rationals (Sec. 3.1), and
          a linear-programming discrete minimax used as an independent check.
 lut      3-D LUT packing and the trilinear, prism, pyramidal and tetrahedral

@@ -3,7 +3,8 @@ infrastructure only).
 
 Every function takes arrays whose last axis holds the three channels.  RGB
 values are on the normalised scale [0, 1] (an 8-bit value v enters as v/255).
-The formulas are the paper's definitions written out, nothing else.
+The formulas are the paper's definitions written out, and their inverses
+(the definitions solved for R, G, B), nothing else.
 """
 import numpy as np
 
@@ -156,6 +157,72 @@ def sct_to_rgb(sct):
     sct = np.asarray(sct, dtype=np.float64)
     L, A, Bang = sct[..., 0], sct[..., 1], sct[..., 2]
     return np.stack([L * np.sin(A) * np.cos(Bang), L * np.sin(A) * np.sin(Bang), L * np.cos(A)], axis=-1)
+
+
+# CIEXYZ -> linear RGB: the inverse of the BT.709 matrix above.
+M_XYZ_RGB = np.linalg.inv(M_RGB_XYZ)
+
+
+def encode_gamma(lin, kind="bt709"):
+    """Linear RGB -> nonlinear R'G'B': the inverse of ``inverse_gamma``.
+
+    ``bt709``: 4.5 L below 0.018 (= 0.081 / 4.5, the decoding breakpoint),
+    else 1.099 L^0.45 - 0.099; negative values take the linear branch.
+    ``srgb``: 12.92 L up to 0.0031308, else 1.055 L^(1/2.4) - 0.055.
+    ``none``: unchanged.
+    """
+    lin = np.asarray(lin, dtype=np.float64)
+    if kind == "bt709":
+        hi = np.maximum(lin, 0.018)
+        return np.where(lin < 0.018, 4.5 * lin, 1.099 * hi ** 0.45 - 0.099)
+    if kind == "srgb":
+        hi = np.maximum(lin, 0.0031308)
+        return np.where(lin <= 0.0031308, 12.92 * lin, 1.055 * hi ** (1.0 / 2.4) - 0.055)
+    if kind == "none":
+        return lin
+    raise ValueError(kind)
+
+
+def lab_f_inv(f):
+    """The inverse of the CIELAB nonlinearity: f^3 where that exceeds the
+    breakpoint 0.008856, else (f - 16/116) / 7.787.  (With the printed
+    constants f jumps at the breakpoint from 0.2068927 to cbrt(0.008856) =
+    0.2068930, so the two branches never overlap; f in the gap, which the
+    forward transform never produces, takes the linear branch.)"""
+    f = np.asarray(f, dtype=np.float64)
+    t = f * f * f
+    return np.where(t > LAB_T0, t, (f - LAB_C) / LAB_K)
+
+
+def lab_to_rgb(lab, gamma="bt709"):
+    """L*a*b* -> R'G'B' (or linear RGB with gamma='none'): the steps of
+    Sec. 3.2.1 inverted in reverse order.  No clipping."""
+    lab = np.asarray(lab, dtype=np.float64)
+    fy = (lab[..., 0] + 16.0) / 116.0
+    f = np.stack([fy + lab[..., 1] / 500.0, fy, fy - lab[..., 2] / 200.0], axis=-1)
+    xyz = lab_f_inv(f) * WHITE_D65
+    return encode_gamma(xyz @ M_XYZ_RGB.T, gamma)
+
+
+def hsi_to_rgb(hsi):
+    """HSI -> RGB, the inverse of the arccos definition (Sec. 3.3.1), by
+    sectors of 2pi/3: in the sector starting at hue h0 with h = H - h0, the
+    channel 'behind' the sector is I (1 - S), the channel at its start is
+    I (1 + S cos h / cos(pi/3 - h)), and the third makes the sum 3 I.
+    Sectors: [0, 2pi/3) B, R, G; [2pi/3, 4pi/3) R, G, B; [4pi/3, 2pi) G, B, R
+    (behind, start, third)."""
+    hsi = np.asarray(hsi, dtype=np.float64)
+    H = np.mod(hsi[..., 0], 2.0 * np.pi)
+    S, I = hsi[..., 1], hsi[..., 2]
+    sector = np.minimum((H // (2.0 * np.pi / 3.0)).astype(int), 2)
+    h = H - sector * (2.0 * np.pi / 3.0)
+    behind = I * (1.0 - S)
+    start = I * (1.0 + S * np.cos(h) / np.cos(np.pi / 3.0 - h))
+    third = 3.0 * I - (behind + start)
+    R = np.where(sector == 0, start, np.where(sector == 1, behind, third))
+    G = np.where(sector == 0, third, np.where(sector == 1, start, behind))
+    B = np.where(sector == 0, behind, np.where(sector == 1, third, start))
+    return np.stack([R, G, B], axis=-1)
 
 
 def delta_e(lab1, lab2):

@@ -107,3 +107,64 @@ def mact_sct(rgb, c_asin2, c_acos, c_atan, c_atanc):
     Bg = horner(c_atanc, R / np.where(g_pos, G, 1.0))
     Bang = np.where(gr, Bf, np.where(r_pos, Bg, np.where(g_pos, 0.5 * np.pi, 0.0)))
     return np.stack([L, A, Bang], axis=-1)
+
+
+# ---------------------------------------------------------------- inverses
+#
+# The inverse transforms with their elementary functions replaced by minimax
+# approximations in the same way: the BT.709 encoding power by a rational on
+# [0.018, 1], sine and cosine by polynomials on [0, pi/2] (SCT) and cosine on
+# [0, 2pi/3] (HSI).  The cube of the CIELAB inverse is exact.
+
+
+def mact_encode709(lin, p, q):
+    """BT.709 encoding with 1.099 L^0.45 - 0.099 replaced by p/q: 4.5 L below
+    0.018, p(L)/q(L) at or above, L clamped to [0, 1] first (the rational is
+    fitted on [0.018, 1] only)."""
+    x = clamp01(lin)
+    hi = x >= 0.018
+    xs = np.where(hi, x, 0.5)
+    return np.where(hi, horner(p, xs) / horner(q, xs), 4.5 * x)
+
+
+def mact_lab_inverse(lab, p_enc, q_enc, gamma="bt709"):
+    """L*a*b* -> R'G'B': f from L*, a*, b*, t by the exact cube (or the linear
+    segment), linear RGB = M^-1 (t * white) clamped to [0, 1], then the
+    approximated encoding (gamma 'bt709') or none ('none')."""
+    lab = np.asarray(lab, dtype=np.float64)
+    fy = (lab[..., 0] + 16.0) / 116.0
+    f = np.stack([fy + lab[..., 1] / 500.0, fy, fy - lab[..., 2] / 200.0], axis=-1)
+    lin = clamp01((colour.lab_f_inv(f) * colour.WHITE_D65) @ colour.M_XYZ_RGB.T)
+    if gamma == "bt709":
+        return mact_encode709(lin, p_enc, q_enc)
+    if gamma == "none":
+        return lin
+    raise ValueError(gamma)
+
+
+def mact_hsi_inverse(hsi, c_cos):
+    """HSI -> RGB by sectors (as colour.hsi_to_rgb) with cos replaced by the
+    polynomial ``c_cos`` on [0, 2pi/3], evaluated at |argument|.  H is taken
+    modulo 2pi."""
+    hsi = np.asarray(hsi, dtype=np.float64)
+    H = np.mod(hsi[..., 0], 2.0 * np.pi)
+    S, I = hsi[..., 1], hsi[..., 2]
+    sector = np.minimum((H // (2.0 * np.pi / 3.0)).astype(int), 2)
+    h = H - sector * (2.0 * np.pi / 3.0)
+    behind = I * (1.0 - S)
+    start = I * (1.0 + S * horner(c_cos, h) / horner(c_cos, np.abs(np.pi / 3.0 - h)))
+    third = 3.0 * I - (behind + start)
+    R = np.where(sector == 0, start, np.where(sector == 1, behind, third))
+    G = np.where(sector == 0, third, np.where(sector == 1, start, behind))
+    B = np.where(sector == 0, behind, np.where(sector == 1, third, start))
+    return np.stack([R, G, B], axis=-1)
+
+
+def mact_sct_inverse(sct, c_sin, c_cos):
+    """SCT -> RGB (the inverse of Sec. 3.4.1: R = L sin A cos B, G = L sin A
+    sin B, B = L cos A) with sin and cos replaced by polynomials on
+    [0, pi/2], the range of both angles for non-negative RGB."""
+    sct = np.asarray(sct, dtype=np.float64)
+    L, A, Bang = sct[..., 0], sct[..., 1], sct[..., 2]
+    sa = horner(c_sin, A)
+    return np.stack([L * sa * horner(c_cos, Bang), L * sa * horner(c_sin, Bang), L * horner(c_cos, A)], axis=-1)
