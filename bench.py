@@ -17,8 +17,9 @@ The JSON line also carries
                 of the same batch on the host, one thread;
   accuracy      Delta E*ab of the GPU output against the exact transform on that
                 sample, and the oracle's exhaustive-cube figures;
-  forms         (--forms all) HSI, SCT, the CIELAB LUT interpolators, the
-                backward pass, the batched form (1000 uneven images, one
+  forms         (--forms all) HSI, SCT, float16 output, the 4K batch, the
+                inverses and the on-device error statistics, the LUT
+                interpolators, the backward pass, the batched form (1000 uneven images, one
                 graph-captured persistent launch vs 1000 plain launches) and the
                 served form (Poisson arrivals: p50/p99 latency and throughput vs
                 the plain per-request path).
@@ -107,6 +108,32 @@ def bench_4k(M, p, steps):
     del x, y
     torch.cuda.empty_cache()
     return res
+
+
+def bench_inverse(M, x, y, n_px, steps):
+    """Inverse MACT (L*a*b* / HSI / SCT float32 -> R'G'B' float32, 24 bytes per
+    pixel) on the forward output of the batch, and the on-device error
+    statistics of each forward transform over all 2^24 8-bit colours."""
+    import torch
+    import synth
+    out = {}
+    back = torch.empty_like(y)
+    for name in ("lab", "hsi", "sct"):
+        M.transform(x, xform=name, out=y)
+        gm = "bt709" if name == "lab" else "none"
+        ms, _ = time_kernel(lambda: M.inverse(y, xform=name, gamma=gm, out=back), steps)
+        out["%s_inverse" % name] = {"Mpx_s": n_px / ms / 1e3, "GBs": 24.0 * n_px / ms / 1e6, "ms": ms}
+    del back
+    cube = torch.from_numpy(synth.cube_u8()).cuda()
+    for name in ("lab", "hsi", "sct"):
+        M.error_stats(cube, xform=name)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = M.error_stats(cube, xform=name)
+        dt = time.perf_counter() - t0
+        out["%s_error_stats_all_colours" % name] = {"ms": dt * 1e3, "mean": st["mean"], "max": st["max"],
+                                                    "max_abs": st["max_abs"]}
+    return out
 
 
 def bench_lut(M, x, y, n_px, steps):
@@ -350,6 +377,8 @@ def main():
             p = M.default_params(xf)
             ms, _ = time_kernel(lambda: M.transform(x, params=p, out=y), a.steps)
             forms[name] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
+        log("inverses and on-device error statistics")
+        forms["inverse"] = bench_inverse(M, x, y, n_px, a.steps)
     if a.forms in ("all", "lut"):
         log("LUT interpolators")
         forms["lut"] = bench_lut(M, x, y, n_px, a.steps)

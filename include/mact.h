@@ -57,7 +57,8 @@ const char* mact_version(void);
 
 /* ------------------------------------------------- minimax approximations */
 
-/* Functions the paper approximates (Sec. 3.2.2, 3.3.2, 3.4.2, 3.4.3). */
+/* Functions the paper approximates (Sec. 3.2.2, 3.3.2, 3.4.2, 3.4.3), and the
+   ones the inverse transforms approximate in the same way. */
 enum {
   MACT_FN_CBRT = 0,       /* t^(1/3): the CIELAB nonlinearity above 0.008856 */
   MACT_FN_ATAN_SQRT3 = 1, /* arctan(sqrt(3) x): Kender's hue, odd extension */
@@ -65,7 +66,10 @@ enum {
   MACT_FN_ACOS = 3,       /* arccos(x): SCT angle A, B/L < 0.5 */
   MACT_FN_ATAN = 4,       /* arctan(x): SCT angle B for G < R (f of the split) */
   MACT_FN_ATANC = 5,      /* pi/2 - arctan(t): SCT angle B for R <= G (g of the split) */
-  MACT_FN_COUNT = 6
+  MACT_FN_SIN = 6,        /* sin(x): SCT -> RGB */
+  MACT_FN_COS = 7,        /* cos(x): SCT -> RGB and HSI -> RGB */
+  MACT_FN_ENC709 = 8,     /* 1.099 x^0.45 - 0.099: BT.709 encoding above 0.018, CIELAB -> R'G'B' */
+  MACT_FN_COUNT = 9
 };
 
 #define MACT_MAX_DEGREE 7
@@ -100,7 +104,8 @@ mact_status mact_fit_ex(int32_t fn, int32_t n, int32_t m, double lo, double hi, 
    per process and cached): cube root (4,4) rational on [0.008856, 1] (Table 2's
    degree); arctan(sqrt 3 x) degree 5 on [0, 1]; 2 arcsin(y/sqrt 2) degree 5 on
    [0, 1/sqrt 2]; arccos degree 5 on [0, 0.5]; arctan and pi/2 - arctan degree 5
-   on [0, 1] (the full range of G/R and R/G for float inputs). */
+   on [0, 1] (the full range of G/R and R/G for float inputs); sine and cosine
+   degree 7 on [0, pi/2]; the BT.709 encoding (4,4) rational on [0.018, 1]. */
 mact_status mact_default_approx(int32_t fn, mact_approx* out);
 
 /* The coefficients printed in the paper: Table 1 (fn CBRT, m = 0, n = 2..5),
@@ -191,6 +196,54 @@ mact_status mact_transform(const mact_params* params, const mact_image* in, cons
 mact_status mact_transform_backward(const mact_params* params, const mact_image* x,
                                     const mact_image* grad_out, const mact_image* grad_in,
                                     void* hip_stream);
+
+/* ------------------------------------------------------------ inverses, error statistics */
+
+/* Fill *p with the default approximations of the inverse of `xform`:
+     LAB: f[0] = the BT.709 encoding power, (4,4) rational on [0.018, 1];
+     HSI: f[0] = cosine, degree 7 on [0, 2 pi/3];
+     SCT: f[0] = sine, f[1] = cosine, degree 7 on [0, pi/2]. */
+mact_status mact_inverse_params_default(int32_t xform, mact_params* p);
+
+/* Inverse MACT transform of `in` (L*a*b*, HSI or SCT triples) into `out`
+   (R'G'B' on the [0, 1] scale):
+     LAB: fy = (L* + 16)/116, fx = fy + a* / 500, fz = fy - b* / 200; t = f^3 where
+          that exceeds 0.008856, else (f - 16/116)/7.787 (Sec. 3.2.1 solved for
+          t); linear RGB = M^-1 (t * white), clamped to [0, 1]; then, for an
+          `out` with gamma MACT_GAMMA_BT709, 4.5 L below 0.018 and f[0](L) at or
+          above (the encoding that inverts Sec. 3.2.1's inverse gamma); with
+          MACT_GAMMA_NONE the linear values.
+     HSI: by sectors of 2 pi/3 (H taken modulo 2 pi): in the sector starting
+          at h0, with h = H - h0, the channel behind the sector is I (1 - S), the
+          one at its start I (1 + S c(h) / c(|pi/3 - h|)) with c = f[0] ~ cos,
+          and the third 3 I - (the other two) (Sec. 3.3.1 solved for R, G, B).
+     SCT: R = L s(A) c(B), G = L s(A) s(B), B = L c(A) with s = f[0] ~ sin and
+          c = f[1] ~ cos (Sec. 3.4.1's inverse); A, B in [0, pi/2], the range
+          the forward transform gives for non-negative RGB.
+   in: MACT_F32 or MACT_F16, any layout; out: MACT_F32 or MACT_F16, any layout,
+   same geometry.  float32 arithmetic.  Errors: MACT_E_INVALID (NULL, shapes,
+   approximations of the wrong function or degree); MACT_E_UNSUPPORTED (8-bit
+   in, sRGB encoding); MACT_E_DEVICE. */
+mact_status mact_inverse(const mact_params* params, const mact_image* in, const mact_image* out,
+                         void* hip_stream);
+
+/* Accuracy of a forward transform over an image, computed on the device. */
+typedef struct mact_error {
+  int64_t count;       /* pixels */
+  double mean, max;    /* of the metric: Delta E*ab (LAB, Sec. 3.2.1), D_HSI (HSI, Sec. 3.3.1),
+                          or the SCT measure of Sec. 3.4.1 (both triples back to RGB, no
+                          clipping, then CIELAB with BT.709, then Delta E*ab) */
+  double max_abs[3];   /* largest |MACT - exact| per channel (HSI hue wrapped to [0, pi]) */
+} mact_error;
+
+/* Every pixel of `in` (an RGB image as mact_transform takes it) through the
+   MACT transform of `params` (float32, the same arithmetic as mact_transform)
+   and through the exact transform (float64 on the device: the definitions of
+   Sec. 3.2.1, 3.3.1, 3.4.1 with the library's cube root, arctangent and
+   arccosine); the metric per pixel, reduced to mean and max.  Enqueues on
+   `hip_stream`, waits for it, and fills *out.  The library allocates and frees
+   40 bytes of device memory per call.  Errors as mact_transform; MACT_E_NOMEM. */
+mact_status mact_error_stats(const mact_params* params, const mact_image* in, mact_error* out, void* hip_stream);
 
 /* ------------------------------------------------------------ 3-D LUTs */
 

@@ -15,8 +15,9 @@ from ._abi import (CHW, E_BUSY, E_NOCONV, F16, F32, FN_ACOS, FN_ASIN2, FN_ATAN, 
                    U8, Approx, Image, MactError, Params, Request, ServerConfig, ServerStats, Tune, lib)
 
 __all__ = ["fit", "default_approx", "paper_approx", "default_params", "make_params", "image", "transform",
-           "transform_backward", "lut_bytes", "lut_build", "lut_interp", "BatchPlan", "batch_run", "Server",
-           "stream_u8_to_f32", "copy", "MactError", "MactLab"]
+           "transform_backward", "inverse_params", "inverse", "error_stats", "lut_bytes", "lut_build",
+           "lut_interp", "lut_cells_bytes", "lut_cells_build", "lut_cells_interp", "BatchPlan", "batch_run",
+           "Server", "stream_u8_to_f32", "copy", "MactError", "MactLab"]
 
 
 def _torch():
@@ -160,6 +161,41 @@ def transform_backward(x, grad_out, params=None, layout="chw", grad_in=None, str
                                           ctypes.byref(image(grad_out, layout)),
                                           ctypes.byref(image(grad_in, layout)), _stream(stream)))
     return grad_in
+
+
+# ---------------------------------------------------------------- inverses, error statistics
+
+def inverse_params(xform="lab"):
+    """mact_inverse_params_default: the default approximations of the inverse."""
+    p = Params()
+    A.check(lib().mact_inverse_params_default(_xf(xform), ctypes.byref(p)))
+    return p
+
+
+def inverse(x, xform="lab", params=None, layout="hwc", gamma="bt709", out=None, out_layout=None, out_dtype=None,
+            stream=None):
+    """mact_inverse of float tensor x (L*a*b*, HSI or SCT triples) to R'G'B'
+    on the [0, 1] scale; `gamma` is the encoding of the CIELAB inverse's output
+    ('bt709' or 'none')."""
+    torch = _torch()
+    p = params if params is not None else inverse_params(xform)
+    out_layout = layout if out_layout is None else out_layout
+    if out is None:
+        out = _out_like(x, layout, out_layout, out_dtype or torch.float32)
+    A.check(lib().mact_inverse(ctypes.byref(p), ctypes.byref(image(x, layout, "none")),
+                               ctypes.byref(image(out, out_layout, gamma)), _stream(stream)))
+    return out
+
+
+def error_stats(x, xform="lab", params=None, layout="hwc", gamma="bt709", stream=None):
+    """mact_error_stats: accuracy of the MACT transform of RGB tensor x against
+    the exact transform, computed on the device.  Returns a dict with count,
+    mean, max and max_abs (per channel)."""
+    p = params if params is not None else default_params(xform)
+    e = A.ErrorStats()
+    A.check(lib().mact_error_stats(ctypes.byref(p), ctypes.byref(image(x, layout, gamma)), ctypes.byref(e),
+                                   _stream(stream)))
+    return {"count": e.count, "mean": e.mean, "max": e.max, "max_abs": [e.max_abs[c] for c in range(3)]}
 
 
 # ---------------------------------------------------------------- LUTs

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmact.so"
 # status codes
 OK, E_INVALID, E_NOCONV, E_DEVICE, E_NOMEM, E_UNSUPPORTED, E_BUSY = 0, -1, -2, -3, -4, -5, -6
 # functions
-FN_CBRT, FN_ATAN_SQRT3, FN_ASIN2, FN_ACOS, FN_ATAN, FN_ATANC = range(6)
+FN_CBRT, FN_ATAN_SQRT3, FN_ASIN2, FN_ACOS, FN_ATAN, FN_ATANC, FN_SIN, FN_COS, FN_ENC709 = range(9)
 # transforms, element types, layouts, transfer functions, LUT methods
 LAB, HSI, SCT = 0, 1, 2
 U8, F16, F32 = 0, 1, 2
@@ -69,6 +69,10 @@ class ServerStats(ctypes.Structure):
                 ("device_busy_ms", c_double)]
 
 
+class ErrorStats(ctypes.Structure):
+    _fields_ = [("count", c_int64), ("mean", c_double), ("max", c_double), ("max_abs", c_double * 3)]
+
+
 # exported symbol -> (restype, argtypes); the list the ABI test checks against the header
 SIGNATURES = {
     "mact_status_str": (c_char_p, [c_int32]),
@@ -84,6 +88,9 @@ SIGNATURES = {
     "lut_bytes": (c_size_t, [c_int32, c_int32]),
     "lut_build": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
     "lut_interp": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(Image), POINTER(Image), c_void_p]),
+    "mact_inverse_params_default": (c_int32, [c_int32, POINTER(Params)]),
+    "mact_inverse": (c_int32, [POINTER(Params), POINTER(Image), POINTER(Image), c_void_p]),
+    "mact_error_stats": (c_int32, [POINTER(Params), POINTER(Image), POINTER(ErrorStats), c_void_p]),
     "lut_cells_bytes": (c_size_t, [c_int32, c_int32]),
     "lut_cells_build": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
     "lut_cells_interp": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(Image), POINTER(Image), c_void_p]),

@@ -148,6 +148,8 @@ const Default kDefaults[MACT_FN_COUNT] = {
     {MACT_FN_CBRT, 4, 4, kLabT0, 1.0},     {MACT_FN_ATAN_SQRT3, 5, 0, 0.0, 1.0},
     {MACT_FN_ASIN2, 5, 0, 0.0, kInvSqrt2}, {MACT_FN_ACOS, 5, 0, 0.0, 0.5},
     {MACT_FN_ATAN, 5, 0, 0.0, 1.0},        {MACT_FN_ATANC, 5, 0, 0.0, 1.0},
+    {MACT_FN_SIN, 7, 0, 0.0, kPi / 2},     {MACT_FN_COS, 7, 0, 0.0, kPi / 2},
+    {MACT_FN_ENC709, 4, 4, 0.018, 1.0},
 };
 
 std::once_flag g_default_once[MACT_FN_COUNT];

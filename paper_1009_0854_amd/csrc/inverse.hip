@@ -1,0 +1,418 @@
+// Inverse transforms (CIELAB, HSI, SCT -> RGB) with minimax approximations,
+// and on-device error statistics of the forward transforms.
+//
+// Inverses: the definitions of Sec. 3.2.1 and 3.3.1 solved for R, G, B, and
+// the SCT inverse of Sec. 3.4.1, with the elementary functions replaced by
+// minimax approximations in the paper's manner: the BT.709 encoding power
+// 1.099 L^0.45 - 0.099 by a rational on [0.018, 1] (the cube of the CIELAB
+// inverse is exact), cosine by a polynomial on [0, 2 pi/3] (HSI), sine and
+// cosine by polynomials on [0, pi/2] (SCT).  float32, explicit fmas, one
+// pixel per lane.
+//
+// Error statistics: every pixel of an RGB image goes through the forward MACT
+// transform (the same per-pixel code as mact_transform, float32) and through
+// the exact transform in float64; the paper's metric of the pair (Delta E*ab,
+// D_HSI, or the SCT measure: both triples back to RGB, then to CIELAB, then
+// Delta E*ab) is reduced to its mean and maximum, with the largest per-channel
+// differences, in one pass.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "launch.h"
+
+namespace mact {
+
+#include "gamma_table.inc"
+
+namespace {
+
+// M^-1 diag(white): t (= XYZ / white) -> linear RGB, rounded once from double.
+struct InvMat {
+  float m[3][3];
+};
+
+InvMat make_inv_mat() {
+  // 3x3 inverse by cofactors, in double
+  const double (*a)[3] = kM;
+  const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
+                     a[0][1] * (a[1][0] * a[2][2] - a[1][2] * a[2][0]) +
+                     a[0][2] * (a[1][0] * a[2][1] - a[1][1] * a[2][0]);
+  double inv[3][3];
+  inv[0][0] = (a[1][1] * a[2][2] - a[1][2] * a[2][1]) / det;
+  inv[0][1] = (a[0][2] * a[2][1] - a[0][1] * a[2][2]) / det;
+  inv[0][2] = (a[0][1] * a[1][2] - a[0][2] * a[1][1]) / det;
+  inv[1][0] = (a[1][2] * a[2][0] - a[1][0] * a[2][2]) / det;
+  inv[1][1] = (a[0][0] * a[2][2] - a[0][2] * a[2][0]) / det;
+  inv[1][2] = (a[0][2] * a[1][0] - a[0][0] * a[1][2]) / det;
+  inv[2][0] = (a[1][0] * a[2][1] - a[1][1] * a[2][0]) / det;
+  inv[2][1] = (a[0][1] * a[2][0] - a[0][0] * a[2][1]) / det;
+  inv[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) / det;
+  InvMat r;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) r.m[i][j] = (float)(inv[i][j] * kWhite[j]);
+  return r;
+}
+
+constexpr float kEnc0 = 0.018f;  // BT.709 encoding breakpoint (0.081 / 4.5)
+constexpr float kTwoPi3f = static_cast<float>(2.0 * kPi / 3.0);
+
+// Raw float element (no clamping): inverse inputs are L*a*b*, HSI or SCT values.
+__device__ __forceinline__ void load_raw(const KImage& im, uint32_t p, float v[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t o = elem_off(im, p, c);
+    if (im.dtype == MACT_F16) v[c] = __half2float(static_cast<const __half*>(im.ptr)[o]);
+    else v[c] = static_cast<const float*>(im.ptr)[o];
+  }
+}
+
+template <int DEG>
+__device__ __forceinline__ void lab_inv_px(const KCoef& k, const InvMat& mi, int gamma, const float v[3], float o[3]) {
+  const float fy = (v[0] + 16.0f) * (1.0f / 116.0f);
+  const float f[3] = {__builtin_fmaf(v[1], 1.0f / 500.0f, fy), fy, __builtin_fmaf(v[2], -1.0f / 200.0f, fy)};
+  float t[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float cube = f[c] * f[c] * f[c];
+    t[c] = cube > kT0f ? cube : (f[c] - kLabCf) * (1.0f / kLabKf);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float lin = clamp01(__builtin_fmaf(mi.m[c][0], t[0], __builtin_fmaf(mi.m[c][1], t[1], mi.m[c][2] * t[2])));
+    if (gamma == MACT_GAMMA_NONE) o[c] = lin;
+    else o[c] = lin >= kEnc0 ? fdiv(horner<DEG>(k.p[0], lin), horner<DEG>(k.q, lin)) : 4.5f * lin;
+  }
+}
+
+template <int DEG>
+__device__ __forceinline__ void hsi_inv_px(const KCoef& k, const float v[3], float o[3]) {
+  float H = v[0];
+  if (H < 0.0f || H >= kTwoPif) H -= kTwoPif * floorf(H * (1.0f / kTwoPif));
+  const float S = v[1], I = v[2];
+  const int sector = H < kTwoPi3f ? 0 : (H < 2.0f * kTwoPi3f ? 1 : 2);
+  const float h = H - (float)sector * kTwoPi3f;
+  const float ratio = fdiv(horner<DEG>(k.p[0], h), horner<DEG>(k.p[0], __builtin_fabsf(kPi3f - h)));
+  const float behind = I * (1.0f - S);
+  const float start = I * __builtin_fmaf(S, ratio, 1.0f);
+  const float third = 3.0f * I - (behind + start);
+  if (sector == 0) { o[0] = start; o[1] = third; o[2] = behind; }
+  else if (sector == 1) { o[0] = behind; o[1] = start; o[2] = third; }
+  else { o[0] = third; o[1] = behind; o[2] = start; }
+}
+
+template <int DEG>
+__device__ __forceinline__ void sct_inv_px(const KCoef& k, const float v[3], float o[3]) {
+  const float L = v[0];
+  const float sa = horner<DEG>(k.p[0], v[1]), ca = horner<DEG>(k.p[1], v[1]);
+  const float sb = horner<DEG>(k.p[0], v[2]), cb = horner<DEG>(k.p[1], v[2]);
+  const float ls = L * sa;
+  o[0] = ls * cb;
+  o[1] = ls * sb;
+  o[2] = L * ca;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_inverse(KImage src, KImage dst, uint32_t n_px, KCoef k, InvMat mi,
+                                                 int gamma) {
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < n_px; p += stride) {
+    float v[3], o[3];
+    load_raw(src, p, v);
+    if (k.xform == MACT_LAB) lab_inv_px<DEG>(k, mi, gamma, v, o);
+    else if (k.xform == MACT_HSI) hsi_inv_px<DEG>(k, v, o);
+    else sct_inv_px<DEG>(k, v, o);
+    store_px(dst, p, o);
+  }
+}
+
+// ---------------------------------------------------------------- exact, float64
+
+__device__ __forceinline__ double dev_inverse_gamma(double k, int gamma) {
+  if (gamma == MACT_GAMMA_BT709) return k < 0.081 ? k / 4.5 : pow((k + 0.099) / 1.099, 1.0 / 0.45);
+  if (gamma == MACT_GAMMA_SRGB) return k <= 0.04045 ? k / 12.92 : pow((k + 0.055) / 1.055, 2.4);
+  return k;
+}
+
+__device__ __forceinline__ void dev_lab(const double rgb[3], int gamma, double out[3]) {
+  double lin[3], f[3];
+  for (int c = 0; c < 3; ++c) lin[c] = dev_inverse_gamma(rgb[c], gamma);
+  for (int r = 0; r < 3; ++r) {
+    const double t = (kM[r][0] * lin[0] + kM[r][1] * lin[1] + kM[r][2] * lin[2]) / kWhite[r];
+    f[r] = t > kLabT0 ? cbrt(t) : kLabK * t + kLabC;
+  }
+  out[0] = 116.0 * f[1] - 16.0;
+  out[1] = 500.0 * (f[0] - f[1]);
+  out[2] = 200.0 * (f[1] - f[2]);
+}
+
+__device__ __forceinline__ void dev_hsi(const double rgb[3], double out[3]) {
+  // Kender's form with the exact arctan (Sec. 3.3.1); H = 0 where undefined
+  const double R = rgb[0], G = rgb[1], B = rgb[2];
+  double H = 0.0;
+  if (R > B && G > B) H = kPi / 3.0 + atan(sqrt(3.0) * (G - R) / ((G - B) + (R - B)));
+  else if (G > R) H = kPi + atan(sqrt(3.0) * (B - G) / ((B - R) + (G - R)));
+  else if (B > G) H = 5.0 * kPi / 3.0 + atan(sqrt(3.0) * (R - B) / ((R - G) + (B - G)));
+  const double s = R + G + B;
+  out[0] = H;
+  out[1] = s > 0.0 ? 1.0 - 3.0 * fmin(R, fmin(G, B)) / s : 0.0;
+  out[2] = s / 3.0;
+}
+
+__device__ __forceinline__ void dev_sct(const double rgb[3], double out[3]) {
+  const double R = rgb[0], G = rgb[1], B = rgb[2];
+  const double L = sqrt(R * R + G * G + B * B);
+  out[0] = L;
+  out[1] = L > 0.0 ? acos(fmin(1.0, B / L)) : 0.0;
+  out[2] = atan2(G, R);
+}
+
+__device__ __forceinline__ void dev_sct_to_rgb(const double s[3], double rgb[3]) {
+  const double sa = sin(s[1]);
+  rgb[0] = s[0] * sa * cos(s[2]);
+  rgb[1] = s[0] * sa * sin(s[2]);
+  rgb[2] = s[0] * cos(s[1]);
+}
+
+__device__ __forceinline__ double dev_delta_e(const double a[3], const double b[3]) {
+  const double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
+  return sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+}
+
+// |a - b| wrapped to [0, pi]
+__device__ __forceinline__ double dev_angle_diff(double a, double b) {
+  double d = fmod(fabs(a - b), 2.0 * kPi);
+  return fmin(d, 2.0 * kPi - d);
+}
+
+// Accumulators: [0] sum of the metric, [1] its max, [2..4] per-channel max |difference|.
+// Maxima of non-negative doubles are kept as their bit patterns, which order like integers.
+struct ErrAcc {
+  double sum;
+  unsigned long long max_bits[4];
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_error(KImage src, uint32_t n_px, KCoef k, int gamma, ErrAcc* acc) {
+  __shared__ float gtab[256];
+  __shared__ double s_red[4][5];
+  gtab[threadIdx.x] = k_gamma_table[gamma][threadIdx.x];
+  __syncthreads();
+  const bool u8 = src.dtype == MACT_U8;
+  const double scale = u8 ? 1.0 / 255.0 : 1.0;
+  double sum = 0.0, mx[4] = {0.0, 0.0, 0.0, 0.0};
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < n_px; p += stride) {
+    float v[3], o[3];
+    load_px(src, p, v);
+    eval_px<DEG>(k, u8, gamma, gtab, v, o);
+    const double rgb[3] = {v[0] * scale, v[1] * scale, v[2] * scale};  // raw values, [0, 1] scale
+    const double m[3] = {o[0], o[1], o[2]};
+    double ex[3], e, d[3];
+    if (k.xform == MACT_LAB) {
+      dev_lab(rgb, gamma, ex);
+      e = dev_delta_e(m, ex);
+      for (int c = 0; c < 3; ++c) d[c] = fabs(m[c] - ex[c]);
+    } else if (k.xform == MACT_HSI) {
+      dev_hsi(rgb, ex);
+      const double th = dev_angle_diff(m[0], ex[0]);
+      const double dv = m[2] - ex[2];
+      e = sqrt(fmax(m[1] * m[1] + ex[1] * ex[1] - 2.0 * m[1] * ex[1] * cos(th) + dv * dv, 0.0));
+      d[0] = th;
+      d[1] = fabs(m[1] - ex[1]);
+      d[2] = fabs(dv);
+    } else {
+      dev_sct(rgb, ex);
+      double ra[3], rb[3], la[3], lb[3];
+      dev_sct_to_rgb(m, ra);
+      dev_sct_to_rgb(ex, rb);
+      dev_lab(ra, MACT_GAMMA_BT709, la);
+      dev_lab(rb, MACT_GAMMA_BT709, lb);
+      e = dev_delta_e(la, lb);
+      for (int c = 0; c < 3; ++c) d[c] = fabs(m[c] - ex[c]);
+    }
+    sum += e;
+    mx[0] = fmax(mx[0], e);
+    for (int c = 0; c < 3; ++c) mx[c + 1] = fmax(mx[c + 1], d[c]);
+  }
+  sum = wave_sum(sum);
+  for (int c = 0; c < 4; ++c) mx[c] = wave_max(mx[c]);
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    s_red[wv][0] = sum;
+    for (int c = 0; c < 4; ++c) s_red[wv][c + 1] = mx[c];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bs = 0.0, bm[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < 4; ++w) {
+      bs += s_red[w][0];
+      for (int c = 0; c < 4; ++c) bm[c] = fmax(bm[c], s_red[w][c + 1]);
+    }
+    atomicAdd(&acc->sum, bs);
+    for (int c = 0; c < 4; ++c) atomicMax(&acc->max_bits[c], (unsigned long long)__double_as_longlong(bm[c]));
+  }
+}
+
+unsigned grid_256(uint64_t work, int per_cu) {
+  const uint64_t need = (work + 255) / 256;
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(need, (uint64_t)device_cus() * per_cu));
+}
+
+// Cached default inverse approximations (made once per process).
+struct InvDefaults {
+  mact_approx enc, cos_h, sin_s, cos_s;
+  mact_status st = MACT_OK;
+};
+
+const InvDefaults& inv_defaults() {
+  static InvDefaults d;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    mact_status s = mact_fit(MACT_FN_ENC709, 4, 4, 0.018, 1.0, &d.enc);
+    if (s == MACT_OK) s = mact_fit(MACT_FN_COS, 7, 0, 0.0, 2.0 * kPi / 3.0, &d.cos_h);
+    if (s == MACT_OK) s = mact_default_approx(MACT_FN_SIN, &d.sin_s);
+    if (s == MACT_OK) s = mact_default_approx(MACT_FN_COS, &d.cos_s);
+    d.st = s;
+  });
+  return d;
+}
+
+// Validation of inverse parameters; the KCoef packing of pack_coef does not
+// apply (the inverse uses f[0] and f[1] in its own way), so they are packed here.
+mact_status pack_inverse(const mact_params* p, int gamma, KCoef* k, int* deg) {
+  if (!p) return fail(MACT_E_INVALID, "mact_inverse: params is NULL");
+  if (p->xform < MACT_LAB || p->xform > MACT_SCT) return fail(MACT_E_INVALID, "mact_inverse: xform %d", p->xform);
+  if (p->out_mode != 0) return fail(MACT_E_INVALID, "mact_inverse: out_mode must be 0");
+  std::memset(k, 0, sizeof *k);
+  k->xform = p->xform;
+  k->q[0] = 1.0f;
+  int d = 0;
+  const int nf = p->xform == MACT_SCT ? 2 : 1;
+  const bool need = !(p->xform == MACT_LAB && gamma == MACT_GAMMA_NONE);
+  for (int i = 0; i < nf && need; ++i) {
+    const mact_approx& a = p->f[i];
+    mact_status s = check_approx(a, p->xform == MACT_LAB, "mact_inverse");
+    if (s != MACT_OK) return s;
+    const int want = p->xform == MACT_LAB ? MACT_FN_ENC709 : p->xform == MACT_HSI ? MACT_FN_COS
+                                                                                  : (i == 0 ? MACT_FN_SIN : MACT_FN_COS);
+    if (a.fn != want) return fail(MACT_E_INVALID, "mact_inverse: f[%d] approximates function %d, expected %d", i, a.fn, want);
+    for (int j = 0; j <= a.n; ++j) k->p[i][j] = (float)a.p[j];
+    d = std::max(d, a.n);
+    if (a.m > 0) {
+      for (int j = 0; j <= a.m; ++j) k->q[j] = (float)a.q[j];
+      d = std::max(d, a.m);
+    }
+  }
+  *deg = d <= 5 ? 5 : 7;
+  return MACT_OK;
+}
+
+}  // namespace
+}  // namespace mact
+
+using namespace mact;
+
+extern "C" mact_status mact_inverse_params_default(int32_t xform, mact_params* p) {
+  clear_error();
+  if (!p) return fail(MACT_E_INVALID, "mact_inverse_params_default: NULL");
+  if (xform < MACT_LAB || xform > MACT_SCT) return fail(MACT_E_INVALID, "mact_inverse_params_default: xform %d", xform);
+  const InvDefaults& d = inv_defaults();
+  if (d.st != MACT_OK) return fail(d.st, "mact_inverse_params_default: fitting the default approximations failed");
+  std::memset(p, 0, sizeof *p);
+  p->xform = xform;
+  if (xform == MACT_LAB) p->f[0] = d.enc;
+  else if (xform == MACT_HSI) p->f[0] = d.cos_h;
+  else {
+    p->f[0] = d.sin_s;
+    p->f[1] = d.cos_s;
+  }
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_inverse(const mact_params* params, const mact_image* in, const mact_image* out,
+                                    void* hip_stream) {
+  clear_error();
+  HostImage hi, ho;
+  mact_status s;
+  if ((s = resolve_image(in, false, "mact_inverse: in", &hi)) != MACT_OK) return s;
+  if ((s = resolve_image(out, true, "mact_inverse: out", &ho)) != MACT_OK) return s;
+  if ((s = check_same_shape(hi, ho, "mact_inverse: out")) != MACT_OK) return s;
+  if (hi.dtype == MACT_U8) return fail(MACT_E_UNSUPPORTED, "mact_inverse: in must be MACT_F32 or MACT_F16");
+  if (!params) return fail(MACT_E_INVALID, "mact_inverse: params is NULL");
+  int gamma = MACT_GAMMA_NONE;
+  if (params->xform == MACT_LAB) {
+    gamma = ho.gamma;
+    if (gamma == MACT_GAMMA_SRGB) return fail(MACT_E_UNSUPPORTED, "mact_inverse: sRGB encoding has no default approximation");
+  }
+  KCoef k;
+  int deg = 5;
+  if ((s = pack_inverse(params, gamma, &k, &deg)) != MACT_OK) return s;
+  static const InvMat mi = make_inv_mat();
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int64_t per = images_per_launch(hi);
+  for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
+    const int64_t cnt = std::min(per, hi.N - n0);
+    const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
+    const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
+    const dim3 grid(grid_256(n_px, 8)), blk(256);
+    if (deg == 5) hipLaunchKernelGGL(k_inverse<5>, grid, blk, 0, st, ks, kd, n_px, k, mi, gamma);
+    else hipLaunchKernelGGL(k_inverse<7>, grid, blk, 0, st, ks, kd, n_px, k, mi, gamma);
+    if ((s = hip_check(hipGetLastError(), "mact_inverse: launch")) != MACT_OK) return s;
+  }
+  return MACT_OK;
+}
+
+extern "C" mact_status mact_error_stats(const mact_params* params, const mact_image* in, mact_error* out,
+                                        void* hip_stream) {
+  clear_error();
+  if (!out) return fail(MACT_E_INVALID, "mact_error_stats: out is NULL");
+  std::memset(out, 0, sizeof *out);
+  mact_status s = check_params(params);
+  if (s != MACT_OK) return s;
+  if (params->out_mode != 0) return fail(MACT_E_INVALID, "mact_error_stats: out_mode must be 0");
+  HostImage hi;
+  if ((s = resolve_image(in, false, "mact_error_stats: in", &hi)) != MACT_OK) return s;
+  KCoef k;
+  const int deg = pack_coef(*params, &k);
+  const int gamma = params->xform == MACT_LAB ? hi.gamma : MACT_GAMMA_NONE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  ErrAcc* d_acc = nullptr;
+  if (hipMalloc(&d_acc, sizeof(ErrAcc)) != hipSuccess) return fail(MACT_E_NOMEM, "mact_error_stats: device allocation");
+  s = hip_check(hipMemsetAsync(d_acc, 0, sizeof(ErrAcc), st), "mact_error_stats: clear");
+  const int64_t per = images_per_launch(hi);
+  for (int64_t n0 = 0; n0 < hi.N && s == MACT_OK; n0 += per) {
+    const int64_t cnt = std::min(per, hi.N - n0);
+    const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
+    const KImage ks = kimage(hi, n0, cnt);
+    const dim3 grid(grid_256(n_px, 16)), blk(256);
+    if (deg == 5) hipLaunchKernelGGL(k_error<5>, grid, blk, 0, st, ks, n_px, k, gamma, d_acc);
+    else hipLaunchKernelGGL(k_error<7>, grid, blk, 0, st, ks, n_px, k, gamma, d_acc);
+    s = hip_check(hipGetLastError(), "mact_error_stats: launch");
+  }
+  ErrAcc h;
+  std::memset(&h, 0, sizeof h);
+  if (s == MACT_OK) s = hip_check(hipMemcpyAsync(&h, d_acc, sizeof h, hipMemcpyDeviceToHost, st), "mact_error_stats: copy");
+  if (s == MACT_OK) s = hip_check(hipStreamSynchronize(st), "mact_error_stats: synchronise");
+  (void)hipFree(d_acc);
+  if (s != MACT_OK) return s;
+  const int64_t count = hi.N * hi.W * hi.H;
+  double mx[4];
+  for (int c = 0; c < 4; ++c) std::memcpy(&mx[c], &h.max_bits[c], sizeof(double));
+  out->count = count;
+  out->mean = h.sum / (double)count;
+  out->max = mx[0];
+  for (int c = 0; c < 3; ++c) out->max_abs[c] = mx[c + 1];
+  return MACT_OK;
+}

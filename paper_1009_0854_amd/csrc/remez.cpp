@@ -33,6 +33,9 @@ double eval_fn(int fn, double x) {
     case MACT_FN_ACOS: return std::acos(x);
     case MACT_FN_ATAN: return std::atan(x);
     case MACT_FN_ATANC: return 0.5 * kPi - std::atan(x);
+    case MACT_FN_SIN: return std::sin(x);
+    case MACT_FN_COS: return std::cos(x);
+    case MACT_FN_ENC709: return 1.099 * std::pow(x, 0.45) - 0.099;
   }
   return NAN;
 }
@@ -42,6 +45,7 @@ bool domain_ok(int fn, double lo, double hi) {
     case MACT_FN_CBRT: return lo >= 0.0;
     case MACT_FN_ASIN2: return lo >= 0.0 && hi <= std::sqrt(2.0);
     case MACT_FN_ACOS: return lo >= -1.0 && hi <= 1.0;
+    case MACT_FN_ENC709: return lo > 0.0;
     default: return true;
   }
 }

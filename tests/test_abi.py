@@ -46,16 +46,18 @@ def test_every_declared_symbol_is_exported(M):
 def test_struct_layouts_match_the_header(M, tmp_path):
     from paper_1009_0854_amd import _abi
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mact.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mact.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
                    "sizeof(mact_approx), sizeof(mact_image), sizeof(mact_params), sizeof(mact_tune),"
                    "sizeof(mact_server_config), sizeof(mact_request), sizeof(mact_server_stats),"
-                   "offsetof(mact_approx, eps), offsetof(mact_image, gamma), offsetof(mact_server_config, params));return 0;}\n")
+                   "offsetof(mact_approx, eps), offsetof(mact_image, gamma), offsetof(mact_server_config, params),"
+                   "sizeof(mact_error), offsetof(mact_error, max_abs));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(_abi.Approx), ctypes.sizeof(_abi.Image), ctypes.sizeof(_abi.Params), ctypes.sizeof(_abi.Tune),
             ctypes.sizeof(_abi.ServerConfig), ctypes.sizeof(_abi.Request), ctypes.sizeof(_abi.ServerStats),
-            _abi.Approx.eps.offset, _abi.Image.gamma.offset, _abi.ServerConfig.params.offset]
+            _abi.Approx.eps.offset, _abi.Image.gamma.offset, _abi.ServerConfig.params.offset,
+            ctypes.sizeof(_abi.ErrorStats), _abi.ErrorStats.max_abs.offset]
     assert got == want
 
 
@@ -70,6 +72,8 @@ FITS = [
     (0, 4, 4, 0.008856, 1.0), (0, 2, 2, 0.008856, 1.0), (0, 3, 4, 0.008856, 1.0), (0, 5, 0, 0.0, 1.0),
     (1, 5, 0, 0.0, 1.0), (1, 3, 0, 0.0, 254 / 256), (2, 5, 0, 0.0, 1 / np.sqrt(2)), (3, 4, 0, 0.0, 0.5),
     (4, 5, 0, 0.0, 1.0), (5, 4, 0, 1 / 255, 1.0),
+    # the inverses' functions: sine and cosine, the BT.709 encoding power
+    (6, 7, 0, 0.0, np.pi / 2), (7, 7, 0, 0.0, np.pi / 2), (7, 7, 0, 0.0, 2 * np.pi / 3), (8, 4, 4, 0.018, 1.0),
 ]
 
 
@@ -77,7 +81,8 @@ FITS = [
 def test_mact_fit_agrees_with_oracle_remez(M, fn, n, m, lo, hi):
     from numpy.polynomial import polynomial as Pm
     from oracle import remez, tables as T
-    f = [T.f_cbrt, T.f_atan_sqrt3, T.f_asin2, T.f_acos, T.f_atan, T.f_atanc][fn]
+    f = [T.f_cbrt, T.f_atan_sqrt3, T.f_asin2, T.f_acos, T.f_atan, T.f_atanc, np.sin, np.cos,
+         lambda x: 1.099 * np.power(x, 0.45) - 0.099][fn]
     a = M.fit(fn, n, m, lo, hi)
     o = remez.remez(f, n, m, lo, hi)
     assert a.converged == 1
@@ -263,3 +268,28 @@ def test_fast_division_method():
         n = n[n < 2 ** 32]
         q = (((n * np.uint64(m)) >> np.uint64(32)) + n) >> np.uint64(s)
         np.testing.assert_array_equal(q, n // np.uint64(d))
+
+
+def test_inverse_and_error_stats_validation_without_gpu(M):
+    # every case is rejected before any launch
+    from paper_1009_0854_amd import _abi as A
+    L = M.lib()
+    i32, o32 = _img(0x1000, A.F32), _img(0x2000, A.F32)
+    p = M.inverse_params("sct")
+    assert p.f[0].fn == A.FN_SIN and p.f[1].fn == A.FN_COS and p.f[0].n == 7
+    assert M.inverse_params("hsi").f[0].fn == A.FN_COS and M.inverse_params("hsi").f[0].hi == pytest.approx(2 * np.pi / 3)
+    assert M.inverse_params("lab").f[0].fn == A.FN_ENC709 and M.inverse_params("lab").f[0].m == 4
+    assert L.mact_inverse(None, ctypes.byref(i32), ctypes.byref(o32), None) == A.E_INVALID
+    assert L.mact_inverse(ctypes.byref(p), ctypes.byref(_img(0x1000, A.U8)), ctypes.byref(o32), None) == A.E_UNSUPPORTED
+    bad = M.inverse_params("sct")
+    bad.f[0], bad.f[1] = bad.f[1], bad.f[0]  # cosine where the sine belongs
+    assert L.mact_inverse(ctypes.byref(bad), ctypes.byref(i32), ctypes.byref(o32), None) == A.E_INVALID
+    srgb = _img(0x2000, A.F32)
+    srgb.gamma = A.GAMMA_SRGB
+    assert L.mact_inverse(ctypes.byref(M.inverse_params("lab")), ctypes.byref(i32), ctypes.byref(srgb), None) == A.E_UNSUPPORTED
+    e = A.ErrorStats()
+    assert L.mact_error_stats(ctypes.byref(M.default_params(0)), ctypes.byref(i32), None, None) == A.E_INVALID
+    assert L.mact_error_stats(None, ctypes.byref(i32), ctypes.byref(e), None) == A.E_INVALID
+    dbg = M.default_params(0)
+    dbg.out_mode = 1
+    assert L.mact_error_stats(ctypes.byref(dbg), ctypes.byref(i32), ctypes.byref(e), None) == A.E_INVALID
