@@ -371,6 +371,12 @@ def main():
         forms["lab_f16_out"] = {"Mpx_s": n_px / h_ms / 1e3, "GBs": 9.0 * n_px / h_ms / 1e6, "ms": h_ms,
                                 "ms_median": h_med, "what": "same batch, float16 output: 9 bytes per pixel"}
         del y16
+        # float16 R'G'B' in (BT.709): the exact decoding power vs its minimax polynomial
+        x16 = (x.to(torch.float16) / 255.0).contiguous()
+        for tag, pp in (("exact", p_lab), ("minimax", M.default_params(0, decode=True))):
+            ms, _ = time_kernel(lambda: M.transform(x16, params=pp, out=y), a.steps)
+            forms["lab_f16_in_decode_%s" % tag] = {"Mpx_s": n_px / ms / 1e3, "GBs": 18.0 * n_px / ms / 1e6, "ms": ms}
+        del x16
         log("4K batch")
         forms["lab_32x4k"] = bench_4k(M, p_lab, a.steps)
         for name, xf in (("hsi", 1), ("sct", 2)):

@@ -69,7 +69,8 @@ enum {
   MACT_FN_SIN = 6,        /* sin(x): SCT -> RGB */
   MACT_FN_COS = 7,        /* cos(x): SCT -> RGB and HSI -> RGB */
   MACT_FN_ENC709 = 8,     /* 1.099 x^0.45 - 0.099: BT.709 encoding above 0.018, CIELAB -> R'G'B' */
-  MACT_FN_COUNT = 9
+  MACT_FN_DEC709 = 9,     /* ((x + 0.099) / 1.099)^(1/0.45): BT.709 decoding above 0.081, float inputs */
+  MACT_FN_COUNT = 10
 };
 
 #define MACT_MAX_DEGREE 7
@@ -105,7 +106,8 @@ mact_status mact_fit_ex(int32_t fn, int32_t n, int32_t m, double lo, double hi, 
    degree); arctan(sqrt 3 x) degree 5 on [0, 1]; 2 arcsin(y/sqrt 2) degree 5 on
    [0, 1/sqrt 2]; arccos degree 5 on [0, 0.5]; arctan and pi/2 - arctan degree 5
    on [0, 1] (the full range of G/R and R/G for float inputs); sine and cosine
-   degree 7 on [0, pi/2]; the BT.709 encoding (4,4) rational on [0.018, 1]. */
+   degree 7 on [0, pi/2]; the BT.709 encoding (4,4) rational on [0.018, 1]; the
+   BT.709 decoding degree 7 on [0.081, 1]. */
 mact_status mact_default_approx(int32_t fn, mact_approx* out);
 
 /* The coefficients printed in the paper: Table 1 (fn CBRT, m = 0, n = 2..5),
@@ -143,7 +145,11 @@ typedef struct mact_image {
 } mact_image;
 
 /* Which approximations a transform uses:
-     LAB: f[0] = cube root (polynomial or rational);
+     LAB: f[0] = cube root (polynomial or rational); optionally f[1] = the
+          BT.709 decoding (fn MACT_FN_DEC709, a polynomial of degree <= 7),
+          which then replaces the exact power for float inputs with gamma
+          MACT_GAMMA_BT709 (8-bit inputs use their exact 256-entry table);
+          f[1] with any other fn is ignored;
      HSI: f[0] = arctan(sqrt 3 x) (polynomial);
      SCT: f[0] = 2 arcsin(y/sqrt 2), f[1] = arccos, f[2] = arctan, f[3] = pi/2 - arctan
           (polynomials).

@@ -41,14 +41,27 @@ def mact_lab_f(t, p, q):
     return np.where(hi, horner(p, ts) / horner(q, ts), colour.LAB_K * t + colour.LAB_C)
 
 
-def mact_lab(rgb, p, q, gamma="bt709", debug=False):
+def mact_decode709(k, c_dec):
+    """BT.709 decoding with ((k + 0.099)/1.099)^(1/0.45) replaced by the
+    polynomial ``c_dec`` (fitted on [0.081, 1]): k/4.5 below 0.081."""
+    k = np.asarray(k, dtype=np.float64)
+    return np.where(k < 0.081, k / 4.5, horner(c_dec, k))
+
+
+def mact_lab(rgb, p, q, gamma="bt709", debug=False, decode=None):
     """RGB -> CIELAB with the cube root replaced by p/q (Sec. 3.2).
 
     Steps: inverse gamma (BT.709 by default), RGB -> XYZ, divide by the D65
     white, approximated f, then L*, a*, b*.  With ``debug`` the three values
-    f~(X/X0), f~(Y/Y0), f~(Z/Z0) are returned instead of L*a*b*.
+    f~(X/X0), f~(Y/Y0), f~(Z/Z0) are returned instead of L*a*b*.  With
+    ``decode`` (polynomial coefficients) and gamma 'bt709' the decoding power
+    is replaced as well.
     """
-    t = colour.lab_t(clamp01(rgb), gamma)
+    if decode is not None and gamma == "bt709":
+        lin = mact_decode709(clamp01(rgb), decode)
+        t = colour.rgb_to_xyz(lin) / colour.WHITE_D65
+    else:
+        t = colour.lab_t(clamp01(rgb), gamma)
     f = mact_lab_f(t, p, q)
     if debug:
         return f

@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmact.so"
 # status codes
 OK, E_INVALID, E_NOCONV, E_DEVICE, E_NOMEM, E_UNSUPPORTED, E_BUSY = 0, -1, -2, -3, -4, -5, -6
 # functions
-FN_CBRT, FN_ATAN_SQRT3, FN_ASIN2, FN_ACOS, FN_ATAN, FN_ATANC, FN_SIN, FN_COS, FN_ENC709 = range(9)
+FN_CBRT, FN_ATAN_SQRT3, FN_ASIN2, FN_ACOS, FN_ATAN, FN_ATANC, FN_SIN, FN_COS, FN_ENC709, FN_DEC709 = range(10)
 # transforms, element types, layouts, transfer functions, LUT methods
 LAB, HSI, SCT = 0, 1, 2
 U8, F16, F32 = 0, 1, 2

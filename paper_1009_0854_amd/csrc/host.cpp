@@ -91,6 +91,10 @@ mact_status check_params(const mact_params* p) {
     mact_status s = check_approx(p->f[i], p->xform == MACT_LAB, names[p->xform][i]);
     if (s != MACT_OK) return s;
   }
+  if (p->xform == MACT_LAB && p->f[1].fn == MACT_FN_DEC709) {
+    mact_status s = check_approx(p->f[1], false, "dec709");
+    if (s != MACT_OK) return s;
+  }
   return MACT_OK;
 }
 
@@ -149,7 +153,7 @@ const Default kDefaults[MACT_FN_COUNT] = {
     {MACT_FN_ASIN2, 5, 0, 0.0, kInvSqrt2}, {MACT_FN_ACOS, 5, 0, 0.0, 0.5},
     {MACT_FN_ATAN, 5, 0, 0.0, 1.0},        {MACT_FN_ATANC, 5, 0, 0.0, 1.0},
     {MACT_FN_SIN, 7, 0, 0.0, kPi / 2},     {MACT_FN_COS, 7, 0, 0.0, kPi / 2},
-    {MACT_FN_ENC709, 4, 4, 0.018, 1.0},
+    {MACT_FN_ENC709, 4, 4, 0.018, 1.0},    {MACT_FN_DEC709, 7, 0, 0.081, 1.0},
 };
 
 std::once_flag g_default_once[MACT_FN_COUNT];

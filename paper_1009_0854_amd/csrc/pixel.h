@@ -38,9 +38,11 @@ constexpr float kInv3 = static_cast<float>(1.0 / 3.0);
 // rule over zero leading coefficients is exact, so evaluating at a padded
 // degree gives the same bits as at the true degree.
 struct KCoef {
-  float p[4][8];  // numerators of f[0..3]
+  float p[4][8];  // numerators of f[0..3]; LAB with `decode`: p[1] is the BT.709 decoding polynomial
   float q[8];     // denominator of f[0] (LAB); {1, 0, ...} otherwise
   int32_t xform, out_mode;
+  int32_t decode;  // LAB: float inputs decode BT.709 with the polynomial p[1] (degree <= 7)
+  int32_t pad;
 };
 
 // n / d for 32-bit n and a fixed d >= 1: q = (umulhi(n, m) + n) >> s with the
@@ -182,9 +184,13 @@ __device__ __forceinline__ void sct_px(const KCoef& k, float R, float G, float B
 
 __device__ __forceinline__ float clamp01(float v) { return __builtin_fminf(__builtin_fmaxf(v, 0.0f), 1.0f); }
 
-// Inverse transfer function of a float input already clamped to [0, 1].
-__device__ __forceinline__ float lin_float(float v, int gamma) {
-  if (gamma == MACT_GAMMA_BT709) return v < 0.081f ? v / 4.5f : __builtin_powf((v + 0.099f) / 1.099f, 1.0f / 0.45f);
+// Inverse transfer function of a float input already clamped to [0, 1].  BT.709
+// above 0.081: the exact power, or (k.decode) its minimax polynomial p[1].
+__device__ __forceinline__ float lin_float(const KCoef& k, float v, int gamma) {
+  if (gamma == MACT_GAMMA_BT709) {
+    if (v < 0.081f) return v / 4.5f;
+    return k.decode ? horner<7>(k.p[1], v) : __builtin_powf((v + 0.099f) / 1.099f, 1.0f / 0.45f);
+  }
   if (gamma == MACT_GAMMA_SRGB) return v <= 0.04045f ? v / 12.92f : __builtin_powf((v + 0.055f) / 1.055f, 2.4f);
   return v;
 }
@@ -242,7 +248,7 @@ __device__ __forceinline__ void eval_px(const KCoef& k, bool u8, int gamma, cons
   if (k.xform == MACT_LAB) {
     float l[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) l[c] = u8 ? gtab[(int)v[c]] : lin_float(v[c], gamma);
+    for (int c = 0; c < 3; ++c) l[c] = u8 ? gtab[(int)v[c]] : lin_float(k, v[c], gamma);
     lab_px<DEG>(k, l[0], l[1], l[2], o);
   } else if (k.xform == MACT_HSI) {
     hsi_px<DEG>(k, v[0], v[1], v[2], u8 ? kInv765 : kInv3, o);
@@ -285,7 +291,7 @@ __device__ __forceinline__ void px4_f16(const KCoef& k, int gamma, uint3 wa, uin
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const float r = half_of(wa, wb, 3 * j), g = half_of(wa, wb, 3 * j + 1), b = half_of(wa, wb, 3 * j + 2);
-    if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(r, gamma), lin_float(g, gamma), lin_float(b, gamma), o + 3 * j);
+    if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(k, r, gamma), lin_float(k, g, gamma), lin_float(k, b, gamma), o + 3 * j);
     else if (XF == MACT_HSI) hsi_px<DEG>(k, r, g, b, kInv3, o + 3 * j);
     else sct_px<DEG>(k, r, g, b, 1.0f, o + 3 * j);
   }

@@ -36,6 +36,7 @@ double eval_fn(int fn, double x) {
     case MACT_FN_SIN: return std::sin(x);
     case MACT_FN_COS: return std::cos(x);
     case MACT_FN_ENC709: return 1.099 * std::pow(x, 0.45) - 0.099;
+    case MACT_FN_DEC709: return std::pow((x + 0.099) / 1.099, 1.0 / 0.45);
   }
   return NAN;
 }
@@ -46,6 +47,7 @@ bool domain_ok(int fn, double lo, double hi) {
     case MACT_FN_ASIN2: return lo >= 0.0 && hi <= std::sqrt(2.0);
     case MACT_FN_ACOS: return lo >= -1.0 && hi <= 1.0;
     case MACT_FN_ENC709: return lo > 0.0;
+    case MACT_FN_DEC709: return lo > -0.099;
     default: return true;
   }
 }

@@ -121,6 +121,11 @@ int pack_coef(const mact_params& p, KCoef* k, int* exact) {
   } else {
     k->q[0] = 1.0f;
   }
+  if (p.xform == MACT_LAB && p.f[1].fn == MACT_FN_DEC709) {
+    // the decoding polynomial has its own fixed evaluation degree (7): it does not raise `deg`
+    for (int j = 0; j <= p.f[1].n; ++j) k->p[1][j] = (float)p.f[1].p[j];
+    k->decode = 1;
+  }
   if (exact) *exact = deg;
   return deg <= 5 ? 5 : 7;
 }
@@ -243,7 +248,7 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
       const __half* h = static_cast<const __half*>(in);
       const float r = clamp01(__half2float(h[3 * p])), g = clamp01(__half2float(h[3 * p + 1])),
                   b = clamp01(__half2float(h[3 * p + 2]));
-      if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(r, gamma), lin_float(g, gamma), lin_float(b, gamma), o);
+      if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(k, r, gamma), lin_float(k, g, gamma), lin_float(k, b, gamma), o);
       else if (XF == MACT_HSI) hsi_px<DEG>(k, r, g, b, kInv3, o);
       else sct_px<DEG>(k, r, g, b, 1.0f, o);
     }
@@ -292,7 +297,7 @@ __global__ __launch_bounds__(256) void k_chw4(const void* __restrict__ in, float
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       float r[3];
-      if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(v[0][j], gamma), lin_float(v[1][j], gamma), lin_float(v[2][j], gamma), r);
+      if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(k, v[0][j], gamma), lin_float(k, v[1][j], gamma), lin_float(k, v[2][j], gamma), r);
       else if (XF == MACT_HSI) hsi_px<DEG>(k, v[0][j], v[1][j], v[2][j], kInv3, r);
       else sct_px<DEG>(k, v[0][j], v[1][j], v[2][j], 1.0f, r);
       o[0][j] = r[0]; o[1][j] = r[1]; o[2][j] = r[2];

@@ -74,6 +74,8 @@ FITS = [
     (4, 5, 0, 0.0, 1.0), (5, 4, 0, 1 / 255, 1.0),
     # the inverses' functions: sine and cosine, the BT.709 encoding power
     (6, 7, 0, 0.0, np.pi / 2), (7, 7, 0, 0.0, np.pi / 2), (7, 7, 0, 0.0, 2 * np.pi / 3), (8, 4, 4, 0.018, 1.0),
+    # the BT.709 decoding power, for float inputs
+    (9, 7, 0, 0.081, 1.0),
 ]
 
 
@@ -82,7 +84,7 @@ def test_mact_fit_agrees_with_oracle_remez(M, fn, n, m, lo, hi):
     from numpy.polynomial import polynomial as Pm
     from oracle import remez, tables as T
     f = [T.f_cbrt, T.f_atan_sqrt3, T.f_asin2, T.f_acos, T.f_atan, T.f_atanc, np.sin, np.cos,
-         lambda x: 1.099 * np.power(x, 0.45) - 0.099][fn]
+         lambda x: 1.099 * np.power(x, 0.45) - 0.099, lambda x: np.power((x + 0.099) / 1.099, 1 / 0.45)][fn]
     a = M.fit(fn, n, m, lo, hi)
     o = remez.remez(f, n, m, lo, hi)
     assert a.converged == 1
@@ -107,7 +109,7 @@ def test_mact_fit_nonconvergence_and_invalid(M):
     assert e.value.status == _abi.E_NOCONV
     L = M.lib()
     out = _abi.Approx()
-    for args in [(0, 8, 0, 0.0, 1.0), (0, 2, 2, 1.0, 0.5), (3, 3, 0, -2.0, 0.5), (0, 2, 2, -1.0, 1.0), (9, 2, 0, 0.0, 1.0)]:
+    for args in [(0, 8, 0, 0.0, 1.0), (0, 2, 2, 1.0, 0.5), (3, 3, 0, -2.0, 0.5), (0, 2, 2, -1.0, 1.0), (_abi.FN_DEC709 + 1, 2, 0, 0.0, 1.0)]:
         assert L.mact_fit(*args, ctypes.byref(out)) == _abi.E_INVALID, args
     assert L.mact_fit(0, 2, 2, 0.1, 1.0, None) == _abi.E_INVALID
     assert L.mact_last_error()

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import mact as OM
 from tests import parity as P
 from tests.cubepool import cube_map_shared
 
@@ -221,3 +222,50 @@ def test_batch_spanning_two_launches(M):
     P.assert_parity(0, gv, P.oracle(0, xs / 255.0, P.coeffs(p)))
     del x, y
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+@pytest.mark.parametrize("layout", ["hwc", "chw", "strided"])
+def test_lab_float_input_with_minimax_decoding(M, dtype, layout):
+    # BT.709-encoded float inputs with the decoding power replaced by its minimax polynomial
+    # (on the fast HWC / CHW kernels and the general one) against the oracle with the same
+    # float32 coefficients; inputs within 1e-6 of the 0.081 branch point may take either branch
+    g = synth.rng(70)
+    x = g.random((2, 45, 67, 3)) * 1.1 - 0.05
+    x[0, 0, :5] = [[0.081, 0.5, 1.0], [0.0, 0.0, 0.0], [1.0, 1.0, 1.0], [0.0809, 0.0811, 0.2], [1.2, -0.1, 0.5]]
+    npdt = np.float16 if dtype == "f16" else np.float32
+    xq = x.astype(npdt)
+    p = M.default_params(0, decode=True)
+    t = torch.from_numpy(xq).cuda()
+    if layout == "chw":
+        y = M.transform(t.permute(0, 3, 1, 2).contiguous(), params=p, layout="chw", out_layout="hwc")
+    elif layout == "strided":
+        big = torch.zeros((2, 45, 70, 3), dtype=t.dtype, device="cuda")
+        big[:, :, :67] = t
+        y = M.transform(big[:, :, :67], params=p)
+    else:
+        y = M.transform(t, params=p)
+    torch.cuda.synchronize()
+    gpu = y.reshape(-1, 3).cpu().numpy().astype(np.float64)
+    xs = xq.astype(np.float64).reshape(-1, 3)
+    co = P.coeffs(p)
+    dec = np.float32(p.f[1].p_list).astype(np.float64)
+    ref = OM.mact_lab(xs, co["p"], co["q"], decode=dec)
+    err = np.abs(gpu - ref) / P.SCALE[0]
+    near = np.any(np.abs(np.clip(xs, 0, 1) - 0.081) <= 1e-6, axis=1)
+    assert err[~near].max() <= P.REL
+    # and it differs from the exact-power path (the approximation is in use)
+    exact = M.transform(t, params=M.default_params(0)).reshape(-1, 3).cpu().numpy()
+    assert np.abs(exact - gpu).max() > 0
+
+
+def test_batched_decoding_equals_plain(M):
+    # the decoding polynomial travels in the batched form's coefficient table
+    g = torch.Generator(device="cuda").manual_seed(71)
+    ins = [torch.rand((h, w, 3), device="cuda", generator=g).half() for (h, w) in [(33, 40), (64, 64), (17, 300)]]
+    outs = [torch.empty(i.shape, dtype=torch.float32, device="cuda") for i in ins]
+    p = M.default_params(0, decode=True)
+    M.batch_run([p] * 3, ins, outs, gammas=["bt709"] * 3)
+    torch.cuda.synchronize()
+    for i, o in zip(ins, outs):
+        assert torch.equal(o, M.transform(i, params=p))

@@ -117,3 +117,21 @@ def test_mact_inverse_approximations_are_not_exact(cube, fits):
     enc, sin, cos, cos_h = fits
     assert np.abs(OM.mact_lab_inverse(C.rgb_to_lab(cube), enc.p, enc.q) - cube).max() > 0.3 * enc.eps
     assert np.abs(OM.mact_sct_inverse(C.rgb_to_sct(cube), sin.p, cos.p) - cube).max() > 0.3 * sin.eps
+
+
+def test_mact_decode709_within_its_error(fits):
+    # the decoding polynomial replaces the power above 0.081 only, within its eps there
+    dec = R.remez(lambda x: ((x + 0.099) / 1.099) ** (1 / 0.45), 7, 0, 0.081, 1.0)
+    k = np.linspace(0.0, 1.0, 100001)
+    d = np.abs(OM.mact_decode709(k, dec.p) - C.inverse_gamma(k))
+    assert d.max() <= dec.eps * (1 + 1e-6)
+    assert np.all(d[k < 0.081] == 0.0)
+    # CIELAB through the approximated decoding: L* moves by at most 116 * f'(t) * |dt|, f' <= 7.787,
+    # |dt| <= eps (Y is a convex combination of the channels); checked on the cube against the bound
+    cube = synth.cube_u8().reshape(-1, 3)[::5] / 255.0
+    from oracle import tables as T
+    cb = R.remez(T.f_cbrt, 4, 4, *T.T2_INTERVAL)
+    a = OM.mact_lab(cube, cb.p, cb.q, decode=dec.p)
+    b = OM.mact_lab(cube, cb.p, cb.q)
+    assert np.abs(a[:, 0] - b[:, 0]).max() <= 116 * 7.787 * dec.eps * 1.01
+    assert np.abs(a - b).max() > 0
