@@ -76,6 +76,31 @@ def lab_t(rgb, gamma="bt709"):
     return rgb_to_xyz(inverse_gamma(rgb, gamma)) / WHITE_D65
 
 
+def xyz_to_luv(xyz):
+    """CIEXYZ -> CIE 1976 L*u*v* relative to D65, with the paper's L* (the
+    same f as CIELAB, so L* is CIELAB's L*): u' = 4X / (X + 15Y + 3Z),
+    v' = 9Y / (X + 15Y + 3Z), u* = 13 L* (u' - u'n), v* = 13 L* (v' - v'n)
+    with u'n, v'n those of the white.  Where X + 15Y + 3Z = 0 (black)
+    u* = v* = 0.  (CIELUV is the extension the paper names in Sec. 4.)"""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    X, Y, Z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
+    Xn, Yn, Zn = WHITE_D65
+    dn = Xn + 15.0 * Yn + 3.0 * Zn
+    un, vn = 4.0 * Xn / dn, 9.0 * Yn / dn
+    d = X + 15.0 * Y + 3.0 * Z
+    pos = d > 0
+    ds = np.where(pos, d, 1.0)
+    L = 116.0 * lab_f(Y / Yn) - 16.0
+    u = np.where(pos, 13.0 * L * (4.0 * X / ds - un), 0.0)
+    v = np.where(pos, 13.0 * L * (9.0 * Y / ds - vn), 0.0)
+    return np.stack([L, u, v], axis=-1)
+
+
+def rgb_to_luv(rgb, gamma="bt709"):
+    """R'G'B' (or linear RGB with gamma='none') in [0,1] -> L*u*v*."""
+    return xyz_to_luv(rgb_to_xyz(inverse_gamma(rgb, gamma)))
+
+
 def rgb_to_hsi(rgb):
     """RGB -> HSI by the arccos definition (Sec. 3.3.1).
 

@@ -69,6 +69,27 @@ def mact_lab(rgb, p, q, gamma="bt709", debug=False, decode=None):
     return np.stack([116.0 * fy - 16.0, 500.0 * (fx - fy), 200.0 * (fy - fz)], axis=-1)
 
 
+def mact_luv(rgb, p, q, gamma="bt709", decode=None):
+    """RGB -> CIE 1976 L*u*v* with the cube root of L* replaced by p/q (the
+    CIELAB nonlinearity, Sec. 3.2.2); u', v' by their exact divisions."""
+    if decode is not None and gamma == "bt709":
+        lin = mact_decode709(clamp01(rgb), decode)
+    else:
+        lin = colour.inverse_gamma(clamp01(rgb), gamma)
+    xyz = colour.rgb_to_xyz(lin)
+    X, Y, Z = xyz[..., 0], xyz[..., 1], xyz[..., 2]
+    Xn, Yn, Zn = colour.WHITE_D65
+    dn = Xn + 15.0 * Yn + 3.0 * Zn
+    un, vn = 4.0 * Xn / dn, 9.0 * Yn / dn
+    d = X + 15.0 * Y + 3.0 * Z
+    pos = d > 0
+    ds = np.where(pos, d, 1.0)
+    L = 116.0 * mact_lab_f(Y / Yn, p, q) - 16.0
+    u = np.where(pos, 13.0 * L * (4.0 * X / ds - un), 0.0)
+    v = np.where(pos, 13.0 * L * (9.0 * Y / ds - vn), 0.0)
+    return np.stack([L, u, v], axis=-1)
+
+
 def odd_poly(c, x):
     """P approximates an odd function on [0, 1]; negative arguments use
     arctan(-x) = -arctan(x) (Sec. 3.3.2): -P(-x) for x < 0, P(x) otherwise."""
