@@ -125,7 +125,7 @@ def bench_inverse(M, x, y, n_px, steps):
         out["%s_inverse" % name] = {"Mpx_s": n_px / ms / 1e3, "GBs": 24.0 * n_px / ms / 1e6, "ms": ms}
     del back
     cube = torch.from_numpy(synth.cube_u8()).cuda()
-    for name in ("lab", "hsi", "sct"):
+    for name in ("lab", "hsi", "sct", "luv"):
         M.error_stats(cube, xform=name)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -379,7 +379,7 @@ def main():
         del x16
         log("4K batch")
         forms["lab_32x4k"] = bench_4k(M, p_lab, a.steps)
-        for name, xf in (("hsi", 1), ("sct", 2)):
+        for name, xf in (("hsi", 1), ("sct", 2), ("luv", 3)):
             p = M.default_params(xf)
             ms, _ = time_kernel(lambda: M.transform(x, params=p, out=y), a.steps)
             forms[name] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}

@@ -119,7 +119,7 @@ mact_status mact_paper_approx(int32_t fn, int32_t n, int32_t m, mact_approx* out
 
 /* ------------------------------------------------------------ images */
 
-enum { MACT_LAB = 0, MACT_HSI = 1, MACT_SCT = 2 };   /* transforms */
+enum { MACT_LAB = 0, MACT_HSI = 1, MACT_SCT = 2, MACT_LUV = 3 };   /* transforms; CIELUV is the extension named in Sec. 4 */
 enum { MACT_U8 = 0, MACT_F16 = 1, MACT_F32 = 2 };    /* element types */
 enum { MACT_HWC = 0, MACT_CHW = 1 };                 /* layouts */
 enum {                                              /* input transfer function (LAB) */
@@ -133,7 +133,7 @@ enum {                                              /* input transfer function (
      CHW: data + (n*batch_stride + c*plane_stride + y*row_stride + x) * elem_size
    Strides are in elements; 0 selects the packed value (HWC row_stride = 3 W;
    CHW row_stride = W, plane_stride = H row_stride; batch_stride = H row_stride
-   (HWC) or 3 plane_stride (CHW)).  `gamma` applies to LAB inputs only. */
+   (HWC) or 3 plane_stride (CHW)).  `gamma` applies to LAB and LUV inputs only. */
 typedef struct mact_image {
   void* data;
   int32_t dtype, layout;
@@ -152,7 +152,8 @@ typedef struct mact_image {
           f[1] with any other fn is ignored;
      HSI: f[0] = arctan(sqrt 3 x) (polynomial);
      SCT: f[0] = 2 arcsin(y/sqrt 2), f[1] = arccos, f[2] = arctan, f[3] = pi/2 - arctan
-          (polynomials).
+          (polynomials);
+     LUV: as LAB (f[0] = cube root, optional f[1] = the BT.709 decoding).
    out_mode 0: transform values.  out_mode 1 (LAB only): the three values of
    the approximated nonlinearity f~(X/X0), f~(Y/Y0), f~(Z/Z0) instead of L*a*b*. */
 typedef struct mact_params {
@@ -179,6 +180,12 @@ mact_status mact_params_default(int32_t xform, mact_params* p);
           (B/L >= 0.5), else P_acos(B/L); angle B = P_atan(G/R) if G < R,
           P_atanc(R/G) if 0 < R <= G, pi/2 if R = 0 < G, 0 if R = G = 0;
           black gives (0, 0, 0).  Radians.
+     LUV: CIE 1976 L*u*v* (Sec. 4 names it as the next transform): linear RGB
+          as for LAB, X, Y, Z by the BT.709 matrix, L* = 116 f~(Y) - 16 with
+          CIELAB's approximated nonlinearity (Y / Yn, Yn = 1), u' = 4X / D,
+          v' = 9Y / D with D = X + 15Y + 3Z, u* = 13 L* (u' - u'n),
+          v* = 13 L* (v' - v'n) with the D65 white's u'n, v'n; D = 0 (black)
+          gives u* = v* = 0.
    in: MACT_U8 / MACT_F16 / MACT_F32, HWC or CHW.  out: MACT_F32 or MACT_F16,
    HWC or CHW, same width, height and batch as `in`.  Evaluation is float32 with
    explicit fused multiply-adds; the result does not depend on the launch
@@ -229,14 +236,14 @@ mact_status mact_inverse_params_default(int32_t xform, mact_params* p);
    in: MACT_F32 or MACT_F16, any layout; out: MACT_F32 or MACT_F16, any layout,
    same geometry.  float32 arithmetic.  Errors: MACT_E_INVALID (NULL, shapes,
    approximations of the wrong function or degree); MACT_E_UNSUPPORTED (8-bit
-   in, sRGB encoding); MACT_E_DEVICE. */
+   in, sRGB encoding, MACT_LUV); MACT_E_DEVICE. */
 mact_status mact_inverse(const mact_params* params, const mact_image* in, const mact_image* out,
                          void* hip_stream);
 
 /* Accuracy of a forward transform over an image, computed on the device. */
 typedef struct mact_error {
   int64_t count;       /* pixels */
-  double mean, max;    /* of the metric: Delta E*ab (LAB, Sec. 3.2.1), D_HSI (HSI, Sec. 3.3.1),
+  double mean, max;    /* of the metric: Delta E*ab (LAB, Sec. 3.2.1), Delta E*uv (LUV), D_HSI (HSI, Sec. 3.3.1),
                           or the SCT measure of Sec. 3.4.1 (both triples back to RGB, no
                           clipping, then CIELAB with BT.709, then Delta E*ab) */
   double max_abs[3];   /* largest |MACT - exact| per channel (HSI hue wrapped to [0, pi]) */

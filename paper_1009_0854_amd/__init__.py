@@ -62,13 +62,13 @@ def paper_approx(fn, n, m=0):
 
 
 def default_params(xform, decode=False):
-    """mact_params_default; with decode=True (CIELAB) float inputs decode
+    """mact_params_default; with decode=True (CIELAB, CIELUV) float inputs decode
     BT.709 with the default minimax polynomial instead of the exact power."""
     p = Params()
     A.check(lib().mact_params_default(_xf(xform), ctypes.byref(p)))
     if decode:
-        if p.xform != A.LAB:
-            raise ValueError("decode applies to CIELAB only")
+        if p.xform not in (A.LAB, A.LUV):
+            raise ValueError("decode applies to CIELAB and CIELUV only")
         p.f[1] = default_approx(A.FN_DEC709)
     return p
 

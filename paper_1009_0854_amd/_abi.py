@@ -14,13 +14,13 @@ OK, E_INVALID, E_NOCONV, E_DEVICE, E_NOMEM, E_UNSUPPORTED, E_BUSY = 0, -1, -2, -
 # functions
 FN_CBRT, FN_ATAN_SQRT3, FN_ASIN2, FN_ACOS, FN_ATAN, FN_ATANC, FN_SIN, FN_COS, FN_ENC709, FN_DEC709 = range(10)
 # transforms, element types, layouts, transfer functions, LUT methods
-LAB, HSI, SCT = 0, 1, 2
+LAB, HSI, SCT, LUV = 0, 1, 2, 3
 U8, F16, F32 = 0, 1, 2
 HWC, CHW = 0, 1
 GAMMA_BT709, GAMMA_SRGB, GAMMA_NONE = 0, 1, 2
 TRILINEAR, PRISM, PYRAMIDAL, TETRAHEDRAL = 0, 1, 2, 3
 
-XFORMS = {"lab": LAB, "hsi": HSI, "sct": SCT}
+XFORMS = {"lab": LAB, "hsi": HSI, "sct": SCT, "luv": LUV}
 GAMMAS = {"bt709": GAMMA_BT709, "srgb": GAMMA_SRGB, "none": GAMMA_NONE}
 METHODS = {"trilinear": TRILINEAR, "prism": PRISM, "pyramidal": PYRAMIDAL, "tetrahedral": TETRAHEDRAL}
 

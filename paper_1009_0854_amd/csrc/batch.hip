@@ -70,11 +70,13 @@ __global__ __launch_bounds__(1024) void k_batch(const BDesc* __restrict__ descs,
         if (d.fast == 1) {  // 8-bit: 12 bytes (4 pixels) per lane
           const uint3 w = win[(cp >> 2) + lane];
           if (k.xform == MACT_LAB) px4_u8<MACT_LAB, DEG>(k, g, w, o);
+          else if (k.xform == MACT_LUV) px4_u8<MACT_LUV, DEG>(k, g, w, o);
           else if (k.xform == MACT_HSI) px4_u8<MACT_HSI, DEG>(k, g, w, o);
           else px4_u8<MACT_SCT, DEG>(k, g, w, o);
         } else {  // float16: 24 bytes per lane
           const uint3 wa = win[(cp >> 1) + 2 * lane], wb = win[(cp >> 1) + 2 * lane + 1];
           if (k.xform == MACT_LAB) px4_f16<MACT_LAB, DEG>(k, d.gamma, wa, wb, o);
+          else if (k.xform == MACT_LUV) px4_f16<MACT_LUV, DEG>(k, d.gamma, wa, wb, o);
           else if (k.xform == MACT_HSI) px4_f16<MACT_HSI, DEG>(k, d.gamma, wa, wb, o);
           else px4_f16<MACT_SCT, DEG>(k, d.gamma, wa, wb, o);
         }
@@ -115,7 +117,7 @@ mact_status make_batch_descs(const mact_params& p, const mact_image* in, const m
   if ((s = check_same_shape(hi, ho, what)) != MACT_OK) return s;
   KCoef k;
   *deg = pack_coef(p, &k);
-  const int gamma = p.xform == MACT_LAB ? hi.gamma : MACT_GAMMA_NONE;
+  const int gamma = uses_gamma(p.xform) ? hi.gamma : MACT_GAMMA_NONE;
   // packed 8-bit (1) or float16 (2) HWC in, packed float32 HWC out: the 4-pixel LDS path
   const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16) && hi.layout == MACT_HWC && hi.packed &&
                     ho.dtype == MACT_F32 && ho.layout == MACT_HWC && ho.packed;

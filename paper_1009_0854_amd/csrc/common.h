@@ -34,6 +34,9 @@ constexpr double kLabK = 7.787;      // slope of its linear segment
 constexpr double kLabC = 16.0 / 116.0;
 constexpr double kPi = 3.14159265358979323846;
 
+// Transforms whose input goes through the transfer function (LAB, LUV).
+inline bool uses_gamma(int xform) { return xform == MACT_LAB || xform == MACT_LUV; }
+
 // Host FP64 exact transforms (used to pack LUTs).  rgb in [0, 1].
 double inverse_gamma(double k, int gamma);
 void exact_lab(const double rgb[3], int gamma, double out[3]);

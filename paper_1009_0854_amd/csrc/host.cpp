@@ -82,16 +82,16 @@ mact_status check_approx(const mact_approx& a, bool rational_ok, const char* wha
 
 mact_status check_params(const mact_params* p) {
   if (!p) return fail(MACT_E_INVALID, "params is NULL");
-  if (p->xform < MACT_LAB || p->xform > MACT_SCT) return fail(MACT_E_INVALID, "unknown transform %d", p->xform);
+  if (p->xform < MACT_LAB || p->xform > MACT_LUV) return fail(MACT_E_INVALID, "unknown transform %d", p->xform);
   if (p->out_mode != 0 && p->out_mode != 1) return fail(MACT_E_INVALID, "out_mode %d not 0 or 1", p->out_mode);
   if (p->out_mode == 1 && p->xform != MACT_LAB) return fail(MACT_E_INVALID, "out_mode 1 is for MACT_LAB only");
   const int nf = p->xform == MACT_SCT ? 4 : 1;
-  static const char* names[3][4] = {{"cbrt"}, {"atan_sqrt3"}, {"asin2", "acos", "atan", "atanc"}};
+  static const char* names[4][4] = {{"cbrt"}, {"atan_sqrt3"}, {"asin2", "acos", "atan", "atanc"}, {"cbrt"}};
   for (int i = 0; i < nf; ++i) {
-    mact_status s = check_approx(p->f[i], p->xform == MACT_LAB, names[p->xform][i]);
+    mact_status s = check_approx(p->f[i], uses_gamma(p->xform), names[p->xform][i]);
     if (s != MACT_OK) return s;
   }
-  if (p->xform == MACT_LAB && p->f[1].fn == MACT_FN_DEC709) {
+  if (uses_gamma(p->xform) && p->f[1].fn == MACT_FN_DEC709) {
     mact_status s = check_approx(p->f[1], false, "dec709");
     if (s != MACT_OK) return s;
   }
@@ -220,10 +220,11 @@ extern "C" mact_status mact_default_approx(int32_t fn, mact_approx* out) {
 extern "C" mact_status mact_params_default(int32_t xform, mact_params* p) {
   clear_error();
   if (!p) return fail(MACT_E_INVALID, "mact_params_default: p is NULL");
-  if (xform < MACT_LAB || xform > MACT_SCT) return fail(MACT_E_INVALID, "unknown transform %d", xform);
+  if (xform < MACT_LAB || xform > MACT_LUV) return fail(MACT_E_INVALID, "unknown transform %d", xform);
   std::memset(p, 0, sizeof *p);
   p->xform = xform;
-  static const int fns[3][4] = {{MACT_FN_CBRT}, {MACT_FN_ATAN_SQRT3}, {MACT_FN_ASIN2, MACT_FN_ACOS, MACT_FN_ATAN, MACT_FN_ATANC}};
+  static const int fns[4][4] = {{MACT_FN_CBRT}, {MACT_FN_ATAN_SQRT3}, {MACT_FN_ASIN2, MACT_FN_ACOS, MACT_FN_ATAN, MACT_FN_ATANC},
+                                {MACT_FN_CBRT}};
   const int nf = xform == MACT_SCT ? 4 : 1;
   for (int i = 0; i < nf; ++i) {
     mact_status s = mact_default_approx(fns[xform][i], &p->f[i]);

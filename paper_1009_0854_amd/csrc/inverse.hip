@@ -13,8 +13,8 @@
 // transform (the same per-pixel code as mact_transform, float32) and through
 // the exact transform in float64; the paper's metric of the pair (Delta E*ab,
 // D_HSI, or the SCT measure: both triples back to RGB, then to CIELAB, then
-// Delta E*ab) is reduced to its mean and maximum, with the largest per-channel
-// differences, in one pass.
+// Delta E*ab; Delta E*uv for CIELUV) is reduced to its mean and maximum, with
+// the largest per-channel differences, in one pass.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -147,6 +147,19 @@ __device__ __forceinline__ void dev_lab(const double rgb[3], int gamma, double o
   out[2] = 200.0 * (f[1] - f[2]);
 }
 
+__device__ __forceinline__ void dev_luv(const double rgb[3], int gamma, double out[3]) {
+  double lin[3], xyz[3];
+  for (int c = 0; c < 3; ++c) lin[c] = dev_inverse_gamma(rgb[c], gamma);
+  for (int r = 0; r < 3; ++r) xyz[r] = kM[r][0] * lin[0] + kM[r][1] * lin[1] + kM[r][2] * lin[2];
+  const double fy = xyz[1] > kLabT0 ? cbrt(xyz[1]) : kLabK * xyz[1] + kLabC;
+  const double L = 116.0 * fy - 16.0;
+  const double d = xyz[0] + 15.0 * xyz[1] + 3.0 * xyz[2];
+  const double dn = kWhite[0] + 15.0 * kWhite[1] + 3.0 * kWhite[2];
+  out[0] = L;
+  out[1] = d > 0.0 ? 13.0 * L * (4.0 * xyz[0] / d - 4.0 * kWhite[0] / dn) : 0.0;
+  out[2] = d > 0.0 ? 13.0 * L * (9.0 * xyz[1] / d - 9.0 * kWhite[1] / dn) : 0.0;
+}
+
 __device__ __forceinline__ void dev_hsi(const double rgb[3], double out[3]) {
   // Kender's form with the exact arctan (Sec. 3.3.1); H = 0 where undefined
   const double R = rgb[0], G = rgb[1], B = rgb[2];
@@ -220,8 +233,9 @@ __global__ __launch_bounds__(256) void k_error(KImage src, uint32_t n_px, KCoef 
     const double rgb[3] = {v[0] * scale, v[1] * scale, v[2] * scale};  // raw values, [0, 1] scale
     const double m[3] = {o[0], o[1], o[2]};
     double ex[3], e, d[3];
-    if (k.xform == MACT_LAB) {
-      dev_lab(rgb, gamma, ex);
+    if (k.xform == MACT_LAB || k.xform == MACT_LUV) {
+      if (k.xform == MACT_LAB) dev_lab(rgb, gamma, ex);
+      else dev_luv(rgb, gamma, ex);
       e = dev_delta_e(m, ex);
       for (int c = 0; c < 3; ++c) d[c] = fabs(m[c] - ex[c]);
     } else if (k.xform == MACT_HSI) {
@@ -351,6 +365,7 @@ extern "C" mact_status mact_inverse(const mact_params* params, const mact_image*
   if ((s = check_same_shape(hi, ho, "mact_inverse: out")) != MACT_OK) return s;
   if (hi.dtype == MACT_U8) return fail(MACT_E_UNSUPPORTED, "mact_inverse: in must be MACT_F32 or MACT_F16");
   if (!params) return fail(MACT_E_INVALID, "mact_inverse: params is NULL");
+  if (params->xform == MACT_LUV) return fail(MACT_E_UNSUPPORTED, "mact_inverse: no inverse for MACT_LUV");
   int gamma = MACT_GAMMA_NONE;
   if (params->xform == MACT_LAB) {
     gamma = ho.gamma;
@@ -386,7 +401,7 @@ extern "C" mact_status mact_error_stats(const mact_params* params, const mact_im
   if ((s = resolve_image(in, false, "mact_error_stats: in", &hi)) != MACT_OK) return s;
   KCoef k;
   const int deg = pack_coef(*params, &k);
-  const int gamma = params->xform == MACT_LAB ? hi.gamma : MACT_GAMMA_NONE;
+  const int gamma = uses_gamma(params->xform) ? hi.gamma : MACT_GAMMA_NONE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   ErrAcc* d_acc = nullptr;
   if (hipMalloc(&d_acc, sizeof(ErrAcc)) != hipSuccess) return fail(MACT_E_NOMEM, "mact_error_stats: device allocation");

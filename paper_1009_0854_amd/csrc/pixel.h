@@ -31,6 +31,15 @@ constexpr float kTwoPif = static_cast<float>(2.0 * kPi);
 constexpr float kInv255 = static_cast<float>(1.0 / 255.0);
 constexpr float kInv765 = static_cast<float>(1.0 / 765.0);
 constexpr float kInv3 = static_cast<float>(1.0 / 3.0);
+// BT.709 matrix rows (linear RGB -> XYZ) and the white's u', v' for CIELUV.
+#define MF(r, c) static_cast<float>(kM[r][c])
+constexpr float kM00 = MF(0, 0), kM01 = MF(0, 1), kM02 = MF(0, 2);
+constexpr float kM10 = MF(1, 0), kM11 = MF(1, 1), kM12 = MF(1, 2);
+constexpr float kM20 = MF(2, 0), kM21 = MF(2, 1), kM22 = MF(2, 2);
+#undef MF
+constexpr double kDn = kWhite[0] + 15.0 * kWhite[1] + 3.0 * kWhite[2];
+constexpr float kUn = static_cast<float>(4.0 * kWhite[0] / kDn);
+constexpr float kVn = static_cast<float>(9.0 * kWhite[1] / kDn);
 
 // ---------------------------------------------------------------- parameters
 
@@ -122,6 +131,29 @@ __device__ __forceinline__ void lab_px(const KCoef& k, float lr, float lg, float
   o[0] = __builtin_fmaf(116.0f, f[1], -16.0f);
   o[1] = 500.0f * (f[0] - f[1]);
   o[2] = 200.0f * (f[1] - f[2]);
+}
+
+// CIE 1976 L*u*v* (the extension named in Sec. 4): L* from the same
+// approximated nonlinearity as CIELAB's (Y / Yn with Yn = 1), u' = 4X / D,
+// v' = 9Y / D with D = X + 15Y + 3Z through one reciprocal; black (D = 0)
+// gives u* = v* = 0.
+template <int DEG>
+__device__ __forceinline__ void luv_px(const KCoef& k, float lr, float lg, float lb, float o[3]) {
+  const float X = __builtin_fmaf(kM00, lr, __builtin_fmaf(kM01, lg, kM02 * lb));
+  const float Y = __builtin_fmaf(kM10, lr, __builtin_fmaf(kM11, lg, kM12 * lb));
+  const float Z = __builtin_fmaf(kM20, lr, __builtin_fmaf(kM21, lg, kM22 * lb));
+  const float fy = Y > kT0f ? fdiv(horner<DEG>(k.p[0], Y), horner<DEG>(k.q, Y)) : __builtin_fmaf(kLabKf, Y, kLabCf);
+  const float L = __builtin_fmaf(116.0f, fy, -16.0f);
+  const float D = __builtin_fmaf(15.0f, Y, __builtin_fmaf(3.0f, Z, X));
+  if (!(D > 0.0f)) {
+    o[0] = L; o[1] = 0.0f; o[2] = 0.0f;
+    return;
+  }
+  const float rD = __builtin_amdgcn_rcpf(D);
+  const float L13 = 13.0f * L;
+  o[0] = L;
+  o[1] = L13 * __builtin_fmaf(4.0f * X, rD, -kUn);
+  o[2] = L13 * __builtin_fmaf(9.0f * Y, rD, -kVn);
 }
 
 // HSI by Kender's branches with the arctan(sqrt 3 x) polynomial (Sec. 3.3).
@@ -245,11 +277,12 @@ __device__ __forceinline__ void store_px(const KImage& im, uint32_t p, const flo
 template <int DEG>
 __device__ __forceinline__ void eval_px(const KCoef& k, bool u8, int gamma, const float* gtab, const float v[3],
                                         float o[3]) {
-  if (k.xform == MACT_LAB) {
+  if (k.xform == MACT_LAB || k.xform == MACT_LUV) {
     float l[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) l[c] = u8 ? gtab[(int)v[c]] : lin_float(k, v[c], gamma);
-    lab_px<DEG>(k, l[0], l[1], l[2], o);
+    if (k.xform == MACT_LAB) lab_px<DEG>(k, l[0], l[1], l[2], o);
+    else luv_px<DEG>(k, l[0], l[1], l[2], o);
   } else if (k.xform == MACT_HSI) {
     hsi_px<DEG>(k, v[0], v[1], v[2], u8 ? kInv765 : kInv3, o);
   } else {
@@ -280,6 +313,7 @@ __device__ __forceinline__ void px4_u8(const KCoef& k, const float* gtab, uint3 
   for (int j = 0; j < 4; ++j) {
     const uint32_t r = byte_of(w, 3 * j), g = byte_of(w, 3 * j + 1), b = byte_of(w, 3 * j + 2);
     if (XF == MACT_LAB) lab_px<DEG>(k, gtab[r], gtab[g], gtab[b], o + 3 * j);
+    else if (XF == MACT_LUV) luv_px<DEG>(k, gtab[r], gtab[g], gtab[b], o + 3 * j);
     else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o + 3 * j);
     else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o + 3 * j);
   }
@@ -292,6 +326,7 @@ __device__ __forceinline__ void px4_f16(const KCoef& k, int gamma, uint3 wa, uin
   for (int j = 0; j < 4; ++j) {
     const float r = half_of(wa, wb, 3 * j), g = half_of(wa, wb, 3 * j + 1), b = half_of(wa, wb, 3 * j + 2);
     if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(k, r, gamma), lin_float(k, g, gamma), lin_float(k, b, gamma), o + 3 * j);
+    else if (XF == MACT_LUV) luv_px<DEG>(k, lin_float(k, r, gamma), lin_float(k, g, gamma), lin_float(k, b, gamma), o + 3 * j);
     else if (XF == MACT_HSI) hsi_px<DEG>(k, r, g, b, kInv3, o + 3 * j);
     else sct_px<DEG>(k, r, g, b, 1.0f, o + 3 * j);
   }

@@ -115,13 +115,13 @@ int pack_coef(const mact_params& p, KCoef* k, int* exact) {
     for (int j = 0; j <= p.f[i].n; ++j) k->p[i][j] = (float)p.f[i].p[j];
     deg = std::max(deg, p.f[i].n);
   }
-  if (p.xform == MACT_LAB && p.f[0].m > 0) {
+  if (uses_gamma(p.xform) && p.f[0].m > 0) {
     for (int j = 0; j <= p.f[0].m; ++j) k->q[j] = (float)p.f[0].q[j];
     deg = std::max(deg, p.f[0].m);
   } else {
     k->q[0] = 1.0f;
   }
-  if (p.xform == MACT_LAB && p.f[1].fn == MACT_FN_DEC709) {
+  if (uses_gamma(p.xform) && p.f[1].fn == MACT_FN_DEC709) {
     // the decoding polynomial has its own fixed evaluation degree (7): it does not raise `deg`
     for (int j = 0; j <= p.f[1].n; ++j) k->p[1][j] = (float)p.f[1].p[j];
     k->decode = 1;
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
   constexpr uint32_t F4PC = OUT == MACT_F32 ? 192 : 96;  // 16-byte output words per chunk
   __shared__ f4 s_out[kHotWaves][kChunksPerWave * 192];
   __shared__ float gtab[256];
-  if (IN == MACT_U8 && XF == MACT_LAB) {
+  if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
     for (uint32_t i = threadIdx.x; i < 256u; i += kHotBlock) gtab[i] = k_gamma_table[gamma][i];
     __syncthreads();
   }
@@ -242,6 +242,7 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
       const uint8_t* b8 = static_cast<const uint8_t*>(in);
       const uint32_t r = b8[3 * p], g = b8[3 * p + 1], b = b8[3 * p + 2];
       if (XF == MACT_LAB) lab_px<DEG>(k, gtab[r], gtab[g], gtab[b], o);
+      else if (XF == MACT_LUV) luv_px<DEG>(k, gtab[r], gtab[g], gtab[b], o);
       else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o);
       else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o);
     } else {
@@ -249,6 +250,7 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
       const float r = clamp01(__half2float(h[3 * p])), g = clamp01(__half2float(h[3 * p + 1])),
                   b = clamp01(__half2float(h[3 * p + 2]));
       if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(k, r, gamma), lin_float(k, g, gamma), lin_float(k, b, gamma), o);
+      else if (XF == MACT_LUV) luv_px<DEG>(k, lin_float(k, r, gamma), lin_float(k, g, gamma), lin_float(k, b, gamma), o);
       else if (XF == MACT_HSI) hsi_px<DEG>(k, r, g, b, kInv3, o);
       else sct_px<DEG>(k, r, g, b, 1.0f, o);
     }
@@ -298,6 +300,7 @@ __global__ __launch_bounds__(256) void k_chw4(const void* __restrict__ in, float
     for (int j = 0; j < 4; ++j) {
       float r[3];
       if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(k, v[0][j], gamma), lin_float(k, v[1][j], gamma), lin_float(k, v[2][j], gamma), r);
+      else if (XF == MACT_LUV) luv_px<DEG>(k, lin_float(k, v[0][j], gamma), lin_float(k, v[1][j], gamma), lin_float(k, v[2][j], gamma), r);
       else if (XF == MACT_HSI) hsi_px<DEG>(k, v[0][j], v[1][j], v[2][j], kInv3, r);
       else sct_px<DEG>(k, v[0][j], v[1][j], v[2][j], 1.0f, r);
       o[0][j] = r[0]; o[1][j] = r[1]; o[2][j] = r[2];
@@ -465,6 +468,7 @@ static void launch_hwc4(int xform, const void* in, void* out, uint32_t n_px, con
   const dim3 grid(hot_grid(n_px)), blk(kHotBlock);
   if (xform == MACT_LAB) hipLaunchKernelGGL((k_hwc4<IN, OUT, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, k, gamma);
   else if (xform == MACT_HSI) hipLaunchKernelGGL((k_hwc4<IN, OUT, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, k, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_hwc4<IN, OUT, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, k, gamma);
   else hipLaunchKernelGGL((k_hwc4<IN, OUT, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, k, gamma);
 }
 
@@ -491,6 +495,7 @@ static void launch_chw4(int xform, const void* in, float* out, uint32_t n_px, ui
   const FastDiv d = make_fastdiv(hw / 4);
   if (xform == MACT_LAB) hipLaunchKernelGGL((k_chw4<IN, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
   else if (xform == MACT_HSI) hipLaunchKernelGGL((k_chw4<IN, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_chw4<IN, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
   else hipLaunchKernelGGL((k_chw4<IN, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
 }
 
@@ -512,7 +517,7 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   KCoef k;
   int exact_deg = 7;
   const int deg = pack_coef(*params, &k, &exact_deg);
-  const int gamma = params->xform == MACT_LAB ? hi.gamma : MACT_GAMMA_NONE;
+  const int gamma = uses_gamma(params->xform) ? hi.gamma : MACT_GAMMA_NONE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   // fast shapes: packed 8-bit / float16 HWC -> packed float32 / float16 HWC, and packed float32 /
   // float16 CHW -> packed float32 CHW with W H a multiple of 4; everything else takes k_generic

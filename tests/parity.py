@@ -5,11 +5,13 @@ import numpy as np
 
 from oracle import mact as OM
 
-# per-channel full scale (L*, a*, b*), (H, S, I), (L, A, B)
+# per-channel full scale (L*, a*, b*), (H, S, I), (L, A, B), (L*, u*, v*): the factor in front of
+# each output's bounded part (|u' - u'n|, |v' - v'n| < 1 with L* <= 100 gives 13 * 100)
 SCALE = {
     0: np.array([116.0, 1000.0, 400.0]),
     1: np.array([2 * np.pi, 1.0, 1.0]),
     2: np.array([np.sqrt(3.0), np.pi / 2, np.pi / 2]),
+    3: np.array([116.0, 1300.0, 1300.0]),
 }
 REL = 2e-6  # float32 parity bound relative to the channel's full scale
 
@@ -21,7 +23,7 @@ def f32(v):
 def coeffs(params):
     """Oracle-form coefficients of a Params struct, rounded to float32."""
     xf = params.xform
-    if xf == 0:
+    if xf in (0, 3):
         a = params.f[0]
         q = a.q_list if a.m > 0 else [1.0]
         return {"p": f32(a.p_list), "q": f32(q)}
@@ -34,6 +36,8 @@ def oracle(xform, x01, co, gamma="bt709", debug=False):
     """The oracle's MACT transform of normalised RGB x01 (..., 3)."""
     if xform == 0:
         return OM.mact_lab(x01, co["p"], co["q"], gamma=gamma, debug=debug)
+    if xform == 3:
+        return OM.mact_luv(x01, co["p"], co["q"], gamma=gamma)
     if xform == 1:
         return OM.mact_hsi(x01, co["c"])
     return OM.mact_sct(x01, co["asin2"], co["acos"], co["atan"], co["atanc"])

@@ -121,7 +121,7 @@ def test_round_trip_on_the_1080p_batch(M, xform):
     assert np.abs(got - want).max() <= tol
 
 
-@pytest.mark.parametrize("xform", [0, 1, 2], ids=["lab", "hsi", "sct"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
 def test_error_stats_equal_the_oracle_metric_of_the_gpu_output(M, xform):
     # the device's float64 reference and metric against the oracle's, on the same float32
     # MACT outputs: agreement to float64 rounding
@@ -141,9 +141,13 @@ def test_error_stats_equal_the_oracle_metric_of_the_gpu_output(M, xform):
         d = C.d_hsi(y, ex)
         ch = np.array([C.angle_diff(y[:, 0], ex[:, 0]).max(), np.abs(y[:, 1] - ex[:, 1]).max(),
                        np.abs(y[:, 2] - ex[:, 2]).max()])
-    else:
+    elif xform == 2:
         ex = C.rgb_to_sct(rgb)
         d = C.sct_delta_e(y, ex)
+        ch = np.abs(y - ex).max(axis=0)
+    else:
+        ex = C.rgb_to_luv(rgb)
+        d = C.delta_e(y, ex)  # Delta E*uv: the Euclidean distance in L*u*v*
         ch = np.abs(y - ex).max(axis=0)
     assert st["count"] == img.shape[0] * img.shape[1]
     # float64 library functions differ by an ulp or so; the oracle's hue is the arccos form,

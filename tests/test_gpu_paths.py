@@ -37,15 +37,15 @@ SHAPES = [(1, 4), (5, 7), (64, 96), (257, 300)]
 
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("dtype", ["u8", "f16"])
-@pytest.mark.parametrize("xform", [0, 1, 2])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3])
 def test_hwc_fast_equals_general(M, xform, dtype, shape):
     g = torch.Generator(device="cuda").manual_seed(sum(shape) + xform)
     if dtype == "u8":
         x = torch.randint(0, 256, (2,) + shape + (3,), dtype=torch.uint8, device="cuda", generator=g)
-        gammas = ["bt709", "srgb", "none"] if xform == 0 else ["bt709"]
+        gammas = ["bt709", "srgb", "none"] if xform in (0, 3) else ["bt709"]
     else:
         x = (torch.rand((2,) + shape + (3,), device="cuda", generator=g) * 1.1 - 0.05).half()
-        gammas = ["none", "bt709"] if xform == 0 else ["none"]
+        gammas = ["none", "bt709"] if xform in (0, 3) else ["none"]
     p = M.default_params(xform)
     for gm in gammas:
         fast = M.transform(x, params=p, gamma=gm)
@@ -67,13 +67,13 @@ def test_hwc_fast_equals_general(M, xform, dtype, shape):
 
 @pytest.mark.parametrize("shape", SHAPES + [(33, 31)])
 @pytest.mark.parametrize("dtype", ["u8", "f16"])
-@pytest.mark.parametrize("xform", [0, 1, 2])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3])
 def test_hwc_f16_output_fast_equals_general(M, xform, dtype, shape):
     # float16 output: the fast kernel rounds in the same place as the general one
     g = torch.Generator(device="cuda").manual_seed(7 * sum(shape) + xform)
     if dtype == "u8":
         x = torch.randint(0, 256, (3,) + shape + (3,), dtype=torch.uint8, device="cuda", generator=g)
-        gm = "bt709" if xform == 0 else "none"
+        gm = "bt709" if xform in (0, 3) else "none"
     else:
         x = (torch.rand((3,) + shape + (3,), device="cuda", generator=g) * 1.1 - 0.05).half()
         gm = "none"
@@ -89,7 +89,7 @@ def test_hwc_f16_output_fast_equals_general(M, xform, dtype, shape):
 
 @pytest.mark.parametrize("hw", [(4, 1), (16, 24), (64, 64), (129, 20)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
-@pytest.mark.parametrize("xform", [0, 1, 2])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3])
 def test_chw_fast_equals_general(M, xform, dtype, hw):
     g = torch.Generator(device="cuda").manual_seed(hw[0] * 7 + hw[1] + xform)
     x = (torch.rand((3, 3) + hw, device="cuda", generator=g) * 1.1 - 0.05).to(dtype)

@@ -27,7 +27,7 @@ def _run(M, x_np, xform, params=None, layout="hwc", gamma="bt709", out_dtype=Non
     return y.cpu().numpy()
 
 
-@pytest.mark.parametrize("xform", [0, 1, 2], ids=["lab", "hsi", "sct"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
 def test_c1_uniform_512(M, xform):
     # 512 x 512 uint8, i.i.d. uniform (seed 1), default approximations
     img = synth.uniform_u8(512, 512, seed=1)
@@ -60,7 +60,7 @@ def _cube_cmp(v8, start, shared, xform, co):
     return P.max_scaled_err(xform, g, P.oracle(xform, v8 / 255.0, co))
 
 
-@pytest.mark.parametrize("xform", [0, 1, 2], ids=["lab", "hsi", "sct"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
 def test_exhaustive_cube(M, xform):
     # every 8-bit colour once (4096 x 4096)
     cube = synth.cube_u8()
@@ -72,7 +72,7 @@ def test_exhaustive_cube(M, xform):
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (1, 5), (3, 7), (17, 33), (255, 257)])
-@pytest.mark.parametrize("xform", [0, 1, 2], ids=["lab", "hsi", "sct"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
 def test_ragged_sizes_and_special_colours(M, shape, xform):
     img = synth.uniform_u8(*shape, seed=sum(shape))
     special = np.array([[0, 0, 0], [255, 255, 255], [128, 128, 128], [255, 0, 0], [0, 255, 0], [0, 0, 255],
@@ -85,7 +85,7 @@ def test_ragged_sizes_and_special_colours(M, shape, xform):
     P.assert_parity(xform, gpu, P.oracle(xform, img / 255.0, P.coeffs(p)))
 
 
-@pytest.mark.parametrize("xform", [0, 1, 2], ids=["lab", "hsi", "sct"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
 def test_float_inputs_layouts_and_clamp(M, xform):
     g = synth.rng(21)
     x = g.uniform(-0.1, 1.1, (2, 3, 61, 67)).astype(np.float32)  # N C H W, some values clamp
@@ -94,8 +94,8 @@ def test_float_inputs_layouts_and_clamp(M, xform):
     gpu = _run(M, x, xform, p, layout="chw", gamma=gamma)
     ref = P.oracle(xform, np.moveaxis(x.astype(np.float64), 1, -1), P.coeffs(p), gamma=gamma)
     ref = np.moveaxis(ref, -1, 1)
-    if xform == 0:
-        P.assert_parity(0, np.moveaxis(gpu, 1, -1), np.moveaxis(ref, 1, -1))
+    if xform in (0, 3):
+        P.assert_parity(xform, np.moveaxis(gpu, 1, -1), np.moveaxis(ref, 1, -1))
         return
     # float inputs: pixels within a relative 1e-6 of an SCT branch boundary may take either branch
     gv, rv = np.moveaxis(gpu, 1, -1).reshape(-1, 3), np.moveaxis(ref, 1, -1).reshape(-1, 3)
@@ -109,7 +109,7 @@ def test_float_inputs_layouts_and_clamp(M, xform):
     assert not bad.any(), err[bad][:5]
 
 
-@pytest.mark.parametrize("xform", [0, 1, 2], ids=["lab", "hsi", "sct"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
 def test_u8_input_f16_output(M, xform):
     # C1 through the float16-output form of the hot kernel (9 bytes per pixel moved):
     # the oracle value rounded to float16 within one half-unit of the float16 result
@@ -121,7 +121,7 @@ def test_u8_input_f16_output(M, xform):
     assert np.all(np.abs(gpu16 - ref) <= tol)
 
 
-@pytest.mark.parametrize("xform", [0, 1, 2], ids=["lab", "hsi", "sct"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
 def test_f16_input_and_f16_output(M, xform):
     g = synth.rng(22)
     xh = g.random((40, 50, 3)).astype(np.float16)
@@ -172,7 +172,7 @@ def test_batch_of_1080p_sampled(M):
     g = synth.rng(99)
     idx = g.integers(0, n * 1080 * 1920, 200000)
     flat = imgs.reshape(-1, 3)[idx]
-    for xform in (0, 1, 2):
+    for xform in (0, 1, 2, 3):
         p = M.default_params(xform)
         y = M.transform(x, xform=xform, params=p)
         torch.cuda.synchronize()
@@ -196,7 +196,7 @@ def test_batch_of_4k_sampled(M):
     g = torch.Generator(device="cuda").manual_seed(7)
     x = torch.randint(0, 256, (32, 2160, 3840, 3), dtype=torch.uint8, device="cuda", generator=g)
     y = torch.empty((32, 2160, 3840, 3), dtype=torch.float32, device="cuda")
-    for xform in (0, 1, 2):
+    for xform in (0, 1, 2, 3):
         p = M.default_params(xform)
         M.transform(x, xform=xform, params=p, out=y)
         torch.cuda.synchronize()
