@@ -138,7 +138,7 @@ def bench_inverse(M, x, y, n_px, steps):
 
 def bench_lut(M, x, y, n_px, steps):
     out = {}
-    for N in (17, 33):
+    for N in (9, 17, 33):
         L = M.lut_build("lab", N)
         for method in ("trilinear", "prism", "pyramidal", "tetrahedral"):
             ms, _ = time_kernel(lambda: M.lut_interp(L, N, "lab", method, x, out=y), steps)

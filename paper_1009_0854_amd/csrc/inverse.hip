@@ -6,7 +6,8 @@
 // minimax approximations in the paper's manner: the BT.709 encoding power
 // 1.099 L^0.45 - 0.099 by a rational on [0.018, 1] (the cube of the CIELAB
 // inverse is exact), cosine by a polynomial on [0, 2 pi/3] (HSI), sine and
-// cosine by polynomials on [0, pi/2] (SCT).  float32, explicit fmas, one
+// cosine by polynomials on [0, pi/2] (SCT).  float32, explicit fmas; packed
+// float32 HWC goes through LDS-staged coalesced chunks, everything else one
 // pixel per lane.
 //
 // Error statistics: every pixel of an RGB image goes through the forward MACT
@@ -125,6 +126,79 @@ __global__ __launch_bounds__(256) void k_inverse(KImage src, KImage dst, uint32_
     else sct_inv_px<DEG>(k, v, o);
     store_px(dst, p, o);
   }
+}
+
+// Packed float32 HWC in and out, 16-byte aligned: each wave takes 256-pixel
+// chunks (3 KB each way).  The chunk comes in as three 1 KB coalesced loads
+// into the wave's LDS slice, each lane reads its 4 pixels (48 bytes) from
+// there, computes them, writes them back to the slice, and the chunk leaves
+// as three 1 KB coalesced stores.  The same per-pixel code as k_inverse.
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int DEG, int XF>
+__global__ __launch_bounds__(256) void k_inverse4(const f4* __restrict__ in, f4* __restrict__ out, uint32_t n_px,
+                                                  KCoef k, InvMat mi, int gamma) {
+  __shared__ f4 s_buf[4][192];
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  f4* s = s_buf[wv];
+  const uint32_t n_chunks = n_px >> 8;
+  for (uint32_t c = blockIdx.x * 4u + wv; c < n_chunks; c += gridDim.x * 4u) {
+    const f4* src = in + (size_t)c * 192;
+    const f4 a0 = src[lane], a1 = src[64 + lane], a2 = src[128 + lane];
+    s[lane] = a0;
+    s[64 + lane] = a1;
+    s[128 + lane] = a2;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the chunk is in LDS
+    __builtin_amdgcn_wave_barrier();
+    const f4 b0 = s[3 * lane], b1 = s[3 * lane + 1], b2 = s[3 * lane + 2];
+    const float v[12] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w, b2.x, b2.y, b2.z, b2.w};
+    float o[12];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (XF == MACT_LAB) lab_inv_px<DEG>(k, mi, gamma, v + 3 * j, o + 3 * j);
+      else if (XF == MACT_HSI) hsi_inv_px<DEG>(k, v + 3 * j, o + 3 * j);
+      else sct_inv_px<DEG>(k, v + 3 * j, o + 3 * j);
+    }
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // every lane's reads are done before the slice is rewritten
+    __builtin_amdgcn_wave_barrier();
+    s[3 * lane] = f4{o[0], o[1], o[2], o[3]};
+    s[3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
+    s[3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+    f4* dst = out + (size_t)c * 192;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(s[q * 64 + lane], dst + q * 64 + lane);
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_wave_barrier();
+  }
+  // the last n_px % 256 pixels, one per thread of block 0
+  const uint32_t tail0 = n_chunks << 8;
+  if (blockIdx.x == 0 && threadIdx.x < n_px - tail0) {
+    const float* fi = reinterpret_cast<const float*>(in);
+    float* fo = reinterpret_cast<float*>(out);
+    const size_t p = tail0 + threadIdx.x;
+    const float v[3] = {fi[3 * p], fi[3 * p + 1], fi[3 * p + 2]};
+    float o[3];
+    if (XF == MACT_LAB) lab_inv_px<DEG>(k, mi, gamma, v, o);
+    else if (XF == MACT_HSI) hsi_inv_px<DEG>(k, v, o);
+    else sct_inv_px<DEG>(k, v, o);
+    fo[3 * p] = o[0];
+    fo[3 * p + 1] = o[1];
+    fo[3 * p + 2] = o[2];
+  }
+}
+
+template <int DEG>
+void launch_inverse4(int xform, const void* in, void* out, uint32_t n_px, const KCoef& k, const InvMat& mi, int gamma,
+                     unsigned grid, hipStream_t st) {
+  const f4* i4 = static_cast<const f4*>(in);
+  f4* o4 = static_cast<f4*>(out);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_inverse4<DEG, MACT_LAB>), dim3(grid), dim3(256), 0, st, i4, o4, n_px, k, mi, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_inverse4<DEG, MACT_HSI>), dim3(grid), dim3(256), 0, st, i4, o4, n_px, k, mi, gamma);
+  else hipLaunchKernelGGL((k_inverse4<DEG, MACT_SCT>), dim3(grid), dim3(256), 0, st, i4, o4, n_px, k, mi, gamma);
 }
 
 // ---------------------------------------------------------------- exact, float64
@@ -377,13 +451,23 @@ extern "C" mact_status mact_inverse(const mact_params* params, const mact_image*
   static const InvMat mi = make_inv_mat();
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const int64_t per = images_per_launch(hi);
+  const bool fast = hi.dtype == MACT_F32 && ho.dtype == MACT_F32 && hi.layout == MACT_HWC && ho.layout == MACT_HWC &&
+                    hi.packed && ho.packed;
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
     const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
     const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
-    const dim3 grid(grid_256(n_px, 8)), blk(256);
-    if (deg == 5) hipLaunchKernelGGL(k_inverse<5>, grid, blk, 0, st, ks, kd, n_px, k, mi, gamma);
-    else hipLaunchKernelGGL(k_inverse<7>, grid, blk, 0, st, ks, kd, n_px, k, mi, gamma);
+    if (fast && (uintptr_t)ks.ptr % 16 == 0 && (uintptr_t)kd.ptr % 16 == 0) {
+      // one 256-pixel chunk per wave per step, 4 waves per workgroup; at least one workgroup for the tail
+      const unsigned grid = (unsigned)std::max<uint64_t>(
+          1, std::min<uint64_t>(((uint64_t)(n_px >> 8) + 3) / 4, (uint64_t)device_cus() * 8));
+      if (deg == 5) launch_inverse4<5>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
+      else launch_inverse4<7>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
+    } else {
+      const dim3 grid(grid_256(n_px, 8)), blk(256);
+      if (deg == 5) hipLaunchKernelGGL(k_inverse<5>, grid, blk, 0, st, ks, kd, n_px, k, mi, gamma);
+      else hipLaunchKernelGGL(k_inverse<7>, grid, blk, 0, st, ks, kd, n_px, k, mi, gamma);
+    }
     if ((s = hip_check(hipGetLastError(), "mact_inverse: launch")) != MACT_OK) return s;
   }
   return MACT_OK;

@@ -179,3 +179,22 @@ def test_error_stats_of_every_colour_match_the_oracle_tables(M, xform, key, tol_
     if xform == 2:
         assert st["max_abs"][1] == pytest.approx(g["sct_dA"]["max"], abs=1e-6)
         assert st["max_abs"][2] == pytest.approx(g["sct_dB"]["max"], abs=1e-6)
+
+
+@pytest.mark.parametrize("shape", [(1, 3), (7, 9), (64, 64), (129, 257)])
+@pytest.mark.parametrize("xform", ["lab", "hsi", "sct"])
+def test_inverse_fast_path_equals_general(M, xform, shape):
+    # packed float32 HWC (LDS-staged chunks, ragged tail) gives the bits of the one-pixel-per-lane
+    # kernel, which a row-padded view of the same values forces
+    g = synth.rng(sum(shape))
+    rgb = g.random((2,) + shape + (3,))
+    fwd = {"lab": C.rgb_to_lab, "hsi": C.rgb_to_hsi, "sct": C.rgb_to_sct}[xform](rgb).astype(np.float32)
+    x = torch.from_numpy(fwd).cuda()
+    p = M.inverse_params(xform)
+    big = torch.zeros((2, shape[0], shape[1] + 3, 3), dtype=torch.float32, device="cuda")
+    big[:, :, :shape[1]] = x
+    for gm in (["bt709", "none"] if xform == "lab" else ["none"]):
+        fast = M.inverse(x, xform=xform, params=p, gamma=gm)
+        general = M.inverse(big[:, :, :shape[1]], xform=xform, params=p, gamma=gm)
+        torch.cuda.synchronize()
+        assert torch.equal(fast, general), gm
