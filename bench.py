@@ -377,6 +377,12 @@ def main():
             ms, _ = time_kernel(lambda: M.transform(x16, params=pp, out=y), a.steps)
             forms["lab_f16_in_decode_%s" % tag] = {"Mpx_s": n_px / ms / 1e3, "GBs": 18.0 * n_px / ms / 1e6, "ms": ms}
         del x16
+        # 16-bit codes (the 8-bit batch times 257), BT.709: exact power vs minimax decoding
+        x16u = torch.from_numpy(batch_np.astype(np.uint16) * np.uint16(257)).cuda()
+        for tag, pp in (("exact", p_lab), ("minimax", M.default_params(0, decode=True))):
+            ms, _ = time_kernel(lambda: M.transform(x16u, params=pp, out=y), a.steps)
+            forms["lab_u16_in_decode_%s" % tag] = {"Mpx_s": n_px / ms / 1e3, "GBs": 18.0 * n_px / ms / 1e6, "ms": ms}
+        del x16u
         log("4K batch")
         forms["lab_32x4k"] = bench_4k(M, p_lab, a.steps)
         for name, xf in (("hsi", 1), ("sct", 2), ("luv", 3)):

@@ -120,7 +120,7 @@ mact_status mact_paper_approx(int32_t fn, int32_t n, int32_t m, mact_approx* out
 /* ------------------------------------------------------------ images */
 
 enum { MACT_LAB = 0, MACT_HSI = 1, MACT_SCT = 2, MACT_LUV = 3 };   /* transforms; CIELUV is the extension named in Sec. 4 */
-enum { MACT_U8 = 0, MACT_F16 = 1, MACT_F32 = 2 };    /* element types */
+enum { MACT_U8 = 0, MACT_F16 = 1, MACT_F32 = 2, MACT_U16 = 3 };  /* element types; U16 codes are full-range (v / 65535) */
 enum { MACT_HWC = 0, MACT_CHW = 1 };                 /* layouts */
 enum {                                              /* input transfer function (LAB) */
   MACT_GAMMA_BT709 = 0, /* Sec. 3.2.1's inverse gamma (ITU-R BT.709); default */

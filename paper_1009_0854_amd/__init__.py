@@ -88,7 +88,7 @@ def make_params(xform, approxes, out_mode=0):
 
 def _dtype_code(t):
     torch = _torch()
-    m = {torch.uint8: U8, torch.float16: F16, torch.float32: F32}
+    m = {torch.uint8: U8, torch.float16: F16, torch.float32: F32, torch.uint16: A.U16}
     if t.dtype not in m:
         raise TypeError("unsupported dtype %s" % t.dtype)
     return m[t.dtype]

@@ -15,7 +15,7 @@ OK, E_INVALID, E_NOCONV, E_DEVICE, E_NOMEM, E_UNSUPPORTED, E_BUSY = 0, -1, -2, -
 FN_CBRT, FN_ATAN_SQRT3, FN_ASIN2, FN_ACOS, FN_ATAN, FN_ATANC, FN_SIN, FN_COS, FN_ENC709, FN_DEC709 = range(10)
 # transforms, element types, layouts, transfer functions, LUT methods
 LAB, HSI, SCT, LUV = 0, 1, 2, 3
-U8, F16, F32 = 0, 1, 2
+U8, F16, F32, U16 = 0, 1, 2, 3
 HWC, CHW = 0, 1
 GAMMA_BT709, GAMMA_SRGB, GAMMA_NONE = 0, 1, 2
 TRILINEAR, PRISM, PYRAMIDAL, TETRAHEDRAL = 0, 1, 2, 3

@@ -95,11 +95,10 @@ __global__ __launch_bounds__(1024) void k_batch(const BDesc* __restrict__ descs,
       }
       pstart = p0 + (nchunk << 8);
     }
-    const bool u8 = d.src.dtype == MACT_U8;
     for (uint32_t p = pstart + threadIdx.x; p < p1; p += blockDim.x) {
       float v[3], o[3];
       load_px(d.src, p, v);
-      eval_px<DEG>(k, u8, d.gamma, g, v, o);
+      eval_px<DEG>(k, d.src.dtype, d.gamma, g, v, o);
       store_px(d.dst, p, o);
     }
   }

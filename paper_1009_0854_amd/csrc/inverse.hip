@@ -296,14 +296,13 @@ __global__ __launch_bounds__(256) void k_error(KImage src, uint32_t n_px, KCoef 
   __shared__ double s_red[4][5];
   gtab[threadIdx.x] = k_gamma_table[gamma][threadIdx.x];
   __syncthreads();
-  const bool u8 = src.dtype == MACT_U8;
-  const double scale = u8 ? 1.0 / 255.0 : 1.0;
+  const double scale = src.dtype == MACT_U8 ? 1.0 / 255.0 : src.dtype == MACT_U16 ? 1.0 / 65535.0 : 1.0;
   double sum = 0.0, mx[4] = {0.0, 0.0, 0.0, 0.0};
   const uint32_t stride = gridDim.x * 256u;
   for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < n_px; p += stride) {
     float v[3], o[3];
     load_px(src, p, v);
-    eval_px<DEG>(k, u8, gamma, gtab, v, o);
+    eval_px<DEG>(k, src.dtype, gamma, gtab, v, o);
     const double rgb[3] = {v[0] * scale, v[1] * scale, v[2] * scale};  // raw values, [0, 1] scale
     const double m[3] = {o[0], o[1], o[2]};
     double ex[3], e, d[3];
@@ -437,7 +436,8 @@ extern "C" mact_status mact_inverse(const mact_params* params, const mact_image*
   if ((s = resolve_image(in, false, "mact_inverse: in", &hi)) != MACT_OK) return s;
   if ((s = resolve_image(out, true, "mact_inverse: out", &ho)) != MACT_OK) return s;
   if ((s = check_same_shape(hi, ho, "mact_inverse: out")) != MACT_OK) return s;
-  if (hi.dtype == MACT_U8) return fail(MACT_E_UNSUPPORTED, "mact_inverse: in must be MACT_F32 or MACT_F16");
+  if (hi.dtype == MACT_U8 || hi.dtype == MACT_U16)
+    return fail(MACT_E_UNSUPPORTED, "mact_inverse: in must be MACT_F32 or MACT_F16");
   if (!params) return fail(MACT_E_INVALID, "mact_inverse: params is NULL");
   if (params->xform == MACT_LUV) return fail(MACT_E_UNSUPPORTED, "mact_inverse: no inverse for MACT_LUV");
   int gamma = MACT_GAMMA_NONE;

@@ -206,7 +206,7 @@ __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (u8) locate_u8((uint32_t)v[c], N, i[c], f[c]);
-      else locate_f(v[c], N, i[c], f[c]);
+      else locate_f(src.dtype == MACT_U16 ? v[c] * kInv65535 : v[c], N, i[c], f[c]);
     }
     lut_px<METHOD, XF, CELL>(nodes, N, i, f, o);
     store_px(dst, p, o);

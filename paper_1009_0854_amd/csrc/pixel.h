@@ -31,6 +31,8 @@ constexpr float kTwoPif = static_cast<float>(2.0 * kPi);
 constexpr float kInv255 = static_cast<float>(1.0 / 255.0);
 constexpr float kInv765 = static_cast<float>(1.0 / 765.0);
 constexpr float kInv3 = static_cast<float>(1.0 / 3.0);
+constexpr float kInv65535 = static_cast<float>(1.0 / 65535.0);
+constexpr float kInv196605 = static_cast<float>(1.0 / 196605.0);  // 1 / (3 * 65535)
 // BT.709 matrix rows (linear RGB -> XYZ) and the white's u', v' for CIELUV.
 #define MF(r, c) static_cast<float>(kM[r][c])
 constexpr float kM00 = MF(0, 0), kM01 = MF(0, 1), kM02 = MF(0, 2);
@@ -242,12 +244,14 @@ __device__ __forceinline__ int64_t elem_off(const KImage& im, uint32_t p, int c)
   return (int64_t)n * im.bs + (int64_t)c * im.ps + (int64_t)y * im.rs + x;
 }
 
-// Raw pixel: 8-bit codes as integer-valued floats, float inputs clamped to [0, 1].
+// Raw pixel: 8- and 16-bit codes as integer-valued floats (exact), float
+// inputs clamped to [0, 1].
 __device__ __forceinline__ void load_px(const KImage& im, uint32_t p, float v[3]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const int64_t o = elem_off(im, p, c);
     if (im.dtype == MACT_U8) v[c] = (float)static_cast<const uint8_t*>(im.ptr)[o];
+    else if (im.dtype == MACT_U16) v[c] = (float)static_cast<const uint16_t*>(im.ptr)[o];
     else if (im.dtype == MACT_F16) v[c] = clamp01(__half2float(static_cast<const __half*>(im.ptr)[o]));
     else v[c] = clamp01(static_cast<const float*>(im.ptr)[o]);
   }
@@ -272,21 +276,24 @@ __device__ __forceinline__ void store_px(const KImage& im, uint32_t p, const flo
   }
 }
 
-// One pixel of any transform from its raw value (as load_px returns it).
-// `gtab` is the 256-entry inverse gamma of the image's transfer function.
+// One pixel of any transform from its raw value (as load_px returns it) of
+// element type `dtype`.  `gtab` is the 256-entry inverse gamma of the image's
+// transfer function (8-bit inputs); 16-bit codes are normalised to [0, 1] and
+// decoded like float inputs.  HSI and SCT are scale-free and take the codes.
 template <int DEG>
-__device__ __forceinline__ void eval_px(const KCoef& k, bool u8, int gamma, const float* gtab, const float v[3],
+__device__ __forceinline__ void eval_px(const KCoef& k, int dtype, int gamma, const float* gtab, const float v[3],
                                         float o[3]) {
   if (k.xform == MACT_LAB || k.xform == MACT_LUV) {
     float l[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) l[c] = u8 ? gtab[(int)v[c]] : lin_float(k, v[c], gamma);
+    for (int c = 0; c < 3; ++c)
+      l[c] = dtype == MACT_U8 ? gtab[(int)v[c]] : lin_float(k, dtype == MACT_U16 ? v[c] * kInv65535 : v[c], gamma);
     if (k.xform == MACT_LAB) lab_px<DEG>(k, l[0], l[1], l[2], o);
     else luv_px<DEG>(k, l[0], l[1], l[2], o);
   } else if (k.xform == MACT_HSI) {
-    hsi_px<DEG>(k, v[0], v[1], v[2], u8 ? kInv765 : kInv3, o);
+    hsi_px<DEG>(k, v[0], v[1], v[2], dtype == MACT_U8 ? kInv765 : dtype == MACT_U16 ? kInv196605 : kInv3, o);
   } else {
-    sct_px<DEG>(k, v[0], v[1], v[2], u8 ? kInv255 : 1.0f, o);
+    sct_px<DEG>(k, v[0], v[1], v[2], dtype == MACT_U8 ? kInv255 : dtype == MACT_U16 ? kInv65535 : 1.0f, o);
   }
 }
 
@@ -316,6 +323,33 @@ __device__ __forceinline__ void px4_u8(const KCoef& k, const float* gtab, uint3 
     else if (XF == MACT_LUV) luv_px<DEG>(k, gtab[r], gtab[g], gtab[b], o + 3 * j);
     else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o + 3 * j);
     else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o + 3 * j);
+  }
+}
+
+// Code i (0..11) of 24 bytes held as two 12-byte words (16-bit input), as a float.
+__device__ __forceinline__ float code16_of(uint3 a, uint3 b, int i) {
+  const uint3 w = i < 6 ? a : b;
+  const int j = i < 6 ? i : i - 6;
+  const uint32_t word = j < 2 ? w.x : (j < 4 ? w.y : w.z);
+  return (float)((word >> (16 * (j & 1))) & 0xffffu);
+}
+
+// The same 4 pixels from 16-bit codes: eval_px's arithmetic for MACT_U16.
+template <int XF, int DEG>
+__device__ __forceinline__ void px4_u16(const KCoef& k, int gamma, uint3 wa, uint3 wb, float o[12]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float r = code16_of(wa, wb, 3 * j), g = code16_of(wa, wb, 3 * j + 1), b = code16_of(wa, wb, 3 * j + 2);
+    if (XF == MACT_LAB || XF == MACT_LUV) {
+      const float lr = lin_float(k, r * kInv65535, gamma), lg = lin_float(k, g * kInv65535, gamma),
+                  lb = lin_float(k, b * kInv65535, gamma);
+      if (XF == MACT_LAB) lab_px<DEG>(k, lr, lg, lb, o + 3 * j);
+      else luv_px<DEG>(k, lr, lg, lb, o + 3 * j);
+    } else if (XF == MACT_HSI) {
+      hsi_px<DEG>(k, r, g, b, kInv196605, o + 3 * j);
+    } else {
+      sct_px<DEG>(k, r, g, b, kInv65535, o + 3 * j);
+    }
   }
 }
 

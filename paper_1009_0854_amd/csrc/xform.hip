@@ -34,13 +34,14 @@ FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
-static size_t elem_size(int dtype) { return dtype == MACT_U8 ? 1 : dtype == MACT_F16 ? 2 : 4; }
+static size_t elem_size(int dtype) { return dtype == MACT_U8 ? 1 : (dtype == MACT_F16 || dtype == MACT_U16) ? 2 : 4; }
 
 mact_status resolve_image(const mact_image* im, bool is_output, const char* what, HostImage* out) {
   if (!im) return fail(MACT_E_INVALID, "%s: image is NULL", what);
   if (!im->data) return fail(MACT_E_INVALID, "%s: data is NULL", what);
-  if (im->dtype < MACT_U8 || im->dtype > MACT_F32) return fail(MACT_E_INVALID, "%s: unknown dtype %d", what, im->dtype);
-  if (is_output && im->dtype == MACT_U8) return fail(MACT_E_UNSUPPORTED, "%s: 8-bit output is not supported", what);
+  if (im->dtype < MACT_U8 || im->dtype > MACT_U16) return fail(MACT_E_INVALID, "%s: unknown dtype %d", what, im->dtype);
+  if (is_output && (im->dtype == MACT_U8 || im->dtype == MACT_U16))
+    return fail(MACT_E_UNSUPPORTED, "%s: integer output is not supported", what);
   if (im->layout != MACT_HWC && im->layout != MACT_CHW) return fail(MACT_E_INVALID, "%s: unknown layout %d", what, im->layout);
   if (im->width <= 0 || im->height <= 0) return fail(MACT_E_INVALID, "%s: size %lld x %lld", what, (long long)im->width, (long long)im->height);
   if (im->batch < 0) return fail(MACT_E_INVALID, "%s: batch %lld < 0", what, (long long)im->batch);
@@ -178,7 +179,7 @@ constexpr int kHotWaves = kHotBlock / 64;
 template <int IN, int OUT, int DEG, int XF>
 __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in, void* __restrict__ out,
                                                      uint32_t n_px, KCoef k, int gamma) {
-  constexpr int WPC = IN == MACT_U8 ? 1 : 2;      // 12-byte words per lane per chunk
+  constexpr int WPC = IN == MACT_U8 ? 1 : 2;      // 12-byte words per lane per chunk (16-bit inputs: 2)
   constexpr uint32_t F4PC = OUT == MACT_F32 ? 192 : 96;  // 16-byte output words per chunk
   __shared__ f4 s_out[kHotWaves][kChunksPerWave * 192];
   __shared__ float gtab[256];
@@ -203,6 +204,7 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
       if (c0 + j >= n_chunks) break;
       float o[12];
       if (IN == MACT_U8) px4_u8<XF, DEG>(k, gtab, w[j][0], o);
+      else if (IN == MACT_U16) px4_u16<XF, DEG>(k, gamma, w[j][0], w[j][WPC - 1], o);
       else px4_f16<XF, DEG>(k, gamma, w[j][0], w[j][WPC - 1], o);
       if (OUT == MACT_F32) {
         s_out[wv][j * 192 + 3 * lane] = f4{o[0], o[1], o[2], o[3]};
@@ -245,6 +247,19 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
       else if (XF == MACT_LUV) luv_px<DEG>(k, gtab[r], gtab[g], gtab[b], o);
       else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o);
       else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o);
+    } else if (IN == MACT_U16) {
+      const uint16_t* c16 = static_cast<const uint16_t*>(in);
+      const float r = (float)c16[3 * p], g = (float)c16[3 * p + 1], b = (float)c16[3 * p + 2];
+      if (XF == MACT_LAB || XF == MACT_LUV) {
+        const float lr = lin_float(k, r * kInv65535, gamma), lg = lin_float(k, g * kInv65535, gamma),
+                    lb = lin_float(k, b * kInv65535, gamma);
+        if (XF == MACT_LAB) lab_px<DEG>(k, lr, lg, lb, o);
+        else luv_px<DEG>(k, lr, lg, lb, o);
+      } else if (XF == MACT_HSI) {
+        hsi_px<DEG>(k, r, g, b, kInv196605, o);
+      } else {
+        sct_px<DEG>(k, r, g, b, kInv65535, o);
+      }
     } else {
       const __half* h = static_cast<const __half*>(in);
       const float r = clamp01(__half2float(h[3 * p])), g = clamp01(__half2float(h[3 * p + 1])),
@@ -317,12 +332,11 @@ __global__ __launch_bounds__(256) void k_generic(KImage src, KImage dst, uint32_
   __shared__ float gtab[256];
   gtab[threadIdx.x] = k_gamma_table[gamma][threadIdx.x];
   __syncthreads();
-  const bool u8 = src.dtype == MACT_U8;
   const uint32_t stride = gridDim.x * 256u;
   for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < n_px; p += stride) {
     float v[3], o[3];
     load_px(src, p, v);
-    eval_px<DEG>(k, u8, gamma, gtab, v, o);
+    eval_px<DEG>(k, src.dtype, gamma, gtab, v, o);
     store_px(dst, p, o);
   }
 }
@@ -521,7 +535,8 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   // fast shapes: packed 8-bit / float16 HWC -> packed float32 / float16 HWC, and packed float32 /
   // float16 CHW -> packed float32 CHW with W H a multiple of 4; everything else takes k_generic
-  const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16) && hi.layout == MACT_HWC && hi.packed &&
+  const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
+                    hi.packed &&
                     (ho.dtype == MACT_F32 || ho.dtype == MACT_F16) && ho.layout == MACT_HWC && ho.packed;
   const bool chw4 = (hi.dtype == MACT_F32 || hi.dtype == MACT_F16) && hi.layout == MACT_CHW && hi.packed &&
                     ho.dtype == MACT_F32 && ho.layout == MACT_CHW && ho.packed && (hi.W * hi.H) % 4 == 0;
@@ -533,6 +548,7 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
     void* op = static_cast<char*>(ho.data) + (size_t)(n0 * ho.bs) * ho.esize;
     if (hwc4 && aligned(ip, 4) && aligned(op, 16)) {
       if (hi.dtype == MACT_U8) launch_hwc4_io<MACT_U8>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
+      else if (hi.dtype == MACT_U16) launch_hwc4_io<MACT_U16>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
       else launch_hwc4_io<MACT_F16>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
     } else if (chw4 && aligned(ip, 4 * hi.esize) && aligned(op, 16)) {
       const uint32_t hw = (uint32_t)(hi.W * hi.H);

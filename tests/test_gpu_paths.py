@@ -36,20 +36,31 @@ SHAPES = [(1, 4), (5, 7), (64, 96), (257, 300)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("dtype", ["u8", "f16"])
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f16"])
 @pytest.mark.parametrize("xform", [0, 1, 2, 3])
 def test_hwc_fast_equals_general(M, xform, dtype, shape):
     g = torch.Generator(device="cuda").manual_seed(sum(shape) + xform)
     if dtype == "u8":
         x = torch.randint(0, 256, (2,) + shape + (3,), dtype=torch.uint8, device="cuda", generator=g)
         gammas = ["bt709", "srgb", "none"] if xform in (0, 3) else ["bt709"]
+    elif dtype == "u16":
+        c = np.random.default_rng(sum(shape) + xform).integers(0, 65536, (2,) + shape + (3,)).astype(np.uint16)
+        x = torch.from_numpy(c).cuda()
+        gammas = ["bt709", "srgb", "none"] if xform in (0, 3) else ["none"]
     else:
         x = (torch.rand((2,) + shape + (3,), device="cuda", generator=g) * 1.1 - 0.05).half()
         gammas = ["none", "bt709"] if xform in (0, 3) else ["none"]
     p = M.default_params(xform)
+    if dtype == "u16":
+        # torch has few 16-bit unsigned kernels on the GPU: build the padded copy on the host
+        big = np.zeros((2, shape[0], shape[1] + 3, 3), dtype=np.uint16)
+        big[:, :, :shape[1]] = c
+        padded = torch.from_numpy(big).cuda()[:, :, :shape[1]]
+    else:
+        padded = _padded_hwc(x)
     for gm in gammas:
         fast = M.transform(x, params=p, gamma=gm)
-        general = M.transform(_padded_hwc(x), params=p, gamma=gm)
+        general = M.transform(padded, params=p, gamma=gm)
         torch.cuda.synchronize()
         assert torch.equal(fast, general), (gm,)
     if dtype == "f16":

@@ -269,3 +269,64 @@ def test_batched_decoding_equals_plain(M):
     torch.cuda.synchronize()
     for i, o in zip(ins, outs):
         assert torch.equal(o, M.transform(i, params=p))
+
+
+@pytest.mark.parametrize("layout", ["hwc", "chw", "strided"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
+def test_u16_inputs(M, xform, layout):
+    # 16-bit codes (full range, v / 65535) on the fast HWC kernel and the general one, every transfer
+    # function for CIELAB / CIELUV, the minimax decoding too; against the oracle on v / 65535.  Branch
+    # guards as for float inputs: SCT pixels within 1e-6 (relative) of a branch plane
+    g = synth.rng(80 + xform)
+    c = g.integers(0, 65536, (2, 29, 71, 3)).astype(np.uint16)
+    c[0, 0, :6] = [[0, 0, 0], [65535, 65535, 65535], [65535, 0, 0], [0, 65535, 0], [1, 2, 3], [5308, 5309, 40000]]
+    # torch has few 16-bit unsigned kernels on the GPU: every layout is built on the host
+    t = torch.from_numpy(c).cuda()
+    t_chw = torch.from_numpy(np.ascontiguousarray(np.moveaxis(c, -1, 1))).cuda()
+    big = np.zeros((2, 29, 75, 3), dtype=np.uint16)
+    big[:, :, :71] = c
+    t_strided = torch.from_numpy(big).cuda()[:, :, :71]
+    x01 = c.astype(np.float64).reshape(-1, 3) / 65535.0
+    cases = [("bt709", False), ("srgb", False), ("none", False), ("bt709", True)] if xform in (0, 3) else [("none", False)]
+    for gm, dec in cases:
+        p = M.default_params(xform, decode=dec)
+        if layout == "chw":
+            y = M.transform(t_chw, xform=xform, params=p, layout="chw", gamma=gm, out_layout="hwc")
+        elif layout == "strided":
+            y = M.transform(t_strided, xform=xform, params=p, gamma=gm)
+        else:
+            y = M.transform(t, xform=xform, params=p, gamma=gm)
+        torch.cuda.synchronize()
+        gpu = y.reshape(-1, 3).cpu().numpy().astype(np.float64)
+        co = P.coeffs(p)
+        if dec:
+            ref = (OM.mact_lab if xform == 0 else OM.mact_luv)(x01, co["p"], co["q"], decode=np.float32(
+                p.f[1].p_list).astype(np.float64))
+        else:
+            ref = P.oracle(xform, x01, co, gamma=gm)
+        err = np.abs(gpu - ref) / P.SCALE[xform]
+        if xform == 2:
+            R, G, B = x01[:, 0], x01[:, 1], x01[:, 2]
+            near = (np.abs(3 * B * B - (R * R + G * G)) <= 1e-6 * (R * R + G * G + B * B)) | (np.abs(G - R) <= 1e-6)
+            err = err[~near]
+        assert err.max() <= P.REL, (gm, dec, err.max(axis=0))
+
+
+def test_u16_error_stats_and_lut(M):
+    # the device's statistics on 16-bit input equal the oracle's metric of the GPU output; the LUT
+    # locates 16-bit codes as normalised floats
+    from oracle import colour as C, lut as OL
+    g = synth.rng(88)
+    c = g.integers(0, 65536, (300, 301, 3)).astype(np.uint16)
+    t = torch.from_numpy(c).cuda()
+    x01 = c.astype(np.float64).reshape(-1, 3) / 65535.0
+    p = M.default_params(0)
+    y = M.transform(t, params=p).reshape(-1, 3).double().cpu().numpy()
+    st = M.error_stats(t, params=p)
+    d = C.delta_e(y, C.rgb_to_lab(x01))
+    assert st["mean"] == pytest.approx(d.mean(), rel=1e-9) and st["max"] == pytest.approx(d.max(), rel=1e-9)
+    L = M.lut_build("lab", 17)
+    out = M.lut_interp(L, 17, "lab", "tetrahedral", t)
+    torch.cuda.synchronize()
+    ref, _ = OL.interp(OL.build("lab", 17), "lab", "tetrahedral", x=x01.astype(np.float32).astype(np.float64))
+    assert np.abs(out.reshape(-1, 3).cpu().numpy() - ref.reshape(-1, 3)).max() / 116.0 <= 2e-5
