@@ -263,7 +263,7 @@ mact_status mact_error_stats(const mact_params* params, const mact_image* in, ma
 enum { MACT_TRILINEAR = 0, MACT_PRISM = 1, MACT_PYRAMIDAL = 2, MACT_TETRAHEDRAL = 3 };
 
 /* Bytes of a packed N x N x N LUT for `xform`: N^3 nodes of 4 floats (LAB:
-   L*, a*, b*, 0; HSI: cos H, sin H, S, I) or 8 floats (SCT: L, cos A, sin A,
+   L*, a*, b*, 0; LUV: L*, u*, v*, 0; HSI: cos H, sin H, S, I) or 8 floats (SCT: L, cos A, sin A,
    cos B, sin B, 0, 0, 0).  Node (i, j, k) at index (i N + j) N + k holds the
    exact transform of the input (i, j, k)/(N - 1) (Sec. 3.5.3's packing).
    Returns 0 for invalid arguments. */
@@ -272,7 +272,7 @@ size_t lut_bytes(int32_t xform, int32_t n);
 /* Packing (Sec. 3.5.3): evaluates the exact transform in FP64 on the host at
    every node, rounds to float32 and copies the packed LUT to the device buffer
    `dev_lut` (caller-owned, >= lut_bytes bytes) on `hip_stream`.  Returns after
-   the copy has completed.  n in 2..256.  gamma applies to LAB. */
+   the copy has completed.  n in 2..256.  gamma applies to LAB and LUV. */
 mact_status lut_build(int32_t xform, int32_t n, int32_t gamma, float* dev_lut, size_t bytes,
                       void* hip_stream);
 
@@ -381,16 +381,16 @@ typedef struct mact_server_config {
   int32_t compute_streams; /* concurrent batches in flight (1..8) */
   int32_t max_queue;       /* submitted but not admitted requests before MACT_E_BUSY */
   int32_t reserved;
-  mact_params params[3];   /* per transform: LAB, HSI, SCT */
+  mact_params params[4];   /* per transform: LAB, HSI, SCT, LUV */
 } mact_server_config;
 
 typedef struct mact_request {
   const void* host_in;     /* pinned host pixels, packed HWC */
   void* host_out;          /* pinned host output, packed HWC */
-  int32_t in_dtype;        /* MACT_U8 or MACT_F16 */
+  int32_t in_dtype;        /* MACT_U8, MACT_U16, MACT_F16 or MACT_F32 */
   int32_t out_dtype;       /* MACT_F32 or MACT_F16 */
-  int32_t xform;           /* MACT_LAB / MACT_HSI / MACT_SCT */
-  int32_t gamma;           /* LAB input transfer function */
+  int32_t xform;           /* MACT_LAB / MACT_HSI / MACT_SCT / MACT_LUV */
+  int32_t gamma;           /* LAB / LUV input transfer function */
   int64_t width, height;
 } mact_request;
 

@@ -38,7 +38,8 @@ import numpy as np
 from . import colour
 
 # Which output channels are angles, per transform.
-ANGULAR = {"lab": (False, False, False), "hsi": (True, False, False), "sct": (False, True, True)}
+ANGULAR = {"lab": (False, False, False), "hsi": (True, False, False), "sct": (False, True, True),
+           "luv": (False, False, False)}
 
 
 def node_inputs(N):
@@ -56,6 +57,8 @@ def build(xform, N, gamma="bt709"):
         return colour.rgb_to_hsi(grid)
     if xform == "sct":
         return colour.rgb_to_sct(grid)
+    if xform == "luv":
+        return colour.rgb_to_luv(grid, gamma)
     raise ValueError(xform)
 
 

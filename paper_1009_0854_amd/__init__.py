@@ -326,7 +326,7 @@ class Server:
         cfg.max_batch = int(max_batch)
         cfg.compute_streams = int(compute_streams)
         cfg.max_queue = int(max_queue)
-        for i, x in enumerate(("lab", "hsi", "sct")):
+        for i, x in enumerate(("lab", "hsi", "sct", "luv")):
             cfg.params[i] = (params or {}).get(x) or default_params(x)
         h = ctypes.c_void_p()
         A.check(lib().mact_server_create(ctypes.byref(cfg), ctypes.byref(h)))

@@ -55,7 +55,7 @@ class Tune(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("arena_bytes", c_size_t), ("max_batch", c_int32), ("compute_streams", c_int32),
-                ("max_queue", c_int32), ("reserved", c_int32), ("params", Params * 3)]
+                ("max_queue", c_int32), ("reserved", c_int32), ("params", Params * 4)]
 
 
 class Request(ctypes.Structure):

@@ -42,6 +42,7 @@ double inverse_gamma(double k, int gamma);
 void exact_lab(const double rgb[3], int gamma, double out[3]);
 void exact_hsi(const double rgb[3], double out[3]);
 void exact_sct(const double rgb[3], double out[3]);
+void exact_luv(const double rgb[3], int gamma, double out[3]);
 
 // Validation shared by the entry points.
 mact_status check_approx(const mact_approx& a, bool rational_ok, const char* what);

@@ -67,6 +67,20 @@ void exact_sct(const double rgb[3], double out[3]) {
   out[2] = std::atan2(G, R);
 }
 
+void exact_luv(const double rgb[3], int gamma, double out[3]) {
+  // CIE 1976 L*u*v* with the CIELAB L* (the extension named in Sec. 4)
+  double lin[3], xyz[3];
+  for (int c = 0; c < 3; ++c) lin[c] = inverse_gamma(rgb[c], gamma);
+  for (int r = 0; r < 3; ++r) xyz[r] = kM[r][0] * lin[0] + kM[r][1] * lin[1] + kM[r][2] * lin[2];
+  const double fy = xyz[1] > kLabT0 ? std::cbrt(xyz[1]) : kLabK * xyz[1] + kLabC;
+  const double L = 116.0 * fy - 16.0;
+  const double d = xyz[0] + 15.0 * xyz[1] + 3.0 * xyz[2];
+  const double dn = kWhite[0] + 15.0 * kWhite[1] + 3.0 * kWhite[2];
+  out[0] = L;
+  out[1] = d > 0.0 ? 13.0 * L * (4.0 * xyz[0] / d - 4.0 * kWhite[0] / dn) : 0.0;
+  out[2] = d > 0.0 ? 13.0 * L * (9.0 * xyz[1] / d - 9.0 * kWhite[1] / dn) : 0.0;
+}
+
 // ---------------------------------------------------------------- validation
 
 mact_status check_approx(const mact_approx& a, bool rational_ok, const char* what) {

@@ -158,7 +158,7 @@ __device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, uint32_t N,
     a0.w = __builtin_fmaf(w[c], v0.w, a0.w);
     if (NF == 2) a1 = __builtin_fmaf(w[c], nodes[n + 1].x, a1);
   }
-  if (XF == MACT_LAB) {
+  if (XF == MACT_LAB || XF == MACT_LUV) {
     o[0] = a0.x; o[1] = a0.y; o[2] = a0.z;
   } else if (XF == MACT_HSI) {
     float h = atan2f(a0.y, a0.x);
@@ -404,7 +404,7 @@ template <bool CELL>
 static mact_status interp_common(const char* what, const float* dev_lut, int32_t n, int32_t xform, int32_t method,
                                  const mact_image* in, const mact_image* out, void* hip_stream) {
   if (!dev_lut) return fail(MACT_E_INVALID, "%s: LUT pointer is NULL", what);
-  if (xform < MACT_LAB || xform > MACT_SCT || n < 2 || n > 256)
+  if (xform < MACT_LAB || xform > MACT_LUV || n < 2 || n > 256)
     return fail(MACT_E_INVALID, "%s: transform %d / size %d invalid", what, xform, n);
   if (method < MACT_TRILINEAR || method > MACT_TETRAHEDRAL) return fail(MACT_E_INVALID, "%s: method %d", what, method);
   if ((uintptr_t)dev_lut % 16) return fail(MACT_E_INVALID, "%s: LUT not 16-byte aligned", what);
@@ -425,6 +425,7 @@ static mact_status interp_common(const char* what, const float* dev_lut, int32_t
     hipError_t e;
     if (xform == MACT_LAB) e = launch_lut_m<MACT_LAB, CELL>(method, lut, n, hi, ho, n0, cnt, n_px, st);
     else if (xform == MACT_HSI) e = launch_lut_m<MACT_HSI, CELL>(method, lut, n, hi, ho, n0, cnt, n_px, st);
+    else if (xform == MACT_LUV) e = launch_lut_m<MACT_LUV, CELL>(method, lut, n, hi, ho, n0, cnt, n_px, st);
     else e = launch_lut_m<MACT_SCT, CELL>(method, lut, n, hi, ho, n0, cnt, n_px, st);
     std::snprintf(nm, sizeof nm, "%s: launch", what);
     if ((s = hip_check(e, nm)) != MACT_OK) return s;
@@ -437,7 +438,7 @@ static mact_status interp_common(const char* what, const float* dev_lut, int32_t
 using namespace mact;
 
 extern "C" size_t lut_bytes(int32_t xform, int32_t n) {
-  if (xform < MACT_LAB || xform > MACT_SCT || n < 2 || n > 256) return 0;
+  if (xform < MACT_LAB || xform > MACT_LUV || n < 2 || n > 256) return 0;
   return (size_t)n * n * n * node_floats(xform) * sizeof(float);
 }
 
@@ -459,6 +460,9 @@ extern "C" mact_status lut_build(int32_t xform, int32_t n, int32_t gamma, float*
         float* dst = &host[((size_t)(i * n + j) * n + k) * nf];
         if (xform == MACT_LAB) {
           exact_lab(rgb, gamma, o);
+          dst[0] = (float)o[0]; dst[1] = (float)o[1]; dst[2] = (float)o[2];
+        } else if (xform == MACT_LUV) {
+          exact_luv(rgb, gamma, o);
           dst[0] = (float)o[0]; dst[1] = (float)o[1]; dst[2] = (float)o[2];
         } else if (xform == MACT_HSI) {
           exact_hsi(rgb, o);
@@ -483,7 +487,7 @@ extern "C" mact_status lut_interp(const float* dev_lut, int32_t n, int32_t xform
 }
 
 extern "C" size_t lut_cells_bytes(int32_t xform, int32_t n) {
-  if (xform < MACT_LAB || xform > MACT_SCT || n < 2 || n > 256) return 0;
+  if (xform < MACT_LAB || xform > MACT_LUV || n < 2 || n > 256) return 0;
   const size_t m = (size_t)(n - 1);
   return m * m * m * 8 * node_floats(xform) * sizeof(float);
 }

@@ -21,7 +21,7 @@
 //   3. a slot is free again as soon as its kernel has finished; each request
 //      completes, and returns its arena space, when its own output copy has
 //      landed (an event per request), not when its whole batch has.
-// The coefficient table of the three transforms stays resident.
+// The coefficient table of the four transforms stays resident.
 //
 // Locking: the scheduler owns the request pipeline and makes its HIP calls
 // without holding any lock that callers take.  Callers meet it at three small
@@ -117,7 +117,7 @@ struct Slot {
   hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;
 };
 
-size_t esize(int dtype) { return dtype == MACT_U8 ? 1 : dtype == MACT_F16 ? 2 : 4; }
+size_t esize(int dtype) { return dtype == MACT_U8 ? 1 : (dtype == MACT_F16 || dtype == MACT_U16) ? 2 : 4; }
 
 }  // namespace
 
@@ -433,7 +433,7 @@ extern "C" mact_status mact_server_create(const mact_server_config* cfg, mact_se
   if (cfg->compute_streams < 1 || cfg->compute_streams > 8)
     return fail(MACT_E_INVALID, "mact_server_create: compute_streams %d outside 1..8", cfg->compute_streams);
   if (cfg->max_queue < 1) return fail(MACT_E_INVALID, "mact_server_create: max_queue %d", cfg->max_queue);
-  for (int x = 0; x < 3; ++x) {
+  for (int x = 0; x < 4; ++x) {
     if (cfg->params[x].xform != x)
       return fail(MACT_E_INVALID, "mact_server_create: params[%d].xform must be %d", x, x);
     mact_status st = check_params(&cfg->params[x]);
@@ -443,8 +443,8 @@ extern "C" mact_status mact_server_create(const mact_server_config* cfg, mact_se
   if (!s) return fail(MACT_E_NOMEM, "mact_server_create: host allocation");
   s->cfg = *cfg;
   s->device = current_device();
-  KCoef k[3];
-  for (int x = 0; x < 3; ++x) s->deg = std::max(s->deg, pack_coef(cfg->params[x], &k[x]));
+  KCoef k[4];
+  for (int x = 0; x < 4; ++x) s->deg = std::max(s->deg, pack_coef(cfg->params[x], &k[x]));
   s->arena.reset(new Arena(cfg->arena_bytes));
   mact_status st = MACT_OK;
   if (hipMalloc(&s->d_arena, cfg->arena_bytes) != hipSuccess || hipMalloc(&s->d_coefs, sizeof k) != hipSuccess) {
@@ -481,10 +481,10 @@ extern "C" mact_status mact_server_submit(mact_server* s, const mact_request* r,
   clear_error();
   if (!s || !r || !id) return fail(MACT_E_INVALID, "mact_server_submit: NULL argument");
   if (!r->host_in || !r->host_out) return fail(MACT_E_INVALID, "mact_server_submit: NULL host buffer");
-  if (r->in_dtype != MACT_U8 && r->in_dtype != MACT_F16 && r->in_dtype != MACT_F32)
+  if (r->in_dtype != MACT_U8 && r->in_dtype != MACT_U16 && r->in_dtype != MACT_F16 && r->in_dtype != MACT_F32)
     return fail(MACT_E_INVALID, "mact_server_submit: in_dtype %d", r->in_dtype);
   if (r->out_dtype != MACT_F32 && r->out_dtype != MACT_F16) return fail(MACT_E_INVALID, "mact_server_submit: out_dtype %d", r->out_dtype);
-  if (r->xform < MACT_LAB || r->xform > MACT_SCT) return fail(MACT_E_INVALID, "mact_server_submit: xform %d", r->xform);
+  if (r->xform < MACT_LAB || r->xform > MACT_LUV) return fail(MACT_E_INVALID, "mact_server_submit: xform %d", r->xform);
   if (r->gamma < MACT_GAMMA_BT709 || r->gamma > MACT_GAMMA_NONE) return fail(MACT_E_INVALID, "mact_server_submit: gamma %d", r->gamma);
   if (r->width <= 0 || r->height <= 0 || (uint64_t)r->width * (uint64_t)r->height >= (1ull << 31))
     return fail(MACT_E_INVALID, "mact_server_submit: size %lld x %lld", (long long)r->width, (long long)r->height);

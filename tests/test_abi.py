@@ -202,7 +202,7 @@ def test_lut_validation_without_gpu(M):
     assert L.lut_bytes(0, 17) == 17 ** 3 * 16
     assert L.lut_bytes(1, 33) == 33 ** 3 * 16
     assert L.lut_bytes(2, 17) == 17 ** 3 * 32
-    assert L.lut_bytes(0, 1) == 0 and L.lut_bytes(3, 17) == 0 and L.lut_bytes(0, 257) == 0
+    assert L.lut_bytes(0, 1) == 0 and L.lut_bytes(4, 17) == 0 and L.lut_bytes(0, 257) == 0
     assert L.lut_build(0, 1, 0, ctypes.c_void_p(0x1000), 1 << 20, None) == A.E_INVALID
     assert L.lut_build(0, 17, 0, None, 1 << 20, None) == A.E_INVALID
     assert L.lut_build(0, 17, 0, ctypes.c_void_p(0x1000), 100, None) == A.E_INVALID
@@ -214,7 +214,7 @@ def test_lut_validation_without_gpu(M):
     assert L.lut_cells_bytes(0, 17) == 16 ** 3 * 8 * 16
     assert L.lut_cells_bytes(2, 33) == 32 ** 3 * 8 * 32
     assert L.lut_cells_bytes(0, 2) == 8 * 16
-    assert L.lut_cells_bytes(0, 1) == 0 and L.lut_cells_bytes(3, 17) == 0 and L.lut_cells_bytes(1, 257) == 0
+    assert L.lut_cells_bytes(0, 1) == 0 and L.lut_cells_bytes(4, 17) == 0 and L.lut_cells_bytes(1, 257) == 0
     need = L.lut_cells_bytes(0, 17)
     assert L.lut_cells_build(ctypes.c_void_p(0x1000), 17, 0, ctypes.c_void_p(0x2000), need - 1, None) == A.E_INVALID
     assert L.lut_cells_build(None, 17, 0, ctypes.c_void_p(0x2000), need, None) == A.E_INVALID

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 METHODS = ["trilinear", "prism", "pyramidal", "tetrahedral"]
-XF = {"lab": 0, "hsi": 1, "sct": 2}
+XF = {"lab": 0, "hsi": 1, "sct": 2, "luv": 3}
 
 
 @pytest.fixture(scope="module")
@@ -50,7 +50,7 @@ def _compare(xform, gpu, ref, rlen, mask=None):
 
 @pytest.mark.parametrize("N", [17, 33])
 @pytest.mark.parametrize("method", METHODS)
-@pytest.mark.parametrize("xform", ["lab", "hsi", "sct"])
+@pytest.mark.parametrize("xform", ["lab", "hsi", "sct", "luv"])
 def test_u8_parity(M, xform, method, N):
     img = synth.uniform_u8(129, 131, seed=N)
     img.reshape(-1, 3)[:6] = [[0, 0, 0], [255, 255, 255], [128, 128, 128], [255, 0, 0], [0, 0, 255], [17, 17, 200]]

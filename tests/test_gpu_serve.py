@@ -20,9 +20,13 @@ def _requests(n, seed, lo=16, hi=600):
     sizes, g = synth.uneven_sizes(n, seed, lo, hi)
     reqs = []
     for (h, w) in sizes:
-        xf = int(g.integers(0, 3))
-        if g.random() < 0.5:
+        xf = int(g.integers(0, 4))  # CIELAB, HSI, SCT, CIELUV
+        kind = g.random()
+        if kind < 0.4:
             x = torch.from_numpy(g.integers(0, 256, (h, w, 3), dtype=np.uint8)).pin_memory()
+            gamma = "bt709"
+        elif kind < 0.6:
+            x = torch.from_numpy(g.integers(0, 65536, (h, w, 3)).astype(np.uint16)).pin_memory()
             gamma = "bt709"
         else:
             x = torch.from_numpy(g.random((h, w, 3)).astype(np.float16)).pin_memory()
