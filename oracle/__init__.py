@@ -19,8 +19,9 @@ mact     FP64 evaluation of the minimax-approximated transforms (Sec. 3.2.2,
          3.3.2, 3.4.2-3.4.3) exactly as the GPU kernels evaluate them, and of
          the inverses with sine, cosine and the BT.709 encoding power replaced
          by minimax approximations in the same way.
-remez    Remez exchange for minimax polynomials and rationals (Sec. 3.1), and
-         a linear-programming discrete minimax used as an independent check.
+remez    Remez exchange for minimax polynomials and rationals (Sec. 3.1),
+         optionally under a positive weight (max |w (p/q - f)|), and a
+         linear-programming discrete minimax used as an independent check.
 lut      3-D LUT packing and the trilinear, prism, pyramidal and tetrahedral
          interpolators, with angular channels (Sec. 3.5.3).
 grad     analytic Jacobian of the minimax CIELAB transform and central finite

@@ -18,6 +18,11 @@ criterion but gives no steps.  This is the textbook algorithm:
   5. stop when the largest error and the smallest reference error agree to a
      relative tolerance.
 
+A positive weight w(x) turns the criterion into max |w (p/q - f)| (weighted
+Chebyshev approximation): the levelled equations become
+p(x_i) - (f(x_i) + (-1)^i E / w(x_i)) q(x_i) = 0 and the extrema are those of
+w e.  With w = 1 (the default) this is the plain minimax of Sec. 3.1.
+
 Coefficients are solved in the Chebyshev basis on [a, b] and returned as
 monomial coefficients in x, lowest degree first, with q[0] = 1.
 
@@ -146,12 +151,15 @@ def _exchange(xs, es, N):
     return np.asarray(keep_x)
 
 
-def _solve_level(f, n, m, a, b, ref):
-    """Levelled solve on the reference: Chebyshev coefficients of p, q and E."""
+def _solve_level(f, n, m, a, b, ref, w=None):
+    """Levelled solve on the reference: Chebyshev coefficients of p, q and E
+    (E is the level of the weighted error w e)."""
     s = _to_s(ref, a, b)
     fi = f(ref)
     N = len(ref)
     sig = (-1.0) ** np.arange(N)
+    if w is not None:
+        sig = sig / w(ref)
     Tn = C.chebvander(s, n)
     if m == 0:
         A = np.hstack([Tn, sig[:, None]])
@@ -183,12 +191,15 @@ def _solve_level(f, n, m, a, b, ref):
     return best
 
 
-def remez(f, n, m, a, b, tol=1e-8, maxit=100, ref=None):
+def remez(f, n, m, a, b, tol=1e-8, maxit=100, ref=None, w=None):
     """Minimax approximation of f by p/q, deg p = n, deg q = m, on [a, b].
 
     Returns a Fit (monomial p, q with q[0] = 1, eps = max |p/q - f| on the
     interval, the final reference, the iteration count, the convergence flag).
+    With a weight w (a callable, positive on [a, b]) the fit minimises
+    max |w (p/q - f)| and eps is that weighted maximum.
     """
+    wf = (lambda x: np.ones_like(np.asarray(x, dtype=np.float64))) if w is None else w
     N = n + m + 2
     if ref is None:
         ref = 0.5 * (a + b) - 0.5 * (b - a) * np.cos(np.pi * np.arange(N) / (N - 1))
@@ -197,11 +208,11 @@ def remez(f, n, m, a, b, tol=1e-8, maxit=100, ref=None):
     eps = np.inf
     it = 0
     for it in range(1, maxit + 1):
-        cp, cq, E = _solve_level(f, n, m, a, b, ref)
+        cp, cq, E = _solve_level(f, n, m, a, b, ref, w)
 
         def err(x, cp=cp, cq=cq):
             s = _to_s(x, a, b)
-            return C.chebval(s, cp) / C.chebval(s, cq) - f(x)
+            return wf(x) * (C.chebval(s, cp) / C.chebval(s, cq) - f(x))
 
         xs, es = _local_extrema(err, a, b, ref)
         eps = float(np.max(np.abs(es)))
@@ -217,62 +228,68 @@ def remez(f, n, m, a, b, tol=1e-8, maxit=100, ref=None):
     q = _cheb_to_monomial_x(cq, a, b)
     p, q = p / q[0], q / q[0]
     fit = Fit(p, q, 0.0, ref, it, converged, a, b)
-    fit.eps = max_error(fit, f, a, b)
+    fit.eps = max_error(fit, f, a, b, w=w)
     return fit
 
 
-def max_error(g, f, a, b, n_pts=1 << 18):
-    """Max |g - f| on [a, b]: dense Chebyshev sampling then local refinement
-    around the largest samples."""
+def max_error(g, f, a, b, n_pts=1 << 18, w=None):
+    """Max |g - f| (max |w (g - f)| with a weight) on [a, b]: dense Chebyshev
+    sampling then local refinement around the largest samples."""
+    wf = (lambda x: np.ones_like(x)) if w is None else w
     k = np.arange(n_pts)
     x = np.unique(np.clip(0.5 * (a + b) - 0.5 * (b - a) * np.cos(np.pi * k / (n_pts - 1)), a, b))
-    e = np.abs(g(x) - f(x))
+    e = np.abs(wf(x) * (g(x) - f(x)))
     best = float(np.max(e))
     for i in np.argsort(e)[-8:]:
         lo, hi = x[max(i - 1, 0)], x[min(i + 1, len(x) - 1)]
         if hi <= lo:
             continue
-        r = scipy.optimize.minimize_scalar(lambda t: -abs(float(g(np.array([t]))[0] - f(np.array([t]))[0])),
-                                           bounds=(lo, hi), method="bounded")
+
+        def neg(t):
+            tt = np.array([t])
+            return -abs(float(wf(tt)[0] * (g(tt)[0] - f(tt)[0])))
+        r = scipy.optimize.minimize_scalar(neg, bounds=(lo, hi), method="bounded")
         best = max(best, -float(r.fun))
     return best
 
 
-def lp_minimax(f, n, m, a, b, n_grid=3001, rel_tol=1e-7):
+def lp_minimax(f, n, m, a, b, n_grid=3001, rel_tol=1e-7, w=None):
     """Discrete minimax of f by p/q on n_grid Chebyshev points of [a, b] by
     linear programming: directly for m = 0; for m > 0 by bisection on the
     level d with the feasibility problem |p(x_i) - f(x_i) q(x_i)| <= d q(x_i),
-    q(x_i) >= 1.  Returns (p, q, eps on the grid), monomial in x, q[0] = 1."""
+    q(x_i) >= 1.  Returns (p, q, eps on the grid), monomial in x, q[0] = 1.
+    With a weight w the bound at x_i is d / w(x_i) (and eps is weighted)."""
     k = np.arange(n_grid)
     x = 0.5 * (a + b) - 0.5 * (b - a) * np.cos(np.pi * k / (n_grid - 1))
     s = _to_s(x, a, b)
     fx = f(x)
+    wx = np.ones_like(x) if w is None else w(x)
     Tn = C.chebvander(s, n)
     if m == 0:
-        # variables: c (n+1), d ; minimise d s.t. +-(Tn c - f) <= d
-        ones = np.ones((n_grid, 1))
-        A = np.vstack([np.hstack([Tn, -ones]), np.hstack([-Tn, -ones])])
-        rhs = np.concatenate([fx, -fx])
+        # variables: c (n+1), d ; minimise d s.t. +-w (Tn c - f) <= d
+        col = -np.ones((n_grid, 1))
+        A = np.vstack([np.hstack([wx[:, None] * Tn, col]), np.hstack([-wx[:, None] * Tn, col])])
+        rhs = np.concatenate([wx * fx, -wx * fx])
         cost = np.zeros(n + 2)
         cost[-1] = 1.0
         r = scipy.optimize.linprog(cost, A_ub=A, b_ub=rhs, bounds=[(None, None)] * (n + 2), method="highs")
         cp = r.x[:n + 1]
         p = _cheb_to_monomial_x(cp, a, b)
-        return p, np.array([1.0]), float(np.max(np.abs(Pm.polyval(x, p) - fx)))
+        return p, np.array([1.0]), float(np.max(np.abs(wx * (Pm.polyval(x, p) - fx))))
     Tm = C.chebvander(s, m)
     nv = n + 1 + m + 1
 
     def feasible(d):
         # p - f q <= d q  ->  Tn cp - (f + d) Tm cq <= 0 ; -(p - f q) <= d q -> -Tn cp + (f - d) Tm cq <= 0
-        A1 = np.hstack([Tn, -(fx + d)[:, None] * Tm])
-        A2 = np.hstack([-Tn, (fx - d)[:, None] * Tm])
+        A1 = np.hstack([Tn, -(fx + d / wx)[:, None] * Tm])
+        A2 = np.hstack([-Tn, (fx - d / wx)[:, None] * Tm])
         A3 = np.hstack([np.zeros((n_grid, n + 1)), -Tm])  # q >= 1
         A = np.vstack([A1, A2, A3])
         rhs = np.concatenate([np.zeros(2 * n_grid), -np.ones(n_grid)])
         r = scipy.optimize.linprog(np.zeros(nv), A_ub=A, b_ub=rhs, bounds=[(-1e6, 1e6)] * nv, method="highs")
         return r.x if r.status == 0 else None
 
-    lo, hi = 0.0, float(np.max(np.abs(fx))) + 1.0
+    lo, hi = 0.0, float(np.max(np.abs(wx * fx))) + float(np.max(wx))
     sol = feasible(hi)
     while hi - lo > rel_tol * hi:
         mid = 0.5 * (lo + hi)
@@ -284,4 +301,4 @@ def lp_minimax(f, n, m, a, b, n_grid=3001, rel_tol=1e-7):
     p = _cheb_to_monomial_x(sol[:n + 1], a, b)
     q = _cheb_to_monomial_x(sol[n + 1:], a, b)
     p, q = p / q[0], q / q[0]
-    return p, q, float(np.max(np.abs(Pm.polyval(x, p) / Pm.polyval(x, q) - fx)))
+    return p, q, float(np.max(np.abs(wx * (Pm.polyval(x, p) / Pm.polyval(x, q) - fx))))

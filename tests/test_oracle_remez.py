@@ -121,3 +121,76 @@ def test_polynomial_matches_lp_minimax():
     fit = remez.remez(T.f_atan, 5, 0, 0.0, 1.0)
     _, _, eps_lp = remez.lp_minimax(T.f_atan, 5, 0, 0.0, 1.0)
     assert fit.eps == pytest.approx(eps_lp, rel=1e-4)
+
+
+# ----------------------------------------------------------------- weighted fits
+
+
+def _weighted_alternation_ok(fit, f, w, rel=1e-6):
+    e = w(fit.alt) * (fit(fit.alt) - f(fit.alt))
+    assert len(fit.alt) == len(fit.p) + len(fit.q)
+    assert np.all(np.sign(e[1:]) == -np.sign(e[:-1])), e
+    np.testing.assert_allclose(np.abs(e), fit.eps, rtol=rel)
+
+
+def test_weighted_relative_sqrt_closed_form():
+    # relative-error (w = 1/f) linear minimax of sqrt on [a, b]: the weighted error
+    # (c0 + c1 x)/sqrt(x) - 1 is convex in sqrt(x) with its minimum at x* = c0/c1; levelling
+    # it at a, x*, b gives c0 = c1 sqrt(ab), c1 = 2 / (a^(1/4) + b^(1/4))^2 and the level
+    # c1 (sqrt(a) + sqrt(b)) - 1
+    a, b = 0.25, 1.0
+    c1 = 2.0 / (a ** 0.25 + b ** 0.25) ** 2
+    c0 = c1 * np.sqrt(a * b)
+    level = c1 * (np.sqrt(a) + np.sqrt(b)) - 1.0
+    w = lambda x: 1.0 / np.sqrt(x)
+    fit = remez.remez(np.sqrt, 1, 0, a, b, w=w)
+    assert fit.converged
+    np.testing.assert_allclose(fit.p, [c0, c1], rtol=1e-10)
+    assert fit.eps == pytest.approx(level, rel=1e-9)
+    np.testing.assert_allclose(np.sort(fit.alt), [a, np.sqrt(a * b), b], atol=1e-7)
+    _weighted_alternation_ok(fit, np.sqrt, w)
+
+
+def test_weighted_constant_closed_form():
+    # best constant for f(x) = x on [0, 1] under w = 1 + x: w(0) c = w(1) (1 - c), so c = 2/3
+    # and the level is 2/3 (w (c - x) falls on [0, c] and w (x - c) rises on [c, 1])
+    w = lambda x: 1.0 + np.asarray(x, dtype=np.float64)
+    fit = remez.remez(lambda x: np.asarray(x, dtype=np.float64), 0, 0, 0.0, 1.0, w=w)
+    assert fit.p[0] == pytest.approx(2.0 / 3.0, rel=1e-12)
+    assert fit.eps == pytest.approx(2.0 / 3.0, rel=1e-9)
+
+
+def test_constant_weight_scales_the_level_only():
+    # a constant weight c leaves the best approximation unchanged and scales the level by c
+    plain = remez.remez(T.f_cbrt, 4, 4, *T.T2_INTERVAL)
+    w3 = remez.remez(T.f_cbrt, 4, 4, *T.T2_INTERVAL, w=lambda x: np.full_like(np.asarray(x, dtype=np.float64), 3.0))
+    np.testing.assert_allclose(w3.p, plain.p, rtol=1e-7)
+    np.testing.assert_allclose(w3.q, plain.q, rtol=1e-7)
+    assert w3.eps == pytest.approx(3.0 * plain.eps, rel=1e-6)
+
+
+def _damped(beta, delta, a=T.T2_INTERVAL[0], b=T.T2_INTERVAL[1]):
+    return lambda x: ((np.asarray(x, dtype=np.float64) - a + delta) / (b - a + delta)) ** beta
+
+
+@pytest.mark.parametrize("nm", [(2, 2), (3, 3), (4, 4)])
+def test_weighted_rational_matches_lp_minimax(nm):
+    # an independent algorithm (LP with the weight in its bounds) reaches the same weighted optimum
+    n, m = nm
+    w = _damped(0.5, 0.02)
+    fit = remez.remez(T.f_cbrt, n, m, *T.T2_INTERVAL, w=w)
+    assert fit.converged
+    _, _, eps_lp = remez.lp_minimax(T.f_cbrt, n, m, *T.T2_INTERVAL, w=w)
+    assert fit.eps <= eps_lp * (1 + 1e-3)
+    assert fit.eps >= eps_lp * (1 - 1e-2)
+    _weighted_alternation_ok(fit, T.f_cbrt, w, rel=1e-5)
+
+
+def test_weighted_polynomial_matches_lp_minimax():
+    w = lambda x: 1.0 + 4.0 * np.asarray(x, dtype=np.float64) ** 2
+    fit = remez.remez(T.f_atan, 5, 0, 0.0, 1.0, w=w)
+    _, _, eps_lp = remez.lp_minimax(T.f_atan, 5, 0, 0.0, 1.0, w=w)
+    # the LP solver's feasibility tolerance (1e-7 on constraints scaled by w up to 5) leaves
+    # its level a few 1e-4 above the optimum; the alternation below is the optimality proof
+    assert eps_lp * (1 - 1e-2) <= fit.eps <= eps_lp * (1 + 1e-3)
+    _weighted_alternation_ok(fit, T.f_atan, w)
