@@ -73,12 +73,18 @@ __global__ __launch_bounds__(1024) void k_batch(const BDesc* __restrict__ descs,
           else if (k.xform == MACT_LUV) px4_u8<MACT_LUV, DEG>(k, g, w, o);
           else if (k.xform == MACT_HSI) px4_u8<MACT_HSI, DEG>(k, g, w, o);
           else px4_u8<MACT_SCT, DEG>(k, g, w, o);
-        } else {  // float16: 24 bytes per lane
+        } else if (d.fast == 2) {  // float16: 24 bytes per lane
           const uint3 wa = win[(cp >> 1) + 2 * lane], wb = win[(cp >> 1) + 2 * lane + 1];
           if (k.xform == MACT_LAB) px4_f16<MACT_LAB, DEG>(k, d.gamma, wa, wb, o);
           else if (k.xform == MACT_LUV) px4_f16<MACT_LUV, DEG>(k, d.gamma, wa, wb, o);
           else if (k.xform == MACT_HSI) px4_f16<MACT_HSI, DEG>(k, d.gamma, wa, wb, o);
           else px4_f16<MACT_SCT, DEG>(k, d.gamma, wa, wb, o);
+        } else {  // 16-bit codes: 24 bytes per lane
+          const uint3 wa = win[(cp >> 1) + 2 * lane], wb = win[(cp >> 1) + 2 * lane + 1];
+          if (k.xform == MACT_LAB) px4_u16<MACT_LAB, DEG>(k, d.gamma, wa, wb, o);
+          else if (k.xform == MACT_LUV) px4_u16<MACT_LUV, DEG>(k, d.gamma, wa, wb, o);
+          else if (k.xform == MACT_HSI) px4_u16<MACT_HSI, DEG>(k, d.gamma, wa, wb, o);
+          else px4_u16<MACT_SCT, DEG>(k, d.gamma, wa, wb, o);
         }
         __builtin_amdgcn_wave_barrier();
         s[3 * lane] = f4{o[0], o[1], o[2], o[3]};
@@ -117,8 +123,9 @@ mact_status make_batch_descs(const mact_params& p, const mact_image* in, const m
   KCoef k;
   *deg = pack_coef(p, &k);
   const int gamma = uses_gamma(p.xform) ? hi.gamma : MACT_GAMMA_NONE;
-  // packed 8-bit (1) or float16 (2) HWC in, packed float32 HWC out: the 4-pixel LDS path
-  const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16) && hi.layout == MACT_HWC && hi.packed &&
+  // packed 8-bit (1), float16 (2) or 16-bit (3) HWC in, packed float32 HWC out: the 4-pixel LDS path
+  const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
+                    hi.packed &&
                     ho.dtype == MACT_F32 && ho.layout == MACT_HWC && ho.packed;
   const int64_t per = images_per_launch(hi);
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
@@ -131,7 +138,7 @@ mact_status make_batch_descs(const mact_params& p, const mact_image* in, const m
     d.coef = coef;
     d.gamma = gamma;
     const bool al = (uintptr_t)d.src.ptr % 4 == 0 && (uintptr_t)d.dst.ptr % 16 == 0;
-    d.fast = (hwc4 && al) ? (hi.dtype == MACT_U8 ? 1 : 2) : 0;
+    d.fast = (hwc4 && al) ? (hi.dtype == MACT_U8 ? 1 : hi.dtype == MACT_F16 ? 2 : 3) : 0;
     descs->push_back(d);
   }
   return MACT_OK;

@@ -42,7 +42,7 @@ struct BDesc {
   uint32_t n_px;  // pixels (N H W) of this descriptor, < 2^31
   int32_t coef;   // index into the coefficient table
   int32_t gamma;  // inverse-gamma row for 8-bit LAB inputs
-  int32_t fast;   // packed 8-bit HWC in, packed float32 HWC out, aligned: 4-pixel path
+  int32_t fast;   // packed HWC in (1: 8-bit, 2: float16, 3: 16-bit), packed float32 HWC out, aligned: 4-pixel path
 };
 
 // Host preparation of one batch entry: validates (params, in, out) and appends

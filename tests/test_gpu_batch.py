@@ -75,6 +75,41 @@ def test_batch_equals_plain_bitwise(M, tune):
     plan.close()
 
 
+@pytest.mark.parametrize("tune", [None, (256, 4096, 4, 32), (256, 4096, 1, 32)], ids=["autotuned", "v4", "v1"])
+def test_batch_16bit_and_cieluv_equal_plain_bitwise(M, tune):
+    # packed 16-bit HWC takes the 4-pixel path (24 bytes per lane), a row-strided 16-bit view the
+    # one-pixel path; every transform incl. CIELUV, every transfer function, the minimax decoding
+    g = synth.rng(91)
+    sizes = [(1, 1), (3, 85), (16, 16), (37, 300), (64, 129), (200, 203), (511, 17)]
+    params, ins, outs, lays, gams = [], [], [], [], []
+    for i, (h, w) in enumerate(sizes):
+        c = g.integers(0, 65536, (h, w + 3, 3)).astype(np.uint16)
+        # torch has few 16-bit unsigned kernels on the GPU: packed copies are made on the host
+        if i % 3 != 2:
+            x = torch.from_numpy(np.ascontiguousarray(c[:, :w])).cuda()
+        else:
+            x = torch.from_numpy(c).cuda()[:, :w]
+        xf = i % 4
+        gm = ["bt709", "srgb", "none"][i % 3] if xf in (0, 3) else "none"
+        p = M.default_params(xf, decode=(xf in (0, 3) and i % 2 == 1))
+        params.append(p)
+        ins.append(x)
+        outs.append(torch.empty((h, w, 3), dtype=torch.float32, device="cuda"))
+        lays.append("hwc")
+        gams.append(gm)
+    ref = _plain(M, params, ins, lays, gams)
+    t = M.Tune(*tune) if tune else None
+    plan = M.BatchPlan(params, ins, outs, lays, gams, lays, tune=t)
+    for use_graph in (True, False):
+        for o in outs:
+            o.fill_(float("nan"))
+        plan.launch(use_graph=use_graph)
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, ref)):
+            assert torch.equal(o, r), (i, use_graph)
+    plan.close()
+
+
 def test_graph_replays_with_eager_work_between(M):
     params, ins, outs, lays, gams, olays, _ = _mixed_batch(M, 25, seed=4)
     ref = _plain(M, params, ins, lays, gams)
