@@ -155,6 +155,35 @@ def bench_inverse(M, x, y, n_px, steps):
     return out
 
 
+def bench_weighted_fits(M, x, y, n_px, steps):
+    """CIELAB cube-root fits of degree (4, 4): the plain minimax, the paper's
+    printed row and weighted minimax fits under the dark-end damped weight
+    ((t - t0 + delta) / (1 - t0 + delta))^beta.  For each: the on-device
+    Delta E*ab mean and max over all 2^24 8-bit colours, the host time of the
+    fit, and the transform's rate on the batch (the same kernel)."""
+    import torch
+    import synth
+    cube = torch.from_numpy(synth.cube_u8()).cuda()
+    out = {}
+    cases = [("minimax", None), ("paper_row", "paper")] + \
+        [("weighted_b%.2f_d%.3f" % bd, bd) for bd in ((0.25, 0.01), (0.5, 0.01), (0.5, 0.005), (0.75, 0.02), (1.0, 0.05))]
+    for name, arg in cases:
+        t0 = time.perf_counter()
+        if arg is None:
+            ap = M.fit(M.FN_CBRT, 4, 4, 0.008856, 1.0)
+        elif arg == "paper":
+            ap = M.paper_approx(M.FN_CBRT, 4, 4)
+        else:
+            ap = M.fit(M.FN_CBRT, 4, 4, 0.008856, 1.0, weight=M.dark_end_weight(*arg))
+        fit_s = time.perf_counter() - t0
+        p = M.make_params("lab", [ap])
+        st = M.error_stats(cube, params=p)
+        ms, _ = time_kernel(lambda: M.transform(x, params=p, out=y), max(10, steps // 4))
+        out[name] = {"dE_mean": st["mean"], "dE_max": st["max"], "eps": ap.eps, "fit_s": fit_s,
+                     "Mpx_s": n_px / ms / 1e3}
+    return out
+
+
 def bench_lut(M, x, y, n_px, steps):
     out = {}
     for N in (9, 17, 33):
@@ -410,6 +439,8 @@ def main():
             forms[name] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
         log("inverses and on-device error statistics")
         forms["inverse"] = bench_inverse(M, x, y, n_px, a.steps)
+        log("weighted cube-root fits")
+        forms["weighted_fits"] = bench_weighted_fits(M, x, y, n_px, a.steps)
     if a.forms in ("all", "lut"):
         log("LUT interpolators")
         forms["lut"] = bench_lut(M, x, y, n_px, a.steps)

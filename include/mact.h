@@ -74,6 +74,7 @@ enum {
 };
 
 #define MACT_MAX_DEGREE 7
+#define MACT_MAX_WEIGHT_SAMPLES 65536
 
 /* A minimax approximation p/q on [lo, hi] (Sec. 3.1).  Monomial coefficients,
    lowest degree first, q[0] = 1 for fits made here (printed tables keep the
@@ -85,7 +86,7 @@ typedef struct mact_approx {
   double lo, hi;     /* fit interval */
   double p[8];       /* numerator coefficients (entries > n are 0) */
   double q[8];       /* denominator coefficients (entries > m are 0) */
-  double eps;        /* max |f - p/q| on [lo, hi] */
+  double eps;        /* max |f - p/q| on [lo, hi] (max |w (f - p/q)| for a weighted fit) */
   double alt[18];    /* final alternation points (n + m + 2 of them) */
   int32_t n_alt;
   int32_t converged; /* 1 if the levelled error met the tolerance */
@@ -100,6 +101,19 @@ typedef struct mact_approx {
 mact_status mact_fit(int32_t fn, int32_t n, int32_t m, double lo, double hi, mact_approx* out);
 mact_status mact_fit_ex(int32_t fn, int32_t n, int32_t m, double lo, double hi, int32_t max_iter,
                         mact_approx* out);
+
+/* Weighted Chebyshev fit: p/q minimising max |w(x) (f(x) - p(x)/q(x))| on
+   [lo, hi], the criterion of Sec. 3.1 under a positive weight (w = 1 is
+   mact_fit).  `weight` holds n_weight samples of w at the equally spaced points
+   lo + i (hi - lo) / (n_weight - 1), i = 0..n_weight-1 (host memory, read
+   during the call only); w is linear between samples.  A weight small near one
+   end of the interval lets the error grow there and shrink elsewhere: for the
+   CIELAB cube root, damping the dark end trades the largest Delta E*ab over the
+   RGB cube for a smaller mean.  out->eps is the weighted maximum.  Errors: as
+   mact_fit_ex, and MACT_E_INVALID for a NULL weight, n_weight outside
+   2..MACT_MAX_WEIGHT_SAMPLES, or a sample that is not positive and finite. */
+mact_status mact_fit_weighted(int32_t fn, int32_t n, int32_t m, double lo, double hi, const double* weight,
+                              int32_t n_weight, int32_t max_iter, mact_approx* out);
 
 /* The library's default approximation of `fn` (its own Remez fits, made once
    per process and cached): cube root (4,4) rational on [0.008856, 1] (Table 2's

@@ -14,7 +14,7 @@ from ._abi import (CHW, E_BUSY, E_NOCONV, F16, F32, FN_ACOS, FN_ASIN2, FN_ATAN, 
                    GAMMA_BT709, GAMMA_NONE, GAMMA_SRGB, HSI, HWC, LAB, PRISM, PYRAMIDAL, SCT, TETRAHEDRAL, TRILINEAR,
                    U8, Approx, Image, MactError, Params, Request, ServerConfig, ServerStats, Tune, lib)
 
-__all__ = ["fit", "default_approx", "paper_approx", "default_params", "make_params", "image", "transform",
+__all__ = ["fit", "dark_end_weight", "default_approx", "paper_approx", "default_params", "make_params", "image", "transform",
            "transform_backward", "inverse_params", "inverse", "error_stats", "lut_bytes", "lut_build",
            "lut_interp", "lut_cells_bytes", "lut_cells_build", "lut_cells_interp", "BatchPlan", "batch_run",
            "Server", "stream_u8_to_f32", "copy", "MactError", "MactLab"]
@@ -41,12 +41,31 @@ def _stream(stream=None):
 
 # ---------------------------------------------------------------- approximations
 
-def fit(fn, n, m, lo, hi, max_iter=100, allow_noconv=False):
-    """mact_fit: Remez fit of function `fn` (FN_*) by p/q, degrees (n, m), on [lo, hi]."""
+def fit(fn, n, m, lo, hi, max_iter=100, allow_noconv=False, weight=None, n_weight=4097):
+    """mact_fit: Remez fit of function `fn` (FN_*) by p/q, degrees (n, m), on [lo, hi].
+
+    With `weight` (samples at equally spaced points of [lo, hi], or a callable
+    sampled at `n_weight` such points) the fit is mact_fit_weighted's: it
+    minimises max |w (f - p/q)| and eps is that weighted maximum."""
     out = Approx()
-    st = lib().mact_fit_ex(int(fn), int(n), int(m), float(lo), float(hi), int(max_iter), ctypes.byref(out))
+    if weight is None:
+        st = lib().mact_fit_ex(int(fn), int(n), int(m), float(lo), float(hi), int(max_iter), ctypes.byref(out))
+    else:
+        if callable(weight):
+            weight = [float(weight(lo + (hi - lo) * i / (n_weight - 1))) for i in range(n_weight)]
+        w = (ctypes.c_double * len(weight))(*[float(v) for v in weight])
+        st = lib().mact_fit_weighted(int(fn), int(n), int(m), float(lo), float(hi), w, len(weight), int(max_iter),
+                                     ctypes.byref(out))
     A.check(st, allow=(E_NOCONV,) if allow_noconv else ())
     return out
+
+
+def dark_end_weight(beta, delta, lo=0.008856, hi=1.0):
+    """The weight ((t - lo + delta) / (hi - lo + delta))^beta for a CIELAB
+    cube-root fit: it damps the criterion near the threshold (the darkest
+    colours, few in number), so the error shrinks over the rest of the range.
+    beta = 0 is the plain minimax fit."""
+    return lambda t: ((t - lo + delta) / (hi - lo + delta)) ** beta
 
 
 def default_approx(fn):

@@ -93,8 +93,21 @@ bool solve(std::vector<double> A, std::vector<double>& b, int N) {
 struct Problem {
   int fn, n, m;
   double a, b;
+  // weight samples at nw equally spaced points of [a, b], linear in between; none = 1
+  const double* w = nullptr;
+  int nw = 0;
   double to_s(double x) const { return (2.0 * x - a - b) / (b - a); }
   double f(double x) const { return eval_fn(fn, x); }
+  double weight(double x) const {
+    if (!w) return 1.0;
+    double u = (x - a) / (b - a) * (nw - 1);
+    if (!(u > 0.0)) return w[0];
+    if (u >= nw - 1) return w[nw - 1];
+    int i = (int)u;
+    if (i > nw - 2) i = nw - 2;
+    double r = u - i;
+    return w[i] + r * (w[i + 1] - w[i]);
+  }
 };
 
 struct Approx {
@@ -104,7 +117,8 @@ struct Approx {
     double s = pr.to_s(x);
     return cheb(cp, s) / cheb(cq, s);
   }
-  double err(const Problem& pr, double x) const { return value(pr, x) - pr.f(x); }
+  // the weighted error w (p/q - f) whose maximum the fit levels
+  double err(const Problem& pr, double x) const { return pr.weight(x) * (value(pr, x) - pr.f(x)); }
 };
 
 void cheb_row(double s, int deg, double* out) {
@@ -149,7 +163,7 @@ bool level(const Problem& pr, const std::vector<double>& ref, Approx& ap) {
         cheb_row(s[i], m, Tm.data());
         for (int j = 1; j <= m; ++j) A[i * N + n + j] = -fi[i] * Tm[j];
       }
-      A[i * N + N - 1] = -sig[i] * qprev[i];
+      A[i * N + N - 1] = -sig[i] * qprev[i] / pr.weight(ref[i]);
       rhs[i] = fi[i];
     }
     if (!solve(A, rhs, N)) return false;
@@ -275,9 +289,9 @@ double horner(const double* c, int deg, double x) {
   return acc;
 }
 
-// max |p/q - f| of the monomial form on a dense grid, refined near the top samples.
+// max |w (p/q - f)| of the monomial form on a dense grid, refined near the top samples.
 double monomial_eps(const Problem& pr, const mact_approx& o) {
-  auto e = [&](double x) { return std::fabs(horner(o.p, o.n, x) / horner(o.q, o.m, x) - pr.f(x)); };
+  auto e = [&](double x) { return std::fabs(pr.weight(x) * (horner(o.p, o.n, x) / horner(o.q, o.m, x) - pr.f(x))); };
   const int G = 1 << 16;
   double best = 0.0;
   std::vector<std::pair<double, int>> top;
@@ -375,9 +389,9 @@ Result fit_problem(const Problem& pr, int max_iter, int depth) {
 
 using namespace mact;
 
-extern "C" mact_status mact_fit_ex(int32_t fn, int32_t n, int32_t m, double lo, double hi, int32_t max_iter,
-                                   mact_approx* out) {
-  clear_error();
+namespace {
+mact_status fit_impl(int32_t fn, int32_t n, int32_t m, double lo, double hi, const double* w, int32_t nw,
+                     int32_t max_iter, mact_approx* out) {
   if (!out) return fail(MACT_E_INVALID, "mact_fit: out is NULL");
   if (fn < 0 || fn >= MACT_FN_COUNT) return fail(MACT_E_INVALID, "mact_fit: unknown function %d", fn);
   if (n < 0 || n > MACT_MAX_DEGREE || m < 0 || m > MACT_MAX_DEGREE)
@@ -388,7 +402,7 @@ extern "C" mact_status mact_fit_ex(int32_t fn, int32_t n, int32_t m, double lo, 
   if (!domain_ok(fn, lo, hi)) return fail(MACT_E_INVALID, "mact_fit: [%g, %g] leaves the domain of function %d", lo, hi, fn);
   if (max_iter < 1) return fail(MACT_E_INVALID, "mact_fit: max_iter %d < 1", max_iter);
 
-  Problem pr{fn, n, m, lo, hi};
+  Problem pr{fn, n, m, lo, hi, w, nw};
   Result r = fit_problem(pr, max_iter, 0);
   std::memset(out, 0, sizeof *out);
   out->fn = fn;
@@ -412,6 +426,27 @@ extern "C" mact_status mact_fit_ex(int32_t fn, int32_t n, int32_t m, double lo, 
   return MACT_OK;
 }
 
+}  // namespace
+
+extern "C" mact_status mact_fit_ex(int32_t fn, int32_t n, int32_t m, double lo, double hi, int32_t max_iter,
+                                   mact_approx* out) {
+  clear_error();
+  return fit_impl(fn, n, m, lo, hi, nullptr, 0, max_iter, out);
+}
+
 extern "C" mact_status mact_fit(int32_t fn, int32_t n, int32_t m, double lo, double hi, mact_approx* out) {
   return mact_fit_ex(fn, n, m, lo, hi, 100, out);
+}
+
+extern "C" mact_status mact_fit_weighted(int32_t fn, int32_t n, int32_t m, double lo, double hi,
+                                         const double* weight, int32_t n_weight, int32_t max_iter,
+                                         mact_approx* out) {
+  clear_error();
+  if (!weight) return fail(MACT_E_INVALID, "mact_fit_weighted: weight is NULL");
+  if (n_weight < 2 || n_weight > MACT_MAX_WEIGHT_SAMPLES)
+    return fail(MACT_E_INVALID, "mact_fit_weighted: n_weight %d outside 2..%d", n_weight, MACT_MAX_WEIGHT_SAMPLES);
+  for (int i = 0; i < n_weight; ++i)
+    if (!(weight[i] > 0.0) || !std::isfinite(weight[i]))
+      return fail(MACT_E_INVALID, "mact_fit_weighted: weight[%d] = %g is not positive and finite", i, weight[i]);
+  return fit_impl(fn, n, m, lo, hi, weight, n_weight, max_iter, out);
 }

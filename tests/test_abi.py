@@ -100,6 +100,71 @@ def test_mact_fit_agrees_with_oracle_remez(M, fn, n, m, lo, hi):
     np.testing.assert_allclose(np.abs(e), a.eps, rtol=1e-5)
 
 
+WEIGHTED = [
+    # the dark-end damped weight of the CIELAB cube root, (beta, delta)
+    (0, 4, 4, 0.008856, 1.0, "damped", (0.5, 0.02)), (0, 4, 4, 0.008856, 1.0, "damped", (0.25, 0.002)),
+    (0, 3, 3, 0.008856, 1.0, "damped", (1.0, 0.1)),
+    # a smooth polynomial weight on the arctangent
+    (4, 5, 0, 0.0, 1.0, "poly", None),
+]
+
+
+@pytest.mark.parametrize("fn,n,m,lo,hi,kind,arg", WEIGHTED)
+def test_mact_fit_weighted_agrees_with_oracle_remez(M, fn, n, m, lo, hi, kind, arg):
+    # both sides fit under the same piecewise-linear weight (the library's samples, interpolated)
+    from numpy.polynomial import polynomial as Pm
+    from oracle import remez, tables as T
+    f = [T.f_cbrt, None, None, None, T.f_atan][fn]
+    if kind == "damped":
+        g = M.dark_end_weight(*arg, lo=lo, hi=hi)
+    else:
+        g = lambda x: 1.0 + 4.0 * x * x
+    knots = np.linspace(lo, hi, 4097)
+    samples = g(knots)
+    w = lambda x: np.interp(np.asarray(x, dtype=np.float64), knots, samples)
+    a = M.fit(fn, n, m, lo, hi, weight=samples)
+    o = remez.remez(f, n, m, lo, hi, w=w)
+    assert a.converged == 1 and o.converged
+    assert a.eps == pytest.approx(o.eps, rel=1e-6)
+    x = np.linspace(lo, hi, 20001)
+    r_lib = Pm.polyval(x, a.p_list) / Pm.polyval(x, a.q_list)
+    assert np.max(np.abs(w(x) * (r_lib - o(x)))) <= 1e-3 * o.eps
+    alt = np.array(a.alt[:a.n_alt])
+    e = w(alt) * (Pm.polyval(alt, a.p_list) / Pm.polyval(alt, a.q_list) - f(alt))
+    assert a.n_alt == n + m + 2
+    assert np.all(np.sign(e[1:]) == -np.sign(e[:-1]))
+    np.testing.assert_allclose(np.abs(e), a.eps, rtol=1e-5)
+    # the callable form samples the same points (up to the rounding of the sample positions)
+    b = M.fit(fn, n, m, lo, hi, weight=g, n_weight=4097)
+    np.testing.assert_allclose(b.p_list, a.p_list, rtol=1e-8)
+    assert b.eps == pytest.approx(a.eps, rel=1e-8)
+
+
+def test_mact_fit_weighted_constant_weight_is_the_plain_fit(M):
+    a = M.fit(0, 4, 4, 0.008856, 1.0)
+    b = M.fit(0, 4, 4, 0.008856, 1.0, weight=[2.5, 2.5])
+    np.testing.assert_allclose(b.p_list, a.p_list, rtol=1e-9)
+    np.testing.assert_allclose(b.q_list, a.q_list, rtol=1e-9)
+    assert b.eps == pytest.approx(2.5 * a.eps, rel=1e-9)
+
+
+def test_mact_fit_weighted_invalid(M):
+    from paper_1009_0854_amd import _abi
+    L = M.lib()
+    out = _abi.Approx()
+    ok = (ctypes.c_double * 3)(1.0, 2.0, 1.0)
+    assert L.mact_fit_weighted(0, 2, 2, 0.1, 1.0, None, 3, 100, ctypes.byref(out)) == _abi.E_INVALID
+    assert L.mact_fit_weighted(0, 2, 2, 0.1, 1.0, ok, 1, 100, ctypes.byref(out)) == _abi.E_INVALID
+    assert L.mact_fit_weighted(0, 2, 2, 0.1, 1.0, ok, 65537, 100, ctypes.byref(out)) == _abi.E_INVALID
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        w = (ctypes.c_double * 3)(1.0, bad, 1.0)
+        assert L.mact_fit_weighted(0, 2, 2, 0.1, 1.0, w, 3, 100, ctypes.byref(out)) == _abi.E_INVALID, bad
+        assert b"weight" in L.mact_last_error()
+    assert L.mact_fit_weighted(0, 2, 2, 0.1, 1.0, ok, 3, 100, None) == _abi.E_INVALID
+    assert L.mact_fit_weighted(0, 2, 2, 1.0, 0.5, ok, 3, 100, ctypes.byref(out)) == _abi.E_INVALID
+    assert L.mact_fit_weighted(0, 2, 2, 0.1, 1.0, ok, 3, 100, ctypes.byref(out)) == _abi.OK
+
+
 def test_mact_fit_nonconvergence_and_invalid(M):
     from paper_1009_0854_amd import _abi
     a = M.fit(0, 4, 4, 0.008856, 1.0, max_iter=1, allow_noconv=True)

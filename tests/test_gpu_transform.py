@@ -55,6 +55,23 @@ def test_lab_paper_coefficients(M):
     P.assert_parity(0, gpu, P.oracle(0, img / 255.0, P.coeffs(p)))
 
 
+@pytest.mark.parametrize("beta,delta", [(0.5, 0.01), (1.0, 0.05)])
+def test_lab_weighted_fit_parity_and_error_statistics(M, beta, delta):
+    # a weighted (4, 4) fit through the same kernel: element parity with the oracle's
+    # evaluation of the same coefficients, and the device's error statistics over a
+    # subsample of the cube equal the oracle metric of the device output
+    from oracle import colour as C
+    ap = M.fit(M.FN_CBRT, 4, 4, 0.008856, 1.0, weight=M.dark_end_weight(beta, delta))
+    p = M.make_params(0, [ap])
+    img = synth.cube_u8().reshape(-1, 3)[::61].reshape(1, -1, 3)
+    gpu = _run(M, img, 0, p)
+    P.assert_parity(0, gpu, P.oracle(0, img / 255.0, P.coeffs(p)))
+    st = M.error_stats(torch.from_numpy(np.ascontiguousarray(img)).cuda(), params=p)
+    d = C.delta_e(gpu.reshape(-1, 3).astype(np.float64), C.rgb_to_lab(img.reshape(-1, 3) / 255.0))
+    assert st["mean"] == pytest.approx(d.mean(), rel=1e-9, abs=1e-11)
+    assert st["max"] == pytest.approx(d.max(), rel=1e-9, abs=1e-11)
+
+
 def _cube_cmp(v8, start, shared, xform, co):
     g = shared[start:start + len(v8)]
     return P.max_scaled_err(xform, g, P.oracle(xform, v8 / 255.0, co))
