@@ -10,8 +10,8 @@ here imports the product.
 
 Modules
 -------
-colour   exact RGB->CIELAB / HSI / SCT transforms, their inverses (the
-         definitions solved for R, G, B; the SCT one is the paper's own) and
+colour   exact RGB->CIELAB / HSI / SCT / CIELUV transforms, their inverses
+         (the definitions solved for R, G, B; the SCT one is the paper's own) and
          the error metrics (Sec. 3.2.1, 3.3.1, 3.4.1 and the metric of
          Sec. 3.4.1).
 tables   the coefficient tables printed in the paper (Tables 1-7).

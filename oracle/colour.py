@@ -229,6 +229,34 @@ def lab_to_rgb(lab, gamma="bt709"):
     return encode_gamma(xyz @ M_XYZ_RGB.T, gamma)
 
 
+def luv_to_xyz(luv):
+    """CIE 1976 L*u*v* -> CIEXYZ (relative to D65), the definition solved for
+    X, Y, Z: Y from L* as in CIELAB (``lab_f_inv`` of (L* + 16) / 116),
+    u' = u* / (13 L*) + u'n, v' = v* / (13 L*) + v'n, and from u' = 4X / D,
+    v' = 9Y / D: X = Y 9u' / (4v'), Z = Y (12 - 3u' - 20v') / (4v').  L* = 0
+    (black, the only colour with Y = 0) gives X = Y = Z = 0."""
+    luv = np.asarray(luv, dtype=np.float64)
+    L, u, v = luv[..., 0], luv[..., 1], luv[..., 2]
+    Xn, Yn, Zn = WHITE_D65
+    dn = Xn + 15.0 * Yn + 3.0 * Zn
+    un, vn = 4.0 * Xn / dn, 9.0 * Yn / dn
+    pos = L > 0
+    Ls = np.where(pos, L, 1.0)
+    Y = np.where(pos, Yn * lab_f_inv((L + 16.0) / 116.0), 0.0)
+    up = u / (13.0 * Ls) + un
+    vp = v / (13.0 * Ls) + vn
+    vs = np.where(pos, vp, 1.0)
+    X = np.where(pos, Y * 9.0 * up / (4.0 * vs), 0.0)
+    Z = np.where(pos, Y * (12.0 - 3.0 * up - 20.0 * vp) / (4.0 * vs), 0.0)
+    return np.stack([X, Y, Z], axis=-1)
+
+
+def luv_to_rgb(luv, gamma="bt709"):
+    """L*u*v* -> R'G'B' (or linear RGB with gamma='none'): XYZ, the inverse
+    matrix, then the encoding.  No clipping."""
+    return encode_gamma(luv_to_xyz(luv) @ M_XYZ_RGB.T, gamma)
+
+
 def hsi_to_rgb(hsi):
     """HSI -> RGB, the inverse of the arccos definition (Sec. 3.3.1), by
     sectors of 2pi/3: in the sector starting at hue h0 with h = H - h0, the

@@ -176,6 +176,19 @@ def mact_lab_inverse(lab, p_enc, q_enc, gamma="bt709"):
     raise ValueError(gamma)
 
 
+def mact_luv_inverse(luv, p_enc, q_enc, gamma="bt709"):
+    """L*u*v* -> R'G'B': XYZ by the definition (colour.luv_to_xyz: the exact
+    cube or linear segment for Y, then u', v' and the two quotients), linear
+    RGB = M^-1 XYZ clamped to [0, 1], then the approximated encoding, as in
+    ``mact_lab_inverse``."""
+    lin = clamp01(colour.luv_to_xyz(luv) @ colour.M_XYZ_RGB.T)
+    if gamma == "bt709":
+        return mact_encode709(lin, p_enc, q_enc)
+    if gamma == "none":
+        return lin
+    raise ValueError(gamma)
+
+
 def mact_hsi_inverse(hsi, c_cos):
     """HSI -> RGB by sectors (as colour.hsi_to_rgb) with cos replaced by the
     polynomial ``c_cos`` on [0, 2pi/3], evaluated at |argument|.  H is taken

@@ -25,6 +25,25 @@ def test_lab_round_trip_every_colour(cube, gamma):
     assert np.abs(back - cube).max() < 1e-12
 
 
+@pytest.mark.parametrize("gamma", ["bt709", "none"])
+def test_luv_round_trip_every_colour(cube, gamma):
+    back = C.luv_to_rgb(C.rgb_to_luv(cube, gamma), gamma)
+    assert np.abs(back - cube).max() < 1e-12
+
+
+def test_luv_inverse_special_values():
+    # white, black, grays (u* = v* = 0 is the white's chromaticity at every lightness)
+    assert np.allclose(C.luv_to_rgb(np.array([100.0, 0.0, 0.0])), 1.0, atol=1e-12)
+    assert np.array_equal(C.luv_to_rgb(np.array([0.0, 0.0, 0.0])), [0.0, 0.0, 0.0])
+    for L in (1.0, 8.0, 50.0, 99.0):
+        rgb = C.luv_to_rgb(np.array([L, 0.0, 0.0]), "none")
+        assert np.allclose(rgb, rgb[0], atol=1e-13)
+    # Y of the definition: the luminance row of the matrix applied to linear RGB
+    lin = synth.rng(3).random((1000, 3))
+    xyz = C.luv_to_xyz(C.rgb_to_luv(lin, "none"))
+    assert np.allclose(xyz[:, 1], lin @ C.M_RGB_XYZ[1], atol=1e-13)
+
+
 def test_hsi_round_trip_every_colour(cube):
     back = C.hsi_to_rgb(C.rgb_to_hsi(cube))
     assert np.abs(back - cube).max() < 1e-12
@@ -91,6 +110,16 @@ def test_mact_lab_inverse_within_the_encoding_error(cube, fits):
     got = OM.mact_lab_inverse(lab, enc.p, enc.q)
     assert np.abs(got - cube).max() <= enc.eps * (1 + 1e-6) + 1e-12
     lin = OM.mact_lab_inverse(lab, enc.p, enc.q, gamma="none")
+    assert np.abs(lin - C.inverse_gamma(cube)).max() < 1e-12
+
+
+def test_mact_luv_inverse_within_the_encoding_error(cube, fits):
+    enc = fits[0]
+    luv = C.rgb_to_luv(cube)
+    got = OM.mact_luv_inverse(luv, enc.p, enc.q)
+    assert np.abs(got - cube).max() <= enc.eps * (1 + 1e-6) + 1e-12
+    assert np.abs(got - cube).max() > 0.3 * enc.eps
+    lin = OM.mact_luv_inverse(luv, enc.p, enc.q, gamma="none")
     assert np.abs(lin - C.inverse_gamma(cube)).max() < 1e-12
 
 
