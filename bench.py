@@ -130,16 +130,16 @@ def bench_4k(M, p, steps):
 
 
 def bench_inverse(M, x, y, n_px, steps):
-    """Inverse MACT (L*a*b* / HSI / SCT float32 -> R'G'B' float32, 24 bytes per
+    """Inverse MACT (L*a*b* / HSI / SCT / L*u*v* float32 -> R'G'B' float32, 24 bytes per
     pixel) on the forward output of the batch, and the on-device error
     statistics of each forward transform over all 2^24 8-bit colours."""
     import torch
     import synth
     out = {}
     back = torch.empty_like(y)
-    for name in ("lab", "hsi", "sct"):
+    for name in ("lab", "hsi", "sct", "luv"):
         M.transform(x, xform=name, out=y)
-        gm = "bt709" if name == "lab" else "none"
+        gm = "bt709" if name in ("lab", "luv") else "none"
         ms, _ = time_kernel(lambda: M.inverse(y, xform=name, gamma=gm, out=back), steps)
         out["%s_inverse" % name] = {"Mpx_s": n_px / ms / 1e3, "GBs": 24.0 * n_px / ms / 1e6, "ms": ms}
     del back

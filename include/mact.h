@@ -227,12 +227,12 @@ mact_status mact_transform_backward(const mact_params* params, const mact_image*
 /* ------------------------------------------------------------ inverses, error statistics */
 
 /* Fill *p with the default approximations of the inverse of `xform`:
-     LAB: f[0] = the BT.709 encoding power, (4,4) rational on [0.018, 1];
+     LAB, LUV: f[0] = the BT.709 encoding power, (4,4) rational on [0.018, 1];
      HSI: f[0] = cosine, degree 7 on [0, 2 pi/3];
      SCT: f[0] = sine, f[1] = cosine, degree 7 on [0, pi/2]. */
 mact_status mact_inverse_params_default(int32_t xform, mact_params* p);
 
-/* Inverse MACT transform of `in` (L*a*b*, HSI or SCT triples) into `out`
+/* Inverse MACT transform of `in` (L*a*b*, HSI, SCT or L*u*v* triples) into `out`
    (R'G'B' on the [0, 1] scale):
      LAB: fy = (L* + 16)/116, fx = fy + a* / 500, fz = fy - b* / 200; t = f^3 where
           that exceeds 0.008856, else (f - 16/116)/7.787 (Sec. 3.2.1 solved for
@@ -247,10 +247,15 @@ mact_status mact_inverse_params_default(int32_t xform, mact_params* p);
      SCT: R = L s(A) c(B), G = L s(A) s(B), B = L c(A) with s = f[0] ~ sin and
           c = f[1] ~ cos (Sec. 3.4.1's inverse); A, B in [0, pi/2], the range
           the forward transform gives for non-negative RGB.
+     LUV: Y from L* as for LAB; u' = u* / (13 L*) + u'n, v' = v* / (13 L*) + v'n;
+          X = 9 u' Y / (4 v'), Z = (12 - 3 u' - 20 v') Y / (4 v') (the CIE 1976
+          definition solved for X, Y, Z); L* <= 0 gives black; then M^-1 XYZ,
+          the clamp and the encoding as for LAB.  Triples off the image of the
+          forward transform (v' <= 0) give unspecified values.
    in: MACT_F32 or MACT_F16, any layout; out: MACT_F32 or MACT_F16, any layout,
    same geometry.  float32 arithmetic.  Errors: MACT_E_INVALID (NULL, shapes,
    approximations of the wrong function or degree); MACT_E_UNSUPPORTED (8-bit
-   in, sRGB encoding, MACT_LUV); MACT_E_DEVICE. */
+   in, sRGB encoding); MACT_E_DEVICE. */
 mact_status mact_inverse(const mact_params* params, const mact_image* in, const mact_image* out,
                          void* hip_stream);
 

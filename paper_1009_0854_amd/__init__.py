@@ -199,9 +199,9 @@ def inverse_params(xform="lab"):
 
 def inverse(x, xform="lab", params=None, layout="hwc", gamma="bt709", out=None, out_layout=None, out_dtype=None,
             stream=None):
-    """mact_inverse of float tensor x (L*a*b*, HSI or SCT triples) to R'G'B'
-    on the [0, 1] scale; `gamma` is the encoding of the CIELAB inverse's output
-    ('bt709' or 'none')."""
+    """mact_inverse of float tensor x (L*a*b*, HSI, SCT or L*u*v* triples) to
+    R'G'B' on the [0, 1] scale; `gamma` is the encoding of the CIELAB and
+    CIELUV inverses' output ('bt709' or 'none')."""
     torch = _torch()
     p = params if params is not None else inverse_params(xform)
     out_layout = layout if out_layout is None else out_layout

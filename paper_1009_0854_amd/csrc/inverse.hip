@@ -1,11 +1,12 @@
-// Inverse transforms (CIELAB, HSI, SCT -> RGB) with minimax approximations,
-// and on-device error statistics of the forward transforms.
+// Inverse transforms (CIELAB, HSI, SCT, CIELUV -> RGB) with minimax
+// approximations, and on-device error statistics of the forward transforms.
 //
-// Inverses: the definitions of Sec. 3.2.1 and 3.3.1 solved for R, G, B, and
-// the SCT inverse of Sec. 3.4.1, with the elementary functions replaced by
+// Inverses: the definitions of Sec. 3.2.1 and 3.3.1 solved for R, G, B, the
+// SCT inverse of Sec. 3.4.1, and the CIE 1976 L*u*v* definition (the extension
+// named in Sec. 4) solved for X, Y, Z, with the elementary functions replaced by
 // minimax approximations in the paper's manner: the BT.709 encoding power
-// 1.099 L^0.45 - 0.099 by a rational on [0.018, 1] (the cube of the CIELAB
-// inverse is exact), cosine by a polynomial on [0, 2 pi/3] (HSI), sine and
+// 1.099 L^0.45 - 0.099 by a rational on [0.018, 1] (the cube of the CIELAB and
+// CIELUV inverses is exact), cosine by a polynomial on [0, 2 pi/3] (HSI), sine and
 // cosine by polynomials on [0, pi/2] (SCT).  float32, explicit fmas; packed
 // float32 HWC goes through LDS-staged coalesced chunks, everything else one
 // pixel per lane.
@@ -29,12 +30,13 @@ namespace mact {
 
 namespace {
 
-// M^-1 diag(white): t (= XYZ / white) -> linear RGB, rounded once from double.
+// M^-1 diag(white): t (= XYZ / white) -> linear RGB (CIELAB), or M^-1 alone:
+// XYZ -> linear RGB (CIELUV); rounded once from double.
 struct InvMat {
   float m[3][3];
 };
 
-InvMat make_inv_mat() {
+InvMat make_inv_mat(bool fold_white) {
   // 3x3 inverse by cofactors, in double
   const double (*a)[3] = kM;
   const double det = a[0][0] * (a[1][1] * a[2][2] - a[1][2] * a[2][1]) -
@@ -52,7 +54,7 @@ InvMat make_inv_mat() {
   inv[2][2] = (a[0][0] * a[1][1] - a[0][1] * a[1][0]) / det;
   InvMat r;
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) r.m[i][j] = (float)(inv[i][j] * kWhite[j]);
+    for (int j = 0; j < 3; ++j) r.m[i][j] = (float)(fold_white ? inv[i][j] * kWhite[j] : inv[i][j]);
   return r;
 }
 
@@ -82,6 +84,32 @@ __device__ __forceinline__ void lab_inv_px(const KCoef& k, const InvMat& mi, int
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const float lin = clamp01(__builtin_fmaf(mi.m[c][0], t[0], __builtin_fmaf(mi.m[c][1], t[1], mi.m[c][2] * t[2])));
+    if (gamma == MACT_GAMMA_NONE) o[c] = lin;
+    else o[c] = lin >= kEnc0 ? fdiv(horner<DEG>(k.p[0], lin), horner<DEG>(k.q, lin)) : 4.5f * lin;
+  }
+}
+
+// CIE 1976 L*u*v* -> R'G'B'.  Y from L* as in CIELAB (Y/Yn = t, Yn = 1); u', v'
+// from u*, v* through one reciprocal of 13 L*; X = 9 u' q and Z = (12 - 3u' - 20v') q
+// with q = Y / (4 v').  L* <= 0 is black.  Values off the image of the forward
+// transform (v' <= 0) give unspecified results.
+template <int DEG>
+__device__ __forceinline__ void luv_inv_px(const KCoef& k, const InvMat& mi, int gamma, const float v[3], float o[3]) {
+  float X = 0.0f, Y = 0.0f, Z = 0.0f;
+  if (v[0] > 0.0f) {
+    const float fy = (v[0] + 16.0f) * (1.0f / 116.0f);
+    const float cube = fy * fy * fy;
+    Y = cube > kT0f ? cube : (fy - kLabCf) * (1.0f / kLabKf);
+    const float r13 = fdiv(1.0f, 13.0f * v[0]);
+    const float up = __builtin_fmaf(v[1], r13, kUn);
+    const float vp = __builtin_fmaf(v[2], r13, kVn);
+    const float q = fdiv(Y, 4.0f * vp);
+    X = 9.0f * up * q;
+    Z = __builtin_fmaf(-3.0f, up, __builtin_fmaf(-20.0f, vp, 12.0f)) * q;
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float lin = clamp01(__builtin_fmaf(mi.m[c][0], X, __builtin_fmaf(mi.m[c][1], Y, mi.m[c][2] * Z)));
     if (gamma == MACT_GAMMA_NONE) o[c] = lin;
     else o[c] = lin >= kEnc0 ? fdiv(horner<DEG>(k.p[0], lin), horner<DEG>(k.q, lin)) : 4.5f * lin;
   }
@@ -122,6 +150,7 @@ __global__ __launch_bounds__(256) void k_inverse(KImage src, KImage dst, uint32_
     float v[3], o[3];
     load_raw(src, p, v);
     if (k.xform == MACT_LAB) lab_inv_px<DEG>(k, mi, gamma, v, o);
+    else if (k.xform == MACT_LUV) luv_inv_px<DEG>(k, mi, gamma, v, o);
     else if (k.xform == MACT_HSI) hsi_inv_px<DEG>(k, v, o);
     else sct_inv_px<DEG>(k, v, o);
     store_px(dst, p, o);
@@ -157,6 +186,7 @@ __global__ __launch_bounds__(256) void k_inverse4(const f4* __restrict__ in, f4*
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (XF == MACT_LAB) lab_inv_px<DEG>(k, mi, gamma, v + 3 * j, o + 3 * j);
+      else if (XF == MACT_LUV) luv_inv_px<DEG>(k, mi, gamma, v + 3 * j, o + 3 * j);
       else if (XF == MACT_HSI) hsi_inv_px<DEG>(k, v + 3 * j, o + 3 * j);
       else sct_inv_px<DEG>(k, v + 3 * j, o + 3 * j);
     }
@@ -183,6 +213,7 @@ __global__ __launch_bounds__(256) void k_inverse4(const f4* __restrict__ in, f4*
     const float v[3] = {fi[3 * p], fi[3 * p + 1], fi[3 * p + 2]};
     float o[3];
     if (XF == MACT_LAB) lab_inv_px<DEG>(k, mi, gamma, v, o);
+    else if (XF == MACT_LUV) luv_inv_px<DEG>(k, mi, gamma, v, o);
     else if (XF == MACT_HSI) hsi_inv_px<DEG>(k, v, o);
     else sct_inv_px<DEG>(k, v, o);
     fo[3 * p] = o[0];
@@ -197,6 +228,7 @@ void launch_inverse4(int xform, const void* in, void* out, uint32_t n_px, const 
   const f4* i4 = static_cast<const f4*>(in);
   f4* o4 = static_cast<f4*>(out);
   if (xform == MACT_LAB) hipLaunchKernelGGL((k_inverse4<DEG, MACT_LAB>), dim3(grid), dim3(256), 0, st, i4, o4, n_px, k, mi, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_inverse4<DEG, MACT_LUV>), dim3(grid), dim3(256), 0, st, i4, o4, n_px, k, mi, gamma);
   else if (xform == MACT_HSI) hipLaunchKernelGGL((k_inverse4<DEG, MACT_HSI>), dim3(grid), dim3(256), 0, st, i4, o4, n_px, k, mi, gamma);
   else hipLaunchKernelGGL((k_inverse4<DEG, MACT_SCT>), dim3(grid), dim3(256), 0, st, i4, o4, n_px, k, mi, gamma);
 }
@@ -380,20 +412,21 @@ const InvDefaults& inv_defaults() {
 // apply (the inverse uses f[0] and f[1] in its own way), so they are packed here.
 mact_status pack_inverse(const mact_params* p, int gamma, KCoef* k, int* deg) {
   if (!p) return fail(MACT_E_INVALID, "mact_inverse: params is NULL");
-  if (p->xform < MACT_LAB || p->xform > MACT_SCT) return fail(MACT_E_INVALID, "mact_inverse: xform %d", p->xform);
+  if (p->xform < MACT_LAB || p->xform > MACT_LUV) return fail(MACT_E_INVALID, "mact_inverse: xform %d", p->xform);
   if (p->out_mode != 0) return fail(MACT_E_INVALID, "mact_inverse: out_mode must be 0");
   std::memset(k, 0, sizeof *k);
   k->xform = p->xform;
   k->q[0] = 1.0f;
   int d = 0;
   const int nf = p->xform == MACT_SCT ? 2 : 1;
-  const bool need = !(p->xform == MACT_LAB && gamma == MACT_GAMMA_NONE);
+  const bool encodes = p->xform == MACT_LAB || p->xform == MACT_LUV;
+  const bool need = !(encodes && gamma == MACT_GAMMA_NONE);
   for (int i = 0; i < nf && need; ++i) {
     const mact_approx& a = p->f[i];
-    mact_status s = check_approx(a, p->xform == MACT_LAB, "mact_inverse");
+    mact_status s = check_approx(a, encodes, "mact_inverse");
     if (s != MACT_OK) return s;
-    const int want = p->xform == MACT_LAB ? MACT_FN_ENC709 : p->xform == MACT_HSI ? MACT_FN_COS
-                                                                                  : (i == 0 ? MACT_FN_SIN : MACT_FN_COS);
+    const int want = encodes ? MACT_FN_ENC709 : p->xform == MACT_HSI ? MACT_FN_COS
+                                                                     : (i == 0 ? MACT_FN_SIN : MACT_FN_COS);
     if (a.fn != want) return fail(MACT_E_INVALID, "mact_inverse: f[%d] approximates function %d, expected %d", i, a.fn, want);
     for (int j = 0; j <= a.n; ++j) k->p[i][j] = (float)a.p[j];
     d = std::max(d, a.n);
@@ -414,12 +447,12 @@ using namespace mact;
 extern "C" mact_status mact_inverse_params_default(int32_t xform, mact_params* p) {
   clear_error();
   if (!p) return fail(MACT_E_INVALID, "mact_inverse_params_default: NULL");
-  if (xform < MACT_LAB || xform > MACT_SCT) return fail(MACT_E_INVALID, "mact_inverse_params_default: xform %d", xform);
+  if (xform < MACT_LAB || xform > MACT_LUV) return fail(MACT_E_INVALID, "mact_inverse_params_default: xform %d", xform);
   const InvDefaults& d = inv_defaults();
   if (d.st != MACT_OK) return fail(d.st, "mact_inverse_params_default: fitting the default approximations failed");
   std::memset(p, 0, sizeof *p);
   p->xform = xform;
-  if (xform == MACT_LAB) p->f[0] = d.enc;
+  if (xform == MACT_LAB || xform == MACT_LUV) p->f[0] = d.enc;
   else if (xform == MACT_HSI) p->f[0] = d.cos_h;
   else {
     p->f[0] = d.sin_s;
@@ -439,16 +472,16 @@ extern "C" mact_status mact_inverse(const mact_params* params, const mact_image*
   if (hi.dtype == MACT_U8 || hi.dtype == MACT_U16)
     return fail(MACT_E_UNSUPPORTED, "mact_inverse: in must be MACT_F32 or MACT_F16");
   if (!params) return fail(MACT_E_INVALID, "mact_inverse: params is NULL");
-  if (params->xform == MACT_LUV) return fail(MACT_E_UNSUPPORTED, "mact_inverse: no inverse for MACT_LUV");
   int gamma = MACT_GAMMA_NONE;
-  if (params->xform == MACT_LAB) {
+  if (params->xform == MACT_LAB || params->xform == MACT_LUV) {
     gamma = ho.gamma;
     if (gamma == MACT_GAMMA_SRGB) return fail(MACT_E_UNSUPPORTED, "mact_inverse: sRGB encoding has no default approximation");
   }
   KCoef k;
   int deg = 5;
   if ((s = pack_inverse(params, gamma, &k, &deg)) != MACT_OK) return s;
-  static const InvMat mi = make_inv_mat();
+  static const InvMat mi_lab = make_inv_mat(true), mi_luv = make_inv_mat(false);
+  const InvMat& mi = params->xform == MACT_LUV ? mi_luv : mi_lab;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const int64_t per = images_per_launch(hi);
   const bool fast = hi.dtype == MACT_F32 && ho.dtype == MACT_F32 && hi.layout == MACT_HWC && ho.layout == MACT_HWC &&

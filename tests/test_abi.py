@@ -354,6 +354,12 @@ def test_inverse_and_error_stats_validation_without_gpu(M):
     srgb = _img(0x2000, A.F32)
     srgb.gamma = A.GAMMA_SRGB
     assert L.mact_inverse(ctypes.byref(M.inverse_params("lab")), ctypes.byref(i32), ctypes.byref(srgb), None) == A.E_UNSUPPORTED
+    assert L.mact_inverse(ctypes.byref(M.inverse_params("luv")), ctypes.byref(i32), ctypes.byref(srgb), None) == A.E_UNSUPPORTED
+    luv = M.inverse_params("luv")
+    assert luv.xform == A.LUV and luv.f[0].fn == A.FN_ENC709 and luv.f[0].m == 4
+    luv.f[0] = M.inverse_params("hsi").f[0]  # cosine where the encoding belongs
+    assert L.mact_inverse(ctypes.byref(luv), ctypes.byref(i32), ctypes.byref(o32), None) == A.E_INVALID
+    assert L.mact_inverse_params_default(4, ctypes.byref(luv)) == A.E_INVALID
     e = A.ErrorStats()
     assert L.mact_error_stats(ctypes.byref(M.default_params(0)), ctypes.byref(i32), None, None) == A.E_INVALID
     assert L.mact_error_stats(None, ctypes.byref(i32), ctypes.byref(e), None) == A.E_INVALID

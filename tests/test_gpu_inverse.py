@@ -1,5 +1,5 @@
-"""GPU parity of the inverse transforms (mact_inverse) against the oracle's
-approximated inverses, and of the on-device error statistics
+"""GPU parity of the inverse transforms (mact_inverse; CIELAB, HSI, SCT and
+CIELUV) against the oracle's approximated inverses, and of the on-device error statistics
 (mact_error_stats) against the oracle's metrics."""
 import json
 import os
@@ -67,6 +67,27 @@ def test_lab_inverse_parity(M, colours, gamma):
     assert err.max() <= 1.2e-5, err.max()
 
 
+@pytest.mark.parametrize("gamma", ["bt709", "none"])
+def test_luv_inverse_parity(M, colours, gamma):
+    # float32 rounding bound: X, Y, Z (each at most the white's) carry about 12 float32 roundings
+    # (the cube, 1/(13 L*), u', v', q, the products); the rows of M^-1 weight them by at most
+    # sum_j |M^-1_0j| white_j = 5.16, and the encoding's slope is at most 4.5:
+    # 4.5 * 5.16 * 12 * 2^-24 = 1.7e-5
+    p = M.inverse_params("luv")
+    co = _inv_coeffs(p)
+    luv = C.rgb_to_luv(colours).astype(np.float32).astype(np.float64)
+    gpu = _run_inverse(M, luv.reshape(1, -1, 3), "luv", p, gamma=gamma).reshape(-1, 3)
+    ref = OM.mact_luv_inverse(luv, co["p0"], co["q0"], gamma=gamma)
+    err = np.abs(gpu - ref)
+    if gamma == "bt709":
+        lin = OM.mact_luv_inverse(luv, co["p0"], co["q0"], gamma="none")
+        err[np.abs(lin - 0.018) <= 1e-6] = 0.0
+    assert err.max() <= 1.7e-5, err.max()
+    # black is black
+    blk = _run_inverse(M, np.zeros((1, 1, 3)), "luv", p, gamma=gamma)
+    assert np.array_equal(blk, np.zeros((1, 1, 3)))
+
+
 def test_hsi_inverse_parity(M, colours):
     # |start| <= 3 I with a ratio of two cosine polynomials (each >= 1/2): a few float32 ulps
     p = M.inverse_params("hsi")
@@ -86,12 +107,12 @@ def test_sct_inverse_parity(M, colours):
     assert np.abs(gpu - ref).max() <= 2e-6 * np.sqrt(3.0)
 
 
-@pytest.mark.parametrize("xform", ["lab", "hsi", "sct"])
+@pytest.mark.parametrize("xform", ["lab", "hsi", "sct", "luv"])
 def test_inverse_layouts_and_float16(M, xform):
     # CHW float16 in, HWC float32 out: the same values as packed HWC float32 in
     g = synth.rng(31)
     rgb = g.random((2, 37, 53, 3))
-    fwd = {"lab": C.rgb_to_lab, "hsi": C.rgb_to_hsi, "sct": C.rgb_to_sct}[xform](rgb).astype(np.float16)
+    fwd = {"lab": C.rgb_to_lab, "hsi": C.rgb_to_hsi, "sct": C.rgb_to_sct, "luv": C.rgb_to_luv}[xform](rgb).astype(np.float16)
     p = M.inverse_params(xform)
     a = _run_inverse(M, fwd.astype(np.float32), xform, p)
     chw = np.ascontiguousarray(np.moveaxis(fwd, -1, 1))
@@ -104,20 +125,20 @@ def test_inverse_layouts_and_float16(M, xform):
     assert torch.equal(h, torch.from_numpy(np.moveaxis(a, -1, 1).astype(np.float32)).cuda().half())
 
 
-@pytest.mark.parametrize("xform", ["lab", "hsi", "sct"])
+@pytest.mark.parametrize("xform", ["lab", "hsi", "sct", "luv"])
 def test_round_trip_on_the_1080p_batch(M, xform):
     # MACT forward then MACT inverse on the GPU returns the 8-bit colours to within a
     # fraction of one code (sampled pixels of 4 images of the benchmark batch)
     imgs = synth.smooth_batch_u8(4, 1080, 1920, 1000)
     x = torch.from_numpy(imgs).cuda()
     y = M.transform(x, xform=xform)
-    gm = "bt709" if xform == "lab" else "none"
+    gm = "bt709" if xform in ("lab", "luv") else "none"
     back = M.inverse(y, xform=xform, gamma=gm)
     torch.cuda.synchronize()
     idx = torch.from_numpy(synth.rng(5).integers(0, x.numel() // 3, 200000)).cuda()
     got = back.reshape(-1, 3)[idx].cpu().numpy().astype(np.float64)
     want = imgs.reshape(-1, 3)[idx.cpu().numpy()] / 255.0
-    tol = {"lab": 2e-3, "hsi": 2e-3, "sct": 2e-4}[xform]
+    tol = {"lab": 2e-3, "hsi": 2e-3, "sct": 2e-4, "luv": 2e-3}[xform]
     assert np.abs(got - want).max() <= tol
 
 
@@ -182,18 +203,18 @@ def test_error_stats_of_every_colour_match_the_oracle_tables(M, xform, key, tol_
 
 
 @pytest.mark.parametrize("shape", [(1, 3), (7, 9), (64, 64), (129, 257)])
-@pytest.mark.parametrize("xform", ["lab", "hsi", "sct"])
+@pytest.mark.parametrize("xform", ["lab", "hsi", "sct", "luv"])
 def test_inverse_fast_path_equals_general(M, xform, shape):
     # packed float32 HWC (LDS-staged chunks, ragged tail) gives the bits of the one-pixel-per-lane
     # kernel, which a row-padded view of the same values forces
     g = synth.rng(sum(shape))
     rgb = g.random((2,) + shape + (3,))
-    fwd = {"lab": C.rgb_to_lab, "hsi": C.rgb_to_hsi, "sct": C.rgb_to_sct}[xform](rgb).astype(np.float32)
+    fwd = {"lab": C.rgb_to_lab, "hsi": C.rgb_to_hsi, "sct": C.rgb_to_sct, "luv": C.rgb_to_luv}[xform](rgb).astype(np.float32)
     x = torch.from_numpy(fwd).cuda()
     p = M.inverse_params(xform)
     big = torch.zeros((2, shape[0], shape[1] + 3, 3), dtype=torch.float32, device="cuda")
     big[:, :, :shape[1]] = x
-    for gm in (["bt709", "none"] if xform == "lab" else ["none"]):
+    for gm in (["bt709", "none"] if xform in ("lab", "luv") else ["none"]):
         fast = M.inverse(x, xform=xform, params=p, gamma=gm)
         general = M.inverse(big[:, :, :shape[1]], xform=xform, params=p, gamma=gm)
         torch.cuda.synchronize()
