@@ -491,9 +491,9 @@ extern "C" mact_status mact_inverse(const mact_params* params, const mact_image*
     const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
     const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
     if (fast && (uintptr_t)ks.ptr % 16 == 0 && (uintptr_t)kd.ptr % 16 == 0) {
-      // one 256-pixel chunk per wave per step, 4 waves per workgroup; at least one workgroup for the tail
-      const unsigned grid = (unsigned)std::max<uint64_t>(
-          1, std::min<uint64_t>(((uint64_t)(n_px >> 8) + 3) / 4, (uint64_t)device_cus() * 8));
+      // one 256-pixel chunk per wave, 4 waves per workgroup, the grid covering the image once;
+      // at least one workgroup for the tail
+      const unsigned grid = (unsigned)std::max<uint64_t>(1, ((uint64_t)(n_px >> 8) + 3) / 4);
       if (deg == 5) launch_inverse4<5>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
       else launch_inverse4<7>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
     } else {

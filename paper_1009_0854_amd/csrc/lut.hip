@@ -353,9 +353,12 @@ static hipError_t launch_lut(const f4* lut, uint32_t N, const HostImage& hi, con
     const unsigned block = lds ? 1024 : 256;
     const size_t shm = (lds ? bytes : 0) + (size_t)(block / 64) * 192 * sizeof(f4);
     const uint64_t chunks = std::max<uint64_t>(1, n_px >> 8);
-    const uint64_t per_cu = lds ? std::max<uint64_t>(1, std::min<uint64_t>(2, lds_max / shm)) : 8;
-    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((chunks + block / 64 - 1) / (block / 64),
-                                                                             (uint64_t)device_cus() * per_cu));
+    // a staged grid is worth keeping: one or two resident workgroups per CU stride over the image;
+    // gathers from global memory: the grid covers the image once, one chunk per wave
+    const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(2, lds_max / shm));
+    const uint64_t need = (chunks + block / 64 - 1) / (block / 64);
+    const unsigned grid = (unsigned)std::max<uint64_t>(1, lds ? std::min<uint64_t>(need, (uint64_t)device_cus() * per_cu)
+                                                              : std::min<uint64_t>(need, 0x7fffffffu));
     const uint8_t* in8 = static_cast<const uint8_t*>(ip);
     // lanes on consecutive pixels pay off for gathers through the L1 (33^3: +13-16%, SCT +44%
     // on smooth images) but not for LDS-staged grids (-0 to -6%)
