@@ -343,8 +343,9 @@ mact_status lut_cells_interp(const float* dev_cells, int32_t n, int32_t xform, i
 typedef struct mact_tune {
   int32_t block;      /* threads per workgroup: 64, 128, 256, 512, 1024 */
   int32_t tile;       /* pixels per work tile: multiple of the block, >= block */
-  int32_t vec;        /* pixels per lane per step on the packed 8-bit path: 1, 2 or 4 */
-  int32_t waves_per_cu; /* persistent grid = CUs x this, capped by the tile count */
+  int32_t vec;        /* pixels per lane per step on the packed HWC paths: 1 or 4 */
+  int32_t waves_per_cu; /* 1..64: persistent grid = CUs x this / (block / 64) workgroups, capped
+                           by the tile count; 0: one workgroup per tile */
 } mact_tune;
 
 typedef struct mact_batch_plan mact_batch_plan;

@@ -156,6 +156,9 @@ uint32_t build_tiles(const std::vector<BDesc>& descs, uint32_t tile, std::vector
 }
 
 unsigned batch_grid(const mact_tune& tune, uint32_t total_tiles) {
+  // waves_per_cu 0: the grid covers the tile list once (streaming launches run faster this way
+  // than a few resident workgroups per CU walking the list)
+  if (tune.waves_per_cu == 0) return std::max<uint32_t>(1, std::min<uint32_t>(total_tiles, 0x7fffffffu));
   const uint64_t per_cu = std::max<uint64_t>(1, (uint64_t)tune.waves_per_cu * 64 / tune.block);
   const uint64_t cap = (uint64_t)device_cus() * per_cu;
   return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(total_tiles, cap));
@@ -185,7 +188,7 @@ static mact_status check_tune(const mact_tune& t) {
   if (t.tile < 256 || t.tile % 256 || t.tile < t.block)
     return fail(MACT_E_INVALID, "mact_tune: tile %d must be a multiple of 256 and >= block", t.tile);
   if (t.vec != 1 && t.vec != 4) return fail(MACT_E_INVALID, "mact_tune: vec %d not 1 or 4", t.vec);
-  if (t.waves_per_cu < 1 || t.waves_per_cu > 64) return fail(MACT_E_INVALID, "mact_tune: waves_per_cu %d", t.waves_per_cu);
+  if (t.waves_per_cu < 0 || t.waves_per_cu > 64) return fail(MACT_E_INVALID, "mact_tune: waves_per_cu %d", t.waves_per_cu);
   return MACT_OK;
 }
 
@@ -374,7 +377,7 @@ static mact_status plan_autotune(mact_batch_plan* p) {
   static const int blocks[] = {256, 512, 1024};
   static const int tiles[] = {8192, 32768, 131072};
   static const int vecs[] = {4, 1};
-  static const int waves[] = {16, 32};
+  static const int waves[] = {16, 32, 0};
   // every candidate timed 3 times (best of), then the 4 fastest 8 times more
   std::vector<std::pair<float, mact_tune>> timed;
   for (int v : vecs)

@@ -304,6 +304,9 @@ def test_batch_and_server_validation_without_gpu(M):
     assert L.mact_batch_plan_create(p, i, o, 1, ctypes.byref(t), None, ctypes.byref(h)) == A.E_INVALID
     t = A.Tune(256, 4096, 3, 32)
     assert L.mact_batch_plan_create(p, i, o, 1, ctypes.byref(t), None, ctypes.byref(h)) == A.E_INVALID
+    for w in (-1, 65):
+        t = A.Tune(256, 4096, 4, w)
+        assert L.mact_batch_plan_create(p, i, o, 1, ctypes.byref(t), None, ctypes.byref(h)) == A.E_INVALID
     cfg = A.ServerConfig()
     cfg.arena_bytes, cfg.max_batch, cfg.compute_streams, cfg.max_queue = 1 << 30, 64, 2, 100
     for x in range(3):

@@ -54,10 +54,12 @@ def _plain(M, params, ins, lays, gams):
     return [M.transform(x, params=p, layout=l, gamma=gm) for p, x, l, gm in zip(params, ins, lays, gams)]
 
 
-TUNES = [None, (256, 4096, 4, 32), (1024, 16384, 4, 16), (256, 4096, 1, 32), (64, 256, 1, 8), (512, 65536, 4, 64)]
+TUNES = [None, (256, 4096, 4, 32), (1024, 16384, 4, 16), (256, 4096, 1, 32), (64, 256, 1, 8), (512, 65536, 4, 64),
+         (1024, 8192, 4, 0), (256, 1024, 1, 0)]
 
 
-@pytest.mark.parametrize("tune", TUNES, ids=["autotuned", "b256v4", "b1024v4", "b256v1", "b64t256", "b512big"])
+@pytest.mark.parametrize("tune", TUNES, ids=["autotuned", "b256v4", "b1024v4", "b256v1", "b64t256", "b512big",
+                                             "b1024v4full", "b256v1full"])
 def test_batch_equals_plain_bitwise(M, tune):
     params, ins, outs, lays, gams, olays, _ = _mixed_batch(M, 40, seed=3)
     ref = _plain(M, params, ins, lays, gams)
@@ -75,7 +77,8 @@ def test_batch_equals_plain_bitwise(M, tune):
     plan.close()
 
 
-@pytest.mark.parametrize("tune", [None, (256, 4096, 4, 32), (256, 4096, 1, 32)], ids=["autotuned", "v4", "v1"])
+@pytest.mark.parametrize("tune", [None, (256, 4096, 4, 32), (256, 4096, 1, 32), (512, 2048, 4, 0)],
+                         ids=["autotuned", "v4", "v1", "v4full"])
 def test_batch_16bit_and_cieluv_equal_plain_bitwise(M, tune):
     # packed 16-bit HWC takes the 4-pixel path (24 bytes per lane), a row-strided 16-bit view the
     # one-pixel path; every transform incl. CIELUV, every transfer function, the minimax decoding
