@@ -45,10 +45,11 @@ def log(*a):
     print("bench:", *a, file=sys.stderr, flush=True)
 
 
-def time_kernel(fn, steps, warmup=2):
+def time_kernel(fn, steps, warmup=2, spread=None):
     """Mean and median duration (ms) of fn() over `steps` launches, HIP events
     recorded around each launch on torch's current stream, which is the stream
-    the library launches on."""
+    the library launches on.  With a dict `spread`, also its 10th and 90th
+    percentiles there."""
     import torch
     for _ in range(warmup):
         fn()
@@ -60,6 +61,8 @@ def time_kernel(fn, steps, warmup=2):
         b.record()
     torch.cuda.synchronize()
     per = [a.elapsed_time(b) for a, b in ev]
+    if spread is not None:
+        spread["p10"], spread["p90"] = float(np.percentile(per, 10)), float(np.percentile(per, 90))
     return float(np.mean(per)), float(np.median(per))
 
 
@@ -105,7 +108,14 @@ def cpu_baseline(batch_np, y, budget_px, chunk=1 << 22):
         t0 = time.perf_counter()
         list(ex.map(one, range(0, len(every), small)))
         dt_all = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return ({"value": len(every) / dt_all / 1e6, "unit": "Mpixel/s", "cores": n_thr, "kind": "oracle",
+             "nproc": os.cpu_count(), "cpu_model": model,
              "sample": "the whole 64x1080p batch (%d pixels) in chunks of 2^20 on %d threads; FP64 numpy MACT CIELAB"
                        % (len(every), n_thr),
              "seconds": dt_all, "single_thread": single},
@@ -400,7 +410,8 @@ def main():
     wall = time.perf_counter() - t0
     value = n_px * a.steps / wall / 1e6
 
-    k_ms, k_med = time_kernel(step, a.steps)
+    k_spread = {}
+    k_ms, k_med = time_kernel(step, a.steps, spread=k_spread)
     achieved = 15.0 * n_px / (k_ms * 1e-3) / 1e9
 
     forms = {}
@@ -433,10 +444,17 @@ def main():
         del x16u
         log("4K batch")
         forms["lab_32x4k"] = bench_4k(M, p_lab, a.steps)
+        # each rate beside its accuracy: the paper's metric (D_HSI for HSI, the inverse-SCT Delta E*ab
+        # for SCT, Delta E*uv for CIELUV) over all 2^24 8-bit colours, on the device
+        cube = torch.from_numpy(synth.cube_u8()).cuda()
         for name, xf in (("hsi", 1), ("sct", 2), ("luv", 3)):
             p = M.default_params(xf)
             ms, _ = time_kernel(lambda: M.transform(x, params=p, out=y), a.steps)
-            forms[name] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
+            st = M.error_stats(cube, params=p)
+            forms[name] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms,
+                           "metric_mean_all_colours": st["mean"], "metric_max_all_colours": st["max"],
+                           "max_abs_per_channel": st["max_abs"]}
+        del cube
         log("inverses and on-device error statistics")
         forms["inverse"] = bench_inverse(M, x, y, n_px, a.steps)
         log("weighted cube-root fits")
@@ -481,7 +499,8 @@ def main():
                    "max_dE_exhaustive_cube": acc.get("exhaustive_cube_oracle", {}).get("lab", {}).get("max")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_hwc4<U8,F32,4,LAB>",
-                     "kernel_ms": k_ms, "kernel_ms_median": k_med, "algorithmic_bytes_per_px": 15,
+                     "kernel_ms": k_ms, "kernel_ms_median": k_med, "kernel_ms_p10": k_spread["p10"],
+                     "kernel_ms_p90": k_spread["p90"], "algorithmic_bytes_per_px": 15,
                      "pixels_per_launch": n_px},
         "cpu_baseline": cpu,
         "accuracy": acc,

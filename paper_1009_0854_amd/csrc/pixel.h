@@ -53,7 +53,7 @@ struct KCoef {
   float q[8];     // denominator of f[0] (LAB); {1, 0, ...} otherwise
   int32_t xform, out_mode;
   int32_t decode;  // LAB: float inputs decode BT.709 with the polynomial p[1] (degree <= 7)
-  int32_t pad;
+  float lab_c;     // 16/116, the linear segment's offset (CIELAB, CIELUV), as a value pin_lead can place
 };
 
 // n / d for 32-bit n and a fixed d >= 1: q = (umulhi(n, m) + n) >> s with the
@@ -79,15 +79,17 @@ struct KImage {
 
 // ---------------------------------------------------------------- polynomial
 
-// Moves the leading coefficient of every polynomial into a vector register,
-// once per kernel.  A vector instruction may read one scalar register, so the
-// first Horner step, fma(c[DEG], x, c[DEG-1]), would otherwise need a copy at
-// every evaluation.  Values are unchanged.
+// Moves the leading coefficient of every polynomial, and the linear segment's
+// offset, into vector registers once per kernel.  A vector instruction may read
+// one scalar register or literal, so the first Horner step,
+// fma(c[DEG], x, c[DEG-1]), and the segment fma(7.787, t, 16/116) would
+// otherwise each need a copy at every evaluation.  Values are unchanged.
 template <int DEG>
 __device__ __forceinline__ void pin_lead(KCoef& k) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(k.p[i][DEG]));
   asm volatile("" : "+v"(k.q[DEG]));
+  asm volatile("" : "+v"(k.lab_c));
 }
 
 template <int DEG>
@@ -100,6 +102,18 @@ __device__ __forceinline__ float horner(const float* c, float x) {
 
 // a / b through the hardware reciprocal (about one ulp) and one multiply.
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// Square root through the hardware instruction (about one ulp; the correctly
+// rounded library form costs about 16 instructions).  SMALL: the argument may
+// lie below 2^-96 (tiny float32 inputs), where it is scaled by 2^64 first and
+// the root by 2^-32, both exact; above 2^-96 both forms give the same bits.
+template <bool SMALL>
+__device__ __forceinline__ float fsqrt(float x) {
+  if (!SMALL) return __builtin_amdgcn_sqrtf(x);
+  const bool tiny = x < 0x1p-96f;
+  const float r = __builtin_amdgcn_sqrtf(tiny ? x * 0x1p64f : x);
+  return tiny ? r * 0x1p-32f : r;
+}
 
 // ---------------------------------------------------------------- transforms
 
@@ -116,7 +130,7 @@ __device__ __forceinline__ void lab_f3(const KCoef& k, float lr, float lg, float
     if (t[c] > kT0f)
       f[c] = fdiv(horner<DEG>(k.p[0], t[c]), horner<DEG>(k.q, t[c]));
     else
-      f[c] = __builtin_fmaf(kLabKf, t[c], kLabCf);
+      f[c] = __builtin_fmaf(kLabKf, t[c], k.lab_c);
   }
 }
 
@@ -144,7 +158,7 @@ __device__ __forceinline__ void luv_px(const KCoef& k, float lr, float lg, float
   const float X = __builtin_fmaf(kM00, lr, __builtin_fmaf(kM01, lg, kM02 * lb));
   const float Y = __builtin_fmaf(kM10, lr, __builtin_fmaf(kM11, lg, kM12 * lb));
   const float Z = __builtin_fmaf(kM20, lr, __builtin_fmaf(kM21, lg, kM22 * lb));
-  const float fy = Y > kT0f ? fdiv(horner<DEG>(k.p[0], Y), horner<DEG>(k.q, Y)) : __builtin_fmaf(kLabKf, Y, kLabCf);
+  const float fy = Y > kT0f ? fdiv(horner<DEG>(k.p[0], Y), horner<DEG>(k.q, Y)) : __builtin_fmaf(kLabKf, Y, k.lab_c);
   const float L = __builtin_fmaf(116.0f, fy, -16.0f);
   const float D = __builtin_fmaf(15.0f, Y, __builtin_fmaf(3.0f, Z, X));
   if (!(D > 0.0f)) {
@@ -187,8 +201,10 @@ __device__ __forceinline__ void hsi_px(const KCoef& k, float R, float G, float B
 }
 
 // SCT with the arcsin/arccos/arctan polynomials (Sec. 3.4).  R, G, B on any
-// common scale; `lscale` maps the norm to L on the [0, 1] input scale.
-template <int DEG>
+// common scale; `lscale` maps the norm to L on the [0, 1] input scale.  SMALL
+// = false where neither square-root argument can fall below 2^-96: 8- and
+// 16-bit codes on their integer scales, float16 values.
+template <int DEG, bool SMALL = true>
 __device__ __forceinline__ void sct_px(const KCoef& k, float R, float G, float B, float lscale, float o[3]) {
   const float rg2 = __builtin_fmaf(R, R, G * G);
   const float L2 = __builtin_fmaf(B, B, rg2);
@@ -196,10 +212,10 @@ __device__ __forceinline__ void sct_px(const KCoef& k, float R, float G, float B
     o[0] = 0.0f; o[1] = 0.0f; o[2] = 0.0f;
     return;
   }
-  const float L = __builtin_sqrtf(L2);
+  const float L = fsqrt<SMALL>(L2);
   float A;
   if (3.0f * (B * B) >= rg2) {  // B/L >= 0.5: arccos(B/L) = 2 arcsin(sqrt(1 - B/L) / sqrt 2)
-    const float y = __builtin_sqrtf(fdiv(rg2, L * (L + B)));
+    const float y = fsqrt<SMALL>(fdiv(rg2, L * (L + B)));
     A = horner<DEG>(k.p[0], y);
   } else {
     A = horner<DEG>(k.p[1], fdiv(B, L));
@@ -267,6 +283,15 @@ __device__ __forceinline__ __half f2h_rn(float x) {
   return __float2half_rn(x);
 }
 
+// Two float32 values -> two float16, each rounded to nearest even (the bits of
+// f2h_rn), packed in one word with `a` in the low half: one packed conversion.
+__device__ __forceinline__ uint32_t pack2_h_rn(float a, float b) {
+  asm volatile("" : "+v"(a));
+  asm volatile("" : "+v"(b));
+  const __half2 h = __floats2half2_rn(a, b);
+  return __builtin_bit_cast(uint32_t, h);
+}
+
 __device__ __forceinline__ void store_px(const KImage& im, uint32_t p, const float o3[3]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -322,7 +347,7 @@ __device__ __forceinline__ void px4_u8(const KCoef& k, const float* gtab, uint3 
     if (XF == MACT_LAB) lab_px<DEG>(k, gtab[r], gtab[g], gtab[b], o + 3 * j);
     else if (XF == MACT_LUV) luv_px<DEG>(k, gtab[r], gtab[g], gtab[b], o + 3 * j);
     else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o + 3 * j);
-    else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o + 3 * j);
+    else sct_px<DEG, false>(k, (float)r, (float)g, (float)b, kInv255, o + 3 * j);
   }
 }
 
@@ -348,7 +373,7 @@ __device__ __forceinline__ void px4_u16(const KCoef& k, int gamma, uint3 wa, uin
     } else if (XF == MACT_HSI) {
       hsi_px<DEG>(k, r, g, b, kInv196605, o + 3 * j);
     } else {
-      sct_px<DEG>(k, r, g, b, kInv65535, o + 3 * j);
+      sct_px<DEG, false>(k, r, g, b, kInv65535, o + 3 * j);
     }
   }
 }
@@ -362,7 +387,7 @@ __device__ __forceinline__ void px4_f16(const KCoef& k, int gamma, uint3 wa, uin
     if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(k, r, gamma), lin_float(k, g, gamma), lin_float(k, b, gamma), o + 3 * j);
     else if (XF == MACT_LUV) luv_px<DEG>(k, lin_float(k, r, gamma), lin_float(k, g, gamma), lin_float(k, b, gamma), o + 3 * j);
     else if (XF == MACT_HSI) hsi_px<DEG>(k, r, g, b, kInv3, o + 3 * j);
-    else sct_px<DEG>(k, r, g, b, 1.0f, o + 3 * j);
+    else sct_px<DEG, false>(k, r, g, b, 1.0f, o + 3 * j);
   }
 }
 

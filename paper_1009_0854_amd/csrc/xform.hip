@@ -110,6 +110,7 @@ int pack_coef(const mact_params& p, KCoef* k, int* exact) {
   std::memset(k, 0, sizeof *k);
   k->xform = p.xform;
   k->out_mode = p.out_mode;
+  k->lab_c = kLabCf;
   const int nf = p.xform == MACT_SCT ? 4 : 1;
   int deg = 0;
   for (int i = 0; i < nf; ++i) {
@@ -176,19 +177,28 @@ static unsigned full_grid(uint64_t work_items, int block) {
 // writes bytes 16 l .. 16 l + 15 of each KB: every store instruction covers
 // 1 KB of contiguous output.  Writing the results straight from the lane (a
 // 48-byte stride across the wave) runs at about a third of this bandwidth.
-// Each wave handles kChunksPerWave chunks and the grid covers the image once
-// (no grid-stride loop).  Requires `in` 4-byte and `out` 16-byte aligned;
-// blockDim.x == kHotBlock.
+// Each wave handles hot_cpw(IN, OUT, XF) chunks and the grid covers the image
+// once (no grid-stride loop).  Two chunks per wave keep two loads in flight per
+// lane.  CIELUV from 8-bit input to float32 takes one: its single rational and
+// reciprocal form one long dependent chain per pixel, and with a 12 KB
+// transpose buffer per workgroup the CU holds 8 workgroups instead of 6 (12%
+// faster measured; the same change made CIELAB 3% and the float16-input forms
+// 30% slower).  Requires `in` 4-byte and `out` 16-byte aligned; blockDim.x ==
+// kHotBlock.
 constexpr int kHotBlock = 256;
 constexpr int kChunksPerWave = 2;
 constexpr int kHotWaves = kHotBlock / 64;
+constexpr int hot_cpw(int in, int out, int xf) {
+  return (xf == MACT_LUV && in == MACT_U8 && out == MACT_F32) ? 1 : kChunksPerWave;
+}
 
 template <int IN, int OUT, int DEG, int XF>
 __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in, void* __restrict__ out,
                                                      uint32_t n_px, KCoef k, int gamma) {
   constexpr int WPC = IN == MACT_U8 ? 1 : 2;      // 12-byte words per lane per chunk (16-bit inputs: 2)
   constexpr uint32_t F4PC = OUT == MACT_F32 ? 192 : 96;  // 16-byte output words per chunk
-  __shared__ f4 s_out[kHotWaves][kChunksPerWave * 192];
+  constexpr int CPW = hot_cpw(IN, OUT, XF);
+  __shared__ f4 s_out[kHotWaves][CPW * F4PC];
   __shared__ float gtab[256];
   if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
     for (uint32_t i = threadIdx.x; i < 256u; i += kHotBlock) gtab[i] = k_gamma_table[gamma][i];
@@ -198,16 +208,16 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
   const uint3* win = reinterpret_cast<const uint3*>(in);
   const uint32_t n_chunks = n_px >> 8;
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-  const uint32_t c0 = (blockIdx.x * kHotWaves + wv) * kChunksPerWave;
+  const uint32_t c0 = (blockIdx.x * kHotWaves + wv) * CPW;
   if (c0 < n_chunks) {
-    uint3 w[kChunksPerWave][WPC];
+    uint3 w[CPW][WPC];
 #pragma unroll
-    for (int j = 0; j < kChunksPerWave; ++j)
+    for (int j = 0; j < CPW; ++j)
       if (c0 + j < n_chunks)
 #pragma unroll
         for (int q = 0; q < WPC; ++q) w[j][q] = win[((size_t)(c0 + j) * 64 + lane) * WPC + q];
 #pragma unroll
-    for (int j = 0; j < kChunksPerWave; ++j) {
+    for (int j = 0; j < CPW; ++j) {
       if (c0 + j >= n_chunks) break;
       float o[12];
       if (IN == MACT_U8) px4_u8<XF, DEG>(k, gtab, w[j][0], o);
@@ -222,10 +232,8 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
         f2* s2 = reinterpret_cast<f2*>(&s_out[wv][0]);
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
-          const uint32_t lo = (uint32_t)__half_as_ushort(f2h_rn(o[4 * t])) |
-                              ((uint32_t)__half_as_ushort(f2h_rn(o[4 * t + 1])) << 16);
-          const uint32_t hi = (uint32_t)__half_as_ushort(f2h_rn(o[4 * t + 2])) |
-                              ((uint32_t)__half_as_ushort(f2h_rn(o[4 * t + 3])) << 16);
+          const uint32_t lo = pack2_h_rn(o[4 * t], o[4 * t + 1]);
+          const uint32_t hi = pack2_h_rn(o[4 * t + 2], o[4 * t + 3]);
           s2[j * 192 + 3 * lane + t] = f2{__uint_as_float(lo), __uint_as_float(hi)};
         }
       }
@@ -234,10 +242,11 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
     __builtin_amdgcn_wave_barrier();
-    const uint32_t n_valid = min((uint32_t)kChunksPerWave, n_chunks - c0) * F4PC;
+    const uint32_t n_valid = min((uint32_t)CPW, n_chunks - c0) * F4PC;
     f4* dst = reinterpret_cast<f4*>(out) + (size_t)c0 * F4PC;
+    static_assert((CPW * F4PC) % 64 == 0, "whole 1 KB stores per wave");
 #pragma unroll
-    for (int q = 0; q < (int)(kChunksPerWave * F4PC / 64); ++q) {
+    for (int q = 0; q < (int)(CPW * F4PC / 64); ++q) {
       const uint32_t e = q * 64 + lane;
       if (e < n_valid) __builtin_nontemporal_store(s_out[wv][e], dst + e);
     }
@@ -253,7 +262,7 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
       if (XF == MACT_LAB) lab_px<DEG>(k, gtab[r], gtab[g], gtab[b], o);
       else if (XF == MACT_LUV) luv_px<DEG>(k, gtab[r], gtab[g], gtab[b], o);
       else if (XF == MACT_HSI) hsi_px<DEG>(k, (float)r, (float)g, (float)b, kInv765, o);
-      else sct_px<DEG>(k, (float)r, (float)g, (float)b, kInv255, o);
+      else sct_px<DEG, false>(k, (float)r, (float)g, (float)b, kInv255, o);
     } else if (IN == MACT_U16) {
       const uint16_t* c16 = static_cast<const uint16_t*>(in);
       const float r = (float)c16[3 * p], g = (float)c16[3 * p + 1], b = (float)c16[3 * p + 2];
@@ -265,7 +274,7 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
       } else if (XF == MACT_HSI) {
         hsi_px<DEG>(k, r, g, b, kInv196605, o);
       } else {
-        sct_px<DEG>(k, r, g, b, kInv65535, o);
+        sct_px<DEG, false>(k, r, g, b, kInv65535, o);
       }
     } else {
       const __half* h = static_cast<const __half*>(in);
@@ -274,7 +283,7 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
       if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(k, r, gamma), lin_float(k, g, gamma), lin_float(k, b, gamma), o);
       else if (XF == MACT_LUV) luv_px<DEG>(k, lin_float(k, r, gamma), lin_float(k, g, gamma), lin_float(k, b, gamma), o);
       else if (XF == MACT_HSI) hsi_px<DEG>(k, r, g, b, kInv3, o);
-      else sct_px<DEG>(k, r, g, b, 1.0f, o);
+      else sct_px<DEG, false>(k, r, g, b, 1.0f, o);
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -286,8 +295,8 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
 
 // Blocks of k_hwc4 for n_px pixels: every full chunk covered once, and at
 // least one block for the tail.
-static unsigned hot_grid(uint32_t n_px) {
-  const uint32_t per_block = kHotWaves * kChunksPerWave;
+static unsigned hot_grid(uint32_t n_px, int cpw = kChunksPerWave) {
+  const uint32_t per_block = kHotWaves * cpw;
   return std::max<unsigned>(1, ((n_px >> 8) + per_block - 1) / per_block);
 }
 
@@ -324,7 +333,7 @@ __global__ __launch_bounds__(256) void k_chw4(const void* __restrict__ in, float
       if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(k, v[0][j], gamma), lin_float(k, v[1][j], gamma), lin_float(k, v[2][j], gamma), r);
       else if (XF == MACT_LUV) luv_px<DEG>(k, lin_float(k, v[0][j], gamma), lin_float(k, v[1][j], gamma), lin_float(k, v[2][j], gamma), r);
       else if (XF == MACT_HSI) hsi_px<DEG>(k, v[0][j], v[1][j], v[2][j], kInv3, r);
-      else sct_px<DEG>(k, v[0][j], v[1][j], v[2][j], 1.0f, r);
+      else sct_px<DEG, IN == MACT_F32>(k, v[0][j], v[1][j], v[2][j], 1.0f, r);
       o[0][j] = r[0]; o[1][j] = r[1]; o[2][j] = r[2];
     }
 #pragma unroll
@@ -486,7 +495,7 @@ __global__ __launch_bounds__(256) void k_copy16(const f4* __restrict__ in, f4* _
 template <int IN, int OUT, int DEG>
 static void launch_hwc4(int xform, const void* in, void* out, uint32_t n_px, const KCoef& k, int gamma,
                         hipStream_t st) {
-  const dim3 grid(hot_grid(n_px)), blk(kHotBlock);
+  const dim3 grid(hot_grid(n_px, hot_cpw(IN, OUT, xform))), blk(kHotBlock);
   if (xform == MACT_LAB) hipLaunchKernelGGL((k_hwc4<IN, OUT, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, k, gamma);
   else if (xform == MACT_HSI) hipLaunchKernelGGL((k_hwc4<IN, OUT, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, k, gamma);
   else if (xform == MACT_LUV) hipLaunchKernelGGL((k_hwc4<IN, OUT, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, k, gamma);
