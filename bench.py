@@ -139,6 +139,31 @@ def bench_4k(M, p, steps):
     return res
 
 
+def bench_general(M, x, y, p, n_px, steps):
+    """CIELAB on layouts other than packed HWC: the 8-bit batch as a
+    row-padded view (rows 8 pixels apart beyond their width; the row-strided
+    kernel) into packed float32 HWC, and as CHW planes into HWC (the
+    one-pixel-per-lane kernel) and into CHW (the CHW kernel).  15 bytes per
+    pixel."""
+    import torch
+    out = {}
+    n, h, w, _ = x.shape
+    pad = torch.empty((n, h, w + 8, 3), dtype=torch.uint8, device="cuda")
+    pad[:, :, :w] = x
+    view = pad[:, :, :w]
+    ms, _ = time_kernel(lambda: M.transform(view, params=p, out=y), steps)
+    out["u8_row_padded_view"] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
+    del pad, view
+    chw = x.permute(0, 3, 1, 2).contiguous()
+    ms, _ = time_kernel(lambda: M.transform(chw, params=p, layout="chw", out=y, out_layout="hwc"), steps)
+    out["u8_chw_to_hwc"] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
+    ychw = y.view(n, 3, h, w)
+    ms, _ = time_kernel(lambda: M.transform(chw, params=p, layout="chw", out=ychw, out_layout="chw"), steps)
+    out["u8_chw_to_chw"] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
+    del chw, ychw
+    return out
+
+
 def bench_inverse(M, x, y, n_px, steps):
     """Inverse MACT (L*a*b* / HSI / SCT / L*u*v* float32 -> R'G'B' float32, 24 bytes per
     pixel) on the forward output of the batch, and the on-device error
@@ -444,6 +469,8 @@ def main():
         del x16u
         log("4K batch")
         forms["lab_32x4k"] = bench_4k(M, p_lab, a.steps)
+        log("general path")
+        forms["general_path"] = bench_general(M, x, y, p_lab, n_px, a.steps)
         # each rate beside its accuracy: the paper's metric (D_HSI for HSI, the inverse-SCT Delta E*ab
         # for SCT, Delta E*uv for CIELUV) over all 2^24 8-bit colours, on the device
         cube = torch.from_numpy(synth.cube_u8()).cuda()

@@ -379,18 +379,23 @@ static mact_status plan_autotune(mact_batch_plan* p) {
   static const int vecs[] = {4, 1};
   static const int waves[] = {16, 32, 0};
   // every candidate timed 3 times (best of), then the 4 fastest 8 times more
-  std::vector<std::pair<float, mact_tune>> timed;
+  std::vector<mact_tune> cands;
   for (int v : vecs)
     for (int b : blocks)
       for (int t : tiles)
-        for (int w : waves) {
-          p->tune = mact_tune{b, t, v, w};
-          mact_status s = plan_set_tiles(p);
-          if (s != MACT_OK) return s;
-          float ms = INFINITY;
-          if ((s = plan_time(p, 3, &ms)) != MACT_OK) return s;
-          timed.emplace_back(ms, p->tune);
-        }
+        for (int w : waves) cands.push_back(mact_tune{b, t, v, w});
+  // one workgroup per small tile: one or two 256-pixel chunks per wave, the plain kernel's shape
+  for (int b : {256, 512})
+    for (int t : {2048, 4096}) cands.push_back(mact_tune{b, t, 4, 0});
+  std::vector<std::pair<float, mact_tune>> timed;
+  for (const mact_tune& c : cands) {
+    p->tune = c;
+    mact_status s = plan_set_tiles(p);
+    if (s != MACT_OK) return s;
+    float ms = INFINITY;
+    if ((s = plan_time(p, 3, &ms)) != MACT_OK) return s;
+    timed.emplace_back(ms, p->tune);
+  }
   std::stable_sort(timed.begin(), timed.end(),
                    [](const std::pair<float, mact_tune>& a, const std::pair<float, mact_tune>& b) { return a.first < b.first; });
   mact_tune best = timed.front().second;

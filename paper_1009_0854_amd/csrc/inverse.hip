@@ -497,7 +497,7 @@ extern "C" mact_status mact_inverse(const mact_params* params, const mact_image*
       if (deg == 5) launch_inverse4<5>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
       else launch_inverse4<7>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
     } else {
-      const dim3 grid(grid_256(n_px, 8)), blk(256);
+      const dim3 grid(std::max<uint32_t>(1, (n_px + 255) / 256)), blk(256);
       if (deg == 5) hipLaunchKernelGGL(k_inverse<5>, grid, blk, 0, st, ks, kd, n_px, k, mi, gamma);
       else hipLaunchKernelGGL(k_inverse<7>, grid, blk, 0, st, ks, kd, n_px, k, mi, gamma);
     }

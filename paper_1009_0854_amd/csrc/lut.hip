@@ -377,8 +377,11 @@ static hipError_t launch_lut(const f4* lut, uint32_t N, const HostImage& hi, con
   const bool lds = !CELL && bytes <= lds_max;
   const unsigned block = lds ? 1024 : 256;
   const uint64_t need = (n_px + block - 1) / block;
-  const uint64_t per_cu = lds ? std::max<uint64_t>(1, std::min<uint64_t>(2, lds_max / bytes)) : 8;
-  const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(need, (uint64_t)device_cus() * per_cu));
+  // a staged grid: one or two resident workgroups per CU stride over the image; otherwise the grid
+  // covers the image once
+  const uint64_t per_cu = std::max<uint64_t>(1, std::min<uint64_t>(2, lds_max / std::max<size_t>(bytes, 1)));
+  const unsigned grid = (unsigned)std::max<uint64_t>(1, lds ? std::min<uint64_t>(need, (uint64_t)device_cus() * per_cu)
+                                                            : std::min<uint64_t>(need, 0x7fffffffu));
   if (lds) {
     auto k = k_lut<METHOD, XF, true, false>;
     hipError_t e = allow_lds(k, bytes);

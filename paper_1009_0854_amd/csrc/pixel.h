@@ -322,6 +322,24 @@ __device__ __forceinline__ void eval_px(const KCoef& k, int dtype, int gamma, co
   }
 }
 
+// eval_px with the element type and the transform fixed at compile time: the
+// same arithmetic, so the same bits.
+template <int IN, int XF, int DEG>
+__device__ __forceinline__ void px1(const KCoef& k, int gamma, const float* gtab, const float v[3], float o[3]) {
+  if (XF == MACT_LAB || XF == MACT_LUV) {
+    float l[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      l[c] = IN == MACT_U8 ? gtab[(int)v[c]] : lin_float(k, IN == MACT_U16 ? v[c] * kInv65535 : v[c], gamma);
+    if (XF == MACT_LAB) lab_px<DEG>(k, l[0], l[1], l[2], o);
+    else luv_px<DEG>(k, l[0], l[1], l[2], o);
+  } else if (XF == MACT_HSI) {
+    hsi_px<DEG>(k, v[0], v[1], v[2], IN == MACT_U8 ? kInv765 : IN == MACT_U16 ? kInv196605 : kInv3, o);
+  } else {
+    sct_px<DEG, IN == MACT_F32>(k, v[0], v[1], v[2], IN == MACT_U8 ? kInv255 : IN == MACT_U16 ? kInv65535 : 1.0f, o);
+  }
+}
+
 // ---------------------------------------------------------------- 4-pixel groups
 
 // Byte i (0..11) of 12 bytes held as one 12-byte word.

@@ -5,7 +5,9 @@
 //  * k_hwc4: the hot path, packed 8-bit (or float16) HWC in and packed
 //    float32 (or float16) HWC out, staged through LDS so that every global
 //    store is a contiguous run of 1 KB per wave (details at the kernel).
-//  * k_chw4: packed float32 / float16 CHW, 4 pixels per lane, vector access
+//  * k_rows4: row-strided HWC views (crops, pitched rows), k_hwc4's pattern
+//    per 256-pixel run of a row.
+//  * k_chw4: packed CHW of any input type, 4 pixels per lane, vector access
 //    per plane.
 //  * k_generic: any element type, layout and stride, one pixel per lane step.
 // All call the same per-pixel functions (pixel.h), so they give identical bits.
@@ -150,12 +152,6 @@ int device_cus() {
   return cus;
 }
 
-static unsigned grid_for(uint64_t work_items, int block, int blocks_per_cu) {
-  const uint64_t need = (work_items + block - 1) / block;
-  const uint64_t cap = (uint64_t)device_cus() * blocks_per_cu;
-  return (unsigned)std::max<uint64_t>(1, std::min(need, cap));
-}
-
 // One work item per thread: the grid covers the work once.  Streaming kernels
 // run 4-26% faster this way than with a few resident workgroups per CU
 // striding over the work.
@@ -293,6 +289,64 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
   }
 }
 
+// Row-strided HWC (a view whose rows or images are not adjacent: a crop, a
+// pitched allocation) -> packed float32 HWC, W a multiple of 4.  Every row is
+// cut into 256-pixel chunks, the last one partial, one chunk per wave; each
+// chunk takes k_hwc4's 12-byte loads (lanes past the row's end idle), its
+// per-pixel code and its LDS-transposed 1 KB stores.  Requires the input
+// pointer and both strides (in bytes) to be multiples of 4 and `out` 16-byte
+// aligned.
+struct RowGeom {
+  uint32_t W, cpr, H;      // pixels per row, chunks per row, rows per image
+  FastDiv div_cpr, div_h;  // chunk -> row, row -> image
+  uint64_t rs_b, bs_b;     // input row and image strides in bytes
+};
+
+template <int IN, int DEG, int XF>
+__global__ __launch_bounds__(kHotBlock) void k_rows4(const uint8_t* __restrict__ in, float* __restrict__ out,
+                                                     uint32_t n_chunks, RowGeom g, KCoef k, int gamma) {
+  constexpr int WPC = IN == MACT_U8 ? 1 : 2;  // 12-byte words per lane (16-bit inputs: 2)
+  __shared__ f4 s_out[kHotWaves][192];
+  __shared__ float gtab[256];
+  if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
+    for (uint32_t i = threadIdx.x; i < 256u; i += kHotBlock) gtab[i] = k_gamma_table[gamma][i];
+    __syncthreads();
+  }
+  pin_lead<DEG>(k);
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t c = blockIdx.x * kHotWaves + wv;
+  if (c >= n_chunks) return;  // no block-wide barrier follows
+  const uint32_t r = g.div_cpr.div(c), j = c - r * g.cpr;
+  const uint32_t n = g.div_h.div(r), y = r - n * g.H;
+  const uint32_t px0 = j * 256u, cnt = min(256u, g.W - px0);  // cnt: a multiple of 4
+  const uint3* row = reinterpret_cast<const uint3*>(in + n * g.bs_b + y * g.rs_b + (uint64_t)px0 * 3u * WPC);
+  float o[12];
+  if (4u * lane < cnt) {
+    uint3 w[WPC];
+#pragma unroll
+    for (int q = 0; q < WPC; ++q) w[q] = row[lane * WPC + q];
+    if (IN == MACT_U8) px4_u8<XF, DEG>(k, gtab, w[0], o);
+    else if (IN == MACT_U16) px4_u16<XF, DEG>(k, gamma, w[0], w[WPC - 1], o);
+    else px4_f16<XF, DEG>(k, gamma, w[0], w[WPC - 1], o);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) o[q] = 0.0f;
+  }
+  s_out[wv][3 * lane] = f4{o[0], o[1], o[2], o[3]};
+  s_out[wv][3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
+  s_out[wv][3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): every lane's LDS writes have landed
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t n_valid = cnt / 4u * 3u;  // 16-byte words of the chunk's output
+  f4* dst = reinterpret_cast<f4*>(out) + ((uint64_t)r * g.W + px0) / 4u * 3u;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const uint32_t e = q * 64 + lane;
+    if (e < n_valid) __builtin_nontemporal_store(s_out[wv][e], dst + e);
+  }
+}
+
 // Blocks of k_hwc4 for n_px pixels: every full chunk covered once, and at
 // least one block for the tail.
 static unsigned hot_grid(uint32_t n_px, int cpw = kChunksPerWave) {
@@ -300,40 +354,51 @@ static unsigned hot_grid(uint32_t n_px, int cpw = kChunksPerWave) {
   return std::max<unsigned>(1, ((n_px >> 8) + per_block - 1) / per_block);
 }
 
-// Packed CHW (float32 or float16) -> packed float32 CHW, 4 pixels per lane:
-// one 16-byte (8-byte for float16) load per plane and one 16-byte store per
-// plane, each contiguous across the wave.  Requires W H % 4 == 0 and the
-// pointers aligned to the vector width.
+// Packed CHW (float32, float16, 16-bit or 8-bit) -> packed float32 CHW, 4
+// pixels per lane: one 16-, 8- or 4-byte load per plane and one 16-byte store
+// per plane, each contiguous across the wave.  Requires W H % 4 == 0 and the
+// input pointer aligned to 4 elements.
 template <int IN, int DEG, int XF>
 __global__ __launch_bounds__(256) void k_chw4(const void* __restrict__ in, float* __restrict__ out, uint32_t n_px,
                                                uint32_t hw, FastDiv div_hw4, KCoef k, int gamma) {
+  __shared__ float gtab[256];
+  if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
+    for (uint32_t i = threadIdx.x; i < 256u; i += 256u) gtab[i] = k_gamma_table[gamma][i];
+    __syncthreads();
+  }
+  pin_lead<DEG>(k);
   const uint32_t n4 = n_px >> 2, hw4 = hw >> 2;
   const uint32_t stride = gridDim.x * 256u;
   for (uint32_t g4 = blockIdx.x * 256u + threadIdx.x; g4 < n4; g4 += stride) {
     const uint32_t n = div_hw4.div(g4);
     const size_t base = (size_t)n * 3 * hw + 4 * (size_t)(g4 - n * hw4);  // element offset of plane 0
-    float v[3][4];
+    float v[4][3];  // raw values, as load_px returns them
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (IN == MACT_F32) {
         const f4 x = *reinterpret_cast<const f4*>(static_cast<const float*>(in) + base + (size_t)c * hw);
-        v[c][0] = clamp01(x.x); v[c][1] = clamp01(x.y); v[c][2] = clamp01(x.z); v[c][3] = clamp01(x.w);
-      } else {
+        v[0][c] = clamp01(x.x); v[1][c] = clamp01(x.y); v[2][c] = clamp01(x.z); v[3][c] = clamp01(x.w);
+      } else if (IN == MACT_F16) {
         const uint2 x = *reinterpret_cast<const uint2*>(static_cast<const __half*>(in) + base + (size_t)c * hw);
-        v[c][0] = clamp01(__half2float(__ushort_as_half((uint16_t)x.x)));
-        v[c][1] = clamp01(__half2float(__ushort_as_half((uint16_t)(x.x >> 16))));
-        v[c][2] = clamp01(__half2float(__ushort_as_half((uint16_t)x.y)));
-        v[c][3] = clamp01(__half2float(__ushort_as_half((uint16_t)(x.y >> 16))));
+        v[0][c] = clamp01(__half2float(__ushort_as_half((uint16_t)x.x)));
+        v[1][c] = clamp01(__half2float(__ushort_as_half((uint16_t)(x.x >> 16))));
+        v[2][c] = clamp01(__half2float(__ushort_as_half((uint16_t)x.y)));
+        v[3][c] = clamp01(__half2float(__ushort_as_half((uint16_t)(x.y >> 16))));
+      } else if (IN == MACT_U16) {
+        const uint2 x = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(in) + base + (size_t)c * hw);
+        v[0][c] = (float)(x.x & 0xffffu); v[1][c] = (float)(x.x >> 16);
+        v[2][c] = (float)(x.y & 0xffffu); v[3][c] = (float)(x.y >> 16);
+      } else {
+        const uint32_t x = *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(in) + base + (size_t)c * hw);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j][c] = (float)((x >> (8 * j)) & 0xffu);
       }
     }
     float o[3][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       float r[3];
-      if (XF == MACT_LAB) lab_px<DEG>(k, lin_float(k, v[0][j], gamma), lin_float(k, v[1][j], gamma), lin_float(k, v[2][j], gamma), r);
-      else if (XF == MACT_LUV) luv_px<DEG>(k, lin_float(k, v[0][j], gamma), lin_float(k, v[1][j], gamma), lin_float(k, v[2][j], gamma), r);
-      else if (XF == MACT_HSI) hsi_px<DEG>(k, v[0][j], v[1][j], v[2][j], kInv3, r);
-      else sct_px<DEG, IN == MACT_F32>(k, v[0][j], v[1][j], v[2][j], 1.0f, r);
+      px1<IN, XF, DEG>(k, gamma, gtab, v[j], r);
       o[0][j] = r[0]; o[1][j] = r[1]; o[2][j] = r[2];
     }
 #pragma unroll
@@ -348,6 +413,7 @@ __global__ __launch_bounds__(256) void k_generic(KImage src, KImage dst, uint32_
   __shared__ float gtab[256];
   gtab[threadIdx.x] = k_gamma_table[gamma][threadIdx.x];
   __syncthreads();
+  pin_lead<DEG>(k);
   const uint32_t stride = gridDim.x * 256u;
   for (uint32_t p = blockIdx.x * 256u + threadIdx.x; p < n_px; p += stride) {
     float v[3], o[3];
@@ -519,6 +585,25 @@ static void launch_hwc4_io(int xform, int out_dtype, int deg, const void* in, vo
 }
 
 template <int IN, int DEG>
+static void launch_rows4_deg(int xform, const void* in, float* out, uint32_t n_chunks, const RowGeom& g,
+                             const KCoef& k, int gamma, hipStream_t st) {
+  const dim3 grid(std::max<uint32_t>(1, (n_chunks + kHotWaves - 1) / kHotWaves)), blk(kHotBlock);
+  const uint8_t* i8 = static_cast<const uint8_t*>(in);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_rows4<IN, DEG, MACT_LAB>), grid, blk, 0, st, i8, out, n_chunks, g, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_rows4<IN, DEG, MACT_HSI>), grid, blk, 0, st, i8, out, n_chunks, g, k, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_rows4<IN, DEG, MACT_LUV>), grid, blk, 0, st, i8, out, n_chunks, g, k, gamma);
+  else hipLaunchKernelGGL((k_rows4<IN, DEG, MACT_SCT>), grid, blk, 0, st, i8, out, n_chunks, g, k, gamma);
+}
+
+template <int IN>
+static void launch_rows4(int xform, int deg, const void* in, float* out, uint32_t n_chunks, const RowGeom& g,
+                         const KCoef& k, int gamma, hipStream_t st) {
+  if (deg <= 4) launch_rows4_deg<IN, 4>(xform, in, out, n_chunks, g, k, gamma, st);
+  else if (deg == 5) launch_rows4_deg<IN, 5>(xform, in, out, n_chunks, g, k, gamma, st);
+  else launch_rows4_deg<IN, 7>(xform, in, out, n_chunks, g, k, gamma, st);
+}
+
+template <int IN, int DEG>
 static void launch_chw4(int xform, const void* in, float* out, uint32_t n_px, uint32_t hw, const KCoef& k, int gamma,
                         hipStream_t st) {
   const dim3 grid(full_grid(n_px / 4, 256)), blk(256);
@@ -549,13 +634,18 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   const int deg = pack_coef(*params, &k, &exact_deg);
   const int gamma = uses_gamma(params->xform) ? hi.gamma : MACT_GAMMA_NONE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  // fast shapes: packed 8-bit / float16 HWC -> packed float32 / float16 HWC, and packed float32 /
-  // float16 CHW -> packed float32 CHW with W H a multiple of 4; everything else takes k_generic
+  // fast shapes: packed 8-bit / float16 / 16-bit HWC -> packed float32 / float16 HWC, row-strided HWC
+  // -> packed float32 HWC, and packed CHW of any input type -> packed float32 CHW with W H a
+  // multiple of 4; everything else takes k_generic
   const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
                     hi.packed &&
                     (ho.dtype == MACT_F32 || ho.dtype == MACT_F16) && ho.layout == MACT_HWC && ho.packed;
-  const bool chw4 = (hi.dtype == MACT_F32 || hi.dtype == MACT_F16) && hi.layout == MACT_CHW && hi.packed &&
+  const bool chw4 = hi.layout == MACT_CHW && hi.packed &&
                     ho.dtype == MACT_F32 && ho.layout == MACT_CHW && ho.packed && (hi.W * hi.H) % 4 == 0;
+  // row-strided 8-bit / float16 / 16-bit HWC -> packed float32 HWC, rows of a multiple of 4 pixels
+  const bool rows4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
+                     !hi.packed && ho.dtype == MACT_F32 && ho.layout == MACT_HWC && ho.packed && hi.W % 4 == 0 &&
+                     (hi.rs * (int64_t)hi.esize) % 4 == 0 && (hi.bs * (int64_t)hi.esize) % 4 == 0;
   const int64_t per = images_per_launch(hi);
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
@@ -566,18 +656,39 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
       if (hi.dtype == MACT_U8) launch_hwc4_io<MACT_U8>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
       else if (hi.dtype == MACT_U16) launch_hwc4_io<MACT_U16>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
       else launch_hwc4_io<MACT_F16>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
+    } else if (rows4 && aligned(ip, 4) && aligned(op, 16)) {
+      RowGeom g;
+      g.W = (uint32_t)hi.W;
+      g.H = (uint32_t)hi.H;
+      g.cpr = (g.W + 255u) / 256u;
+      g.div_cpr = make_fastdiv(g.cpr);
+      g.div_h = make_fastdiv(g.H);
+      g.rs_b = (uint64_t)hi.rs * hi.esize;
+      g.bs_b = (uint64_t)hi.bs * hi.esize;
+      const uint32_t n_chunks = (uint32_t)(cnt * hi.H) * g.cpr;
+      float* of = static_cast<float*>(op);
+      if (hi.dtype == MACT_U8) launch_rows4<MACT_U8>(params->xform, exact_deg, ip, of, n_chunks, g, k, gamma, st);
+      else if (hi.dtype == MACT_U16) launch_rows4<MACT_U16>(params->xform, exact_deg, ip, of, n_chunks, g, k, gamma, st);
+      else launch_rows4<MACT_F16>(params->xform, exact_deg, ip, of, n_chunks, g, k, gamma, st);
     } else if (chw4 && aligned(ip, 4 * hi.esize) && aligned(op, 16)) {
       const uint32_t hw = (uint32_t)(hi.W * hi.H);
+      float* of = static_cast<float*>(op);
       if (hi.dtype == MACT_F32) {
-        if (deg == 5) launch_chw4<MACT_F32, 5>(params->xform, ip, static_cast<float*>(op), n_px, hw, k, gamma, st);
-        else launch_chw4<MACT_F32, 7>(params->xform, ip, static_cast<float*>(op), n_px, hw, k, gamma, st);
+        if (deg == 5) launch_chw4<MACT_F32, 5>(params->xform, ip, of, n_px, hw, k, gamma, st);
+        else launch_chw4<MACT_F32, 7>(params->xform, ip, of, n_px, hw, k, gamma, st);
+      } else if (hi.dtype == MACT_F16) {
+        if (deg == 5) launch_chw4<MACT_F16, 5>(params->xform, ip, of, n_px, hw, k, gamma, st);
+        else launch_chw4<MACT_F16, 7>(params->xform, ip, of, n_px, hw, k, gamma, st);
+      } else if (hi.dtype == MACT_U16) {
+        if (deg == 5) launch_chw4<MACT_U16, 5>(params->xform, ip, of, n_px, hw, k, gamma, st);
+        else launch_chw4<MACT_U16, 7>(params->xform, ip, of, n_px, hw, k, gamma, st);
       } else {
-        if (deg == 5) launch_chw4<MACT_F16, 5>(params->xform, ip, static_cast<float*>(op), n_px, hw, k, gamma, st);
-        else launch_chw4<MACT_F16, 7>(params->xform, ip, static_cast<float*>(op), n_px, hw, k, gamma, st);
+        if (deg == 5) launch_chw4<MACT_U8, 5>(params->xform, ip, of, n_px, hw, k, gamma, st);
+        else launch_chw4<MACT_U8, 7>(params->xform, ip, of, n_px, hw, k, gamma, st);
       }
     } else {
       const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
-      const unsigned grid = grid_for(n_px, 256, 8);
+      const unsigned grid = full_grid(n_px, 256);
       if (deg == 5) hipLaunchKernelGGL(k_generic<5>, dim3(grid), dim3(256), 0, st, ks, kd, n_px, k, gamma);
       else hipLaunchKernelGGL(k_generic<7>, dim3(grid), dim3(256), 0, st, ks, kd, n_px, k, gamma);
     }
@@ -629,7 +740,7 @@ extern "C" mact_status mact_transform_backward(const mact_params* params, const 
       else hipLaunchKernelGGL(k_lab_backward_chw4<7>, grid, dim3(256), 0, st, xp, gp, dp, n_px, hw, d, k, kg);
     } else {
       const KImage kx = kimage(hx, n0, cnt), kgo = kimage(hg, n0, cnt), kd = kimage(hd, n0, cnt);
-      const unsigned grid = grid_for(n_px, 256, 8);
+      const unsigned grid = full_grid(n_px, 256);
       if (deg == 5) hipLaunchKernelGGL(k_lab_backward<5>, dim3(grid), dim3(256), 0, st, kx, kgo, kd, n_px, k, kg);
       else hipLaunchKernelGGL(k_lab_backward<7>, dim3(grid), dim3(256), 0, st, kx, kgo, kd, n_px, k, kg);
     }

@@ -166,6 +166,59 @@ def test_lab_gamma_options_on_float_input(M):
         P.assert_parity(0, gpu, P.oracle(0, img / 255.0, P.coeffs(p), gamma=gamma), what="u8 " + gamma)
 
 
+VIEW_CASES = [  # (images, rows, width, row padding px, padding rows per image)
+    (2, 3, 4, 0, 1), (1, 5, 256, 4, 0), (3, 7, 260, 12, 2), (2, 4, 1000, 8, 0), (1, 2, 1028, 4, 3),
+    (2, 3, 20, 3, 0),  # rows of 23 pixels: an 8-bit row stride that is not a multiple of 4 bytes
+    (1, 3, 18, 2, 0),  # a width that is not a multiple of 4
+]
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f16", "u16"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
+def test_row_strided_views_equal_packed(M, dtype, xform):
+    # crops of padded rows and images (the row-strided kernel where rows hold a multiple of 4 pixels
+    # and the strides are whole words, the one-pixel kernel otherwise) give the packed input's bits
+    g = synth.rng(200 + xform)
+    pars = [M.default_params(xform), M.make_params(xform, [M.paper_approx(M.FN_CBRT, 4, 4)])] if xform in (0, 3) \
+        else [M.default_params(xform)]
+    if xform in (0, 3) and dtype != "u8":
+        pars.append(M.default_params(xform, decode=True))
+    for (n, h, w, rpad, ipad) in VIEW_CASES:
+        shape = (n, h + ipad, w + rpad, 3)
+        if dtype == "u8":
+            base = g.integers(0, 256, shape).astype(np.uint8)
+        elif dtype == "u16":
+            base = g.integers(0, 65536, shape).astype(np.uint16)
+        else:
+            base = g.random(shape).astype(np.float16)
+        view = torch.from_numpy(base).cuda()[:, :h, :w]
+        packed = torch.from_numpy(np.ascontiguousarray(base[:, :h, :w])).cuda()
+        for p in pars:
+            for gm in (["bt709", "none"] if xform in (0, 3) else ["none"]):
+                a = M.transform(view, xform=xform, params=p, gamma=gm)
+                b = M.transform(packed, xform=xform, params=p, gamma=gm)
+                torch.cuda.synchronize()
+                assert torch.equal(a, b), (n, h, w, rpad, ipad, gm)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
+def test_integer_chw_equals_packed_hwc(M, dtype, xform):
+    # 8- and 16-bit CHW planes (the CHW kernel where W H is a multiple of 4, the one-pixel kernel
+    # otherwise) give the bits of the packed HWC input, plane by plane
+    g = synth.rng(300 + xform)
+    for (n, h, w) in [(2, 16, 20), (1, 33, 36), (3, 8, 1000), (1, 7, 9)]:
+        hwc = g.integers(0, 256 if dtype == "u8" else 65536, (n, h, w, 3)).astype(np.uint8 if dtype == "u8" else np.uint16)
+        chw = torch.from_numpy(np.ascontiguousarray(np.moveaxis(hwc, -1, 1))).cuda()
+        x = torch.from_numpy(hwc).cuda()
+        for gm in (["bt709", "srgb", "none"] if xform in (0, 3) else ["none"]):
+            p = M.default_params(xform)
+            a = M.transform(chw, xform=xform, params=p, layout="chw", gamma=gm)
+            b = M.transform(x, xform=xform, params=p, gamma=gm)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm)
+
+
 def test_strided_views(M):
     # a row-strided HWC view and a non-packed output take the general kernel: same values
     img = synth.uniform_u8(64, 80, seed=5)
