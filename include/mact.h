@@ -200,10 +200,15 @@ mact_status mact_params_default(int32_t xform, mact_params* p);
           v' = 9Y / D with D = X + 15Y + 3Z, u* = 13 L* (u' - u'n),
           v* = 13 L* (v' - v'n) with the D65 white's u'n, v'n; D = 0 (black)
           gives u* = v* = 0.
-   in: MACT_U8 / MACT_F16 / MACT_F32, HWC or CHW.  out: MACT_F32 or MACT_F16,
-   HWC or CHW, same width, height and batch as `in`.  Evaluation is float32 with
-   explicit fused multiply-adds; the result does not depend on the launch
-   configuration, so every form (plain, batched, served) gives identical bits.
+   in: MACT_U8 / MACT_U16 / MACT_F16 / MACT_F32, HWC or CHW, any strides.  out:
+   MACT_F32 or MACT_F16, HWC or CHW, same width, height and batch as `in`.
+   Evaluation is float32 with explicit fused multiply-adds; the result does not
+   depend on the layout or the launch configuration, so every form (plain,
+   batched, served) gives identical bits.  Coalesced kernels serve packed HWC
+   in (8-bit, 16-bit, float16) to packed HWC out, row-strided HWC views to
+   packed float32 HWC (rows of a multiple of 4 pixels, strides whole 4-byte
+   words), and packed CHW to packed float32 CHW (W H a multiple of 4); other
+   combinations run one pixel per lane at a fraction of the bandwidth.
    Errors: MACT_E_INVALID (NULL pointers, sizes <= 0, strides too small,
    mismatched shapes, gamma set for HSI/SCT, out_mode 1 for HSI/SCT, degrees
    outside 0..7); MACT_E_UNSUPPORTED (rational approximations for HSI/SCT,
