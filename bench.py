@@ -528,7 +528,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_hwc4<U8,F32,4,LAB>",
                      "kernel_ms": k_ms, "kernel_ms_median": k_med, "kernel_ms_p10": k_spread["p10"],
                      "kernel_ms_p90": k_spread["p90"], "algorithmic_bytes_per_px": 15,
-                     "pixels_per_launch": n_px},
+                     "pixels_per_launch": n_px,
+                     # the same run's 16-byte copy (equal reads and writes, a grid covering the copy once):
+                     # the practical ceiling of this machine's HBM for a streaming kernel
+                     "copy16_GBs": forms["copy16"]["GBs"],
+                     "frac_of_copy16": achieved / forms["copy16"]["GBs"]},
         "cpu_baseline": cpu,
         "accuracy": acc,
         "forms": forms,
