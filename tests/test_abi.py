@@ -210,6 +210,44 @@ def test_default_params(M):
             assert a.converged == 1 and 0 < a.eps < 2e-4
 
 
+def test_host_entry_points_are_reentrant(M):
+    # fits, weighted fits and the default approximations called from 8 host threads at once
+    # (ctypes drops the interpreter lock for the call) give the single-threaded results, and a
+    # failing call's detail string stays on its own thread
+    import threading
+    from paper_1009_0854_amd import _abi
+    jobs = [(0, 4, 4, 0.008856, 1.0, None), (4, 5, 0, 0.0, 1.0, None), (6, 7, 0, 0.0, np.pi / 2, None),
+            (0, 3, 3, 0.008856, 1.0, (0.5, 0.01))]
+
+    def run(job):
+        fn, n, m, lo, hi, w = job
+        a = M.fit(fn, n, m, lo, hi, weight=None if w is None else M.dark_end_weight(*w))
+        return list(a.p_list), list(a.q_list), a.eps
+
+    want = [run(j) for j in jobs]
+    got, errs = {}, {}
+
+    def worker(t):
+        L = M.lib()
+        for r in range(3):
+            for i, j in enumerate(jobs):
+                got[(t, r, i)] = run(j)
+            assert M.default_params(t % 4).xform == t % 4
+            st = L.mact_fit(0, 9, 0, 0.0, 1.0, None)  # invalid: this thread's own error text
+            errs[(t, r)] = (st, L.mact_last_error())
+
+    ts = [threading.Thread(target=worker, args=(t,)) for t in range(8)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert len(got) == 8 * 3 * len(jobs)
+    for (t, r, i), v in got.items():
+        assert v == want[i], (t, r, i)
+    for st, msg in errs.values():
+        assert st == _abi.E_INVALID and (b"out is NULL" in msg or b"degrees" in msg), msg
+
+
 def _img(data=1, dtype=0, layout=0, w=4, h=3, **kw):
     from paper_1009_0854_amd import _abi
     im = _abi.Image()
