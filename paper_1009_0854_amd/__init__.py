@@ -118,6 +118,9 @@ def image(t, layout="hwc", gamma="bt709"):
     CHW (3, H, W) or (N, 3, H, W).  Strides are taken from the tensor."""
     if not t.is_cuda:
         raise ValueError("image(): tensor must be on the GPU")
+    if t.numel() == 0:
+        # the C ABI reads batch 0 as one image: an empty tensor has no description
+        raise ValueError("image(): empty tensor %s" % (tuple(t.shape),))
     im = Image()
     im.data = t.data_ptr()
     im.dtype = _dtype_code(t)
@@ -171,6 +174,8 @@ def transform(x, xform="lab", params=None, layout="hwc", gamma="bt709", out=None
     out_layout = layout if out_layout is None else out_layout
     if out is None:
         out = _out_like(x, layout, out_layout, out_dtype or torch.float32)
+    if x.numel() == 0:  # nothing to transform
+        return out
     A.check(lib().mact_transform(ctypes.byref(p), ctypes.byref(image(x, layout, gamma)),
                                  ctypes.byref(image(out, out_layout)), _stream(stream)))
     return out
@@ -182,6 +187,8 @@ def transform_backward(x, grad_out, params=None, layout="chw", grad_in=None, str
     p = params if params is not None else default_params("lab")
     if grad_in is None:
         grad_in = torch.empty_like(x)
+    if x.numel() == 0:
+        return grad_in
     A.check(lib().mact_transform_backward(ctypes.byref(p), ctypes.byref(image(x, layout, "none")),
                                           ctypes.byref(image(grad_out, layout)),
                                           ctypes.byref(image(grad_in, layout)), _stream(stream)))
@@ -207,6 +214,8 @@ def inverse(x, xform="lab", params=None, layout="hwc", gamma="bt709", out=None, 
     out_layout = layout if out_layout is None else out_layout
     if out is None:
         out = _out_like(x, layout, out_layout, out_dtype or torch.float32)
+    if x.numel() == 0:  # nothing to transform
+        return out
     A.check(lib().mact_inverse(ctypes.byref(p), ctypes.byref(image(x, layout, "none")),
                                ctypes.byref(image(out, out_layout, gamma)), _stream(stream)))
     return out
@@ -218,6 +227,8 @@ def error_stats(x, xform="lab", params=None, layout="hwc", gamma="bt709", stream
     mean, max and max_abs (per channel)."""
     p = params if params is not None else default_params(xform)
     e = A.ErrorStats()
+    if x.numel() == 0:
+        return {"count": 0, "mean": 0.0, "max": 0.0, "max_abs": [0.0, 0.0, 0.0]}
     A.check(lib().mact_error_stats(ctypes.byref(p), ctypes.byref(image(x, layout, gamma)), ctypes.byref(e),
                                    _stream(stream)))
     return {"count": e.count, "mean": e.mean, "max": e.max, "max_abs": [e.max_abs[c] for c in range(3)]}
@@ -246,6 +257,8 @@ def lut_interp(lut, n, xform, method, x, layout="hwc", out=None, out_layout=None
     if out is None:
         out = _out_like(x, layout, out_layout, out_dtype or torch.float32)
     m = A.METHODS[method] if isinstance(method, str) else int(method)
+    if x.numel() == 0:  # nothing to transform
+        return out
     A.check(lib().lut_interp(ctypes.c_void_p(lut.data_ptr()), int(n), _xf(xform), m,
                              ctypes.byref(image(x, layout, "none")), ctypes.byref(image(out, out_layout)),
                              _stream(stream)))
@@ -276,6 +289,8 @@ def lut_cells_interp(cells, n, xform, method, x, layout="hwc", out=None, out_lay
     if out is None:
         out = _out_like(x, layout, out_layout, out_dtype or torch.float32)
     m = A.METHODS[method] if isinstance(method, str) else int(method)
+    if x.numel() == 0:  # nothing to transform
+        return out
     A.check(lib().lut_cells_interp(ctypes.c_void_p(cells.data_ptr()), int(n), _xf(xform), m,
                                    ctypes.byref(image(x, layout, "none")), ctypes.byref(image(out, out_layout)),
                                    _stream(stream)))

@@ -5,6 +5,7 @@
 //  * k_hwc4: the hot path, packed 8-bit (or float16) HWC in and packed
 //    float32 (or float16) HWC out, staged through LDS so that every global
 //    store is a contiguous run of 1 KB per wave (details at the kernel).
+//  * k_hwc4f: k_hwc4 for packed float32 HWC input, staged through LDS both ways.
 //  * k_rows4: row-strided HWC views (crops, pitched rows), k_hwc4's pattern
 //    per 256-pixel run of a row.
 //  * k_chw4: packed CHW of any input type, 4 pixels per lane, vector access
@@ -281,6 +282,99 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
       else if (XF == MACT_HSI) hsi_px<DEG>(k, r, g, b, kInv3, o);
       else sct_px<DEG, false>(k, r, g, b, 1.0f, o);
     }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (OUT == MACT_F32) static_cast<float*>(out)[3 * p + c] = o[c];
+      else static_cast<__half*>(out)[3 * p + c] = f2h_rn(o[c]);
+    }
+  }
+}
+
+// Packed float32 HWC -> packed float32 / float16 HWC: k_hwc4 for 12-byte
+// pixels.  A chunk's 3 KB of input come in as three coalesced 1 KB loads into
+// the wave's LDS slice; each lane reads its 4 pixels (48 bytes) back from
+// there, and the results leave through the same slice as in k_hwc4.  Requires
+// `in` and `out` 16-byte aligned; blockDim.x == kHotBlock.
+template <int OUT, int DEG, int XF>
+__global__ __launch_bounds__(kHotBlock) void k_hwc4f(const f4* __restrict__ in, void* __restrict__ out,
+                                                      uint32_t n_px, KCoef k, int gamma) {
+  constexpr uint32_t F4PC = OUT == MACT_F32 ? 192 : 96;  // 16-byte output words per chunk
+  constexpr int CPW = kChunksPerWave;
+  __shared__ f4 s_buf[kHotWaves][CPW * 192];
+  pin_lead<DEG>(k);
+  const uint32_t n_chunks = n_px >> 8;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t c0 = (blockIdx.x * kHotWaves + wv) * CPW;
+  if (c0 < n_chunks) {
+    const uint32_t nc = min((uint32_t)CPW, n_chunks - c0);
+    f4 a[CPW][3];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j)
+      if ((uint32_t)j < nc)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) a[j][q] = in[(size_t)(c0 + j) * 192 + q * 64 + lane];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j)
+      if ((uint32_t)j < nc)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s_buf[wv][j * 192 + q * 64 + lane] = a[j][q];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the chunks are in LDS
+    __builtin_amdgcn_wave_barrier();
+    float v[CPW][12];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j)
+      if ((uint32_t)j < nc) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const f4 b = s_buf[wv][j * 192 + 3 * lane + t];
+          v[j][4 * t] = b.x; v[j][4 * t + 1] = b.y; v[j][4 * t + 2] = b.z; v[j][4 * t + 3] = b.w;
+        }
+      }
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // every lane's reads are done before the slice is rewritten
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+      if ((uint32_t)j >= nc) break;
+      float o[12];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float raw[3] = {clamp01(v[j][3 * i]), clamp01(v[j][3 * i + 1]), clamp01(v[j][3 * i + 2])};
+        px1<MACT_F32, XF, DEG>(k, gamma, nullptr, raw, o + 3 * i);
+      }
+      if (OUT == MACT_F32) {
+        s_buf[wv][j * 192 + 3 * lane] = f4{o[0], o[1], o[2], o[3]};
+        s_buf[wv][j * 192 + 3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
+        s_buf[wv][j * 192 + 3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+      } else {
+        f2* s2 = reinterpret_cast<f2*>(&s_buf[wv][0]);  // chunk j's halves start at 8-byte word 192 j
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const uint32_t lo = pack2_h_rn(o[4 * t], o[4 * t + 1]);
+          const uint32_t hi = pack2_h_rn(o[4 * t + 2], o[4 * t + 3]);
+          s2[j * 192 + 3 * lane + t] = f2{__uint_as_float(lo), __uint_as_float(hi)};
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    const uint32_t n_valid = nc * F4PC;
+    f4* dst = reinterpret_cast<f4*>(out) + (size_t)c0 * F4PC;
+#pragma unroll
+    for (int q = 0; q < (int)(CPW * F4PC / 64); ++q) {
+      const uint32_t e = q * 64 + lane;
+      if (e < n_valid) __builtin_nontemporal_store(s_buf[wv][e], dst + e);
+    }
+  }
+  // the last n_px % 256 pixels, one per lane of block 0
+  const uint32_t tail0 = n_chunks << 8;
+  if (blockIdx.x == 0 && threadIdx.x < n_px - tail0) {
+    const size_t p = tail0 + threadIdx.x;
+    const float* fi = reinterpret_cast<const float*>(in);
+    const float raw[3] = {clamp01(fi[3 * p]), clamp01(fi[3 * p + 1]), clamp01(fi[3 * p + 2])};
+    float o[3];
+    px1<MACT_F32, XF, DEG>(k, gamma, nullptr, raw, o);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (OUT == MACT_F32) static_cast<float*>(out)[3 * p + c] = o[c];
@@ -584,6 +678,30 @@ static void launch_hwc4_io(int xform, int out_dtype, int deg, const void* in, vo
   }
 }
 
+template <int OUT, int DEG>
+static void launch_hwc4f_deg(int xform, const void* in, void* out, uint32_t n_px, const KCoef& k, int gamma,
+                             hipStream_t st) {
+  const dim3 grid(hot_grid(n_px)), blk(kHotBlock);
+  const f4* i4 = static_cast<const f4*>(in);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_hwc4f<OUT, DEG, MACT_LAB>), grid, blk, 0, st, i4, out, n_px, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_hwc4f<OUT, DEG, MACT_HSI>), grid, blk, 0, st, i4, out, n_px, k, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_hwc4f<OUT, DEG, MACT_LUV>), grid, blk, 0, st, i4, out, n_px, k, gamma);
+  else hipLaunchKernelGGL((k_hwc4f<OUT, DEG, MACT_SCT>), grid, blk, 0, st, i4, out, n_px, k, gamma);
+}
+
+static void launch_hwc4f(int xform, int out_dtype, int deg, const void* in, void* out, uint32_t n_px, const KCoef& k,
+                         int gamma, hipStream_t st) {
+  if (out_dtype == MACT_F32) {
+    if (deg <= 4) launch_hwc4f_deg<MACT_F32, 4>(xform, in, out, n_px, k, gamma, st);
+    else if (deg == 5) launch_hwc4f_deg<MACT_F32, 5>(xform, in, out, n_px, k, gamma, st);
+    else launch_hwc4f_deg<MACT_F32, 7>(xform, in, out, n_px, k, gamma, st);
+  } else {
+    if (deg <= 4) launch_hwc4f_deg<MACT_F16, 4>(xform, in, out, n_px, k, gamma, st);
+    else if (deg == 5) launch_hwc4f_deg<MACT_F16, 5>(xform, in, out, n_px, k, gamma, st);
+    else launch_hwc4f_deg<MACT_F16, 7>(xform, in, out, n_px, k, gamma, st);
+  }
+}
+
 template <int IN, int DEG>
 static void launch_rows4_deg(int xform, const void* in, float* out, uint32_t n_chunks, const RowGeom& g,
                              const KCoef& k, int gamma, hipStream_t st) {
@@ -634,7 +752,7 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   const int deg = pack_coef(*params, &k, &exact_deg);
   const int gamma = uses_gamma(params->xform) ? hi.gamma : MACT_GAMMA_NONE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  // fast shapes: packed 8-bit / float16 / 16-bit HWC -> packed float32 / float16 HWC, row-strided HWC
+  // fast shapes: packed HWC of any input type -> packed float32 / float16 HWC, row-strided HWC
   // -> packed float32 HWC, and packed CHW of any input type -> packed float32 CHW with W H a
   // multiple of 4; everything else takes k_generic
   const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
@@ -642,6 +760,8 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
                     (ho.dtype == MACT_F32 || ho.dtype == MACT_F16) && ho.layout == MACT_HWC && ho.packed;
   const bool chw4 = hi.layout == MACT_CHW && hi.packed &&
                     ho.dtype == MACT_F32 && ho.layout == MACT_CHW && ho.packed && (hi.W * hi.H) % 4 == 0;
+  const bool hwc4f = hi.dtype == MACT_F32 && hi.layout == MACT_HWC && hi.packed &&
+                     (ho.dtype == MACT_F32 || ho.dtype == MACT_F16) && ho.layout == MACT_HWC && ho.packed;
   // row-strided 8-bit / float16 / 16-bit HWC -> packed float32 HWC, rows of a multiple of 4 pixels
   const bool rows4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
                      !hi.packed && ho.dtype == MACT_F32 && ho.layout == MACT_HWC && ho.packed && hi.W % 4 == 0 &&
@@ -656,6 +776,8 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
       if (hi.dtype == MACT_U8) launch_hwc4_io<MACT_U8>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
       else if (hi.dtype == MACT_U16) launch_hwc4_io<MACT_U16>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
       else launch_hwc4_io<MACT_F16>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
+    } else if (hwc4f && aligned(ip, 16) && aligned(op, 16)) {
+      launch_hwc4f(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
     } else if (rows4 && aligned(ip, 4) && aligned(op, 16)) {
       RowGeom g;
       g.W = (uint32_t)hi.W;

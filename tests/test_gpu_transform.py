@@ -127,6 +127,44 @@ def test_float_inputs_layouts_and_clamp(M, xform):
 
 
 @pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
+def test_f32_hwc_fast_path(M, xform):
+    # packed float32 HWC (the LDS-staged kernel; ragged tails, values outside [0, 1]) equals a
+    # row-padded view of the same values (the one-pixel kernel) bitwise, fp32 and fp16 out, and the
+    # oracle to the parity bar (the SCT branch guard for float inputs)
+    g = synth.rng(40 + xform)
+    pars = [M.default_params(xform)]
+    if xform in (0, 3):
+        pars += [M.make_params(xform, [M.paper_approx(M.FN_CBRT, 4, 4)]), M.default_params(xform, decode=True)]
+    for shape in [(1, 1, 3), (3, 7, 5), (2, 16, 32), (1, 37, 300)]:
+        x = g.uniform(-0.1, 1.1, shape + (3,)).astype(np.float32)
+        packed = torch.from_numpy(x).cuda()
+        big = torch.zeros(shape[:2] + (shape[2] + 1, 3), dtype=torch.float32, device="cuda")
+        big[:, :, :shape[2]] = packed
+        view = big[:, :, :shape[2]]
+        for p in pars:
+            for gm in (["bt709", "srgb", "none"] if xform in (0, 3) else ["none"]):
+                for od in (torch.float32, torch.float16):
+                    a = M.transform(packed, xform=xform, params=p, gamma=gm, out_dtype=od)
+                    b = M.transform(view, xform=xform, params=p, gamma=gm, out_dtype=od)
+                    torch.cuda.synchronize()
+                    assert torch.equal(a, b), (shape, gm, od)
+    p = M.default_params(xform)
+    x = g.uniform(-0.1, 1.1, (2, 33, 129, 3)).astype(np.float32)
+    gpu = _run(M, x, xform, p, gamma="none").reshape(-1, 3).astype(np.float64)
+    ref = P.oracle(xform, x.astype(np.float64).reshape(-1, 3), P.coeffs(p), gamma="none")
+    if xform in (0, 3):
+        P.assert_parity(xform, gpu, ref)
+        return
+    err = np.abs(gpu - ref) / P.SCALE[xform]
+    if xform == 2:
+        xc = np.clip(x.astype(np.float64).reshape(-1, 3), 0, 1)
+        R, G, B = xc[:, 0], xc[:, 1], xc[:, 2]
+        near = (np.abs(3 * B * B - (R * R + G * G)) <= 1e-6 * (R * R + G * G + B * B)) | (np.abs(G - R) <= 1e-6)
+        err = err[~near]
+    assert err.max() <= P.REL, err.max(axis=0)
+
+
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
 def test_u8_input_f16_output(M, xform):
     # C1 through the float16-output form of the hot kernel (9 bytes per pixel moved):
     # the oracle value rounded to float16 within one half-unit of the float16 result
@@ -217,6 +255,25 @@ def test_integer_chw_equals_packed_hwc(M, dtype, xform):
             b = M.transform(x, xform=xform, params=p, gamma=gm)
             torch.cuda.synchronize()
             assert torch.equal(a, b.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm)
+
+
+def test_empty_inputs_give_empty_outputs(M):
+    # an empty batch or image is a no-op with an empty result (the C ABI reads batch 0 as one
+    # image, so the binding never describes an empty tensor to it)
+    for shape in [(0, 8, 8, 3), (2, 0, 8, 3), (1, 8, 0, 3)]:
+        x = torch.zeros(shape, dtype=torch.uint8, device="cuda")
+        y = M.transform(x, xform="lab")
+        assert y.shape == shape and y.dtype == torch.float32
+        assert M.transform(x.float(), xform="hsi", out_dtype=torch.float16).shape == shape
+        assert M.inverse(x.float(), xform="sct").shape == shape
+        assert M.error_stats(x, xform="lab")["count"] == 0
+        lut = M.lut_build("lab", 17)
+        assert M.lut_interp(lut, 17, "lab", "tetrahedral", x).shape == shape
+        xc = torch.zeros((shape[0], 3, shape[1], shape[2]), dtype=torch.float32, device="cuda")
+        assert M.transform_backward(xc, xc.clone()).shape == xc.shape
+        with pytest.raises(ValueError):
+            M.image(x)
+    torch.cuda.synchronize()
 
 
 def test_strided_views(M):
