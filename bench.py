@@ -467,9 +467,13 @@ def main():
             ms, _ = time_kernel(lambda: M.transform(x16u, params=pp, out=y), a.steps)
             forms["lab_u16_in_decode_%s" % tag] = {"Mpx_s": n_px / ms / 1e3, "GBs": 18.0 * n_px / ms / 1e6, "ms": ms}
         del x16u
-        x32 = x.float().div_(255.0)  # float32 HWC input (BT.709-encoded values in [0, 1]): 24 B/px
-        ms, _ = time_kernel(lambda: M.transform(x32, params=p_lab, out=y), a.steps)
-        forms["lab_f32_hwc_in"] = {"Mpx_s": n_px / ms / 1e3, "GBs": 24.0 * n_px / ms / 1e6, "ms": ms}
+        # float32 HWC input (BT.709-encoded values in [0, 1]): 24 B/px; the exact decoding power, the
+        # minimax decoding, and linear input (no decoding)
+        x32 = x.float().div_(255.0)
+        for tag, pp, gm in (("decode_exact", p_lab, "bt709"), ("decode_minimax", M.default_params(0, decode=True), "bt709"),
+                            ("linear", p_lab, "none")):
+            ms, _ = time_kernel(lambda: M.transform(x32, params=pp, gamma=gm, out=y), a.steps)
+            forms["lab_f32_hwc_in_" + tag] = {"Mpx_s": n_px / ms / 1e3, "GBs": 24.0 * n_px / ms / 1e6, "ms": ms}
         del x32
         log("4K batch")
         forms["lab_32x4k"] = bench_4k(M, p_lab, a.steps)
