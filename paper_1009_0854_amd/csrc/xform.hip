@@ -293,13 +293,17 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
 // Packed float32 HWC -> packed float32 / float16 HWC: k_hwc4 for 12-byte
 // pixels.  A chunk's 3 KB of input come in as three coalesced 1 KB loads into
 // the wave's LDS slice; each lane reads its 4 pixels (48 bytes) back from
-// there, and the results leave through the same slice as in k_hwc4.  Requires
-// `in` and `out` 16-byte aligned; blockDim.x == kHotBlock.
+// there, and the results leave through the same slice as in k_hwc4.  One chunk
+// per wave: a 12 KB buffer per workgroup, 8 workgroups per CU (two chunks per
+// wave measured 5.5 TB/s, the one-chunk inverse kernel of the same pattern
+// 5.8).  Requires `in` and `out` 16-byte aligned; blockDim.x == kHotBlock.
+constexpr int kF32Cpw = 1;
+
 template <int OUT, int DEG, int XF>
 __global__ __launch_bounds__(kHotBlock) void k_hwc4f(const f4* __restrict__ in, void* __restrict__ out,
                                                       uint32_t n_px, KCoef k, int gamma) {
   constexpr uint32_t F4PC = OUT == MACT_F32 ? 192 : 96;  // 16-byte output words per chunk
-  constexpr int CPW = kChunksPerWave;
+  constexpr int CPW = kF32Cpw;
   __shared__ f4 s_buf[kHotWaves][CPW * 192];
   pin_lead<DEG>(k);
   const uint32_t n_chunks = n_px >> 8;
@@ -362,7 +366,7 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4f(const f4* __restrict__ in, 
     const uint32_t n_valid = nc * F4PC;
     f4* dst = reinterpret_cast<f4*>(out) + (size_t)c0 * F4PC;
 #pragma unroll
-    for (int q = 0; q < (int)(CPW * F4PC / 64); ++q) {
+    for (int q = 0; q < (int)((CPW * F4PC + 63) / 64); ++q) {
       const uint32_t e = q * 64 + lane;
       if (e < n_valid) __builtin_nontemporal_store(s_buf[wv][e], dst + e);
     }
@@ -681,7 +685,7 @@ static void launch_hwc4_io(int xform, int out_dtype, int deg, const void* in, vo
 template <int OUT, int DEG>
 static void launch_hwc4f_deg(int xform, const void* in, void* out, uint32_t n_px, const KCoef& k, int gamma,
                              hipStream_t st) {
-  const dim3 grid(hot_grid(n_px)), blk(kHotBlock);
+  const dim3 grid(hot_grid(n_px, kF32Cpw)), blk(kHotBlock);
   const f4* i4 = static_cast<const f4*>(in);
   if (xform == MACT_LAB) hipLaunchKernelGGL((k_hwc4f<OUT, DEG, MACT_LAB>), grid, blk, 0, st, i4, out, n_px, k, gamma);
   else if (xform == MACT_HSI) hipLaunchKernelGGL((k_hwc4f<OUT, DEG, MACT_HSI>), grid, blk, 0, st, i4, out, n_px, k, gamma);
