@@ -549,12 +549,24 @@ def main():
 
 
 def kernel_hash():
-    """Hash of the hot kernel's sources, to tell whether stored counters are stale."""
+    """Hash of the hot kernel's sources, to tell whether stored counters are
+    stale: the per-pixel code and constants (pixel.h, common.h) and, from
+    xform.hip, the hot kernel with its launch constants, grid and launcher."""
     import hashlib
+    import re
+    csrc = os.path.join(ROOT, "paper_1009_0854_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("xform.hip", "pixel.h"):
-        with open(os.path.join(ROOT, "paper_1009_0854_amd", "csrc", f), "rb") as fh:
+    for f in ("pixel.h", "common.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "xform.hip")) as fh:
+        src = fh.read()
+    # from the launch constants to the end of k_hwc4, and the launcher template
+    a = src.index("constexpr int kHotBlock")
+    b = src.index("\n}\n", src.index("void k_hwc4(")) + 3
+    h.update(src[a:b].encode())
+    for pat in (r"static unsigned hot_grid\(.*?\n}\n", r"static void launch_hwc4\(.*?\n}\n"):
+        h.update(re.search(pat, src, re.S).group(0).encode())
     return h.hexdigest()[:16]
 
 
