@@ -142,9 +142,9 @@ def bench_4k(M, p, steps):
 def bench_general(M, x, y, p, n_px, steps):
     """CIELAB on layouts other than packed HWC: the 8-bit batch as a
     row-padded view (rows 8 pixels apart beyond their width; the row-strided
-    kernel) into packed float32 HWC, and as CHW planes into HWC (the
-    one-pixel-per-lane kernel) and into CHW (the CHW kernel).  15 bytes per
-    pixel."""
+    kernel) into packed float32 HWC, as CHW planes into HWC (the
+    one-pixel-per-lane kernel) and into CHW (the CHW kernel), and packed HWC
+    into CHW.  15 bytes per pixel."""
     import torch
     out = {}
     n, h, w, _ = x.shape
@@ -160,6 +160,8 @@ def bench_general(M, x, y, p, n_px, steps):
     ychw = y.view(n, 3, h, w)
     ms, _ = time_kernel(lambda: M.transform(chw, params=p, layout="chw", out=ychw, out_layout="chw"), steps)
     out["u8_chw_to_chw"] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
+    ms, _ = time_kernel(lambda: M.transform(x, params=p, out=ychw, out_layout="chw"), steps)
+    out["u8_hwc_to_chw"] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
     del chw, ychw
     return out
 

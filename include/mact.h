@@ -205,10 +205,11 @@ mact_status mact_params_default(int32_t xform, mact_params* p);
    Evaluation is float32 with explicit fused multiply-adds; the result does not
    depend on the layout or the launch configuration, so every form (plain,
    batched, served) gives identical bits.  Coalesced kernels serve packed HWC
-   in (8-bit, 16-bit, float16) to packed HWC out, row-strided HWC views to
-   packed float32 HWC (rows of a multiple of 4 pixels, strides whole 4-byte
-   words), and packed CHW to packed float32 CHW (W H a multiple of 4); other
-   combinations run one pixel per lane at a fraction of the bandwidth.
+   in to packed HWC out, packed HWC or CHW in to packed float32 CHW or HWC out
+   (W H a multiple of 4), and row-strided HWC views (8-bit, 16-bit, float16)
+   to packed float32 HWC (rows of a multiple of 4 pixels, strides whole 4-byte
+   words); other combinations run one pixel per lane at a fraction of the
+   bandwidth.
    Errors: MACT_E_INVALID (NULL pointers, sizes <= 0, strides too small,
    mismatched shapes, gamma set for HSI/SCT, out_mode 1 for HSI/SCT, degrees
    outside 0..7); MACT_E_UNSUPPORTED (rational approximations for HSI/SCT,

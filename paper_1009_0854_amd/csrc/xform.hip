@@ -10,6 +10,10 @@
 //    per 256-pixel run of a row.
 //  * k_chw4: packed CHW of any input type, 4 pixels per lane, vector access
 //    per plane.
+//  * k_hwc_chw4: packed HWC of any input type -> packed float32 CHW, 4 pixels
+//    per lane, no LDS.
+//  * k_chw_hwc4: packed CHW of any input type -> packed float32 HWC through
+//    the wave's LDS slice.
 //  * k_generic: any element type, layout and stride, one pixel per lane step.
 // All call the same per-pixel functions (pixel.h), so they give identical bits.
 #include <algorithm>
@@ -506,6 +510,131 @@ __global__ __launch_bounds__(256) void k_chw4(const void* __restrict__ in, float
   }
 }
 
+// Packed HWC (8-bit, 16-bit, float16 or float32) -> packed float32 CHW, 4
+// pixels per lane with W H a multiple of 4: the lane loads its 4 pixels as one
+// 12-byte load (two for 16-bit types, three 16-byte loads for float32; the
+// wave's loads cover one contiguous run), and writes each output plane's 4
+// values as one 16-byte store, contiguous across the wave.  No LDS.  Requires
+// `in` aligned to 4 bytes (16 for float32) and `out` to 16.
+template <int IN, int DEG, int XF>
+__global__ __launch_bounds__(256) void k_hwc_chw4(const void* __restrict__ in, float* __restrict__ out,
+                                                  uint32_t n_px, uint32_t hw, FastDiv div_hw4, KCoef k, int gamma) {
+  __shared__ float gtab[256];
+  if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
+    for (uint32_t i = threadIdx.x; i < 256u; i += 256u) gtab[i] = k_gamma_table[gamma][i];
+    __syncthreads();
+  }
+  pin_lead<DEG>(k);
+  const uint32_t n4 = n_px >> 2, hw4 = hw >> 2;
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t g4 = blockIdx.x * 256u + threadIdx.x; g4 < n4; g4 += stride) {
+    float v[12];  // raw values of the 4 pixels, as load_px returns them
+    if (IN == MACT_U8) {
+      const uint3 w = reinterpret_cast<const uint3*>(in)[g4];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) v[i] = (float)byte_of(w, i);
+    } else if (IN == MACT_U16) {
+      const uint3 wa = reinterpret_cast<const uint3*>(in)[2 * (size_t)g4];
+      const uint3 wb = reinterpret_cast<const uint3*>(in)[2 * (size_t)g4 + 1];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) v[i] = code16_of(wa, wb, i);
+    } else if (IN == MACT_F16) {
+      const uint3 wa = reinterpret_cast<const uint3*>(in)[2 * (size_t)g4];
+      const uint3 wb = reinterpret_cast<const uint3*>(in)[2 * (size_t)g4 + 1];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) v[i] = half_of(wa, wb, i);
+    } else {
+      const f4* f = reinterpret_cast<const f4*>(in) + 3 * (size_t)g4;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const f4 b = f[t];
+        v[4 * t] = clamp01(b.x); v[4 * t + 1] = clamp01(b.y); v[4 * t + 2] = clamp01(b.z); v[4 * t + 3] = clamp01(b.w);
+      }
+    }
+    float o[3][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float r[3];
+      px1<IN, XF, DEG>(k, gamma, gtab, v + 3 * j, r);
+      o[0][j] = r[0]; o[1][j] = r[1]; o[2][j] = r[2];
+    }
+    const uint32_t n = div_hw4.div(g4);
+    const size_t base = (size_t)n * 3 * hw + 4 * (size_t)(g4 - n * hw4);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      __builtin_nontemporal_store(f4{o[c][0], o[c][1], o[c][2], o[c][3]},
+                                  reinterpret_cast<f4*>(out + base + (size_t)c * hw));
+  }
+}
+
+// Packed CHW (8-bit, 16-bit, float16 or float32) -> packed float32 HWC, W H a
+// multiple of 4: one 256-pixel chunk of the batch per wave (the last one
+// partial).  Each lane loads its 4 pixels from each plane (one 4-, 8- or
+// 16-byte load per plane, contiguous across the wave), computes them, and the
+// results leave through the wave's LDS slice as k_hwc4's 1 KB stores.
+template <int IN, int DEG, int XF>
+__global__ __launch_bounds__(kHotBlock) void k_chw_hwc4(const void* __restrict__ in, float* __restrict__ out,
+                                                        uint32_t n_px, uint32_t hw, FastDiv div_hw4, KCoef k,
+                                                        int gamma) {
+  __shared__ f4 s_out[kHotWaves][192];
+  __shared__ float gtab[256];
+  if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
+    for (uint32_t i = threadIdx.x; i < 256u; i += kHotBlock) gtab[i] = k_gamma_table[gamma][i];
+    __syncthreads();
+  }
+  pin_lead<DEG>(k);
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t c = blockIdx.x * kHotWaves + wv, n_chunks = (n_px + 255u) >> 8;
+  if (c >= n_chunks) return;  // no block-wide barrier follows
+  const uint32_t cnt = min(256u, n_px - c * 256u);  // a multiple of 4
+  const uint32_t g4 = c * 64u + lane, hw4 = hw >> 2;
+  float o[12];
+  if (4u * lane < cnt) {
+    const uint32_t n = div_hw4.div(g4);
+    const size_t base = (size_t)n * 3 * hw + 4 * (size_t)(g4 - n * hw4);  // element offset in plane 0
+    float v[4][3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      if (IN == MACT_F32) {
+        const f4 x = *reinterpret_cast<const f4*>(static_cast<const float*>(in) + base + (size_t)ch * hw);
+        v[0][ch] = clamp01(x.x); v[1][ch] = clamp01(x.y); v[2][ch] = clamp01(x.z); v[3][ch] = clamp01(x.w);
+      } else if (IN == MACT_F16) {
+        const uint2 x = *reinterpret_cast<const uint2*>(static_cast<const __half*>(in) + base + (size_t)ch * hw);
+        v[0][ch] = clamp01(__half2float(__ushort_as_half((uint16_t)x.x)));
+        v[1][ch] = clamp01(__half2float(__ushort_as_half((uint16_t)(x.x >> 16))));
+        v[2][ch] = clamp01(__half2float(__ushort_as_half((uint16_t)x.y)));
+        v[3][ch] = clamp01(__half2float(__ushort_as_half((uint16_t)(x.y >> 16))));
+      } else if (IN == MACT_U16) {
+        const uint2 x = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(in) + base + (size_t)ch * hw);
+        v[0][ch] = (float)(x.x & 0xffffu); v[1][ch] = (float)(x.x >> 16);
+        v[2][ch] = (float)(x.y & 0xffffu); v[3][ch] = (float)(x.y >> 16);
+      } else {
+        const uint32_t x = *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(in) + base + (size_t)ch * hw);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j][ch] = (float)((x >> (8 * j)) & 0xffu);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) px1<IN, XF, DEG>(k, gamma, gtab, v[j], o + 3 * j);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) o[q] = 0.0f;
+  }
+  s_out[wv][3 * lane] = f4{o[0], o[1], o[2], o[3]};
+  s_out[wv][3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
+  s_out[wv][3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): every lane's LDS writes have landed
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t n_valid = cnt / 4u * 3u;
+  f4* dst = reinterpret_cast<f4*>(out) + (size_t)c * 192;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const uint32_t e = q * 64 + lane;
+    if (e < n_valid) __builtin_nontemporal_store(s_out[wv][e], dst + e);
+  }
+}
+
 template <int DEG>
 __global__ __launch_bounds__(256) void k_generic(KImage src, KImage dst, uint32_t n_px, KCoef k, int gamma) {
   __shared__ float gtab[256];
@@ -726,6 +855,42 @@ static void launch_rows4(int xform, int deg, const void* in, float* out, uint32_
 }
 
 template <int IN, int DEG>
+static void launch_hwc_chw4(int xform, const void* in, float* out, uint32_t n_px, uint32_t hw, const KCoef& k,
+                            int gamma, hipStream_t st) {
+  const dim3 grid(full_grid(n_px / 4, 256)), blk(256);
+  const FastDiv d = make_fastdiv(hw / 4);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_hwc_chw4<IN, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_hwc_chw4<IN, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_hwc_chw4<IN, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else hipLaunchKernelGGL((k_hwc_chw4<IN, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+}
+
+template <int IN, int DEG>
+static void launch_chw_hwc4(int xform, const void* in, float* out, uint32_t n_px, uint32_t hw, const KCoef& k,
+                            int gamma, hipStream_t st) {
+  const dim3 grid(std::max<uint32_t>(1, (((n_px + 255u) >> 8) + kHotWaves - 1) / kHotWaves)), blk(kHotBlock);
+  const FastDiv d = make_fastdiv(hw / 4);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_chw_hwc4<IN, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_chw_hwc4<IN, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_chw_hwc4<IN, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else hipLaunchKernelGGL((k_chw_hwc4<IN, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+}
+
+template <int IN>
+static void launch_chw_hwc4_deg(int xform, int deg, const void* in, float* out, uint32_t n_px, uint32_t hw,
+                                const KCoef& k, int gamma, hipStream_t st) {
+  if (deg == 5) launch_chw_hwc4<IN, 5>(xform, in, out, n_px, hw, k, gamma, st);
+  else launch_chw_hwc4<IN, 7>(xform, in, out, n_px, hw, k, gamma, st);
+}
+
+template <int IN>
+static void launch_hwc_chw4_deg(int xform, int deg, const void* in, float* out, uint32_t n_px, uint32_t hw,
+                                const KCoef& k, int gamma, hipStream_t st) {
+  if (deg == 5) launch_hwc_chw4<IN, 5>(xform, in, out, n_px, hw, k, gamma, st);
+  else launch_hwc_chw4<IN, 7>(xform, in, out, n_px, hw, k, gamma, st);
+}
+
+template <int IN, int DEG>
 static void launch_chw4(int xform, const void* in, float* out, uint32_t n_px, uint32_t hw, const KCoef& k, int gamma,
                         hipStream_t st) {
   const dim3 grid(full_grid(n_px / 4, 256)), blk(256);
@@ -756,9 +921,9 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   const int deg = pack_coef(*params, &k, &exact_deg);
   const int gamma = uses_gamma(params->xform) ? hi.gamma : MACT_GAMMA_NONE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  // fast shapes: packed HWC of any input type -> packed float32 / float16 HWC, row-strided HWC
-  // -> packed float32 HWC, and packed CHW of any input type -> packed float32 CHW with W H a
-  // multiple of 4; everything else takes k_generic
+  // fast shapes: packed HWC of any input type -> packed float32 / float16 HWC or (W H a multiple
+  // of 4) packed float32 CHW, row-strided HWC -> packed float32 HWC, and packed CHW of any input type
+  // -> packed float32 CHW or HWC (W H a multiple of 4); everything else takes k_generic
   const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
                     hi.packed &&
                     (ho.dtype == MACT_F32 || ho.dtype == MACT_F16) && ho.layout == MACT_HWC && ho.packed;
@@ -766,6 +931,10 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
                     ho.dtype == MACT_F32 && ho.layout == MACT_CHW && ho.packed && (hi.W * hi.H) % 4 == 0;
   const bool hwc4f = hi.dtype == MACT_F32 && hi.layout == MACT_HWC && hi.packed &&
                      (ho.dtype == MACT_F32 || ho.dtype == MACT_F16) && ho.layout == MACT_HWC && ho.packed;
+  const bool hwc_chw4 = hi.layout == MACT_HWC && hi.packed && ho.dtype == MACT_F32 && ho.layout == MACT_CHW &&
+                        ho.packed && (hi.W * hi.H) % 4 == 0;
+  const bool chw_hwc4 = hi.layout == MACT_CHW && hi.packed && ho.dtype == MACT_F32 && ho.layout == MACT_HWC &&
+                        ho.packed && (hi.W * hi.H) % 4 == 0;
   // row-strided 8-bit / float16 / 16-bit HWC -> packed float32 HWC, rows of a multiple of 4 pixels
   const bool rows4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
                      !hi.packed && ho.dtype == MACT_F32 && ho.layout == MACT_HWC && ho.packed && hi.W % 4 == 0 &&
@@ -782,6 +951,20 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
       else launch_hwc4_io<MACT_F16>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
     } else if (hwc4f && aligned(ip, 16) && aligned(op, 16)) {
       launch_hwc4f(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
+    } else if (hwc_chw4 && aligned(ip, hi.dtype == MACT_F32 ? 16 : 4) && aligned(op, 16)) {
+      const uint32_t hw = (uint32_t)(hi.W * hi.H);
+      float* of = static_cast<float*>(op);
+      if (hi.dtype == MACT_U8) launch_hwc_chw4_deg<MACT_U8>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
+      else if (hi.dtype == MACT_U16) launch_hwc_chw4_deg<MACT_U16>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
+      else if (hi.dtype == MACT_F16) launch_hwc_chw4_deg<MACT_F16>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
+      else launch_hwc_chw4_deg<MACT_F32>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
+    } else if (chw_hwc4 && aligned(ip, 4 * hi.esize) && aligned(op, 16)) {
+      const uint32_t hw = (uint32_t)(hi.W * hi.H);
+      float* of = static_cast<float*>(op);
+      if (hi.dtype == MACT_U8) launch_chw_hwc4_deg<MACT_U8>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
+      else if (hi.dtype == MACT_U16) launch_chw_hwc4_deg<MACT_U16>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
+      else if (hi.dtype == MACT_F16) launch_chw_hwc4_deg<MACT_F16>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
+      else launch_chw_hwc4_deg<MACT_F32>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
     } else if (rows4 && aligned(ip, 4) && aligned(op, 16)) {
       RowGeom g;
       g.W = (uint32_t)hi.W;

@@ -239,22 +239,28 @@ def test_row_strided_views_equal_packed(M, dtype, xform):
                 assert torch.equal(a, b), (n, h, w, rpad, ipad, gm)
 
 
-@pytest.mark.parametrize("dtype", ["u8", "u16"])
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f16", "f32"])
 @pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
-def test_integer_chw_equals_packed_hwc(M, dtype, xform):
-    # 8- and 16-bit CHW planes (the CHW kernel where W H is a multiple of 4, the one-pixel kernel
-    # otherwise) give the bits of the packed HWC input, plane by plane
+def test_chw_inputs_equal_packed_hwc(M, dtype, xform):
+    # CHW planes into CHW and into HWC (the 4-pixel kernels where W H is a multiple of 4, the
+    # one-pixel kernel otherwise; a partial last chunk at 3 x 8 x 1000) give the bits of the packed
+    # HWC input
     g = synth.rng(300 + xform)
     for (n, h, w) in [(2, 16, 20), (1, 33, 36), (3, 8, 1000), (1, 7, 9)]:
-        hwc = g.integers(0, 256 if dtype == "u8" else 65536, (n, h, w, 3)).astype(np.uint8 if dtype == "u8" else np.uint16)
+        if dtype in ("u8", "u16"):
+            hwc = g.integers(0, 256 if dtype == "u8" else 65536, (n, h, w, 3)).astype(np.uint8 if dtype == "u8" else np.uint16)
+        else:
+            hwc = g.uniform(-0.05, 1.05, (n, h, w, 3)).astype(np.float16 if dtype == "f16" else np.float32)
         chw = torch.from_numpy(np.ascontiguousarray(np.moveaxis(hwc, -1, 1))).cuda()
         x = torch.from_numpy(hwc).cuda()
         for gm in (["bt709", "srgb", "none"] if xform in (0, 3) else ["none"]):
             p = M.default_params(xform)
             a = M.transform(chw, xform=xform, params=p, layout="chw", gamma=gm)
+            c = M.transform(chw, xform=xform, params=p, layout="chw", out_layout="hwc", gamma=gm)
             b = M.transform(x, xform=xform, params=p, gamma=gm)
             torch.cuda.synchronize()
             assert torch.equal(a, b.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm)
+            assert torch.equal(c, b), (n, h, w, gm)
 
 
 def test_empty_inputs_give_empty_outputs(M):
@@ -274,6 +280,29 @@ def test_empty_inputs_give_empty_outputs(M):
         with pytest.raises(ValueError):
             M.image(x)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f16", "f32"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
+def test_hwc_to_chw_equals_hwc_permuted(M, dtype, xform):
+    # packed HWC into packed float32 CHW (the 4-pixel kernel where W H is a multiple of 4, the
+    # one-pixel kernel otherwise) gives the HWC result's bits, plane by plane
+    g = synth.rng(400 + xform)
+    for (n, h, w) in [(2, 16, 20), (1, 33, 36), (3, 8, 1000), (1, 7, 9)]:
+        if dtype == "u8":
+            a = g.integers(0, 256, (n, h, w, 3)).astype(np.uint8)
+        elif dtype == "u16":
+            a = g.integers(0, 65536, (n, h, w, 3)).astype(np.uint16)
+        else:
+            a = g.uniform(-0.05, 1.05, (n, h, w, 3)).astype(np.float16 if dtype == "f16" else np.float32)
+        x = torch.from_numpy(a).cuda()
+        pars = [M.default_params(xform)] + ([M.default_params(xform, decode=True)] if xform in (0, 3) else [])
+        for p in pars:
+            for gm in (["bt709", "none"] if xform in (0, 3) else ["none"]):
+                c = M.transform(x, xform=xform, params=p, gamma=gm, out_layout="chw")
+                r = M.transform(x, xform=xform, params=p, gamma=gm)
+                torch.cuda.synchronize()
+                assert torch.equal(c, r.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm)
 
 
 def test_strided_views(M):
