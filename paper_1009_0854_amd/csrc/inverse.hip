@@ -8,8 +8,8 @@
 // 1.099 L^0.45 - 0.099 by a rational on [0.018, 1] (the cube of the CIELAB and
 // CIELUV inverses is exact), cosine by a polynomial on [0, 2 pi/3] (HSI), sine and
 // cosine by polynomials on [0, pi/2] (SCT).  float32, explicit fmas; packed
-// float32 HWC goes through LDS-staged coalesced chunks, everything else one
-// pixel per lane.
+// float32 HWC goes through LDS-staged coalesced chunks, packed CHW (float32,
+// float16) 4 pixels per lane by planes, everything else one pixel per lane.
 //
 // Error statistics: every pixel of an RGB image goes through the forward MACT
 // transform (the same per-pixel code as mact_transform, float32) and through
@@ -220,6 +220,58 @@ __global__ __launch_bounds__(256) void k_inverse4(const f4* __restrict__ in, f4*
     fo[3 * p + 1] = o[1];
     fo[3 * p + 2] = o[2];
   }
+}
+
+// Packed CHW (float32 or float16) -> packed float32 CHW, W H a multiple of 4
+// (network outputs): 4 pixels per lane, one 16- or 8-byte load and one 16-byte
+// store per plane, each contiguous across the wave.  The same per-pixel code.
+template <int IN, int DEG, int XF>
+__global__ __launch_bounds__(256) void k_inverse_chw4(const void* __restrict__ in, float* __restrict__ out,
+                                                      uint32_t n_px, uint32_t hw, FastDiv div_hw4, KCoef k, InvMat mi,
+                                                      int gamma) {
+  const uint32_t n4 = n_px >> 2, hw4 = hw >> 2;
+  const uint32_t stride = gridDim.x * 256u;
+  for (uint32_t g4 = blockIdx.x * 256u + threadIdx.x; g4 < n4; g4 += stride) {
+    const uint32_t n = div_hw4.div(g4);
+    const size_t base = (size_t)n * 3 * hw + 4 * (size_t)(g4 - n * hw4);
+    float v[4][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (IN == MACT_F32) {
+        const f4 x = *reinterpret_cast<const f4*>(static_cast<const float*>(in) + base + (size_t)c * hw);
+        v[0][c] = x.x; v[1][c] = x.y; v[2][c] = x.z; v[3][c] = x.w;
+      } else {
+        const uint2 x = *reinterpret_cast<const uint2*>(static_cast<const __half*>(in) + base + (size_t)c * hw);
+        v[0][c] = __half2float(__ushort_as_half((uint16_t)x.x));
+        v[1][c] = __half2float(__ushort_as_half((uint16_t)(x.x >> 16)));
+        v[2][c] = __half2float(__ushort_as_half((uint16_t)x.y));
+        v[3][c] = __half2float(__ushort_as_half((uint16_t)(x.y >> 16)));
+      }
+    }
+    float o[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (XF == MACT_LAB) lab_inv_px<DEG>(k, mi, gamma, v[j], o[j]);
+      else if (XF == MACT_LUV) luv_inv_px<DEG>(k, mi, gamma, v[j], o[j]);
+      else if (XF == MACT_HSI) hsi_inv_px<DEG>(k, v[j], o[j]);
+      else sct_inv_px<DEG>(k, v[j], o[j]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      __builtin_nontemporal_store(f4{o[0][c], o[1][c], o[2][c], o[3][c]},
+                                  reinterpret_cast<f4*>(out + base + (size_t)c * hw));
+  }
+}
+
+template <int IN, int DEG>
+void launch_inverse_chw4(int xform, const void* in, float* out, uint32_t n_px, uint32_t hw, const KCoef& k,
+                         const InvMat& mi, int gamma, hipStream_t st) {
+  const dim3 grid(std::max<uint32_t>(1, (n_px / 4 + 255) / 256)), blk(256);
+  const FastDiv d = make_fastdiv(hw / 4);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_inverse_chw4<IN, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, hw, d, k, mi, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_inverse_chw4<IN, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, hw, d, k, mi, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_inverse_chw4<IN, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, hw, d, k, mi, gamma);
+  else hipLaunchKernelGGL((k_inverse_chw4<IN, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, hw, d, k, mi, gamma);
 }
 
 template <int DEG>
@@ -486,6 +538,8 @@ extern "C" mact_status mact_inverse(const mact_params* params, const mact_image*
   const int64_t per = images_per_launch(hi);
   const bool fast = hi.dtype == MACT_F32 && ho.dtype == MACT_F32 && hi.layout == MACT_HWC && ho.layout == MACT_HWC &&
                     hi.packed && ho.packed;
+  const bool chw4 = (hi.dtype == MACT_F32 || hi.dtype == MACT_F16) && ho.dtype == MACT_F32 && hi.layout == MACT_CHW &&
+                    ho.layout == MACT_CHW && hi.packed && ho.packed && (hi.W * hi.H) % 4 == 0;
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
     const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
@@ -496,6 +550,16 @@ extern "C" mact_status mact_inverse(const mact_params* params, const mact_image*
       const unsigned grid = (unsigned)std::max<uint64_t>(1, ((uint64_t)(n_px >> 8) + 3) / 4);
       if (deg == 5) launch_inverse4<5>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
       else launch_inverse4<7>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
+    } else if (chw4 && (uintptr_t)ks.ptr % (4 * hi.esize) == 0 && (uintptr_t)kd.ptr % 16 == 0) {
+      const uint32_t hw = (uint32_t)(hi.W * hi.H);
+      float* of = static_cast<float*>(kd.ptr);
+      if (hi.dtype == MACT_F32) {
+        if (deg == 5) launch_inverse_chw4<MACT_F32, 5>(params->xform, ks.ptr, of, n_px, hw, k, mi, gamma, st);
+        else launch_inverse_chw4<MACT_F32, 7>(params->xform, ks.ptr, of, n_px, hw, k, mi, gamma, st);
+      } else {
+        if (deg == 5) launch_inverse_chw4<MACT_F16, 5>(params->xform, ks.ptr, of, n_px, hw, k, mi, gamma, st);
+        else launch_inverse_chw4<MACT_F16, 7>(params->xform, ks.ptr, of, n_px, hw, k, mi, gamma, st);
+      }
     } else {
       const dim3 grid(std::max<uint32_t>(1, (n_px + 255) / 256)), blk(256);
       if (deg == 5) hipLaunchKernelGGL(k_inverse<5>, grid, blk, 0, st, ks, kd, n_px, k, mi, gamma);

@@ -125,6 +125,25 @@ def test_inverse_layouts_and_float16(M, xform):
     assert torch.equal(h, torch.from_numpy(np.moveaxis(a, -1, 1).astype(np.float32)).cuda().half())
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float16], ids=["f32", "f16"])
+@pytest.mark.parametrize("xform", ["lab", "hsi", "sct", "luv"])
+def test_inverse_chw_equals_hwc(M, xform, dtype):
+    # packed CHW planes (the 4-pixel plane kernel where W H is a multiple of 4, the one-pixel kernel
+    # otherwise) give the HWC result's bits, plane by plane
+    g = synth.rng(77)
+    fwd = {"lab": C.rgb_to_lab, "hsi": C.rgb_to_hsi, "sct": C.rgb_to_sct, "luv": C.rgb_to_luv}[xform]
+    p = M.inverse_params(xform)
+    for (n, h, w) in [(2, 16, 20), (1, 33, 36), (3, 8, 1000), (1, 7, 9)]:
+        v = fwd(g.random((n, h, w, 3))).astype(dtype)
+        hwc = torch.from_numpy(v).cuda()
+        chw = torch.from_numpy(np.ascontiguousarray(np.moveaxis(v, -1, 1))).cuda()
+        for gm in (["bt709", "none"] if xform in ("lab", "luv") else ["none"]):
+            a = M.inverse(chw, xform=xform, params=p, layout="chw", gamma=gm)
+            b = M.inverse(hwc, xform=xform, params=p, gamma=gm)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm)
+
+
 @pytest.mark.parametrize("xform", ["lab", "hsi", "sct", "luv"])
 def test_round_trip_on_the_1080p_batch(M, xform):
     # MACT forward then MACT inverse on the GPU returns the 8-bit colours to within a
