@@ -77,7 +77,7 @@ mact_status resolve_image(const mact_image* im, bool is_output, const char* what
     if (h.ps < h.H * h.rs) return fail(MACT_E_INVALID, "%s: plane_stride too small", what);
     h.bs = im->batch_stride ? im->batch_stride : 3 * h.ps;
     if (h.N > 1 && h.bs < 3 * h.ps) return fail(MACT_E_INVALID, "%s: batch_stride too small", what);
-    h.packed = h.rs == h.W && h.ps == h.H * h.W;
+    h.packed = h.rs == h.W && h.ps == h.H * h.W && (h.N == 1 || h.bs == 3 * h.ps);
   }
   if (h.rs < 0 || h.ps < 0 || h.bs < 0) return fail(MACT_E_INVALID, "%s: negative stride", what);
   *out = h;

@@ -305,6 +305,26 @@ def test_hwc_to_chw_equals_hwc_permuted(M, dtype, xform):
                 assert torch.equal(c, r.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm)
 
 
+def test_chw_batch_with_gaps_between_images(M):
+    # CHW images whose batch stride exceeds 3 planes (a slice of a 4-channel batch) are not packed:
+    # every path must honour the batch stride (regression: the plane kernels once assumed it)
+    g = synth.rng(500)
+    base = g.integers(0, 256, (3, 4, 16, 20)).astype(np.uint8)
+    view = torch.from_numpy(base).cuda()[:, :3]
+    packed = torch.from_numpy(np.ascontiguousarray(base[:, :3])).cuda()
+    for xf in (0, 1, 2, 3):
+        for ol in ("chw", "hwc"):
+            a = M.transform(view, xform=xf, layout="chw", out_layout=ol)
+            b = M.transform(packed, xform=xf, layout="chw", out_layout=ol)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b), (xf, ol)
+    f = torch.from_numpy(g.random((2, 4, 8, 12)).astype(np.float32)).cuda()
+    a = M.inverse(f[:, :3], xform="sct", layout="chw")
+    b = M.inverse(f[:, :3].contiguous(), xform="sct", layout="chw")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def test_strided_views(M):
     # a row-strided HWC view and a non-packed output take the general kernel: same values
     img = synth.uniform_u8(64, 80, seed=5)
