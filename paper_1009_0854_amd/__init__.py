@@ -121,6 +121,9 @@ def image(t, layout="hwc", gamma="bt709"):
     if t.numel() == 0:
         # the C ABI reads batch 0 as one image: an empty tensor has no description
         raise ValueError("image(): empty tensor %s" % (tuple(t.shape),))
+    if any(st == 0 and n > 1 for st, n in zip(t.stride(), t.shape)):
+        # the C ABI reads a stride of 0 as "packed": a broadcast view would be read past its storage
+        raise ValueError("image(): broadcast (zero-stride) tensor; call .contiguous() first")
     im = Image()
     im.data = t.data_ptr()
     im.dtype = _dtype_code(t)

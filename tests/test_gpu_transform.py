@@ -279,6 +279,11 @@ def test_empty_inputs_give_empty_outputs(M):
         assert M.transform_backward(xc, xc.clone()).shape == xc.shape
         with pytest.raises(ValueError):
             M.image(x)
+    # broadcast views (zero strides) are refused rather than read past their storage
+    row = torch.zeros((1, 7, 3), dtype=torch.uint8, device="cuda")
+    for v in (row.expand(5, 7, 3), row.unsqueeze(0).expand(4, 1, 7, 3).expand(4, 6, 7, 3)):
+        with pytest.raises(ValueError):
+            M.transform(v)
     torch.cuda.synchronize()
 
 
