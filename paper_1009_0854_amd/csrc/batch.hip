@@ -2,18 +2,21 @@
 // element types, layouts and transforms.
 //
 // Every image is cut into tiles of `tile` pixels; tile t belongs to the image
-// i with tile_start[i] <= t < tile_start[i+1].  A grid sized to the GPU walks
-// the tile list (tile t, t + gridDim.x, ...), so that the workgroups in flight
-// work on neighbouring tiles (one contiguous run of tiles per workgroup
-// measured 7% slower); each workgroup finds its tile's image by binary search
-// (wave-uniform, scalar loads), then transforms the tile's pixels with the
-// same per-pixel functions as the plain kernels --
-// packed 8-bit HWC -> float32 HWC tiles through the 4-pixel LDS-transposed
-// path, everything else one pixel per lane -- so outputs are bitwise equal to
-// mact_transform's.  The plan captures the launch in a HIP graph.  The launch
-// shape (block, tile, vector path, waves per CU) comes from an autotuner that
-// times candidates on the actual batch and caches the winner per GPU and
-// shape class (optionally in a JSON file named by MACT_AUTOTUNE_CACHE).
+// i with tile_start[i] <= t < tile_start[i+1].  The grid either covers the
+// tile list once (one workgroup per tile) or, sized to the GPU, walks it (tile
+// t, t + gridDim.x, ...), so that the workgroups in flight work on
+// neighbouring tiles (one contiguous run of tiles per workgroup measured 7%
+// slower).  Each workgroup finds its tile's image in the plan's per-tile map
+// (or, for the served form's small batches, by a wave-uniform binary search
+// over tile_start), then transforms the tile's pixels with the same per-pixel
+// functions as the plain kernels -- packed 8-bit, 16-bit and float16 HWC ->
+// float32 HWC tiles through the 4-pixel LDS-transposed path, everything else
+// one pixel per lane -- so outputs are bitwise equal to mact_transform's.  The
+// plan captures the launch in a HIP graph.  The launch shape (block, tile,
+// vector path, waves per CU or one workgroup per tile) comes from an
+// autotuner that times candidates on the actual batch and caches the winner
+// per GPU and shape class (optionally in a JSON file named by
+// MACT_AUTOTUNE_CACHE).
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
