@@ -14,6 +14,11 @@
 //   5. stops when max|e| and the smallest levelled error agree to 1e-8.
 // A reference that yields a pole is replaced by the alternation set of the
 // next lower denominator degree with one point inserted (continuation).
+//
+// mact_fit_weighted: the same with a positive weight w, levelling
+// w (p/q - f): the levelled equations carry (-1)^i E q(x_i) / w(x_i), and the
+// extrema, the exchange and the reported eps are those of the weighted error.
+// w is given as samples at equally spaced points, linear in between.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
