@@ -23,6 +23,7 @@
 #include <mutex>
 
 #include "launch.h"
+#include "planes.h"
 
 namespace mact {
 
@@ -235,19 +236,7 @@ __global__ __launch_bounds__(256) void k_inverse_chw4(const void* __restrict__ i
     const uint32_t n = div_hw4.div(g4);
     const size_t base = (size_t)n * 3 * hw + 4 * (size_t)(g4 - n * hw4);
     float v[4][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (IN == MACT_F32) {
-        const f4 x = *reinterpret_cast<const f4*>(static_cast<const float*>(in) + base + (size_t)c * hw);
-        v[0][c] = x.x; v[1][c] = x.y; v[2][c] = x.z; v[3][c] = x.w;
-      } else {
-        const uint2 x = *reinterpret_cast<const uint2*>(static_cast<const __half*>(in) + base + (size_t)c * hw);
-        v[0][c] = __half2float(__ushort_as_half((uint16_t)x.x));
-        v[1][c] = __half2float(__ushort_as_half((uint16_t)(x.x >> 16)));
-        v[2][c] = __half2float(__ushort_as_half((uint16_t)x.y));
-        v[3][c] = __half2float(__ushort_as_half((uint16_t)(x.y >> 16)));
-      }
-    }
+    load_planes4<IN, true>(in, base, hw, v);
     float o[4][3];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {

@@ -21,6 +21,7 @@
 #include <mutex>
 
 #include "launch.h"
+#include "planes.h"
 
 namespace mact {
 
@@ -475,27 +476,7 @@ __global__ __launch_bounds__(256) void k_chw4(const void* __restrict__ in, float
     const uint32_t n = div_hw4.div(g4);
     const size_t base = (size_t)n * 3 * hw + 4 * (size_t)(g4 - n * hw4);  // element offset of plane 0
     float v[4][3];  // raw values, as load_px returns them
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (IN == MACT_F32) {
-        const f4 x = *reinterpret_cast<const f4*>(static_cast<const float*>(in) + base + (size_t)c * hw);
-        v[0][c] = clamp01(x.x); v[1][c] = clamp01(x.y); v[2][c] = clamp01(x.z); v[3][c] = clamp01(x.w);
-      } else if (IN == MACT_F16) {
-        const uint2 x = *reinterpret_cast<const uint2*>(static_cast<const __half*>(in) + base + (size_t)c * hw);
-        v[0][c] = clamp01(__half2float(__ushort_as_half((uint16_t)x.x)));
-        v[1][c] = clamp01(__half2float(__ushort_as_half((uint16_t)(x.x >> 16))));
-        v[2][c] = clamp01(__half2float(__ushort_as_half((uint16_t)x.y)));
-        v[3][c] = clamp01(__half2float(__ushort_as_half((uint16_t)(x.y >> 16))));
-      } else if (IN == MACT_U16) {
-        const uint2 x = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(in) + base + (size_t)c * hw);
-        v[0][c] = (float)(x.x & 0xffffu); v[1][c] = (float)(x.x >> 16);
-        v[2][c] = (float)(x.y & 0xffffu); v[3][c] = (float)(x.y >> 16);
-      } else {
-        const uint32_t x = *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(in) + base + (size_t)c * hw);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v[j][c] = (float)((x >> (8 * j)) & 0xffu);
-      }
-    }
+    load_planes4<IN>(in, base, hw, v);
     float o[3][4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -593,27 +574,7 @@ __global__ __launch_bounds__(kHotBlock) void k_chw_hwc4(const void* __restrict__
     const uint32_t n = div_hw4.div(g4);
     const size_t base = (size_t)n * 3 * hw + 4 * (size_t)(g4 - n * hw4);  // element offset in plane 0
     float v[4][3];
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      if (IN == MACT_F32) {
-        const f4 x = *reinterpret_cast<const f4*>(static_cast<const float*>(in) + base + (size_t)ch * hw);
-        v[0][ch] = clamp01(x.x); v[1][ch] = clamp01(x.y); v[2][ch] = clamp01(x.z); v[3][ch] = clamp01(x.w);
-      } else if (IN == MACT_F16) {
-        const uint2 x = *reinterpret_cast<const uint2*>(static_cast<const __half*>(in) + base + (size_t)ch * hw);
-        v[0][ch] = clamp01(__half2float(__ushort_as_half((uint16_t)x.x)));
-        v[1][ch] = clamp01(__half2float(__ushort_as_half((uint16_t)(x.x >> 16))));
-        v[2][ch] = clamp01(__half2float(__ushort_as_half((uint16_t)x.y)));
-        v[3][ch] = clamp01(__half2float(__ushort_as_half((uint16_t)(x.y >> 16))));
-      } else if (IN == MACT_U16) {
-        const uint2 x = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(in) + base + (size_t)ch * hw);
-        v[0][ch] = (float)(x.x & 0xffffu); v[1][ch] = (float)(x.x >> 16);
-        v[2][ch] = (float)(x.y & 0xffffu); v[3][ch] = (float)(x.y >> 16);
-      } else {
-        const uint32_t x = *reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(in) + base + (size_t)ch * hw);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v[j][ch] = (float)((x >> (8 * j)) & 0xffu);
-      }
-    }
+    load_planes4<IN>(in, base, hw, v);
 #pragma unroll
     for (int j = 0; j < 4; ++j) px1<IN, XF, DEG>(k, gamma, gtab, v[j], o + 3 * j);
   } else {
