@@ -224,6 +224,26 @@ def bench_weighted_fits(M, x, y, n_px, steps):
     return out
 
 
+def bench_exact_gain(M, x, y, n_px, steps):
+    """MACT's gain over the exact transforms in float32 with the device's
+    elementary functions (the paper's Table 11 comparison, on the GPU): the
+    same batch, the same access pattern, float32 and float16 output."""
+    import torch
+    out = {}
+    y16 = torch.empty(y.shape, dtype=torch.float16, device="cuda")
+    for name, xf in (("lab", 0), ("hsi", 1), ("sct", 2), ("luv", 3)):
+        p = M.default_params(xf)
+        r = {}
+        for tag, o in (("f32_out", y), ("f16_out", y16)):
+            m_ms, _ = time_kernel(lambda: M.transform(x, params=p, out=o), steps)
+            e_ms, _ = time_kernel(lambda: M.transform_exact(x, xform=xf, out=o), steps)
+            r[tag] = {"mact_ms": m_ms, "exact_ms": e_ms, "gain": e_ms / m_ms,
+                      "mact_Mpx_s": n_px / m_ms / 1e3, "exact_Mpx_s": n_px / e_ms / 1e3}
+        out[name] = r
+    del y16
+    return out
+
+
 def bench_lut(M, x, y, n_px, steps):
     out = {}
     for N in (9, 17, 33):
@@ -500,6 +520,8 @@ def main():
         del cube
         log("inverses and on-device error statistics")
         forms["inverse"] = bench_inverse(M, x, y, n_px, a.steps)
+        log("gain over the exact float32 transforms")
+        forms["exact_gain"] = bench_exact_gain(M, x, y, n_px, a.steps)
         log("weighted cube-root fits")
         forms["weighted_fits"] = bench_weighted_fits(M, x, y, n_px, a.steps)
     if a.forms in ("all", "lut"):

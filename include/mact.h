@@ -217,6 +217,18 @@ mact_status mact_params_default(int32_t xform, mact_params* p);
 mact_status mact_transform(const mact_params* params, const mact_image* in, const mact_image* out,
                            void* hip_stream);
 
+/* The exact transform of `xform` in float32 with the device's elementary
+   functions -- the baseline MACT replaces, for measuring its gain as the paper
+   does against the C library's functions (Sec. 3.5, Table 11).  Everything but
+   the approximated functions is MACT's own arithmetic: the 8-bit inverse-gamma
+   table, the matrix, the linear segment, Kender's branches.  LAB / LUV use
+   cbrtf; HSI atanf(sqrt 3 x); SCT sqrtf, arccos(B/L) as 2 asinf(sqrt((1 - B/L)
+   / 2)) where B/L >= 0.5 and acosf(B/L) below, and atan2f(G, R).  in: packed
+   8-bit HWC, 4-byte aligned; out: packed float32 or float16 HWC, 16-byte
+   aligned.  Errors: as mact_transform; MACT_E_UNSUPPORTED for other element
+   types, layouts or alignments. */
+mact_status mact_transform_exact(int32_t xform, const mact_image* in, const mact_image* out, void* hip_stream);
+
 /* Vector-Jacobian product of the LAB transform (chain rule through the
    definition of Sec. 3.2 with f~ in place of the cube root; the paper does not
    differentiate the transform):

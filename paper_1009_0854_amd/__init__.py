@@ -15,6 +15,7 @@ from ._abi import (CHW, E_BUSY, E_NOCONV, F16, F32, FN_ACOS, FN_ASIN2, FN_ATAN, 
                    U8, Approx, Image, MactError, Params, Request, ServerConfig, ServerStats, Tune, lib)
 
 __all__ = ["fit", "dark_end_weight", "default_approx", "paper_approx", "default_params", "make_params", "image", "transform",
+           "transform_exact",
            "transform_backward", "inverse_params", "inverse", "error_stats", "lut_bytes", "lut_build",
            "lut_interp", "lut_cells_bytes", "lut_cells_build", "lut_cells_interp", "BatchPlan", "batch_run",
            "Server", "stream_u8_to_f32", "copy", "MactError", "MactLab"]
@@ -181,6 +182,19 @@ def transform(x, xform="lab", params=None, layout="hwc", gamma="bt709", out=None
         return out
     A.check(lib().mact_transform(ctypes.byref(p), ctypes.byref(image(x, layout, gamma)),
                                  ctypes.byref(image(out, out_layout)), _stream(stream)))
+    return out
+
+
+def transform_exact(x, xform="lab", gamma="bt709", out=None, out_dtype=None, stream=None):
+    """mact_transform_exact: the exact transform in float32 with the device's
+    elementary functions (the baseline MACT replaces), packed 8-bit HWC in."""
+    torch = _torch()
+    if out is None:
+        out = _out_like(x, "hwc", "hwc", out_dtype or torch.float32)
+    if x.numel() == 0:
+        return out
+    A.check(lib().mact_transform_exact(_xf(xform), ctypes.byref(image(x, "hwc", gamma)),
+                                       ctypes.byref(image(out, "hwc")), _stream(stream)))
     return out
 
 

@@ -80,6 +80,7 @@ SIGNATURES = {
     "mact_version": (c_char_p, []),
     "mact_fit": (c_int32, [c_int32, c_int32, c_int32, c_double, c_double, POINTER(Approx)]),
     "mact_fit_ex": (c_int32, [c_int32, c_int32, c_int32, c_double, c_double, c_int32, POINTER(Approx)]),
+    "mact_transform_exact": (c_int32, [c_int32, POINTER(Image), POINTER(Image), c_void_p]),
     "mact_fit_weighted": (c_int32, [c_int32, c_int32, c_int32, c_double, c_double, POINTER(c_double), c_int32,
                                     c_int32, POINTER(Approx)]),
     "mact_default_approx": (c_int32, [c_int32, POINTER(Approx)]),

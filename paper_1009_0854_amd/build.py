@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmact.so")
 BUILD = os.path.join(ROOT, "_build")
 
-HIP_SOURCES = ["xform.hip", "lut.hip", "batch.hip", "serve.hip", "inverse.hip"]
+HIP_SOURCES = ["xform.hip", "lut.hip", "batch.hip", "serve.hip", "inverse.hip", "exact.hip"]
 CPP_SOURCES = ["remez.cpp", "host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

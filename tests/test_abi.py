@@ -378,6 +378,20 @@ def test_fast_division_method():
         np.testing.assert_array_equal(q, n // np.uint64(d))
 
 
+def test_exact_baseline_validation_without_gpu(M):
+    from paper_1009_0854_amd import _abi as A
+    L = M.lib()
+    u8, f32, o32 = _img(0x1000, A.U8), _img(0x1000, A.F32), _img(0x2000, A.F32)
+    assert L.mact_transform_exact(4, ctypes.byref(u8), ctypes.byref(o32), None) == A.E_INVALID
+    assert L.mact_transform_exact(-1, ctypes.byref(u8), ctypes.byref(o32), None) == A.E_INVALID
+    assert L.mact_transform_exact(0, ctypes.byref(f32), ctypes.byref(o32), None) == A.E_UNSUPPORTED
+    chw = _img(0x1000, A.U8, layout=A.CHW)
+    assert L.mact_transform_exact(0, ctypes.byref(chw), ctypes.byref(o32), None) == A.E_UNSUPPORTED
+    assert L.mact_transform_exact(0, None, ctypes.byref(o32), None) == A.E_INVALID
+    assert L.mact_transform_exact(0, ctypes.byref(u8), ctypes.byref(_img(0x2000, A.U8)), None) == A.E_UNSUPPORTED
+    assert b"mact_transform_exact" in L.mact_last_error()
+
+
 def test_inverse_and_error_stats_validation_without_gpu(M):
     # every case is rejected before any launch
     from paper_1009_0854_amd import _abi as A
