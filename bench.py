@@ -140,29 +140,36 @@ def bench_4k(M, p, steps):
 
 
 def bench_general(M, x, y, p, n_px, steps):
-    """CIELAB on layouts other than packed HWC: the 8-bit batch as a
-    row-padded view (rows 8 pixels apart beyond their width; the row-strided
-    kernel) into packed float32 HWC, as CHW planes into HWC (the
-    one-pixel-per-lane kernel) and into CHW (the CHW kernel), and packed HWC
-    into CHW.  15 bytes per pixel."""
+    """CIELAB on layouts other than packed HWC, float32 (15 bytes per pixel)
+    and float16 output (9): the 8-bit batch as a row-padded view (rows 8
+    pixels apart beyond their width; the row-strided kernel) into packed HWC,
+    as CHW planes into HWC and into CHW, and packed HWC into CHW (the plane
+    kernels)."""
     import torch
     out = {}
     n, h, w, _ = x.shape
+    y16 = y.view(-1).view(torch.float16)[: n_px * 3].view(n, h, w, 3)  # float16 output in y's memory
+
+    def rec(name, ms, bpp):
+        out[name] = {"Mpx_s": n_px / ms / 1e3, "GBs": bpp * n_px / ms / 1e6, "ms": ms}
+
     pad = torch.empty((n, h, w + 8, 3), dtype=torch.uint8, device="cuda")
     pad[:, :, :w] = x
     view = pad[:, :, :w]
-    ms, _ = time_kernel(lambda: M.transform(view, params=p, out=y), steps)
-    out["u8_row_padded_view"] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
+    for tag, o, bpp in (("", y, 15.0), ("_f16", y16, 9.0)):
+        ms, _ = time_kernel(lambda: M.transform(view, params=p, out=o), steps)
+        rec("u8_row_padded_view" + tag, ms, bpp)
     del pad, view
     chw = x.permute(0, 3, 1, 2).contiguous()
-    ms, _ = time_kernel(lambda: M.transform(chw, params=p, layout="chw", out=y, out_layout="hwc"), steps)
-    out["u8_chw_to_hwc"] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
-    ychw = y.view(n, 3, h, w)
-    ms, _ = time_kernel(lambda: M.transform(chw, params=p, layout="chw", out=ychw, out_layout="chw"), steps)
-    out["u8_chw_to_chw"] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
-    ms, _ = time_kernel(lambda: M.transform(x, params=p, out=ychw, out_layout="chw"), steps)
-    out["u8_hwc_to_chw"] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "ms": ms}
-    del chw, ychw
+    for tag, o, bpp in (("", y, 15.0), ("_f16", y16, 9.0)):
+        ochw = o.view(n, 3, h, w)
+        ms, _ = time_kernel(lambda: M.transform(chw, params=p, layout="chw", out=o, out_layout="hwc"), steps)
+        rec("u8_chw_to_hwc" + tag, ms, bpp)
+        ms, _ = time_kernel(lambda: M.transform(chw, params=p, layout="chw", out=ochw, out_layout="chw"), steps)
+        rec("u8_chw_to_chw" + tag, ms, bpp)
+        ms, _ = time_kernel(lambda: M.transform(x, params=p, out=ochw, out_layout="chw"), steps)
+        rec("u8_hwc_to_chw" + tag, ms, bpp)
+    del chw
     return out
 
 

@@ -392,11 +392,64 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4f(const f4* __restrict__ in, 
   }
 }
 
+// Helpers of the kernels below whose output is float32 or float16 (OUT).
+//
+// stage4: a lane's 4 results (12 values, pixel by pixel) into its wave's LDS
+// slice, at 16-byte word 3 lane (float32) or 8-byte word 3 lane (float16,
+// rounded to nearest even).
+template <int OUT>
+__device__ __forceinline__ void stage4(f4* slice, uint32_t lane, const float o[12]) {
+  if (OUT == MACT_F32) {
+    slice[3 * lane] = f4{o[0], o[1], o[2], o[3]};
+    slice[3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
+    slice[3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+  } else {
+    f2* s2 = reinterpret_cast<f2*>(slice);
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      s2[3 * lane + t] = f2{__uint_as_float(pack2_h_rn(o[4 * t], o[4 * t + 1])),
+                            __uint_as_float(pack2_h_rn(o[4 * t + 2], o[4 * t + 3]))};
+  }
+}
+
+// store_staged: once every lane has staged, the wave's cnt pixels (a multiple
+// of 4, at most 256) from its slice to packed HWC output at dst.  float32
+// leaves as 16-byte stores (each instruction 1 KB of contiguous output, dst
+// 16-byte aligned), float16 as 8-byte stores (512 B per instruction; dst need
+// only be 8-byte aligned, which any run of a multiple of 4 pixels keeps).
+template <int OUT>
+__device__ __forceinline__ void store_staged(const f4* slice, void* dst, uint32_t cnt, uint32_t lane) {
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): every lane's LDS writes have landed
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t n_valid = cnt / 4u * 3u;  // 16-byte (float32) or 8-byte (float16) words
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const uint32_t e = q * 64 + lane;
+    if (e < n_valid) {
+      if (OUT == MACT_F32) __builtin_nontemporal_store(slice[e], static_cast<f4*>(dst) + e);
+      else __builtin_nontemporal_store(reinterpret_cast<const f2*>(slice)[e], static_cast<f2*>(dst) + e);
+    }
+  }
+}
+
+// store_plane4: a lane's 4 results of one output plane to packed CHW output at
+// element offset e (a multiple of 4): one 16-byte (float32) or 8-byte (float16)
+// store, contiguous across the wave.
+template <int OUT>
+__device__ __forceinline__ void store_plane4(void* out, size_t e, float a, float b, float c, float d) {
+  if (OUT == MACT_F32)
+    __builtin_nontemporal_store(f4{a, b, c, d}, reinterpret_cast<f4*>(static_cast<float*>(out) + e));
+  else
+    __builtin_nontemporal_store(f2{__uint_as_float(pack2_h_rn(a, b)), __uint_as_float(pack2_h_rn(c, d))},
+                                reinterpret_cast<f2*>(static_cast<__half*>(out) + e));
+}
+
 // Row-strided HWC (a view whose rows or images are not adjacent: a crop, a
-// pitched allocation) -> packed float32 HWC, W a multiple of 4.  Every row is
-// cut into 256-pixel chunks, the last one partial, one chunk per wave; each
-// chunk takes k_hwc4's 12-byte loads (lanes past the row's end idle), its
-// per-pixel code and its LDS-transposed 1 KB stores.  Requires the input
+// pitched allocation) -> packed float32 or float16 HWC, W a multiple of 4.
+// Every row is cut into 256-pixel chunks, the last one partial, one chunk per
+// wave; each chunk takes k_hwc4's 12-byte loads (lanes past the row's end
+// idle), its per-pixel code and its LDS-transposed stores.  Requires the input
 // pointer and both strides (in bytes) to be multiples of 4 and `out` 16-byte
 // aligned.
 struct RowGeom {
@@ -405,11 +458,12 @@ struct RowGeom {
   uint64_t rs_b, bs_b;     // input row and image strides in bytes
 };
 
-template <int IN, int DEG, int XF>
-__global__ __launch_bounds__(kHotBlock) void k_rows4(const uint8_t* __restrict__ in, float* __restrict__ out,
+template <int IN, int OUT, int DEG, int XF>
+__global__ __launch_bounds__(kHotBlock) void k_rows4(const uint8_t* __restrict__ in, void* __restrict__ out,
                                                      uint32_t n_chunks, RowGeom g, KCoef k, int gamma) {
   constexpr int WPC = IN == MACT_U8 ? 1 : 2;  // 12-byte words per lane (16-bit inputs: 2)
-  __shared__ f4 s_out[kHotWaves][192];
+  constexpr uint32_t OSZ = OUT == MACT_F32 ? 4 : 2;
+  __shared__ f4 s_out[kHotWaves][3 * OSZ * 16];
   __shared__ float gtab[256];
   if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
     for (uint32_t i = threadIdx.x; i < 256u; i += kHotBlock) gtab[i] = k_gamma_table[gamma][i];
@@ -435,19 +489,8 @@ __global__ __launch_bounds__(kHotBlock) void k_rows4(const uint8_t* __restrict__
 #pragma unroll
     for (int q = 0; q < 12; ++q) o[q] = 0.0f;
   }
-  s_out[wv][3 * lane] = f4{o[0], o[1], o[2], o[3]};
-  s_out[wv][3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
-  s_out[wv][3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): every lane's LDS writes have landed
-  __builtin_amdgcn_wave_barrier();
-  const uint32_t n_valid = cnt / 4u * 3u;  // 16-byte words of the chunk's output
-  f4* dst = reinterpret_cast<f4*>(out) + ((uint64_t)r * g.W + px0) / 4u * 3u;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const uint32_t e = q * 64 + lane;
-    if (e < n_valid) __builtin_nontemporal_store(s_out[wv][e], dst + e);
-  }
+  stage4<OUT>(s_out[wv], lane, o);
+  store_staged<OUT>(s_out[wv], static_cast<char*>(out) + ((uint64_t)r * g.W + px0) * 3u * OSZ, cnt, lane);
 }
 
 // Blocks of k_hwc4 for n_px pixels: every full chunk covered once, and at
@@ -457,12 +500,12 @@ static unsigned hot_grid(uint32_t n_px, int cpw = kChunksPerWave) {
   return std::max<unsigned>(1, ((n_px >> 8) + per_block - 1) / per_block);
 }
 
-// Packed CHW (float32, float16, 16-bit or 8-bit) -> packed float32 CHW, 4
-// pixels per lane: one 16-, 8- or 4-byte load per plane and one 16-byte store
-// per plane, each contiguous across the wave.  Requires W H % 4 == 0 and the
-// input pointer aligned to 4 elements.
-template <int IN, int DEG, int XF>
-__global__ __launch_bounds__(256) void k_chw4(const void* __restrict__ in, float* __restrict__ out, uint32_t n_px,
+// Packed CHW (float32, float16, 16-bit or 8-bit) -> packed float32 or float16
+// CHW, 4 pixels per lane: one 16-, 8- or 4-byte load per plane and one 16- or
+// 8-byte store per plane, each contiguous across the wave.  Requires W H % 4
+// == 0 and the input pointer aligned to 4 elements.
+template <int IN, int OUT, int DEG, int XF>
+__global__ __launch_bounds__(256) void k_chw4(const void* __restrict__ in, void* __restrict__ out, uint32_t n_px,
                                                uint32_t hw, FastDiv div_hw4, KCoef k, int gamma) {
   __shared__ float gtab[256];
   if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
@@ -485,20 +528,18 @@ __global__ __launch_bounds__(256) void k_chw4(const void* __restrict__ in, float
       o[0][j] = r[0]; o[1][j] = r[1]; o[2][j] = r[2];
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      __builtin_nontemporal_store(f4{o[c][0], o[c][1], o[c][2], o[c][3]},
-                                  reinterpret_cast<f4*>(out + base + (size_t)c * hw));
+    for (int c = 0; c < 3; ++c) store_plane4<OUT>(out, base + (size_t)c * hw, o[c][0], o[c][1], o[c][2], o[c][3]);
   }
 }
 
-// Packed HWC (8-bit, 16-bit, float16 or float32) -> packed float32 CHW, 4
-// pixels per lane with W H a multiple of 4: the lane loads its 4 pixels as one
-// 12-byte load (two for 16-bit types, three 16-byte loads for float32; the
-// wave's loads cover one contiguous run), and writes each output plane's 4
-// values as one 16-byte store, contiguous across the wave.  No LDS.  Requires
-// `in` aligned to 4 bytes (16 for float32) and `out` to 16.
-template <int IN, int DEG, int XF>
-__global__ __launch_bounds__(256) void k_hwc_chw4(const void* __restrict__ in, float* __restrict__ out,
+// Packed HWC (8-bit, 16-bit, float16 or float32) -> packed float32 or float16
+// CHW, 4 pixels per lane with W H a multiple of 4: the lane loads its 4 pixels
+// as one 12-byte load (two for 16-bit types, three 16-byte loads for float32;
+// the wave's loads cover one contiguous run), and writes each output plane's 4
+// values as one 16- or 8-byte store, contiguous across the wave.  No LDS.
+// Requires `in` aligned to 4 bytes (16 for float32) and `out` to 16.
+template <int IN, int OUT, int DEG, int XF>
+__global__ __launch_bounds__(256) void k_hwc_chw4(const void* __restrict__ in, void* __restrict__ out,
                                                   uint32_t n_px, uint32_t hw, FastDiv div_hw4, KCoef k, int gamma) {
   __shared__ float gtab[256];
   if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
@@ -542,22 +583,21 @@ __global__ __launch_bounds__(256) void k_hwc_chw4(const void* __restrict__ in, f
     const uint32_t n = div_hw4.div(g4);
     const size_t base = (size_t)n * 3 * hw + 4 * (size_t)(g4 - n * hw4);
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      __builtin_nontemporal_store(f4{o[c][0], o[c][1], o[c][2], o[c][3]},
-                                  reinterpret_cast<f4*>(out + base + (size_t)c * hw));
+    for (int c = 0; c < 3; ++c) store_plane4<OUT>(out, base + (size_t)c * hw, o[c][0], o[c][1], o[c][2], o[c][3]);
   }
 }
 
-// Packed CHW (8-bit, 16-bit, float16 or float32) -> packed float32 HWC, W H a
-// multiple of 4: one 256-pixel chunk of the batch per wave (the last one
-// partial).  Each lane loads its 4 pixels from each plane (one 4-, 8- or
+// Packed CHW (8-bit, 16-bit, float16 or float32) -> packed float32 or float16
+// HWC, W H a multiple of 4: one 256-pixel chunk of the batch per wave (the last
+// one partial).  Each lane loads its 4 pixels from each plane (one 4-, 8- or
 // 16-byte load per plane, contiguous across the wave), computes them, and the
-// results leave through the wave's LDS slice as k_hwc4's 1 KB stores.
-template <int IN, int DEG, int XF>
-__global__ __launch_bounds__(kHotBlock) void k_chw_hwc4(const void* __restrict__ in, float* __restrict__ out,
+// results leave through the wave's LDS slice as in k_rows4.
+template <int IN, int OUT, int DEG, int XF>
+__global__ __launch_bounds__(kHotBlock) void k_chw_hwc4(const void* __restrict__ in, void* __restrict__ out,
                                                         uint32_t n_px, uint32_t hw, FastDiv div_hw4, KCoef k,
                                                         int gamma) {
-  __shared__ f4 s_out[kHotWaves][192];
+  constexpr uint32_t OSZ = OUT == MACT_F32 ? 4 : 2;
+  __shared__ f4 s_out[kHotWaves][3 * OSZ * 16];
   __shared__ float gtab[256];
   if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
     for (uint32_t i = threadIdx.x; i < 256u; i += kHotBlock) gtab[i] = k_gamma_table[gamma][i];
@@ -581,19 +621,8 @@ __global__ __launch_bounds__(kHotBlock) void k_chw_hwc4(const void* __restrict__
 #pragma unroll
     for (int q = 0; q < 12; ++q) o[q] = 0.0f;
   }
-  s_out[wv][3 * lane] = f4{o[0], o[1], o[2], o[3]};
-  s_out[wv][3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
-  s_out[wv][3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): every lane's LDS writes have landed
-  __builtin_amdgcn_wave_barrier();
-  const uint32_t n_valid = cnt / 4u * 3u;
-  f4* dst = reinterpret_cast<f4*>(out) + (size_t)c * 192;
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const uint32_t e = q * 64 + lane;
-    if (e < n_valid) __builtin_nontemporal_store(s_out[wv][e], dst + e);
-  }
+  stage4<OUT>(s_out[wv], lane, o);
+  store_staged<OUT>(s_out[wv], static_cast<char*>(out) + (size_t)c * 768u * OSZ, cnt, lane);
 }
 
 template <int DEG>
@@ -796,70 +825,96 @@ static void launch_hwc4f(int xform, int out_dtype, int deg, const void* in, void
   }
 }
 
-template <int IN, int DEG>
-static void launch_rows4_deg(int xform, const void* in, float* out, uint32_t n_chunks, const RowGeom& g,
-                             const KCoef& k, int gamma, hipStream_t st) {
+// The layout kernels below, instanced over output type and degree: OUT is
+// float32 or float16; DEG as for k_hwc4 (k_rows4) or 5 / 7 (the others).
+template <int IN, int OUT, int DEG>
+static void launch_rows4(int xform, const void* in, void* out, uint32_t n_chunks, const RowGeom& g, const KCoef& k,
+                         int gamma, hipStream_t st) {
   const dim3 grid(std::max<uint32_t>(1, (n_chunks + kHotWaves - 1) / kHotWaves)), blk(kHotBlock);
   const uint8_t* i8 = static_cast<const uint8_t*>(in);
-  if (xform == MACT_LAB) hipLaunchKernelGGL((k_rows4<IN, DEG, MACT_LAB>), grid, blk, 0, st, i8, out, n_chunks, g, k, gamma);
-  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_rows4<IN, DEG, MACT_HSI>), grid, blk, 0, st, i8, out, n_chunks, g, k, gamma);
-  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_rows4<IN, DEG, MACT_LUV>), grid, blk, 0, st, i8, out, n_chunks, g, k, gamma);
-  else hipLaunchKernelGGL((k_rows4<IN, DEG, MACT_SCT>), grid, blk, 0, st, i8, out, n_chunks, g, k, gamma);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_rows4<IN, OUT, DEG, MACT_LAB>), grid, blk, 0, st, i8, out, n_chunks, g, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_rows4<IN, OUT, DEG, MACT_HSI>), grid, blk, 0, st, i8, out, n_chunks, g, k, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_rows4<IN, OUT, DEG, MACT_LUV>), grid, blk, 0, st, i8, out, n_chunks, g, k, gamma);
+  else hipLaunchKernelGGL((k_rows4<IN, OUT, DEG, MACT_SCT>), grid, blk, 0, st, i8, out, n_chunks, g, k, gamma);
+}
+
+template <int IN, int OUT>
+static void launch_rows4_deg(int xform, int deg, const void* in, void* out, uint32_t n_chunks, const RowGeom& g,
+                             const KCoef& k, int gamma, hipStream_t st) {
+  if (deg <= 4) launch_rows4<IN, OUT, 4>(xform, in, out, n_chunks, g, k, gamma, st);
+  else if (deg == 5) launch_rows4<IN, OUT, 5>(xform, in, out, n_chunks, g, k, gamma, st);
+  else launch_rows4<IN, OUT, 7>(xform, in, out, n_chunks, g, k, gamma, st);
 }
 
 template <int IN>
-static void launch_rows4(int xform, int deg, const void* in, float* out, uint32_t n_chunks, const RowGeom& g,
-                         const KCoef& k, int gamma, hipStream_t st) {
-  if (deg <= 4) launch_rows4_deg<IN, 4>(xform, in, out, n_chunks, g, k, gamma, st);
-  else if (deg == 5) launch_rows4_deg<IN, 5>(xform, in, out, n_chunks, g, k, gamma, st);
-  else launch_rows4_deg<IN, 7>(xform, in, out, n_chunks, g, k, gamma, st);
+static void launch_rows4_io(int xform, int out_dtype, int deg, const void* in, void* out, uint32_t n_chunks,
+                            const RowGeom& g, const KCoef& k, int gamma, hipStream_t st) {
+  if (out_dtype == MACT_F32) launch_rows4_deg<IN, MACT_F32>(xform, deg, in, out, n_chunks, g, k, gamma, st);
+  else launch_rows4_deg<IN, MACT_F16>(xform, deg, in, out, n_chunks, g, k, gamma, st);
 }
 
-template <int IN, int DEG>
-static void launch_hwc_chw4(int xform, const void* in, float* out, uint32_t n_px, uint32_t hw, const KCoef& k,
+template <int IN, int OUT, int DEG>
+static void launch_hwc_chw4(int xform, const void* in, void* out, uint32_t n_px, uint32_t hw, const KCoef& k,
                             int gamma, hipStream_t st) {
   const dim3 grid(full_grid(n_px / 4, 256)), blk(256);
   const FastDiv d = make_fastdiv(hw / 4);
-  if (xform == MACT_LAB) hipLaunchKernelGGL((k_hwc_chw4<IN, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
-  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_hwc_chw4<IN, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
-  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_hwc_chw4<IN, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
-  else hipLaunchKernelGGL((k_hwc_chw4<IN, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_hwc_chw4<IN, OUT, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_hwc_chw4<IN, OUT, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_hwc_chw4<IN, OUT, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else hipLaunchKernelGGL((k_hwc_chw4<IN, OUT, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
 }
 
-template <int IN, int DEG>
-static void launch_chw_hwc4(int xform, const void* in, float* out, uint32_t n_px, uint32_t hw, const KCoef& k,
+template <int IN, int OUT, int DEG>
+static void launch_chw_hwc4(int xform, const void* in, void* out, uint32_t n_px, uint32_t hw, const KCoef& k,
                             int gamma, hipStream_t st) {
   const dim3 grid(std::max<uint32_t>(1, (((n_px + 255u) >> 8) + kHotWaves - 1) / kHotWaves)), blk(kHotBlock);
   const FastDiv d = make_fastdiv(hw / 4);
-  if (xform == MACT_LAB) hipLaunchKernelGGL((k_chw_hwc4<IN, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
-  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_chw_hwc4<IN, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
-  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_chw_hwc4<IN, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
-  else hipLaunchKernelGGL((k_chw_hwc4<IN, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_chw_hwc4<IN, OUT, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_chw_hwc4<IN, OUT, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_chw_hwc4<IN, OUT, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else hipLaunchKernelGGL((k_chw_hwc4<IN, OUT, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
 }
 
-template <int IN>
-static void launch_chw_hwc4_deg(int xform, int deg, const void* in, float* out, uint32_t n_px, uint32_t hw,
-                                const KCoef& k, int gamma, hipStream_t st) {
-  if (deg == 5) launch_chw_hwc4<IN, 5>(xform, in, out, n_px, hw, k, gamma, st);
-  else launch_chw_hwc4<IN, 7>(xform, in, out, n_px, hw, k, gamma, st);
-}
-
-template <int IN>
-static void launch_hwc_chw4_deg(int xform, int deg, const void* in, float* out, uint32_t n_px, uint32_t hw,
-                                const KCoef& k, int gamma, hipStream_t st) {
-  if (deg == 5) launch_hwc_chw4<IN, 5>(xform, in, out, n_px, hw, k, gamma, st);
-  else launch_hwc_chw4<IN, 7>(xform, in, out, n_px, hw, k, gamma, st);
-}
-
-template <int IN, int DEG>
-static void launch_chw4(int xform, const void* in, float* out, uint32_t n_px, uint32_t hw, const KCoef& k, int gamma,
+template <int IN, int OUT, int DEG>
+static void launch_chw4(int xform, const void* in, void* out, uint32_t n_px, uint32_t hw, const KCoef& k, int gamma,
                         hipStream_t st) {
   const dim3 grid(full_grid(n_px / 4, 256)), blk(256);
   const FastDiv d = make_fastdiv(hw / 4);
-  if (xform == MACT_LAB) hipLaunchKernelGGL((k_chw4<IN, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
-  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_chw4<IN, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
-  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_chw4<IN, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
-  else hipLaunchKernelGGL((k_chw4<IN, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_chw4<IN, OUT, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_chw4<IN, OUT, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_chw4<IN, OUT, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+  else hipLaunchKernelGGL((k_chw4<IN, OUT, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, hw, d, k, gamma);
+}
+
+// The three plane kernels, by kind (0: CHW -> CHW, 1: HWC -> CHW, 2: CHW ->
+// HWC), input type, output type and degree (5 or 7).
+template <int KIND, int IN, int OUT, int DEG>
+static void launch_planes(int xform, const void* in, void* out, uint32_t n_px, uint32_t hw, const KCoef& k, int gamma,
+                          hipStream_t st) {
+  if (KIND == 0) launch_chw4<IN, OUT, DEG>(xform, in, out, n_px, hw, k, gamma, st);
+  else if (KIND == 1) launch_hwc_chw4<IN, OUT, DEG>(xform, in, out, n_px, hw, k, gamma, st);
+  else launch_chw_hwc4<IN, OUT, DEG>(xform, in, out, n_px, hw, k, gamma, st);
+}
+
+template <int KIND, int IN>
+static void launch_planes_io(int xform, int out_dtype, int deg, const void* in, void* out, uint32_t n_px, uint32_t hw,
+                             const KCoef& k, int gamma, hipStream_t st) {
+  if (out_dtype == MACT_F32) {
+    if (deg == 5) launch_planes<KIND, IN, MACT_F32, 5>(xform, in, out, n_px, hw, k, gamma, st);
+    else launch_planes<KIND, IN, MACT_F32, 7>(xform, in, out, n_px, hw, k, gamma, st);
+  } else {
+    if (deg == 5) launch_planes<KIND, IN, MACT_F16, 5>(xform, in, out, n_px, hw, k, gamma, st);
+    else launch_planes<KIND, IN, MACT_F16, 7>(xform, in, out, n_px, hw, k, gamma, st);
+  }
+}
+
+template <int KIND>
+static void launch_planes_any(int in_dtype, int xform, int out_dtype, int deg, const void* in, void* out,
+                              uint32_t n_px, uint32_t hw, const KCoef& k, int gamma, hipStream_t st) {
+  if (in_dtype == MACT_U8) launch_planes_io<KIND, MACT_U8>(xform, out_dtype, deg, in, out, n_px, hw, k, gamma, st);
+  else if (in_dtype == MACT_U16) launch_planes_io<KIND, MACT_U16>(xform, out_dtype, deg, in, out, n_px, hw, k, gamma, st);
+  else if (in_dtype == MACT_F16) launch_planes_io<KIND, MACT_F16>(xform, out_dtype, deg, in, out, n_px, hw, k, gamma, st);
+  else launch_planes_io<KIND, MACT_F32>(xform, out_dtype, deg, in, out, n_px, hw, k, gamma, st);
 }
 
 static bool aligned(const void* p, size_t a) { return (uintptr_t)p % a == 0; }
@@ -882,23 +937,19 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   const int deg = pack_coef(*params, &k, &exact_deg);
   const int gamma = uses_gamma(params->xform) ? hi.gamma : MACT_GAMMA_NONE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  // fast shapes: packed HWC of any input type -> packed float32 / float16 HWC or (W H a multiple
-  // of 4) packed float32 CHW, row-strided HWC -> packed float32 HWC, and packed CHW of any input type
-  // -> packed float32 CHW or HWC (W H a multiple of 4); everything else takes k_generic
+  // fast shapes, each to float32 or float16: packed HWC of any input type -> packed HWC or (W H a
+  // multiple of 4) packed CHW, row-strided 8-/16-bit HWC -> packed HWC (rows of a multiple of 4
+  // pixels), packed CHW of any input type -> packed CHW or HWC (W H a multiple of 4); everything
+  // else takes k_generic
+  const bool f_out = ho.dtype == MACT_F32 || ho.dtype == MACT_F16;
   const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
-                    hi.packed &&
-                    (ho.dtype == MACT_F32 || ho.dtype == MACT_F16) && ho.layout == MACT_HWC && ho.packed;
-  const bool chw4 = hi.layout == MACT_CHW && hi.packed &&
-                    ho.dtype == MACT_F32 && ho.layout == MACT_CHW && ho.packed && (hi.W * hi.H) % 4 == 0;
-  const bool hwc4f = hi.dtype == MACT_F32 && hi.layout == MACT_HWC && hi.packed &&
-                     (ho.dtype == MACT_F32 || ho.dtype == MACT_F16) && ho.layout == MACT_HWC && ho.packed;
-  const bool hwc_chw4 = hi.layout == MACT_HWC && hi.packed && ho.dtype == MACT_F32 && ho.layout == MACT_CHW &&
-                        ho.packed && (hi.W * hi.H) % 4 == 0;
-  const bool chw_hwc4 = hi.layout == MACT_CHW && hi.packed && ho.dtype == MACT_F32 && ho.layout == MACT_HWC &&
-                        ho.packed && (hi.W * hi.H) % 4 == 0;
-  // row-strided 8-bit / float16 / 16-bit HWC -> packed float32 HWC, rows of a multiple of 4 pixels
+                    hi.packed && f_out && ho.layout == MACT_HWC && ho.packed;
+  const bool hwc4f = hi.dtype == MACT_F32 && hi.layout == MACT_HWC && hi.packed && f_out && ho.layout == MACT_HWC &&
+                     ho.packed;
+  const bool planes4 = hi.packed && ho.packed && f_out && (hi.W * hi.H) % 4 == 0 &&
+                       (hi.layout == MACT_CHW || ho.layout == MACT_CHW);
   const bool rows4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
-                     !hi.packed && ho.dtype == MACT_F32 && ho.layout == MACT_HWC && ho.packed && hi.W % 4 == 0 &&
+                     !hi.packed && f_out && ho.layout == MACT_HWC && ho.packed && hi.W % 4 == 0 &&
                      (hi.rs * (int64_t)hi.esize) % 4 == 0 && (hi.bs * (int64_t)hi.esize) % 4 == 0;
   const int64_t per = images_per_launch(hi);
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
@@ -906,26 +957,23 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
     const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
     const void* ip = static_cast<const char*>(hi.data) + (size_t)(n0 * hi.bs) * hi.esize;
     void* op = static_cast<char*>(ho.data) + (size_t)(n0 * ho.bs) * ho.esize;
+    // input alignment of the plane kernels: 4 elements of a CHW plane, a 12-byte load of HWC
+    // pixels (16 bytes for float32)
+    const size_t planes_align = hi.layout == MACT_CHW ? 4 * hi.esize : hi.dtype == MACT_F32 ? 16 : 4;
     if (hwc4 && aligned(ip, 4) && aligned(op, 16)) {
       if (hi.dtype == MACT_U8) launch_hwc4_io<MACT_U8>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
       else if (hi.dtype == MACT_U16) launch_hwc4_io<MACT_U16>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
       else launch_hwc4_io<MACT_F16>(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
     } else if (hwc4f && aligned(ip, 16) && aligned(op, 16)) {
       launch_hwc4f(params->xform, ho.dtype, exact_deg, ip, op, n_px, k, gamma, st);
-    } else if (hwc_chw4 && aligned(ip, hi.dtype == MACT_F32 ? 16 : 4) && aligned(op, 16)) {
+    } else if (planes4 && aligned(ip, planes_align) && aligned(op, 16)) {
       const uint32_t hw = (uint32_t)(hi.W * hi.H);
-      float* of = static_cast<float*>(op);
-      if (hi.dtype == MACT_U8) launch_hwc_chw4_deg<MACT_U8>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
-      else if (hi.dtype == MACT_U16) launch_hwc_chw4_deg<MACT_U16>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
-      else if (hi.dtype == MACT_F16) launch_hwc_chw4_deg<MACT_F16>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
-      else launch_hwc_chw4_deg<MACT_F32>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
-    } else if (chw_hwc4 && aligned(ip, 4 * hi.esize) && aligned(op, 16)) {
-      const uint32_t hw = (uint32_t)(hi.W * hi.H);
-      float* of = static_cast<float*>(op);
-      if (hi.dtype == MACT_U8) launch_chw_hwc4_deg<MACT_U8>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
-      else if (hi.dtype == MACT_U16) launch_chw_hwc4_deg<MACT_U16>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
-      else if (hi.dtype == MACT_F16) launch_chw_hwc4_deg<MACT_F16>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
-      else launch_chw_hwc4_deg<MACT_F32>(params->xform, deg, ip, of, n_px, hw, k, gamma, st);
+      if (hi.layout == MACT_CHW && ho.layout == MACT_CHW)
+        launch_planes_any<0>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_px, hw, k, gamma, st);
+      else if (ho.layout == MACT_CHW)
+        launch_planes_any<1>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_px, hw, k, gamma, st);
+      else
+        launch_planes_any<2>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_px, hw, k, gamma, st);
     } else if (rows4 && aligned(ip, 4) && aligned(op, 16)) {
       RowGeom g;
       g.W = (uint32_t)hi.W;
@@ -936,26 +984,9 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
       g.rs_b = (uint64_t)hi.rs * hi.esize;
       g.bs_b = (uint64_t)hi.bs * hi.esize;
       const uint32_t n_chunks = (uint32_t)(cnt * hi.H) * g.cpr;
-      float* of = static_cast<float*>(op);
-      if (hi.dtype == MACT_U8) launch_rows4<MACT_U8>(params->xform, exact_deg, ip, of, n_chunks, g, k, gamma, st);
-      else if (hi.dtype == MACT_U16) launch_rows4<MACT_U16>(params->xform, exact_deg, ip, of, n_chunks, g, k, gamma, st);
-      else launch_rows4<MACT_F16>(params->xform, exact_deg, ip, of, n_chunks, g, k, gamma, st);
-    } else if (chw4 && aligned(ip, 4 * hi.esize) && aligned(op, 16)) {
-      const uint32_t hw = (uint32_t)(hi.W * hi.H);
-      float* of = static_cast<float*>(op);
-      if (hi.dtype == MACT_F32) {
-        if (deg == 5) launch_chw4<MACT_F32, 5>(params->xform, ip, of, n_px, hw, k, gamma, st);
-        else launch_chw4<MACT_F32, 7>(params->xform, ip, of, n_px, hw, k, gamma, st);
-      } else if (hi.dtype == MACT_F16) {
-        if (deg == 5) launch_chw4<MACT_F16, 5>(params->xform, ip, of, n_px, hw, k, gamma, st);
-        else launch_chw4<MACT_F16, 7>(params->xform, ip, of, n_px, hw, k, gamma, st);
-      } else if (hi.dtype == MACT_U16) {
-        if (deg == 5) launch_chw4<MACT_U16, 5>(params->xform, ip, of, n_px, hw, k, gamma, st);
-        else launch_chw4<MACT_U16, 7>(params->xform, ip, of, n_px, hw, k, gamma, st);
-      } else {
-        if (deg == 5) launch_chw4<MACT_U8, 5>(params->xform, ip, of, n_px, hw, k, gamma, st);
-        else launch_chw4<MACT_U8, 7>(params->xform, ip, of, n_px, hw, k, gamma, st);
-      }
+      if (hi.dtype == MACT_U8) launch_rows4_io<MACT_U8>(params->xform, ho.dtype, exact_deg, ip, op, n_chunks, g, k, gamma, st);
+      else if (hi.dtype == MACT_U16) launch_rows4_io<MACT_U16>(params->xform, ho.dtype, exact_deg, ip, op, n_chunks, g, k, gamma, st);
+      else launch_rows4_io<MACT_F16>(params->xform, ho.dtype, exact_deg, ip, op, n_chunks, g, k, gamma, st);
     } else {
       const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
       const unsigned grid = full_grid(n_px, 256);

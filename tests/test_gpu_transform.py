@@ -233,18 +233,19 @@ def test_row_strided_views_equal_packed(M, dtype, xform):
         packed = torch.from_numpy(np.ascontiguousarray(base[:, :h, :w])).cuda()
         for p in pars:
             for gm in (["bt709", "none"] if xform in (0, 3) else ["none"]):
-                a = M.transform(view, xform=xform, params=p, gamma=gm)
-                b = M.transform(packed, xform=xform, params=p, gamma=gm)
-                torch.cuda.synchronize()
-                assert torch.equal(a, b), (n, h, w, rpad, ipad, gm)
+                for od in (torch.float32, torch.float16):
+                    a = M.transform(view, xform=xform, params=p, gamma=gm, out_dtype=od)
+                    b = M.transform(packed, xform=xform, params=p, gamma=gm, out_dtype=od)
+                    torch.cuda.synchronize()
+                    assert a.dtype == od and torch.equal(a, b), (n, h, w, rpad, ipad, gm, od)
 
 
 @pytest.mark.parametrize("dtype", ["u8", "u16", "f16", "f32"])
 @pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
 def test_chw_inputs_equal_packed_hwc(M, dtype, xform):
-    # CHW planes into CHW and into HWC (the 4-pixel kernels where W H is a multiple of 4, the
-    # one-pixel kernel otherwise; a partial last chunk at 3 x 8 x 1000) give the bits of the packed
-    # HWC input
+    # CHW planes into CHW and into HWC, float32 or float16 (the 4-pixel kernels where W H is a
+    # multiple of 4, the one-pixel kernel otherwise; a partial last chunk at 3 x 8 x 1000) give the
+    # bits of the packed HWC input
     g = synth.rng(300 + xform)
     for (n, h, w) in [(2, 16, 20), (1, 33, 36), (3, 8, 1000), (1, 7, 9)]:
         if dtype in ("u8", "u16"):
@@ -255,12 +256,13 @@ def test_chw_inputs_equal_packed_hwc(M, dtype, xform):
         x = torch.from_numpy(hwc).cuda()
         for gm in (["bt709", "srgb", "none"] if xform in (0, 3) else ["none"]):
             p = M.default_params(xform)
-            a = M.transform(chw, xform=xform, params=p, layout="chw", gamma=gm)
-            c = M.transform(chw, xform=xform, params=p, layout="chw", out_layout="hwc", gamma=gm)
-            b = M.transform(x, xform=xform, params=p, gamma=gm)
-            torch.cuda.synchronize()
-            assert torch.equal(a, b.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm)
-            assert torch.equal(c, b), (n, h, w, gm)
+            for od in (torch.float32, torch.float16):
+                a = M.transform(chw, xform=xform, params=p, layout="chw", gamma=gm, out_dtype=od)
+                c = M.transform(chw, xform=xform, params=p, layout="chw", out_layout="hwc", gamma=gm, out_dtype=od)
+                b = M.transform(x, xform=xform, params=p, gamma=gm, out_dtype=od)
+                torch.cuda.synchronize()
+                assert a.dtype == od and torch.equal(a, b.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm, od)
+                assert c.dtype == od and torch.equal(c, b), (n, h, w, gm, od)
 
 
 def test_empty_inputs_give_empty_outputs(M):
@@ -290,8 +292,8 @@ def test_empty_inputs_give_empty_outputs(M):
 @pytest.mark.parametrize("dtype", ["u8", "u16", "f16", "f32"])
 @pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
 def test_hwc_to_chw_equals_hwc_permuted(M, dtype, xform):
-    # packed HWC into packed float32 CHW (the 4-pixel kernel where W H is a multiple of 4, the
-    # one-pixel kernel otherwise) gives the HWC result's bits, plane by plane
+    # packed HWC into packed float32 or float16 CHW (the 4-pixel kernel where W H is a multiple of
+    # 4, the one-pixel kernel otherwise) gives the HWC result's bits, plane by plane
     g = synth.rng(400 + xform)
     for (n, h, w) in [(2, 16, 20), (1, 33, 36), (3, 8, 1000), (1, 7, 9)]:
         if dtype == "u8":
@@ -304,10 +306,11 @@ def test_hwc_to_chw_equals_hwc_permuted(M, dtype, xform):
         pars = [M.default_params(xform)] + ([M.default_params(xform, decode=True)] if xform in (0, 3) else [])
         for p in pars:
             for gm in (["bt709", "none"] if xform in (0, 3) else ["none"]):
-                c = M.transform(x, xform=xform, params=p, gamma=gm, out_layout="chw")
-                r = M.transform(x, xform=xform, params=p, gamma=gm)
-                torch.cuda.synchronize()
-                assert torch.equal(c, r.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm)
+                for od in (torch.float32, torch.float16):
+                    c = M.transform(x, xform=xform, params=p, gamma=gm, out_layout="chw", out_dtype=od)
+                    r = M.transform(x, xform=xform, params=p, gamma=gm, out_dtype=od)
+                    torch.cuda.synchronize()
+                    assert c.dtype == od and torch.equal(c, r.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm, od)
 
 
 def test_chw_batch_with_gaps_between_images(M):
@@ -319,10 +322,11 @@ def test_chw_batch_with_gaps_between_images(M):
     packed = torch.from_numpy(np.ascontiguousarray(base[:, :3])).cuda()
     for xf in (0, 1, 2, 3):
         for ol in ("chw", "hwc"):
-            a = M.transform(view, xform=xf, layout="chw", out_layout=ol)
-            b = M.transform(packed, xform=xf, layout="chw", out_layout=ol)
-            torch.cuda.synchronize()
-            assert torch.equal(a, b), (xf, ol)
+            for od in (torch.float32, torch.float16):
+                a = M.transform(view, xform=xf, layout="chw", out_layout=ol, out_dtype=od)
+                b = M.transform(packed, xform=xf, layout="chw", out_layout=ol, out_dtype=od)
+                torch.cuda.synchronize()
+                assert torch.equal(a, b), (xf, ol, od)
     f = torch.from_numpy(g.random((2, 4, 8, 12)).astype(np.float32)).cuda()
     a = M.inverse(f[:, :3], xform="sct", layout="chw")
     b = M.inverse(f[:, :3].contiguous(), xform="sct", layout="chw")
