@@ -27,6 +27,7 @@ The JSON line also carries
 """
 import argparse
 import json
+import math
 import os
 import sys
 import threading
@@ -251,27 +252,72 @@ def bench_exact_gain(M, x, y, n_px, steps):
     return out
 
 
+def batch_stats(M, xin, params, gamma="bt709"):
+    """Accuracy of the MACT transform over the whole input batch against the
+    exact transform in float64, on the device (mact_error_stats): mean and max
+    Delta E*ab for CIELAB."""
+    st = M.error_stats(xin, params=params, gamma=gamma)
+    return {"dE_mean_batch": st["mean"], "dE_max_batch": st["max"]}
+
+
+def lut_error(xf, out, ref):
+    """Deviation of a LUT's output from `ref`, the exact float32 transform of
+    the same pixels (mact_transform_exact), over the whole batch, in the
+    transform's own measure: CIELAB Delta E*ab; HSI's D_HSI with the hue
+    difference wrapped to [0, pi]; SCT's angle errors, wrapped."""
+    import torch
+    o, r = out.reshape(-1, 3), ref.reshape(-1, 3)
+    if xf == "lab":
+        d = (o - r).square().sum(-1).sqrt()
+        return {"dE_mean_batch": float(d.mean()), "dE_max_batch": float(d.max())}
+
+    def wrap(a):
+        a = a.abs().remainder(2 * math.pi)
+        return torch.minimum(a, 2 * math.pi - a)
+
+    if xf == "hsi":
+        th = wrap(o[:, 0] - r[:, 0])
+        v = o[:, 1].square() + r[:, 1].square() - 2 * o[:, 1] * r[:, 1] * th.cos() + (o[:, 2] - r[:, 2]).square()
+        d = v.clamp_min(0).sqrt()
+        return {"D_HSI_mean_batch": float(d.mean()), "D_HSI_max_batch": float(d.max())}
+    da, db = wrap(o[:, 1] - r[:, 1]), wrap(o[:, 2] - r[:, 2])
+    return {"dA_mean_batch": float(da.mean()), "dA_max_batch": float(da.max()),
+            "dB_mean_batch": float(db.mean()), "dB_max_batch": float(db.max()),
+            "dL_max_batch": float((o[:, 0] - r[:, 0]).abs().max())}
+
+
 def bench_lut(M, x, y, n_px, steps):
+    """Every LUT interpolator on the 8-bit batch, each rate beside its error
+    against the exact float32 transform over the same batch."""
+    import torch
     out = {}
+
+    def rec(name, xf, ms, ref):
+        out[name] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15 * n_px / ms / 1e6, "ms": ms, **lut_error(xf, y, ref)}
+
+    ref = M.transform_exact(x, xform="lab")
     for N in (9, 17, 33):
         L = M.lut_build("lab", N)
         for method in ("trilinear", "prism", "pyramidal", "tetrahedral"):
             ms, _ = time_kernel(lambda: M.lut_interp(L, N, "lab", method, x, out=y), steps)
-            out["lab_%s_%d" % (method, N)] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15 * n_px / ms / 1e6, "ms": ms}
+            rec("lab_%s_%d" % (method, N), "lab", ms, ref)
         # the cell-major form: one pixel's corners in one contiguous run
         C = M.lut_cells_build(L, N, "lab")
         for method in ("trilinear", "prism", "pyramidal", "tetrahedral"):
             ms, _ = time_kernel(lambda: M.lut_cells_interp(C, N, "lab", method, x, out=y), steps)
-            out["lab_cells_%s_%d" % (method, N)] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15 * n_px / ms / 1e6, "ms": ms}
+            rec("lab_cells_%s_%d" % (method, N), "lab", ms, ref)
         del C
     for xf in ("hsi", "sct"):
+        ref = M.transform_exact(x, xform=xf)
         for N in (17, 33):
             L = M.lut_build(xf, N)
             ms, _ = time_kernel(lambda: M.lut_interp(L, N, xf, "trilinear", x, out=y), steps)
-            out["%s_trilinear_%d" % (xf, N)] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15 * n_px / ms / 1e6, "ms": ms}
+            rec("%s_trilinear_%d" % (xf, N), xf, ms, ref)
             C = M.lut_cells_build(L, N, xf)
             ms, _ = time_kernel(lambda: M.lut_cells_interp(C, N, xf, "trilinear", x, out=y), steps)
-            out["%s_cells_trilinear_%d" % (xf, N)] = {"Mpx_s": n_px / ms / 1e3, "GBs": 15 * n_px / ms / 1e6, "ms": ms}
+            rec("%s_cells_trilinear_%d" % (xf, N), xf, ms, ref)
+    del ref
+    torch.cuda.synchronize()
     return out
 
 
@@ -494,13 +540,15 @@ def main():
         x16 = (x.to(torch.float16) / 255.0).contiguous()
         for tag, pp in (("exact", p_lab), ("minimax", M.default_params(0, decode=True))):
             ms, _ = time_kernel(lambda: M.transform(x16, params=pp, out=y), a.steps)
-            forms["lab_f16_in_decode_%s" % tag] = {"Mpx_s": n_px / ms / 1e3, "GBs": 18.0 * n_px / ms / 1e6, "ms": ms}
+            forms["lab_f16_in_decode_%s" % tag] = {"Mpx_s": n_px / ms / 1e3, "GBs": 18.0 * n_px / ms / 1e6, "ms": ms,
+                                                   **batch_stats(M, x16, pp)}
         del x16
         # 16-bit codes (the 8-bit batch times 257), BT.709: exact power vs minimax decoding
         x16u = torch.from_numpy(batch_np.astype(np.uint16) * np.uint16(257)).cuda()
         for tag, pp in (("exact", p_lab), ("minimax", M.default_params(0, decode=True))):
             ms, _ = time_kernel(lambda: M.transform(x16u, params=pp, out=y), a.steps)
-            forms["lab_u16_in_decode_%s" % tag] = {"Mpx_s": n_px / ms / 1e3, "GBs": 18.0 * n_px / ms / 1e6, "ms": ms}
+            forms["lab_u16_in_decode_%s" % tag] = {"Mpx_s": n_px / ms / 1e3, "GBs": 18.0 * n_px / ms / 1e6, "ms": ms,
+                                                   **batch_stats(M, x16u, pp)}
         del x16u
         # float32 HWC input (BT.709-encoded values in [0, 1]): 24 B/px; the exact decoding power, the
         # minimax decoding, and linear input (no decoding)
@@ -508,7 +556,8 @@ def main():
         for tag, pp, gm in (("decode_exact", p_lab, "bt709"), ("decode_minimax", M.default_params(0, decode=True), "bt709"),
                             ("linear", p_lab, "none")):
             ms, _ = time_kernel(lambda: M.transform(x32, params=pp, gamma=gm, out=y), a.steps)
-            forms["lab_f32_hwc_in_" + tag] = {"Mpx_s": n_px / ms / 1e3, "GBs": 24.0 * n_px / ms / 1e6, "ms": ms}
+            forms["lab_f32_hwc_in_" + tag] = {"Mpx_s": n_px / ms / 1e3, "GBs": 24.0 * n_px / ms / 1e6, "ms": ms,
+                                              **batch_stats(M, x32, pp, gm)}
         del x32
         log("4K batch")
         forms["lab_32x4k"] = bench_4k(M, p_lab, a.steps)
@@ -546,11 +595,14 @@ def main():
     torch.cuda.synchronize()
     log("cpu baseline (oracle)")
     cpu, acc = cpu_baseline(batch_np, y, a.cpu_px)
+    # the headline's Delta E*ab over the whole batch against the device's float64 exact transform
+    acc["whole_batch_device_reference"] = batch_stats(M, x, p_lab)
     gold = os.path.join(ROOT, "tests", "golden", "mact_accuracy.json")
     if os.path.exists(gold):
         with open(gold) as f:
             g = json.load(f)
-        acc["exhaustive_cube_oracle"] = {k: g[k] for k in ("lab", "hsi", "hsi_dH", "sct", "sct_dA", "sct_dB")}
+        acc["exhaustive_cube_oracle"] = {k: g[k] for k in ("lab", "hsi", "hsi_dH", "sct", "sct_dA", "sct_dB", "luv")
+                                         if k in g}
         acc["exhaustive_cube_lut_dE"] = {k: v for k, v in g.items() if k.startswith("lut_")}
 
     traffic = None

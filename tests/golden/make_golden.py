@@ -7,7 +7,8 @@ library's default degrees and intervals, FP64 evaluation).
 
 CIELAB: Delta E*ab (Sec. 3.2.1).  HSI: D_HSI (Sec. 3.3.1) and the hue error.
 SCT: Delta E*ab through the inverse SCT (Sec. 3.4.1) and the angle errors.
-LUTs: Delta E*ab of the CIELAB LUT at 17^3 and 33^3 (Sec. 3.5.3).
+CIELUV: Delta E*uv (the CIE 1976 L*u*v* distance; Sec. 4 names the transform).
+LUTs: Delta E*ab of the CIELAB LUT at 9^3, 17^3 and 33^3 (Sec. 3.5.3).
 """
 import json
 import os
@@ -53,6 +54,9 @@ def _chunk(v8, F, luts):
     db = np.abs(s[:, 2] - ex_sct[:, 2])
     out["sct_dA"] = (da.sum(), da.max())
     out["sct_dB"] = (db.sum(), db.max())
+    ex_luv = colour.rgb_to_luv(x)
+    d = colour.delta_e(mact.mact_luv(x, F["cbrt"].p, F["cbrt"].q), ex_luv)
+    out["luv"] = (d.sum(), d.max())
     for key, L in luts.items():
         o, _ = lut.interp(L, "lab", key[0], v8=v8)
         d = colour.delta_e(o, ex_lab)
@@ -62,7 +66,7 @@ def _chunk(v8, F, luts):
 
 def main():
     F = fits()
-    luts = {(m, N): lut.build("lab", N) for m in ("trilinear", "prism", "pyramidal", "tetrahedral") for N in (17, 33)}
+    luts = {(m, N): lut.build("lab", N) for m in ("trilinear", "prism", "pyramidal", "tetrahedral") for N in (9, 17, 33)}
     parts = cube_map(_chunk, F, luts)
     n = float(1 << 24)
     res = {}
@@ -70,7 +74,7 @@ def main():
         res[k] = {"mean": float(sum(p[k][0] for p in parts) / n), "max": float(max(p[k][1] for p in parts))}
     res["fits"] = {k: {"n": len(f.p) - 1, "m": len(f.q) - 1, "lo": f.a, "hi": f.b, "eps": f.eps} for k, f in F.items()}
     res["what"] = ("oracle FP64, all 2^24 8-bit colours, BT.709 inverse gamma; lab/sct: Delta E*ab, hsi: D_HSI, "
-                   "hsi_dH / sct_dA / sct_dB: angle errors in radians; lut_*: CIELAB LUT Delta E*ab")
+                   "hsi_dH / sct_dA / sct_dB: angle errors in radians; luv: Delta E*uv; lut_*: CIELAB LUT Delta E*ab")
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "mact_accuracy.json")
     with open(path, "w") as f:
         json.dump(res, f, indent=1, sort_keys=True)

@@ -202,8 +202,12 @@ def test_error_stats_equal_the_oracle_metric_of_the_gpu_output(M, xform):
 # roundings (8 * 2^-24 ~ 4.8e-7 relative, f <= 1), and a*, b* amplify a difference of two f by 500
 # and 200, so one pixel's Delta E moves by at most sqrt(116^2 + 1000^2 + 400^2) * 4.8e-7 ~ 5.2e-4;
 # the mean moves far less.  HSI: hue in float32 on [0, 2pi] (a few ulp ~ 2e-6), so 2e-5; SCT: 5e-5.
+# CIELUV: L* = 116 f~ - 16 moves by 116 * 4.8e-7 ~ 5.6e-5; u*, v* = 13 L* (u' - u'n) with |u' - u'n|,
+# |v' - v'n| < 0.5 and L* <= 100 add 13 * 0.5 * 5.6e-5 ~ 3.6e-4 through L* and about 13 * 100 * 0.6 *
+# 2.4e-7 ~ 1.9e-4 through the float32 quotients: 6e-4 for one pixel.
 @pytest.mark.parametrize("xform,key,tol_mean,tol_max", [(0, "lab", 2e-5, 5.2e-4), (1, "hsi", 2e-5, 2e-5),
-                                                         (2, "sct", 5e-5, 5e-5)], ids=["lab", "hsi", "sct"])
+                                                         (2, "sct", 5e-5, 5e-5), (3, "luv", 2e-5, 6e-4)],
+                         ids=["lab", "hsi", "sct", "luv"])
 def test_error_stats_of_every_colour_match_the_oracle_tables(M, xform, key, tol_mean, tol_max):
     # all 2^24 colours on the GPU against the oracle's exhaustive statistics
     with open(os.path.join(HERE, "golden", "mact_accuracy.json")) as f:
