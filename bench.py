@@ -8,6 +8,9 @@ place of the cube root) over a batch of 64 synthetic 1920x1080 8-bit images
 seeds 1000..1063), packed HWC uint8 in, packed HWC float32 out, inputs
 resident in HBM.  One step = one mact_transform over the whole batch; `value`
 is Mpixel/s over the K timed steps (wall clock, synchronised on both sides).
+The W untimed warm-up steps default to 100: in a fresh process the first
+launch loads the code object (about 11 ms) and the next few dozen run 3-8%
+slower while the memory system settles.
 
 The JSON line also carries
   roofline      the hot kernel's achieved HBM bandwidth: 15 algorithmic bytes
@@ -477,7 +480,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--forms", default="all", choices=["all", "none", "lut"],
                     help="all: every form; none: the headline and its ceilings only; lut: the headline and the LUTs")
     ap.add_argument("--cpu-px", type=int, default=1 << 25)
