@@ -642,13 +642,14 @@ def main():
 
 def kernel_hash():
     """Hash of the hot kernel's sources, to tell whether stored counters are
-    stale: the per-pixel code and constants (pixel.h, common.h) and, from
+    stale: the per-pixel code and constants (pixel.h, common.h), the
+    streaming stores (stream.h) and, from
     xform.hip, the hot kernel with its launch constants, grid and launcher."""
     import hashlib
     import re
     csrc = os.path.join(ROOT, "paper_1009_0854_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("pixel.h", "common.h"):
+    for f in ("pixel.h", "common.h", "stream.h"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     with open(os.path.join(csrc, "xform.hip")) as fh:

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "launch.h"
+#include "stream.h"
 
 namespace mact {
 
@@ -96,9 +97,9 @@ __global__ __launch_bounds__(1024) void k_batch(const BDesc* __restrict__ descs,
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): every lane's LDS writes have landed
         __builtin_amdgcn_wave_barrier();
-        f4* dst = reinterpret_cast<f4*>(d.dst.ptr) + (size_t)(cp >> 2) * 3;
+        const StreamBuf dst = wave_stream_buf(reinterpret_cast<f4*>(d.dst.ptr) + (size_t)(cp >> 2) * 3, 3072u);
 #pragma unroll
-        for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(s[q * 64 + lane], dst + q * 64 + lane);
+        for (int q = 0; q < 3; ++q) stream_store(dst, (q * 64 + lane) * 16u, s[q * 64 + lane]);
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
       }

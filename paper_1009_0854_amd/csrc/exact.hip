@@ -18,6 +18,7 @@
 #include <cmath>
 
 #include "launch.h"
+#include "stream.h"
 
 namespace mact {
 
@@ -128,11 +129,11 @@ __global__ __launch_bounds__(kBlock) void k_exact4(const uint8_t* __restrict__ i
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): every lane's LDS writes have landed
     __builtin_amdgcn_wave_barrier();
     const uint32_t n_valid = min((uint32_t)kCpw, n_chunks - c0) * F4PC;
-    f4* dst = reinterpret_cast<f4*>(out) + (size_t)c0 * F4PC;
+    const StreamBuf dst = wave_stream_buf(reinterpret_cast<f4*>(out) + (size_t)c0 * F4PC, n_valid * 16u);
 #pragma unroll
     for (int q = 0; q < (int)(kCpw * F4PC / 64); ++q) {
       const uint32_t e = q * 64 + lane;
-      if (e < n_valid) __builtin_nontemporal_store(s_out[wv][e], dst + e);
+      if (e < n_valid) stream_store(dst, e * 16u, s_out[wv][e]);
     }
   }
   // the last n_px % 256 pixels, one per lane of block 0

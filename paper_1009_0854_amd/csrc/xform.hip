@@ -22,6 +22,7 @@
 
 #include "launch.h"
 #include "planes.h"
+#include "stream.h"
 
 namespace mact {
 
@@ -245,12 +246,12 @@ __global__ __launch_bounds__(kHotBlock) void k_hwc4(const void* __restrict__ in,
     __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
     __builtin_amdgcn_wave_barrier();
     const uint32_t n_valid = min((uint32_t)CPW, n_chunks - c0) * F4PC;
-    f4* dst = reinterpret_cast<f4*>(out) + (size_t)c0 * F4PC;
+    const StreamBuf dst = wave_stream_buf(reinterpret_cast<f4*>(out) + (size_t)c0 * F4PC, n_valid * 16u);
     static_assert((CPW * F4PC) % 64 == 0, "whole 1 KB stores per wave");
 #pragma unroll
     for (int q = 0; q < (int)(CPW * F4PC / 64); ++q) {
       const uint32_t e = q * 64 + lane;
-      if (e < n_valid) __builtin_nontemporal_store(s_out[wv][e], dst + e);
+      if (e < n_valid) stream_store(dst, e * 16u, s_out[wv][e]);
     }
   }
   // the last n_px % 256 pixels, one per lane of block 0
@@ -423,12 +424,14 @@ __device__ __forceinline__ void store_staged(const f4* slice, void* dst, uint32_
   __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): every lane's LDS writes have landed
   __builtin_amdgcn_wave_barrier();
   const uint32_t n_valid = cnt / 4u * 3u;  // 16-byte (float32) or 8-byte (float16) words
+  constexpr uint32_t WB = OUT == MACT_F32 ? 16 : 8;
+  const StreamBuf b = wave_stream_buf(dst, n_valid * WB);
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const uint32_t e = q * 64 + lane;
     if (e < n_valid) {
-      if (OUT == MACT_F32) __builtin_nontemporal_store(slice[e], static_cast<f4*>(dst) + e);
-      else __builtin_nontemporal_store(reinterpret_cast<const f2*>(slice)[e], static_cast<f2*>(dst) + e);
+      if (OUT == MACT_F32) stream_store(b, e * WB, slice[e]);
+      else stream_store(b, e * WB, reinterpret_cast<const f2*>(slice)[e]);
     }
   }
 }
@@ -768,9 +771,15 @@ __global__ __launch_bounds__(kHotBlock) void k_stream_u8_f32(const uint8_t* __re
       out[3 * (size_t)tail0 + e] = (float)in[3 * (size_t)tail0 + e];
 }
 
+// A 16-byte copy, each wave one run of 64 words, with the streaming stores of
+// the transform kernels.
 __global__ __launch_bounds__(256) void k_copy16(const f4* __restrict__ in, f4* __restrict__ out, uint64_t n) {
   const uint64_t stride = (uint64_t)gridDim.x * 256u;
-  for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < n; i += stride) __builtin_nontemporal_store(in[i], out + i);
+  const uint32_t lane = threadIdx.x & 63u;
+  for (uint64_t w0 = blockIdx.x * 256ull + (threadIdx.x & ~63u); w0 < n; w0 += stride) {
+    const StreamBuf b = wave_stream_buf(out + w0, (uint32_t)std::min<uint64_t>(64, n - w0) * 16u);
+    if (w0 + lane < n) stream_store(b, lane * 16u, in[w0 + lane]);
+  }
 }
 
 // ---------------------------------------------------------------- dispatch
