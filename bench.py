@@ -148,7 +148,8 @@ def bench_general(M, x, y, p, n_px, steps):
     and float16 output (9): the 8-bit batch as a row-padded view (rows 8
     pixels apart beyond their width; the row-strided kernel) into packed HWC,
     as CHW planes into HWC and into CHW, and packed HWC into CHW (the plane
-    kernels)."""
+    kernels); row-strided CHW planes into HWC and a row-padded float32 view
+    into HWC, float32 out."""
     import torch
     out = {}
     n, h, w, _ = x.shape
@@ -173,7 +174,20 @@ def bench_general(M, x, y, p, n_px, steps):
         rec("u8_chw_to_chw" + tag, ms, bpp)
         ms, _ = time_kernel(lambda: M.transform(x, params=p, out=ochw, out_layout="chw"), steps)
         rec("u8_hwc_to_chw" + tag, ms, bpp)
-    del chw
+    # row-strided CHW (each plane's rows 8 pixels apart beyond their width) into packed HWC; float32
+    # HWC rows 8 pixels apart into packed HWC (24 bytes per pixel)
+    cpad = torch.empty((n, 3, h, w + 8), dtype=torch.uint8, device="cuda")
+    cpad[..., :w] = chw
+    cview = cpad[..., :w]
+    ms, _ = time_kernel(lambda: M.transform(cview, params=p, layout="chw", out=y, out_layout="hwc"), steps)
+    rec("u8_chw_row_view_to_hwc", ms, 15.0)
+    del cpad, cview, chw
+    fpad = torch.empty((n, h, w + 8, 3), dtype=torch.float32, device="cuda")
+    fpad[:, :, :w] = x.float().div_(255.0)
+    fview = fpad[:, :, :w]
+    ms, _ = time_kernel(lambda: M.transform(fview, params=p, out=y), steps)
+    rec("f32_row_padded_view", ms, 24.0)
+    del fpad, fview
     return out
 
 

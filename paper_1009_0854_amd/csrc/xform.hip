@@ -452,9 +452,9 @@ __device__ __forceinline__ void store_plane4(void* out, size_t e, float a, float
 // pitched allocation) -> packed float32 or float16 HWC, W a multiple of 4.
 // Every row is cut into 256-pixel chunks, the last one partial, one chunk per
 // wave; each chunk takes k_hwc4's 12-byte loads (lanes past the row's end
-// idle), its per-pixel code and its LDS-transposed stores.  Requires the input
-// pointer and both strides (in bytes) to be multiples of 4 and `out` 16-byte
-// aligned.
+// idle; float32 pixels: three 16-byte loads per lane), its per-pixel code and
+// its LDS-transposed stores.  Requires the input pointer and both strides (in
+// bytes) to be multiples of 4 (16 for float32) and `out` 16-byte aligned.
 struct RowGeom {
   uint32_t W, cpr, H;      // pixels per row, chunks per row, rows per image
   FastDiv div_cpr, div_h;  // chunk -> row, row -> image
@@ -464,7 +464,7 @@ struct RowGeom {
 template <int IN, int OUT, int DEG, int XF>
 __global__ __launch_bounds__(kHotBlock) void k_rows4(const uint8_t* __restrict__ in, void* __restrict__ out,
                                                      uint32_t n_chunks, RowGeom g, KCoef k, int gamma) {
-  constexpr int WPC = IN == MACT_U8 ? 1 : 2;  // 12-byte words per lane (16-bit inputs: 2)
+  constexpr int WPC = IN == MACT_U8 ? 1 : IN == MACT_F32 ? 4 : 2;  // 12-byte words per lane
   constexpr uint32_t OSZ = OUT == MACT_F32 ? 4 : 2;
   __shared__ f4 s_out[kHotWaves][3 * OSZ * 16];
   __shared__ float gtab[256];
@@ -481,7 +481,17 @@ __global__ __launch_bounds__(kHotBlock) void k_rows4(const uint8_t* __restrict__
   const uint32_t px0 = j * 256u, cnt = min(256u, g.W - px0);  // cnt: a multiple of 4
   const uint3* row = reinterpret_cast<const uint3*>(in + n * g.bs_b + y * g.rs_b + (uint64_t)px0 * 3u * WPC);
   float o[12];
-  if (4u * lane < cnt) {
+  if (4u * lane < cnt && IN == MACT_F32) {
+    const f4* rf = reinterpret_cast<const f4*>(row) + 3u * lane;  // 48 bytes per lane, 16-byte aligned
+    float v[12];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const f4 b = rf[t];
+      v[4 * t] = clamp01(b.x); v[4 * t + 1] = clamp01(b.y); v[4 * t + 2] = clamp01(b.z); v[4 * t + 3] = clamp01(b.w);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) px1<MACT_F32, XF, DEG>(k, gamma, gtab, v + 3 * q, o + 3 * q);
+  } else if (4u * lane < cnt) {
     uint3 w[WPC];
 #pragma unroll
     for (int q = 0; q < WPC; ++q) w[q] = row[lane * WPC + q];
@@ -626,6 +636,61 @@ __global__ __launch_bounds__(kHotBlock) void k_chw_hwc4(const void* __restrict__
   }
   stage4<OUT>(s_out[wv], lane, o);
   store_staged<OUT>(s_out[wv], static_cast<char*>(out) + (size_t)c * 768u * OSZ, cnt, lane);
+}
+
+// Row-strided CHW (a crop of the planes, a batch with gaps between images)
+// -> packed float32 or float16, HWC (OCHW false) or CHW.  W a multiple of 4;
+// the input pointer and the row, plane and image strides multiples of 4
+// elements, the plane stride below 2^32.  Every row is cut into 256-pixel runs,
+// one per wave, 4 pixels per lane: one 4-, 8- or 16-byte load per plane.  HWC
+// output leaves through the wave's LDS slice as in k_rows4, CHW output as one
+// store per plane and lane.
+struct ChwRows {
+  uint32_t W, cpr, H;      // pixels per row, runs per row, rows per image
+  FastDiv div_cpr, div_h;  // run -> row, row -> image
+  uint64_t rs, bs;         // input row and image strides, elements
+  uint32_t ps;             // input plane stride, elements
+};
+
+template <int IN, int OUT, int DEG, int XF, bool OCHW>
+__global__ __launch_bounds__(kHotBlock) void k_chw_rows4(const void* __restrict__ in, void* __restrict__ out,
+                                                         uint32_t n_chunks, ChwRows g, KCoef k, int gamma) {
+  constexpr uint32_t OSZ = OUT == MACT_F32 ? 4 : 2;
+  __shared__ f4 s_out[kHotWaves][OCHW ? 1 : 3 * OSZ * 16];
+  __shared__ float gtab[256];
+  if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
+    for (uint32_t i = threadIdx.x; i < 256u; i += kHotBlock) gtab[i] = k_gamma_table[gamma][i];
+    __syncthreads();
+  }
+  pin_lead<DEG>(k);
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t c = blockIdx.x * kHotWaves + wv;
+  if (c >= n_chunks) return;  // no block-wide barrier follows
+  const uint32_t r = g.div_cpr.div(c), j = c - r * g.cpr;
+  const uint32_t n = g.div_h.div(r), y = r - n * g.H;
+  const uint32_t px0 = j * 256u, cnt = min(256u, g.W - px0);  // cnt: a multiple of 4
+  const bool live = 4u * lane < cnt;
+  float o[12];
+  if (live) {
+    float v[4][3];
+    load_planes4<IN>(in, (size_t)n * g.bs + (size_t)y * g.rs + px0 + 4u * lane, g.ps, v);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) px1<IN, XF, DEG>(k, gamma, gtab, v[q], o + 3 * q);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 12; ++q) o[q] = 0.0f;
+  }
+  if (OCHW) {
+    if (live) {
+      const size_t hw = (size_t)g.W * g.H;
+      const size_t e = (size_t)n * 3 * hw + (size_t)y * g.W + px0 + 4u * lane;  // element offset in plane 0
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) store_plane4<OUT>(out, e + ch * hw, o[ch], o[3 + ch], o[6 + ch], o[9 + ch]);
+    }
+  } else {
+    stage4<OUT>(s_out[wv], lane, o);
+    store_staged<OUT>(s_out[wv], static_cast<char*>(out) + ((uint64_t)r * g.W + px0) * 3u * OSZ, cnt, lane);
+  }
 }
 
 template <int DEG>
@@ -926,6 +991,37 @@ static void launch_planes_any(int in_dtype, int xform, int out_dtype, int deg, c
   else launch_planes_io<KIND, MACT_F32>(xform, out_dtype, deg, in, out, n_px, hw, k, gamma, st);
 }
 
+template <int IN, int OUT, int DEG, bool OCHW>
+static void launch_chw_rows4(int xform, const void* in, void* out, uint32_t n_chunks, const ChwRows& g, const KCoef& k,
+                             int gamma, hipStream_t st) {
+  const dim3 grid(std::max<uint32_t>(1, (n_chunks + kHotWaves - 1) / kHotWaves)), blk(kHotBlock);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_chw_rows4<IN, OUT, DEG, MACT_LAB, OCHW>), grid, blk, 0, st, in, out, n_chunks, g, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_chw_rows4<IN, OUT, DEG, MACT_HSI, OCHW>), grid, blk, 0, st, in, out, n_chunks, g, k, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_chw_rows4<IN, OUT, DEG, MACT_LUV, OCHW>), grid, blk, 0, st, in, out, n_chunks, g, k, gamma);
+  else hipLaunchKernelGGL((k_chw_rows4<IN, OUT, DEG, MACT_SCT, OCHW>), grid, blk, 0, st, in, out, n_chunks, g, k, gamma);
+}
+
+template <int IN, bool OCHW>
+static void launch_chw_rows4_io(int xform, int out_dtype, int deg, const void* in, void* out, uint32_t n_chunks,
+                                const ChwRows& g, const KCoef& k, int gamma, hipStream_t st) {
+  if (out_dtype == MACT_F32) {
+    if (deg == 5) launch_chw_rows4<IN, MACT_F32, 5, OCHW>(xform, in, out, n_chunks, g, k, gamma, st);
+    else launch_chw_rows4<IN, MACT_F32, 7, OCHW>(xform, in, out, n_chunks, g, k, gamma, st);
+  } else {
+    if (deg == 5) launch_chw_rows4<IN, MACT_F16, 5, OCHW>(xform, in, out, n_chunks, g, k, gamma, st);
+    else launch_chw_rows4<IN, MACT_F16, 7, OCHW>(xform, in, out, n_chunks, g, k, gamma, st);
+  }
+}
+
+template <bool OCHW>
+static void launch_chw_rows4_any(int in_dtype, int xform, int out_dtype, int deg, const void* in, void* out,
+                                 uint32_t n_chunks, const ChwRows& g, const KCoef& k, int gamma, hipStream_t st) {
+  if (in_dtype == MACT_U8) launch_chw_rows4_io<MACT_U8, OCHW>(xform, out_dtype, deg, in, out, n_chunks, g, k, gamma, st);
+  else if (in_dtype == MACT_U16) launch_chw_rows4_io<MACT_U16, OCHW>(xform, out_dtype, deg, in, out, n_chunks, g, k, gamma, st);
+  else if (in_dtype == MACT_F16) launch_chw_rows4_io<MACT_F16, OCHW>(xform, out_dtype, deg, in, out, n_chunks, g, k, gamma, st);
+  else launch_chw_rows4_io<MACT_F32, OCHW>(xform, out_dtype, deg, in, out, n_chunks, g, k, gamma, st);
+}
+
 static bool aligned(const void* p, size_t a) { return (uintptr_t)p % a == 0; }
 
 }  // namespace mact
@@ -947,9 +1043,9 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   const int gamma = uses_gamma(params->xform) ? hi.gamma : MACT_GAMMA_NONE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   // fast shapes, each to float32 or float16: packed HWC of any input type -> packed HWC or (W H a
-  // multiple of 4) packed CHW, row-strided 8-/16-bit HWC -> packed HWC (rows of a multiple of 4
-  // pixels), packed CHW of any input type -> packed CHW or HWC (W H a multiple of 4); everything
-  // else takes k_generic
+  // multiple of 4) packed CHW, row-strided HWC -> packed HWC and row-strided CHW -> packed HWC or
+  // CHW (rows of a multiple of 4 pixels), packed CHW of any input type -> packed CHW or HWC (W H a
+  // multiple of 4); everything else takes k_generic
   const bool f_out = ho.dtype == MACT_F32 || ho.dtype == MACT_F16;
   const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
                     hi.packed && f_out && ho.layout == MACT_HWC && ho.packed;
@@ -957,9 +1053,13 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
                      ho.packed;
   const bool planes4 = hi.packed && ho.packed && f_out && (hi.W * hi.H) % 4 == 0 &&
                        (hi.layout == MACT_CHW || ho.layout == MACT_CHW);
-  const bool rows4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
-                     !hi.packed && f_out && ho.layout == MACT_HWC && ho.packed && hi.W % 4 == 0 &&
-                     (hi.rs * (int64_t)hi.esize) % 4 == 0 && (hi.bs * (int64_t)hi.esize) % 4 == 0;
+  const int64_t rows_align = hi.dtype == MACT_F32 ? 16 : 4;  // row starts: a 12-byte load, or 16-byte loads
+  const bool rows4 = hi.layout == MACT_HWC && !hi.packed && f_out && ho.layout == MACT_HWC && ho.packed &&
+                     hi.W % 4 == 0 && (hi.rs * (int64_t)hi.esize) % rows_align == 0 &&
+                     (hi.bs * (int64_t)hi.esize) % rows_align == 0;
+  // row-strided CHW -> packed HWC or CHW: rows of a multiple of 4 pixels, strides of whole 4-element groups
+  const bool chw_rows4 = hi.layout == MACT_CHW && !hi.packed && f_out && ho.packed && hi.W % 4 == 0 &&
+                         hi.rs % 4 == 0 && hi.ps % 4 == 0 && hi.bs % 4 == 0 && hi.ps < ((int64_t)1 << 32);
   const int64_t per = images_per_launch(hi);
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
@@ -983,7 +1083,7 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
         launch_planes_any<1>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_px, hw, k, gamma, st);
       else
         launch_planes_any<2>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_px, hw, k, gamma, st);
-    } else if (rows4 && aligned(ip, 4) && aligned(op, 16)) {
+    } else if (rows4 && aligned(ip, (size_t)rows_align) && aligned(op, 16)) {
       RowGeom g;
       g.W = (uint32_t)hi.W;
       g.H = (uint32_t)hi.H;
@@ -995,7 +1095,23 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
       const uint32_t n_chunks = (uint32_t)(cnt * hi.H) * g.cpr;
       if (hi.dtype == MACT_U8) launch_rows4_io<MACT_U8>(params->xform, ho.dtype, exact_deg, ip, op, n_chunks, g, k, gamma, st);
       else if (hi.dtype == MACT_U16) launch_rows4_io<MACT_U16>(params->xform, ho.dtype, exact_deg, ip, op, n_chunks, g, k, gamma, st);
-      else launch_rows4_io<MACT_F16>(params->xform, ho.dtype, exact_deg, ip, op, n_chunks, g, k, gamma, st);
+      else if (hi.dtype == MACT_F16) launch_rows4_io<MACT_F16>(params->xform, ho.dtype, exact_deg, ip, op, n_chunks, g, k, gamma, st);
+      else launch_rows4_io<MACT_F32>(params->xform, ho.dtype, exact_deg, ip, op, n_chunks, g, k, gamma, st);
+    } else if (chw_rows4 && aligned(ip, 4 * hi.esize) && aligned(op, 16)) {
+      ChwRows g;
+      g.W = (uint32_t)hi.W;
+      g.H = (uint32_t)hi.H;
+      g.cpr = (g.W + 255u) / 256u;
+      g.div_cpr = make_fastdiv(g.cpr);
+      g.div_h = make_fastdiv(g.H);
+      g.rs = (uint64_t)hi.rs;
+      g.bs = (uint64_t)hi.bs;
+      g.ps = (uint32_t)hi.ps;
+      const uint32_t n_chunks = (uint32_t)(cnt * hi.H) * g.cpr;
+      if (ho.layout == MACT_CHW)
+        launch_chw_rows4_any<true>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_chunks, g, k, gamma, st);
+      else
+        launch_chw_rows4_any<false>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_chunks, g, k, gamma, st);
     } else {
       const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
       const unsigned grid = full_grid(n_px, 256);

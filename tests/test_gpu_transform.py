@@ -211,24 +211,29 @@ VIEW_CASES = [  # (images, rows, width, row padding px, padding rows per image)
 ]
 
 
-@pytest.mark.parametrize("dtype", ["u8", "f16", "u16"])
+def _base(g, dtype, shape):
+    if dtype == "u8":
+        return g.integers(0, 256, shape).astype(np.uint8)
+    if dtype == "u16":
+        return g.integers(0, 65536, shape).astype(np.uint16)
+    if dtype == "f16":
+        return g.random(shape).astype(np.float16)
+    return g.uniform(-0.05, 1.05, shape).astype(np.float32)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f16", "u16", "f32"])
 @pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
 def test_row_strided_views_equal_packed(M, dtype, xform):
     # crops of padded rows and images (the row-strided kernel where rows hold a multiple of 4 pixels
-    # and the strides are whole words, the one-pixel kernel otherwise) give the packed input's bits
+    # and the strides are whole words, 16-byte units for float32; the one-pixel kernel otherwise)
+    # give the packed input's bits
     g = synth.rng(200 + xform)
     pars = [M.default_params(xform), M.make_params(xform, [M.paper_approx(M.FN_CBRT, 4, 4)])] if xform in (0, 3) \
         else [M.default_params(xform)]
     if xform in (0, 3) and dtype != "u8":
         pars.append(M.default_params(xform, decode=True))
     for (n, h, w, rpad, ipad) in VIEW_CASES:
-        shape = (n, h + ipad, w + rpad, 3)
-        if dtype == "u8":
-            base = g.integers(0, 256, shape).astype(np.uint8)
-        elif dtype == "u16":
-            base = g.integers(0, 65536, shape).astype(np.uint16)
-        else:
-            base = g.random(shape).astype(np.float16)
+        base = _base(g, dtype, (n, h + ipad, w + rpad, 3))
         view = torch.from_numpy(base).cuda()[:, :h, :w]
         packed = torch.from_numpy(np.ascontiguousarray(base[:, :h, :w])).cuda()
         for p in pars:
@@ -263,6 +268,30 @@ def test_chw_inputs_equal_packed_hwc(M, dtype, xform):
                 torch.cuda.synchronize()
                 assert a.dtype == od and torch.equal(a, b.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm, od)
                 assert c.dtype == od and torch.equal(c, b), (n, h, w, gm, od)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f16", "f32"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3], ids=["lab", "hsi", "sct", "luv"])
+def test_chw_row_views_equal_packed(M, dtype, xform):
+    # crops of CHW planes and batches with gaps between images (the row-strided CHW kernel where rows
+    # hold a multiple of 4 pixels and every stride is a multiple of 4 elements, the one-pixel kernel
+    # otherwise), into CHW and HWC, float32 and float16: the packed HWC input's bits
+    g = synth.rng(600 + xform)
+    cases = VIEW_CASES + [(3, 6, 12, 0, 0)]  # the last one: 4 planes per image, the fourth skipped
+    for (n, h, w, rpad, ipad) in cases:
+        extra = 1 if (rpad, ipad) == (0, 0) else 0
+        base = _base(g, dtype, (n, 3 + extra, h + ipad, w + rpad))
+        view = torch.from_numpy(base).cuda()[:, :3, :h, :w]
+        hwc = torch.from_numpy(np.ascontiguousarray(np.moveaxis(base[:, :3, :h, :w], 1, -1))).cuda()
+        for gm in (["bt709", "none"] if xform in (0, 3) else ["none"]):
+            p = M.default_params(xform)
+            for od in (torch.float32, torch.float16):
+                a = M.transform(view, xform=xform, params=p, layout="chw", gamma=gm, out_dtype=od)
+                c = M.transform(view, xform=xform, params=p, layout="chw", out_layout="hwc", gamma=gm, out_dtype=od)
+                b = M.transform(hwc, xform=xform, params=p, gamma=gm, out_dtype=od)
+                torch.cuda.synchronize()
+                assert a.dtype == od and torch.equal(a, b.permute(0, 3, 1, 2).contiguous()), (n, h, w, rpad, ipad, gm, od)
+                assert c.dtype == od and torch.equal(c, b), (n, h, w, rpad, ipad, gm, od)
 
 
 def test_empty_inputs_give_empty_outputs(M):
