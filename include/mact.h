@@ -204,11 +204,14 @@ mact_status mact_params_default(int32_t xform, mact_params* p);
    MACT_F32 or MACT_F16, HWC or CHW, same width, height and batch as `in`.
    Evaluation is float32 with explicit fused multiply-adds; the result does not
    depend on the layout or the launch configuration, so every form (plain,
-   batched, served) gives identical bits.  Coalesced kernels serve packed HWC
-   in to packed HWC out, packed HWC or CHW in to packed float32 CHW or HWC out
-   (W H a multiple of 4), and row-strided HWC views (8-bit, 16-bit, float16)
-   to packed float32 HWC (rows of a multiple of 4 pixels, strides whole 4-byte
-   words); other combinations run one pixel per lane at a fraction of the
+   batched, served) gives identical bits.  Coalesced kernels, each to float32
+   or float16 output, serve packed HWC in to packed HWC out; packed HWC or CHW
+   in to packed CHW or HWC out (W H a multiple of 4); row-strided HWC views to
+   packed HWC (rows of a multiple of 4 pixels, strides in whole 4-byte words,
+   16-byte for float32); and row-strided CHW views (crops of the planes, gaps
+   between images) to packed HWC or CHW (rows of a multiple of 4 pixels,
+   strides in whole 4-element groups).  Other combinations (odd widths, other
+   strides, strided outputs) run one pixel per lane at a fraction of the
    bandwidth.
    Errors: MACT_E_INVALID (NULL pointers, sizes <= 0, strides too small,
    mismatched shapes, gamma set for HSI/SCT, out_mode 1 for HSI/SCT, degrees
