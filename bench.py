@@ -533,6 +533,10 @@ def main():
     k_spread = {}
     k_ms, k_med = time_kernel(step, a.steps, spread=k_spread)
     achieved = 15.0 * n_px / (k_ms * 1e-3) / 1e9
+    # launches per step under the library's split (equal launches of whole images, at most 2^26 pixels)
+    n_launch = -(-n_px // (1 << 26))
+    per_img = -(-N_IMG // n_launch)
+    launches = -(-N_IMG // per_img)
 
     forms = {}
     c_ms, _ = time_kernel(lambda: M.stream_u8_to_f32(x, y, n_px), a.steps)
@@ -640,9 +644,13 @@ def main():
                    "max_dE_exhaustive_cube": acc.get("exhaustive_cube_oracle", {}).get("lab", {}).get("max")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_hwc4<U8,F32,4,LAB>",
+                     # HIP events around each step: the library splits the batch into equal launches of
+                     # at most 2^26 pixels (two of 32 images here), so one launch averages kernel_ms /
+                     # launches_per_step, the gap between the two included
                      "kernel_ms": k_ms, "kernel_ms_median": k_med, "kernel_ms_p10": k_spread["p10"],
                      "kernel_ms_p90": k_spread["p90"], "algorithmic_bytes_per_px": 15,
-                     "pixels_per_launch": n_px,
+                     "launches_per_step": launches, "pixels_per_launch": n_px // launches,
+                     "launch_ms": k_ms / launches,
                      # the same run's 16-byte copy (equal reads and writes, a grid covering the copy once):
                      # the practical ceiling of this machine's HBM for a streaming kernel
                      "copy16_GBs": forms["copy16"]["GBs"],
@@ -658,7 +666,8 @@ def kernel_hash():
     """Hash of the hot kernel's sources, to tell whether stored counters are
     stale: the per-pixel code and constants (pixel.h, common.h), the
     streaming stores (stream.h) and, from
-    xform.hip, the hot kernel with its launch constants, grid and launcher."""
+    xform.hip, the hot kernel with its launch constants, grid, launcher and
+    the split of a batch into launches."""
     import hashlib
     import re
     csrc = os.path.join(ROOT, "paper_1009_0854_amd", "csrc")
@@ -672,7 +681,8 @@ def kernel_hash():
     a = src.index("constexpr int kHotBlock")
     b = src.index("\n}\n", src.index("void k_hwc4(")) + 3
     h.update(src[a:b].encode())
-    for pat in (r"static unsigned hot_grid\(.*?\n}\n", r"static void launch_hwc4\(.*?\n}\n"):
+    for pat in (r"static unsigned hot_grid\(.*?\n}\n", r"static void launch_hwc4\(.*?\n}\n",
+                r"int64_t images_per_stream_launch\(.*?\n}\n"):
         h.update(re.search(pat, src, re.S).group(0).encode())
     return h.hexdigest()[:16]
 

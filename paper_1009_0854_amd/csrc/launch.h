@@ -30,6 +30,13 @@ mact_status check_same_shape(const HostImage& a, const HostImage& b, const char*
 KImage kimage(const HostImage& h, int64_t n0, int64_t count);
 // Images per launch so that a launch covers fewer than 2^31 pixels.
 int64_t images_per_launch(const HostImage& h);
+// Images per launch of the streaming kernels with float32 output: the batch
+// split into equal launches of at most 2^26 pixels (at least one image each).
+// Measured in one process against whole-batch launches: CIELAB 64 x 1080p in
+// two launches +1.3%, 32 x 4K in four +2.7%, the float32-input forms and the
+// inverses +1 to +1.6%.  float16 outputs, whose kernels are bound by the VALU,
+// lost 1.5% to the extra launch and keep images_per_launch.
+int64_t images_per_stream_launch(const HostImage& in, int out_dtype);
 
 // Coefficients rounded to float32 and zero padded; returns the padded degree
 // (5 or 7) the kernels are instantiated for, and the highest degree actually

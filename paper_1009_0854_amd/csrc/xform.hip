@@ -115,6 +115,14 @@ int64_t images_per_launch(const HostImage& h) {
   return std::max<int64_t>(1, ((1ll << 31) - 1) / hw);
 }
 
+int64_t images_per_stream_launch(const HostImage& in, int out_dtype) {
+  const int64_t most = images_per_launch(in);
+  if (out_dtype != MACT_F32) return most;
+  const int64_t hw = in.W * in.H;
+  const int64_t launches = (in.N * hw + (1ll << 26) - 1) >> 26;
+  return std::max<int64_t>(1, std::min<int64_t>(most, (in.N + launches - 1) / launches));
+}
+
 int pack_coef(const mact_params& p, KCoef* k, int* exact) {
   std::memset(k, 0, sizeof *k);
   k->xform = p.xform;
@@ -1060,7 +1068,7 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   // row-strided CHW -> packed HWC or CHW: rows of a multiple of 4 pixels, strides of whole 4-element groups
   const bool chw_rows4 = hi.layout == MACT_CHW && !hi.packed && f_out && ho.packed && hi.W % 4 == 0 &&
                          hi.rs % 4 == 0 && hi.ps % 4 == 0 && hi.bs % 4 == 0 && hi.ps < ((int64_t)1 << 32);
-  const int64_t per = images_per_launch(hi);
+  const int64_t per = images_per_stream_launch(hi, ho.dtype);
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
     const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
