@@ -39,13 +39,13 @@ template <int DEG, int VEC>
 __global__ __launch_bounds__(1024) void k_batch(const BDesc* __restrict__ descs, const KCoef* __restrict__ coefs,
                                                 const uint32_t* __restrict__ tile_start,
                                                 const uint32_t* __restrict__ tile_img, int32_t count,
-                                                uint32_t total_tiles, uint32_t tile) {
+                                                uint32_t tile0, uint32_t total_tiles, uint32_t tile) {
   __shared__ float gtab[3][256];
   extern __shared__ f4 s_out[];  // VEC == 4: 192 float4 per wave
   for (uint32_t i = threadIdx.x; i < 768u; i += blockDim.x) gtab[i >> 8][i & 255u] = k_gamma_table[i >> 8][i & 255u];
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (uint32_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+  for (uint32_t t = tile0 + blockIdx.x; t < total_tiles; t += gridDim.x) {
     int32_t lo = 0;
     if (tile_img) {
       lo = (int32_t)tile_img[t];
@@ -168,22 +168,32 @@ unsigned batch_grid(const mact_tune& tune, uint32_t total_tiles) {
   return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(total_tiles, cap));
 }
 
+// The tile list runs as equal launches of at most 2^26 pixels of tiles each
+// (one launch for small batches): streaming launches of that size run faster
+// than one launch over a whole large batch.
 hipError_t launch_batch_kernel(const BDesc* d_descs, const KCoef* d_coefs, const uint32_t* d_tiles, int32_t count,
                                uint32_t total_tiles, const mact_tune& tune, int deg, hipStream_t st,
                                const uint32_t* d_tile_img) {
   if (total_tiles == 0) return hipSuccess;
-  const unsigned grid = batch_grid(tune, total_tiles);
   const size_t shm = tune.vec == 4 ? (size_t)(tune.block / 64) * 192 * sizeof(f4) : 0;
-  const dim3 g(grid), b(tune.block);
   const uint32_t tile = (uint32_t)tune.tile;
-  if (deg == 5) {
-    if (tune.vec == 4) hipLaunchKernelGGL((k_batch<5, 4>), g, b, shm, st, d_descs, d_coefs, d_tiles, d_tile_img, count, total_tiles, tile);
-    else hipLaunchKernelGGL((k_batch<5, 1>), g, b, shm, st, d_descs, d_coefs, d_tiles, d_tile_img, count, total_tiles, tile);
-  } else {
-    if (tune.vec == 4) hipLaunchKernelGGL((k_batch<7, 4>), g, b, shm, st, d_descs, d_coefs, d_tiles, d_tile_img, count, total_tiles, tile);
-    else hipLaunchKernelGGL((k_batch<7, 1>), g, b, shm, st, d_descs, d_coefs, d_tiles, d_tile_img, count, total_tiles, tile);
+  const uint64_t launches = std::max<uint64_t>(1, ((uint64_t)total_tiles * tile + (1ull << 26) - 1) >> 26);
+  const uint32_t per = (uint32_t)(((uint64_t)total_tiles + launches - 1) / launches);
+  const dim3 b(tune.block);
+  for (uint32_t t0 = 0; t0 < total_tiles; t0 += per) {
+    const uint32_t t1 = std::min(total_tiles, t0 + per);
+    const dim3 g(batch_grid(tune, t1 - t0));
+    if (deg == 5) {
+      if (tune.vec == 4) hipLaunchKernelGGL((k_batch<5, 4>), g, b, shm, st, d_descs, d_coefs, d_tiles, d_tile_img, count, t0, t1, tile);
+      else hipLaunchKernelGGL((k_batch<5, 1>), g, b, shm, st, d_descs, d_coefs, d_tiles, d_tile_img, count, t0, t1, tile);
+    } else {
+      if (tune.vec == 4) hipLaunchKernelGGL((k_batch<7, 4>), g, b, shm, st, d_descs, d_coefs, d_tiles, d_tile_img, count, t0, t1, tile);
+      else hipLaunchKernelGGL((k_batch<7, 1>), g, b, shm, st, d_descs, d_coefs, d_tiles, d_tile_img, count, t0, t1, tile);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 static mact_status check_tune(const mact_tune& t) {
