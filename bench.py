@@ -194,7 +194,7 @@ def bench_general(M, x, y, p, n_px, steps):
 
 def bench_inverse(M, x, y, n_px, steps):
     """Inverse MACT (L*a*b* / HSI / SCT / L*u*v* float32 -> R'G'B' float32, 24 bytes per
-    pixel) on the forward output of the batch, and the on-device error
+    pixel; CIELAB also to float16) on the forward output of the batch, and the on-device error
     statistics of each forward transform over all 2^24 8-bit colours."""
     import torch
     import synth
@@ -208,7 +208,12 @@ def bench_inverse(M, x, y, n_px, steps):
         rt = max(float((back[i].float() - x[i].float() / 255.0).abs().max()) for i in range(x.shape[0]))
         out["%s_inverse" % name] = {"Mpx_s": n_px / ms / 1e3, "GBs": 24.0 * n_px / ms / 1e6, "ms": ms,
                                     "round_trip_max_abs": rt}
-    del back
+    # CIELAB inverse to float16 R'G'B' (18 bytes per pixel)
+    back16 = back.view(-1).view(torch.float16)[: n_px * 3].view(back.shape)
+    M.transform(x, xform="lab", out=y)
+    ms, _ = time_kernel(lambda: M.inverse(y, xform="lab", out=back16), steps)
+    out["lab_inverse_f16_out"] = {"Mpx_s": n_px / ms / 1e3, "GBs": 18.0 * n_px / ms / 1e6, "ms": ms}
+    del back, back16
     cube = torch.from_numpy(synth.cube_u8()).cuda()
     for name in ("lab", "hsi", "sct", "luv"):
         M.error_stats(cube, xform=name)

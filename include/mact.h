@@ -274,7 +274,10 @@ mact_status mact_inverse_params_default(int32_t xform, mact_params* p);
           the clamp and the encoding as for LAB.  Triples off the image of the
           forward transform (v' <= 0) give unspecified values.
    in: MACT_F32 or MACT_F16, any layout; out: MACT_F32 or MACT_F16, any layout,
-   same geometry.  float32 arithmetic.  Errors: MACT_E_INVALID (NULL, shapes,
+   same geometry.  float32 arithmetic; float16 outputs are the float32 results
+   rounded to nearest even.  Coalesced kernels serve packed float32 HWC in to
+   packed HWC out and packed CHW in to packed CHW out (W H a multiple of 4);
+   other combinations run one pixel per lane.  Errors: MACT_E_INVALID (NULL, shapes,
    approximations of the wrong function or degree); MACT_E_UNSUPPORTED (8-bit
    in, sRGB encoding); MACT_E_DEVICE. */
 mact_status mact_inverse(const mact_params* params, const mact_image* in, const mact_image* out,

@@ -158,15 +158,18 @@ __global__ __launch_bounds__(256) void k_inverse(KImage src, KImage dst, uint32_
   }
 }
 
-// Packed float32 HWC in and out, 16-byte aligned: each wave takes 256-pixel
-// chunks (3 KB each way).  The chunk comes in as three 1 KB coalesced loads
-// into the wave's LDS slice, each lane reads its 4 pixels (48 bytes) from
-// there, computes them, writes them back to the slice, and the chunk leaves
-// as three 1 KB coalesced stores.  The same per-pixel code as k_inverse.
+// Packed float32 HWC in, packed float32 or float16 (OUT) HWC out, 16-byte
+// aligned: each wave takes 256-pixel chunks (3 KB in; 3 KB or 1.5 KB out).
+// The chunk comes in as three 1 KB coalesced loads into the wave's LDS slice,
+// each lane reads its 4 pixels (48 bytes) from there, computes them, writes
+// them back to the slice (float16 rounded to nearest even), and the chunk
+// leaves as three coalesced stores of 1 KB (512 B for float16).  The same
+// per-pixel code as k_inverse.
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 
-template <int DEG, int XF>
-__global__ __launch_bounds__(256) void k_inverse4(const f4* __restrict__ in, f4* __restrict__ out, uint32_t n_px,
+template <int DEG, int XF, int OUT>
+__global__ __launch_bounds__(256) void k_inverse4(const f4* __restrict__ in, void* __restrict__ out, uint32_t n_px,
                                                   KCoef k, InvMat mi, int gamma) {
   __shared__ f4 s_buf[4][192];
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
@@ -193,15 +196,30 @@ __global__ __launch_bounds__(256) void k_inverse4(const f4* __restrict__ in, f4*
     }
     __builtin_amdgcn_s_waitcnt(0xc07f);  // every lane's reads are done before the slice is rewritten
     __builtin_amdgcn_wave_barrier();
-    s[3 * lane] = f4{o[0], o[1], o[2], o[3]};
-    s[3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
-    s[3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+    if (OUT == MACT_F32) {
+      s[3 * lane] = f4{o[0], o[1], o[2], o[3]};
+      s[3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
+      s[3 * lane + 2] = f4{o[8], o[9], o[10], o[11]};
+    } else {
+      f2* s2 = reinterpret_cast<f2*>(s);  // 12 halves per lane: three 8-byte words
+#pragma unroll
+      for (int t = 0; t < 3; ++t)
+        s2[3 * lane + t] = f2{__uint_as_float(pack2_h_rn(o[4 * t], o[4 * t + 1])),
+                              __uint_as_float(pack2_h_rn(o[4 * t + 2], o[4 * t + 3]))};
+    }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __builtin_amdgcn_wave_barrier();
-    f4* dst = out + (size_t)c * 192;
+    if (OUT == MACT_F32) {
+      f4* dst = static_cast<f4*>(out) + (size_t)c * 192;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(s[q * 64 + lane], dst + q * 64 + lane);
+      for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(s[q * 64 + lane], dst + q * 64 + lane);
+    } else {
+      f2* dst = static_cast<f2*>(out) + (size_t)c * 192;
+      const f2* s2 = reinterpret_cast<const f2*>(s);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(s2[q * 64 + lane], dst + q * 64 + lane);
+    }
     __builtin_amdgcn_s_waitcnt(0xc07f);
     __builtin_amdgcn_wave_barrier();
   }
@@ -209,7 +227,6 @@ __global__ __launch_bounds__(256) void k_inverse4(const f4* __restrict__ in, f4*
   const uint32_t tail0 = n_chunks << 8;
   if (blockIdx.x == 0 && threadIdx.x < n_px - tail0) {
     const float* fi = reinterpret_cast<const float*>(in);
-    float* fo = reinterpret_cast<float*>(out);
     const size_t p = tail0 + threadIdx.x;
     const float v[3] = {fi[3 * p], fi[3 * p + 1], fi[3 * p + 2]};
     float o[3];
@@ -217,17 +234,20 @@ __global__ __launch_bounds__(256) void k_inverse4(const f4* __restrict__ in, f4*
     else if (XF == MACT_LUV) luv_inv_px<DEG>(k, mi, gamma, v, o);
     else if (XF == MACT_HSI) hsi_inv_px<DEG>(k, v, o);
     else sct_inv_px<DEG>(k, v, o);
-    fo[3 * p] = o[0];
-    fo[3 * p + 1] = o[1];
-    fo[3 * p + 2] = o[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (OUT == MACT_F32) static_cast<float*>(out)[3 * p + c] = o[c];
+      else static_cast<__half*>(out)[3 * p + c] = f2h_rn(o[c]);
+    }
   }
 }
 
-// Packed CHW (float32 or float16) -> packed float32 CHW, W H a multiple of 4
-// (network outputs): 4 pixels per lane, one 16- or 8-byte load and one 16-byte
-// store per plane, each contiguous across the wave.  The same per-pixel code.
-template <int IN, int DEG, int XF>
-__global__ __launch_bounds__(256) void k_inverse_chw4(const void* __restrict__ in, float* __restrict__ out,
+// Packed CHW (float32 or float16) -> packed float32 or float16 (OUT) CHW, W H
+// a multiple of 4 (network outputs): 4 pixels per lane, one 16- or 8-byte load
+// and one 16- or 8-byte store per plane, each contiguous across the wave.  The
+// same per-pixel code.
+template <int IN, int DEG, int XF, int OUT>
+__global__ __launch_bounds__(256) void k_inverse_chw4(const void* __restrict__ in, void* __restrict__ out,
                                                       uint32_t n_px, uint32_t hw, FastDiv div_hw4, KCoef k, InvMat mi,
                                                       int gamma) {
   const uint32_t n4 = n_px >> 2, hw4 = hw >> 2;
@@ -246,32 +266,49 @@ __global__ __launch_bounds__(256) void k_inverse_chw4(const void* __restrict__ i
       else sct_inv_px<DEG>(k, v[j], o[j]);
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      __builtin_nontemporal_store(f4{o[0][c], o[1][c], o[2][c], o[3][c]},
-                                  reinterpret_cast<f4*>(out + base + (size_t)c * hw));
+    for (int c = 0; c < 3; ++c) {
+      if (OUT == MACT_F32)
+        __builtin_nontemporal_store(f4{o[0][c], o[1][c], o[2][c], o[3][c]},
+                                    reinterpret_cast<f4*>(static_cast<float*>(out) + base + (size_t)c * hw));
+      else
+        __builtin_nontemporal_store(f2{__uint_as_float(pack2_h_rn(o[0][c], o[1][c])),
+                                       __uint_as_float(pack2_h_rn(o[2][c], o[3][c]))},
+                                    reinterpret_cast<f2*>(static_cast<__half*>(out) + base + (size_t)c * hw));
+    }
   }
 }
 
-template <int IN, int DEG>
-void launch_inverse_chw4(int xform, const void* in, float* out, uint32_t n_px, uint32_t hw, const KCoef& k,
+template <int IN, int DEG, int OUT>
+void launch_inverse_chw4(int xform, const void* in, void* out, uint32_t n_px, uint32_t hw, const KCoef& k,
                          const InvMat& mi, int gamma, hipStream_t st) {
   const dim3 grid(std::max<uint32_t>(1, (n_px / 4 + 255) / 256)), blk(256);
   const FastDiv d = make_fastdiv(hw / 4);
-  if (xform == MACT_LAB) hipLaunchKernelGGL((k_inverse_chw4<IN, DEG, MACT_LAB>), grid, blk, 0, st, in, out, n_px, hw, d, k, mi, gamma);
-  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_inverse_chw4<IN, DEG, MACT_LUV>), grid, blk, 0, st, in, out, n_px, hw, d, k, mi, gamma);
-  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_inverse_chw4<IN, DEG, MACT_HSI>), grid, blk, 0, st, in, out, n_px, hw, d, k, mi, gamma);
-  else hipLaunchKernelGGL((k_inverse_chw4<IN, DEG, MACT_SCT>), grid, blk, 0, st, in, out, n_px, hw, d, k, mi, gamma);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_inverse_chw4<IN, DEG, MACT_LAB, OUT>), grid, blk, 0, st, in, out, n_px, hw, d, k, mi, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_inverse_chw4<IN, DEG, MACT_LUV, OUT>), grid, blk, 0, st, in, out, n_px, hw, d, k, mi, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_inverse_chw4<IN, DEG, MACT_HSI, OUT>), grid, blk, 0, st, in, out, n_px, hw, d, k, mi, gamma);
+  else hipLaunchKernelGGL((k_inverse_chw4<IN, DEG, MACT_SCT, OUT>), grid, blk, 0, st, in, out, n_px, hw, d, k, mi, gamma);
 }
 
-template <int DEG>
+template <int IN>
+void launch_inverse_chw4_io(int xform, int out_dtype, int deg, const void* in, void* out, uint32_t n_px, uint32_t hw,
+                            const KCoef& k, const InvMat& mi, int gamma, hipStream_t st) {
+  if (out_dtype == MACT_F32) {
+    if (deg == 5) launch_inverse_chw4<IN, 5, MACT_F32>(xform, in, out, n_px, hw, k, mi, gamma, st);
+    else launch_inverse_chw4<IN, 7, MACT_F32>(xform, in, out, n_px, hw, k, mi, gamma, st);
+  } else {
+    if (deg == 5) launch_inverse_chw4<IN, 5, MACT_F16>(xform, in, out, n_px, hw, k, mi, gamma, st);
+    else launch_inverse_chw4<IN, 7, MACT_F16>(xform, in, out, n_px, hw, k, mi, gamma, st);
+  }
+}
+
+template <int DEG, int OUT>
 void launch_inverse4(int xform, const void* in, void* out, uint32_t n_px, const KCoef& k, const InvMat& mi, int gamma,
                      unsigned grid, hipStream_t st) {
   const f4* i4 = static_cast<const f4*>(in);
-  f4* o4 = static_cast<f4*>(out);
-  if (xform == MACT_LAB) hipLaunchKernelGGL((k_inverse4<DEG, MACT_LAB>), dim3(grid), dim3(256), 0, st, i4, o4, n_px, k, mi, gamma);
-  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_inverse4<DEG, MACT_LUV>), dim3(grid), dim3(256), 0, st, i4, o4, n_px, k, mi, gamma);
-  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_inverse4<DEG, MACT_HSI>), dim3(grid), dim3(256), 0, st, i4, o4, n_px, k, mi, gamma);
-  else hipLaunchKernelGGL((k_inverse4<DEG, MACT_SCT>), dim3(grid), dim3(256), 0, st, i4, o4, n_px, k, mi, gamma);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_inverse4<DEG, MACT_LAB, OUT>), dim3(grid), dim3(256), 0, st, i4, out, n_px, k, mi, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_inverse4<DEG, MACT_LUV, OUT>), dim3(grid), dim3(256), 0, st, i4, out, n_px, k, mi, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_inverse4<DEG, MACT_HSI, OUT>), dim3(grid), dim3(256), 0, st, i4, out, n_px, k, mi, gamma);
+  else hipLaunchKernelGGL((k_inverse4<DEG, MACT_SCT, OUT>), dim3(grid), dim3(256), 0, st, i4, out, n_px, k, mi, gamma);
 }
 
 // ---------------------------------------------------------------- exact, float64
@@ -525,9 +562,9 @@ extern "C" mact_status mact_inverse(const mact_params* params, const mact_image*
   const InvMat& mi = params->xform == MACT_LUV ? mi_luv : mi_lab;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const int64_t per = images_per_stream_launch(hi, ho.dtype);
-  const bool fast = hi.dtype == MACT_F32 && ho.dtype == MACT_F32 && hi.layout == MACT_HWC && ho.layout == MACT_HWC &&
-                    hi.packed && ho.packed;
-  const bool chw4 = (hi.dtype == MACT_F32 || hi.dtype == MACT_F16) && ho.dtype == MACT_F32 && hi.layout == MACT_CHW &&
+  // float32 or float16 out for both 4-pixel paths
+  const bool fast = hi.dtype == MACT_F32 && hi.layout == MACT_HWC && ho.layout == MACT_HWC && hi.packed && ho.packed;
+  const bool chw4 = (hi.dtype == MACT_F32 || hi.dtype == MACT_F16) && hi.layout == MACT_CHW &&
                     ho.layout == MACT_CHW && hi.packed && ho.packed && (hi.W * hi.H) % 4 == 0;
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
@@ -537,18 +574,17 @@ extern "C" mact_status mact_inverse(const mact_params* params, const mact_image*
       // one 256-pixel chunk per wave, 4 waves per workgroup, the grid covering the image once;
       // at least one workgroup for the tail
       const unsigned grid = (unsigned)std::max<uint64_t>(1, ((uint64_t)(n_px >> 8) + 3) / 4);
-      if (deg == 5) launch_inverse4<5>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
-      else launch_inverse4<7>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
+      if (ho.dtype == MACT_F32) {
+        if (deg == 5) launch_inverse4<5, MACT_F32>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
+        else launch_inverse4<7, MACT_F32>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
+      } else {
+        if (deg == 5) launch_inverse4<5, MACT_F16>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
+        else launch_inverse4<7, MACT_F16>(params->xform, ks.ptr, kd.ptr, n_px, k, mi, gamma, grid, st);
+      }
     } else if (chw4 && (uintptr_t)ks.ptr % (4 * hi.esize) == 0 && (uintptr_t)kd.ptr % 16 == 0) {
       const uint32_t hw = (uint32_t)(hi.W * hi.H);
-      float* of = static_cast<float*>(kd.ptr);
-      if (hi.dtype == MACT_F32) {
-        if (deg == 5) launch_inverse_chw4<MACT_F32, 5>(params->xform, ks.ptr, of, n_px, hw, k, mi, gamma, st);
-        else launch_inverse_chw4<MACT_F32, 7>(params->xform, ks.ptr, of, n_px, hw, k, mi, gamma, st);
-      } else {
-        if (deg == 5) launch_inverse_chw4<MACT_F16, 5>(params->xform, ks.ptr, of, n_px, hw, k, mi, gamma, st);
-        else launch_inverse_chw4<MACT_F16, 7>(params->xform, ks.ptr, of, n_px, hw, k, mi, gamma, st);
-      }
+      if (hi.dtype == MACT_F32) launch_inverse_chw4_io<MACT_F32>(params->xform, ho.dtype, deg, ks.ptr, kd.ptr, n_px, hw, k, mi, gamma, st);
+      else launch_inverse_chw4_io<MACT_F16>(params->xform, ho.dtype, deg, ks.ptr, kd.ptr, n_px, hw, k, mi, gamma, st);
     } else {
       const dim3 grid(std::max<uint32_t>(1, (n_px + 255) / 256)), blk(256);
       if (deg == 5) hipLaunchKernelGGL(k_inverse<5>, grid, blk, 0, st, ks, kd, n_px, k, mi, gamma);

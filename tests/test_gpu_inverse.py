@@ -129,7 +129,7 @@ def test_inverse_layouts_and_float16(M, xform):
 @pytest.mark.parametrize("xform", ["lab", "hsi", "sct", "luv"])
 def test_inverse_chw_equals_hwc(M, xform, dtype):
     # packed CHW planes (the 4-pixel plane kernel where W H is a multiple of 4, the one-pixel kernel
-    # otherwise) give the HWC result's bits, plane by plane
+    # otherwise) give the HWC result's bits, plane by plane, for float32 and float16 outputs
     g = synth.rng(77)
     fwd = {"lab": C.rgb_to_lab, "hsi": C.rgb_to_hsi, "sct": C.rgb_to_sct, "luv": C.rgb_to_luv}[xform]
     p = M.inverse_params(xform)
@@ -138,10 +138,11 @@ def test_inverse_chw_equals_hwc(M, xform, dtype):
         hwc = torch.from_numpy(v).cuda()
         chw = torch.from_numpy(np.ascontiguousarray(np.moveaxis(v, -1, 1))).cuda()
         for gm in (["bt709", "none"] if xform in ("lab", "luv") else ["none"]):
-            a = M.inverse(chw, xform=xform, params=p, layout="chw", gamma=gm)
-            b = M.inverse(hwc, xform=xform, params=p, gamma=gm)
-            torch.cuda.synchronize()
-            assert torch.equal(a, b.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm)
+            for od in (torch.float32, torch.float16):
+                a = M.inverse(chw, xform=xform, params=p, layout="chw", gamma=gm, out_dtype=od)
+                b = M.inverse(hwc, xform=xform, params=p, gamma=gm, out_dtype=od)
+                torch.cuda.synchronize()
+                assert a.dtype == od and torch.equal(a, b.permute(0, 3, 1, 2).contiguous()), (n, h, w, gm, od)
 
 
 @pytest.mark.parametrize("xform", ["lab", "hsi", "sct", "luv"])
@@ -229,7 +230,7 @@ def test_error_stats_of_every_colour_match_the_oracle_tables(M, xform, key, tol_
 @pytest.mark.parametrize("xform", ["lab", "hsi", "sct", "luv"])
 def test_inverse_fast_path_equals_general(M, xform, shape):
     # packed float32 HWC (LDS-staged chunks, ragged tail) gives the bits of the one-pixel-per-lane
-    # kernel, which a row-padded view of the same values forces
+    # kernel, which a row-padded view of the same values forces, for float32 and float16 outputs
     g = synth.rng(sum(shape))
     rgb = g.random((2,) + shape + (3,))
     fwd = {"lab": C.rgb_to_lab, "hsi": C.rgb_to_hsi, "sct": C.rgb_to_sct, "luv": C.rgb_to_luv}[xform](rgb).astype(np.float32)
@@ -238,7 +239,13 @@ def test_inverse_fast_path_equals_general(M, xform, shape):
     big = torch.zeros((2, shape[0], shape[1] + 3, 3), dtype=torch.float32, device="cuda")
     big[:, :, :shape[1]] = x
     for gm in (["bt709", "none"] if xform in ("lab", "luv") else ["none"]):
-        fast = M.inverse(x, xform=xform, params=p, gamma=gm)
-        general = M.inverse(big[:, :, :shape[1]], xform=xform, params=p, gamma=gm)
+        for od in (torch.float32, torch.float16):
+            fast = M.inverse(x, xform=xform, params=p, gamma=gm, out_dtype=od)
+            general = M.inverse(big[:, :, :shape[1]], xform=xform, params=p, gamma=gm, out_dtype=od)
+            torch.cuda.synchronize()
+            assert fast.dtype == od and torch.equal(fast, general), (gm, od)
+        # float16 out is the float32 result rounded to nearest even
+        f32 = M.inverse(x, xform=xform, params=p, gamma=gm)
+        f16 = M.inverse(x, xform=xform, params=p, gamma=gm, out_dtype=torch.float16)
         torch.cuda.synchronize()
-        assert torch.equal(fast, general), gm
+        assert torch.equal(f16, f32.half()), gm
