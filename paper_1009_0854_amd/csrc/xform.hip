@@ -1,20 +1,24 @@
 // Plain per-pixel MACT transforms (Sec. 3.2-3.4), the backward pass of the
 // CIELAB transform, and the reference streaming kernels.
 //
-// Three kernel shapes:
-//  * k_hwc4: the hot path, packed 8-bit (or float16) HWC in and packed
-//    float32 (or float16) HWC out, staged through LDS so that every global
+// The kernels:
+//  * k_hwc4: the hot path, packed 8-bit, 16-bit or float16 HWC in and packed
+//    float32 or float16 HWC out, staged through LDS so that every global
 //    store is a contiguous run of 1 KB per wave (details at the kernel).
 //  * k_hwc4f: k_hwc4 for packed float32 HWC input, staged through LDS both ways.
 //  * k_rows4: row-strided HWC views (crops, pitched rows), k_hwc4's pattern
 //    per 256-pixel run of a row.
+//  * k_chw_rows4: row-strided CHW views (crops of the planes, gaps between
+//    images) -> packed HWC or CHW, one load per plane and lane.
 //  * k_chw4: packed CHW of any input type, 4 pixels per lane, vector access
 //    per plane.
-//  * k_hwc_chw4: packed HWC of any input type -> packed float32 CHW, 4 pixels
-//    per lane, no LDS.
-//  * k_chw_hwc4: packed CHW of any input type -> packed float32 HWC through
-//    the wave's LDS slice.
+//  * k_hwc_chw4: packed HWC of any input type -> packed CHW, 4 pixels per
+//    lane, no LDS.
+//  * k_chw_hwc4: packed CHW of any input type -> packed HWC through the
+//    wave's LDS slice.
 //  * k_generic: any element type, layout and stride, one pixel per lane step.
+// Every kernel but k_generic writes float32 or float16 by template; k_generic
+// writes either at run time.
 // All call the same per-pixel functions (pixel.h), so they give identical bits.
 #include <algorithm>
 #include <cstring>
