@@ -212,7 +212,10 @@ mact_status mact_params_default(int32_t xform, mact_params* p);
    between images) to packed HWC or CHW (rows of a multiple of 4 pixels,
    strides in whole 4-element groups).  Other combinations (odd widths, other
    strides, strided outputs) run one pixel per lane at a fraction of the
-   bandwidth.
+   bandwidth.  With float32 output, a batch of more than 2^26 pixels runs as
+   several launches of whole images, in order on `hip_stream` (equal groups of
+   at most 2^26 pixels, or one image each if images are larger); a graph
+   captured from the call holds them all.
    Errors: MACT_E_INVALID (NULL pointers, sizes <= 0, strides too small,
    mismatched shapes, gamma set for HSI/SCT, out_mode 1 for HSI/SCT, degrees
    outside 0..7); MACT_E_UNSUPPORTED (rational approximations for HSI/SCT,
@@ -277,7 +280,8 @@ mact_status mact_inverse_params_default(int32_t xform, mact_params* p);
    same geometry.  float32 arithmetic; float16 outputs are the float32 results
    rounded to nearest even.  Coalesced kernels serve packed float32 HWC in to
    packed HWC out and packed CHW in to packed CHW out (W H a multiple of 4);
-   other combinations run one pixel per lane.  Errors: MACT_E_INVALID (NULL, shapes,
+   other combinations run one pixel per lane.  Large float32-output batches
+   run as several launches, as for mact_transform.  Errors: MACT_E_INVALID (NULL, shapes,
    approximations of the wrong function or degree); MACT_E_UNSUPPORTED (8-bit
    in, sRGB encoding); MACT_E_DEVICE. */
 mact_status mact_inverse(const mact_params* params, const mact_image* in, const mact_image* out,
