@@ -49,11 +49,11 @@ def log(*a):
     print("bench:", *a, file=sys.stderr, flush=True)
 
 
-def time_kernel(fn, steps, warmup=2, spread=None):
-    """Mean and median duration (ms) of fn() over `steps` launches, HIP events
-    recorded around each launch on torch's current stream, which is the stream
-    the library launches on.  With a dict `spread`, also its 10th and 90th
-    percentiles there."""
+def time_kernel(fn, steps, warmup=20, spread=None):
+    """Mean and median duration (ms) of fn() over `steps` launches after
+    `warmup` untimed ones, HIP events recorded around each launch on torch's
+    current stream, which is the stream the library launches on.  With a dict
+    `spread`, also its 10th and 90th percentiles there."""
     import torch
     for _ in range(warmup):
         fn()
@@ -141,8 +141,8 @@ def bench_4k(M, p, steps):
     x = torch.randint(0, 256, (32, 2160, 3840, 3), dtype=torch.uint8, device="cuda", generator=g)
     y = torch.empty((32, 2160, 3840, 3), dtype=torch.float32, device="cuda")
     n_px = 32 * 2160 * 3840
-    # fresh buffers settle like a fresh process: 20 warm-up steps (about 13 ms)
-    ms, med = time_kernel(lambda: M.transform(x, params=p, out=y), steps, warmup=20)
+    # fresh buffers settle like a fresh process: time_kernel's 20 warm-up steps (about 13 ms)
+    ms, med = time_kernel(lambda: M.transform(x, params=p, out=y), steps)
     res = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "frac_of_8TBs": 15.0 * n_px / ms / 8e9,
            "ms": ms, "ms_median": med, "pixels": n_px}
     del x, y
