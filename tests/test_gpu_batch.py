@@ -172,6 +172,44 @@ def test_config3_uneven_1000_images_against_plain_and_oracle(M):
     plan.close()
 
 
+@pytest.mark.parametrize("tune", [(256, 4096, 4, 0), (1024, 8192, 4, 32), (256, 4096, 1, 16)],
+                         ids=["full_grid", "persistent", "vec1_persistent"])
+def test_split_launches_equal_plain_for_fixed_shapes(M, tune):
+    # 200 large images (about 0.4 Gpx): the tile list runs as several launches of at most 2^26
+    # pixels, each with the shape's grid (one workgroup per tile, or a persistent grid walking
+    # its part of the list); every image equals its plain launch bitwise
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    g = synth.rng(9)
+    params, ins, outs, gams = [], [], [], []
+    px = 0
+    for i in range(200):
+        h, w = int(g.integers(1000, 1600)), int(g.integers(1000, 1600))
+        if i % 2 == 0:
+            x = torch.randint(0, 256, (h, w, 3), dtype=torch.uint8, device="cuda", generator=gen)
+            gams.append("bt709")
+        else:
+            x = torch.rand((h, w, 3), device="cuda", generator=gen).half()
+            gams.append("none")
+        params.append(M.default_params(i % 4))
+        ins.append(x)
+        outs.append(torch.empty((h, w, 3), dtype=torch.float32, device="cuda"))
+        px += h * w
+    assert px > 4 * (1 << 26)
+    from paper_1009_0854_amd import _abi as A
+    t = A.Tune()
+    t.block, t.tile, t.vec, t.waves_per_cu = tune
+    plan = M.BatchPlan(params, ins, outs, gammas=gams, tune=t)
+    for use_graph in (True, False):
+        for o in outs:
+            o.fill_(float("nan"))
+        plan.launch(use_graph=use_graph)
+        torch.cuda.synchronize()
+        for i in range(200):
+            r = M.transform(ins[i], params=params[i], gamma=gams[i])
+            assert torch.equal(outs[i], r), (tune, use_graph, i)
+    plan.close()
+
+
 def test_batch_run_convenience(M):
     params, ins, outs, lays, gams, olays, _ = _mixed_batch(M, 7, seed=5)
     ref = _plain(M, params, ins, lays, gams)
