@@ -252,7 +252,8 @@ def test_chw_inputs_equal_packed_hwc(M, dtype, xform):
     # multiple of 4, the one-pixel kernel otherwise; a partial last chunk at 3 x 8 x 1000) give the
     # bits of the packed HWC input
     g = synth.rng(300 + xform)
-    for (n, h, w) in [(2, 16, 20), (1, 33, 36), (3, 8, 1000), (1, 7, 9)]:
+    # (2, 32, 64) and (3, 16, 128): planes of a multiple of 1024 pixels
+    for (n, h, w) in [(2, 16, 20), (1, 33, 36), (3, 8, 1000), (1, 7, 9), (2, 32, 64), (3, 16, 128)]:
         if dtype in ("u8", "u16"):
             hwc = g.integers(0, 256 if dtype == "u8" else 65536, (n, h, w, 3)).astype(np.uint8 if dtype == "u8" else np.uint16)
         else:
