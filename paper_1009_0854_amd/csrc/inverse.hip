@@ -319,9 +319,8 @@ __device__ __forceinline__ double dev_inverse_gamma(double k, int gamma) {
   return k;
 }
 
-__device__ __forceinline__ void dev_lab(const double rgb[3], int gamma, double out[3]) {
-  double lin[3], f[3];
-  for (int c = 0; c < 3; ++c) lin[c] = dev_inverse_gamma(rgb[c], gamma);
+__device__ __forceinline__ void dev_lab_lin(const double lin[3], double out[3]) {
+  double f[3];
   for (int r = 0; r < 3; ++r) {
     const double t = (kM[r][0] * lin[0] + kM[r][1] * lin[1] + kM[r][2] * lin[2]) / kWhite[r];
     f[r] = t > kLabT0 ? cbrt(t) : kLabK * t + kLabC;
@@ -331,9 +330,14 @@ __device__ __forceinline__ void dev_lab(const double rgb[3], int gamma, double o
   out[2] = 200.0 * (f[1] - f[2]);
 }
 
-__device__ __forceinline__ void dev_luv(const double rgb[3], int gamma, double out[3]) {
-  double lin[3], xyz[3];
+__device__ __forceinline__ void dev_lab(const double rgb[3], int gamma, double out[3]) {
+  double lin[3];
   for (int c = 0; c < 3; ++c) lin[c] = dev_inverse_gamma(rgb[c], gamma);
+  dev_lab_lin(lin, out);
+}
+
+__device__ __forceinline__ void dev_luv_lin(const double lin[3], double out[3]) {
+  double xyz[3];
   for (int r = 0; r < 3; ++r) xyz[r] = kM[r][0] * lin[0] + kM[r][1] * lin[1] + kM[r][2] * lin[2];
   const double fy = xyz[1] > kLabT0 ? cbrt(xyz[1]) : kLabK * xyz[1] + kLabC;
   const double L = 116.0 * fy - 16.0;
@@ -342,6 +346,12 @@ __device__ __forceinline__ void dev_luv(const double rgb[3], int gamma, double o
   out[0] = L;
   out[1] = d > 0.0 ? 13.0 * L * (4.0 * xyz[0] / d - 4.0 * kWhite[0] / dn) : 0.0;
   out[2] = d > 0.0 ? 13.0 * L * (9.0 * xyz[1] / d - 9.0 * kWhite[1] / dn) : 0.0;
+}
+
+__device__ __forceinline__ void dev_luv(const double rgb[3], int gamma, double out[3]) {
+  double lin[3];
+  for (int c = 0; c < 3; ++c) lin[c] = dev_inverse_gamma(rgb[c], gamma);
+  dev_luv_lin(lin, out);
 }
 
 __device__ __forceinline__ void dev_hsi(const double rgb[3], double out[3]) {
@@ -417,8 +427,17 @@ __global__ __launch_bounds__(256) void k_error(KImage src, uint32_t n_px, KCoef 
     const double m[3] = {o[0], o[1], o[2]};
     double ex[3], e, d[3];
     if (k.xform == MACT_LAB || k.xform == MACT_LUV) {
-      if (k.xform == MACT_LAB) dev_lab(rgb, gamma, ex);
-      else dev_luv(rgb, gamma, ex);
+      if (src.dtype == MACT_U8) {
+        // 8-bit codes: the decoded values from the double-precision table (no pow per pixel)
+        const double lin[3] = {k_gamma_table64[gamma][(int)v[0]], k_gamma_table64[gamma][(int)v[1]],
+                               k_gamma_table64[gamma][(int)v[2]]};
+        if (k.xform == MACT_LAB) dev_lab_lin(lin, ex);
+        else dev_luv_lin(lin, ex);
+      } else if (k.xform == MACT_LAB) {
+        dev_lab(rgb, gamma, ex);
+      } else {
+        dev_luv(rgb, gamma, ex);
+      }
       e = dev_delta_e(m, ex);
       for (int c = 0; c < 3; ++c) d[c] = fabs(m[c] - ex[c]);
     } else if (k.xform == MACT_HSI) {
