@@ -450,11 +450,20 @@ __global__ __launch_bounds__(256) void k_error(KImage src, uint32_t n_px, KCoef 
       d[2] = fabs(dv);
     } else {
       dev_sct(rgb, ex);
-      double ra[3], rb[3], la[3], lb[3];
+      double ra[3], la[3], lb[3];
       dev_sct_to_rgb(m, ra);
-      dev_sct_to_rgb(ex, rb);
       dev_lab(ra, MACT_GAMMA_BT709, la);
-      dev_lab(rb, MACT_GAMMA_BT709, lb);
+      if (src.dtype == MACT_U8) {
+        // the exact triple inverts to the input itself: its L*a*b* from the decoding table
+        const double lin[3] = {k_gamma_table64[MACT_GAMMA_BT709][(int)v[0]],
+                               k_gamma_table64[MACT_GAMMA_BT709][(int)v[1]],
+                               k_gamma_table64[MACT_GAMMA_BT709][(int)v[2]]};
+        dev_lab_lin(lin, lb);
+      } else {
+        double rb[3];
+        dev_sct_to_rgb(ex, rb);
+        dev_lab(rb, MACT_GAMMA_BT709, lb);
+      }
       e = dev_delta_e(la, lb);
       for (int c = 0; c < 3; ++c) d[c] = fabs(m[c] - ex[c]);
     }
