@@ -142,9 +142,11 @@ def bench_4k(M, p, steps):
     y = torch.empty((32, 2160, 3840, 3), dtype=torch.float32, device="cuda")
     n_px = 32 * 2160 * 3840
     # fresh buffers settle like a fresh process: time_kernel's 20 warm-up steps (about 13 ms)
-    ms, med = time_kernel(lambda: M.transform(x, params=p, out=y), steps)
+    spread = {}
+    ms, med = time_kernel(lambda: M.transform(x, params=p, out=y), steps, spread=spread)
     res = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "frac_of_8TBs": 15.0 * n_px / ms / 8e9,
-           "ms": ms, "ms_median": med, "pixels": n_px}
+           "ms": ms, "ms_median": med, "ms_p10": spread["p10"], "ms_p90": spread["p90"], "pixels": n_px,
+           **batch_stats(M, x, p)}
     del x, y
     torch.cuda.empty_cache()
     return res
