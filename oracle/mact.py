@@ -31,49 +31,58 @@ def clamp01(rgb):
     return np.clip(np.asarray(rgb, dtype=np.float64), 0.0, 1.0)
 
 
-def mact_lab_f(t, p, q):
+def mact_lab_f(t, p, q, hi=None):
     """The approximated CIELAB nonlinearity: p(t)/q(t) above 0.008856 (the
     minimax rational standing in for the cube root, Sec. 3.2.2), the exact
-    linear segment at or below it."""
+    linear segment at or below it.  ``hi`` (a boolean mask like t), when
+    given, chooses the branch instead of the comparison: a test uses it to
+    evaluate a value within rounding of the threshold on either side."""
     t = np.asarray(t, dtype=np.float64)
-    hi = t > colour.LAB_T0
+    hi = t > colour.LAB_T0 if hi is None else np.asarray(hi, dtype=bool)
     ts = np.where(hi, t, 0.5)  # keep q away from any root on the unused branch
     return np.where(hi, horner(p, ts) / horner(q, ts), colour.LAB_K * t + colour.LAB_C)
 
 
-def mact_decode709(k, c_dec):
+def mact_decode709(k, c_dec, hi=None):
     """BT.709 decoding with ((k + 0.099)/1.099)^(1/0.45) replaced by the
-    polynomial ``c_dec`` (fitted on [0.081, 1]): k/4.5 below 0.081."""
+    polynomial ``c_dec`` (fitted on [0.081, 1]): k/4.5 below 0.081.  ``hi``
+    (a boolean mask like k), when given, chooses the polynomial branch in
+    place of the comparison k >= 0.081."""
     k = np.asarray(k, dtype=np.float64)
-    return np.where(k < 0.081, k / 4.5, horner(c_dec, k))
+    lo = k < 0.081 if hi is None else ~np.asarray(hi, dtype=bool)
+    return np.where(lo, k / 4.5, horner(c_dec, k))
 
 
-def mact_lab(rgb, p, q, gamma="bt709", debug=False, decode=None):
+def mact_lab(rgb, p, q, gamma="bt709", debug=False, decode=None, decode_hi=None, f_hi=None):
     """RGB -> CIELAB with the cube root replaced by p/q (Sec. 3.2).
 
     Steps: inverse gamma (BT.709 by default), RGB -> XYZ, divide by the D65
     white, approximated f, then L*, a*, b*.  With ``debug`` the three values
     f~(X/X0), f~(Y/Y0), f~(Z/Z0) are returned instead of L*a*b*.  With
     ``decode`` (polynomial coefficients) and gamma 'bt709' the decoding power
-    is replaced as well.
+    is replaced as well.  ``decode_hi`` and ``f_hi`` (boolean masks like rgb)
+    force the branch of the decoding (per input channel) and of f (per X, Y,
+    Z) instead of the comparisons with 0.081 and 0.008856.
     """
     if decode is not None and gamma == "bt709":
-        lin = mact_decode709(clamp01(rgb), decode)
+        lin = mact_decode709(clamp01(rgb), decode, decode_hi)
         t = colour.rgb_to_xyz(lin) / colour.WHITE_D65
     else:
         t = colour.lab_t(clamp01(rgb), gamma)
-    f = mact_lab_f(t, p, q)
+    f = mact_lab_f(t, p, q, f_hi)
     if debug:
         return f
     fx, fy, fz = f[..., 0], f[..., 1], f[..., 2]
     return np.stack([116.0 * fy - 16.0, 500.0 * (fx - fy), 200.0 * (fy - fz)], axis=-1)
 
 
-def mact_luv(rgb, p, q, gamma="bt709", decode=None):
+def mact_luv(rgb, p, q, gamma="bt709", decode=None, decode_hi=None, f_hi=None):
     """RGB -> CIE 1976 L*u*v* with the cube root of L* replaced by p/q (the
-    CIELAB nonlinearity, Sec. 3.2.2); u', v' by their exact divisions."""
+    CIELAB nonlinearity, Sec. 3.2.2); u', v' by their exact divisions.
+    ``decode_hi`` (a mask like rgb) and ``f_hi`` (a mask over pixels, for
+    Y / Yn) force branches as in ``mact_lab``."""
     if decode is not None and gamma == "bt709":
-        lin = mact_decode709(clamp01(rgb), decode)
+        lin = mact_decode709(clamp01(rgb), decode, decode_hi)
     else:
         lin = colour.inverse_gamma(clamp01(rgb), gamma)
     xyz = colour.rgb_to_xyz(lin)
@@ -84,7 +93,7 @@ def mact_luv(rgb, p, q, gamma="bt709", decode=None):
     d = X + 15.0 * Y + 3.0 * Z
     pos = d > 0
     ds = np.where(pos, d, 1.0)
-    L = 116.0 * mact_lab_f(Y / Yn, p, q) - 16.0
+    L = 116.0 * mact_lab_f(Y / Yn, p, q, f_hi) - 16.0
     u = np.where(pos, 13.0 * L * (4.0 * X / ds - un), 0.0)
     v = np.where(pos, 13.0 * L * (9.0 * Y / ds - vn), 0.0)
     return np.stack([L, u, v], axis=-1)
@@ -111,7 +120,7 @@ def mact_hsi(rgb, c_atan):
     return np.stack([H, hsi[..., 1], hsi[..., 2]], axis=-1)
 
 
-def mact_sct(rgb, c_asin2, c_acos, c_atan, c_atanc):
+def mact_sct(rgb, c_asin2, c_acos, c_atan, c_atanc, upper=None, g_lt_r=None):
     """RGB -> SCT with the inverse trigonometric functions replaced by
     polynomials (Sec. 3.4.2, 3.4.3).
 
@@ -123,6 +132,10 @@ def mact_sct(rgb, c_asin2, c_acos, c_atan, c_atanc):
     ("c_atan"); for 0 < R <= G the polynomial of g, pi/2 - arctan(R/G)
     ("c_atanc"); pi/2 for R = 0 < G; 0 for R = G = 0.
     L = 0 gives (0, 0, 0).
+    ``upper`` and ``g_lt_r`` (boolean masks over pixels), when given, choose
+    the branch of angle A (the arcsin form) and of angle B (f of G/R) instead
+    of the comparisons, for evaluating a pixel within rounding of a branch
+    plane on either side; g_lt_r applies where R and G are both positive.
     """
     rgb = clamp01(rgb)
     R, G, B = rgb[..., 0], rgb[..., 1], rgb[..., 2]
@@ -130,13 +143,13 @@ def mact_sct(rgb, c_asin2, c_acos, c_atan, c_atanc):
     L = np.sqrt(rg2 + B * B)
     pos = L > 0
     Ls = np.where(pos, L, 1.0)
-    upper = 3.0 * B * B >= rg2
+    upper = 3.0 * B * B >= rg2 if upper is None else np.asarray(upper, dtype=bool)
     y = np.sqrt(rg2 / (Ls * (Ls + B)))
     A = np.where(upper, horner(c_asin2, y), horner(c_acos, B / Ls))
     A = np.where(pos, A, 0.0)
-    gr = G < R
     r_pos = R > 0
     g_pos = G > 0
+    gr = G < R if g_lt_r is None else np.where(r_pos & g_pos, np.asarray(g_lt_r, dtype=bool), G < R)
     Bf = horner(c_atan, G / np.where(r_pos, R, 1.0))
     Bg = horner(c_atanc, R / np.where(g_pos, G, 1.0))
     Bang = np.where(gr, Bf, np.where(r_pos, Bg, np.where(g_pos, 0.5 * np.pi, 0.0)))

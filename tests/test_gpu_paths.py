@@ -66,14 +66,8 @@ def test_hwc_fast_equals_general(M, xform, dtype, shape):
     if dtype == "f16":
         # and against the oracle
         xs = np.clip(x.float().cpu().numpy().astype(np.float64), 0, 1).reshape(-1, 3)
-        ref = P.oracle(xform, xs, P.coeffs(p), gamma=gammas[0])
         got = M.transform(x, params=p, gamma=gammas[0]).reshape(-1, 3).cpu().numpy()
-        err = np.abs(got - ref) / P.SCALE[xform]
-        if xform == 2:
-            R, G, B = xs[:, 0], xs[:, 1], xs[:, 2]
-            near = (np.abs(3 * B * B - (R * R + G * G)) <= 1e-6 * (xs * xs).sum(1)) | (np.abs(G - R) <= 1e-6)
-            err = err[~near]
-        assert err.max() <= P.REL
+        P.assert_parity_ties(xform, got, xs, P.coeffs(p), gamma=gammas[0])
 
 
 @pytest.mark.parametrize("shape", SHAPES + [(33, 31)])

@@ -38,6 +38,33 @@ def test_bt709_inverse_gamma_values():
     assert abs(lo - hi) < 1e-4
 
 
+def test_srgb_transfer_function_values():
+    # IEC 61966-2-1 (the sRGB option): decoding k/12.92 up to 0.04045, ((k + 0.055)/1.055)^2.4 above.
+    # Pins that do not restate the formula:
+    #  - the two decoding branches meet at the breakpoint 0.04045 (to 2.3e-9), and the two
+    #    encoding branches at its image 0.0031308;
+    #  - tabulated values of the standard's curve: code 0.5 decodes to 0.2140411, the 8-bit code 128
+    #    to 0.2158605, and 18% linear grey encodes to 0.4613561;
+    #  - 8-bit mid grey (128, 128, 128) has L* = 53.585 (Y = 0.2158605 relative to white).
+    # A consistent wrong exponent pair (2.2 and 1/2.2) passes a round trip but none of these.
+    lo = colour.inverse_gamma(np.array([0.04045 - 1e-12]), "srgb")[0]
+    hi = colour.inverse_gamma(np.array([0.04045 + 1e-12]), "srgb")[0]
+    assert abs(lo - hi) < 1e-8
+    assert abs(lo - 0.0031308) < 1e-7
+    elo = colour.encode_gamma(np.array([0.0031308 - 1e-12]), "srgb")[0]
+    ehi = colour.encode_gamma(np.array([0.0031308 + 1e-12]), "srgb")[0]
+    assert abs(elo - ehi) < 1e-7 and abs(elo - 0.04045) < 1e-6
+    np.testing.assert_allclose(colour.inverse_gamma(np.array([0.5, 128 / 255.0, 1.0, 0.0]), "srgb"),
+                               [0.2140411, 0.2158605, 1.0, 0.0], atol=1e-7)
+    np.testing.assert_allclose(colour.encode_gamma(np.array([0.18, 0.2140411405]), "srgb"), [0.4613561, 0.5],
+                               atol=1e-7)
+    lab = colour.rgb_to_lab(np.full(3, 128 / 255.0), gamma="srgb")
+    np.testing.assert_allclose(lab, [53.585, 0.0, 0.0], atol=1e-3)
+    # the linear segment below the breakpoint: slope 1/12.92 through the origin
+    np.testing.assert_allclose(colour.inverse_gamma(np.array([0.02, -0.01]), "srgb"),
+                               [0.02 / 12.92, -0.01 / 12.92], rtol=1e-15)
+
+
 def _cbrt_counts(v8):
     t = colour.lab_t(v8 / 255.0)
     return (t > colour.LAB_T0).sum(axis=0)

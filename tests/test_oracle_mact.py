@@ -96,3 +96,41 @@ def test_clamping_of_float_inputs(fits):
     fc = fits["cbrt"]
     x = np.array([[-0.5, 1.5, 0.3]])
     np.testing.assert_array_equal(mact.mact_lab(x, fc.p, fc.q), mact.mact_lab(np.array([[0, 1, 0.3]]), fc.p, fc.q))
+
+
+def test_forced_branches_and_the_tie_rule(fits):
+    # The forced-branch options evaluate the other side of a boundary; the parity tie rule accepts a
+    # value from the other side only for a pixel within 1e-6 of that boundary, and rejects it elsewhere.
+    from tests import parity as P
+    co = {"asin2": fits["asin2"].p, "acos": fits["acos"].p, "atan": fits["atan"].p, "atanc": fits["atanc"].p}
+    # on the angle-A plane 3 B^2 = R^2 + G^2 (B/L = 1/2) and on G = R
+    on_a = np.array([[0.3, 0.4, np.sqrt(0.25 / 3.0)]])
+    on_b = np.array([[0.6, 0.6 * (1 + 1e-7), 0.1]])
+    for x, key in ((on_a, "upper"), (on_b, "g_lt_r")):
+        own = mact.mact_sct(x, co["asin2"], co["acos"], co["atan"], co["atanc"])
+        sides = [mact.mact_sct(x, co["asin2"], co["acos"], co["atan"], co["atanc"], **{key: np.array([v])})
+                 for v in (False, True)]
+        # the oracle's own value is one side; the other side approximates the same angle, to the
+        # fits' errors, but differs beyond the parity bar
+        assert any(np.array_equal(own, s) for s in sides)
+        other = sides[1] if np.array_equal(own, sides[0]) else sides[0]
+        assert np.abs(other - own).max() < 1e-4
+        assert np.any(np.abs(other - own)[0] / P.SCALE[2] > P.REL)
+        assert P.assert_parity_ties(2, other, x, co) == 1
+        far = x * np.array([1.0, 1.1, 1.0])  # off both planes
+        wrong = mact.mact_sct(far, co["asin2"], co["acos"], co["atan"], co["atanc"]) + other - own
+        with pytest.raises(AssertionError):
+            P.assert_parity_ties(2, wrong, far, co)
+    # the BT.709 decoding breakpoint: a channel at 0.081 on the linear side of the polynomial
+    cb = fits["cbrt"]
+    dec = remez.remez(lambda k: ((k + 0.099) / 1.099) ** (1 / 0.45), 7, 0, 0.081, 1.0).p
+    x = np.array([[0.081, 0.5, 0.9]])
+    own = mact.mact_lab(x, cb.p, cb.q, decode=dec)
+    other = mact.mact_lab(x, cb.p, cb.q, decode=dec, decode_hi=np.array([[False, True, True]]))
+    assert np.abs(other - own).max() / 116.0 > P.REL
+    assert P.assert_parity_ties(0, other, x, {"p": cb.p, "q": cb.q}, decode=dec) == 1
+    with pytest.raises(AssertionError):
+        P.assert_parity_ties(0, other, x + np.array([[0.01, 0, 0]]), {"p": cb.p, "q": cb.q}, decode=dec)
+    # forcing the side a value is on already changes nothing
+    same = mact.mact_lab(x, cb.p, cb.q, decode=dec, decode_hi=x >= 0.081, f_hi=np.ones((1, 3), bool))
+    np.testing.assert_array_equal(same, own)
