@@ -428,7 +428,9 @@ typedef struct mact_server_config {
   int32_t max_batch;       /* most requests in one launch */
   int32_t compute_streams; /* concurrent batches in flight (1..8) */
   int32_t max_queue;       /* submitted but not admitted requests before MACT_E_BUSY */
-  int32_t reserved;
+  int32_t fail_request;    /* fault injection for tests of the error path: the request with this id is
+                              rejected when its batch is built, as if its descriptors were invalid,
+                              and completes with MACT_E_INVALID; 0 in normal use */
   mact_params params[4];   /* per transform: LAB, HSI, SCT, LUV */
 } mact_server_config;
 
@@ -447,6 +449,7 @@ typedef struct mact_server_stats {
   double p50_ms, p99_ms, mean_ms; /* submit -> output copied back, completed requests */
   double mean_batch;              /* requests per launch */
   double device_busy_ms;          /* sum of batch kernel times */
+  int64_t failed;                 /* requests completed with an error status */
 } mact_server_stats;
 
 typedef struct mact_server mact_server;
@@ -456,11 +459,19 @@ mact_status mact_server_create(const mact_server_config* cfg, mact_server** srv)
    are already waiting (nothing is queued); MACT_E_INVALID if it could never fit
    the arena or its fields are out of range. */
 mact_status mact_server_submit(mact_server* srv, const mact_request* req, int64_t* id);
-/* *done = 1 once request `id` has completed (its host_out is written). */
+/* *done = 1 once request `id` has completed.  A request completes either with
+   its host_out written (MACT_OK) or with an error: its descriptors were
+   rejected, or a copy, the launch or an event of its batch reported a HIP
+   error.  For a request completed with an error, poll sets *done = 1 and
+   returns that status (the detail in mact_last_error); host_out is then
+   unspecified. */
 mact_status mact_server_poll(mact_server* srv, int64_t id, int32_t* done);
-/* Block until request `id` completes or timeout_ms passes (MACT_E_BUSY). */
+/* Block until request `id` completes or timeout_ms passes (MACT_E_BUSY).
+   Returns the request's status: MACT_OK, or the error it completed with
+   (MACT_E_INVALID, MACT_E_DEVICE) as poll reports it. */
 mact_status mact_server_wait(mact_server* srv, int64_t id, int32_t timeout_ms);
-/* Latency of a completed request in milliseconds (submit -> output on host). */
+/* Latency of a completed request in milliseconds (submit -> output on host);
+   the request's error status if it completed with one. */
 mact_status mact_server_latency(mact_server* srv, int64_t id, double* ms);
 mact_status mact_server_stats_get(mact_server* srv, mact_server_stats* st);
 /* Drains every queued request, stops the scheduler, frees the arena. */

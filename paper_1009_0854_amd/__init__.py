@@ -368,15 +368,33 @@ def batch_run(params, ins, outs, layouts=None, gammas=None, out_layouts=None, tu
 
 # ---------------------------------------------------------------- serving
 
+def check_request_tensors(host_in, host_out):
+    """The served form's buffers: contiguous (H, W, 3) host tensors of one
+    shape (the engine copies H W 3 elements into and out of them); raises
+    ValueError otherwise."""
+    for name, t in (("host_in", host_in), ("host_out", host_out)):
+        if t.is_cuda:
+            raise ValueError("Server.submit: %s must be a host tensor" % name)
+        if t.dim() != 3 or t.shape[-1] != 3:
+            raise ValueError("Server.submit: %s must be (H, W, 3), got %s" % (name, tuple(t.shape)))
+        if not t.is_contiguous():
+            raise ValueError("Server.submit: %s must be contiguous" % name)
+    if tuple(host_out.shape) != tuple(host_in.shape):
+        raise ValueError("Server.submit: host_out shape %s differs from host_in shape %s"
+                         % (tuple(host_out.shape), tuple(host_in.shape)))
+
+
 class Server:
     """Continuous-batching engine (mact_server_*)."""
 
-    def __init__(self, arena_bytes=1 << 30, max_batch=64, compute_streams=2, max_queue=1 << 16, params=None):
+    def __init__(self, arena_bytes=1 << 30, max_batch=64, compute_streams=2, max_queue=1 << 16, params=None,
+                 fail_request=0):
         cfg = ServerConfig()
         cfg.arena_bytes = int(arena_bytes)
         cfg.max_batch = int(max_batch)
         cfg.compute_streams = int(compute_streams)
         cfg.max_queue = int(max_queue)
+        cfg.fail_request = int(fail_request)  # fault injection for tests of the error path; 0 = off
         for i, x in enumerate(("lab", "hsi", "sct", "luv")):
             cfg.params[i] = (params or {}).get(x) or default_params(x)
         h = ctypes.c_void_p()
@@ -385,8 +403,10 @@ class Server:
         self._keep = {}
 
     def submit(self, host_in, host_out, xform="lab", gamma="bt709"):
-        """Queue one packed HWC image held in pinned host tensors; returns its id."""
-        torch = _torch()
+        """Queue one packed HWC image held in pinned host tensors; returns its id.
+        Both tensors must be contiguous (H, W, 3) host tensors of the same shape:
+        the engine copies H W 3 elements in and out of them."""
+        check_request_tensors(host_in, host_out)
         r = Request()
         r.host_in = host_in.data_ptr()
         r.host_out = host_out.data_ptr()
@@ -398,7 +418,6 @@ class Server:
         i = ctypes.c_int64()
         A.check(lib().mact_server_submit(self._h, ctypes.byref(r), ctypes.byref(i)))
         self._keep[i.value] = (host_in, host_out)
-        del torch
         return i.value
 
     def poll(self, rid):
@@ -407,8 +426,12 @@ class Server:
         return bool(d.value)
 
     def wait(self, rid, timeout_ms=60000):
-        A.check(lib().mact_server_wait(self._h, int(rid), int(timeout_ms)))
-        self._keep.pop(rid, None)
+        """Blocks until request `rid` completes; raises MactError with the
+        request's status if it completed with an error (or on a time-out)."""
+        st = lib().mact_server_wait(self._h, int(rid), int(timeout_ms))
+        if st != E_BUSY:
+            self._keep.pop(rid, None)
+        A.check(st)
 
     def latency_ms(self, rid):
         v = ctypes.c_double()

@@ -55,7 +55,7 @@ class Tune(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("arena_bytes", c_size_t), ("max_batch", c_int32), ("compute_streams", c_int32),
-                ("max_queue", c_int32), ("reserved", c_int32), ("params", Params * 4)]
+                ("max_queue", c_int32), ("fail_request", c_int32), ("params", Params * 4)]
 
 
 class Request(ctypes.Structure):
@@ -66,7 +66,7 @@ class Request(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", c_int64), ("completed", c_int64), ("rejected", c_int64), ("batches", c_int64),
                 ("p50_ms", c_double), ("p99_ms", c_double), ("mean_ms", c_double), ("mean_batch", c_double),
-                ("device_busy_ms", c_double)]
+                ("device_busy_ms", c_double), ("failed", c_int64)]
 
 
 class ErrorStats(ctypes.Structure):

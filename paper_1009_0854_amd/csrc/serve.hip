@@ -23,6 +23,14 @@
 //      landed (an event per request), not when its whole batch has.
 // The coefficient table of the four transforms stays resident.
 //
+// Errors: every HIP call the scheduler makes is checked.  A request whose
+// descriptors are rejected, whose copy or launch cannot be enqueued, or whose
+// events report a device error completes at once with that status (and its
+// arena space returned); poll and wait return the status, so a failure never
+// shows up as a request that is done with its output unwritten, nor as a wait
+// that times out.  Only hipSuccess and hipErrorNotReady of an event query
+// count as "complete" and "pending".
+//
 // Locking: the scheduler owns the request pipeline and makes its HIP calls
 // without holding any lock that callers take.  Callers meet it at three small
 // locks: `mu_in` (incoming requests and the id map), `mu_done` (completion
@@ -35,6 +43,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdarg>
 #include <sys/prctl.h>
 #include <cstring>
 #include <deque>
@@ -102,8 +111,11 @@ struct Req {
   int64_t id = 0;
   mact_request r{};
   size_t in_bytes = 0, out_bytes = 0, in_off = 0, out_off = 0;
+  bool placed = false;  // holds arena space
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  Clock::time_point t_submit, t_done;  // t_done is written before done is set
+  Clock::time_point t_submit, t_done;  // t_done, status and err are written before done is set
+  mact_status status = MACT_OK;
+  char err[256] = "";
   std::atomic<bool> done{false};
 };
 
@@ -146,7 +158,7 @@ struct mact_server {
   std::condition_variable cv_done;
   std::mutex mu_stats;  // lat_ms, completed, batches, batched_reqs, busy_ms
   std::vector<double> lat_ms;
-  int64_t completed = 0, batches = 0, batched_reqs = 0;
+  int64_t completed = 0, failed = 0, batches = 0, batched_reqs = 0;
   double busy_ms = 0.0;
 
   // the scheduler's own
@@ -158,6 +170,8 @@ struct mact_server {
   std::thread th;
 
   void loop();
+  void release(Req* q);
+  void fail_req(Req* q, mact_status st, const char* fmt, ...);
   hipEvent_t get_event();
   bool take_incoming();
   bool admit();
@@ -167,6 +181,7 @@ struct mact_server {
   bool finish_requests();
 };
 
+// nullptr if the pool is empty and a new event cannot be created
 hipEvent_t mact_server::get_event() {
   if (!ev_pool.empty()) {
     hipEvent_t e = ev_pool.back();
@@ -174,8 +189,41 @@ hipEvent_t mact_server::get_event() {
     return e;
   }
   hipEvent_t e = nullptr;
-  (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
   return e;
+}
+
+// Returns the request's arena space and events.
+void mact_server::release(Req* q) {
+  if (q->placed) {
+    arena->release(q->in_off, q->in_bytes);
+    arena->release(q->out_off, q->out_bytes);
+    q->placed = false;
+  }
+  if (q->ev_in) ev_pool.push_back(q->ev_in);
+  if (q->ev_out) ev_pool.push_back(q->ev_out);
+  q->ev_in = q->ev_out = nullptr;
+}
+
+// Completes request q with an error: its status and detail are what poll and
+// wait report.  The caller has removed q from the scheduler's lists.
+void mact_server::fail_req(Req* q, mact_status st, const char* fmt, ...) {
+  release(q);
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(q->err, sizeof q->err, fmt, ap);
+  va_end(ap);
+  q->status = st;
+  q->t_done = Clock::now();
+  {
+    std::lock_guard<std::mutex> g(mu_done);
+    q->done.store(true);
+  }
+  {
+    std::lock_guard<std::mutex> g(mu_stats);
+    ++failed;
+  }
+  cv_done.notify_all();
 }
 
 bool mact_server::take_incoming() {
@@ -200,32 +248,52 @@ bool mact_server::admit() {
     waiting.fetch_sub(1);
     q->in_off = in_off;
     q->out_off = out_off;
+    q->placed = true;
+    any = true;
     q->ev_in = get_event();
     q->ev_out = get_event();
-    (void)hipMemcpyAsync(d_arena + in_off, q->r.host_in, q->in_bytes, hipMemcpyHostToDevice, copy_stream);
-    (void)hipEventRecord(q->ev_in, copy_stream);
+    if (!q->ev_in || !q->ev_out) {
+      fail_req(q, MACT_E_DEVICE, "request %lld: no event for its copies", (long long)q->id);
+      continue;
+    }
+    hipError_t e = hipMemcpyAsync(d_arena + in_off, q->r.host_in, q->in_bytes, hipMemcpyHostToDevice, copy_stream);
+    if (e == hipSuccess) e = hipEventRecord(q->ev_in, copy_stream);
+    if (e != hipSuccess) {
+      fail_req(q, MACT_E_DEVICE, "request %lld: input copy: %s", (long long)q->id, hipGetErrorString(e));
+      continue;
+    }
     copying.push_back(q);
-    any = true;
   }
   return any;
 }
 
 void mact_server::poll_copies() {
-  // copies complete in admission order (one copy stream): stop at the first pending one
+  // copies complete in admission order (one copy stream): stop at the first pending one; a
+  // device error fails the request instead of leaving it pending for ever
   size_t i = 0;
-  while (i < copying.size() && hipEventQuery(copying[i]->ev_in) == hipSuccess) ++i;
-  ready.insert(ready.end(), copying.begin(), copying.begin() + i);
+  while (i < copying.size()) {
+    Req* q = copying[i];
+    const hipError_t e = hipEventQuery(q->ev_in);
+    if (e == hipErrorNotReady) break;
+    if (e == hipSuccess) {
+      ready.push_back(q);
+    } else {
+      fail_req(q, MACT_E_DEVICE, "request %lld: input copy: %s", (long long)q->id, hipGetErrorString(e));
+    }
+    ++i;
+  }
   copying.erase(copying.begin(), copying.begin() + i);
 }
 
 bool mact_server::launch(Slot& s) {
   if (ready.empty()) return false;
   const size_t n = std::min<size_t>(ready.size(), (size_t)cfg.max_batch);
-  s.reqs.assign(ready.begin(), ready.begin() + n);  // admission order is arrival order
+  std::vector<Req*> take(ready.begin(), ready.begin() + n);  // admission order is arrival order
   ready.erase(ready.begin(), ready.begin() + n);
+  s.reqs.clear();
   std::vector<BDesc> descs;
   descs.reserve(n);
-  for (Req* q : s.reqs) {
+  for (Req* q : take) {
     mact_image in{}, out{};
     in.data = d_arena + q->in_off;
     in.dtype = q->r.in_dtype;
@@ -239,41 +307,70 @@ bool mact_server::launch(Slot& s) {
     out.width = q->r.width;
     out.height = q->r.height;
     int d = 5;
-    (void)make_batch_descs(cfg.params[q->r.xform], &in, &out, q->r.xform, &descs, &d, "mact_server");
+    const size_t before = descs.size();
+    mact_status st = cfg.fail_request != 0 && q->id == cfg.fail_request
+                         ? fail(MACT_E_INVALID, "descriptors rejected (the configuration's fail_request)")
+                         : make_batch_descs(cfg.params[q->r.xform], &in, &out, q->r.xform, &descs, &d, "mact_server");
+    if (st != MACT_OK) {
+      descs.resize(before);
+      fail_req(q, st, "request %lld: %s", (long long)q->id, mact_last_error());
+      clear_error();
+      continue;
+    }
+    s.reqs.push_back(q);
   }
+  if (s.reqs.empty()) return true;  // every request of the batch failed: progress, the slot stays free
   std::vector<uint32_t> ts;
   const uint32_t total = build_tiles(descs, (uint32_t)tune.tile, &ts);
   const size_t db = descs.size() * sizeof(BDesc), tb = ts.size() * sizeof(uint32_t);
   std::memcpy(s.h_buf, descs.data(), db);
   std::memcpy(s.h_buf + db, ts.data(), tb);
-  (void)hipMemcpyAsync(s.d_buf, s.h_buf, db + tb, hipMemcpyHostToDevice, s.stream);
-  (void)hipEventRecord(s.ev_k0, s.stream);
-  (void)launch_batch_kernel(reinterpret_cast<const BDesc*>(s.d_buf), d_coefs,
+  hipError_t e = hipMemcpyAsync(s.d_buf, s.h_buf, db + tb, hipMemcpyHostToDevice, s.stream);
+  if (e == hipSuccess) e = hipEventRecord(s.ev_k0, s.stream);
+  if (e == hipSuccess)
+    e = launch_batch_kernel(reinterpret_cast<const BDesc*>(s.d_buf), d_coefs,
                             reinterpret_cast<const uint32_t*>(s.d_buf + db), (int32_t)descs.size(), total, tune, deg,
                             s.stream);
-  (void)hipEventRecord(s.ev_k1, s.stream);
-  (void)hipStreamWaitEvent(d2h_stream, s.ev_k1, 0);
+  if (e == hipSuccess) e = hipEventRecord(s.ev_k1, s.stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(d2h_stream, s.ev_k1, 0);
+  if (e != hipSuccess) {
+    // the batch may or may not have been enqueued: wait for the slot's stream before its
+    // requests' arena space can be handed out again
+    (void)hipStreamSynchronize(s.stream);
+    for (Req* q : s.reqs) fail_req(q, MACT_E_DEVICE, "request %lld: batch launch: %s", (long long)q->id, hipGetErrorString(e));
+    s.reqs.clear();
+    return true;
+  }
   std::vector<Req*> by_size(s.reqs);
   std::stable_sort(by_size.begin(), by_size.end(), [](const Req* a, const Req* b) { return a->out_bytes < b->out_bytes; });
   for (Req* q : by_size) {
-    (void)hipMemcpyAsync(q->r.host_out, d_arena + q->out_off, q->out_bytes, hipMemcpyDeviceToHost, d2h_stream);
-    (void)hipEventRecord(q->ev_out, d2h_stream);
+    e = hipMemcpyAsync(q->r.host_out, d_arena + q->out_off, q->out_bytes, hipMemcpyDeviceToHost, d2h_stream);
+    if (e == hipSuccess) e = hipEventRecord(q->ev_out, d2h_stream);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(d2h_stream);
+      fail_req(q, MACT_E_DEVICE, "request %lld: output copy: %s", (long long)q->id, hipGetErrorString(e));
+      continue;
+    }
     draining.push_back(q);
   }
   s.busy = true;
   s.t_launch = Clock::now();
   std::lock_guard<std::mutex> g(mu_stats);
   ++batches;
-  batched_reqs += (int64_t)n;
+  batched_reqs += (int64_t)s.reqs.size();
   return true;
 }
 
 bool mact_server::finish_slots() {
   bool any = false;
   for (Slot& s : slots) {
-    if (!s.busy || hipEventQuery(s.ev_k1) != hipSuccess) continue;
+    if (!s.busy) continue;
+    const hipError_t e = hipEventQuery(s.ev_k1);
+    if (e == hipErrorNotReady) continue;
+    // on a device error the slot is freed as well: its requests' output events report the
+    // error and fail them in finish_requests
     float kms = 0.0f;
-    if (hipEventElapsedTime(&kms, s.ev_k0, s.ev_k1) == hipSuccess) {
+    if (e == hipSuccess && hipEventElapsedTime(&kms, s.ev_k0, s.ev_k1) == hipSuccess) {
       std::lock_guard<std::mutex> g(mu_stats);
       busy_ms += kms;
     }
@@ -286,28 +383,31 @@ bool mact_server::finish_slots() {
 
 bool mact_server::finish_requests() {
   std::vector<double> lat;
+  bool any = false;
   const auto now = Clock::now();
   for (size_t i = 0; i < draining.size();) {
     Req* q = draining[i];
-    if (hipEventQuery(q->ev_out) != hipSuccess) {
+    const hipError_t e = hipEventQuery(q->ev_out);
+    if (e == hipErrorNotReady) {
       ++i;
       continue;
     }
-    arena->release(q->in_off, q->in_bytes);
-    arena->release(q->out_off, q->out_bytes);
-    ev_pool.push_back(q->ev_in);
-    ev_pool.push_back(q->ev_out);
-    q->ev_in = q->ev_out = nullptr;
+    draining[i] = draining.back();
+    draining.pop_back();
+    any = true;
+    if (e != hipSuccess) {
+      fail_req(q, MACT_E_DEVICE, "request %lld: output copy: %s", (long long)q->id, hipGetErrorString(e));
+      continue;
+    }
+    release(q);
     q->t_done = now;
     lat.push_back(std::chrono::duration<double, std::milli>(q->t_done - q->t_submit).count());
     {
       std::lock_guard<std::mutex> g(mu_done);  // a waiter checks done under this lock
       q->done.store(true);
     }
-    draining[i] = draining.back();
-    draining.pop_back();
   }
-  if (lat.empty()) return false;
+  if (lat.empty()) return any;
   {
     std::lock_guard<std::mutex> g(mu_stats);
     lat_ms.insert(lat_ms.end(), lat.begin(), lat.end());
@@ -437,6 +537,7 @@ extern "C" mact_status mact_server_create(const mact_server_config* cfg, mact_se
   if (cfg->compute_streams < 1 || cfg->compute_streams > 8)
     return fail(MACT_E_INVALID, "mact_server_create: compute_streams %d outside 1..8", cfg->compute_streams);
   if (cfg->max_queue < 1) return fail(MACT_E_INVALID, "mact_server_create: max_queue %d", cfg->max_queue);
+  if (cfg->fail_request < 0) return fail(MACT_E_INVALID, "mact_server_create: fail_request %d < 0", cfg->fail_request);
   for (int x = 0; x < 4; ++x) {
     if (cfg->params[x].xform != x)
       return fail(MACT_E_INVALID, "mact_server_create: params[%d].xform must be %d", x, x);
@@ -533,6 +634,7 @@ extern "C" mact_status mact_server_poll(mact_server* s, int64_t id, int32_t* don
   Req* q = find_req(s, id);
   if (!q) return fail(MACT_E_INVALID, "mact_server_poll: unknown request %lld", (long long)id);
   *done = q->done.load() ? 1 : 0;
+  if (*done && q->status != MACT_OK) return fail(q->status, "mact_server_poll: %s", q->err);
   return MACT_OK;
 }
 
@@ -544,6 +646,7 @@ extern "C" mact_status mact_server_wait(mact_server* s, int64_t id, int32_t time
   std::unique_lock<std::mutex> lk(s->mu_done);
   if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), [q] { return q->done.load(); }))
     return fail(MACT_E_BUSY, "mact_server_wait: request %lld not done after %d ms", (long long)id, timeout_ms);
+  if (q->status != MACT_OK) return fail(q->status, "mact_server_wait: %s", q->err);
   return MACT_OK;
 }
 
@@ -553,6 +656,7 @@ extern "C" mact_status mact_server_latency(mact_server* s, int64_t id, double* m
   Req* q = find_req(s, id);
   if (!q) return fail(MACT_E_INVALID, "mact_server_latency: unknown request %lld", (long long)id);
   if (!q->done.load()) return fail(MACT_E_BUSY, "mact_server_latency: request %lld not done", (long long)id);
+  if (q->status != MACT_OK) return fail(q->status, "mact_server_latency: %s", q->err);
   *ms = std::chrono::duration<double, std::milli>(q->t_done - q->t_submit).count();
   return MACT_OK;
 }
@@ -568,6 +672,7 @@ extern "C" mact_status mact_server_stats_get(mact_server* s, mact_server_stats* 
   }
   std::lock_guard<std::mutex> g(s->mu_stats);
   st->completed = s->completed;
+  st->failed = s->failed;
   st->batches = s->batches;
   st->mean_batch = s->batches ? (double)s->batched_reqs / s->batches : 0.0;
   st->device_busy_ms = s->busy_ms;

@@ -46,18 +46,20 @@ def test_every_declared_symbol_is_exported(M):
 def test_struct_layouts_match_the_header(M, tmp_path):
     from paper_1009_0854_amd import _abi
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mact.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mact.h"\nint main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
                    "sizeof(mact_approx), sizeof(mact_image), sizeof(mact_params), sizeof(mact_tune),"
                    "sizeof(mact_server_config), sizeof(mact_request), sizeof(mact_server_stats),"
                    "offsetof(mact_approx, eps), offsetof(mact_image, gamma), offsetof(mact_server_config, params),"
-                   "sizeof(mact_error), offsetof(mact_error, max_abs));return 0;}\n")
+                   "sizeof(mact_error), offsetof(mact_error, max_abs), offsetof(mact_server_config, fail_request),"
+                   "offsetof(mact_server_stats, failed));return 0;}\n")
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(_abi.Approx), ctypes.sizeof(_abi.Image), ctypes.sizeof(_abi.Params), ctypes.sizeof(_abi.Tune),
             ctypes.sizeof(_abi.ServerConfig), ctypes.sizeof(_abi.Request), ctypes.sizeof(_abi.ServerStats),
             _abi.Approx.eps.offset, _abi.Image.gamma.offset, _abi.ServerConfig.params.offset,
-            ctypes.sizeof(_abi.ErrorStats), _abi.ErrorStats.max_abs.offset]
+            ctypes.sizeof(_abi.ErrorStats), _abi.ErrorStats.max_abs.offset, _abi.ServerConfig.fail_request.offset,
+            _abi.ServerStats.failed.offset]
     assert got == want
 
 
@@ -358,6 +360,31 @@ def test_batch_and_server_validation_without_gpu(M):
     bad = A.ServerConfig.from_buffer_copy(cfg)
     bad.params[1] = M.default_params(0)
     assert L.mact_server_create(ctypes.byref(bad), ctypes.byref(h)) == A.E_INVALID
+    bad = A.ServerConfig.from_buffer_copy(cfg)
+    bad.fail_request = -1
+    assert L.mact_server_create(ctypes.byref(bad), ctypes.byref(h)) == A.E_INVALID
+
+
+def test_server_submit_refuses_mismatched_host_tensors(M):
+    # the engine copies H W 3 elements into and out of the two host tensors, so the binding
+    # refuses anything but two contiguous (H, W, 3) host tensors of one shape
+    torch = pytest.importorskip("torch")
+    x = torch.zeros((4, 5, 3), dtype=torch.uint8)
+    y = torch.zeros((4, 5, 3), dtype=torch.float32)
+    M.check_request_tensors(x, y)
+    bad = [
+        (x, torch.zeros((4, 4, 3), dtype=torch.float32)),           # smaller output
+        (x, torch.zeros((5, 4, 3), dtype=torch.float32)),           # same size, other shape
+        (torch.zeros((3, 4, 5), dtype=torch.uint8), torch.zeros((3, 4, 5))),  # CHW
+        (x.reshape(20, 3), y.reshape(20, 3)),                       # not (H, W, 3)
+        (torch.zeros((4, 6, 3), dtype=torch.uint8)[:, :5], y),      # strided input
+        (x, torch.zeros((4, 6, 3))[:, :5]),                         # strided output
+        (x, torch.zeros((4, 5, 3, 1))[..., 0]),                     # a view that happens to be fine
+    ]
+    for k, (a, b) in enumerate(bad[:-1]):
+        with pytest.raises(ValueError):
+            M.check_request_tensors(a, b)
+    M.check_request_tensors(*bad[-1])
 
 
 def test_fast_division_method():

@@ -143,3 +143,70 @@ def test_destroy_drains_queued_requests(M):
     srv.close()
     for x, y, xf, gm in reqs:
         assert torch.equal(y, _plain(M, x, xf, gm, y.dtype))
+
+
+def test_c5_sized_requests_against_plain_and_oracle(M):
+    # requests of the served workload's sizes (256 x 256 to 3840 x 2160, 8-bit or float16, all
+    # three transforms) mixed with small ones: every output equals the plain path bitwise, and
+    # sampled pixels of each equal the oracle to the parity bar (float inputs near a branch plane
+    # may take either side)
+    from tests import parity as P
+    g = synth.rng(60)
+    shapes = [(2160, 3840, "u8", 0), (2160, 3840, "f16", 2), (256, 256, "u8", 1), (1080, 1920, "f16", 0),
+              (1500, 2000, "u8", 2), (720, 1280, "f16", 1), (31, 45, "u8", 0), (64, 17, "f16", 2), (300, 257, "u8", 1)]
+    reqs = []
+    for h, w, kind, xf in shapes:
+        if kind == "u8":
+            x = torch.from_numpy(g.integers(0, 256, (h, w, 3), dtype=np.uint8)).pin_memory()
+            gm = "bt709"
+        else:
+            x = torch.from_numpy(g.random((h, w, 3)).astype(np.float16)).pin_memory()
+            gm = "none"
+        reqs.append((x, torch.empty((h, w, 3), dtype=torch.float32).pin_memory(), xf, gm))
+    srv = M.Server(arena_bytes=1 << 30, max_batch=64, compute_streams=2)
+    ids = [srv.submit(x, y, xf, gm) for x, y, xf, gm in reqs]
+    for i in ids:
+        srv.wait(i, 120000)
+    srv.close()
+    for (x, y, xf, gm), i in zip(reqs, ids):
+        assert torch.equal(y, _plain(M, x, xf, gm, torch.float32)), i
+        flat = x.reshape(-1, 3)
+        k = g.integers(0, flat.shape[0], min(20000, flat.shape[0]))
+        xv = flat[torch.from_numpy(k)].double().numpy()
+        if x.dtype == torch.uint8:
+            xv = xv / 255.0
+        got = y.reshape(-1, 3)[torch.from_numpy(k)].double().numpy()
+        P.assert_parity_ties(xf, got, xv, P.coeffs(M.default_params(xf)), gamma=gm,
+                             what="request %d %s %s" % (i, tuple(x.shape), x.dtype))
+
+
+def test_failed_request_reports_its_status(M):
+    # a request whose descriptors are rejected when its batch is built (forced from the host with
+    # the configuration's fault-injection field) completes at once with MACT_E_INVALID: wait and
+    # poll report it, instead of a completion with the output unwritten or a time-out; the other
+    # requests of the same batches complete with the plain path's bits
+    import time
+    from paper_1009_0854_amd import _abi
+    reqs = _requests(8, seed=11, lo=16, hi=200)
+    srv = M.Server(arena_bytes=64 << 20, max_batch=4, compute_streams=1, fail_request=3)
+    ids = [srv.submit(x, y, xf, gm) for x, y, xf, gm in reqs]
+    assert ids[2] == 3
+    for (x, y, xf, gm), i in zip(reqs, ids):
+        if i == 3:
+            t0 = time.perf_counter()
+            with pytest.raises(_abi.MactError) as e:
+                srv.wait(i, 60000)
+            assert e.value.status == _abi.E_INVALID and time.perf_counter() - t0 < 30.0
+            assert "rejected" in str(e.value)
+            with pytest.raises(_abi.MactError) as e:
+                srv.poll(i)
+            assert e.value.status == _abi.E_INVALID
+            with pytest.raises(_abi.MactError):
+                srv.latency_ms(i)
+            continue
+        srv.wait(i, 60000)
+        assert srv.poll(i)
+        assert torch.equal(y, _plain(M, x, xf, gm, y.dtype)), i
+    st = srv.stats()
+    assert st.failed == 1 and st.completed == len(reqs) - 1 and st.submitted == len(reqs)
+    srv.close()
