@@ -183,3 +183,161 @@ def interp(lut, xform, method, x=None, v8=None):
             out[..., ch] = th
             rlen[..., ch] = np.hypot(acc_s[..., ch], acc_c[..., ch])
     return out, rlen
+
+
+# ---------------------------------------------------------------- caching form
+#
+# Sec. 3.5.3 times a second version of every method, "caching": the
+# differences between neighbouring lattice points are computed ahead of time
+# and stored in each node.  Reading: a node, as the 000 corner of its cell,
+# stores its own value and the differences along the 12 edges of that cell,
+# 13 values per channel (33^3 nodes x 3 channels x 13 values x 8 bytes is the
+# 10.7 MB the paper quotes as the largest LUT storage).  Each method then
+# needs no subtraction per pixel: its value is the node value plus a weighted
+# sum of edge differences, algebraically the standard weighted corner sum.
+#
+# Entry order in a record: 0 the node value c000; 1-4 the R edges
+# c(1,g,b) - c(0,g,b) for (g, b) = 00, 01, 10, 11; 5-8 the G edges
+# c(r,1,b) - c(r,0,b) for (r, b) = 00, 01, 10, 11; 9-12 the B edges
+# c(r,g,1) - c(r,g,0) for (r, g) = 00, 01, 10, 11.
+
+
+def edge_r(g, b):
+    return 1 + 2 * g + b
+
+
+def edge_g(r, b):
+    return 5 + 2 * r + b
+
+
+def edge_b(r, g):
+    return 9 + 2 * r + g
+
+
+def components(lut, xform):
+    """The values a node contributes to a weighted sum: linear channels as
+    they are, each angular channel as its unit vector (cos, sin)."""
+    parts = []
+    for ch, ang in enumerate(ANGULAR[xform]):
+        if ang:
+            parts += [np.cos(lut[..., ch]), np.sin(lut[..., ch])]
+        else:
+            parts.append(lut[..., ch])
+    return np.stack(parts, axis=-1)
+
+
+def build_cache(xform, N, gamma="bt709"):
+    """The caching LUT: (N-1, N-1, N-1, 13, C) records, FP64, record (i, j, k)
+    for the node (i, j, k) as the 000 corner of its cell; C the components of
+    ``components`` (3 for CIELAB and CIELUV, 4 for HSI, 5 for SCT)."""
+    c = components(build(xform, N, gamma), xform)
+    m = N - 1
+
+    def node(dr, dg, db):
+        return c[dr:dr + m, dg:dg + m, db:db + m]
+
+    rec = np.empty((m, m, m, 13, c.shape[-1]))
+    rec[..., 0, :] = node(0, 0, 0)
+    for u in (0, 1):
+        for v in (0, 1):
+            rec[..., edge_r(u, v), :] = node(1, u, v) - node(0, u, v)
+            rec[..., edge_g(u, v), :] = node(u, 1, v) - node(u, 0, v)
+            rec[..., edge_b(u, v), :] = node(u, v, 1) - node(u, v, 0)
+    return rec
+
+
+def cache_terms(method, f):
+    """(entry, weight) pairs of a method in the caching form: the value is
+    entry 0 plus sum weight x entry.  Derived from the corner weights of
+    ``corner_weights`` by writing every corner as c000 plus the edges of a
+    path to it:
+      trilinear    c000 + f_B dB(00) + f_G [(1-f_B) dG(00) + f_B dG(01)]
+                   + f_R [bilinear blend in (f_G, f_B) of the four R edges];
+      tetrahedral  along the path of decreasing fractions: c000 + f1 (first
+                   edge) + f2 (second) + f3 (third);
+      prism        c000 + f_R dR(00) + the triangle's two edges, each blended
+                   linearly along R;
+      pyramidal    c000 + f_s (s edge at u = v = 1) + f_u (1 - f_v) (u edge at
+                   s = v = 0) + f_v (v edge at s = u = 0) + f_u f_v (u edge at
+                   s = 0, v = 1), for s the axis of the smallest fraction."""
+    fr, fg, fb = f[..., 0], f[..., 1], f[..., 2]
+    zero = np.zeros_like(fr)
+    if method == "trilinear":
+        return [(edge_b(0, 0), fb), (edge_g(0, 0), fg * (1 - fb)), (edge_g(0, 1), fg * fb),
+                (edge_r(0, 0), fr * (1 - fg) * (1 - fb)), (edge_r(0, 1), fr * (1 - fg) * fb),
+                (edge_r(1, 0), fr * fg * (1 - fb)), (edge_r(1, 1), fr * fg * fb)]
+    if method == "prism":
+        up = fg >= fb
+        return [(edge_r(0, 0), fr),
+                (edge_g(0, 0), np.where(up, fg * (1 - fr), zero)), (edge_g(1, 0), np.where(up, fg * fr, zero)),
+                (edge_b(0, 1), np.where(up, fb * (1 - fr), zero)), (edge_b(1, 1), np.where(up, fb * fr, zero)),
+                (edge_b(0, 0), np.where(up, zero, fb * (1 - fr))), (edge_b(1, 0), np.where(up, zero, fb * fr)),
+                (edge_g(0, 1), np.where(up, zero, fg * (1 - fr))), (edge_g(1, 1), np.where(up, zero, fg * fr))]
+    if method == "tetrahedral":
+        # the six orders of the fractions, ties broken R before G before B as in corner_weights
+        order = np.argsort(-f, axis=-1, kind="stable")
+        fs = np.take_along_axis(f, order, axis=-1)
+        terms = []
+        for a1 in range(3):
+            for a2 in range(3):
+                if a2 == a1:
+                    continue
+                a3 = 3 - a1 - a2
+                sel = (order[..., 0] == a1) & (order[..., 1] == a2)
+                pos = [0, 0, 0]
+                for k, a in enumerate((a1, a2, a3)):
+                    others = [pos[j] for j in range(3) if j != a]
+                    idx = (edge_r, edge_g, edge_b)[a](*others)
+                    terms.append((idx, np.where(sel, fs[..., k], zero)))
+                    pos[a] = 1
+        return terms
+    if method == "pyramidal":
+        kmin = np.argmin(f, axis=-1)
+        terms = []
+        for s in range(3):
+            sel = kmin == s
+            u, v = [j for j in range(3) if j != s]
+
+            def edge(axis, at):  # edge along `axis`, the other two coordinates from the dict `at`
+                others = [at[j] for j in range(3) if j != axis]
+                return (edge_r, edge_g, edge_b)[axis](*others)
+
+            fs_, fu, fv = f[..., s], f[..., u], f[..., v]
+            terms += [(edge(s, {u: 1, v: 1}), np.where(sel, fs_, zero)),
+                      (edge(u, {s: 0, v: 0}), np.where(sel, fu * (1 - fv), zero)),
+                      (edge(v, {s: 0, u: 0}), np.where(sel, fv, zero)),
+                      (edge(u, {s: 0, v: 1}), np.where(sel, fu * fv, zero))]
+        return terms
+    raise ValueError(method)
+
+
+def interp_cache(cache, xform, method, x=None, v8=None):
+    """Interpolate with the caching form (``build_cache``) at normalised x or
+    8-bit v8: the record of the pixel's cell, entry 0 plus the method's
+    weighted edge differences, per component; angular channels are the angle
+    of their (cos, sin) resultant, as in ``interp``.  Returns (values,
+    resultant length per channel)."""
+    N = cache.shape[0] + 1
+    if v8 is not None:
+        i, f = locate_u8(v8, N)
+    else:
+        i, f = locate(x, N)
+    rec = cache[i[..., 0], i[..., 1], i[..., 2]]  # (..., 13, C)
+    acc = rec[..., 0, :].copy()
+    for e, w in cache_terms(method, f):
+        acc += w[..., None] * rec[..., e, :]
+    out = np.empty(f.shape[:-1] + (3,))
+    rlen = np.ones_like(out)
+    k = 0
+    for ch, ang in enumerate(ANGULAR[xform]):
+        if ang:
+            th = np.arctan2(acc[..., k + 1], acc[..., k])
+            if xform == "hsi":
+                th = np.mod(th, 2.0 * np.pi)
+            out[..., ch] = th
+            rlen[..., ch] = np.hypot(acc[..., k], acc[..., k + 1])
+            k += 2
+        else:
+            out[..., ch] = acc[..., k]
+            k += 1
+    return out, rlen

@@ -172,3 +172,39 @@ def test_pyramidal_form_is_discontinuous_at_pyramid_boundary():
     above, _ = lut.interp(L, "lab", "pyramidal", x=np.array([[f, f - 1e-12, fb]]))
     assert below[0, 0] == pytest.approx(f * (1 - fb), abs=1e-9)
     assert above[0, 0] == pytest.approx(0.0, abs=1e-9)
+
+
+@pytest.mark.parametrize("method", ["trilinear", "prism", "pyramidal", "tetrahedral"])
+@pytest.mark.parametrize("xform", ["lab", "hsi", "sct", "luv"])
+def test_caching_form_equals_the_standard_form(xform, method):
+    # Sec. 3.5.3's caching version stores per node its value and the differences to its
+    # neighbours; every method then adds weighted differences to the node value.  It is the same
+    # interpolant: equal to the weighted corner sum to FP64 rounding, at float and 8-bit inputs,
+    # at nodes and on cell faces (where the pyramidal form's choice of pyramid changes)
+    g = synth.rng(17)
+    for N in (2, 9, 17):
+        std, cache = lut.build(xform, N), lut.build_cache(xform, N)
+        x = np.concatenate([g.random((5000, 3)), lut.node_inputs(N)[g.integers(0, N, (500, 3))],
+                            np.repeat(g.random((500, 1)), 3, axis=1)])
+        v8 = np.concatenate([g.integers(0, 256, (5000, 3)), [[0, 0, 0], [255, 255, 255], [255, 0, 0], [7, 7, 200]]])
+        for kw in ({"x": x}, {"v8": v8}):
+            a, ra = lut.interp(std, xform, method, **kw)
+            b, rb = lut.interp_cache(cache, xform, method, **kw)
+            d = np.abs(a - b)
+            ang = np.array(lut.ANGULAR[xform])
+            d[:, ang] = np.minimum(d[:, ang], 2 * np.pi - d[:, ang]) * ra[:, ang]
+            assert d.max() <= 1e-12 * max(1.0, np.abs(a).max()), (N, list(kw), d.max())
+            np.testing.assert_allclose(rb, ra, rtol=0, atol=1e-12)
+
+
+def test_caching_record_size_is_the_papers_storage():
+    # 13 values per channel and node (the node value and its cell's 12 edge differences): the
+    # 33^3 three-channel CIELAB LUT in FP64 is the 10.7 MB the paper quotes as the largest storage
+    rec = lut.build_cache("lab", 33)
+    assert rec.shape == (32, 32, 32, 13, 3)
+    assert round(33 ** 3 * rec.shape[-1] * rec.shape[-2] * 8 / 2 ** 20, 1) == 10.7
+    # the four edges along one axis of a cell differ by the second differences, and a cell's
+    # edges close: going round a face (R then G, or G then R) reaches the same corner
+    r, gg = rec[..., lut.edge_r(0, 0), :] + rec[..., lut.edge_g(1, 0), :], \
+        rec[..., lut.edge_g(0, 0), :] + rec[..., lut.edge_r(1, 0), :]
+    np.testing.assert_allclose(r, gg, rtol=0, atol=1e-12)

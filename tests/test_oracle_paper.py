@@ -82,3 +82,24 @@ def test_table12_lut_errors():
         got_avg, got_max = mean_max([p[key] for p in parts])
         assert got_avg == pytest.approx(avg, abs=1e-6), key
         assert got_max == pytest.approx(mx, abs=1e-6), key
+
+
+def _t12_cache(v8, caches):
+    ex = colour.rgb_to_lab(v8 / 255.0)
+    out = {}
+    for (method, N), C in caches.items():
+        o, _ = lut.interp_cache(C, "lab", method, v8=v8)
+        out[(method, N)] = sum_max(colour.delta_e(o, ex))
+    return out
+
+
+def test_table12_lut_errors_caching_form():
+    # Table 12 prints one error per method for the standard and the caching versions: the
+    # caching form reproduces the same digits
+    caches = {(m, N): lut.build_cache("lab", N) for m in ("trilinear", "prism", "tetrahedral") for N in (9, 33)}
+    parts = cube_map(_t12_cache, caches)
+    for key in caches:
+        avg, mx = T.T12_LUT_ERR[key]
+        got_avg, got_max = mean_max([p[key] for p in parts])
+        assert got_avg == pytest.approx(avg, abs=1e-6), key
+        assert got_max == pytest.approx(mx, abs=1e-6), key
