@@ -305,6 +305,22 @@ typedef struct mact_error {
    40 bytes of device memory per call.  Errors as mact_transform; MACT_E_NOMEM. */
 mact_status mact_error_stats(const mact_params* params, const mact_image* in, mact_error* out, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   statistics as mact_error_stats, with the same kernels, arguments, results
+   and errors, but no hipMalloc, hipFree or other allocating call.  The
+   accumulator (one 40-byte record) lives in a fixed 256-byte device array that
+   each GPU the library runs on holds until the process ends; its address is
+   looked up once per GPU, on the first call with that GPU current.  The record
+   does not grow with the input, so no image size is refused on its account.
+   Every call on one GPU shares that record and clears it first: calls that
+   overlap on one GPU (other threads, other streams) race and must be
+   serialised by the caller.  Enqueues on `hip_stream` and waits for it, as
+   mact_error_stats does.  MACT_E_UNSUPPORTED for a device index of 64 or
+   more; MACT_E_DEVICE if the array's address cannot be obtained. */
+mact_status mact_error_stats_noalloc(const mact_params* params, const mact_image* in, mact_error* out,
+                                     void* hip_stream);
+
 /* ------------------------------------------------------------ 3-D LUTs */
 
 enum { MACT_TRILINEAR = 0, MACT_PRISM = 1, MACT_PYRAMIDAL = 2, MACT_TETRAHEDRAL = 3 };

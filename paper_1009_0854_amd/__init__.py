@@ -251,6 +251,19 @@ def error_stats(x, xform="lab", params=None, layout="hwc", gamma="bt709", stream
     return {"count": e.count, "mean": e.mean, "max": e.max, "max_abs": [e.max_abs[c] for c in range(3)]}
 
 
+def error_stats_noalloc(x, xform="lab", params=None, layout="hwc", gamma="bt709", stream=None):
+    """mact_error_stats_noalloc: error_stats without any device allocation in
+    the library (the accumulator is a fixed per-GPU device array; calls that
+    overlap on one GPU race)."""
+    p = params if params is not None else default_params(xform)
+    e = A.ErrorStats()
+    if x.numel() == 0:
+        return {"count": 0, "mean": 0.0, "max": 0.0, "max_abs": [0.0, 0.0, 0.0]}
+    A.check(lib().mact_error_stats_noalloc(ctypes.byref(p), ctypes.byref(image(x, layout, gamma)), ctypes.byref(e),
+                                           _stream(stream)))
+    return {"count": e.count, "mean": e.mean, "max": e.max, "max_abs": [e.max_abs[c] for c in range(3)]}
+
+
 # ---------------------------------------------------------------- LUTs
 
 def lut_bytes(xform, n):

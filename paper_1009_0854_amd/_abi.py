@@ -94,6 +94,7 @@ SIGNATURES = {
     "mact_inverse_params_default": (c_int32, [c_int32, POINTER(Params)]),
     "mact_inverse": (c_int32, [POINTER(Params), POINTER(Image), POINTER(Image), c_void_p]),
     "mact_error_stats": (c_int32, [POINTER(Params), POINTER(Image), POINTER(ErrorStats), c_void_p]),
+    "mact_error_stats_noalloc": (c_int32, [POINTER(Params), POINTER(Image), POINTER(ErrorStats), c_void_p]),
     "lut_cells_bytes": (c_size_t, [c_int32, c_int32]),
     "lut_cells_build": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
     "lut_cells_interp": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(Image), POINTER(Image), c_void_p]),

@@ -623,23 +623,34 @@ extern "C" mact_status mact_inverse(const mact_params* params, const mact_image*
   return MACT_OK;
 }
 
-extern "C" mact_status mact_error_stats(const mact_params* params, const mact_image* in, mact_error* out,
-                                        void* hip_stream) {
-  clear_error();
-  if (!out) return fail(MACT_E_INVALID, "mact_error_stats: out is NULL");
+namespace mact {
+namespace {
+
+__global__ void k_clear_acc(ErrAcc* acc) {
+  acc->sum = 0.0;
+  for (int c = 0; c < 4; ++c) acc->max_bits[c] = 0ull;
+}
+
+// Both forms of the error statistics: validate, clear the accumulator `d_acc`
+// (a fill kernel, not a memset), launch k_error over the image in equal
+// launches, copy the record back, wait for the stream and fill *out.
+mact_status error_stats_with(const mact_params* params, const mact_image* in, mact_error* out, void* hip_stream,
+                             ErrAcc* (*get_acc)(mact_status*), void (*put_acc)(ErrAcc*), const char* what) {
+  if (!out) return fail(MACT_E_INVALID, "%s: out is NULL", what);
   std::memset(out, 0, sizeof *out);
   mact_status s = check_params(params);
   if (s != MACT_OK) return s;
-  if (params->out_mode != 0) return fail(MACT_E_INVALID, "mact_error_stats: out_mode must be 0");
+  if (params->out_mode != 0) return fail(MACT_E_INVALID, "%s: out_mode must be 0", what);
   HostImage hi;
-  if ((s = resolve_image(in, false, "mact_error_stats: in", &hi)) != MACT_OK) return s;
+  if ((s = resolve_image(in, false, what, &hi)) != MACT_OK) return s;
   KCoef k;
   const int deg = pack_coef(*params, &k);
   const int gamma = uses_gamma(params->xform) ? hi.gamma : MACT_GAMMA_NONE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  ErrAcc* d_acc = nullptr;
-  if (hipMalloc(&d_acc, sizeof(ErrAcc)) != hipSuccess) return fail(MACT_E_NOMEM, "mact_error_stats: device allocation");
-  s = hip_check(hipMemsetAsync(d_acc, 0, sizeof(ErrAcc), st), "mact_error_stats: clear");
+  ErrAcc* d_acc = get_acc(&s);
+  if (!d_acc) return s;
+  hipLaunchKernelGGL(k_clear_acc, dim3(1), dim3(1), 0, st, d_acc);
+  s = hip_check(hipGetLastError(), "error statistics: clear");
   const int64_t per = images_per_launch(hi);
   for (int64_t n0 = 0; n0 < hi.N && s == MACT_OK; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
@@ -648,13 +659,13 @@ extern "C" mact_status mact_error_stats(const mact_params* params, const mact_im
     const dim3 grid(grid_256(n_px, 16)), blk(256);
     if (deg == 5) hipLaunchKernelGGL(k_error<5>, grid, blk, 0, st, ks, n_px, k, gamma, d_acc);
     else hipLaunchKernelGGL(k_error<7>, grid, blk, 0, st, ks, n_px, k, gamma, d_acc);
-    s = hip_check(hipGetLastError(), "mact_error_stats: launch");
+    s = hip_check(hipGetLastError(), "error statistics: launch");
   }
   ErrAcc h;
   std::memset(&h, 0, sizeof h);
-  if (s == MACT_OK) s = hip_check(hipMemcpyAsync(&h, d_acc, sizeof h, hipMemcpyDeviceToHost, st), "mact_error_stats: copy");
-  if (s == MACT_OK) s = hip_check(hipStreamSynchronize(st), "mact_error_stats: synchronise");
-  (void)hipFree(d_acc);
+  if (s == MACT_OK) s = hip_check(hipMemcpyAsync(&h, d_acc, sizeof h, hipMemcpyDeviceToHost, st), "error statistics: copy");
+  if (s == MACT_OK) s = hip_check(hipStreamSynchronize(st), "error statistics: synchronise");
+  put_acc(d_acc);
   if (s != MACT_OK) return s;
   const int64_t count = hi.N * hi.W * hi.H;
   double mx[4];
@@ -664,4 +675,77 @@ extern "C" mact_status mact_error_stats(const mact_params* params, const mact_im
   out->max = mx[0];
   for (int c = 0; c < 3; ++c) out->max_abs[c] = mx[c + 1];
   return MACT_OK;
+}
+
+ErrAcc* alloc_acc(mact_status* s) {
+  ErrAcc* d = nullptr;
+  if (hipMalloc(&d, sizeof(ErrAcc)) != hipSuccess) {
+    *s = fail(MACT_E_NOMEM, "mact_error_stats: device allocation");
+    return nullptr;
+  }
+  return d;
+}
+
+void free_acc(ErrAcc* d) { (void)hipFree(d); }
+
+}  // namespace
+}  // namespace mact
+
+extern "C" mact_status mact_error_stats(const mact_params* params, const mact_image* in, mact_error* out,
+                                        void* hip_stream) {
+  clear_error();
+  return error_stats_with(params, in, out, hip_stream, alloc_acc, free_acc, "mact_error_stats");
+}
+
+// ---------------------------------------------------------------- the allocation-free form
+//
+// The accumulator of mact_error_stats_noalloc lives in `scratch`, a file-scope
+// device array: each GPU the library runs on holds its own copy, at its own
+// address, until the process ends.  In host code the array's name stands for
+// no device address, so host code never passes it to a kernel or a copy; it
+// uses the address hipGetSymbolAddress returns for the current GPU, looked up
+// once per GPU.  Every call on one GPU uses the same record (cleared by the
+// call before use), so calls that overlap on one GPU race.
+
+static constexpr size_t kScratchBytes = 256;
+static_assert(sizeof(mact::ErrAcc) <= kScratchBytes, "the accumulator record must fit the scratch array");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices];
+
+mact::ErrAcc* scratch_acc(mact_status* s) {
+  int dev = -1;
+  if ((*s = mact::hip_check(hipGetDevice(&dev), "mact_error_stats_noalloc: current device")) != MACT_OK) return nullptr;
+  if (dev < 0 || dev >= kMaxScratchDevices) {
+    *s = mact::fail(MACT_E_UNSUPPORTED, "mact_error_stats_noalloc: device %d beyond the %d the library serves", dev,
+                    kMaxScratchDevices);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if ((*s = mact::hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)),
+                              "mact_error_stats_noalloc: scratch address")) != MACT_OK)
+      return nullptr;
+    if (!ptr) {
+      *s = mact::fail(MACT_E_DEVICE, "mact_error_stats_noalloc: no scratch address on device %d", dev);
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return static_cast<mact::ErrAcc*>(g_scratch_ptr[dev]);
+}
+
+void keep_acc(mact::ErrAcc*) {}
+
+}  // namespace
+
+extern "C" mact_status mact_error_stats_noalloc(const mact_params* params, const mact_image* in, mact_error* out,
+                                                void* hip_stream) {
+  clear_error();
+  return error_stats_with(params, in, out, hip_stream, scratch_acc, keep_acc, "mact_error_stats_noalloc");
 }

@@ -448,3 +448,8 @@ def test_inverse_and_error_stats_validation_without_gpu(M):
     dbg = M.default_params(0)
     dbg.out_mode = 1
     assert L.mact_error_stats(ctypes.byref(dbg), ctypes.byref(i32), ctypes.byref(e), None) == A.E_INVALID
+    # the allocation-free form validates the same way, before it looks up its device record
+    assert L.mact_error_stats_noalloc(ctypes.byref(M.default_params(0)), ctypes.byref(i32), None, None) == A.E_INVALID
+    assert L.mact_error_stats_noalloc(None, ctypes.byref(i32), ctypes.byref(e), None) == A.E_INVALID
+    assert L.mact_error_stats_noalloc(ctypes.byref(dbg), ctypes.byref(i32), ctypes.byref(e), None) == A.E_INVALID
+    assert b"mact_error_stats_noalloc" in L.mact_last_error()
