@@ -326,10 +326,11 @@ mact_status mact_error_stats_noalloc(const mact_params* params, const mact_image
 enum { MACT_TRILINEAR = 0, MACT_PRISM = 1, MACT_PYRAMIDAL = 2, MACT_TETRAHEDRAL = 3 };
 
 /* Bytes of a packed N x N x N LUT for `xform`: N^3 nodes of 4 floats (LAB:
-   L*, a*, b*, 0; LUV: L*, u*, v*, 0; HSI: cos H, sin H, S, I) or 8 floats (SCT: L, cos A, sin A,
-   cos B, sin B, 0, 0, 0).  Node (i, j, k) at index (i N + j) N + k holds the
-   exact transform of the input (i, j, k)/(N - 1) (Sec. 3.5.3's packing).
-   Returns 0 for invalid arguments. */
+   L*, a*, b*, 0; LUV: L*, u*, v*, 0; HSI: cos H, sin H, S, I; SCT: cos A,
+   sin A, cos B, sin B); for SCT the N^3 nodes are followed by a plane of N^3
+   floats holding L, padded to a multiple of 16 bytes (20 bytes a node).  Node
+   (i, j, k) at index (i N + j) N + k holds the exact transform of the input
+   (i, j, k)/(N - 1) (Sec. 3.5.3's packing).  Returns 0 for invalid arguments. */
 size_t lut_bytes(int32_t xform, int32_t n);
 
 /* Packing (Sec. 3.5.3): evaluates the exact transform in FP64 on the host at
@@ -361,9 +362,11 @@ mact_status lut_interp(const float* dev_lut, int32_t n, int32_t xform, int32_t m
    Sec. 3.5.3 (which store neighbour information in every node to save
    per-pixel work): (N-1)^3 cells, cell (i, j, k) at index (i (N-1) + j) (N-1)
    + k, each holding its 8 corner nodes in the order dR dG dB = 000, 001, 010,
-   011, 100, 101, 110, 111, nodes as in lut_bytes.  One pixel's corners are then
-   one contiguous 128-byte run (256 for SCT) rather than four runs N and N^2
-   nodes apart.  Returns the bytes, 0 for invalid arguments. */
+   011, 100, 101, 110, 111, nodes as in lut_bytes (for SCT the 8 (N-1)^3 nodes
+   are followed by their L values, one float each, in the same order).  One
+   pixel's corners are then one contiguous 128-byte run (and 32 bytes of L for
+   SCT) rather than four runs N and N^2 nodes apart.  Returns the bytes, 0 for
+   invalid arguments. */
 size_t lut_cells_bytes(int32_t xform, int32_t n);
 
 /* Fills `dev_cells` (caller-owned device buffer, >= lut_cells_bytes bytes,
@@ -381,6 +384,39 @@ mact_status lut_cells_build(const float* dev_lut, int32_t n, int32_t xform, floa
 mact_status lut_cells_interp(const float* dev_cells, int32_t n, int32_t xform, int32_t method,
                              const mact_image* in, const mact_image* out, void* hip_stream);
 
+/* The caching LUT of Sec. 3.5.3: the paper's second version of every method,
+   which precomputes the differences between neighbouring lattice points and
+   stores them with each node.  (N-1)^3 records, record (i, j, k) at index
+   (i (N-1) + j) (N-1) + k for the node (i, j, k) as the 000 corner of its cell,
+   each of 13 entries of C floats: entry 0 the node value c000; entries 1-4 the
+   R edges c(1,g,b) - c(0,g,b) for (g, b) = 00, 01, 10, 11; 5-8 the G edges
+   c(r,1,b) - c(r,0,b) for (r, b) = 00, 01, 10, 11; 9-12 the B edges
+   c(r,g,1) - c(r,g,0) for (r, g) = 00, 01, 10, 11.  C = 3 (LAB: L*, a*, b*;
+   LUV: L*, u*, v*), 4 (HSI: cos H, sin H, S, I) or 5 (SCT: L, cos A, sin A,
+   cos B, sin B).  Returns the bytes (rounded up to 16), 0 for invalid
+   arguments. */
+size_t lut_cache_bytes(int32_t xform, int32_t n);
+
+/* Builds the caching form on the host: the exact transform at every node in
+   FP64 (as lut_build), the differences in FP64, each value rounded once to
+   float32; copies it to `dev_cache` (caller-owned device buffer, >=
+   lut_cache_bytes bytes, 16-byte aligned) on `hip_stream` and returns after
+   the copy has completed.  n in 2..256; gamma applies to LAB and LUV.
+   Errors: MACT_E_INVALID (NULL, misaligned, n, gamma, short buffer);
+   MACT_E_DEVICE. */
+mact_status lut_cache_build(int32_t xform, int32_t n, int32_t gamma, float* dev_cache, size_t bytes,
+                            void* hip_stream);
+
+/* Interpolation with the caching form: the same extraction as lut_interp, then
+   the pixel's record: entry 0 plus each of the method's edge differences times
+   its weight (trilinear 7, prism 5, pyramidal 4, tetrahedral 3 terms; the
+   corner weights of lut_interp regrouped along paths from c000, so the result
+   equals lut_interp's up to float32 rounding, not bitwise).  Records that fit
+   the LDS beside the store buffers (9^3 LAB, HSI) are staged there; the rest
+   are read through the L2.  Arguments and errors as lut_interp. */
+mact_status lut_cache_interp(const float* dev_cache, int32_t n, int32_t xform, int32_t method,
+                             const mact_image* in, const mact_image* out, void* hip_stream);
+
 /* ------------------------------------------------------------ batched form */
 
 /* Launch shape picked by the autotuner (or given by the caller). */
@@ -390,14 +426,23 @@ typedef struct mact_tune {
   int32_t vec;        /* pixels per lane per step on the packed HWC paths: 1 or 4 */
   int32_t waves_per_cu; /* 1..64: persistent grid = CUs x this / (block / 64) workgroups, capped
                            by the tile count; 0: one workgroup per tile */
+  int32_t one_launch; /* 1: the whole tile list in one launch; 0: equal launches of at most
+                         2^26 pixels of tiles each (a large batch becomes several kernel nodes
+                         of one graph: streaming launches of that size measured faster) */
 } mact_tune;
 
 typedef struct mact_batch_plan mact_batch_plan;
 
-/* A persistent batched transform of `count` images of any sizes, element
-   types, layouts and transforms (image i uses params[i], in[i], out[i]) in one
-   launch: the images are cut into tiles of `tile` pixels, and a grid sized to
-   the GPU walks the tile list.  The per-pixel arithmetic is that of
+/* A batched transform of `count` images of any sizes, element types, layouts
+   and transforms (image i uses params[i], in[i], out[i]) captured in one HIP
+   graph: the images are cut into tiles of `tile` pixels, and either a
+   persistent grid sized to the GPU walks the tile list (waves_per_cu > 0) or
+   one workgroup takes each tile (waves_per_cu = 0), in one launch
+   (one_launch = 1) or in equal launches of at most 2^26 pixels.  The
+   autotuner chooses among all of these by time on the batch itself; on MI355X
+   it picks full-grid split launches, which measured faster than one
+   persistent launch (a persistent grid walking a streaming workload holds
+   fewer bytes in flight).  The per-pixel arithmetic is that of
    mact_transform, so every output is bitwise equal to the plain call's.  The
    plan copies the descriptors to device memory (library-owned), picks the
    launch shape with the autotuner when `tune` is NULL (timings on `hip_stream`,

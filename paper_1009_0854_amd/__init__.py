@@ -17,7 +17,8 @@ from ._abi import (CHW, E_BUSY, E_NOCONV, F16, F32, FN_ACOS, FN_ASIN2, FN_ATAN, 
 __all__ = ["fit", "dark_end_weight", "default_approx", "paper_approx", "default_params", "make_params", "image", "transform",
            "transform_exact",
            "transform_backward", "inverse_params", "inverse", "error_stats", "lut_bytes", "lut_build",
-           "lut_interp", "lut_cells_bytes", "lut_cells_build", "lut_cells_interp", "BatchPlan", "batch_run",
+           "lut_interp", "lut_cells_bytes", "lut_cells_build", "lut_cells_interp",
+           "lut_cache_bytes", "lut_cache_build", "lut_cache_interp", "BatchPlan", "batch_run",
            "Server", "stream_u8_to_f32", "copy", "MactError", "MactLab"]
 
 
@@ -322,6 +323,38 @@ def lut_cells_interp(cells, n, xform, method, x, layout="hwc", out=None, out_lay
     if x.numel() == 0:  # nothing to transform
         return out
     A.check(lib().lut_cells_interp(ctypes.c_void_p(cells.data_ptr()), int(n), _xf(xform), m,
+                                   ctypes.byref(image(x, layout, "none")), ctypes.byref(image(out, out_layout)),
+                                   _stream(stream)))
+    return out
+
+
+def lut_cache_bytes(xform, n):
+    return int(lib().lut_cache_bytes(_xf(xform), int(n)))
+
+
+def lut_cache_build(xform, n, gamma="bt709", device="cuda", stream=None):
+    """Caching form (lut_cache_build): per-cell records of the node value and
+    the 12 edge differences, as a float32 device tensor."""
+    torch = _torch()
+    nbytes = lut_cache_bytes(xform, n)
+    if nbytes == 0:
+        raise MactError(A.E_INVALID, "lut_cache_bytes: invalid xform/n")
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device=device)
+    A.check(lib().lut_cache_build(_xf(xform), int(n), _gm(gamma), ctypes.c_void_p(buf.data_ptr()), nbytes,
+                                  _stream(stream)))
+    return buf
+
+
+def lut_cache_interp(cache, n, xform, method, x, layout="hwc", out=None, out_layout=None, out_dtype=None,
+                     stream=None):
+    torch = _torch()
+    out_layout = layout if out_layout is None else out_layout
+    if out is None:
+        out = _out_like(x, layout, out_layout, out_dtype or torch.float32)
+    m = A.METHODS[method] if isinstance(method, str) else int(method)
+    if x.numel() == 0:  # nothing to transform
+        return out
+    A.check(lib().lut_cache_interp(ctypes.c_void_p(cache.data_ptr()), int(n), _xf(xform), m,
                                    ctypes.byref(image(x, layout, "none")), ctypes.byref(image(out, out_layout)),
                                    _stream(stream)))
     return out

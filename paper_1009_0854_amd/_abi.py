@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("block", c_int32), ("tile", c_int32), ("vec", c_int32), ("waves_per_cu", c_int32)]
+    _fields_ = [("block", c_int32), ("tile", c_int32), ("vec", c_int32), ("waves_per_cu", c_int32),
+                ("one_launch", c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -98,6 +99,9 @@ SIGNATURES = {
     "lut_cells_bytes": (c_size_t, [c_int32, c_int32]),
     "lut_cells_build": (c_int32, [c_void_p, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
     "lut_cells_interp": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(Image), POINTER(Image), c_void_p]),
+    "lut_cache_bytes": (c_size_t, [c_int32, c_int32]),
+    "lut_cache_build": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_size_t, c_void_p]),
+    "lut_cache_interp": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(Image), POINTER(Image), c_void_p]),
     "mact_batch_plan_create": (c_int32, [POINTER(Params), POINTER(Image), POINTER(Image), c_int32, POINTER(Tune),
                                          c_void_p, POINTER(c_void_p)]),
     "mact_batch_plan_launch": (c_int32, [c_void_p, c_int32, c_void_p]),

@@ -177,7 +177,8 @@ hipError_t launch_batch_kernel(const BDesc* d_descs, const KCoef* d_coefs, const
   if (total_tiles == 0) return hipSuccess;
   const size_t shm = tune.vec == 4 ? (size_t)(tune.block / 64) * 192 * sizeof(f4) : 0;
   const uint32_t tile = (uint32_t)tune.tile;
-  const uint64_t launches = std::max<uint64_t>(1, ((uint64_t)total_tiles * tile + (1ull << 26) - 1) >> 26);
+  const uint64_t launches =
+      tune.one_launch ? 1 : std::max<uint64_t>(1, ((uint64_t)total_tiles * tile + (1ull << 26) - 1) >> 26);
   const uint32_t per = (uint32_t)(((uint64_t)total_tiles + launches - 1) / launches);
   const dim3 b(tune.block);
   for (uint32_t t0 = 0; t0 < total_tiles; t0 += per) {
@@ -203,6 +204,7 @@ static mact_status check_tune(const mact_tune& t) {
     return fail(MACT_E_INVALID, "mact_tune: tile %d must be a multiple of 256 and >= block", t.tile);
   if (t.vec != 1 && t.vec != 4) return fail(MACT_E_INVALID, "mact_tune: vec %d not 1 or 4", t.vec);
   if (t.waves_per_cu < 0 || t.waves_per_cu > 64) return fail(MACT_E_INVALID, "mact_tune: waves_per_cu %d", t.waves_per_cu);
+  if (t.one_launch != 0 && t.one_launch != 1) return fail(MACT_E_INVALID, "mact_tune: one_launch %d not 0 or 1", t.one_launch);
   return MACT_OK;
 }
 
@@ -218,7 +220,8 @@ const char* cache_path() {
   return (p && *p) ? p : nullptr;
 }
 
-// File format: one JSON object, "key": [block, tile, vec, waves_per_cu] entries.
+// File format: one JSON object, "key": [block, tile, vec, waves_per_cu, one_launch] entries (an entry
+// of the first four alone reads as one_launch 0).
 void load_cache_file_locked() {
   if (g_tune_file_loaded) return;
   g_tune_file_loaded = true;
@@ -238,10 +241,11 @@ void load_cache_file_locked() {
     const std::string key = s.substr(pos + 1, end - pos - 1);
     const size_t lb = s.find('[', end), rb = s.find(']', end);
     if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
-    mact_tune t;
-    if (std::sscanf(s.c_str() + lb + 1, "%d , %d , %d , %d", &t.block, &t.tile, &t.vec, &t.waves_per_cu) == 4 &&
-        check_tune(t) == MACT_OK)
-      g_tune_cache[key] = t;
+    mact_tune t{};
+    const int got = std::sscanf(s.c_str() + lb + 1, "%d , %d , %d , %d , %d", &t.block, &t.tile, &t.vec,
+                                &t.waves_per_cu, &t.one_launch);
+    if (got == 4) t.one_launch = 0;
+    if ((got == 4 || got == 5) && check_tune(t) == MACT_OK) g_tune_cache[key] = t;
     pos = rb + 1;
   }
   clear_error();
@@ -256,8 +260,8 @@ void save_cache_file_locked() {
   std::fprintf(f, "{\n");
   size_t i = 0;
   for (const auto& kv : g_tune_cache) {
-    std::fprintf(f, "  \"%s\": [%d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second.block, kv.second.tile, kv.second.vec,
-                 kv.second.waves_per_cu, ++i == g_tune_cache.size() ? "" : ",");
+    std::fprintf(f, "  \"%s\": [%d, %d, %d, %d, %d]%s\n", kv.first.c_str(), kv.second.block, kv.second.tile,
+                 kv.second.vec, kv.second.waves_per_cu, kv.second.one_launch, ++i == g_tune_cache.size() ? "" : ",");
   }
   std::fprintf(f, "}\n");
   std::fclose(f);
@@ -397,10 +401,14 @@ static mact_status plan_autotune(mact_batch_plan* p) {
   for (int v : vecs)
     for (int b : blocks)
       for (int t : tiles)
-        for (int w : waves) cands.push_back(mact_tune{b, t, v, w});
+        for (int w : waves) {
+          cands.push_back(mact_tune{b, t, v, w, 0});
+          // a persistent grid also as one launch over the whole tile list
+          if (w > 0) cands.push_back(mact_tune{b, t, v, w, 1});
+        }
   // one workgroup per small tile: one or two 256-pixel chunks per wave, the plain kernel's shape
   for (int b : {256, 512})
-    for (int t : {2048, 4096}) cands.push_back(mact_tune{b, t, 4, 0});
+    for (int t : {2048, 4096}) cands.push_back(mact_tune{b, t, 4, 0, 0});
   std::vector<std::pair<float, mact_tune>> timed;
   for (const mact_tune& c : cands) {
     p->tune = c;

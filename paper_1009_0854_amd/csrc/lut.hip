@@ -2,21 +2,23 @@
 //
 // Packing runs on the host in FP64 (the exact transform at every node) and
 // uploads float32 nodes.  A node is one float4 (LAB: L*, a*, b*, 0; HSI:
-// cos H, sin H, S, I) or two (SCT: L, cos A, sin A, cos B | sin B, 0, 0, 0):
-// angular channels are stored as unit vectors so that circular interpolation
-// needs no trigonometry per corner.
+// cos H, sin H, S, I; SCT: cos A, sin A, cos B, sin B): angular channels are
+// stored as unit vectors so that circular interpolation needs no
+// trigonometry per corner.  SCT's fifth value, L, lives in a plane of one
+// float per node after the N^3 float4 (20 bytes a node, with no padding).
 //
 // Interpolation: a grid of a few workgroups per CU strides over the image.
-// When the packed grid fits the workgroup's LDS (17^3 x 16 B = 78.6 KB) it is
-// staged there once per workgroup and every corner gather is an LDS read;
-// larger grids (33^3 x 16 B = 575 KB) are gathered from global memory through
-// the L2.  Packed 8-bit HWC -> float32 HWC takes k_lut4 (the transform's
+// When the packed grid fits the workgroup's LDS beside the store buffers
+// (17^3: 78.6 KB, SCT 98.3 KB) it is staged there once per workgroup and
+// every corner gather is an LDS read; larger grids (33^3 x 16 B = 575 KB) are
+// gathered from global memory through the L2.  Packed 8-bit HWC -> float32 HWC takes k_lut4 (the transform's
 // 12-byte loads and LDS-transposed 1 KB stores); other shapes take k_lut, one
 // pixel per lane.  Each method is a weighted sum of its 8, 6, 5 or 4 corners.
 //
 // Cell-major form: (N-1)^3 cells, each holding its 8 corner nodes in one
-// contiguous run (128 bytes; 256 for SCT), so that one pixel's corners are
-// one cache line instead of four lines N and N^2 nodes apart.  It plays the
+// contiguous run (128 bytes; for SCT followed, after all cells, by the
+// cells' 8 L values, 32 bytes a cell), so that one pixel's corners are one
+// cache line instead of four lines N and N^2 nodes apart.  It plays the
 // part of the paper's caching LUTs, which store neighbour information in every
 // node to save per-pixel work; here what the stored neighbours save is memory
 // transactions.  Corner ids (dR dG dB as bits 2, 1, 0) stand in for the node
@@ -35,7 +37,17 @@ namespace mact {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-static int node_floats(int xform) { return xform == MACT_SCT ? 8 : 4; }
+// float4 units of a LUT of `entries` nodes (packed: N^3; cell-major: 8 per
+// cell): one per node, and for SCT the L plane, one float per node, after them.
+static size_t lut_f4s(int xform, size_t entries) { return entries + (xform == MACT_SCT ? (entries + 3) / 4 : 0); }
+
+// Bytes of the caching form: (N-1)^3 records of 13 entries of C floats
+// (3, 4 or 5 components), rounded up to 16 bytes.
+static size_t lut_cache_size(int xform, size_t n) {
+  const size_t c = xform == MACT_SCT ? 5 : xform == MACT_HSI ? 4 : 3;
+  const size_t m = n - 1;
+  return (m * m * m * 13 * c * sizeof(float) + 15) / 16 * 16;
+}
 
 // ---------------------------------------------------------------- device
 
@@ -136,12 +148,125 @@ struct Corners<MACT_PYRAMIDAL> {
   }
 };
 
-// One pixel: the method's weighted corner sum at cell i, fractions f.  CELL:
-// `nodes` is the cell-major form.
-template <int METHOD, int XF, bool CELL>
-__device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, uint32_t N, const uint32_t i[3], const float f[3],
-                                       float o[3]) {
-  const int NF = XF == MACT_SCT ? 2 : 1;  // float4 per node
+// Layout of a LUT buffer: packed nodes, cell-major corners, or the caching
+// form's difference records.
+enum { kPacked = 0, kCells = 1, kCache = 2 };
+
+// Components of a caching-form entry: LAB, LUV: the three channels; HSI:
+// cos H, sin H, S, I; SCT: L, cos A, sin A, cos B, sin B.
+template <int XF>
+struct CacheC {
+  static constexpr int C = XF == MACT_SCT ? 5 : XF == MACT_HSI ? 4 : 3;
+};
+
+// Entries of a caching record: 0 the node value c000, then the differences
+// along the cell's 12 edges: 1 + 2g + b the R edge at (g, b), 5 + 2r + b the G
+// edge at (r, b), 9 + 2r + g the B edge at (r, g).
+__device__ __forceinline__ constexpr int edge_r(int g, int b) { return 1 + 2 * g + b; }
+__device__ __forceinline__ constexpr int edge_g(int r, int b) { return 5 + 2 * r + b; }
+__device__ __forceinline__ constexpr int edge_b(int r, int g) { return 9 + 2 * r + g; }
+
+// Caching form (Sec. 3.5.3): the record of the pixel's cell, entry 0 plus the
+// method's edge differences, each times its weight: every corner of the
+// method's corner sum written as c000 plus the edges of a path to it, so no
+// corner subtraction is left per pixel.
+template <int METHOD, int XF>
+__device__ __forceinline__ void lut_px_cache(const float* __restrict__ cache, uint32_t N, const uint32_t i[3],
+                                             const float f[3], float o[3]) {
+  constexpr int C = CacheC<XF>::C;
+  const float* __restrict__ r = cache + (size_t)(((i[0] * (N - 1) + i[1]) * (N - 1) + i[2])) * (13 * C);
+  float acc[C];
+#pragma unroll
+  for (int k = 0; k < C; ++k) acc[k] = r[k];
+  auto add = [&](int e, float w) {
+#pragma unroll
+    for (int k = 0; k < C; ++k) acc[k] = __builtin_fmaf(w, r[e * C + k], acc[k]);
+  };
+  const float fr = f[0], fg = f[1], fb = f[2];
+  if (METHOD == MACT_TRILINEAR) {
+    const float gb = fg * fb, g0 = fg - gb, rg = fr * fg;
+    add(edge_b(0, 0), fb);
+    add(edge_g(0, 0), g0);
+    add(edge_g(0, 1), gb);
+    add(edge_r(0, 0), (fr - rg) * (1.0f - fb));
+    add(edge_r(0, 1), (fr - rg) * fb);
+    add(edge_r(1, 0), rg * (1.0f - fb));
+    add(edge_r(1, 1), rg * fb);
+  } else if (METHOD == MACT_PRISM) {
+    // linear along R; the (G, B) triangle chosen by f_G >= f_B, its two edges blended along R
+    const float r0 = 1.0f - fr;
+    add(edge_r(0, 0), fr);
+    if (fg >= fb) {
+      add(edge_g(0, 0), fg * r0);
+      add(edge_g(1, 0), fg * fr);
+      add(edge_b(0, 1), fb * r0);
+      add(edge_b(1, 1), fb * fr);
+    } else {
+      add(edge_b(0, 0), fb * r0);
+      add(edge_b(1, 0), fb * fr);
+      add(edge_g(0, 1), fg * r0);
+      add(edge_g(1, 1), fg * fr);
+    }
+  } else if (METHOD == MACT_TETRAHEDRAL) {
+    // the path from c000 along the axes in decreasing order of the fractions (ties R, G, B):
+    // each step's edge sits where the earlier steps have moved to
+    int e1, e2, e3;
+    float w1, w2, w3;
+    if (fr >= fg) {
+      if (fg >= fb) { e1 = edge_r(0, 0); w1 = fr; e2 = edge_g(1, 0); w2 = fg; e3 = edge_b(1, 1); w3 = fb; }
+      else if (fr >= fb) { e1 = edge_r(0, 0); w1 = fr; e2 = edge_b(1, 0); w2 = fb; e3 = edge_g(1, 1); w3 = fg; }
+      else { e1 = edge_b(0, 0); w1 = fb; e2 = edge_r(0, 1); w2 = fr; e3 = edge_g(1, 1); w3 = fg; }
+    } else {
+      if (fr >= fb) { e1 = edge_g(0, 0); w1 = fg; e2 = edge_r(1, 0); w2 = fr; e3 = edge_b(1, 1); w3 = fb; }
+      else if (fg >= fb) { e1 = edge_g(0, 0); w1 = fg; e2 = edge_b(0, 1); w2 = fb; e3 = edge_r(1, 1); w3 = fr; }
+      else { e1 = edge_b(0, 0); w1 = fb; e2 = edge_g(0, 1); w2 = fg; e3 = edge_r(1, 1); w3 = fr; }
+    }
+    add(e1, w1);
+    add(e2, w2);
+    add(e3, w3);
+  } else {
+    // pyramidal: s the axis of the smallest fraction (ties R, G, B), u, v the other two in order:
+    // c000 + f_s (s edge at u = v = 1) + f_u (1 - f_v) (u edge at s = v = 0) + f_v (v edge at
+    // s = u = 0) + f_u f_v (u edge at s = 0, v = 1)
+    int es, eu0, ev, eu1;
+    float fs, fu, fv;
+    if (fr <= fg && fr <= fb) {
+      es = edge_r(1, 1); eu0 = edge_g(0, 0); ev = edge_b(0, 0); eu1 = edge_g(0, 1); fs = fr; fu = fg; fv = fb;
+    } else if (fg <= fb) {
+      es = edge_g(1, 1); eu0 = edge_r(0, 0); ev = edge_b(0, 0); eu1 = edge_r(0, 1); fs = fg; fu = fr; fv = fb;
+    } else {
+      es = edge_b(1, 1); eu0 = edge_r(0, 0); ev = edge_g(0, 0); eu1 = edge_r(1, 0); fs = fb; fu = fr; fv = fg;
+    }
+    const float uv = fu * fv;
+    add(es, fs);
+    add(eu0, fu - uv);
+    add(ev, fv);
+    add(eu1, uv);
+  }
+  if (XF == MACT_LAB || XF == MACT_LUV) {
+    o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2];
+  } else if (XF == MACT_HSI) {
+    float h = atan2f(acc[1], acc[0]);
+    if (h < 0.0f) h += kTwoPif;
+    o[0] = h; o[1] = acc[2]; o[2] = acc[C - 1];
+  } else {
+    o[0] = acc[0];
+    o[1] = atan2f(acc[2], acc[1]);
+    o[2] = atan2f(acc[C - 1], acc[3]);
+  }
+}
+
+// One pixel: the method's weighted corner sum at cell i, fractions f.  FORM
+// kCells: `nodes` is the cell-major form; kCache: the caching records.
+// `lp`: SCT's L plane (one float per entry of `nodes`); unused otherwise.
+template <int METHOD, int XF, int FORM>
+__device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, const float* __restrict__ lp, uint32_t N,
+                                       const uint32_t i[3], const float f[3], float o[3]) {
+  if (FORM == kCache) {
+    lut_px_cache<METHOD, XF>(reinterpret_cast<const float*>(nodes), N, i, f, o);
+    return;
+  }
+  constexpr bool CELL = FORM == kCells;
   const uint32_t base = CELL ? ((i[0] * (N - 1) + i[1]) * (N - 1) + i[2]) * 8u : (i[0] * N + i[1]) * N + i[2];
   uint32_t off[8];
   float w[8];
@@ -150,13 +275,13 @@ __device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, uint32_t N,
   float a1 = 0.0f;
 #pragma unroll
   for (int c = 0; c < Corners<METHOD>::K; ++c) {
-    const uint32_t n = (base + off[c]) * NF;
+    const uint32_t n = base + off[c];
     const f4 v0 = nodes[n];
     a0.x = __builtin_fmaf(w[c], v0.x, a0.x);
     a0.y = __builtin_fmaf(w[c], v0.y, a0.y);
     a0.z = __builtin_fmaf(w[c], v0.z, a0.z);
     a0.w = __builtin_fmaf(w[c], v0.w, a0.w);
-    if (NF == 2) a1 = __builtin_fmaf(w[c], nodes[n + 1].x, a1);
+    if (XF == MACT_SCT) a1 = __builtin_fmaf(w[c], lp[n], a1);
   }
   if (XF == MACT_LAB || XF == MACT_LUV) {
     o[0] = a0.x; o[1] = a0.y; o[2] = a0.z;
@@ -165,37 +290,52 @@ __device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, uint32_t N,
     if (h < 0.0f) h += kTwoPif;
     o[0] = h; o[1] = a0.z; o[2] = a0.w;
   } else {
-    o[0] = a0.x;
-    o[1] = atan2f(a0.z, a0.y);
-    o[2] = atan2f(a1, a0.w);
+    o[0] = a1;
+    o[1] = atan2f(a0.y, a0.x);
+    o[2] = atan2f(a0.w, a0.z);
   }
 }
 
-template <int METHOD, int XF, bool CELL>
-__device__ __forceinline__ void lut_px_u8(const f4* __restrict__ nodes, uint32_t N, uint32_t r, uint32_t g, uint32_t b,
-                                          float o[3]) {
+template <int METHOD, int XF, int FORM>
+__device__ __forceinline__ void lut_px_u8(const f4* __restrict__ nodes, const float* __restrict__ lp, uint32_t N,
+                                          uint32_t r, uint32_t g, uint32_t b, float o[3]) {
   uint32_t i[3];
   float f[3];
   locate_u8(r, N, i[0], f[0]);
   locate_u8(g, N, i[1], f[1]);
   locate_u8(b, N, i[2], f[2]);
-  lut_px<METHOD, XF, CELL>(nodes, N, i, f, o);
+  lut_px<METHOD, XF, FORM>(nodes, lp, N, i, f, o);
 }
 
-// Any element type, layout and stride: one pixel per lane step.  LDS and
-// CELL are exclusive.
-template <int METHOD, int XF, bool LDS, bool CELL>
+// Node entries of a LUT of size N (packed N^3, cell-major 8 (N-1)^3), after
+// which SCT's L plane starts; and the float4 units of the whole buffer
+// (caching: (N-1)^3 records of 13 C floats, rounded up to a float4).
+template <int FORM>
+__device__ __forceinline__ uint32_t lut_entries(uint32_t N) {
+  return FORM == kCells ? 8u * (N - 1) * (N - 1) * (N - 1) : N * N * N;
+}
+
+template <int XF, int FORM>
+__device__ __forceinline__ uint32_t lut_f4_units(uint32_t N) {
+  if (FORM == kCache) return ((N - 1) * (N - 1) * (N - 1) * 13u * CacheC<XF>::C + 3u) / 4u;
+  const uint32_t e = lut_entries<FORM>(N);
+  return XF == MACT_SCT ? e + (e + 3) / 4 : e;
+}
+
+// Any element type, layout and stride: one pixel per lane step.  LDS: the
+// buffer (any form) staged in LDS.
+template <int METHOD, int XF, bool LDS, int FORM>
 __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32_t N, KImage src, KImage dst,
                                               uint32_t n_px) {
   extern __shared__ f4 s_lut[];
-  const int NF = XF == MACT_SCT ? 2 : 1;
-  const uint32_t n_nodes = N * N * N;
   const f4* nodes = lut;
   if (LDS) {
-    for (uint32_t i = threadIdx.x; i < n_nodes * NF; i += blockDim.x) s_lut[i] = lut[i];
+    const uint32_t n_f4 = lut_f4_units<XF, FORM>(N);
+    for (uint32_t i = threadIdx.x; i < n_f4; i += blockDim.x) s_lut[i] = lut[i];
     __syncthreads();
     nodes = s_lut;
   }
+  const float* lp = reinterpret_cast<const float*>(nodes + lut_entries<FORM>(N));
   const bool u8 = src.dtype == MACT_U8;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n_px; p += stride) {
@@ -208,7 +348,7 @@ __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32
       if (u8) locate_u8((uint32_t)v[c], N, i[c], f[c]);
       else locate_f(src.dtype == MACT_U16 ? v[c] * kInv65535 : v[c], N, i[c], f[c]);
     }
-    lut_px<METHOD, XF, CELL>(nodes, N, i, f, o);
+    lut_px<METHOD, XF, FORM>(nodes, lp, N, i, f, o);
     store_px(dst, p, o);
   }
 }
@@ -223,19 +363,20 @@ __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32
 // often share cache lines.  Either way the results leave through the wave's
 // LDS slice as 1 KB contiguous stores.  LDS holds the LUT (when LDS) followed
 // by 3 KB per wave.
-template <int METHOD, int XF, bool LDS, bool CELL, bool SPREAD>
+template <int METHOD, int XF, bool LDS, int FORM, bool SPREAD>
 __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint32_t N, const uint8_t* __restrict__ in,
                                                float* __restrict__ out, uint32_t n_px) {
   extern __shared__ f4 smem[];
-  const int NF = XF == MACT_SCT ? 2 : 1;
-  const uint32_t n_nodes = N * N * N;
+  const uint32_t n_ent = lut_entries<FORM>(N);
+  const uint32_t n_f4 = lut_f4_units<XF, FORM>(N);
   const f4* nodes = lut;
-  f4* tbuf = smem + (LDS ? n_nodes * NF : 0);
+  f4* tbuf = smem + (LDS ? n_f4 : 0);
   if (LDS) {
-    for (uint32_t i = threadIdx.x; i < n_nodes * NF; i += blockDim.x) smem[i] = lut[i];
+    for (uint32_t i = threadIdx.x; i < n_f4; i += blockDim.x) smem[i] = lut[i];
     __syncthreads();
     nodes = smem;
   }
+  const float* lp = reinterpret_cast<const float*>(nodes + n_ent);
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   f4* s = tbuf + wv * 192;
   const uint32_t n_chunks = n_px >> 8;
@@ -245,7 +386,8 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
       float o[12];
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        lut_px_u8<METHOD, XF, CELL>(nodes, N, byte_of(w, 3 * j), byte_of(w, 3 * j + 1), byte_of(w, 3 * j + 2), o + 3 * j);
+        lut_px_u8<METHOD, XF, FORM>(nodes, lp, N, byte_of(w, 3 * j), byte_of(w, 3 * j + 1), byte_of(w, 3 * j + 2),
+                                    o + 3 * j);
       __builtin_amdgcn_wave_barrier();
       s[3 * lane] = f4{o[0], o[1], o[2], o[3]};
       s[3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
@@ -272,7 +414,7 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         float o[3];
-        lut_px_u8<METHOD, XF, CELL>(nodes, N, rgb[j][0], rgb[j][1], rgb[j][2], o);
+        lut_px_u8<METHOD, XF, FORM>(nodes, lp, N, rgb[j][0], rgb[j][1], rgb[j][2], o);
         const uint32_t p = lane + 64 * j;
         sf[3 * p] = o[0];
         sf[3 * p + 1] = o[1];
@@ -292,23 +434,27 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
   if (blockIdx.x == 0)
     for (uint32_t p = tail0 + threadIdx.x; p < n_px; p += blockDim.x) {
       float o[3];
-      lut_px_u8<METHOD, XF, CELL>(nodes, N, in[3 * (size_t)p], in[3 * (size_t)p + 1], in[3 * (size_t)p + 2], o);
+      lut_px_u8<METHOD, XF, FORM>(nodes, lp, N, in[3 * (size_t)p], in[3 * (size_t)p + 1], in[3 * (size_t)p + 2], o);
       out[3 * (size_t)p] = o[0];
       out[3 * (size_t)p + 1] = o[1];
       out[3 * (size_t)p + 2] = o[2];
     }
 }
 
-// Cell-major form from the packed grid: element t of the output is float4 q
-// of corner c of cell (i, j, k), t = ((cell 8) + c) NF + q.  A plain copy.
-__global__ __launch_bounds__(256) void k_lut_cells(const f4* __restrict__ nodes, uint32_t N, uint32_t NF,
-                                                   f4* __restrict__ cells, uint32_t n_elems) {
+// Cell-major form from the packed grid: entry t = cell 8 + c is corner c of
+// cell (i, j, k), the packed node (i + dR, j + dG, k + dB); with `lplanes`, the
+// node's L (SCT) goes to the cells' L plane as well.  A plain copy.
+__global__ __launch_bounds__(256) void k_lut_cells(const f4* __restrict__ nodes, uint32_t N, bool lplanes,
+                                                   f4* __restrict__ cells, uint32_t n_ent) {
   const uint32_t M = N - 1;
-  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n_elems; t += gridDim.x * 256u) {
-    const uint32_t q = t % NF, c = (t / NF) & 7u, cell = t / (8u * NF);
+  const float* lsrc = reinterpret_cast<const float*>(nodes + N * N * N);
+  float* ldst = reinterpret_cast<float*>(cells + n_ent);
+  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n_ent; t += gridDim.x * 256u) {
+    const uint32_t c = t & 7u, cell = t >> 3;
     const uint32_t k = cell % M, j = (cell / M) % M, i = cell / (M * M);
     const uint32_t node = ((i + (c >> 2)) * N + (j + ((c >> 1) & 1u))) * N + (k + (c & 1u));
-    cells[t] = nodes[node * NF + q];
+    cells[t] = nodes[node];
+    if (lplanes) ldst[t] = lsrc[node];
   }
 }
 
@@ -336,18 +482,19 @@ static hipError_t allow_lds(K k, size_t bytes) {
 // (as many copies of the grid as the CU's LDS holds), grid-stride.  Grid
 // gathered through the L2 (and every cell-major grid): 256-thread
 // workgroups, eight per CU.
-template <int METHOD, int XF, bool CELL>
+template <int METHOD, int XF, int FORM>
 static hipError_t launch_lut(const f4* lut, uint32_t N, const HostImage& hi, const HostImage& ho, int64_t n0,
                              int64_t cnt, uint32_t n_px, hipStream_t st) {
-  const size_t bytes = (size_t)N * N * N * node_floats(XF) * sizeof(float);
+  constexpr bool CELL = FORM == kCells;  // cell-major grids are always read through the L2
+  const size_t bytes = FORM == kCache ? lut_cache_size(XF, N) : lut_f4s(XF, (size_t)N * N * N) * sizeof(f4);
   const size_t lds_max = (size_t)max_lds_bytes();
   const void* ip = static_cast<const char*>(hi.data) + (size_t)(n0 * hi.bs) * hi.esize;
   float* op = static_cast<float*>(ho.data) + (size_t)(n0 * ho.bs);
   const bool fast = hi.dtype == MACT_U8 && hi.layout == MACT_HWC && hi.packed && ho.dtype == MACT_F32 &&
                     ho.layout == MACT_HWC && ho.packed && (uintptr_t)ip % 4 == 0 && (uintptr_t)op % 16 == 0;
   const size_t t_lds = 16 * 192 * sizeof(f4);  // k_lut4 with 1024 threads: 16 waves x 3 KB
-  // a grid that fits LDS alone but not beside k_lut4's transpose buffers (17^3 SCT) is
-  // still worth staging: k_lut below
+  // a grid that fits LDS alone but not beside k_lut4's transpose buffers is still worth
+  // staging: k_lut below
   if (fast && (CELL || bytes + t_lds <= lds_max || bytes > lds_max)) {
     const bool lds = !CELL && bytes + t_lds <= lds_max;
     const unsigned block = lds ? 1024 : 256;
@@ -363,12 +510,12 @@ static hipError_t launch_lut(const f4* lut, uint32_t N, const HostImage& hi, con
     // lanes on consecutive pixels pay off for gathers through the L1 (33^3: +13-16%, SCT +44%
     // on smooth images) but not for LDS-staged grids (-0 to -6%)
     if (lds) {
-      auto k = k_lut4<METHOD, XF, true, false, false>;
+      auto k = k_lut4<METHOD, XF, true, FORM, false>;
       hipError_t e = allow_lds(k, shm);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, lut, N, in8, op, n_px);
     } else {
-      auto k = k_lut4<METHOD, XF, false, CELL, true>;
+      auto k = k_lut4<METHOD, XF, false, FORM, true>;
       hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, lut, N, in8, op, n_px);
     }
     return hipGetLastError();
@@ -383,30 +530,30 @@ static hipError_t launch_lut(const f4* lut, uint32_t N, const HostImage& hi, con
   const unsigned grid = (unsigned)std::max<uint64_t>(1, lds ? std::min<uint64_t>(need, (uint64_t)device_cus() * per_cu)
                                                             : std::min<uint64_t>(need, 0x7fffffffu));
   if (lds) {
-    auto k = k_lut<METHOD, XF, true, false>;
+    auto k = k_lut<METHOD, XF, true, FORM>;
     hipError_t e = allow_lds(k, bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(grid), dim3(block), bytes, st, lut, N, s, d, n_px);
   } else {
-    hipLaunchKernelGGL((k_lut<METHOD, XF, false, CELL>), dim3(grid), dim3(block), 0, st, lut, N, s, d, n_px);
+    hipLaunchKernelGGL((k_lut<METHOD, XF, false, FORM>), dim3(grid), dim3(block), 0, st, lut, N, s, d, n_px);
   }
   return hipGetLastError();
 }
 
-template <int XF, bool CELL>
+template <int XF, int FORM>
 static hipError_t launch_lut_m(int method, const f4* lut, uint32_t N, const HostImage& hi, const HostImage& ho,
                                int64_t n0, int64_t cnt, uint32_t n_px, hipStream_t st) {
   switch (method) {
-    case MACT_TRILINEAR: return launch_lut<MACT_TRILINEAR, XF, CELL>(lut, N, hi, ho, n0, cnt, n_px, st);
-    case MACT_PRISM: return launch_lut<MACT_PRISM, XF, CELL>(lut, N, hi, ho, n0, cnt, n_px, st);
-    case MACT_PYRAMIDAL: return launch_lut<MACT_PYRAMIDAL, XF, CELL>(lut, N, hi, ho, n0, cnt, n_px, st);
-    default: return launch_lut<MACT_TETRAHEDRAL, XF, CELL>(lut, N, hi, ho, n0, cnt, n_px, st);
+    case MACT_TRILINEAR: return launch_lut<MACT_TRILINEAR, XF, FORM>(lut, N, hi, ho, n0, cnt, n_px, st);
+    case MACT_PRISM: return launch_lut<MACT_PRISM, XF, FORM>(lut, N, hi, ho, n0, cnt, n_px, st);
+    case MACT_PYRAMIDAL: return launch_lut<MACT_PYRAMIDAL, XF, FORM>(lut, N, hi, ho, n0, cnt, n_px, st);
+    default: return launch_lut<MACT_TETRAHEDRAL, XF, FORM>(lut, N, hi, ho, n0, cnt, n_px, st);
   }
 }
 
 // lut_interp and lut_cells_interp: validation, then one launch per run of
 // images of fewer than 2^31 pixels.
-template <bool CELL>
+template <int FORM>
 static mact_status interp_common(const char* what, const float* dev_lut, int32_t n, int32_t xform, int32_t method,
                                  const mact_image* in, const mact_image* out, void* hip_stream) {
   if (!dev_lut) return fail(MACT_E_INVALID, "%s: LUT pointer is NULL", what);
@@ -429,10 +576,10 @@ static mact_status interp_common(const char* what, const float* dev_lut, int32_t
     const int64_t cnt = std::min(per, hi.N - n0);
     const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
     hipError_t e;
-    if (xform == MACT_LAB) e = launch_lut_m<MACT_LAB, CELL>(method, lut, n, hi, ho, n0, cnt, n_px, st);
-    else if (xform == MACT_HSI) e = launch_lut_m<MACT_HSI, CELL>(method, lut, n, hi, ho, n0, cnt, n_px, st);
-    else if (xform == MACT_LUV) e = launch_lut_m<MACT_LUV, CELL>(method, lut, n, hi, ho, n0, cnt, n_px, st);
-    else e = launch_lut_m<MACT_SCT, CELL>(method, lut, n, hi, ho, n0, cnt, n_px, st);
+    if (xform == MACT_LAB) e = launch_lut_m<MACT_LAB, FORM>(method, lut, n, hi, ho, n0, cnt, n_px, st);
+    else if (xform == MACT_HSI) e = launch_lut_m<MACT_HSI, FORM>(method, lut, n, hi, ho, n0, cnt, n_px, st);
+    else if (xform == MACT_LUV) e = launch_lut_m<MACT_LUV, FORM>(method, lut, n, hi, ho, n0, cnt, n_px, st);
+    else e = launch_lut_m<MACT_SCT, FORM>(method, lut, n, hi, ho, n0, cnt, n_px, st);
     std::snprintf(nm, sizeof nm, "%s: launch", what);
     if ((s = hip_check(e, nm)) != MACT_OK) return s;
   }
@@ -445,7 +592,7 @@ using namespace mact;
 
 extern "C" size_t lut_bytes(int32_t xform, int32_t n) {
   if (xform < MACT_LAB || xform > MACT_LUV || n < 2 || n > 256) return 0;
-  return (size_t)n * n * n * node_floats(xform) * sizeof(float);
+  return lut_f4s(xform, (size_t)n * n * n) * sizeof(f4);
 }
 
 extern "C" mact_status lut_build(int32_t xform, int32_t n, int32_t gamma, float* dev_lut, size_t bytes,
@@ -456,14 +603,16 @@ extern "C" mact_status lut_build(int32_t xform, int32_t n, int32_t gamma, float*
   if (!dev_lut) return fail(MACT_E_INVALID, "lut_build: dev_lut is NULL");
   if (bytes < need) return fail(MACT_E_INVALID, "lut_build: %zu bytes < %zu needed", bytes, need);
   if (gamma < MACT_GAMMA_BT709 || gamma > MACT_GAMMA_NONE) return fail(MACT_E_INVALID, "lut_build: gamma %d", gamma);
-  const int nf = node_floats(xform);
-  std::vector<float> host((size_t)n * n * n * nf, 0.0f);
+  const size_t n3 = (size_t)n * n * n;
+  std::vector<float> host(need / sizeof(float), 0.0f);
+  float* lplane = host.data() + 4 * n3;  // SCT's L, one float per node
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j)
       for (int k = 0; k < n; ++k) {
         const double rgb[3] = {(double)i / (n - 1), (double)j / (n - 1), (double)k / (n - 1)};
         double o[3];
-        float* dst = &host[((size_t)(i * n + j) * n + k) * nf];
+        const size_t node = (size_t)(i * n + j) * n + k;
+        float* dst = &host[node * 4];
         if (xform == MACT_LAB) {
           exact_lab(rgb, gamma, o);
           dst[0] = (float)o[0]; dst[1] = (float)o[1]; dst[2] = (float)o[2];
@@ -475,9 +624,9 @@ extern "C" mact_status lut_build(int32_t xform, int32_t n, int32_t gamma, float*
           dst[0] = (float)std::cos(o[0]); dst[1] = (float)std::sin(o[0]); dst[2] = (float)o[1]; dst[3] = (float)o[2];
         } else {
           exact_sct(rgb, o);
-          dst[0] = (float)o[0];
-          dst[1] = (float)std::cos(o[1]); dst[2] = (float)std::sin(o[1]);
-          dst[3] = (float)std::cos(o[2]); dst[4] = (float)std::sin(o[2]);
+          dst[0] = (float)std::cos(o[1]); dst[1] = (float)std::sin(o[1]);
+          dst[2] = (float)std::cos(o[2]); dst[3] = (float)std::sin(o[2]);
+          lplane[node] = (float)o[0];
         }
       }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -489,13 +638,13 @@ extern "C" mact_status lut_build(int32_t xform, int32_t n, int32_t gamma, float*
 extern "C" mact_status lut_interp(const float* dev_lut, int32_t n, int32_t xform, int32_t method, const mact_image* in,
                                   const mact_image* out, void* hip_stream) {
   clear_error();
-  return interp_common<false>("lut_interp", dev_lut, n, xform, method, in, out, hip_stream);
+  return interp_common<kPacked>("lut_interp", dev_lut, n, xform, method, in, out, hip_stream);
 }
 
 extern "C" size_t lut_cells_bytes(int32_t xform, int32_t n) {
   if (xform < MACT_LAB || xform > MACT_LUV || n < 2 || n > 256) return 0;
   const size_t m = (size_t)(n - 1);
-  return m * m * m * 8 * node_floats(xform) * sizeof(float);
+  return lut_f4s(xform, m * m * m * 8) * sizeof(f4);
 }
 
 extern "C" mact_status lut_cells_build(const float* dev_lut, int32_t n, int32_t xform, float* dev_cells, size_t bytes,
@@ -507,16 +656,90 @@ extern "C" mact_status lut_cells_build(const float* dev_lut, int32_t n, int32_t 
   if ((uintptr_t)dev_lut % 16 || (uintptr_t)dev_cells % 16)
     return fail(MACT_E_INVALID, "lut_cells_build: LUT pointers must be 16-byte aligned");
   if (bytes < need) return fail(MACT_E_INVALID, "lut_cells_build: %zu bytes < %zu needed", bytes, need);
-  const uint32_t nf4 = (uint32_t)(node_floats(xform) / 4);
-  const uint32_t n_elems = (uint32_t)(need / sizeof(f4));
-  const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n_elems + 255) / 256, (uint64_t)device_cus() * 8));
+  const size_t m = (size_t)(n - 1);
+  const uint32_t n_ent = (uint32_t)(m * m * m * 8);
+  const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n_ent + 255) / 256, (uint64_t)device_cus() * 8));
   hipLaunchKernelGGL(k_lut_cells, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(hip_stream),
-                     reinterpret_cast<const f4*>(dev_lut), (uint32_t)n, nf4, reinterpret_cast<f4*>(dev_cells), n_elems);
+                     reinterpret_cast<const f4*>(dev_lut), (uint32_t)n, xform == MACT_SCT, reinterpret_cast<f4*>(dev_cells),
+                     n_ent);
   return hip_check(hipGetLastError(), "lut_cells_build: launch");
 }
 
 extern "C" mact_status lut_cells_interp(const float* dev_cells, int32_t n, int32_t xform, int32_t method,
                                         const mact_image* in, const mact_image* out, void* hip_stream) {
   clear_error();
-  return interp_common<true>("lut_cells_interp", dev_cells, n, xform, method, in, out, hip_stream);
+  return interp_common<kCells>("lut_cells_interp", dev_cells, n, xform, method, in, out, hip_stream);
+}
+
+extern "C" size_t lut_cache_bytes(int32_t xform, int32_t n) {
+  if (xform < MACT_LAB || xform > MACT_LUV || n < 2 || n > 256) return 0;
+  return lut_cache_size(xform, (size_t)n);
+}
+
+extern "C" mact_status lut_cache_build(int32_t xform, int32_t n, int32_t gamma, float* dev_cache, size_t bytes,
+                                       void* hip_stream) {
+  clear_error();
+  const size_t need = lut_cache_bytes(xform, n);
+  if (need == 0) return fail(MACT_E_INVALID, "lut_cache_build: transform %d / size %d invalid (n in 2..256)", xform, n);
+  if (!dev_cache) return fail(MACT_E_INVALID, "lut_cache_build: dev_cache is NULL");
+  if ((uintptr_t)dev_cache % 16) return fail(MACT_E_INVALID, "lut_cache_build: dev_cache not 16-byte aligned");
+  if (bytes < need) return fail(MACT_E_INVALID, "lut_cache_build: %zu bytes < %zu needed", bytes, need);
+  if (gamma < MACT_GAMMA_BT709 || gamma > MACT_GAMMA_NONE) return fail(MACT_E_INVALID, "lut_cache_build: gamma %d", gamma);
+  // the components of every node in FP64: linear channels as they are, angles as (cos, sin)
+  const int C = xform == MACT_SCT ? 5 : xform == MACT_HSI ? 4 : 3;
+  const size_t n3 = (size_t)n * n * n;
+  std::vector<double> comp(n3 * C);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k) {
+        const double rgb[3] = {(double)i / (n - 1), (double)j / (n - 1), (double)k / (n - 1)};
+        double o[3];
+        double* c = &comp[((size_t)(i * n + j) * n + k) * C];
+        if (xform == MACT_LAB || xform == MACT_LUV) {
+          if (xform == MACT_LAB) exact_lab(rgb, gamma, o);
+          else exact_luv(rgb, gamma, o);
+          c[0] = o[0]; c[1] = o[1]; c[2] = o[2];
+        } else if (xform == MACT_HSI) {
+          exact_hsi(rgb, o);
+          c[0] = std::cos(o[0]); c[1] = std::sin(o[0]); c[2] = o[1]; c[3] = o[2];
+        } else {
+          exact_sct(rgb, o);
+          c[0] = o[0];
+          c[1] = std::cos(o[1]); c[2] = std::sin(o[1]);
+          c[3] = std::cos(o[2]); c[4] = std::sin(o[2]);
+        }
+      }
+  // record of cell (i, j, k): the node value and the 12 edge differences, in FP64, rounded once
+  const int m = n - 1;
+  std::vector<float> host(need / sizeof(float), 0.0f);
+  auto node = [&](int i, int j, int k) { return &comp[((size_t)(i * n + j) * n + k) * C]; };
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j)
+      for (int k = 0; k < m; ++k) {
+        float* r = &host[((size_t)(i * m + j) * m + k) * 13 * C];
+        const double* c0 = node(i, j, k);
+        for (int q = 0; q < C; ++q) r[q] = (float)c0[q];
+        for (int u = 0; u < 2; ++u)
+          for (int v = 0; v < 2; ++v) {
+            const double *r0 = node(i, j + u, k + v), *r1 = node(i + 1, j + u, k + v);  // R edge at (g, b) = (u, v)
+            const double *g0 = node(i + u, j, k + v), *g1 = node(i + u, j + 1, k + v);  // G edge at (r, b) = (u, v)
+            const double *b0 = node(i + u, j + v, k), *b1 = node(i + u, j + v, k + 1);  // B edge at (r, g) = (u, v)
+            for (int q = 0; q < C; ++q) {
+              r[(1 + 2 * u + v) * C + q] = (float)(r1[q] - r0[q]);
+              r[(5 + 2 * u + v) * C + q] = (float)(g1[q] - g0[q]);
+              r[(9 + 2 * u + v) * C + q] = (float)(b1[q] - b0[q]);
+            }
+          }
+      }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  mact_status s = hip_check(hipMemcpyAsync(dev_cache, host.data(), need, hipMemcpyHostToDevice, st),
+                            "lut_cache_build: copy");
+  if (s != MACT_OK) return s;
+  return hip_check(hipStreamSynchronize(st), "lut_cache_build: synchronise");
+}
+
+extern "C" mact_status lut_cache_interp(const float* dev_cache, int32_t n, int32_t xform, int32_t method,
+                                        const mact_image* in, const mact_image* out, void* hip_stream) {
+  clear_error();
+  return interp_common<kCache>("lut_cache_interp", dev_cache, n, xform, method, in, out, hip_stream);
 }

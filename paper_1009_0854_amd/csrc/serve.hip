@@ -138,7 +138,7 @@ struct mact_server {
   int device = 0;
   mact_server_config cfg{};
   int deg = 5;
-  mact_tune tune{512, 8192, 4, 32};  // small tiles: a single request still spreads over the CUs
+  mact_tune tune{512, 8192, 4, 32, 0};  // small tiles: a single request still spreads over the CUs
   std::unique_ptr<Arena> arena;
   char* d_arena = nullptr;
   KCoef* d_coefs = nullptr;

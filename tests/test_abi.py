@@ -306,7 +306,8 @@ def test_lut_validation_without_gpu(M):
     L = M.lib()
     assert L.lut_bytes(0, 17) == 17 ** 3 * 16
     assert L.lut_bytes(1, 33) == 33 ** 3 * 16
-    assert L.lut_bytes(2, 17) == 17 ** 3 * 32
+    assert L.lut_bytes(2, 17) == 17 ** 3 * 16 + (17 ** 3 + 3) // 4 * 16  # SCT: float4 angles + L plane
+    assert L.lut_bytes(2, 9) == 9 ** 3 * 16 + (9 ** 3 + 3) // 4 * 16
     assert L.lut_bytes(0, 1) == 0 and L.lut_bytes(4, 17) == 0 and L.lut_bytes(0, 257) == 0
     assert L.lut_build(0, 1, 0, ctypes.c_void_p(0x1000), 1 << 20, None) == A.E_INVALID
     assert L.lut_build(0, 17, 0, None, 1 << 20, None) == A.E_INVALID
@@ -317,7 +318,7 @@ def test_lut_validation_without_gpu(M):
     assert L.lut_interp(None, 17, 0, 0, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
     # cell-major form: (N-1)^3 cells of 8 nodes
     assert L.lut_cells_bytes(0, 17) == 16 ** 3 * 8 * 16
-    assert L.lut_cells_bytes(2, 33) == 32 ** 3 * 8 * 32
+    assert L.lut_cells_bytes(2, 33) == 32 ** 3 * 8 * 20
     assert L.lut_cells_bytes(0, 2) == 8 * 16
     assert L.lut_cells_bytes(0, 1) == 0 and L.lut_cells_bytes(4, 17) == 0 and L.lut_cells_bytes(1, 257) == 0
     need = L.lut_cells_bytes(0, 17)
@@ -328,6 +329,23 @@ def test_lut_validation_without_gpu(M):
     assert L.lut_cells_interp(ctypes.c_void_p(0x1000), 17, 0, 9, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
     assert L.lut_cells_interp(ctypes.c_void_p(0x1008), 17, 0, 0, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
     assert L.lut_cells_interp(None, 17, 0, 0, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
+    # caching form: (N-1)^3 records of 13 entries of 3 (LAB, LUV), 4 (HSI) or 5 (SCT) floats; 33^3
+    # LAB in float32 is 5.1 MB (the paper's 10.7 MB counts 33^3 nodes in FP64)
+    assert L.lut_cache_bytes(0, 33) == 32 ** 3 * 13 * 3 * 4 == 5111808
+    assert L.lut_cache_bytes(1, 17) == 16 ** 3 * 13 * 4 * 4
+    assert L.lut_cache_bytes(2, 9) == 8 ** 3 * 13 * 5 * 4
+    assert L.lut_cache_bytes(3, 2) == (13 * 3 * 4 + 15) // 16 * 16
+    assert L.lut_cache_bytes(0, 1) == 0 and L.lut_cache_bytes(4, 17) == 0 and L.lut_cache_bytes(0, 257) == 0
+    need = L.lut_cache_bytes(0, 17)
+    assert L.lut_cache_build(0, 17, 0, None, need, None) == A.E_INVALID
+    assert L.lut_cache_build(0, 17, 0, ctypes.c_void_p(0x2008), need, None) == A.E_INVALID
+    assert L.lut_cache_build(0, 17, 0, ctypes.c_void_p(0x2000), need - 1, None) == A.E_INVALID
+    assert L.lut_cache_build(0, 17, 5, ctypes.c_void_p(0x2000), need, None) == A.E_INVALID
+    assert L.lut_cache_build(5, 17, 0, ctypes.c_void_p(0x2000), need, None) == A.E_INVALID
+    assert L.lut_cache_interp(ctypes.c_void_p(0x1000), 17, 0, 9, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
+    assert L.lut_cache_interp(ctypes.c_void_p(0x1008), 17, 0, 0, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
+    assert L.lut_cache_interp(None, 17, 0, 0, ctypes.byref(i), ctypes.byref(o), None) == A.E_INVALID
+    assert b"lut_cache_interp" in L.mact_last_error()
 
 
 def test_batch_and_server_validation_without_gpu(M):
@@ -347,6 +365,10 @@ def test_batch_and_server_validation_without_gpu(M):
     for w in (-1, 65):
         t = A.Tune(256, 4096, 4, w)
         assert L.mact_batch_plan_create(p, i, o, 1, ctypes.byref(t), None, ctypes.byref(h)) == A.E_INVALID
+    for one in (-1, 2):
+        t = A.Tune(256, 4096, 4, 32, one)
+        assert L.mact_batch_plan_create(p, i, o, 1, ctypes.byref(t), None, ctypes.byref(h)) == A.E_INVALID
+        assert b"one_launch" in L.mact_last_error()
     cfg = A.ServerConfig()
     cfg.arena_bytes, cfg.max_batch, cfg.compute_streams, cfg.max_queue = 1 << 30, 64, 2, 100
     for x in range(3):

@@ -1,7 +1,9 @@
-"""The batched form (mact_batch_plan_*): one persistent, graph-captured launch
-over uneven images of mixed element types, layouts and transforms gives the
-same bits as one plain mact_transform per image, for every launch shape; graph
-replays equal eager launches; sampled pixels match the oracle."""
+"""The batched form (mact_batch_plan_*): a graph-captured launch (one
+persistent launch, or equal launches of at most 2^26 pixels) over uneven
+images of mixed element types, layouts and transforms gives the same bits as
+one plain mact_transform per image, for every launch shape; graph replays
+equal eager launches; sampled pixels match the oracle; the autotuner's cache
+file round-trips."""
 import numpy as np
 import pytest
 
@@ -55,11 +57,11 @@ def _plain(M, params, ins, lays, gams):
 
 
 TUNES = [None, (256, 4096, 4, 32), (1024, 16384, 4, 16), (256, 4096, 1, 32), (64, 256, 1, 8), (512, 65536, 4, 64),
-         (1024, 8192, 4, 0), (256, 1024, 1, 0)]
+         (1024, 8192, 4, 0), (256, 1024, 1, 0), (256, 4096, 4, 32, 1), (512, 2048, 4, 0, 1)]
 
 
 @pytest.mark.parametrize("tune", TUNES, ids=["autotuned", "b256v4", "b1024v4", "b256v1", "b64t256", "b512big",
-                                             "b1024v4full", "b256v1full"])
+                                             "b1024v4full", "b256v1full", "b256v4one", "b512v4fullone"])
 def test_batch_equals_plain_bitwise(M, tune):
     params, ins, outs, lays, gams, olays, _ = _mixed_batch(M, 40, seed=3)
     ref = _plain(M, params, ins, lays, gams)
@@ -166,8 +168,10 @@ def test_config3_uneven_1000_images_against_plain_and_oracle(M):
     plan.close()
 
 
-@pytest.mark.parametrize("tune", [(256, 4096, 4, 0), (1024, 8192, 4, 32), (256, 4096, 1, 16)],
-                         ids=["full_grid", "persistent", "vec1_persistent"])
+@pytest.mark.parametrize("tune", [(256, 4096, 4, 0, 0), (1024, 8192, 4, 32, 0), (256, 4096, 1, 16, 0),
+                                  (1024, 8192, 4, 32, 1), (256, 4096, 4, 0, 1)],
+                         ids=["full_grid", "persistent", "vec1_persistent", "persistent_one_launch",
+                              "full_grid_one_launch"])
 def test_split_launches_equal_plain_for_fixed_shapes(M, tune):
     # 200 large images (about 0.4 Gpx): the tile list runs as several launches of at most 2^26
     # pixels, each with the shape's grid (one workgroup per tile, or a persistent grid walking
@@ -191,7 +195,7 @@ def test_split_launches_equal_plain_for_fixed_shapes(M, tune):
     assert px > 4 * (1 << 26)
     from paper_1009_0854_amd import _abi as A
     t = A.Tune()
-    t.block, t.tile, t.vec, t.waves_per_cu = tune
+    t.block, t.tile, t.vec, t.waves_per_cu, t.one_launch = tune
     plan = M.BatchPlan(params, ins, outs, gammas=gams, tune=t)
     for use_graph in (True, False):
         for o in outs:
@@ -210,3 +214,56 @@ def test_batch_run_convenience(M):
     M.batch_run(params, ins, outs, lays, gams, olays, tune=M.Tune(256, 4096, 4, 32))
     for o, r in zip(outs, ref):
         assert torch.equal(o, r)
+
+
+_TUNE_CHILD = r"""
+import json, sys
+import torch
+import paper_1009_0854_amd as M
+sys.path.insert(0, %(root)r)
+from tests.test_gpu_batch import _mixed_batch
+params, ins, outs, lays, gams, olays, _ = _mixed_batch(M, 12, seed=21)
+plan = M.BatchPlan(params, ins, outs, lays, gams, olays)
+t = plan.tune
+ref = [M.transform(x, params=p, layout=l, gamma=gm) for p, x, l, gm in zip(params, ins, lays, gams)]
+plan.launch()
+torch.cuda.synchronize()
+same = all(torch.equal(o, r) for o, r in zip(outs, ref))
+plan.close()
+print(json.dumps({"tune": [t.block, t.tile, t.vec, t.waves_per_cu, t.one_launch], "same": same}))
+"""
+
+
+def test_autotune_cache_file_round_trip(tmp_path):
+    # a first process tunes the batch and writes the cache file; a second process, given a file
+    # whose entry for that key names another valid shape, takes that shape without tuning; its
+    # outputs still equal the plain calls' (one process at a time on the GPU)
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.json"
+    env = dict(os.environ, MACT_AUTOTUNE_CACHE=str(cache), PYTHONPATH=root)
+    code = _TUNE_CHILD % {"root": root}
+
+    def child():
+        r = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    first = child()
+    assert first["same"]
+    entries = json.loads(cache.read_text())
+    assert len(entries) == 1
+    key, val = next(iter(entries.items()))
+    assert val == first["tune"]
+    assert key.startswith("gfx950") or "|cu" in key
+    seeded = [64, 256, 1, 3, 1] if val != [64, 256, 1, 3, 1] else [128, 512, 4, 5, 0]
+    cache.write_text(json.dumps({key: seeded}))
+    second = child()
+    assert second["tune"] == seeded and second["same"]
+    # an entry in the older four-number form reads as one_launch 0
+    cache.write_text('{"%s": [%d, %d, %d, %d]}' % (key, 256, 4096, 4, 7))
+    third = child()
+    assert third["tune"] == [256, 4096, 4, 7, 0] and third["same"]

@@ -119,8 +119,9 @@ def test_table12_from_gpu_output(M):
 
 
 def test_lut_33_goes_through_l2_and_17_sct_through_lds(M):
-    # sizes: 33^3 x 16 B does not fit 160 KB of LDS; 17^3 x 32 B (SCT) does
-    assert M.lut_bytes("lab", 33) > 163840 >= M.lut_bytes("sct", 17)
+    # sizes: 33^3 x 16 B does not fit 160 KB of LDS; 17^3 x 20 B (SCT) fits beside the 48 KB of
+    # the 4-pixel kernel's store buffers
+    assert M.lut_bytes("lab", 33) > 163840 >= M.lut_bytes("sct", 17) + 48 * 1024
     img = synth.uniform_u8(40, 41, seed=9)
     for xform, N in (("sct", 17), ("sct", 33), ("hsi", 33)):
         gpu, _ = _interp(M, xform, N, "tetrahedral", img)
@@ -135,13 +136,18 @@ def test_cells_hold_the_corner_nodes(M, xform, N):
     L = M.lut_build(xform, N)
     C = M.lut_cells_build(L, N, xform)
     torch.cuda.synchronize()
-    nf = M.lut_bytes(xform, N) // 4 // N ** 3
-    nodes = L.view(N, N, N, nf)
-    cells = C.view(N - 1, N - 1, N - 1, 8, nf)
-    for c in range(8):
-        dr, dg, db = c >> 2, (c >> 1) & 1, c & 1
-        ref = nodes[dr:dr + N - 1, dg:dg + N - 1, db:db + N - 1]
-        assert torch.equal(cells[:, :, :, c], ref), c
+    n3, m3 = N ** 3, 8 * (N - 1) ** 3
+    nodes = L[:4 * n3].view(N, N, N, 4)
+    cells = C[:4 * m3].view(N - 1, N - 1, N - 1, 8, 4)
+    planes = [(nodes, cells)]
+    if xform == "sct":  # the L planes after the float4 nodes
+        assert M.lut_bytes(xform, N) == 4 * (4 * n3 + (n3 + 3) // 4 * 4)
+        planes.append((L[4 * n3:5 * n3].view(N, N, N), C[4 * m3:5 * m3].view(N - 1, N - 1, N - 1, 8)))
+    for nd, cl in planes:
+        for c in range(8):
+            dr, dg, db = c >> 2, (c >> 1) & 1, c & 1
+            ref = nd[dr:dr + N - 1, dg:dg + N - 1, db:db + N - 1]
+            assert torch.equal(cl[:, :, :, c], ref), c
 
 
 @pytest.mark.parametrize("N", [17, 33])
