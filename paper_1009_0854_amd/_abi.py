@@ -7,7 +7,9 @@ import ctypes
 import os
 from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_void_p
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmact.so")
+# MACT_LIB_VARIANT=san loads the build with sanitized host code (build.py --sanitize)
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        "libmact_san.so" if os.environ.get("MACT_LIB_VARIANT") == "san" else "libmact.so")
 
 # status codes
 OK, E_INVALID, E_NOCONV, E_DEVICE, E_NOMEM, E_UNSUPPORTED, E_BUSY = 0, -1, -2, -3, -4, -5, -6
