@@ -8,17 +8,21 @@ place of the cube root) over a batch of 64 synthetic 1920x1080 8-bit images
 seeds 1000..1063), packed HWC uint8 in, packed HWC float32 out, inputs
 resident in HBM.  One step = one mact_transform over the whole batch; `value`
 is Mpixel/s over the K timed steps (wall clock, synchronised on both sides).
-The W untimed warm-up steps default to 100: in a fresh process the first
-launch loads the code object (about 11 ms) and the next few dozen run 3-8%
-slower while the memory system settles.
+Before the W untimed warm-up steps (default 20) come untimed settling steps,
+at least 150 of them and at least 250 ms, whatever W is: in a fresh process
+the first launch loads the code object (about 11 ms) and the next few dozen
+run 3-8% slower while the memory system settles.
 
 The JSON line also carries
   roofline      the hot kernel's achieved HBM bandwidth: 15 algorithmic bytes
                 per pixel (3 read, 12 written) x pixels per launch / the mean
-                launch duration from HIP events on the launch stream;
-  cpu_baseline  the oracle (FP64 numpy MACT CIELAB) timed on the host: the
-                whole batch on a thread pool of up to 16 threads (value), and
-                a bounded sample on one thread;
+                launch duration from HIP events around each step on the
+                launch stream (a step's launches and the gaps between them);
+                the same for the 32 x 4K batch;
+  cpu_baseline  the oracle timed on the host: the scalar FP64 C oracle
+                (MACT CIELAB, exact CIELAB, tetrahedral LUTs at 17^3 and 33^3)
+                on the first pixels of the batch, on one thread and on a pool
+                of up to 16 threads; median of 10 runs after 3 warm-ups;
   accuracy      Delta E*ab of the GPU output against the exact transform on that
                 sample, and the oracle's exhaustive-cube figures;
   forms         (--forms all) HSI, SCT, float16 output, the 4K batch, the
@@ -70,66 +74,85 @@ def time_kernel(fn, steps, warmup=20, spread=None):
     return float(np.mean(per)), float(np.median(per))
 
 
-def cpu_baseline(batch_np, y, budget_px, chunk=1 << 22):
-    """The oracle timed over the whole batch on the host's cores (chunks of
-    2^20 pixels on a thread pool of at most 16 threads), and on the first
-    `budget_px` pixels on one thread; the GPU output's Delta E*ab against the
-    exact transform on those first pixels."""
-    from threadpoolctl import threadpool_limits
-    from oracle import colour, mact
+def settle(fn, min_steps, min_ms):
+    """Untimed launches of fn() until at least `min_steps` have run and at
+    least `min_ms` of wall time has passed since the first: in a fresh
+    process, and on freshly allocated buffers, the first few dozen launches of
+    a streaming kernel run several per cent slower while the memory system
+    settles.  Returns (steps, ms)."""
+    import torch
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        for _ in range(10):
+            fn()
+        n += 10
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        if n >= min_steps and ms >= min_ms:
+            return n, ms
+
+
+def _median_rate(fn, n_px, warmup=3, runs=10):
+    """Median Mpixel/s of fn() over `runs` timed calls after `warmup` untimed ones."""
+    for _ in range(warmup):
+        fn()
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    med = float(np.median(ts))
+    return {"Mpx_s": n_px / med / 1e6, "median_s": med, "min_s": float(min(ts)), "max_s": float(max(ts))}
+
+
+def cpu_baseline(batch_np, y, sample_px):
+    """The oracle timed on the host: the scalar FP64 C oracle (oracle/cbase.c,
+    gcc -O2, one pixel at a time) on the first pixels of the 64 x 1080p batch,
+    for the MACT CIELAB transform (the default (4,4) rational, coefficients
+    rounded to float32 as the GPU uses them; the headline's CPU counterpart),
+    the exact transform, and tetrahedral LUTs of 17^3 and 33^3 nodes (built
+    once, untimed); each on one thread (sample_px / 8 pixels) and on all
+    threads of the pool (sample_px pixels, equal ranges per thread); 3
+    warm-ups and the median of 10 runs each.  Also the GPU output's
+    Delta E*ab against the oracle's exact transform, and its largest
+    difference from the oracle's MACT values, on the sample."""
+    from oracle import cbase, colour
     import paper_1009_0854_amd as M
     p = M.default_params(0)
     pc = np.float32(p.f[0].p_list).astype(np.float64)
     qc = np.float32(p.f[0].q_list).astype(np.float64)
-    flat = batch_np.reshape(-1, 3)[:budget_px]
-    yflat = y.reshape(-1, 3)
-    dt = dt_exact = 0.0
-    de_max, de_sum, diff = 0.0, 0.0, 0.0
-    with threadpool_limits(1):
-        for s in range(0, len(flat), chunk):
-            v = flat[s:s + chunk] / 255.0
-            t0 = time.perf_counter()
-            ref = mact.mact_lab(v, pc, qc)
-            t1 = time.perf_counter()
-            exact = colour.rgb_to_lab(v)
-            dt += t1 - t0
-            dt_exact += time.perf_counter() - t1
-            gpu = yflat[s:s + len(v)].double().cpu().numpy()
-            de = colour.delta_e(gpu, exact)
-            de_max = max(de_max, float(de.max()))
-            de_sum += float(de.sum())
-            diff = max(diff, float(np.abs(gpu - ref).max()))
-    single = {"value": len(flat) / dt / 1e6, "unit": "Mpixel/s", "cores": 1,
-              "sample": "first %d pixels of the 64x1080p batch; 1 thread" % len(flat), "seconds": dt,
-              # the oracle's exact FP64 transform (library cube root) on the same pixels and thread
-              "exact_value": len(flat) / dt_exact / 1e6, "exact_seconds": dt_exact}
-    # the same oracle over the whole batch on the host's cores: chunks on a thread pool (numpy
-    # releases the interpreter lock inside its array loops); at most 16 threads, the box's share
-    from concurrent.futures import ThreadPoolExecutor
-    every = batch_np.reshape(-1, 3)
-    small = 1 << 20
+    flat = np.ascontiguousarray(batch_np.reshape(-1, 3)[:sample_px])
+    one = flat[: max(1, sample_px // 8)]
     n_thr = max(1, min(16, os.cpu_count() or 1))
-
-    def one(s0):
-        mact.mact_lab(every[s0:s0 + small] / 255.0, pc, qc)
-
-    with threadpool_limits(1), ThreadPoolExecutor(n_thr) as ex:
-        t0 = time.perf_counter()
-        list(ex.map(one, range(0, len(every), small)))
-        dt_all = time.perf_counter() - t0
+    lut17, lut33 = cbase.lut_build_lab(17), cbase.lut_build_lab(33)
+    legs = {"mact_lab": lambda v, t: cbase.lab_mact_u8(v, pc, qc, threads=t),
+            "exact_lab": lambda v, t: cbase.lab_exact_u8(v, threads=t),
+            "lut_tetrahedral_17": lambda v, t: cbase.lut_tetra_u8(lut17, v, threads=t),
+            "lut_tetrahedral_33": lambda v, t: cbase.lut_tetra_u8(lut33, v, threads=t)}
+    res = {}
+    for name, fn in legs.items():
+        res[name] = {"one_thread": _median_rate(lambda: fn(one, 1), len(one)),
+                     "all_threads": _median_rate(lambda: fn(flat, n_thr), len(flat))}
+    # accuracy of the GPU output on the sample
+    gpu = y.reshape(-1, 3)[:sample_px].double().cpu().numpy()
+    exact = cbase.lab_exact_u8(flat, threads=n_thr)
+    ref = cbase.lab_mact_u8(flat, pc, qc, threads=n_thr)
+    de = colour.delta_e(gpu, exact)
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
             model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
     except OSError:
         pass
-    return ({"value": len(every) / dt_all / 1e6, "unit": "Mpixel/s", "cores": n_thr, "kind": "oracle",
+    return ({"value": res["mact_lab"]["all_threads"]["Mpx_s"], "unit": "Mpixel/s", "cores": n_thr, "kind": "oracle",
+             "impl": "scalar FP64 C (oracle/cbase.c, gcc -O2), ctypes calls on a thread pool",
              "nproc": os.cpu_count(), "cpu_model": model,
-             "sample": "the whole 64x1080p batch (%d pixels) in chunks of 2^20 on %d threads; FP64 numpy MACT CIELAB"
-                       % (len(every), n_thr),
-             "seconds": dt_all, "single_thread": single},
-            {"sample_px": len(flat), "gpu_max_dE": de_max, "gpu_mean_dE": de_sum / len(flat),
-             "max_abs_gpu_minus_oracle": diff})
+             "sample": "first %d pixels of the 64x1080p batch on %d threads (%d on one thread); MACT CIELAB "
+                       "(4,4); 3 warm-ups, median of 10 runs" % (len(flat), n_thr, len(one)),
+             "legs": res},
+            {"sample_px": len(flat), "gpu_max_dE": float(de.max()), "gpu_mean_dE": float(de.mean()),
+             "max_abs_gpu_minus_oracle": float(np.abs(gpu - ref).max())})
 
 
 def bench_4k(M, p, steps):
@@ -141,11 +164,14 @@ def bench_4k(M, p, steps):
     x = torch.randint(0, 256, (32, 2160, 3840, 3), dtype=torch.uint8, device="cuda", generator=g)
     y = torch.empty((32, 2160, 3840, 3), dtype=torch.float32, device="cuda")
     n_px = 32 * 2160 * 3840
-    # fresh buffers settle like a fresh process: time_kernel's 20 warm-up steps (about 13 ms)
+    # fresh buffers settle like a fresh process: untimed steps for at least 60 steps (240 launches)
+    # and 200 ms before time_kernel's own 20 warm-up steps
+    s_steps, s_ms = settle(lambda: M.transform(x, params=p, out=y), 60, 200.0)
     spread = {}
     ms, med = time_kernel(lambda: M.transform(x, params=p, out=y), steps, spread=spread)
     res = {"Mpx_s": n_px / ms / 1e3, "GBs": 15.0 * n_px / ms / 1e6, "frac_of_8TBs": 15.0 * n_px / ms / 8e9,
            "ms": ms, "ms_median": med, "ms_p10": spread["p10"], "ms_p90": spread["p90"], "pixels": n_px,
+           "launches_per_step": 4, "launch_ms": ms / 4, "settle_steps": s_steps, "settle_ms": s_ms,
            **batch_stats(M, x, p)}
     del x, y
     torch.cuda.empty_cache()
@@ -338,32 +364,68 @@ def bench_lut(M, x, y, n_px, steps):
             ms, _ = time_kernel(lambda: M.lut_cells_interp(C, N, "lab", method, x, out=y), steps)
             rec("lab_cells_%s_%d" % (method, N), "lab", ms, ref)
         del C
+        # the caching form: per-cell node value and edge differences
+        Cc = M.lut_cache_build("lab", N)
+        for method in ("trilinear", "prism", "pyramidal", "tetrahedral"):
+            ms, _ = time_kernel(lambda: M.lut_cache_interp(Cc, N, "lab", method, x, out=y), steps)
+            rec("lab_cache_%s_%d" % (method, N), "lab", ms, ref)
+        del Cc
+        out["storage_bytes_lab_%d" % N] = {"packed": M.lut_bytes("lab", N), "cells": M.lut_cells_bytes("lab", N),
+                                           "cache": M.lut_cache_bytes("lab", N),
+                                           # the paper's caching storage: N^3 nodes x 3 x 13 values in FP64
+                                           "paper_cache_fp64": N ** 3 * 3 * 13 * 8}
     for xf in ("hsi", "sct"):
         ref = M.transform_exact(x, xform=xf)
         for N in (17, 33):
             L = M.lut_build(xf, N)
-            ms, _ = time_kernel(lambda: M.lut_interp(L, N, xf, "trilinear", x, out=y), steps)
-            rec("%s_trilinear_%d" % (xf, N), xf, ms, ref)
+            for method in ("trilinear", "prism", "pyramidal", "tetrahedral"):
+                ms, _ = time_kernel(lambda: M.lut_interp(L, N, xf, method, x, out=y), steps)
+                rec("%s_%s_%d" % (xf, method, N), xf, ms, ref)
             C = M.lut_cells_build(L, N, xf)
             ms, _ = time_kernel(lambda: M.lut_cells_interp(C, N, xf, "trilinear", x, out=y), steps)
             rec("%s_cells_trilinear_%d" % (xf, N), xf, ms, ref)
+            del C
+            Cc = M.lut_cache_build(xf, N)
+            for method in ("trilinear", "tetrahedral"):
+                ms, _ = time_kernel(lambda: M.lut_cache_interp(Cc, N, xf, method, x, out=y), steps)
+                rec("%s_cache_%s_%d" % (xf, method, N), xf, ms, ref)
+            del Cc
     del ref
     torch.cuda.synchronize()
     return out
 
 
-def bench_backward(M, steps):
+def bench_backward(M, steps, sets=4):
+    """Forward and backward of the minimax CIELAB on 32x3x512x512 float32 CHW
+    (linear input).  The timed launches rotate over `sets` independent buffer
+    sets (x, g, out, dx: 403 MB per set, 1.6 GB in all), so that no launch
+    re-reads data an earlier launch left in the 256 MB Infinity Cache."""
     import torch
     import synth
-    x = torch.from_numpy(synth.uniform_f32((32, 3, 512, 512), seed=4)).cuda()
-    g = torch.randn(x.shape, generator=torch.Generator(device="cuda").manual_seed(5), device="cuda")
-    dx = torch.empty_like(x)
     p = M.default_params(0)
-    lab = torch.empty_like(x)
     n_px = 32 * 512 * 512
-    fms, _ = time_kernel(lambda: M.transform(x, params=p, layout="chw", gamma="none", out=lab), steps)
-    bms, _ = time_kernel(lambda: M.transform_backward(x, g, params=p, layout="chw", grad_in=dx), steps)
-    return {"shape": "32x3x512x512 float32 CHW",
+    xs = [torch.from_numpy(synth.uniform_f32((32, 3, 512, 512), seed=4 + 10 * i)).cuda() for i in range(sets)]
+    gs = [torch.randn(xs[0].shape, generator=torch.Generator(device="cuda").manual_seed(5 + 10 * i), device="cuda")
+          for i in range(sets)]
+    labs = [torch.empty_like(xs[0]) for _ in range(sets)]
+    dxs = [torch.empty_like(xs[0]) for _ in range(sets)]
+    it = {"f": 0, "b": 0}
+
+    def fwd():
+        i = it["f"] % sets
+        it["f"] += 1
+        M.transform(xs[i], params=p, layout="chw", gamma="none", out=labs[i])
+
+    def bwd():
+        i = it["b"] % sets
+        it["b"] += 1
+        M.transform_backward(xs[i], gs[i], params=p, layout="chw", grad_in=dxs[i])
+
+    fms, _ = time_kernel(fwd, steps)
+    bms, _ = time_kernel(bwd, steps)
+    del xs, gs, labs, dxs
+    torch.cuda.empty_cache()
+    return {"shape": "32x3x512x512 float32 CHW", "buffer_sets": sets,
             "forward": {"Mpx_s": n_px / fms / 1e3, "GBs": 24 * n_px / fms / 1e6, "ms": fms},
             "backward": {"Mpx_s": n_px / bms / 1e3, "GBs": 36 * n_px / bms / 1e6, "ms": bms}}
 
@@ -401,24 +463,45 @@ def bench_batch(M, steps):
 
     pms, _ = time_kernel(plain, max(3, steps // 4), warmup=1)
     t = plan.tune
-    res = {"images": 1000, "pixels": px, "bytes": in_bytes + out_bytes,
-           "batched": {"Mpx_s": px / gms / 1e3, "GBs": (in_bytes + out_bytes) / gms / 1e6, "ms": gms},
-           "plain_1000_launches": {"Mpx_s": px / pms / 1e3, "GBs": (in_bytes + out_bytes) / pms / 1e6, "ms": pms},
-           "tune": {"block": t.block, "tile": t.tile, "vec": t.vec, "waves_per_cu": t.waves_per_cu},
-           "plan_create_s": plan_s}
     plan.close()
+
+    def launches_of(t):
+        # the library's split: equal launches of at most 2^26 pixels of tiles, or one
+        tiles = sum(-(-(h * w) // t.tile) for (h, w) in sizes)
+        return 1 if t.one_launch else max(1, -(-(tiles * t.tile) // (1 << 26)))
+
+    def shape(t):
+        return {"block": t.block, "tile": t.tile, "vec": t.vec, "waves_per_cu": t.waves_per_cu,
+                "one_launch": t.one_launch, "persistent": t.waves_per_cu > 0, "launches_per_graph": launches_of(t)}
+
+    # the single persistent launch (a grid sized to the GPU walking the whole tile list, one kernel
+    # node in the graph) for a few fixed shapes, beside the tuned choice
+    single = []
+    for tt in ((256, 8192, 4, 16, 1), (512, 32768, 4, 32, 1), (1024, 131072, 4, 32, 1)):
+        sp = M.BatchPlan(params, ins, outs, None, gams, tune=M.Tune(*tt))
+        sms, _ = time_kernel(lambda: sp.launch(use_graph=True), steps)
+        single.append({**shape(sp.tune), "Mpx_s": px / sms / 1e3, "GBs": (in_bytes + out_bytes) / sms / 1e6, "ms": sms})
+        sp.close()
+    res = {"images": 1000, "pixels": px, "bytes": in_bytes + out_bytes,
+           "batched": {"Mpx_s": px / gms / 1e3, "GBs": (in_bytes + out_bytes) / gms / 1e6, "ms": gms,
+                       "frac_of_8TBs": (in_bytes + out_bytes) / gms / 8e9},
+           "plain_1000_launches": {"Mpx_s": px / pms / 1e3, "GBs": (in_bytes + out_bytes) / pms / 1e6, "ms": pms},
+           "tune": shape(t), "single_persistent_launch": single,
+           "plan_create_s": plan_s}
     del ins, outs
     torch.cuda.empty_cache()
     return res
 
 
-def _requests(n, seed, pool):
-    """Request stream: exponential gaps at 2000/s; width log-uniform in
-    256..3840, height in 256..2160; uint8 or float16 input (50/50); transform
-    uniform over CIELAB, HSI, SCT.  Buffers cycle through `pool` pinned slots."""
+def _requests(n, seed, pool, rate=2000.0):
+    """Request stream: exponential gaps at `rate` per second (all at time 0 for
+    rate None); width log-uniform in 256..3840, height in 256..2160; uint8 or
+    float16 input (50/50); transform uniform over CIELAB, HSI, SCT.  Buffers
+    cycle through `pool` pinned slots."""
     import torch
     import synth
     arr, g = synth.poisson_arrivals(n, 2000.0, seed)
+    arr = np.zeros(n) if rate is None else arr * (2000.0 / rate)
     sizes, g2 = synth.uneven_sizes(n, seed + 1, 256, 3840, 256, 2160)
     kinds = g2.integers(0, 2, n)
     xfs = g2.integers(0, 3, n)
@@ -440,53 +523,55 @@ def _requests(n, seed, pool):
     return reqs
 
 
-def bench_serve(M, n_req=2000, pool=16):
-    import torch
-    reqs = _requests(n_req, 6, pool)
-    px = sum(r[1].shape[0] * r[1].shape[1] for r in reqs)
-    # served: the submitter follows the arrival times; a pinned slot is reused only after its
-    # previous request completed.  The first 400 requests of the stream (0.2 s) run once untimed
-    # on the same server (steady state), then the whole stream is timed.
-    srv = M.Server(arena_bytes=8 << 30, max_batch=64, compute_streams=2, max_queue=1 << 20)
+def _serve_stream(M, srv, rs, pool):
+    """Submits rs at their arrival times (a pinned slot is reused only after
+    its previous request completed) and waits for all; (arrival -> submit lag
+    ms, submit -> done latency ms, wall s)."""
+    ids = [None] * len(rs)
+    lag = [0.0] * len(rs)
+    t0 = time.perf_counter()
+    for i, (ta, x, y, xf, gm) in enumerate(rs):
+        if i >= pool:
+            srv.wait(ids[i - pool], 120000)
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        lag[i] = (time.perf_counter() - t0 - ta) * 1e3  # arrival -> submit
+        ids[i] = srv.submit(x, y, xf, gm)
+    for i in ids:
+        srv.wait(i, 120000)
+    wall = time.perf_counter() - t0
+    lib = np.array([srv.latency_ms(i) for i in ids])
+    return np.array(lag), lib, wall
 
-    def run(rs):
-        ids = [None] * len(rs)
-        lag = [0.0] * len(rs)
-        t0 = time.perf_counter()
-        for i, (ta, x, y, xf, gm) in enumerate(rs):
-            if i >= pool:
-                srv.wait(ids[i - pool], 120000)
-            now = time.perf_counter() - t0
-            if ta > now:
-                time.sleep(ta - now)
-            lag[i] = (time.perf_counter() - t0 - ta) * 1e3  # arrival -> submit
-            ids[i] = srv.submit(x, y, xf, gm)
-        for i in ids:
-            srv.wait(i, 120000)
-        wall = time.perf_counter() - t0
-        lib = np.array([srv.latency_ms(i) for i in ids])
-        return np.array(lag), lib, wall
 
-    run(reqs[:400])
+def _served_stats(M, srv, rs, pool, px, rate, warm):
+    if warm:
+        _serve_stream(M, srv, warm, pool)
     st0 = srv.stats()
-    lag, lib, wall = run(reqs)
+    lag, lib, wall = _serve_stream(M, srv, rs, pool)
     st = srv.stats()
-    srv.close()
     lat = lag + lib
     nb = st.batches - st0.batches
-    served = {"requests": n_req, "Mpx_s": px / wall / 1e6, "p50_ms": float(np.percentile(lat, 50)),
-              "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()), "mean_ms": float(lat.mean()),
-              "p50_ms_from_submit": float(np.percentile(lib, 50)), "p99_ms_from_submit": float(np.percentile(lib, 99)),
-              "p99_arrival_to_submit_ms": float(np.percentile(lag, 99)),
-              "batches": nb, "mean_batch": n_req / max(1, nb), "compute_streams": 2,
-              "device_busy_ms": st.device_busy_ms - st0.device_busy_ms, "wall_s": wall, "offered_req_s": 2000.0,
-              "warmup_requests": 400}
-    # plain per-request path: one stream, copy in, transform, copy out, synchronise, in arrival order
+    return {"requests": len(rs), "Mpx_s": px / wall / 1e6, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "max_ms": float(lat.max()), "mean_ms": float(lat.mean()),
+            "p50_ms_from_submit": float(np.percentile(lib, 50)), "p99_ms_from_submit": float(np.percentile(lib, 99)),
+            "p99_arrival_to_submit_ms": float(np.percentile(lag, 99)),
+            "batches": nb, "mean_batch": len(rs) / max(1, nb), "compute_streams": 2,
+            "device_busy_ms": st.device_busy_ms - st0.device_busy_ms, "wall_s": wall,
+            "offered_req_s": rate if rate is not None else "all at t=0",
+            "warmup_requests": len(warm) if warm else 0, "slots": pool}
+
+
+def _plain_stats(M, rs, px):
+    """The plain per-request path: one stream, copy in, transform, copy out,
+    synchronise, in arrival order."""
+    import torch
     lat = []
     s = torch.cuda.Stream()
     t0 = time.perf_counter()
     with torch.cuda.stream(s):
-        for ta, x, y, xf, gm in reqs:
+        for ta, x, y, xf, gm in rs:
             now = time.perf_counter() - t0
             if ta > now:
                 time.sleep(ta - now)
@@ -497,9 +582,32 @@ def bench_serve(M, n_req=2000, pool=16):
             lat.append((time.perf_counter() - t0 - ta) * 1e3)
     wall = time.perf_counter() - t0
     lat = np.sort(np.array(lat))
-    plain = {"requests": n_req, "Mpx_s": px / wall / 1e6, "p50_ms": float(np.percentile(lat, 50)),
-             "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()), "wall_s": wall}
-    return {"served": served, "plain_per_request": plain,
+    return {"requests": len(rs), "Mpx_s": px / wall / 1e6, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()), "wall_s": wall}
+
+
+def bench_serve(M, n_req=2000, pool=16):
+    """The served form at 2000 requests/s (the first 400 requests of the stream
+    run once untimed on the same server, then the whole stream is timed)
+    beside the plain per-request path; then a load sweep (1000 requests at
+    4000 and 8000 requests/s and all at once, 32 pinned slots) to show
+    continuous batching as the queue fills."""
+    reqs = _requests(n_req, 6, pool)
+    px = sum(r[1].shape[0] * r[1].shape[1] for r in reqs)
+    srv = M.Server(arena_bytes=8 << 30, max_batch=64, compute_streams=2, max_queue=1 << 20)
+    served = _served_stats(M, srv, reqs, pool, px, 2000.0, reqs[:400])
+    plain = _plain_stats(M, reqs, px)
+    del reqs
+    sweep = []
+    for rate in (4000.0, 8000.0, None):
+        rs = _requests(1000, 7, 32, rate)
+        rpx = sum(r[1].shape[0] * r[1].shape[1] for r in rs)
+        sweep.append({"offered_req_s": rate if rate is not None else "all at t=0",
+                      "served": _served_stats(M, srv, rs, 32, rpx, rate, rs[:100]),
+                      "plain_per_request": _plain_stats(M, rs, rpx)})
+        del rs
+    srv.close()
+    return {"served": served, "plain_per_request": plain, "load_sweep": sweep,
             "workload": "Poisson 2000 req/s, %d requests, W~logU[256,3840], H~logU[256,2160], uint8/fp16, "
                         "CIELAB/HSI/SCT; pinned host buffers; latency = arrival -> output on host" % n_req}
 
@@ -508,10 +616,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--forms", default="all", choices=["all", "none", "lut"],
                     help="all: every form; none: the headline and its ceilings only; lut: the headline and the LUTs")
-    ap.add_argument("--cpu-px", type=int, default=1 << 25)
+    ap.add_argument("--cpu-px", type=int, default=1 << 23)
     ap.add_argument("--serve-requests", type=int, default=2000)
     a = ap.parse_args()
     if a.gpus != 1:
@@ -533,7 +641,10 @@ def main():
     def step():
         M.transform(x, params=p_lab, out=y)
 
-    log("CIELAB: %d warmup + %d timed steps" % (a.warmup, a.steps))
+    # untimed settling (at least 150 steps and 250 ms, whatever --warmup says), then the W counted
+    # warm-up steps, then the K timed ones
+    settle_steps, settle_ms = settle(step, 150, 250.0)
+    log("CIELAB: %d settling + %d warmup + %d timed steps" % (settle_steps, a.warmup, a.steps))
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -546,11 +657,13 @@ def main():
 
     k_spread = {}
     k_ms, k_med = time_kernel(step, a.steps, spread=k_spread)
-    achieved = 15.0 * n_px / (k_ms * 1e-3) / 1e9
     # launches per step under the library's split (equal launches of whole images, at most 2^26 pixels)
     n_launch = -(-n_px // (1 << 26))
     per_img = -(-N_IMG // n_launch)
     launches = -(-N_IMG // per_img)
+    # one launch averages step_ms / launches (the short gap between a step's launches included)
+    l_ms, l_med = k_ms / launches, k_med / launches
+    achieved = 15.0 * (n_px // launches) / (l_ms * 1e-3) / 1e9
 
     forms = {}
     c_ms, _ = time_kernel(lambda: M.stream_u8_to_f32(x, y, n_px), a.steps)
@@ -655,25 +768,53 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "RGB->CIELAB MACT, default (4,4) minimax rational; 64 x 1920x1080 uint8 HWC -> float32 HWC",
                    "images": N_IMG, "height": H, "width": W, "pixels_per_step": n_px,
-                   "max_dE_exhaustive_cube": acc.get("exhaustive_cube_oracle", {}).get("lab", {}).get("max")},
+                   "max_dE_exhaustive_cube": acc.get("exhaustive_cube_oracle", {}).get("lab", {}).get("max"),
+                   "settle_steps": settle_steps, "settle_ms": settle_ms, "served": served_summary(forms)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_hwc4<U8,F32,4,LAB>",
-                     # HIP events around each step: the library splits the batch into equal launches of
-                     # at most 2^26 pixels (two of 32 images here), so one launch averages kernel_ms /
-                     # launches_per_step, the gap between the two included
-                     "kernel_ms": k_ms, "kernel_ms_median": k_med, "kernel_ms_p10": k_spread["p10"],
-                     "kernel_ms_p90": k_spread["p90"], "algorithmic_bytes_per_px": 15,
-                     "launches_per_step": launches, "pixels_per_launch": n_px // launches,
-                     "launch_ms": k_ms / launches,
+                     # achieved: 15 B/px x pixels_per_launch / launch_ms.  HIP events around each
+                     # step on the launch stream (step_ms); the library splits the batch into equal
+                     # launches of at most 2^26 pixels (two of 32 images here), so one launch
+                     # averages step_ms / launches_per_step, the gap between the launches included
+                     "launch_ms": l_ms, "launch_ms_median": l_med,
+                     "algorithmic_bytes_per_px": 15, "launches_per_step": launches,
+                     "pixels_per_launch": n_px // launches,
+                     "step_ms": k_ms, "step_ms_median": k_med, "step_ms_p10": k_spread["p10"],
+                     "step_ms_p90": k_spread["p90"],
                      # the same run's 16-byte copy (equal reads and writes, a grid covering the copy once):
                      # the practical ceiling of this machine's HBM for a streaming kernel
                      "copy16_GBs": forms["copy16"]["GBs"],
-                     "frac_of_copy16": achieved / forms["copy16"]["GBs"]},
+                     "frac_of_copy16": achieved / forms["copy16"]["GBs"],
+                     # the same kernel on the 32 x 3840x2160 uint8 batch (four launches of 8 images)
+                     "r_32x4k": r4k_summary(forms)},
         "cpu_baseline": cpu,
         "accuracy": acc,
         "forms": forms,
     }
     print(json.dumps(line), flush=True)
+
+
+def r4k_summary(forms):
+    """The 32 x 4K leg's roofline figures (None without --forms all)."""
+    r = forms.get("lab_32x4k")
+    if not r:
+        return None
+    per = r["pixels"] // r["launches_per_step"]
+    return {"frac": r["frac_of_8TBs"], "achieved": r["GBs"], "launch_ms": r["launch_ms"],
+            "frac_median": 15.0 * r["pixels"] / r["ms_median"] / 8e9, "launches_per_step": r["launches_per_step"],
+            "pixels_per_launch": per, "step_ms": r["ms"], "Mpx_s": r["Mpx_s"]}
+
+
+def served_summary(forms):
+    """The served form's latency and throughput beside the plain per-request
+    path (None without --forms all)."""
+    sv = forms.get("serving")
+    if not sv:
+        return None
+    a, b = sv["served"], sv["plain_per_request"]
+    return {"p50_ms": a["p50_ms"], "p99_ms": a["p99_ms"], "Mpx_s": a["Mpx_s"], "mean_batch": a["mean_batch"],
+            "plain_p50_ms": b["p50_ms"], "plain_p99_ms": b["p99_ms"], "plain_Mpx_s": b["Mpx_s"],
+            "offered_req_s": a["offered_req_s"]}
 
 
 def kernel_hash():
