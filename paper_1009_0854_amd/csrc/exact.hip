@@ -178,7 +178,7 @@ extern "C" mact_status mact_transform_exact(int32_t xform, const mact_image* in,
     return fail(MACT_E_UNSUPPORTED, "mact_transform_exact: packed 8-bit HWC in and packed HWC out only");
   const int gamma = uses_gamma(xform) ? hi.gamma : MACT_GAMMA_NONE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const int64_t per = images_per_stream_launch(hi, ho.dtype);
+  const int64_t per = images_per_stream_launch(hi, ho);
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
     const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);

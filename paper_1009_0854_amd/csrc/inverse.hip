@@ -589,7 +589,7 @@ extern "C" mact_status mact_inverse(const mact_params* params, const mact_image*
   static const InvMat mi_lab = make_inv_mat(true), mi_luv = make_inv_mat(false);
   const InvMat& mi = params->xform == MACT_LUV ? mi_luv : mi_lab;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  const int64_t per = images_per_stream_launch(hi, ho.dtype);
+  const int64_t per = images_per_stream_launch(hi, ho);
   // float32 or float16 out for both 4-pixel paths
   const bool fast = hi.dtype == MACT_F32 && hi.layout == MACT_HWC && ho.layout == MACT_HWC && hi.packed && ho.packed;
   const bool chw4 = (hi.dtype == MACT_F32 || hi.dtype == MACT_F16) && hi.layout == MACT_CHW &&

@@ -35,8 +35,11 @@ int64_t images_per_launch(const HostImage& h);
 // Measured in one process against whole-batch launches: CIELAB 64 x 1080p in
 // two launches +1.3%, 32 x 4K in four +2.7%, the float32-input forms and the
 // inverses +1 to +1.6%.  float16 outputs, whose kernels are bound by the VALU,
-// lost 1.5% to the extra launch and keep images_per_launch.
-int64_t images_per_stream_launch(const HostImage& in, int out_dtype);
+// lost 1.5% to the extra launch and keep images_per_launch.  The count is
+// rounded up so that every launch starts where the coalesced kernels'
+// alignment holds (images with an odd pixel count would otherwise send every
+// launch after the first to the one-pixel kernel).
+int64_t images_per_stream_launch(const HostImage& in, const HostImage& out);
 
 // Coefficients rounded to float32 and zero padded; returns the padded degree
 // (5 or 7) the kernels are instantiated for, and the highest degree actually

@@ -571,7 +571,7 @@ static mact_status interp_common(const char* what, const float* dev_lut, int32_t
   if ((s = check_same_shape(hi, ho, nm)) != MACT_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const f4* lut = reinterpret_cast<const f4*>(dev_lut);
-  const int64_t per = images_per_stream_launch(hi, ho.dtype);
+  const int64_t per = images_per_stream_launch(hi, ho);
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
     const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);

@@ -119,12 +119,26 @@ int64_t images_per_launch(const HostImage& h) {
   return std::max<int64_t>(1, ((1ll << 31) - 1) / hw);
 }
 
-int64_t images_per_stream_launch(const HostImage& in, int out_dtype) {
+int64_t images_per_stream_launch(const HostImage& in, const HostImage& out) {
   const int64_t most = images_per_launch(in);
-  if (out_dtype != MACT_F32) return most;
+  if (out.dtype != MACT_F32) return most;
   const int64_t hw = in.W * in.H;
   const int64_t launches = (in.N * hw + (1ll << 26) - 1) >> 26;
-  return std::max<int64_t>(1, std::min<int64_t>(most, (in.N + launches - 1) / launches));
+  int64_t per = std::max<int64_t>(1, std::min<int64_t>(most, (in.N + launches - 1) / launches));
+  // every launch after the first starts per images further on: keep that offset a multiple of
+  // the coalesced kernels' alignment (input: 4 bytes, 16 for float32 HWC, 4 elements of a CHW
+  // plane; output: 16 bytes), rounding the count up, or a launch would fall back to the
+  // one-pixel kernel
+  const int64_t need_in = in.layout == MACT_CHW ? 4 * (int64_t)in.esize : in.dtype == MACT_F32 ? 16 : 4;
+  const int64_t in_bytes = in.bs * (int64_t)in.esize, out_bytes = out.bs * (int64_t)out.esize;
+  for (int64_t q = 1; q <= 16; q *= 2) {
+    if ((q * in_bytes) % need_in == 0 && (q * out_bytes) % 16 == 0) {
+      const int64_t up = (per + q - 1) / q * q;
+      if (up <= most) per = up;
+      break;
+    }
+  }
+  return per;
 }
 
 int pack_coef(const mact_params& p, KCoef* k, int* exact) {
@@ -1072,7 +1086,7 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   // row-strided CHW -> packed HWC or CHW: rows of a multiple of 4 pixels, strides of whole 4-element groups
   const bool chw_rows4 = hi.layout == MACT_CHW && !hi.packed && f_out && ho.packed && hi.W % 4 == 0 &&
                          hi.rs % 4 == 0 && hi.ps % 4 == 0 && hi.bs % 4 == 0 && hi.ps < ((int64_t)1 << 32);
-  const int64_t per = images_per_stream_launch(hi, ho.dtype);
+  const int64_t per = images_per_stream_launch(hi, ho);
   for (int64_t n0 = 0; n0 < hi.N; n0 += per) {
     const int64_t cnt = std::min(per, hi.N - n0);
     const uint32_t n_px = (uint32_t)(cnt * hi.W * hi.H);
