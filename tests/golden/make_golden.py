@@ -8,7 +8,10 @@ library's default degrees and intervals, FP64 evaluation).
 CIELAB: Delta E*ab (Sec. 3.2.1).  HSI: D_HSI (Sec. 3.3.1) and the hue error.
 SCT: Delta E*ab through the inverse SCT (Sec. 3.4.1) and the angle errors.
 CIELUV: Delta E*uv (the CIE 1976 L*u*v* distance; Sec. 4 names the transform).
-LUTs: Delta E*ab of the CIELAB LUT at 9^3, 17^3 and 33^3 (Sec. 3.5.3).
+LUTs: Delta E*ab of the CIELAB LUT at 9^3, 17^3 and 33^3 (Sec. 3.5.3); for
+the HSI LUTs D_HSI and the hue error, for the SCT LUTs Delta E*ab through the
+inverse SCT and the errors of angles A and B (all four methods, 9^3, 17^3 and
+33^3; angular channels interpolated as unit vectors).
 """
 import json
 import os
@@ -34,7 +37,7 @@ def fits():
     }
 
 
-def _chunk(v8, F, luts):
+def _chunk(v8, F, luts, xluts):
     x = v8 / 255.0
     out = {}
     ex_lab = colour.rgb_to_lab(x)
@@ -61,20 +64,39 @@ def _chunk(v8, F, luts):
         o, _ = lut.interp(L, "lab", key[0], v8=v8)
         d = colour.delta_e(o, ex_lab)
         out["lut_%s_%d" % key] = (d.sum(), d.max())
+    for (xf, m, N), L in xluts.items():
+        o, _ = lut.interp(L, xf, m, v8=v8)
+        tag = "lut_%s_%s_%d" % (xf, m, N)
+        if xf == "hsi":
+            d = colour.d_hsi(o, ex_hsi)
+            a = colour.angle_diff(o[:, 0], ex_hsi[:, 0])
+            out[tag] = (d.sum(), d.max())
+            out[tag + "_dH"] = (a.sum(), a.max())
+        else:
+            d = colour.sct_delta_e(o, ex_sct)
+            da = colour.angle_diff(o[:, 1], ex_sct[:, 1])
+            db = colour.angle_diff(o[:, 2], ex_sct[:, 2])
+            out[tag] = (d.sum(), d.max())
+            out[tag + "_dA"] = (da.sum(), da.max())
+            out[tag + "_dB"] = (db.sum(), db.max())
     return out
 
 
 def main():
     F = fits()
-    luts = {(m, N): lut.build("lab", N) for m in ("trilinear", "prism", "pyramidal", "tetrahedral") for N in (9, 17, 33)}
-    parts = cube_map(_chunk, F, luts)
+    methods = ("trilinear", "prism", "pyramidal", "tetrahedral")
+    luts = {(m, N): lut.build("lab", N) for m in methods for N in (9, 17, 33)}
+    xluts = {(xf, m, N): lut.build(xf, N) for xf in ("hsi", "sct") for m in methods for N in (9, 17, 33)}
+    parts = cube_map(_chunk, F, luts, xluts)
     n = float(1 << 24)
     res = {}
     for k in parts[0]:
         res[k] = {"mean": float(sum(p[k][0] for p in parts) / n), "max": float(max(p[k][1] for p in parts))}
     res["fits"] = {k: {"n": len(f.p) - 1, "m": len(f.q) - 1, "lo": f.a, "hi": f.b, "eps": f.eps} for k, f in F.items()}
     res["what"] = ("oracle FP64, all 2^24 8-bit colours, BT.709 inverse gamma; lab/sct: Delta E*ab, hsi: D_HSI, "
-                   "hsi_dH / sct_dA / sct_dB: angle errors in radians; luv: Delta E*uv; lut_*: CIELAB LUT Delta E*ab")
+                   "hsi_dH / sct_dA / sct_dB: angle errors in radians; luv: Delta E*uv; lut_<method>_<N>: CIELAB "
+                   "LUT Delta E*ab; lut_hsi_*: D_HSI (_dH hue error); lut_sct_*: Delta E*ab through the inverse SCT "
+                   "(_dA, _dB angle errors)")
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "mact_accuracy.json")
     with open(path, "w") as f:
         json.dump(res, f, indent=1, sort_keys=True)
