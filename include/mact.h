@@ -421,12 +421,15 @@ mact_status lut_cache_interp(const float* dev_cache, int32_t n, int32_t xform, i
 
 /* Launch shape picked by the autotuner (or given by the caller). */
 typedef struct mact_tune {
-  int32_t block;      /* threads per workgroup: 64, 128, 256, 512, 1024 */
-  int32_t tile;       /* pixels per work tile: multiple of the block, >= block */
-  int32_t vec;        /* pixels per lane per step on the packed HWC paths: 1 or 4 */
+  int32_t block;      /* threads per workgroup of the general batched kernel: 64, 128, 256, 512, 1024
+                         (the class kernels of the vector path use 256) */
+  int32_t tile;       /* pixels per work tile: multiple of 256 and of the block, >= block */
+  int32_t vec;        /* 4: packed 8-bit, 16-bit and float16 HWC images with packed float32 HWC
+                         output run through the class kernels, 4 pixels per lane; 1: every image
+                         through the general kernel, one pixel per lane */
   int32_t waves_per_cu; /* 1..64: persistent grid = CUs x this / (block / 64) workgroups, capped
                            by the tile count; 0: one workgroup per tile */
-  int32_t one_launch; /* 1: the whole tile list in one launch; 0: equal launches of at most
+  int32_t one_launch; /* 1: each class's tiles in one launch; 0: equal launches of at most
                          2^26 pixels of tiles each (a large batch becomes several kernel nodes
                          of one graph: streaming launches of that size measured faster) */
 } mact_tune;
@@ -435,15 +438,19 @@ typedef struct mact_batch_plan mact_batch_plan;
 
 /* A batched transform of `count` images of any sizes, element types, layouts
    and transforms (image i uses params[i], in[i], out[i]) captured in one HIP
-   graph: the images are cut into tiles of `tile` pixels, and either a
-   persistent grid sized to the GPU walks the tile list (waves_per_cu > 0) or
-   one workgroup takes each tile (waves_per_cu = 0), in one launch
+   graph.  The images are cut into tiles of `tile` pixels and grouped into
+   classes: images of one element type (packed 8-bit, float16 or 16-bit HWC in,
+   packed float32 HWC out), one transform, one coefficient set and one transfer
+   function form a class run by a kernel specialised for it (the plain hot
+   kernel's shape); every other image goes through a general kernel.  Either a
+   persistent grid sized to the GPU walks a class's tiles (waves_per_cu > 0)
+   or one workgroup takes each tile (waves_per_cu = 0), in one launch per class
    (one_launch = 1) or in equal launches of at most 2^26 pixels.  The
    autotuner chooses among all of these by time on the batch itself; on MI355X
-   it picks full-grid split launches, which measured faster than one
-   persistent launch (a persistent grid walking a streaming workload holds
-   fewer bytes in flight).  The per-pixel arithmetic is that of
-   mact_transform, so every output is bitwise equal to the plain call's.  The
+   it picks one workgroup per 2048-pixel tile, which measured faster than a
+   persistent grid (a persistent grid walking a streaming workload holds fewer
+   bytes in flight).  The per-pixel arithmetic is that of mact_transform, so
+   every output is bitwise equal to the plain call's.  The
    plan copies the descriptors to device memory (library-owned), picks the
    launch shape with the autotuner when `tune` is NULL (timings on `hip_stream`,
    cached per GPU and shape class; a JSON cache file is read and written when the

@@ -66,6 +66,10 @@ mact_status make_batch_descs(const mact_params& p, const mact_image* in, const m
 hipError_t launch_batch_kernel(const BDesc* d_descs, const KCoef* d_coefs, const uint32_t* d_tiles, int32_t count,
                                uint32_t total_tiles, const mact_tune& tune, int deg, hipStream_t st,
                                const uint32_t* d_tile_img = nullptr);
+// The same over tiles [first, end) of the list only.
+hipError_t launch_batch_kernel_range(const BDesc* d_descs, const KCoef* d_coefs, const uint32_t* d_tiles, int32_t count,
+                                     uint32_t first, uint32_t end, const mact_tune& tune, int deg, hipStream_t st,
+                                     const uint32_t* d_tile_img);
 // Grid of the batched kernel for a tune and a tile count.
 unsigned batch_grid(const mact_tune& tune, uint32_t total_tiles);
 // Tile list: tile_start[i] = first tile of descriptor i; returns the total.

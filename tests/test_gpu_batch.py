@@ -267,3 +267,29 @@ def test_autotune_cache_file_round_trip(tmp_path):
     cache.write_text('{"%s": [%d, %d, %d, %d]}' % (key, 256, 4096, 4, 7))
     third = child()
     assert third["tune"] == [256, 4096, 4, 7, 0] and third["same"]
+
+
+def test_classes_by_coefficients_and_transfer_function(M):
+    # 8-bit images of one transform but different coefficient sets (the library's fit, the paper's
+    # printed (4,4) and (2,2) rows) and transfer functions fall into separate classes, each run with
+    # its own kernel arguments; every image equals its plain call bitwise, in any interleaving
+    g = torch.Generator(device="cuda").manual_seed(23)
+    sets = [M.default_params("lab"), M.make_params("lab", [M.paper_approx(M.FN_CBRT, 4, 4)]),
+            M.make_params("lab", [M.paper_approx(M.FN_CBRT, 2, 2)]), M.default_params("hsi")]
+    params, ins, outs, gams = [], [], [], []
+    for i in range(16):
+        h, w = 37 + 13 * i, 301 - 7 * i
+        params.append(sets[i % 4])
+        ins.append(torch.randint(0, 256, (h, w, 3), dtype=torch.uint8, device="cuda", generator=g))
+        outs.append(torch.empty((h, w, 3), dtype=torch.float32, device="cuda"))
+        gams.append(("bt709", "srgb")[(i // 4) % 2] if i % 4 != 3 else "none")
+    ref = [M.transform(x, params=p, gamma=gm) for p, x, gm in zip(params, ins, gams)]
+    for tune in (None, M.Tune(256, 2048, 4, 0, 0), M.Tune(256, 4096, 4, 8, 1)):
+        plan = M.BatchPlan(params, ins, outs, None, gams, tune=tune)
+        for o in outs:
+            o.fill_(float("nan"))
+        plan.launch(use_graph=True)
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, ref)):
+            assert torch.equal(o, r), (i, tune)
+        plan.close()
