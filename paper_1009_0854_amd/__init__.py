@@ -16,9 +16,10 @@ from ._abi import (CHW, E_BUSY, E_NOCONV, F16, F32, FN_ACOS, FN_ASIN2, FN_ATAN, 
 
 __all__ = ["fit", "dark_end_weight", "default_approx", "paper_approx", "default_params", "make_params", "image", "transform",
            "transform_exact",
-           "transform_backward", "inverse_params", "inverse", "error_stats", "lut_bytes", "lut_build",
+           "transform_backward", "inverse_params", "inverse", "error_stats", "error_stats_noalloc", "lut_bytes", "lut_build",
            "lut_interp", "lut_cells_bytes", "lut_cells_build", "lut_cells_interp",
-           "lut_cache_bytes", "lut_cache_build", "lut_cache_interp", "BatchPlan", "batch_run",
+           "lut_cache_bytes", "lut_cache_build", "lut_cache_interp",
+           "approx_to_dict", "approx_from_dict", "save_approx", "load_approx", "BatchPlan", "batch_run",
            "Server", "stream_u8_to_f32", "copy", "MactError", "MactLab"]
 
 
@@ -92,6 +93,59 @@ def default_params(xform, decode=False):
             raise ValueError("decode applies to CIELAB and CIELUV only")
         p.f[1] = default_approx(A.FN_DEC709)
     return p
+
+
+# ---------------------------------------------------------------- persisted coefficient sets
+
+_FN_NAMES = {A.FN_CBRT: "cbrt", A.FN_ATAN_SQRT3: "atan_sqrt3", A.FN_ASIN2: "asin2", A.FN_ACOS: "acos",
+             A.FN_ATAN: "atan", A.FN_ATANC: "atanc", A.FN_SIN: "sin", A.FN_COS: "cos", A.FN_ENC709: "enc709",
+             A.FN_DEC709: "dec709"}
+
+
+def approx_to_dict(a):
+    """One approximation as plain JSON data: function, interval, degrees,
+    numerator and denominator coefficients, error, alternation points and the
+    fitter's iteration count and convergence flag."""
+    return {"function": _FN_NAMES.get(a.fn, "fn%d" % a.fn), "fn": int(a.fn), "n": int(a.n), "m": int(a.m),
+            "interval": [a.lo, a.hi], "p": [a.p[k] for k in range(a.n + 1)],
+            "q": [a.q[k] for k in range(a.m + 1)], "eps": a.eps,
+            "alternation": [a.alt[k] for k in range(a.n_alt)], "iters": int(a.iters), "converged": int(a.converged)}
+
+
+def approx_from_dict(d):
+    """The mact_approx that approx_to_dict described (every value exactly:
+    JSON keeps a double's shortest round-trip form)."""
+    a = Approx()
+    a.fn, a.n, a.m = int(d["fn"]), int(d["n"]), int(d["m"])
+    if not (0 <= a.n <= 7 and 0 <= a.m <= 7 and len(d["p"]) == a.n + 1 and len(d["q"]) == a.m + 1):
+        raise ValueError("approx_from_dict: degrees and coefficient counts disagree")
+    if len(d["alternation"]) > 18:
+        raise ValueError("approx_from_dict: more than 18 alternation points")
+    a.lo, a.hi = float(d["interval"][0]), float(d["interval"][1])
+    for k, v in enumerate(d["p"]):
+        a.p[k] = float(v)
+    for k, v in enumerate(d["q"]):
+        a.q[k] = float(v)
+    a.eps = float(d["eps"])
+    for k, v in enumerate(d["alternation"]):
+        a.alt[k] = float(v)
+    a.n_alt = len(d["alternation"])
+    a.iters, a.converged = int(d["iters"]), int(d["converged"])
+    return a
+
+
+def save_approx(path, approxes):
+    """Writes a named set of approximations ({name: mact_approx}) to a JSON file."""
+    import json
+    with open(path, "w") as f:
+        json.dump({k: approx_to_dict(v) for k, v in approxes.items()}, f, indent=1, sort_keys=True)
+
+
+def load_approx(path):
+    """Reads a set written by save_approx: {name: mact_approx}."""
+    import json
+    with open(path) as f:
+        return {k: approx_from_dict(v) for k, v in json.load(f).items()}
 
 
 def make_params(xform, approxes, out_mode=0):
