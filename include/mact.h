@@ -44,7 +44,8 @@ enum {
   MACT_E_DEVICE = -3,      /* a HIP runtime call failed (detail in mact_last_error) */
   MACT_E_NOMEM = -4,       /* a library-owned allocation failed */
   MACT_E_UNSUPPORTED = -5, /* a valid but unimplemented combination */
-  MACT_E_BUSY = -6         /* serving: the request cannot be admitted yet */
+  MACT_E_BUSY = -6,        /* serving: the request cannot be admitted yet */
+  MACT_E_CANCELLED = -7    /* serving: the request was withdrawn before admission */
 };
 
 /* Static description of a status code. */
@@ -518,6 +519,7 @@ typedef struct mact_server_stats {
   double mean_batch;              /* requests per launch */
   double device_busy_ms;          /* sum of batch kernel times */
   int64_t failed;                 /* requests completed with an error status */
+  int64_t cancelled;              /* requests withdrawn before admission (mact_server_cancel) */
 } mact_server_stats;
 
 typedef struct mact_server mact_server;
@@ -536,8 +538,16 @@ mact_status mact_server_submit(mact_server* srv, const mact_request* req, int64_
 mact_status mact_server_poll(mact_server* srv, int64_t id, int32_t* done);
 /* Block until request `id` completes or timeout_ms passes (MACT_E_BUSY).
    Returns the request's status: MACT_OK, or the error it completed with
-   (MACT_E_INVALID, MACT_E_DEVICE) as poll reports it. */
+   (MACT_E_INVALID, MACT_E_DEVICE, MACT_E_CANCELLED) as poll reports it. */
 mact_status mact_server_wait(mact_server* srv, int64_t id, int32_t timeout_ms);
+/* Withdraws request `id` if it is still waiting for admission (no device
+   memory, copy or launch has been given to it yet): it completes at once with
+   MACT_E_CANCELLED, which poll and wait then report, and the engine never
+   touches its host buffers again; the call returns MACT_OK.  A request already
+   admitted (its copies or batch may be in flight, or it has completed) runs to
+   completion and the call returns MACT_E_BUSY; MACT_E_INVALID for an unknown
+   id. */
+mact_status mact_server_cancel(mact_server* srv, int64_t id);
 /* Latency of a completed request in milliseconds (submit -> output on host);
    the request's error status if it completed with one. */
 mact_status mact_server_latency(mact_server* srv, int64_t id, double* ms);

@@ -533,6 +533,17 @@ class Server:
             self._keep.pop(rid, None)
         A.check(st)
 
+    def cancel(self, rid):
+        """Withdraws request `rid` if it is still waiting for admission (True;
+        it then completes with MACT_E_CANCELLED); False if it was already
+        admitted and runs to completion."""
+        st = lib().mact_server_cancel(self._h, int(rid))
+        if st == E_BUSY:
+            return False
+        A.check(st)
+        self._keep.pop(rid, None)
+        return True
+
     def latency_ms(self, rid):
         v = ctypes.c_double()
         A.check(lib().mact_server_latency(self._h, int(rid), ctypes.byref(v)))

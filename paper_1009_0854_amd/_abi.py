@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
                         "libmact_san.so" if os.environ.get("MACT_LIB_VARIANT") == "san" else "libmact.so")
 
 # status codes
-OK, E_INVALID, E_NOCONV, E_DEVICE, E_NOMEM, E_UNSUPPORTED, E_BUSY = 0, -1, -2, -3, -4, -5, -6
+OK, E_INVALID, E_NOCONV, E_DEVICE, E_NOMEM, E_UNSUPPORTED, E_BUSY, E_CANCELLED = 0, -1, -2, -3, -4, -5, -6, -7
 # functions
 FN_CBRT, FN_ATAN_SQRT3, FN_ASIN2, FN_ACOS, FN_ATAN, FN_ATANC, FN_SIN, FN_COS, FN_ENC709, FN_DEC709 = range(10)
 # transforms, element types, layouts, transfer functions, LUT methods
@@ -69,7 +69,7 @@ class Request(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", c_int64), ("completed", c_int64), ("rejected", c_int64), ("batches", c_int64),
                 ("p50_ms", c_double), ("p99_ms", c_double), ("mean_ms", c_double), ("mean_batch", c_double),
-                ("device_busy_ms", c_double), ("failed", c_int64)]
+                ("device_busy_ms", c_double), ("failed", c_int64), ("cancelled", c_int64)]
 
 
 class ErrorStats(ctypes.Structure):
@@ -116,6 +116,7 @@ SIGNATURES = {
     "mact_server_wait": (c_int32, [c_void_p, c_int64, c_int32]),
     "mact_server_latency": (c_int32, [c_void_p, c_int64, POINTER(c_double)]),
     "mact_server_stats_get": (c_int32, [c_void_p, POINTER(ServerStats)]),
+    "mact_server_cancel": (c_int32, [c_void_p, c_int64]),
     "mact_server_destroy": (c_int32, [c_void_p]),
     "mact_stream_u8_to_f32": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
     "mact_copy": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),

@@ -188,6 +188,7 @@ extern "C" const char* mact_status_str(mact_status s) {
     case MACT_E_NOMEM: return "out of memory";
     case MACT_E_UNSUPPORTED: return "unsupported combination";
     case MACT_E_BUSY: return "busy";
+    case MACT_E_CANCELLED: return "cancelled";
   }
   return "unknown status";
 }

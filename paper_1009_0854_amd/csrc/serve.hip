@@ -118,6 +118,9 @@ struct Req {
   mact_status status = MACT_OK;
   char err[256] = "";
   std::atomic<bool> done{false};
+  // 0 waiting for admission, 1 admitted, 2 cancelled: the scheduler (admission) and
+  // mact_server_cancel each move it out of 0 once, so exactly one of them owns the request
+  std::atomic<int> phase{0};
 };
 
 struct Slot {
@@ -159,7 +162,7 @@ struct mact_server {
   std::condition_variable cv_done;
   std::mutex mu_stats;  // lat_ms, completed, batches, batched_reqs, busy_ms
   std::vector<double> lat_ms;
-  int64_t completed = 0, failed = 0, batches = 0, batched_reqs = 0;
+  int64_t completed = 0, failed = 0, cancelled = 0, batches = 0, batched_reqs = 0;
   double busy_ms = 0.0;
 
   // the scheduler's own
@@ -239,6 +242,12 @@ bool mact_server::admit() {
   bool any = false;
   while (!queued.empty()) {
     Req* q = queued.front();
+    if (q->phase.load() == 2) {  // cancelled while waiting: mact_server_cancel has completed it
+      queued.pop_front();
+      waiting.fetch_sub(1);
+      any = true;
+      continue;
+    }
     size_t in_off, out_off;
     if (!arena->alloc(q->in_bytes, &in_off)) break;
     if (!arena->alloc(q->out_bytes, &out_off)) {
@@ -247,6 +256,13 @@ bool mact_server::admit() {
     }
     queued.pop_front();
     waiting.fetch_sub(1);
+    int expect = 0;
+    if (!q->phase.compare_exchange_strong(expect, 1)) {  // cancelled just now
+      arena->release(in_off, q->in_bytes);
+      arena->release(out_off, q->out_bytes);
+      any = true;
+      continue;
+    }
     q->in_off = in_off;
     q->out_off = out_off;
     q->placed = true;
@@ -660,6 +676,30 @@ extern "C" mact_status mact_server_wait(mact_server* s, int64_t id, int32_t time
   return MACT_OK;
 }
 
+extern "C" mact_status mact_server_cancel(mact_server* s, int64_t id) {
+  clear_error();
+  if (!s) return fail(MACT_E_INVALID, "mact_server_cancel: NULL server");
+  Req* q = find_req(s, id);
+  if (!q) return fail(MACT_E_INVALID, "mact_server_cancel: unknown request %lld", (long long)id);
+  int expect = 0;
+  if (!q->phase.compare_exchange_strong(expect, 2))
+    return fail(MACT_E_BUSY, "mact_server_cancel: request %lld already admitted", (long long)id);
+  // the request is ours: complete it; the scheduler drops it from its queue without touching it
+  std::snprintf(q->err, sizeof q->err, "request %lld cancelled before admission", (long long)id);
+  q->status = MACT_E_CANCELLED;
+  q->t_done = Clock::now();
+  {
+    std::lock_guard<std::mutex> g(s->mu_done);
+    q->done.store(true);
+  }
+  {
+    std::lock_guard<std::mutex> g(s->mu_stats);
+    ++s->cancelled;
+  }
+  s->cv_done.notify_all();
+  return MACT_OK;
+}
+
 extern "C" mact_status mact_server_latency(mact_server* s, int64_t id, double* ms) {
   clear_error();
   if (!s || !ms) return fail(MACT_E_INVALID, "mact_server_latency: NULL argument");
@@ -683,6 +723,7 @@ extern "C" mact_status mact_server_stats_get(mact_server* s, mact_server_stats* 
   std::lock_guard<std::mutex> g(s->mu_stats);
   st->completed = s->completed;
   st->failed = s->failed;
+  st->cancelled = s->cancelled;
   st->batches = s->batches;
   st->mean_batch = s->batches ? (double)s->batched_reqs / s->batches : 0.0;
   st->device_busy_ms = s->busy_ms;

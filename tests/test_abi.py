@@ -65,8 +65,9 @@ def test_struct_layouts_match_the_header(M, tmp_path):
 
 def test_status_strings(M):
     L = M.lib()
-    for s in range(0, -7, -1):
-        assert L.mact_status_str(s)
+    for s in range(0, -8, -1):
+        assert L.mact_status_str(s) != b"unknown status"
+    assert L.mact_status_str(-7) == b"cancelled" and L.mact_status_str(-8) == b"unknown status"
     assert b"gfx950" in L.mact_version()
 
 
@@ -385,6 +386,7 @@ def test_batch_and_server_validation_without_gpu(M):
     bad = A.ServerConfig.from_buffer_copy(cfg)
     bad.fail_request = -1
     assert L.mact_server_create(ctypes.byref(bad), ctypes.byref(h)) == A.E_INVALID
+    assert L.mact_server_cancel(None, 1) == A.E_INVALID
 
 
 def test_server_submit_refuses_mismatched_host_tensors(M):
