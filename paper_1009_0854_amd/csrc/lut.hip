@@ -256,6 +256,29 @@ __device__ __forceinline__ void lut_px_cache(const float* __restrict__ cache, ui
   }
 }
 
+// fma of a float4 by a scalar weight: w v + a, channel by channel.
+__device__ __forceinline__ f4 fma4(float w, f4 v, f4 a) {
+  return f4{__builtin_fmaf(w, v.x, a.x), __builtin_fmaf(w, v.y, a.y), __builtin_fmaf(w, v.z, a.z),
+            __builtin_fmaf(w, v.w, a.w)};
+}
+
+// The outputs from the weighted sums: linear channels as they are, angles
+// from their (cos, sin) resultants.
+template <int XF>
+__device__ __forceinline__ void lut_out(f4 a0, float a1, float o[3]) {
+  if (XF == MACT_LAB || XF == MACT_LUV) {
+    o[0] = a0.x; o[1] = a0.y; o[2] = a0.z;
+  } else if (XF == MACT_HSI) {
+    float h = atan2f(a0.y, a0.x);
+    if (h < 0.0f) h += kTwoPif;
+    o[0] = h; o[1] = a0.z; o[2] = a0.w;
+  } else {
+    o[0] = a1;
+    o[1] = atan2f(a0.y, a0.x);
+    o[2] = atan2f(a0.w, a0.z);
+  }
+}
+
 // One pixel: the method's weighted corner sum at cell i, fractions f.  FORM
 // kCells: `nodes` is the cell-major form; kCache: the caching records.
 // `lp`: SCT's L plane (one float per entry of `nodes`); unused otherwise.
@@ -273,26 +296,88 @@ __device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, const float
   Corners<METHOD>::get(f[0], f[1], f[2], CELL ? 4u : N * N, CELL ? 2u : N, off, w);
   f4 a0 = {0.0f, 0.0f, 0.0f, 0.0f};
   float a1 = 0.0f;
+  if (METHOD == MACT_TRILINEAR) {
+    // the corners (c = 4 dR + 2 dG + dB) summed per dB: the product at dR dG = 00, then fused
+    // multiply-adds at 01, 10, 11; the dB = 0 and dB = 1 sums added last.  The two-lane kernel
+    // below sums in this order, so every trilinear path gives the same bits
+    f4 ch[2];
+    float cu[2] = {0.0f, 0.0f};
 #pragma unroll
-  for (int c = 0; c < Corners<METHOD>::K; ++c) {
-    const uint32_t n = base + off[c];
-    const f4 v0 = nodes[n];
-    a0.x = __builtin_fmaf(w[c], v0.x, a0.x);
-    a0.y = __builtin_fmaf(w[c], v0.y, a0.y);
-    a0.z = __builtin_fmaf(w[c], v0.z, a0.z);
-    a0.w = __builtin_fmaf(w[c], v0.w, a0.w);
-    if (XF == MACT_SCT) a1 = __builtin_fmaf(w[c], lp[n], a1);
-  }
-  if (XF == MACT_LAB || XF == MACT_LUV) {
-    o[0] = a0.x; o[1] = a0.y; o[2] = a0.z;
-  } else if (XF == MACT_HSI) {
-    float h = atan2f(a0.y, a0.x);
-    if (h < 0.0f) h += kTwoPif;
-    o[0] = h; o[1] = a0.z; o[2] = a0.w;
+    for (int b = 0; b < 2; ++b) {
+      const uint32_t n0 = base + off[b], n1 = base + off[2 + b], n2 = base + off[4 + b], n3 = base + off[6 + b];
+      ch[b] = fma4(w[6 + b], nodes[n3], fma4(w[4 + b], nodes[n2], fma4(w[2 + b], nodes[n1], w[b] * nodes[n0])));
+      if (XF == MACT_SCT)
+        cu[b] = __builtin_fmaf(w[6 + b], lp[n3], __builtin_fmaf(w[4 + b], lp[n2], __builtin_fmaf(w[2 + b], lp[n1], w[b] * lp[n0])));
+    }
+    a0 = ch[0] + ch[1];
+    a1 = cu[0] + cu[1];
   } else {
-    o[0] = a1;
-    o[1] = atan2f(a0.y, a0.x);
-    o[2] = atan2f(a0.w, a0.z);
+#pragma unroll
+    for (int c = 0; c < Corners<METHOD>::K; ++c) {
+      const uint32_t n = base + off[c];
+      const f4 v0 = nodes[n];
+      a0.x = __builtin_fmaf(w[c], v0.x, a0.x);
+      a0.y = __builtin_fmaf(w[c], v0.y, a0.y);
+      a0.z = __builtin_fmaf(w[c], v0.z, a0.z);
+      a0.w = __builtin_fmaf(w[c], v0.w, a0.w);
+      if (XF == MACT_SCT) a1 = __builtin_fmaf(w[c], lp[n], a1);
+    }
+  }
+  lut_out<XF>(a0, a1, o);
+}
+
+// The value of lane l ^ 1: a DPP quad permutation (1, 0, 3, 2), no LDS access.
+__device__ __forceinline__ float swap1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// Trilinear interpolation of a 256-pixel chunk with 2 lanes per pixel (grids
+// read through the L2).  In each of 8 rounds the lane pair h takes pixel
+// 32 r + h; lane bit 0 is dB, and each lane gathers its 4 corners (dR dG = 00,
+// 01, 10, 11 at that dB).  The two lanes' corners of one (dR, dG) are
+// neighbours along B, one 32-byte run (the cell-major form: one 128-byte run
+// per pixel), so an instruction touches about 32 lines instead of 64 and the
+// vector L1, whose accesses bound these kernels, does about half the work.
+// Each lane sums its corners as a product at dR dG = 00 and fused multiply-adds
+// at 01, 10, 11; the pair adds its two sums: lut_px's order, so the results
+// are lut_px's bits.  The pixel of round r ends in lane 2 h + (r mod
+// 2), slot r / 2.  s8: the chunk's 768 input bytes.
+template <int XF, int FORM>
+__device__ __forceinline__ void tri_pairs(const f4* __restrict__ nodes, const float* __restrict__ lp, uint32_t N,
+                                          const uint8_t* s8, uint32_t lane, f4 acc[4], float acc1[4]) {
+  constexpr bool CELL = FORM == kCells;
+  const uint32_t db = lane & 1u, h = lane >> 1;
+  const uint32_t sR = CELL ? 4u : N * N, sG = CELL ? 2u : N;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t P = 32u * r + h;
+    uint32_t i0, i1, i2;
+    float f0, f1, f2;
+    locate_u8(s8[3 * P], N, i0, f0);
+    locate_u8(s8[3 * P + 1], N, i1, f1);
+    locate_u8(s8[3 * P + 2], N, i2, f2);
+    const float r0 = 1.0f - f0, g0 = 1.0f - f1, wb = db ? f2 : 1.0f - f2;
+    const uint32_t base = (CELL ? ((i0 * (N - 1) + i1) * (N - 1) + i2) * 8u : (i0 * N + i1) * N + i2) + db;
+    uint32_t n[4];
+    float w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // q = 2 dR + dG
+      n[q] = base + (q >> 1) * sR + (q & 1) * sG;
+      w[q] = ((q >> 1) ? f0 : r0) * ((q & 1) ? f1 : g0) * wb;
+    }
+    f4 a = fma4(w[3], nodes[n[3]], fma4(w[2], nodes[n[2]], fma4(w[1], nodes[n[1]], w[0] * nodes[n[0]])));
+    float b = XF == MACT_SCT ? __builtin_fmaf(w[3], lp[n[3]], __builtin_fmaf(w[2], lp[n[2]], __builtin_fmaf(w[1], lp[n[1]], w[0] * lp[n[0]])))
+                             : 0.0f;
+    // plus the partner's sum (a float sum does not depend on the order of its two terms)
+    a = a + f4{swap1(a.x), swap1(a.y), swap1(a.z), swap1(a.w)};
+    if (XF == MACT_SCT) b = b + swap1(b);
+    if (db == (uint32_t)(r & 1)) {
+      acc[r >> 1] = a;
+      acc1[r >> 1] = b;
+    }
+    // one round's gathers in flight at a time: more fit in registers only at a lower occupancy,
+    // and measured slower (cell-major CIELAB and HSI 33^3: 16-18%)
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -385,9 +470,12 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
     if (!SPREAD) {
       float o[12];
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j) {
         lut_px_u8<METHOD, XF, FORM>(nodes, lp, N, byte_of(w, 3 * j), byte_of(w, 3 * j + 1), byte_of(w, 3 * j + 2),
                                     o + 3 * j);
+        // SCT's trilinear sums: two pixels' gathers in flight at most, or the corners outgrow the registers
+        if (METHOD == MACT_TRILINEAR && XF == MACT_SCT && (j & 1)) __builtin_amdgcn_sched_barrier(0);
+      }
       __builtin_amdgcn_wave_barrier();
       s[3 * lane] = f4{o[0], o[1], o[2], o[3]};
       s[3 * lane + 1] = f4{o[4], o[5], o[6], o[7]};
@@ -404,21 +492,38 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the bytes have landed
       __builtin_amdgcn_wave_barrier();
-      uint32_t rgb[4][3];
+      if (METHOD == MACT_TRILINEAR && FORM != kCache) {
+        f4 acc[4];
+        float acc1[4];
+        tri_pairs<XF, FORM>(nodes, lp, N, s8, lane, acc, acc1);
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // every lane has read its bytes before the slice is reused
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+        for (int m = 0; m < 4; ++m) {
+          float o[3];
+          lut_out<XF>(acc[m], acc1[m], o);
+          const uint32_t p = 32u * (2u * m + (lane & 1u)) + (lane >> 1);
+          sf[3 * p] = o[0];
+          sf[3 * p + 1] = o[1];
+          sf[3 * p + 2] = o[2];
+        }
+      } else {
+        uint32_t rgb[4][3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) rgb[j][q] = s8[3 * (lane + 64 * j) + q];
-      __builtin_amdgcn_s_waitcnt(0xc07f);  // every lane has read its bytes before the slice is reused
-      __builtin_amdgcn_wave_barrier();
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float o[3];
-        lut_px_u8<METHOD, XF, FORM>(nodes, lp, N, rgb[j][0], rgb[j][1], rgb[j][2], o);
-        const uint32_t p = lane + 64 * j;
-        sf[3 * p] = o[0];
-        sf[3 * p + 1] = o[1];
-        sf[3 * p + 2] = o[2];
+          for (int q = 0; q < 3; ++q) rgb[j][q] = s8[3 * (lane + 64 * j) + q];
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // every lane has read its bytes before the slice is reused
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float o[3];
+          lut_px_u8<METHOD, XF, FORM>(nodes, lp, N, rgb[j][0], rgb[j][1], rgb[j][2], o);
+          const uint32_t p = lane + 64 * j;
+          sf[3 * p] = o[0];
+          sf[3 * p + 1] = o[1];
+          sf[3 * p + 2] = o[2];
+        }
       }
     }
     __builtin_amdgcn_wave_barrier();
