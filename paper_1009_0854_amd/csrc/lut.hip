@@ -51,6 +51,40 @@ static size_t lut_cache_size(int xform, size_t n) {
 
 // ---------------------------------------------------------------- device
 
+// atan2(y, x) for the angular channels' resultants, with atan2's quadrants and
+// signed zeros.  The ratio t = min / max of |x|, |y| (a reciprocal and one
+// Newton correction) folds the angle into [0, pi/4]; there atan t =
+// t + t^3 Q(t^2), Q of degree 7 fitted for relative error on [0, 1]
+// (1.7e-8; 1.1 ulp in float32 over [0, 1]); pi/2 - and pi - unfold it with
+// two-part constants.  About 25 instructions, against about 45 for the
+// library's atan2f, which the HSI and SCT LUT kernels spend most of their
+// arithmetic on.  Arguments below 2^-64 are scaled first, since the
+// reciprocal of a denormal overflows.
+__device__ __forceinline__ float lut_atan2(float y, float x) {
+  // |x|, |y| <= 1 here; scaled by 2^64 (exactly) so that no denormal reaches the reciprocal, and
+  // max >= 2^-100 so that (0, 0) gives t = 0
+  const float ax = fabsf(x) * 0x1p64f, ay = fabsf(y) * 0x1p64f;
+  const float mx = fmaxf(fmaxf(ax, ay), 0x1p-100f), mn = fminf(ax, ay);
+  const float r = __builtin_amdgcn_rcpf(mx);
+  float t = mn * r;
+  t = __builtin_fmaf(__builtin_fmaf(-mx, t, mn), r, t);
+  const float s = t * t;
+  float q = 0x1.7ed22cp-9f;
+  q = __builtin_fmaf(q, s, -0x1.0c2c1p-6f);
+  q = __builtin_fmaf(q, s, 0x1.61fdd8p-5f);
+  q = __builtin_fmaf(q, s, -0x1.3556b4p-4f);
+  q = __builtin_fmaf(q, s, 0x1.b4e12ap-4f);
+  q = __builtin_fmaf(q, s, -0x1.230adcp-3f);
+  q = __builtin_fmaf(q, s, 0x1.9978f4p-3f);
+  q = __builtin_fmaf(q, s, -0x1.5554dcp-2f);
+  float a = __builtin_fmaf(t * s, q, t);
+  constexpr float kPi2Lo = static_cast<float>(kPi / 2.0 - static_cast<double>(kPi2f));
+  constexpr float kPiLo = static_cast<float>(kPi - static_cast<double>(kPif));
+  if (ay > ax) a = (kPi2f - a) + kPi2Lo;  // exact difference: a lies in [pi/4, pi/2]
+  if (__builtin_signbit(x)) a = (kPif - a) + kPiLo;
+  return __builtin_copysignf(a, y);
+}
+
 // Extraction: cell and fraction per channel.
 __device__ __forceinline__ void locate_u8(uint32_t v, uint32_t N, uint32_t& i, float& f) {
   const uint32_t num = v * (N - 1);
@@ -246,13 +280,13 @@ __device__ __forceinline__ void lut_px_cache(const float* __restrict__ cache, ui
   if (XF == MACT_LAB || XF == MACT_LUV) {
     o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2];
   } else if (XF == MACT_HSI) {
-    float h = atan2f(acc[1], acc[0]);
+    float h = lut_atan2(acc[1], acc[0]);
     if (h < 0.0f) h += kTwoPif;
     o[0] = h; o[1] = acc[2]; o[2] = acc[C - 1];
   } else {
     o[0] = acc[0];
-    o[1] = atan2f(acc[2], acc[1]);
-    o[2] = atan2f(acc[C - 1], acc[3]);
+    o[1] = lut_atan2(acc[2], acc[1]);
+    o[2] = lut_atan2(acc[C - 1], acc[3]);
   }
 }
 
@@ -269,13 +303,13 @@ __device__ __forceinline__ void lut_out(f4 a0, float a1, float o[3]) {
   if (XF == MACT_LAB || XF == MACT_LUV) {
     o[0] = a0.x; o[1] = a0.y; o[2] = a0.z;
   } else if (XF == MACT_HSI) {
-    float h = atan2f(a0.y, a0.x);
+    float h = lut_atan2(a0.y, a0.x);
     if (h < 0.0f) h += kTwoPif;
     o[0] = h; o[1] = a0.z; o[2] = a0.w;
   } else {
     o[0] = a1;
-    o[1] = atan2f(a0.y, a0.x);
-    o[2] = atan2f(a0.w, a0.z);
+    o[1] = lut_atan2(a0.y, a0.x);
+    o[2] = lut_atan2(a0.w, a0.z);
   }
 }
 
