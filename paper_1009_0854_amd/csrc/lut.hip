@@ -332,16 +332,22 @@ __device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, const float
   float a1 = 0.0f;
   if (METHOD == MACT_TRILINEAR) {
     // the corners (c = 4 dR + 2 dG + dB) summed per dB: the product at dR dG = 00, then fused
-    // multiply-adds at 01, 10, 11; the dB = 0 and dB = 1 sums added last.  The two-lane kernel
-    // below sums in this order, so every trilinear path gives the same bits
+    // multiply-adds at 01, 10, 11; the dB = 0 and dB = 1 sums added last (SCT's L: per dR).  The
+    // two-lane kernel below sums in this order, so every trilinear path gives the same bits
     f4 ch[2];
     float cu[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const uint32_t n0 = base + off[b], n1 = base + off[2 + b], n2 = base + off[4 + b], n3 = base + off[6 + b];
       ch[b] = fma4(w[6 + b], nodes[n3], fma4(w[4 + b], nodes[n2], fma4(w[2 + b], nodes[n1], w[b] * nodes[n0])));
-      if (XF == MACT_SCT)
-        cu[b] = __builtin_fmaf(w[6 + b], lp[n3], __builtin_fmaf(w[4 + b], lp[n2], __builtin_fmaf(w[2 + b], lp[n1], w[b] * lp[n0])));
+    }
+    // SCT's L: corners 0..3 and 4..7 (dR = 0 and 1) each summed in corner order, then added
+#pragma unroll
+    for (int h = 0; h < 2 && XF == MACT_SCT; ++h) {
+      const uint32_t* o = off + 4 * h;
+      const float* v = w + 4 * h;
+      cu[h] = __builtin_fmaf(v[3], lp[base + o[3]],
+                             __builtin_fmaf(v[2], lp[base + o[2]], __builtin_fmaf(v[1], lp[base + o[1]], v[0] * lp[base + o[0]])));
     }
     a0 = ch[0] + ch[1];
     a1 = cu[0] + cu[1];
@@ -359,6 +365,10 @@ __device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, const float
   }
   lut_out<XF>(a0, a1, o);
 }
+
+// Two floats at a 4-byte aligned address (global memory takes unaligned
+// multi-dword loads).
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
 
 // The value of lane l ^ 1: a DPP quad permutation (1, 0, 3, 2), no LDS access.
 __device__ __forceinline__ float swap1(float v) {
@@ -400,8 +410,21 @@ __device__ __forceinline__ void tri_pairs(const f4* __restrict__ nodes, const fl
       w[q] = ((q >> 1) ? f0 : r0) * ((q & 1) ? f1 : g0) * wb;
     }
     f4 a = fma4(w[3], nodes[n[3]], fma4(w[2], nodes[n[2]], fma4(w[1], nodes[n[1]], w[0] * nodes[n[0]])));
-    float b = XF == MACT_SCT ? __builtin_fmaf(w[3], lp[n[3]], __builtin_fmaf(w[2], lp[n[2]], __builtin_fmaf(w[1], lp[n[1]], w[0] * lp[n[0]])))
-                             : 0.0f;
+    float b = 0.0f;
+    if (XF == MACT_SCT) {
+      // SCT's L: this lane sums the corners with dR = its lane bit, c = 4 dR .. 4 dR + 3, whose L
+      // values are two neighbouring pairs along B (the cell-major form: one 16-byte run)
+      const uint32_t c0 = base - db + (CELL ? 4u * db : db * sR);
+      float4 v;
+      if (CELL) {
+        v = *reinterpret_cast<const float4*>(lp + c0);
+      } else {
+        const f2u lo = *reinterpret_cast<const f2u*>(lp + c0), hi = *reinterpret_cast<const f2u*>(lp + c0 + sG);
+        v = float4{lo.x, lo.y, hi.x, hi.y};
+      }
+      const float wr = db ? f0 : r0, wg0 = wr * g0, wg1 = wr * f1, b0 = 1.0f - f2;
+      b = __builtin_fmaf(wg1 * f2, v.w, __builtin_fmaf(wg1 * b0, v.z, __builtin_fmaf(wg0 * f2, v.y, wg0 * b0 * v.x)));
+    }
     // plus the partner's sum (a float sum does not depend on the order of its two terms)
     a = a + f4{swap1(a.x), swap1(a.y), swap1(a.z), swap1(a.w)};
     if (XF == MACT_SCT) b = b + swap1(b);
@@ -485,6 +508,7 @@ __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32
 template <int METHOD, int XF, bool LDS, int FORM, bool SPREAD>
 __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint32_t N, const uint8_t* __restrict__ in,
                                                float* __restrict__ out, uint32_t n_px) {
+  static_assert(!(LDS && SPREAD), "the consecutive-lane form gathers from global memory (its loads may be unaligned)");
   extern __shared__ f4 smem[];
   const uint32_t n_ent = lut_entries<FORM>(N);
   const uint32_t n_f4 = lut_f4_units<XF, FORM>(N);
