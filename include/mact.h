@@ -352,8 +352,8 @@ mact_status lut_build(int32_t xform, int32_t n, int32_t gamma, float* dev_lut, s
      TETRAHEDRAL fractions sorted f1 >= f2 >= f3, path 000 -> 111 along the
                  axes in that order, weights 1-f1, f1-f2, f2-f3, f3: 4 corners.
    Angular channels (H; angles A and B) are interpolated as circular data: the
-   angle of the weighted sum of the nodes' unit vectors (H in [0, 2 pi), SCT
-   angles in (-pi, pi]).  Grids whose bytes fit the workgroup's LDS are staged
+   angle of the weighted sum of the nodes' unit vectors, within 2 float32 ulp of
+   atan2 (H in [0, 2 pi), SCT angles in (-pi, pi]).  Grids whose bytes fit the workgroup's LDS are staged
    there; larger ones are read through the L2.  in/out as mact_transform.
    Errors: MACT_E_INVALID (NULL, n outside 2..256, bad method, shapes). */
 mact_status lut_interp(const float* dev_lut, int32_t n, int32_t xform, int32_t method,

@@ -18,12 +18,11 @@
 // Cell-major form: (N-1)^3 cells, each holding its 8 corner nodes in one
 // contiguous run (128 bytes; for SCT followed, after all cells, by the
 // cells' 8 L values, 32 bytes a cell), so that one pixel's corners are one
-// cache line instead of four lines N and N^2 nodes apart.  It plays the
-// part of the paper's caching LUTs, which store neighbour information in every
-// node to save per-pixel work; here what the stored neighbours save is memory
-// transactions.  Corner ids (dR dG dB as bits 2, 1, 0) stand in for the node
-// strides, so both forms sum the same values in the same order and give the
-// same bits.
+// cache line instead of four lines N and N^2 nodes apart: the form that only
+// reorders memory, beside the paper's caching records (kCache below), which
+// store edge differences to save arithmetic.  Corner ids (dR dG dB as bits 2,
+// 1, 0) stand in for the node strides, so both forms sum the same values in
+// the same order and give the same bits.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
