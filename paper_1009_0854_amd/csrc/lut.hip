@@ -121,24 +121,44 @@ struct Corners<MACT_TETRAHEDRAL> {
   static constexpr int K = 4;
   __device__ __forceinline__ static void get(float fr, float fg, float fb, uint32_t sR, uint32_t sG, uint32_t off[4],
                                              float w[4]) {
-    // decreasing order of the fractions, ties R before G before B
-    float f1, f2, f3;
-    uint32_t s1, s2;
-    if (fr >= fg) {
-      if (fg >= fb) { f1 = fr; f2 = fg; f3 = fb; s1 = sR; s2 = sG; }
-      else if (fr >= fb) { f1 = fr; f2 = fb; f3 = fg; s1 = sR; s2 = 1; }
-      else { f1 = fb; f2 = fr; f3 = fg; s1 = 1; s2 = sR; }
-    } else {
-      if (fr >= fb) { f1 = fg; f2 = fr; f3 = fb; s1 = sG; s2 = sR; }
-      else if (fg >= fb) { f1 = fg; f2 = fb; f3 = fr; s1 = sG; s2 = 1; }
-      else { f1 = fb; f2 = fg; f3 = fr; s1 = 1; s2 = sG; }
-    }
+    // decreasing order of the fractions, ties R before G before B, without branches: the largest,
+    // median and smallest values, the stride of the largest axis (s1) and of the smallest (s3)
+    const bool rg = fr >= fg, rb = fr >= fb, gb = fg >= fb;
+    const float f1 = fmaxf(fmaxf(fr, fg), fb), f3 = fminf(fminf(fr, fg), fb);
+    const float f2 = __builtin_amdgcn_fmed3f(fr, fg, fb);
+    const uint32_t s1 = rg ? (rb ? sR : 1u) : (gb ? sG : 1u);
+    const uint32_t s3 = rg ? (gb ? 1u : sG) : (rb ? 1u : sR);
     off[0] = 0; w[0] = 1.0f - f1;
     off[1] = s1; w[1] = f1 - f2;
-    off[2] = s1 + s2; w[2] = f2 - f3;
+    off[2] = sR + sG + 1u - s3; w[2] = f2 - f3;
     off[3] = sR + sG + 1; w[3] = f3;
   }
 };
+
+// The tetrahedral corners by branches on the fraction order: the same corners
+// and weights as Corners<MACT_TETRAHEDRAL>.  Where one lane takes one pixel
+// and neighbouring lanes take neighbouring pixels (the L2 path), the branches
+// are mostly uniform over a wave, and this form measured faster there (CIELAB
+// 33^3: 153 vs 139-146 Gpx/s); elsewhere the branch-free form is (17^3 in LDS,
+// HSI and SCT: +8-11%).
+__device__ __forceinline__ void tet_corners_branch(float fr, float fg, float fb, uint32_t sR, uint32_t sG,
+                                                   uint32_t off[4], float w[4]) {
+  float f1, f2, f3;
+  uint32_t s1, s2;
+  if (fr >= fg) {
+    if (fg >= fb) { f1 = fr; f2 = fg; f3 = fb; s1 = sR; s2 = sG; }
+    else if (fr >= fb) { f1 = fr; f2 = fb; f3 = fg; s1 = sR; s2 = 1; }
+    else { f1 = fb; f2 = fr; f3 = fg; s1 = 1; s2 = sR; }
+  } else {
+    if (fr >= fb) { f1 = fg; f2 = fr; f3 = fb; s1 = sG; s2 = sR; }
+    else if (fg >= fb) { f1 = fg; f2 = fb; f3 = fr; s1 = sG; s2 = 1; }
+    else { f1 = fb; f2 = fg; f3 = fr; s1 = 1; s2 = sG; }
+  }
+  off[0] = 0; w[0] = 1.0f - f1;
+  off[1] = s1; w[1] = f1 - f2;
+  off[2] = s1 + s2; w[2] = f2 - f3;
+  off[3] = sR + sG + 1; w[3] = f3;
+}
 
 template <>
 struct Corners<MACT_PRISM> {
@@ -315,7 +335,7 @@ __device__ __forceinline__ void lut_out(f4 a0, float a1, float o[3]) {
 // One pixel: the method's weighted corner sum at cell i, fractions f.  FORM
 // kCells: `nodes` is the cell-major form; kCache: the caching records.
 // `lp`: SCT's L plane (one float per entry of `nodes`); unused otherwise.
-template <int METHOD, int XF, int FORM>
+template <int METHOD, int XF, int FORM, bool BRANCH = false>
 __device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, const float* __restrict__ lp, uint32_t N,
                                        const uint32_t i[3], const float f[3], float o[3]) {
   if (FORM == kCache) {
@@ -326,42 +346,33 @@ __device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, const float
   const uint32_t base = CELL ? ((i[0] * (N - 1) + i[1]) * (N - 1) + i[2]) * 8u : (i[0] * N + i[1]) * N + i[2];
   uint32_t off[8];
   float w[8];
-  Corners<METHOD>::get(f[0], f[1], f[2], CELL ? 4u : N * N, CELL ? 2u : N, off, w);
-  f4 a0 = {0.0f, 0.0f, 0.0f, 0.0f};
-  float a1 = 0.0f;
-  if (METHOD == MACT_TRILINEAR) {
-    // the corners (c = 4 dR + 2 dG + dB) summed per dB: the product at dR dG = 00, then fused
-    // multiply-adds at 01, 10, 11; the dB = 0 and dB = 1 sums added last (SCT's L: per dR).  The
-    // two-lane kernel below sums in this order, so every trilinear path gives the same bits
-    f4 ch[2];
-    float cu[2] = {0.0f, 0.0f};
+  if constexpr (METHOD == MACT_TETRAHEDRAL && BRANCH)
+    tet_corners_branch(f[0], f[1], f[2], CELL ? 4u : N * N, CELL ? 2u : N, off, w);
+  else
+    Corners<METHOD>::get(f[0], f[1], f[2], CELL ? 4u : N * N, CELL ? 2u : N, off, w);
+  // The corners in two chains, even and odd corner ids (each a product, then fused multiply-adds
+  // in id order), added last; for trilinear (c = 4 dR + 2 dG + dB) the chains are dB = 0 and 1.
+  // SCT's L: the same chains, except trilinear's, which are dR = 0 and 1 (corners 0..3 and 4..7).
+  // The two-lane kernels below sum in this order, so every path gives the same bits.
+  constexpr int K = Corners<METHOD>::K;
+  f4 ch[2];
+  float cu[2] = {0.0f, 0.0f};
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const uint32_t n0 = base + off[b], n1 = base + off[2 + b], n2 = base + off[4 + b], n3 = base + off[6 + b];
-      ch[b] = fma4(w[6 + b], nodes[n3], fma4(w[4 + b], nodes[n2], fma4(w[2 + b], nodes[n1], w[b] * nodes[n0])));
-    }
-    // SCT's L: corners 0..3 and 4..7 (dR = 0 and 1) each summed in corner order, then added
+  for (int b = 0; b < 2; ++b) {
+    ch[b] = w[b] * nodes[base + off[b]];
 #pragma unroll
-    for (int h = 0; h < 2 && XF == MACT_SCT; ++h) {
-      const uint32_t* o = off + 4 * h;
-      const float* v = w + 4 * h;
-      cu[h] = __builtin_fmaf(v[3], lp[base + o[3]],
-                             __builtin_fmaf(v[2], lp[base + o[2]], __builtin_fmaf(v[1], lp[base + o[1]], v[0] * lp[base + o[0]])));
-    }
-    a0 = ch[0] + ch[1];
-    a1 = cu[0] + cu[1];
-  } else {
-#pragma unroll
-    for (int c = 0; c < Corners<METHOD>::K; ++c) {
-      const uint32_t n = base + off[c];
-      const f4 v0 = nodes[n];
-      a0.x = __builtin_fmaf(w[c], v0.x, a0.x);
-      a0.y = __builtin_fmaf(w[c], v0.y, a0.y);
-      a0.z = __builtin_fmaf(w[c], v0.z, a0.z);
-      a0.w = __builtin_fmaf(w[c], v0.w, a0.w);
-      if (XF == MACT_SCT) a1 = __builtin_fmaf(w[c], lp[n], a1);
-    }
+    for (int c = b + 2; c < K; c += 2) ch[b] = fma4(w[c], nodes[base + off[c]], ch[b]);
   }
+#pragma unroll
+  for (int b = 0; b < 2 && XF == MACT_SCT; ++b) {
+    const int c0 = METHOD == MACT_TRILINEAR ? 4 * b : b, dc = METHOD == MACT_TRILINEAR ? 1 : 2;
+    cu[b] = w[c0] * lp[base + off[c0]];
+#pragma unroll
+    for (int c = c0 + dc; c < (METHOD == MACT_TRILINEAR ? c0 + 4 : K); c += dc)
+      cu[b] = __builtin_fmaf(w[c], lp[base + off[c]], cu[b]);
+  }
+  const f4 a0 = ch[0] + ch[1];
+  const float a1 = cu[0] + cu[1];
   lut_out<XF>(a0, a1, o);
 }
 
@@ -437,7 +448,57 @@ __device__ __forceinline__ void tri_pairs(const f4* __restrict__ nodes, const fl
   }
 }
 
-template <int METHOD, int XF, int FORM>
+// Prism, pyramidal and tetrahedral on the cell-major form with 2 lanes per
+// pixel: all of a pixel's corners lie in its cell's 128-byte run, so the lane
+// pair of pixel 32 r + h (round r of 8, as in tri_pairs) touches one line per
+// instruction.  Both lanes take the method's corners and weights; lane bit 0
+// picks the even or the odd corner ids, and each lane sums its chain (a
+// product, then fused multiply-adds in id order, SCT's L alike); the pair adds
+// the two sums.  lut_px's order, so the results are lut_px's bits.
+template <int METHOD, int XF>
+__device__ __forceinline__ void cell_pairs(const f4* __restrict__ nodes, const float* __restrict__ lp, uint32_t N,
+                                           const uint8_t* s8, uint32_t lane, f4 acc[4], float acc1[4]) {
+  constexpr int K = Corners<METHOD>::K;
+  const uint32_t db = lane & 1u, h = lane >> 1;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const uint32_t P = 32u * r + h;
+    uint32_t i0, i1, i2;
+    float f0, f1, f2;
+    locate_u8(s8[3 * P], N, i0, f0);
+    locate_u8(s8[3 * P + 1], N, i1, f1);
+    locate_u8(s8[3 * P + 2], N, i2, f2);
+    uint32_t off[8];
+    float w[8];
+    Corners<METHOD>::get(f0, f1, f2, 4u, 2u, off, w);
+    const uint32_t base = ((i0 * (N - 1) + i1) * (N - 1) + i2) * 8u;
+    f4 a = {0.0f, 0.0f, 0.0f, 0.0f};
+    float b = 0.0f;
+#pragma unroll
+    for (int j = 0; 2 * j < K; ++j) {
+      // corner 2 j + db; with K odd the odd lane has none at the last step
+      const bool has = 2 * j + 1 < K || db == 0;
+      const uint32_t n = base + (db ? off[2 * j + 1 < K ? 2 * j + 1 : 2 * j] : off[2 * j]);
+      const float wc = db ? w[2 * j + 1 < K ? 2 * j + 1 : 2 * j] : w[2 * j];
+      if (has) {
+        const f4 v = nodes[n];
+        a = j == 0 ? wc * v : fma4(wc, v, a);
+        if (XF == MACT_SCT) b = j == 0 ? wc * lp[n] : __builtin_fmaf(wc, lp[n], b);
+      }
+    }
+    // plus the partner's sum (a float sum does not depend on the order of its two terms)
+    a = a + f4{swap1(a.x), swap1(a.y), swap1(a.z), swap1(a.w)};
+    if (XF == MACT_SCT) b = b + swap1(b);
+    if (db == (uint32_t)(r & 1)) {
+      acc[r >> 1] = a;
+      acc1[r >> 1] = b;
+    }
+    // one round's gathers in flight at a time, as in tri_pairs
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int METHOD, int XF, int FORM, bool BRANCH = false>
 __device__ __forceinline__ void lut_px_u8(const f4* __restrict__ nodes, const float* __restrict__ lp, uint32_t N,
                                           uint32_t r, uint32_t g, uint32_t b, float o[3]) {
   uint32_t i[3];
@@ -445,7 +506,7 @@ __device__ __forceinline__ void lut_px_u8(const f4* __restrict__ nodes, const fl
   locate_u8(r, N, i[0], f[0]);
   locate_u8(g, N, i[1], f[1]);
   locate_u8(b, N, i[2], f[2]);
-  lut_px<METHOD, XF, FORM>(nodes, lp, N, i, f, o);
+  lut_px<METHOD, XF, FORM, BRANCH>(nodes, lp, N, i, f, o);
 }
 
 // Node entries of a LUT of size N (packed N^3, cell-major 8 (N-1)^3), after
@@ -549,10 +610,16 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the bytes have landed
       __builtin_amdgcn_wave_barrier();
-      if (METHOD == MACT_TRILINEAR && FORM != kCache) {
+      // two lanes per pixel: trilinear on the packed and cell-major grids; the other methods on
+      // cell-major grids of more than 256 KB (17^3 and up: +2 to +38%; on 9^3, 64 KB, pyramidal
+      // lost 19% and the others nothing)
+      if ((METHOD == MACT_TRILINEAR && FORM != kCache) || (FORM == kCells && (N - 1) * (N - 1) * (N - 1) > 2048u)) {
         f4 acc[4];
         float acc1[4];
-        tri_pairs<XF, FORM>(nodes, lp, N, s8, lane, acc, acc1);
+        if (METHOD == MACT_TRILINEAR)
+          tri_pairs<XF, FORM>(nodes, lp, N, s8, lane, acc, acc1);
+        else
+          cell_pairs<METHOD, XF>(nodes, lp, N, s8, lane, acc, acc1);
         __builtin_amdgcn_s_waitcnt(0xc07f);  // every lane has read its bytes before the slice is reused
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -575,11 +642,14 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           float o[3];
-          lut_px_u8<METHOD, XF, FORM>(nodes, lp, N, rgb[j][0], rgb[j][1], rgb[j][2], o);
+          lut_px_u8<METHOD, XF, FORM, true>(nodes, lp, N, rgb[j][0], rgb[j][1], rgb[j][2], o);
           const uint32_t p = lane + 64 * j;
           sf[3 * p] = o[0];
           sf[3 * p + 1] = o[1];
           sf[3 * p + 2] = o[2];
+          // one pixel's gathers in flight at a time: hoisting the next pixels' gathers costs
+          // occupancy and measured slower (the caching form's trilinear, 33^3: 59-92 vs 102 Gpx/s)
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
