@@ -337,19 +337,24 @@ __device__ __forceinline__ void lut_out(f4 a0, float a1, float o[3]) {
 // `lp`: SCT's L plane (one float per entry of `nodes`); unused otherwise.
 template <int METHOD, int XF, int FORM, bool BRANCH = false>
 __device__ __forceinline__ void lut_px(const f4* __restrict__ nodes, const float* __restrict__ lp, uint32_t N,
-                                       const uint32_t i[3], const float f[3], float o[3]) {
+                                       uint32_t sR, uint32_t sG, const uint32_t i[3], const float f[3], float o[3]) {
   if (FORM == kCache) {
     lut_px_cache<METHOD, XF>(reinterpret_cast<const float*>(nodes), N, i, f, o);
     return;
   }
   constexpr bool CELL = FORM == kCells;
-  const uint32_t base = CELL ? ((i[0] * (N - 1) + i[1]) * (N - 1) + i[2]) * 8u : (i[0] * N + i[1]) * N + i[2];
+  // packed: node (i, j, k) at i sR + j sG + k (N^2, N; more where the grid is staged with padding)
+  const uint32_t base = CELL ? ((i[0] * (N - 1) + i[1]) * (N - 1) + i[2]) * 8u : i[0] * sR + i[1] * sG + i[2];
+  if (CELL) {
+    sR = 4u;
+    sG = 2u;
+  }
   uint32_t off[8];
   float w[8];
   if constexpr (METHOD == MACT_TETRAHEDRAL && BRANCH)
-    tet_corners_branch(f[0], f[1], f[2], CELL ? 4u : N * N, CELL ? 2u : N, off, w);
+    tet_corners_branch(f[0], f[1], f[2], sR, sG, off, w);
   else
-    Corners<METHOD>::get(f[0], f[1], f[2], CELL ? 4u : N * N, CELL ? 2u : N, off, w);
+    Corners<METHOD>::get(f[0], f[1], f[2], sR, sG, off, w);
   // The corners in two chains, even and odd corner ids (each a product, then fused multiply-adds
   // in id order), added last; for trilinear (c = 4 dR + 2 dG + dB) the chains are dB = 0 and 1.
   // SCT's L: the same chains, except trilinear's, which are dR = 0 and 1 (corners 0..3 and 4..7).
@@ -500,13 +505,13 @@ __device__ __forceinline__ void cell_pairs(const f4* __restrict__ nodes, const f
 
 template <int METHOD, int XF, int FORM, bool BRANCH = false>
 __device__ __forceinline__ void lut_px_u8(const f4* __restrict__ nodes, const float* __restrict__ lp, uint32_t N,
-                                          uint32_t r, uint32_t g, uint32_t b, float o[3]) {
+                                          uint32_t sR, uint32_t sG, uint32_t r, uint32_t g, uint32_t b, float o[3]) {
   uint32_t i[3];
   float f[3];
   locate_u8(r, N, i[0], f[0]);
   locate_u8(g, N, i[1], f[1]);
   locate_u8(b, N, i[2], f[2]);
-  lut_px<METHOD, XF, FORM, BRANCH>(nodes, lp, N, i, f, o);
+  lut_px<METHOD, XF, FORM, BRANCH>(nodes, lp, N, sR, sG, i, f, o);
 }
 
 // Node entries of a LUT of size N (packed N^3, cell-major 8 (N-1)^3), after
@@ -550,7 +555,7 @@ __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32
       if (u8) locate_u8((uint32_t)v[c], N, i[c], f[c]);
       else locate_f(src.dtype == MACT_U16 ? v[c] * kInv65535 : v[c], N, i[c], f[c]);
     }
-    lut_px<METHOD, XF, FORM>(nodes, lp, N, i, f, o);
+    lut_px<METHOD, XF, FORM>(nodes, lp, N, N * N, N, i, f, o);
     store_px(dst, p, o);
   }
 }
@@ -566,20 +571,36 @@ __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32
 // LDS slice as 1 KB contiguous stores.  LDS holds the LUT (when LDS) followed
 // by 3 KB per wave.
 template <int METHOD, int XF, bool LDS, int FORM, bool SPREAD>
-__global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint32_t N, const uint8_t* __restrict__ in,
-                                               float* __restrict__ out, uint32_t n_px) {
+__global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint32_t N, uint32_t sR, uint32_t sG,
+                                               const uint8_t* __restrict__ in, float* __restrict__ out, uint32_t n_px) {
   static_assert(!(LDS && SPREAD), "the consecutive-lane form gathers from global memory (its loads may be unaligned)");
   extern __shared__ f4 smem[];
   const uint32_t n_ent = lut_entries<FORM>(N);
   const uint32_t n_f4 = lut_f4_units<XF, FORM>(N);
   const f4* nodes = lut;
-  f4* tbuf = smem + (LDS ? n_f4 : 0);
+  const float* lp = reinterpret_cast<const float*>(lut + n_ent);
+  f4* tbuf = smem;
   if (LDS) {
-    for (uint32_t i = threadIdx.x; i < n_f4; i += blockDim.x) smem[i] = lut[i];
+    if (FORM == kPacked && (sR != N * N || sG != N)) {
+      // staged with padded strides: node (i, j, k) to i sR + j sG + k, the L plane (SCT) alike
+      // after N sR entries
+      const uint32_t nn = N * N, e = N * sR;
+      float* ld = reinterpret_cast<float*>(smem + e);
+      for (uint32_t t = threadIdx.x; t < n_ent; t += blockDim.x) {
+        const uint32_t r = t / nn, g = (t - r * nn) / N, d = r * sR + g * sG + (t - r * nn - g * N);
+        smem[d] = lut[t];
+        if (XF == MACT_SCT) ld[d] = lp[t];
+      }
+      tbuf = smem + e + (XF == MACT_SCT ? (e + 3) / 4 : 0);
+      lp = ld;
+    } else {
+      for (uint32_t i = threadIdx.x; i < n_f4; i += blockDim.x) smem[i] = lut[i];
+      tbuf = smem + n_f4;
+      lp = reinterpret_cast<const float*>(smem + n_ent);
+    }
     __syncthreads();
     nodes = smem;
   }
-  const float* lp = reinterpret_cast<const float*>(nodes + n_ent);
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   f4* s = tbuf + wv * 192;
   const uint32_t n_chunks = n_px >> 8;
@@ -589,8 +610,8 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
       float o[12];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        lut_px_u8<METHOD, XF, FORM>(nodes, lp, N, byte_of(w, 3 * j), byte_of(w, 3 * j + 1), byte_of(w, 3 * j + 2),
-                                    o + 3 * j);
+        lut_px_u8<METHOD, XF, FORM>(nodes, lp, N, sR, sG, byte_of(w, 3 * j), byte_of(w, 3 * j + 1),
+                                    byte_of(w, 3 * j + 2), o + 3 * j);
         // SCT's trilinear sums: two pixels' gathers in flight at most, or the corners outgrow the registers
         if (METHOD == MACT_TRILINEAR && XF == MACT_SCT && (j & 1)) __builtin_amdgcn_sched_barrier(0);
       }
@@ -642,7 +663,7 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           float o[3];
-          lut_px_u8<METHOD, XF, FORM, true>(nodes, lp, N, rgb[j][0], rgb[j][1], rgb[j][2], o);
+          lut_px_u8<METHOD, XF, FORM, true>(nodes, lp, N, sR, sG, rgb[j][0], rgb[j][1], rgb[j][2], o);
           const uint32_t p = lane + 64 * j;
           sf[3 * p] = o[0];
           sf[3 * p + 1] = o[1];
@@ -666,7 +687,8 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
   if (blockIdx.x == 0)
     for (uint32_t p = tail0 + threadIdx.x; p < n_px; p += blockDim.x) {
       float o[3];
-      lut_px_u8<METHOD, XF, FORM>(nodes, lp, N, in[3 * (size_t)p], in[3 * (size_t)p + 1], in[3 * (size_t)p + 2], o);
+      lut_px_u8<METHOD, XF, FORM>(nodes, lp, N, sR, sG, in[3 * (size_t)p], in[3 * (size_t)p + 1], in[3 * (size_t)p + 2],
+                                  o);
       out[3 * (size_t)p] = o[0];
       out[3 * (size_t)p + 1] = o[1];
       out[3 * (size_t)p + 2] = o[2];
@@ -710,6 +732,28 @@ static hipError_t allow_lds(K k, size_t bytes) {
   return hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// Node strides of a packed grid staged in LDS.  A float4 node covers 4 of the
+// LDS's 4-byte banks, so node n sits in bank group n mod 16, and the lanes of
+// one gather mostly hold nodes of a small neighbourhood (neighbouring pixels).
+// Unpadded, the strides N and N^2 are both 1 mod 16 at 17^3: steps along R, G
+// and B land on the same group, and the lanes' gathers collide.  G rows are
+// padded to a stride of 3 mod 16 and R planes to 9 mod 16, which spreads a
+// 3 x 3 x 3 neighbourhood over the groups (a simulation of the batch's pixel
+// spread: at most 1.3 nodes per group per 16 lanes against 3.0), where the
+// grid still fits `room` bytes; `bytes` becomes the staged size.
+static void lds_strides(int xform, uint32_t N, size_t room, uint32_t& sR, uint32_t& sG, size_t& bytes) {
+  uint32_t g = N;
+  while (g % 16 != 3) ++g;
+  uint32_t r = N * g;
+  while (r % 16 != 9) ++r;
+  const size_t e = (size_t)N * r;
+  const size_t b = lut_f4s(xform, e) * sizeof(f4);
+  if (b > room) return;
+  sR = r;
+  sG = g;
+  bytes = b;
+}
+
 // Launch shapes.  LDS-staged grid: 1024-thread workgroups, one or two per CU
 // (as many copies of the grid as the CU's LDS holds), grid-stride.  Grid
 // gathered through the L2 (and every cell-major grid): 256-thread
@@ -730,7 +774,10 @@ static hipError_t launch_lut(const f4* lut, uint32_t N, const HostImage& hi, con
   if (fast && (CELL || bytes + t_lds <= lds_max || bytes > lds_max)) {
     const bool lds = !CELL && bytes + t_lds <= lds_max;
     const unsigned block = lds ? 1024 : 256;
-    const size_t shm = (lds ? bytes : 0) + (size_t)(block / 64) * 192 * sizeof(f4);
+    uint32_t sR = N * N, sG = N;
+    size_t staged = bytes;
+    if (lds && FORM == kPacked) lds_strides(XF, N, lds_max - t_lds, sR, sG, staged);
+    const size_t shm = (lds ? staged : 0) + (size_t)(block / 64) * 192 * sizeof(f4);
     const uint64_t chunks = std::max<uint64_t>(1, n_px >> 8);
     // a staged grid is worth keeping: one or two resident workgroups per CU stride over the image;
     // gathers from global memory: the grid covers the image once, one chunk per wave
@@ -747,10 +794,10 @@ static hipError_t launch_lut(const f4* lut, uint32_t N, const HostImage& hi, con
       auto k = k_lut4<METHOD, XF, true, FORM, false>;
       hipError_t e = allow_lds(k, shm);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, lut, N, in8, op, n_px);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, lut, N, sR, sG, in8, op, n_px);
     } else {
       auto k = k_lut4<METHOD, XF, false, FORM, true>;
-      hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, lut, N, in8, op, n_px);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(block), shm, st, lut, N, sR, sG, in8, op, n_px);
     }
     return hipGetLastError();
   }
