@@ -7,13 +7,19 @@
 // trigonometry per corner.  SCT's fifth value, L, lives in a plane of one
 // float per node after the N^3 float4 (20 bytes a node, with no padding).
 //
-// Interpolation: a grid of a few workgroups per CU strides over the image.
-// When the packed grid fits the workgroup's LDS beside the store buffers
-// (17^3: 78.6 KB, SCT 98.3 KB) it is staged there once per workgroup and
-// every corner gather is an LDS read; larger grids (33^3 x 16 B = 575 KB) are
-// gathered from global memory through the L2.  Packed 8-bit HWC -> float32 HWC takes k_lut4 (the transform's
-// 12-byte loads and LDS-transposed 1 KB stores); other shapes take k_lut, one
-// pixel per lane.  Each method is a weighted sum of its 8, 6, 5 or 4 corners.
+// Interpolation: when the packed grid fits the workgroup's LDS beside the
+// store buffers (17^3: 78.6 KB, SCT 98.3 KB) one or two workgroups per CU
+// stage it once, with G and R strides padded against bank conflicts
+// (lds_strides), and stride over the image; every corner gather is then an LDS
+// read.  Larger grids (33^3 x 16 B = 575 KB) are gathered from global memory
+// through the L2 by a grid that covers the image once, neighbouring lanes on
+// neighbouring pixels, and trilinear (every method on cell-major grids) with
+// two lanes per pixel, which halves the cache lines a gather touches.  Packed
+// 8-bit HWC -> float32 HWC takes k_lut4 (the transform's 12-byte loads and
+// LDS-transposed 1 KB stores); other shapes take k_lut, one pixel per lane.
+// Each method is a weighted sum of its 8, 6, 5 or 4 corners, summed in two
+// chains (even and odd corner ids) on every path, so all paths and forms give
+// the same bits.
 //
 // Cell-major form: (N-1)^3 cells, each holding its 8 corner nodes in one
 // contiguous run (128 bytes; for SCT followed, after all cells, by the
@@ -567,9 +573,11 @@ __global__ __launch_bounds__(1024) void k_lut(const f4* __restrict__ lut, uint32
 // SPREAD = true: the chunk's bytes go through the wave's LDS slice and lane l
 // interpolates pixels l, l + 64, l + 128, l + 192, so the 64 lanes of one
 // corner gather are 64 consecutive pixels, whose corners on smooth images
-// often share cache lines.  Either way the results leave through the wave's
-// LDS slice as 1 KB contiguous stores.  LDS holds the LUT (when LDS) followed
-// by 3 KB per wave.
+// often share cache lines; there trilinear, and every method on a cell-major
+// grid above 256 KB, take two lanes per pixel (tri_pairs, cell_pairs).
+// Either way the results leave through the wave's LDS slice as 1 KB
+// contiguous stores.  LDS holds the LUT (when LDS; packed grids with the node
+// strides sR, sG, else N^2, N) followed by 3 KB per wave.
 template <int METHOD, int XF, bool LDS, int FORM, bool SPREAD>
 __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint32_t N, uint32_t sR, uint32_t sG,
                                                const uint8_t* __restrict__ in, float* __restrict__ out, uint32_t n_px) {
