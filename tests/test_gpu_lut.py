@@ -59,6 +59,20 @@ def test_u8_parity(M, xform, method, N):
     _compare(xform, gpu, ref, rlen)
 
 
+@pytest.mark.parametrize("N", [2, 3, 5, 12, 16, 18, 19])
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("xform", ["lab", "hsi", "sct"])
+def test_u8_parity_odd_grid_sizes(M, xform, method, N):
+    # grids staged in LDS are copied there with their G and R strides padded (to 3 and 9 mod 16
+    # nodes), by an amount that depends on N (19: none; 18: 1 and 3; 2: 1 and 3; SCT 17^3 and
+    # below only), and larger ones are read through the L2: parity for sizes on both sides
+    img = synth.uniform_u8(67, 131, seed=N + 5)
+    img.reshape(-1, 3)[:4] = [[0, 0, 0], [255, 255, 255], [255, 0, 0], [0, 0, 255]]
+    gpu, _ = _interp(M, xform, N, method, img)
+    ref, rlen = OL.interp(OL.build(xform, N), xform, method, v8=img)
+    _compare(xform, gpu, ref, rlen)
+
+
 @pytest.mark.parametrize("method", METHODS)
 def test_float_inputs_and_chw(M, method):
     g = synth.rng(31)
