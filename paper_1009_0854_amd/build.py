@@ -29,7 +29,7 @@ BUILD_SAN = os.path.join(ROOT, "_build_san")
 SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
              "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
 
-HIP_SOURCES = ["xform.hip", "lut.hip", "batch.hip", "serve.hip", "inverse.hip", "exact.hip"]
+HIP_SOURCES = ["xform.hip", "gather.hip", "lut.hip", "batch.hip", "serve.hip", "inverse.hip", "exact.hip"]
 CPP_SOURCES = ["remez.cpp", "host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1,0 +1,165 @@
+// Per-pixel MACT transforms (Sec. 3.2-3.4) for the input shapes the 4-pixel
+// kernels of xform.hip do not take, into packed float32 or float16 HWC or CHW:
+// HWC rows whose width is not a multiple of 4 or whose strides are not whole
+// 4-pixel groups (crops, pitched rows), CHW planes of W H not a multiple of 4,
+// misaligned input pointers.  The catch-all k_generic reads the element type,
+// the transform and the output type at run time and writes each pixel from its
+// lane (a 12-byte stride across the wave for HWC output); here those are
+// template parameters, and HWC output leaves the way the hot kernel's does.
+//
+// A wave takes 256 consecutive pixels of the launch (image after image); lane
+// l takes pixels l, l + 64, l + 128 and l + 192, so that the 64 lanes of one
+// load read neighbouring pixels.  The input's layout and strides come from its
+// descriptor (branches uniform over the launch).  HWC output goes through the
+// wave's LDS slice and leaves as 16-byte (float16: 8-byte) stores, each
+// instruction 1 KB (512 B) of contiguous output; CHW output is stored plane by
+// plane, 64 neighbouring elements per instruction.  The per-pixel code is
+// pixel.h's, so the results are the other kernels' bits.
+#include <algorithm>
+
+#include "launch.h"
+
+namespace mact {
+
+#include "gamma_table.inc"
+
+typedef float g_f4 __attribute__((ext_vector_type(4)));
+typedef float g_f2 __attribute__((ext_vector_type(2)));
+
+// Pixel p of `im` as load_px returns it (codes as integer-valued floats, float
+// inputs clamped to [0, 1]), its element type fixed at compile time.
+template <int IN>
+__device__ __forceinline__ void load_px_t(const KImage& im, uint32_t p, float v[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t o = elem_off(im, p, c);
+    if (IN == MACT_U8) v[c] = (float)static_cast<const uint8_t*>(im.ptr)[o];
+    else if (IN == MACT_U16) v[c] = (float)static_cast<const uint16_t*>(im.ptr)[o];
+    else if (IN == MACT_F16) v[c] = clamp01(__half2float(static_cast<const __half*>(im.ptr)[o]));
+    else v[c] = clamp01(static_cast<const float*>(im.ptr)[o]);
+  }
+}
+
+// Channel c of pixel p (image n, pixel r of hw) of packed output: HWC at
+// 3 p + c, CHW at (3 n + c) hw + r.
+template <int OUT>
+__device__ __forceinline__ void put(void* out, size_t e, float x) {
+  if (OUT == MACT_F32) static_cast<float*>(out)[e] = x;
+  else static_cast<__half*>(out)[e] = f2h_rn(x);
+}
+
+template <int IN, int OUT, int XF, int DEG, bool OCHW>
+__global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ out, uint32_t n_px, uint32_t hw,
+                                                FastDiv div_hw, KCoef k, int gamma) {
+  __shared__ float gtab[256];
+  __shared__ g_f4 s_out[4][OCHW ? 1 : 192];  // 3 KB per wave: 256 pixels of float32 (float16: 1.5 KB)
+  if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
+    gtab[threadIdx.x] = k_gamma_table[gamma][threadIdx.x];
+    __syncthreads();
+  }
+  pin_lead<DEG>(k);
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t n_chunks = n_px >> 8;
+  const uint32_t c = blockIdx.x * 4u + wv;
+  if (c < n_chunks) {
+    float o[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float v[3];
+      load_px_t<IN>(src, 256u * c + lane + 64u * j, v);
+      px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
+    }
+    if (OCHW) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t p = 256u * c + lane + 64u * j, n = div_hw.div(p);
+        const size_t e = (size_t)3 * n * hw + (p - n * hw);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) put<OUT>(out, e + (size_t)ch * hw, o[j][ch]);
+      }
+    } else {
+      // the chunk as packed HWC in the wave's slice, then 3 stores per lane
+      if (OUT == MACT_F32) {
+        float* sf = reinterpret_cast<float*>(s_out[wv]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) sf[3 * (lane + 64 * j) + ch] = o[j][ch];
+      } else {
+        __half* sh = reinterpret_cast<__half*>(s_out[wv]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) sh[3 * (lane + 64 * j) + ch] = f2h_rn(o[j][ch]);
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): every lane's LDS writes have landed
+      __builtin_amdgcn_wave_barrier();
+      if (OUT == MACT_F32) {
+        g_f4* d = static_cast<g_f4*>(out) + (size_t)c * 192;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(s_out[wv][q * 64 + lane], d + q * 64 + lane);
+      } else {
+        const g_f2* s2 = reinterpret_cast<const g_f2*>(s_out[wv]);
+        g_f2* d = static_cast<g_f2*>(out) + (size_t)c * 192;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) __builtin_nontemporal_store(s2[q * 64 + lane], d + q * 64 + lane);
+      }
+    }
+  }
+  // the last n_px % 256 pixels, one per thread of block 0
+  const uint32_t tail0 = n_chunks << 8;
+  if (blockIdx.x == 0 && threadIdx.x < n_px - tail0) {
+    const uint32_t p = tail0 + threadIdx.x;
+    float v[3], r[3];
+    load_px_t<IN>(src, p, v);
+    px1<IN, XF, DEG>(k, gamma, gtab, v, r);
+    const uint32_t n = OCHW ? div_hw.div(p) : 0u;
+    const size_t e = OCHW ? (size_t)3 * n * hw + (p - n * hw) : (size_t)3 * p;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) put<OUT>(out, e + (OCHW ? (size_t)ch * hw : (size_t)ch), r[ch]);
+  }
+}
+
+template <int IN, int OUT, int DEG, bool OCHW>
+static void launch_gather_xf(int xform, const KImage& src, void* out, uint32_t n_px, uint32_t hw, const KCoef& k,
+                             int gamma, hipStream_t st) {
+  const uint32_t blocks = std::max<uint32_t>(1, ((n_px >> 8) + 3) / 4);
+  const FastDiv d = make_fastdiv(hw);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_gather<IN, OUT, MACT_LAB, DEG, OCHW>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_gather<IN, OUT, MACT_HSI, DEG, OCHW>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_gather<IN, OUT, MACT_LUV, DEG, OCHW>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma);
+  else hipLaunchKernelGGL((k_gather<IN, OUT, MACT_SCT, DEG, OCHW>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma);
+}
+
+template <int IN>
+static void launch_gather_in(int xform, int out_dtype, bool ochw, int deg, const KImage& src, void* out, uint32_t n_px,
+                             uint32_t hw, const KCoef& k, int gamma, hipStream_t st) {
+  if (out_dtype == MACT_F32) {
+    if (ochw) {
+      if (deg == 5) launch_gather_xf<IN, MACT_F32, 5, true>(xform, src, out, n_px, hw, k, gamma, st);
+      else launch_gather_xf<IN, MACT_F32, 7, true>(xform, src, out, n_px, hw, k, gamma, st);
+    } else {
+      if (deg == 5) launch_gather_xf<IN, MACT_F32, 5, false>(xform, src, out, n_px, hw, k, gamma, st);
+      else launch_gather_xf<IN, MACT_F32, 7, false>(xform, src, out, n_px, hw, k, gamma, st);
+    }
+  } else {
+    if (ochw) {
+      if (deg == 5) launch_gather_xf<IN, MACT_F16, 5, true>(xform, src, out, n_px, hw, k, gamma, st);
+      else launch_gather_xf<IN, MACT_F16, 7, true>(xform, src, out, n_px, hw, k, gamma, st);
+    } else {
+      if (deg == 5) launch_gather_xf<IN, MACT_F16, 5, false>(xform, src, out, n_px, hw, k, gamma, st);
+      else launch_gather_xf<IN, MACT_F16, 7, false>(xform, src, out, n_px, hw, k, gamma, st);
+    }
+  }
+}
+
+void launch_gather(int in_dtype, int xform, int out_dtype, bool out_chw, int deg, const KImage& src, void* out,
+                   uint32_t n_px, uint32_t hw, const KCoef& k, int gamma, hipStream_t st) {
+  if (in_dtype == MACT_U8) launch_gather_in<MACT_U8>(xform, out_dtype, out_chw, deg, src, out, n_px, hw, k, gamma, st);
+  else if (in_dtype == MACT_U16) launch_gather_in<MACT_U16>(xform, out_dtype, out_chw, deg, src, out, n_px, hw, k, gamma, st);
+  else if (in_dtype == MACT_F16) launch_gather_in<MACT_F16>(xform, out_dtype, out_chw, deg, src, out, n_px, hw, k, gamma, st);
+  else launch_gather_in<MACT_F32>(xform, out_dtype, out_chw, deg, src, out, n_px, hw, k, gamma, st);
+}
+
+}  // namespace mact

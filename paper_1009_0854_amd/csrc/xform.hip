@@ -16,6 +16,7 @@
 //    lane, no LDS.
 //  * k_chw_hwc4: packed CHW of any input type -> packed HWC through the
 //    wave's LDS slice.
+//  * k_gather (gather.hip): any other input into packed HWC or CHW output.
 //  * k_generic: any element type, layout and stride, one pixel per lane step.
 // Every kernel but k_generic writes float32 or float16 by template; k_generic
 // writes either at run time.
@@ -1071,7 +1072,8 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   // fast shapes, each to float32 or float16: packed HWC of any input type -> packed HWC or (W H a
   // multiple of 4) packed CHW, row-strided HWC -> packed HWC and row-strided CHW -> packed HWC or
   // CHW (rows of a multiple of 4 pixels), packed CHW of any input type -> packed CHW or HWC (W H a
-  // multiple of 4); everything else takes k_generic
+  // multiple of 4); any other input into packed output takes k_gather (gather.hip), and strided
+  // or misaligned outputs k_generic
   const bool f_out = ho.dtype == MACT_F32 || ho.dtype == MACT_F16;
   const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
                     hi.packed && f_out && ho.layout == MACT_HWC && ho.packed;
@@ -1138,6 +1140,9 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
         launch_chw_rows4_any<true>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_chunks, g, k, gamma, st);
       else
         launch_chw_rows4_any<false>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_chunks, g, k, gamma, st);
+    } else if (ho.packed && f_out && aligned(op, 16)) {
+      launch_gather(hi.dtype, params->xform, ho.dtype, ho.layout == MACT_CHW, deg, kimage(hi, n0, cnt), op, n_px,
+                    (uint32_t)(hi.W * hi.H), k, gamma, st);
     } else {
       const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
       const unsigned grid = full_grid(n_px, 256);

@@ -140,3 +140,66 @@ def test_layout_change_hwc_to_chw(M):
     torch.cuda.synchronize()
     assert chw.shape == (2, 3, 20, 30)
     assert torch.equal(chw.permute(0, 2, 3, 1), hwc)
+
+
+def _src(dtype, shape, seed):
+    """A packed HWC batch of 2 images on the host, values spanning the type's range."""
+    rng = np.random.default_rng(seed)
+    if dtype == "u8":
+        return rng.integers(0, 256, (2,) + shape + (3,)).astype(np.uint8)
+    if dtype == "u16":
+        return rng.integers(0, 65536, (2,) + shape + (3,)).astype(np.uint16)
+    x = (rng.random((2,) + shape + (3,)) * 1.1 - 0.05).astype(np.float32)
+    return x.astype(np.float16) if dtype == "f16" else x
+
+
+def _host_padded(a, last_pad):
+    """Host array `a` on the GPU in a tensor whose last axis is `last_pad` wider, as a view of the
+    original extent (built on the host: torch has few 16-bit unsigned kernels on the GPU)."""
+    big = np.zeros(a.shape[:-1] + (a.shape[-1] + last_pad,), dtype=a.dtype)
+    big[..., :a.shape[-1]] = a
+    return torch.from_numpy(big).cuda()[..., :a.shape[-1]]
+
+
+def _padded_rows_hwc(a):
+    """Host array `a` (N, H, W, 3) on the GPU in a tensor whose rows are 3 pixels wider, as a view."""
+    big = np.zeros(a.shape[:2] + (a.shape[2] + 3, 3), dtype=a.dtype)
+    big[:, :, :a.shape[2]] = a
+    return torch.from_numpy(big).cuda()[:, :, :a.shape[2]]
+
+
+ODD_SHAPES = [(5, 7), (33, 31), (129, 67)]
+
+
+@pytest.mark.parametrize("out_kind", ["hwc_f32", "hwc_f16", "chw_f32", "chw_f16"])
+@pytest.mark.parametrize("src_kind", ["hwc_rows", "chw_packed", "chw_rows"])
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f16", "f32"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3])
+def test_gather_equals_general(M, xform, dtype, src_kind, out_kind):
+    # inputs no 4-pixel kernel takes (rows of an odd width, CHW planes of an odd W H) into packed
+    # output go to k_gather; the same into a padded (strided) output view to k_generic: same bits
+    p = M.default_params(xform)
+    layout_out, odt = out_kind.split("_")
+    odt = torch.float32 if odt == "f32" else torch.float16
+    for si, shape in enumerate(ODD_SHAPES):
+        x = _src(dtype, shape, 100 * xform + 10 * si + len(src_kind))
+        chw = np.ascontiguousarray(x.transpose(0, 3, 1, 2))
+        if src_kind == "hwc_rows":
+            src, layout = _padded_rows_hwc(x), "hwc"
+        elif src_kind == "chw_packed":
+            src, layout = torch.from_numpy(chw).cuda(), "chw"
+        else:
+            src, layout = _host_padded(chw, 5), "chw"
+        oshape = (2,) + shape + (3,) if layout_out == "hwc" else (2, 3) + shape
+        packed = torch.empty(oshape, dtype=odt, device="cuda")
+        zeros = np.zeros(oshape, dtype=np.float32 if odt == torch.float32 else np.float16)
+        strided = _padded_rows_hwc(zeros) if layout_out == "hwc" else _host_padded(zeros, 2)
+        gm = "bt709" if dtype in ("u8", "u16") else "none"
+        M.transform(src, params=p, layout=layout, gamma=gm, out=packed, out_layout=layout_out)
+        M.transform(src, params=p, layout=layout, gamma=gm, out=strided, out_layout=layout_out)
+        torch.cuda.synchronize()
+        assert torch.equal(packed, strided), (shape,)
+        if dtype == "f32" and odt == torch.float32:
+            xs = np.clip(x.astype(np.float64), 0, 1).reshape(-1, 3)
+            got = packed if layout_out == "hwc" else packed.permute(0, 2, 3, 1)
+            P.assert_parity_ties(xform, got.reshape(-1, 3).cpu().numpy(), xs, P.coeffs(p), gamma="none")
