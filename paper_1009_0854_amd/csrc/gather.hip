@@ -12,9 +12,9 @@
 // load read neighbouring pixels.  The input's layout and strides come from its
 // descriptor (branches uniform over the launch).  HWC output goes through the
 // wave's LDS slice and leaves as 16-byte (float16: 8-byte) stores, each
-// instruction 1 KB (512 B) of contiguous output; CHW output is stored plane by
-// plane, 64 neighbouring elements per instruction.  The per-pixel code is
-// pixel.h's, so the results are the other kernels' bits.
+// instruction 1 KB (512 B) of contiguous output; CHW output goes through the
+// slice as well and leaves as aligned 4-element groups of each plane's run.
+// The per-pixel code is pixel.h's, so the results are the other kernels' bits.
 #include <algorithm>
 
 #include "launch.h"
@@ -52,7 +52,8 @@ template <int IN, int OUT, int XF, int DEG, bool OCHW>
 __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ out, uint32_t n_px, uint32_t hw,
                                                 FastDiv div_hw, KCoef k, int gamma) {
   __shared__ float gtab[256];
-  __shared__ g_f4 s_out[4][OCHW ? 1 : 192];  // 3 KB per wave: 256 pixels of float32 (float16: 1.5 KB)
+  // per wave: 256 pixels of float32 HWC (3 KB; float16 1.5 KB), or 3 planes of 260 elements (CHW)
+  __shared__ g_f4 s_out[4][OCHW ? 195 : 192];
   if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
     gtab[threadIdx.x] = k_gamma_table[gamma][threadIdx.x];
     __syncthreads();
@@ -69,10 +70,62 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
       load_px_t<IN>(src, 256u * c + lane + 64u * j, v);
       px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
     }
-    if (OCHW) {
+    const uint32_t p0 = 256u * c, n0 = div_hw.div(p0);
+    if (OCHW && div_hw.div(p0 + 255u) == n0) {
+      // the chunk inside one image: each plane's 256 outputs are one run starting at element e0.
+      // In the slice, element e0 + k of plane ch sits at ch 260 + e0 % 4 + k, so that the run's
+      // 4-element groups, aligned in the output, are aligned in LDS too; lane l stores group l
+      // (and lane 0 a 65th) with one 16-byte (float16: 8-byte) store, element by element where the
+      // group reaches past the run.
+      const size_t e0 = (size_t)3 * n0 * hw + (p0 - n0 * hw);
+      const uint32_t sh0 = (uint32_t)(e0 & 3u);
+      if (OUT == MACT_F32) {
+        float* sf = reinterpret_cast<float*>(s_out[wv]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) sf[260 * ch + ((sh0 + (uint32_t)(hw & 3u) * ch) & 3u) + lane + 64 * j] = o[j][ch];
+      } else {
+        __half* sh = reinterpret_cast<__half*>(s_out[wv]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) sh[260 * ch + ((sh0 + (uint32_t)(hw & 3u) * ch) & 3u) + lane + 64 * j] = f2h_rn(o[j][ch]);
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const size_t e = e0 + (size_t)ch * hw;  // the plane's run: elements [e, e + 256)
+        const uint32_t sh = (uint32_t)(e & 3u);
+        const size_t a0 = e - sh;                // first group
+        const uint32_t groups = (sh + 256u + 3u) / 4u;
+        for (uint32_t g = lane; g < groups; g += 64u) {
+          const uint32_t lo = 260u * ch + 4u * g;  // the group's slice index
+          const size_t ga = a0 + 4u * g;
+          if (ga >= e && ga + 4u <= e + 256u) {
+            if (OUT == MACT_F32)
+              __builtin_nontemporal_store(*reinterpret_cast<const g_f4*>(reinterpret_cast<const float*>(s_out[wv]) + lo),
+                                          reinterpret_cast<g_f4*>(static_cast<float*>(out) + ga));
+            else
+              __builtin_nontemporal_store(*reinterpret_cast<const g_f2*>(reinterpret_cast<const __half*>(s_out[wv]) + lo),
+                                          reinterpret_cast<g_f2*>(static_cast<__half*>(out) + ga));
+          } else {
+#pragma unroll
+            for (uint32_t t = 0; t < 4u; ++t) {
+              if (ga + t < e || ga + t >= e + 256u) continue;
+              if (OUT == MACT_F32) static_cast<float*>(out)[ga + t] = reinterpret_cast<const float*>(s_out[wv])[lo + t];
+              else static_cast<__half*>(out)[ga + t] = reinterpret_cast<const __half*>(s_out[wv])[lo + t];
+            }
+          }
+        }
+      }
+    } else if (OCHW) {
+      // the chunk spans two images or more: element by element
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const uint32_t p = 256u * c + lane + 64u * j, n = div_hw.div(p);
+        const uint32_t p = p0 + lane + 64u * j, n = div_hw.div(p);
         const size_t e = (size_t)3 * n * hw + (p - n * hw);
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) put<OUT>(out, e + (size_t)ch * hw, o[j][ch]);
