@@ -493,16 +493,16 @@ def bench_batch(M, steps):
     return res
 
 
-def _requests(n, seed, pool, rate=2000.0):
+def _requests(n, seed, pool, rate=2000.0, w_range=(256, 3840), h_range=(256, 2160)):
     """Request stream: exponential gaps at `rate` per second (all at time 0 for
-    rate None); width log-uniform in 256..3840, height in 256..2160; uint8 or
-    float16 input (50/50); transform uniform over CIELAB, HSI, SCT.  Buffers
-    cycle through `pool` pinned slots."""
+    rate None); width and height log-uniform in w_range and h_range (default
+    256..3840 by 256..2160); uint8 or float16 input (50/50); transform uniform
+    over CIELAB, HSI, SCT.  Buffers cycle through `pool` pinned slots."""
     import torch
     import synth
     arr, g = synth.poisson_arrivals(n, 2000.0, seed)
     arr = np.zeros(n) if rate is None else arr * (2000.0 / rate)
-    sizes, g2 = synth.uneven_sizes(n, seed + 1, 256, 3840, 256, 2160)
+    sizes, g2 = synth.uneven_sizes(n, seed + 1, w_range[0], w_range[1], h_range[0], h_range[1])
     kinds = g2.integers(0, 2, n)
     xfs = g2.integers(0, 3, n)
     # one pinned buffer pair per slot, large enough for any request of that slot
@@ -589,9 +589,13 @@ def _plain_stats(M, rs, px):
 def bench_serve(M, n_req=2000, pool=16):
     """The served form at 2000 requests/s (the first 400 requests of the stream
     run once untimed on the same server, then the whole stream is timed)
-    beside the plain per-request path; then a load sweep (1000 requests at
-    4000 and 8000 requests/s and all at once, 32 pinned slots) to show
-    continuous batching as the queue fills."""
+    beside the plain per-request path; then a load sweep of the same request
+    sizes (1000 requests at 4000 and 8000 requests/s and all at once, 32 pinned
+    slots), which the PCIe copies bound (a request's kernel takes microseconds,
+    its copies milliseconds, so a free compute slot finds one ready request and
+    batches hold one); and a sweep of small requests (4000 of 32..256 pixels a
+    side at 20000 and 50000 requests/s and all at once, 256 slots), where
+    several inputs land while the slots are busy and join one batch."""
     reqs = _requests(n_req, 6, pool)
     px = sum(r[1].shape[0] * r[1].shape[1] for r in reqs)
     srv = M.Server(arena_bytes=8 << 30, max_batch=64, compute_streams=2, max_queue=1 << 20)
@@ -606,8 +610,16 @@ def bench_serve(M, n_req=2000, pool=16):
                       "served": _served_stats(M, srv, rs, 32, rpx, rate, rs[:100]),
                       "plain_per_request": _plain_stats(M, rs, rpx)})
         del rs
+    small = []
+    for rate in (20000.0, 50000.0, None):
+        rs = _requests(4000, 11, 256, rate, (32, 256), (32, 256))
+        rpx = sum(r[1].shape[0] * r[1].shape[1] for r in rs)
+        small.append({"offered_req_s": rate if rate is not None else "all at t=0", "sizes": "32..256 a side",
+                      "served": _served_stats(M, srv, rs, 256, rpx, rate, rs[:400]),
+                      "plain_per_request": _plain_stats(M, rs, rpx)})
+        del rs
     srv.close()
-    return {"served": served, "plain_per_request": plain, "load_sweep": sweep,
+    return {"served": served, "plain_per_request": plain, "load_sweep": sweep, "small_requests": small,
             "workload": "Poisson 2000 req/s, %d requests, W~logU[256,3840], H~logU[256,2160], uint8/fp16, "
                         "CIELAB/HSI/SCT; pinned host buffers; latency = arrival -> output on host" % n_req}
 
@@ -812,9 +824,17 @@ def served_summary(forms):
     if not sv:
         return None
     a, b = sv["served"], sv["plain_per_request"]
-    return {"p50_ms": a["p50_ms"], "p99_ms": a["p99_ms"], "Mpx_s": a["Mpx_s"], "mean_batch": a["mean_batch"],
-            "plain_p50_ms": b["p50_ms"], "plain_p99_ms": b["p99_ms"], "plain_Mpx_s": b["Mpx_s"],
-            "offered_req_s": a["offered_req_s"]}
+    out = {"p50_ms": a["p50_ms"], "p99_ms": a["p99_ms"], "Mpx_s": a["Mpx_s"], "mean_batch": a["mean_batch"],
+           "plain_p50_ms": b["p50_ms"], "plain_p99_ms": b["p99_ms"], "plain_Mpx_s": b["Mpx_s"],
+           "offered_req_s": a["offered_req_s"]}
+    # small requests at 50000 requests/s, where batches form
+    sm = [x for x in sv.get("small_requests", []) if x["offered_req_s"] == 50000.0]
+    if sm:
+        c, d = sm[0]["served"], sm[0]["plain_per_request"]
+        out["small_50k_req_s"] = {"mean_batch": c["mean_batch"], "Mpx_s": c["Mpx_s"], "p50_ms": c["p50_ms"],
+                                  "p99_ms": c["p99_ms"], "plain_Mpx_s": d["Mpx_s"], "plain_p50_ms": d["p50_ms"],
+                                  "plain_p99_ms": d["p99_ms"]}
+    return out
 
 
 def kernel_hash():
