@@ -74,3 +74,22 @@ def test_split_of_odd_sized_images_keeps_the_coalesced_kernel(M):
     whole = timed(lambda: M.transform(x, params=p, out=y))
     each = timed(lambda: [M.transform(x[i:i + 1], params=p, out=y[i:i + 1]) for i in range(n)])
     assert whole < 1.5 * each, (whole, each)
+
+
+def test_split_of_odd_planes_through_the_gather_kernel(M):
+    # 17 CHW images of 2161 x 2161 (odd W H; 79 Mpx): no 4-pixel kernel takes them, so each
+    # launch of the split goes to k_gather, into packed CHW and HWC output; every image equals
+    # its own call, on both sides of the split
+    n, h, w = 17, 2161, 2161
+    assert n * h * w > (1 << 26)
+    g = torch.Generator(device="cuda").manual_seed(23)
+    x = torch.randint(0, 256, (n, 3, h, w), dtype=torch.uint8, device="cuda", generator=g)
+    p = M.default_params("sct")
+    for out_layout in ("chw", "hwc"):
+        y = M.transform(x, params=p, layout="chw", out_layout=out_layout)
+        torch.cuda.synchronize()
+        for i in (0, 7, 8, 9, 16):
+            one = M.transform(x[i:i + 1], params=p, layout="chw", out_layout=out_layout)
+            torch.cuda.synchronize()
+            assert torch.equal(y[i:i + 1], one), (out_layout, i)
+        del y
