@@ -40,8 +40,8 @@ __device__ __forceinline__ void load_px_t(const KImage& im, uint32_t p, float v[
   }
 }
 
-// Channel c of pixel p (image n, pixel r of hw) of packed output: HWC at
-// 3 p + c, CHW at (3 n + c) hw + r.
+// Element e of packed output, float16 rounded to nearest even (channel c of
+// pixel p, pixel r of image n: HWC e = 3 p + c, CHW e = (3 n + c) hw + r).
 template <int OUT>
 __device__ __forceinline__ void put(void* out, size_t e, float x) {
   if (OUT == MACT_F32) static_cast<float*>(out)[e] = x;
