@@ -396,26 +396,71 @@ __device__ __forceinline__ float swap1(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
 }
 
+// The order in which a wave takes its chunk's 256 pixels from the L2: ord[q] is
+// the pixel at position q, the pixels grouped by the cache line of their
+// cell's first node (key: R and G cells mod 8, B cell / 8 mod 4; a counting
+// sort through 256 counters in `bins`).  The vector L1 looks up the lines of
+// each group of 4 neighbouring lanes: lanes on pixels of one cell share them,
+// and neighbouring pixels of a noisy image often sit in different cells.
+__device__ __forceinline__ void chunk_order(const uint8_t* s8, uint32_t N, uint32_t lane, uint32_t* bins,
+                                            uint8_t* ord) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) bins[lane + 64 * j] = 0u;
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  uint32_t key[4], rank[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t P = lane + 64u * j;
+    const uint32_t i0 = min(s8[3 * P] * (N - 1) / 255u, N - 2), i1 = min(s8[3 * P + 1] * (N - 1) / 255u, N - 2),
+                   i2 = min(s8[3 * P + 2] * (N - 1) / 255u, N - 2);
+    key[j] = ((i0 & 7u) << 5) | ((i1 & 7u) << 2) | ((i2 >> 3) & 3u);
+    rank[j] = atomicAdd(&bins[key[j]], 1u);
+  }
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  __builtin_amdgcn_wave_barrier();
+  // exclusive scan of the counters: 4 per lane, then across the wave
+  const uint4 cnt = reinterpret_cast<const uint4*>(bins)[lane];
+  const uint32_t tot = cnt.x + cnt.y + cnt.z + cnt.w;
+  uint32_t x = tot;
+#pragma unroll
+  for (uint32_t d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  const uint32_t e = x - tot;
+  reinterpret_cast<uint4*>(bins)[lane] = uint4{e, e + cnt.x, e + cnt.x + cnt.y, e + cnt.x + cnt.y + cnt.z};
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) ord[bins[key[j]] + rank[j]] = (uint8_t)(lane + 64u * j);
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Trilinear interpolation of a 256-pixel chunk with 2 lanes per pixel (grids
-// read through the L2).  In each of 8 rounds the lane pair h takes pixel
-// 32 r + h; lane bit 0 is dB, and each lane gathers its 4 corners (dR dG = 00,
+// read through the L2).  In each of 8 rounds the lane pair h takes the pixel
+// at position 32 r + h of the chunk's order `ord` (chunk_order); lane bit 0 is
+// dB, and each lane gathers its 4 corners (dR dG = 00,
 // 01, 10, 11 at that dB).  The two lanes' corners of one (dR, dG) are
 // neighbours along B, one 32-byte run (the cell-major form: one 128-byte run
 // per pixel), so an instruction touches about 32 lines instead of 64 and the
 // vector L1, whose accesses bound these kernels, does about half the work.
 // Each lane sums its corners as a product at dR dG = 00 and fused multiply-adds
 // at 01, 10, 11; the pair adds its two sums: lut_px's order, so the results
-// are lut_px's bits.  The pixel of round r ends in lane 2 h + (r mod
-// 2), slot r / 2.  s8: the chunk's 768 input bytes.
+// are lut_px's bits.  The sum of round r ends in lane 2 h + (r mod 2), slot
+// r / 2, with its pixel's index in pix.  s8: the chunk's 768 input bytes.
 template <int XF, int FORM>
 __device__ __forceinline__ void tri_pairs(const f4* __restrict__ nodes, const float* __restrict__ lp, uint32_t N,
-                                          const uint8_t* s8, uint32_t lane, f4 acc[4], float acc1[4]) {
+                                          const uint8_t* s8, const uint8_t* ord, uint32_t lane, f4 acc[4],
+                                          float acc1[4], uint32_t pix[4]) {
   constexpr bool CELL = FORM == kCells;
   const uint32_t db = lane & 1u, h = lane >> 1;
   const uint32_t sR = CELL ? 4u : N * N, sG = CELL ? 2u : N;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const uint32_t P = 32u * r + h;
+    const uint32_t P = ord[32u * r + h];
     uint32_t i0, i1, i2;
     float f0, f1, f2;
     locate_u8(s8[3 * P], N, i0, f0);
@@ -452,6 +497,7 @@ __device__ __forceinline__ void tri_pairs(const f4* __restrict__ nodes, const fl
     if (db == (uint32_t)(r & 1)) {
       acc[r >> 1] = a;
       acc1[r >> 1] = b;
+      pix[r >> 1] = P;
     }
     // one round's gathers in flight at a time: more fit in registers only at a lower occupancy,
     // and measured slower (cell-major CIELAB and HSI 33^3: 16-18%)
@@ -461,19 +507,20 @@ __device__ __forceinline__ void tri_pairs(const f4* __restrict__ nodes, const fl
 
 // Prism, pyramidal and tetrahedral on the cell-major form with 2 lanes per
 // pixel: all of a pixel's corners lie in its cell's 128-byte run, so the lane
-// pair of pixel 32 r + h (round r of 8, as in tri_pairs) touches one line per
-// instruction.  Both lanes take the method's corners and weights; lane bit 0
+// pair of a pixel (position 32 r + h of `ord` in round r of 8, as in
+// tri_pairs) touches one line per instruction.  Both lanes take the method's corners and weights; lane bit 0
 // picks the even or the odd corner ids, and each lane sums its chain (a
 // product, then fused multiply-adds in id order, SCT's L alike); the pair adds
 // the two sums.  lut_px's order, so the results are lut_px's bits.
-template <int METHOD, int XF>
+template <int METHOD, int XF, bool SORTED>
 __device__ __forceinline__ void cell_pairs(const f4* __restrict__ nodes, const float* __restrict__ lp, uint32_t N,
-                                           const uint8_t* s8, uint32_t lane, f4 acc[4], float acc1[4]) {
+                                           const uint8_t* s8, const uint8_t* ord, uint32_t lane, f4 acc[4],
+                                           float acc1[4], uint32_t pix[4]) {
   constexpr int K = Corners<METHOD>::K;
   const uint32_t db = lane & 1u, h = lane >> 1;
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const uint32_t P = 32u * r + h;
+    const uint32_t P = SORTED ? ord[32u * r + h] : 32u * r + h;
     uint32_t i0, i1, i2;
     float f0, f1, f2;
     locate_u8(s8[3 * P], N, i0, f0);
@@ -503,6 +550,7 @@ __device__ __forceinline__ void cell_pairs(const f4* __restrict__ nodes, const f
     if (db == (uint32_t)(r & 1)) {
       acc[r >> 1] = a;
       acc1[r >> 1] = b;
+      pix[r >> 1] = P;
     }
     // one round's gathers in flight at a time, as in tri_pairs
     __builtin_amdgcn_sched_barrier(0);
@@ -639,40 +687,50 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the bytes have landed
       __builtin_amdgcn_wave_barrier();
+      // the pixels grouped by cache line (after the wave slices: 256 counters and the order per
+      // wave), except for prism and pyramidal on cell-major grids, whose kernels are bound by their
+      // arithmetic, which the ordering adds to (17^3, 33^3: -12 to -23%)
+      constexpr bool SORT = !(FORM == kCells && (METHOD == MACT_PRISM || METHOD == MACT_PYRAMIDAL));
+      uint32_t* bins = reinterpret_cast<uint32_t*>(tbuf + nw * 192) + wv * 320;
+      uint8_t* ord = reinterpret_cast<uint8_t*>(bins + 256);
+      if (SORT) chunk_order(s8, N, lane, bins, ord);
       // two lanes per pixel: trilinear on the packed and cell-major grids; the other methods on
       // cell-major grids of more than 256 KB (17^3 and up: +2 to +38%; on 9^3, 64 KB, pyramidal
       // lost 19% and the others nothing)
       if ((METHOD == MACT_TRILINEAR && FORM != kCache) || (FORM == kCells && (N - 1) * (N - 1) * (N - 1) > 2048u)) {
         f4 acc[4];
         float acc1[4];
+        uint32_t pix[4];
         if (METHOD == MACT_TRILINEAR)
-          tri_pairs<XF, FORM>(nodes, lp, N, s8, lane, acc, acc1);
+          tri_pairs<XF, FORM>(nodes, lp, N, s8, ord, lane, acc, acc1, pix);
         else
-          cell_pairs<METHOD, XF>(nodes, lp, N, s8, lane, acc, acc1);
+          cell_pairs<METHOD, XF, SORT>(nodes, lp, N, s8, ord, lane, acc, acc1, pix);
         __builtin_amdgcn_s_waitcnt(0xc07f);  // every lane has read its bytes before the slice is reused
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           float o[3];
           lut_out<XF>(acc[m], acc1[m], o);
-          const uint32_t p = 32u * (2u * m + (lane & 1u)) + (lane >> 1);
+          const uint32_t p = pix[m];
           sf[3 * p] = o[0];
           sf[3 * p + 1] = o[1];
           sf[3 * p + 2] = o[2];
         }
       } else {
-        uint32_t rgb[4][3];
+        uint32_t rgb[4][3], pix[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j) {
+          pix[j] = SORT ? ord[lane + 64 * j] : lane + 64u * j;
 #pragma unroll
-          for (int q = 0; q < 3; ++q) rgb[j][q] = s8[3 * (lane + 64 * j) + q];
+          for (int q = 0; q < 3; ++q) rgb[j][q] = s8[3 * pix[j] + q];
+        }
         __builtin_amdgcn_s_waitcnt(0xc07f);  // every lane has read its bytes before the slice is reused
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           float o[3];
           lut_px_u8<METHOD, XF, FORM, true>(nodes, lp, N, sR, sG, rgb[j][0], rgb[j][1], rgb[j][2], o);
-          const uint32_t p = lane + 64 * j;
+          const uint32_t p = pix[j];
           sf[3 * p] = o[0];
           sf[3 * p + 1] = o[1];
           sf[3 * p + 2] = o[2];
@@ -785,7 +843,8 @@ static hipError_t launch_lut(const f4* lut, uint32_t N, const HostImage& hi, con
     uint32_t sR = N * N, sG = N;
     size_t staged = bytes;
     if (lds && FORM == kPacked) lds_strides(XF, N, lds_max - t_lds, sR, sG, staged);
-    const size_t shm = (lds ? staged : 0) + (size_t)(block / 64) * 192 * sizeof(f4);
+    // per wave: the 3 KB slice, and for gathers through the L2 the chunk's counters and order (1280 B)
+    const size_t shm = (lds ? staged : 0) + (size_t)(block / 64) * (192 * sizeof(f4) + (lds ? 0 : 1280));
     const uint64_t chunks = std::max<uint64_t>(1, n_px >> 8);
     // a staged grid is worth keeping: one or two resident workgroups per CU stride over the image;
     // gathers from global memory: the grid covers the image once, one chunk per wave
