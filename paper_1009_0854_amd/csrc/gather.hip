@@ -40,6 +40,32 @@ __device__ __forceinline__ void load_px_t(const KImage& im, uint32_t p, float v[
   }
 }
 
+// Pixel r of one image whose first element is `base` (the image's place in
+// `im`), as load_px_t returns it.  A chunk inside one image takes its base
+// once, uniform over the wave, so a lane's address is its pixel's offset in
+// the image: one division by the row width for row-strided inputs, none for
+// packed ones, where load_px_t divides by the image size and multiplies out
+// the strides for every pixel.
+template <int IN>
+__device__ __forceinline__ void load_in_image(const KImage& im, const void* base, uint32_t r, float v[3]) {
+  int64_t o, step;
+  if (im.packed) {
+    o = im.layout == MACT_HWC ? 3 * (int64_t)r : (int64_t)r;
+  } else {
+    const uint32_t y = im.div_w.div(r), x = r - y * im.W;
+    o = (int64_t)y * im.rs + (im.layout == MACT_HWC ? 3 * (int64_t)x : (int64_t)x);
+  }
+  step = im.layout == MACT_HWC ? 1 : im.ps;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t e = o + c * step;
+    if (IN == MACT_U8) v[c] = (float)static_cast<const uint8_t*>(base)[e];
+    else if (IN == MACT_U16) v[c] = (float)static_cast<const uint16_t*>(base)[e];
+    else if (IN == MACT_F16) v[c] = clamp01(__half2float(static_cast<const __half*>(base)[e]));
+    else v[c] = clamp01(static_cast<const float*>(base)[e]);
+  }
+}
+
 // Element e of packed output, float16 rounded to nearest even (channel c of
 // pixel p, pixel r of image n: HWC e = 3 p + c, CHW e = (3 n + c) hw + r).
 template <int OUT>
@@ -61,17 +87,30 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
   pin_lead<DEG>(k);
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
   const uint32_t n_chunks = n_px >> 8;
-  const uint32_t c = blockIdx.x * 4u + wv;
+  const uint32_t c = __builtin_amdgcn_readfirstlane(blockIdx.x * 4u + wv);
   if (c < n_chunks) {
-    float o[4][3];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      float v[3];
-      load_px_t<IN>(src, 256u * c + lane + 64u * j, v);
-      px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
-    }
     const uint32_t p0 = 256u * c, n0 = div_hw.div(p0);
-    if (OCHW && div_hw.div(p0 + 255u) == n0) {
+    const bool one = div_hw.div(p0 + 255u) == n0;  // the chunk inside one image
+    float o[4][3];
+    if (one) {
+      constexpr int ES = IN == MACT_U8 ? 1 : IN == MACT_F32 ? 4 : 2;
+      const void* base = static_cast<const char*>(src.ptr) + (int64_t)n0 * src.bs * ES;
+      const uint32_t r0 = p0 - n0 * hw;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float v[3];
+        load_in_image<IN>(src, base, r0 + lane + 64u * j, v);
+        px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float v[3];
+        load_px_t<IN>(src, p0 + lane + 64u * j, v);
+        px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
+      }
+    }
+    if (OCHW && one) {
       // the chunk inside one image: each plane's 256 outputs are one run starting at element e0.
       // In the slice, element e0 + k of plane ch sits at ch 260 + e0 % 4 + k, so that the run's
       // 4-element groups, aligned in the output, are aligned in LDS too; lane l stores group l
@@ -185,25 +224,25 @@ static void launch_gather_xf(int xform, const KImage& src, void* out, uint32_t n
   else hipLaunchKernelGGL((k_gather<IN, OUT, MACT_SCT, DEG, OCHW>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma);
 }
 
+// The polynomials at their own degree (up to 4, 5, or up to 7), as the 4-pixel
+// kernels evaluate them: a zero leading coefficient leaves Horner's sums unchanged.
+template <int IN, int OUT, bool OCHW>
+static void launch_gather_deg(int xform, int deg, const KImage& src, void* out, uint32_t n_px, uint32_t hw,
+                              const KCoef& k, int gamma, hipStream_t st) {
+  if (deg <= 4) launch_gather_xf<IN, OUT, 4, OCHW>(xform, src, out, n_px, hw, k, gamma, st);
+  else if (deg == 5) launch_gather_xf<IN, OUT, 5, OCHW>(xform, src, out, n_px, hw, k, gamma, st);
+  else launch_gather_xf<IN, OUT, 7, OCHW>(xform, src, out, n_px, hw, k, gamma, st);
+}
+
 template <int IN>
 static void launch_gather_in(int xform, int out_dtype, bool ochw, int deg, const KImage& src, void* out, uint32_t n_px,
                              uint32_t hw, const KCoef& k, int gamma, hipStream_t st) {
   if (out_dtype == MACT_F32) {
-    if (ochw) {
-      if (deg == 5) launch_gather_xf<IN, MACT_F32, 5, true>(xform, src, out, n_px, hw, k, gamma, st);
-      else launch_gather_xf<IN, MACT_F32, 7, true>(xform, src, out, n_px, hw, k, gamma, st);
-    } else {
-      if (deg == 5) launch_gather_xf<IN, MACT_F32, 5, false>(xform, src, out, n_px, hw, k, gamma, st);
-      else launch_gather_xf<IN, MACT_F32, 7, false>(xform, src, out, n_px, hw, k, gamma, st);
-    }
+    if (ochw) launch_gather_deg<IN, MACT_F32, true>(xform, deg, src, out, n_px, hw, k, gamma, st);
+    else launch_gather_deg<IN, MACT_F32, false>(xform, deg, src, out, n_px, hw, k, gamma, st);
   } else {
-    if (ochw) {
-      if (deg == 5) launch_gather_xf<IN, MACT_F16, 5, true>(xform, src, out, n_px, hw, k, gamma, st);
-      else launch_gather_xf<IN, MACT_F16, 7, true>(xform, src, out, n_px, hw, k, gamma, st);
-    } else {
-      if (deg == 5) launch_gather_xf<IN, MACT_F16, 5, false>(xform, src, out, n_px, hw, k, gamma, st);
-      else launch_gather_xf<IN, MACT_F16, 7, false>(xform, src, out, n_px, hw, k, gamma, st);
-    }
+    if (ochw) launch_gather_deg<IN, MACT_F16, true>(xform, deg, src, out, n_px, hw, k, gamma, st);
+    else launch_gather_deg<IN, MACT_F16, false>(xform, deg, src, out, n_px, hw, k, gamma, st);
   }
 }
 

@@ -78,6 +78,7 @@ uint32_t build_tiles(const std::vector<BDesc>& descs, uint32_t tile, std::vector
 // Any input image (element type in_dtype; layout and strides in `src`) -> packed
 // float32 or float16 (out_dtype) HWC or, with out_chw, CHW of n_px pixels of hw
 // per image, `out` 16-byte aligned: the shapes the 4-pixel kernels do not take.
+// deg: the highest degree among the approximations (evaluated at 4, 5 or 7).
 void launch_gather(int in_dtype, int xform, int out_dtype, bool out_chw, int deg, const KImage& src, void* out,
                    uint32_t n_px, uint32_t hw, const KCoef& k, int gamma, hipStream_t st);
 

@@ -1141,7 +1141,7 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
       else
         launch_chw_rows4_any<false>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_chunks, g, k, gamma, st);
     } else if (ho.packed && f_out && aligned(op, 16)) {
-      launch_gather(hi.dtype, params->xform, ho.dtype, ho.layout == MACT_CHW, deg, kimage(hi, n0, cnt), op, n_px,
+      launch_gather(hi.dtype, params->xform, ho.dtype, ho.layout == MACT_CHW, exact_deg, kimage(hi, n0, cnt), op, n_px,
                     (uint32_t)(hi.W * hi.H), k, gamma, st);
     } else {
       const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
