@@ -113,9 +113,12 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
     if (OCHW && one) {
       // the chunk inside one image: each plane's 256 outputs are one run starting at element e0.
       // In the slice, element e0 + k of plane ch sits at ch 260 + e0 % 4 + k, so that the run's
-      // 4-element groups, aligned in the output, are aligned in LDS too; lane l stores group l
-      // (and lane 0 a 65th) with one 16-byte (float16: 8-byte) store, element by element where the
-      // group reaches past the run.
+      // 4-element groups, aligned in the output, are aligned in LDS too.  A run starting at sh =
+      // e % 4 covers groups 0..63 whole when sh = 0, else groups 1..63 whole and sh elements of a
+      // 65th: lane l stores group l with one 16-byte (float16: 8-byte) store, except lane 0 when
+      // sh != 0, which then stores the run's first 4 - sh and last sh elements one by one, also
+      // non-temporal.  (Those element stores issued first, as plain stores, cost this path 25%;
+      // the groups taken in a loop of one or two passes, both branches in each, 7%.)
       const size_t e0 = (size_t)3 * n0 * hw + (p0 - n0 * hw);
       const uint32_t sh0 = (uint32_t)(e0 & 3u);
       if (OUT == MACT_F32) {
@@ -138,24 +141,31 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
       for (int ch = 0; ch < 3; ++ch) {
         const size_t e = e0 + (size_t)ch * hw;  // the plane's run: elements [e, e + 256)
         const uint32_t sh = (uint32_t)(e & 3u);
-        const size_t a0 = e - sh;                // first group
-        const uint32_t groups = (sh + 256u + 3u) / 4u;
-        for (uint32_t g = lane; g < groups; g += 64u) {
-          const uint32_t lo = 260u * ch + 4u * g;  // the group's slice index
-          const size_t ga = a0 + 4u * g;
-          if (ga >= e && ga + 4u <= e + 256u) {
-            if (OUT == MACT_F32)
-              __builtin_nontemporal_store(*reinterpret_cast<const g_f4*>(reinterpret_cast<const float*>(s_out[wv]) + lo),
-                                          reinterpret_cast<g_f4*>(static_cast<float*>(out) + ga));
-            else
-              __builtin_nontemporal_store(*reinterpret_cast<const g_f2*>(reinterpret_cast<const __half*>(s_out[wv]) + lo),
-                                          reinterpret_cast<g_f2*>(static_cast<__half*>(out) + ga));
-          } else {
+        const uint32_t lo = 260u * ch;           // group 0 in the slice
+        if (OUT == MACT_F32) {
+          float* a0 = static_cast<float*>(out) + (e - sh);  // group 0 in the output
+          const float* sl = reinterpret_cast<const float*>(s_out[wv]) + lo;
+          if (lane != 0 || sh == 0)
+            __builtin_nontemporal_store(*reinterpret_cast<const g_f4*>(sl + 4 * lane), reinterpret_cast<g_f4*>(a0 + 4 * lane));
+          __builtin_amdgcn_sched_barrier(0);
+          if (lane == 0 && sh != 0) {
 #pragma unroll
             for (uint32_t t = 0; t < 4u; ++t) {
-              if (ga + t < e || ga + t >= e + 256u) continue;
-              if (OUT == MACT_F32) static_cast<float*>(out)[ga + t] = reinterpret_cast<const float*>(s_out[wv])[lo + t];
-              else static_cast<__half*>(out)[ga + t] = reinterpret_cast<const __half*>(s_out[wv])[lo + t];
+              const uint32_t i = t >= sh ? t : 256u + t;  // the head's elements of group 0, the tail's of group 64
+              __builtin_nontemporal_store(sl[i], a0 + i);
+            }
+          }
+        } else {
+          __half* a0 = static_cast<__half*>(out) + (e - sh);
+          const __half* sl = reinterpret_cast<const __half*>(s_out[wv]) + lo;
+          if (lane != 0 || sh == 0)
+            __builtin_nontemporal_store(*reinterpret_cast<const g_f2*>(sl + 4 * lane), reinterpret_cast<g_f2*>(a0 + 4 * lane));
+          __builtin_amdgcn_sched_barrier(0);
+          if (lane == 0 && sh != 0) {
+#pragma unroll
+            for (uint32_t t = 0; t < 4u; ++t) {
+              const uint32_t i = t >= sh ? t : 256u + t;
+              __builtin_nontemporal_store(reinterpret_cast<const uint16_t*>(sl)[i], reinterpret_cast<uint16_t*>(a0) + i);
             }
           }
         }
