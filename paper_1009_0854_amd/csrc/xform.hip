@@ -1001,10 +1001,12 @@ template <int KIND, int IN>
 static void launch_planes_io(int xform, int out_dtype, int deg, const void* in, void* out, uint32_t n_px, uint32_t hw,
                              const KCoef& k, int gamma, hipStream_t st) {
   if (out_dtype == MACT_F32) {
-    if (deg == 5) launch_planes<KIND, IN, MACT_F32, 5>(xform, in, out, n_px, hw, k, gamma, st);
+    if (deg <= 4) launch_planes<KIND, IN, MACT_F32, 4>(xform, in, out, n_px, hw, k, gamma, st);
+    else if (deg == 5) launch_planes<KIND, IN, MACT_F32, 5>(xform, in, out, n_px, hw, k, gamma, st);
     else launch_planes<KIND, IN, MACT_F32, 7>(xform, in, out, n_px, hw, k, gamma, st);
   } else {
-    if (deg == 5) launch_planes<KIND, IN, MACT_F16, 5>(xform, in, out, n_px, hw, k, gamma, st);
+    if (deg <= 4) launch_planes<KIND, IN, MACT_F16, 4>(xform, in, out, n_px, hw, k, gamma, st);
+    else if (deg == 5) launch_planes<KIND, IN, MACT_F16, 5>(xform, in, out, n_px, hw, k, gamma, st);
     else launch_planes<KIND, IN, MACT_F16, 7>(xform, in, out, n_px, hw, k, gamma, st);
   }
 }
@@ -1032,10 +1034,12 @@ template <int IN, bool OCHW>
 static void launch_chw_rows4_io(int xform, int out_dtype, int deg, const void* in, void* out, uint32_t n_chunks,
                                 const ChwRows& g, const KCoef& k, int gamma, hipStream_t st) {
   if (out_dtype == MACT_F32) {
-    if (deg == 5) launch_chw_rows4<IN, MACT_F32, 5, OCHW>(xform, in, out, n_chunks, g, k, gamma, st);
+    if (deg <= 4) launch_chw_rows4<IN, MACT_F32, 4, OCHW>(xform, in, out, n_chunks, g, k, gamma, st);
+    else if (deg == 5) launch_chw_rows4<IN, MACT_F32, 5, OCHW>(xform, in, out, n_chunks, g, k, gamma, st);
     else launch_chw_rows4<IN, MACT_F32, 7, OCHW>(xform, in, out, n_chunks, g, k, gamma, st);
   } else {
-    if (deg == 5) launch_chw_rows4<IN, MACT_F16, 5, OCHW>(xform, in, out, n_chunks, g, k, gamma, st);
+    if (deg <= 4) launch_chw_rows4<IN, MACT_F16, 4, OCHW>(xform, in, out, n_chunks, g, k, gamma, st);
+    else if (deg == 5) launch_chw_rows4<IN, MACT_F16, 5, OCHW>(xform, in, out, n_chunks, g, k, gamma, st);
     else launch_chw_rows4<IN, MACT_F16, 7, OCHW>(xform, in, out, n_chunks, g, k, gamma, st);
   }
 }
@@ -1106,11 +1110,11 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
     } else if (planes4 && aligned(ip, planes_align) && aligned(op, 16)) {
       const uint32_t hw = (uint32_t)(hi.W * hi.H);
       if (hi.layout == MACT_CHW && ho.layout == MACT_CHW)
-        launch_planes_any<0>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_px, hw, k, gamma, st);
+        launch_planes_any<0>(hi.dtype, params->xform, ho.dtype, exact_deg, ip, op, n_px, hw, k, gamma, st);
       else if (ho.layout == MACT_CHW)
-        launch_planes_any<1>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_px, hw, k, gamma, st);
+        launch_planes_any<1>(hi.dtype, params->xform, ho.dtype, exact_deg, ip, op, n_px, hw, k, gamma, st);
       else
-        launch_planes_any<2>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_px, hw, k, gamma, st);
+        launch_planes_any<2>(hi.dtype, params->xform, ho.dtype, exact_deg, ip, op, n_px, hw, k, gamma, st);
     } else if (rows4 && aligned(ip, (size_t)rows_align) && aligned(op, 16)) {
       RowGeom g;
       g.W = (uint32_t)hi.W;
@@ -1137,9 +1141,9 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
       g.ps = (uint32_t)hi.ps;
       const uint32_t n_chunks = (uint32_t)(cnt * hi.H) * g.cpr;
       if (ho.layout == MACT_CHW)
-        launch_chw_rows4_any<true>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_chunks, g, k, gamma, st);
+        launch_chw_rows4_any<true>(hi.dtype, params->xform, ho.dtype, exact_deg, ip, op, n_chunks, g, k, gamma, st);
       else
-        launch_chw_rows4_any<false>(hi.dtype, params->xform, ho.dtype, deg, ip, op, n_chunks, g, k, gamma, st);
+        launch_chw_rows4_any<false>(hi.dtype, params->xform, ho.dtype, exact_deg, ip, op, n_chunks, g, k, gamma, st);
     } else if (ho.packed && f_out && aligned(op, 16)) {
       launch_gather(hi.dtype, params->xform, ho.dtype, ho.layout == MACT_CHW, exact_deg, kimage(hi, n0, cnt), op, n_px,
                     (uint32_t)(hi.W * hi.H), k, gamma, st);
@@ -1172,7 +1176,8 @@ extern "C" mact_status mact_transform_backward(const mact_params* params, const 
   if ((s = check_same_shape(hx, hg, "mact_transform_backward: grad_out")) != MACT_OK) return s;
   if ((s = check_same_shape(hx, hd, "mact_transform_backward: grad_in")) != MACT_OK) return s;
   KCoef k;
-  const int deg = pack_coef(*params, &k);
+  int exact_deg = 7;
+  const int deg = pack_coef(*params, &k, &exact_deg);
   KGrad kg;
   std::memset(&kg, 0, sizeof kg);
   for (int j = 1; j <= 7; ++j) {
@@ -1193,7 +1198,8 @@ extern "C" mact_status mact_transform_backward(const mact_params* params, const 
     if (chw4 && aligned(xp, 16) && aligned(gp, 16) && aligned(dp, 16)) {
       const dim3 grid(full_grid(n_px / 4, 256));
       const FastDiv d = make_fastdiv(hw / 4);
-      if (deg == 5) hipLaunchKernelGGL(k_lab_backward_chw4<5>, grid, dim3(256), 0, st, xp, gp, dp, n_px, hw, d, k, kg);
+      if (exact_deg <= 4) hipLaunchKernelGGL(k_lab_backward_chw4<4>, grid, dim3(256), 0, st, xp, gp, dp, n_px, hw, d, k, kg);
+      else if (deg == 5) hipLaunchKernelGGL(k_lab_backward_chw4<5>, grid, dim3(256), 0, st, xp, gp, dp, n_px, hw, d, k, kg);
       else hipLaunchKernelGGL(k_lab_backward_chw4<7>, grid, dim3(256), 0, st, xp, gp, dp, n_px, hw, d, k, kg);
     } else {
       const KImage kx = kimage(hx, n0, cnt), kgo = kimage(hg, n0, cnt), kd = kimage(hd, n0, cnt);
