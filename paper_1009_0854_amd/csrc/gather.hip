@@ -1,11 +1,13 @@
-// Per-pixel MACT transforms (Sec. 3.2-3.4) for the input shapes the 4-pixel
-// kernels of xform.hip do not take, into packed float32 or float16 HWC or CHW:
-// HWC rows whose width is not a multiple of 4 or whose strides are not whole
-// 4-pixel groups (crops, pitched rows), CHW planes of W H not a multiple of 4,
-// misaligned input pointers.  The catch-all k_generic reads the element type,
-// the transform and the output type at run time and writes each pixel from its
-// lane (a 12-byte stride across the wave for HWC output); here those are
-// template parameters, and HWC output leaves the way the hot kernel's does.
+// Per-pixel MACT transforms (Sec. 3.2-3.4) for the shapes the 4-pixel kernels
+// of xform.hip do not take: inputs of HWC rows whose width is not a multiple
+// of 4 or whose strides are not whole 4-pixel groups (crops, pitched rows), CHW
+// planes of W H not a multiple of 4, misaligned input pointers, into packed
+// float32 or float16 HWC or CHW; and any input into float32 or float16 output
+// views that are not packed (a crop of a larger canvas, padded rows or planes).
+// The catch-all k_generic reads the element type, the transform and the output
+// type at run time and computes every address from the descriptors; here those
+// are template parameters, and packed HWC output leaves the way the hot
+// kernel's does.
 //
 // A wave takes 256 consecutive pixels of the launch (image after image); lane
 // l takes pixels l, l + 64, l + 128 and l + 192, so that the 64 lanes of one
@@ -14,6 +16,9 @@
 // wave's LDS slice and leaves as 16-byte (float16: 8-byte) stores, each
 // instruction 1 KB (512 B) of contiguous output; CHW output goes through the
 // slice as well and leaves as aligned 4-element groups of each plane's run.
+// Output views leave from the lanes: a pixel's three values as one 12-byte
+// store (float16: three 2-byte stores), contiguous across the wave along a
+// row, or one store per plane for CHW.
 // The per-pixel code is pixel.h's, so the results are the other kernels' bits.
 #include <algorithm>
 
@@ -25,6 +30,7 @@ namespace mact {
 
 typedef float g_f4 __attribute__((ext_vector_type(4)));
 typedef float g_f2 __attribute__((ext_vector_type(2)));
+typedef float g_f3 __attribute__((ext_vector_type(3))) __attribute__((aligned(4)));  // 12 bytes, 4-aligned
 
 // Pixel p of `im` as load_px returns it (codes as integer-valued floats, float
 // inputs clamped to [0, 1]), its element type fixed at compile time.
@@ -74,12 +80,41 @@ __device__ __forceinline__ void put(void* out, size_t e, float x) {
   else static_cast<__half*>(out)[e] = f2h_rn(x);
 }
 
-template <int IN, int OUT, int XF, int DEG, bool OCHW>
+// Pixel r of one image of the output view `im`, whose first element is `base`:
+// its three values, non-temporal.  HWC float32 as one 12-byte store.
+template <int OUT>
+__device__ __forceinline__ void put_in_image(const KImage& im, void* base, uint32_t r, const float v[3]) {
+  int64_t o;
+  if (im.packed) {
+    o = im.layout == MACT_HWC ? 3 * (int64_t)r : (int64_t)r;
+  } else {
+    const uint32_t y = im.div_w.div(r), x = r - y * im.W;
+    o = (int64_t)y * im.rs + (im.layout == MACT_HWC ? 3 * (int64_t)x : (int64_t)x);
+  }
+  if (OUT == MACT_F32 && im.layout == MACT_HWC) {
+    __builtin_nontemporal_store(g_f3{v[0], v[1], v[2]}, reinterpret_cast<g_f3*>(static_cast<float*>(base) + o));
+    return;
+  }
+  const int64_t step = im.layout == MACT_HWC ? 1 : im.ps;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (OUT == MACT_F32)
+      __builtin_nontemporal_store(v[c], static_cast<float*>(base) + o + c * step);
+    else
+      __builtin_nontemporal_store(__builtin_bit_cast(uint16_t, f2h_rn(v[c])), static_cast<uint16_t*>(base) + o + c * step);
+  }
+}
+
+// OM: kGatherHWC and kGatherCHW write packed output at `out`; kGatherAny writes
+// the output view `dst` (float32 or float16, any layout and strides).
+template <int IN, int OUT, int XF, int DEG, int OM>
 __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ out, uint32_t n_px, uint32_t hw,
-                                                FastDiv div_hw, KCoef k, int gamma) {
+                                                FastDiv div_hw, KCoef k, int gamma, KImage dst) {
+  constexpr bool OCHW = OM == kGatherCHW;
   __shared__ float gtab[256];
   // per wave: 256 pixels of float32 HWC (3 KB; float16 1.5 KB), or 3 planes of 260 elements (CHW)
-  __shared__ g_f4 s_out[4][OCHW ? 195 : 192];
+  // (output views: the chunk's packed HWC input, up to 1.5 KB)
+  __shared__ g_f4 s_out[4][OM == kGatherCHW ? 195 : OM == kGatherHWC ? 192 : 96];
   if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
     gtab[threadIdx.x] = k_gamma_table[gamma][threadIdx.x];
     __syncthreads();
@@ -91,11 +126,36 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
   if (c < n_chunks) {
     const uint32_t p0 = 256u * c, n0 = div_hw.div(p0);
     const bool one = div_hw.div(p0 + 255u) == n0;  // the chunk inside one image
+    const uint32_t r0 = p0 - n0 * hw;              // its first pixel in that image
     float o[4][3];
-    if (one) {
+    if (OM == kGatherAny && IN != MACT_F32 && src.packed && src.layout == MACT_HWC &&
+        (reinterpret_cast<uintptr_t>(src.ptr) & 3u) == 0) {
+      // packed 8- or 16-bit HWC input: the chunk's 768 or 1536 bytes come in as 12-byte words,
+      // lane-contiguous, through the wave's slice (a lane's own pixel is 3 or 6 bytes, so its
+      // element loads would cover a third or half of each line they touch)
+      constexpr int WPC = IN == MACT_U8 ? 1 : 2;
+      const uint3* w = reinterpret_cast<const uint3*>(src.ptr) + (size_t)c * 64u * WPC;
+      uint3* s3 = reinterpret_cast<uint3*>(s_out[wv]);
+#pragma unroll
+      for (int q = 0; q < WPC; ++q) s3[q * 64 + lane] = w[q * 64 + lane];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the chunk is in LDS
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t e = 3u * (lane + 64u * j);
+        float v[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          if (IN == MACT_U8) v[ch] = (float)reinterpret_cast<const uint8_t*>(s3)[e + ch];
+          else if (IN == MACT_U16) v[ch] = (float)reinterpret_cast<const uint16_t*>(s3)[e + ch];
+          else v[ch] = clamp01(__half2float(reinterpret_cast<const __half*>(s3)[e + ch]));
+        }
+        px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
+      }
+    } else if (one) {
       constexpr int ES = IN == MACT_U8 ? 1 : IN == MACT_F32 ? 4 : 2;
       const void* base = static_cast<const char*>(src.ptr) + (int64_t)n0 * src.bs * ES;
-      const uint32_t r0 = p0 - n0 * hw;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         float v[3];
@@ -110,7 +170,19 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
         px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
       }
     }
-    if (OCHW && one) {
+    if (OM == kGatherAny) {
+      if (one) {
+        constexpr int OES = OUT == MACT_F32 ? 4 : 2;
+        void* ob = static_cast<char*>(dst.ptr) + (int64_t)n0 * dst.bs * OES;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) put_in_image<OUT>(dst, ob, r0 + lane + 64u * j, o[j]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) put<OUT>(dst.ptr, elem_off(dst, p0 + lane + 64u * j, ch), o[j][ch]);
+      }
+    } else if (OCHW && one) {
       // the chunk inside one image: each plane's 256 outputs are one run starting at element e0.
       // In the slice, element e0 + k of plane ch sits at ch 260 + e0 % 4 + k, so that the run's
       // 4-element groups, aligned in the output, are aligned in LDS too.  A run starting at sh =
@@ -216,52 +288,60 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
     float v[3], r[3];
     load_px_t<IN>(src, p, v);
     px1<IN, XF, DEG>(k, gamma, gtab, v, r);
-    const uint32_t n = OCHW ? div_hw.div(p) : 0u;
-    const size_t e = OCHW ? (size_t)3 * n * hw + (p - n * hw) : (size_t)3 * p;
+    if (OM == kGatherAny) {
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) put<OUT>(out, e + (OCHW ? (size_t)ch * hw : (size_t)ch), r[ch]);
+      for (int ch = 0; ch < 3; ++ch) put<OUT>(dst.ptr, elem_off(dst, p, ch), r[ch]);
+    } else {
+      const uint32_t n = OCHW ? div_hw.div(p) : 0u;
+      const size_t e = OCHW ? (size_t)3 * n * hw + (p - n * hw) : (size_t)3 * p;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) put<OUT>(out, e + (OCHW ? (size_t)ch * hw : (size_t)ch), r[ch]);
+    }
   }
 }
 
-template <int IN, int OUT, int DEG, bool OCHW>
-static void launch_gather_xf(int xform, const KImage& src, void* out, uint32_t n_px, uint32_t hw, const KCoef& k,
-                             int gamma, hipStream_t st) {
+template <int IN, int OUT, int DEG, int OM>
+static void launch_gather_xf(int xform, const KImage& src, const KImage& dst, void* out, uint32_t n_px, uint32_t hw,
+                             const KCoef& k, int gamma, hipStream_t st) {
   const uint32_t blocks = std::max<uint32_t>(1, ((n_px >> 8) + 3) / 4);
   const FastDiv d = make_fastdiv(hw);
-  if (xform == MACT_LAB) hipLaunchKernelGGL((k_gather<IN, OUT, MACT_LAB, DEG, OCHW>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma);
-  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_gather<IN, OUT, MACT_HSI, DEG, OCHW>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma);
-  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_gather<IN, OUT, MACT_LUV, DEG, OCHW>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma);
-  else hipLaunchKernelGGL((k_gather<IN, OUT, MACT_SCT, DEG, OCHW>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma);
+  if (xform == MACT_LAB) hipLaunchKernelGGL((k_gather<IN, OUT, MACT_LAB, DEG, OM>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma, dst);
+  else if (xform == MACT_HSI) hipLaunchKernelGGL((k_gather<IN, OUT, MACT_HSI, DEG, OM>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma, dst);
+  else if (xform == MACT_LUV) hipLaunchKernelGGL((k_gather<IN, OUT, MACT_LUV, DEG, OM>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma, dst);
+  else hipLaunchKernelGGL((k_gather<IN, OUT, MACT_SCT, DEG, OM>), dim3(blocks), dim3(256), 0, st, src, out, n_px, hw, d, k, gamma, dst);
 }
 
 // The polynomials at their own degree (up to 4, 5, or up to 7), as the 4-pixel
 // kernels evaluate them: a zero leading coefficient leaves Horner's sums unchanged.
-template <int IN, int OUT, bool OCHW>
-static void launch_gather_deg(int xform, int deg, const KImage& src, void* out, uint32_t n_px, uint32_t hw,
-                              const KCoef& k, int gamma, hipStream_t st) {
-  if (deg <= 4) launch_gather_xf<IN, OUT, 4, OCHW>(xform, src, out, n_px, hw, k, gamma, st);
-  else if (deg == 5) launch_gather_xf<IN, OUT, 5, OCHW>(xform, src, out, n_px, hw, k, gamma, st);
-  else launch_gather_xf<IN, OUT, 7, OCHW>(xform, src, out, n_px, hw, k, gamma, st);
+template <int IN, int OUT, int OM>
+static void launch_gather_deg(int xform, int deg, const KImage& src, const KImage& dst, void* out, uint32_t n_px,
+                              uint32_t hw, const KCoef& k, int gamma, hipStream_t st) {
+  if (deg <= 4) launch_gather_xf<IN, OUT, 4, OM>(xform, src, dst, out, n_px, hw, k, gamma, st);
+  else if (deg == 5) launch_gather_xf<IN, OUT, 5, OM>(xform, src, dst, out, n_px, hw, k, gamma, st);
+  else launch_gather_xf<IN, OUT, 7, OM>(xform, src, dst, out, n_px, hw, k, gamma, st);
+}
+
+template <int IN, int OUT>
+static void launch_gather_om(int xform, int out_mode, int deg, const KImage& src, const KImage& dst, void* out,
+                             uint32_t n_px, uint32_t hw, const KCoef& k, int gamma, hipStream_t st) {
+  if (out_mode == kGatherHWC) launch_gather_deg<IN, OUT, kGatherHWC>(xform, deg, src, dst, out, n_px, hw, k, gamma, st);
+  else if (out_mode == kGatherCHW) launch_gather_deg<IN, OUT, kGatherCHW>(xform, deg, src, dst, out, n_px, hw, k, gamma, st);
+  else launch_gather_deg<IN, OUT, kGatherAny>(xform, deg, src, dst, out, n_px, hw, k, gamma, st);
 }
 
 template <int IN>
-static void launch_gather_in(int xform, int out_dtype, bool ochw, int deg, const KImage& src, void* out, uint32_t n_px,
-                             uint32_t hw, const KCoef& k, int gamma, hipStream_t st) {
-  if (out_dtype == MACT_F32) {
-    if (ochw) launch_gather_deg<IN, MACT_F32, true>(xform, deg, src, out, n_px, hw, k, gamma, st);
-    else launch_gather_deg<IN, MACT_F32, false>(xform, deg, src, out, n_px, hw, k, gamma, st);
-  } else {
-    if (ochw) launch_gather_deg<IN, MACT_F16, true>(xform, deg, src, out, n_px, hw, k, gamma, st);
-    else launch_gather_deg<IN, MACT_F16, false>(xform, deg, src, out, n_px, hw, k, gamma, st);
-  }
+static void launch_gather_in(int xform, int out_dtype, int out_mode, int deg, const KImage& src, const KImage& dst,
+                             void* out, uint32_t n_px, uint32_t hw, const KCoef& k, int gamma, hipStream_t st) {
+  if (out_dtype == MACT_F32) launch_gather_om<IN, MACT_F32>(xform, out_mode, deg, src, dst, out, n_px, hw, k, gamma, st);
+  else launch_gather_om<IN, MACT_F16>(xform, out_mode, deg, src, dst, out, n_px, hw, k, gamma, st);
 }
 
-void launch_gather(int in_dtype, int xform, int out_dtype, bool out_chw, int deg, const KImage& src, void* out,
-                   uint32_t n_px, uint32_t hw, const KCoef& k, int gamma, hipStream_t st) {
-  if (in_dtype == MACT_U8) launch_gather_in<MACT_U8>(xform, out_dtype, out_chw, deg, src, out, n_px, hw, k, gamma, st);
-  else if (in_dtype == MACT_U16) launch_gather_in<MACT_U16>(xform, out_dtype, out_chw, deg, src, out, n_px, hw, k, gamma, st);
-  else if (in_dtype == MACT_F16) launch_gather_in<MACT_F16>(xform, out_dtype, out_chw, deg, src, out, n_px, hw, k, gamma, st);
-  else launch_gather_in<MACT_F32>(xform, out_dtype, out_chw, deg, src, out, n_px, hw, k, gamma, st);
+void launch_gather(int in_dtype, int xform, int out_dtype, int out_mode, int deg, const KImage& src, const KImage& dst,
+                   void* out, uint32_t n_px, uint32_t hw, const KCoef& k, int gamma, hipStream_t st) {
+  if (in_dtype == MACT_U8) launch_gather_in<MACT_U8>(xform, out_dtype, out_mode, deg, src, dst, out, n_px, hw, k, gamma, st);
+  else if (in_dtype == MACT_U16) launch_gather_in<MACT_U16>(xform, out_dtype, out_mode, deg, src, dst, out, n_px, hw, k, gamma, st);
+  else if (in_dtype == MACT_F16) launch_gather_in<MACT_F16>(xform, out_dtype, out_mode, deg, src, dst, out, n_px, hw, k, gamma, st);
+  else launch_gather_in<MACT_F32>(xform, out_dtype, out_mode, deg, src, dst, out, n_px, hw, k, gamma, st);
 }
 
 }  // namespace mact

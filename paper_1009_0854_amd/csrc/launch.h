@@ -75,12 +75,15 @@ unsigned batch_grid(const mact_tune& tune, uint32_t total_tiles);
 // Tile list: tile_start[i] = first tile of descriptor i; returns the total.
 uint32_t build_tiles(const std::vector<BDesc>& descs, uint32_t tile, std::vector<uint32_t>* tile_start);
 
-// Any input image (element type in_dtype; layout and strides in `src`) -> packed
-// float32 or float16 (out_dtype) HWC or, with out_chw, CHW of n_px pixels of hw
-// per image, `out` 16-byte aligned: the shapes the 4-pixel kernels do not take.
+// Any input image (element type in_dtype; layout and strides in `src`) -> float32
+// or float16 (out_dtype) output of n_px pixels of hw per image: packed HWC
+// (kGatherHWC) or CHW (kGatherCHW) at `out`, 16-byte aligned: the shapes the
+// 4-pixel kernels do not take; or (kGatherAny) the output view `dst`, any
+// layout and strides, its elements naturally aligned (`out` unused).
 // deg: the highest degree among the approximations (evaluated at 4, 5 or 7).
-void launch_gather(int in_dtype, int xform, int out_dtype, bool out_chw, int deg, const KImage& src, void* out,
-                   uint32_t n_px, uint32_t hw, const KCoef& k, int gamma, hipStream_t st);
+enum { kGatherHWC = 0, kGatherCHW = 1, kGatherAny = 2 };
+void launch_gather(int in_dtype, int xform, int out_dtype, int out_mode, int deg, const KImage& src, const KImage& dst,
+                   void* out, uint32_t n_px, uint32_t hw, const KCoef& k, int gamma, hipStream_t st);
 
 // Compute units of the current device (cached per device).
 int device_cus();

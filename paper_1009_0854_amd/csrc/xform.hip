@@ -1076,8 +1076,8 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
   // fast shapes, each to float32 or float16: packed HWC of any input type -> packed HWC or (W H a
   // multiple of 4) packed CHW, row-strided HWC -> packed HWC and row-strided CHW -> packed HWC or
   // CHW (rows of a multiple of 4 pixels), packed CHW of any input type -> packed CHW or HWC (W H a
-  // multiple of 4); any other input into packed output takes k_gather (gather.hip), and strided
-  // or misaligned outputs k_generic
+  // multiple of 4); any other input into packed output, and any input into an output view that
+  // is not packed, takes k_gather (gather.hip); outputs not aligned to their element take k_generic
   const bool f_out = ho.dtype == MACT_F32 || ho.dtype == MACT_F16;
   const bool hwc4 = (hi.dtype == MACT_U8 || hi.dtype == MACT_F16 || hi.dtype == MACT_U16) && hi.layout == MACT_HWC &&
                     hi.packed && f_out && ho.layout == MACT_HWC && ho.packed;
@@ -1145,8 +1145,11 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
       else
         launch_chw_rows4_any<false>(hi.dtype, params->xform, ho.dtype, exact_deg, ip, op, n_chunks, g, k, gamma, st);
     } else if (ho.packed && f_out && aligned(op, 16)) {
-      launch_gather(hi.dtype, params->xform, ho.dtype, ho.layout == MACT_CHW, exact_deg, kimage(hi, n0, cnt), op, n_px,
-                    (uint32_t)(hi.W * hi.H), k, gamma, st);
+      launch_gather(hi.dtype, params->xform, ho.dtype, ho.layout == MACT_CHW ? kGatherCHW : kGatherHWC, exact_deg,
+                    kimage(hi, n0, cnt), KImage{}, op, n_px, (uint32_t)(hi.W * hi.H), k, gamma, st);
+    } else if (f_out && aligned(op, (size_t)ho.esize)) {
+      launch_gather(hi.dtype, params->xform, ho.dtype, kGatherAny, exact_deg, kimage(hi, n0, cnt), kimage(ho, n0, cnt),
+                    op, n_px, (uint32_t)(hi.W * hi.H), k, gamma, st);
     } else {
       const KImage ks = kimage(hi, n0, cnt), kd = kimage(ho, n0, cnt);
       const unsigned grid = full_grid(n_px, 256);

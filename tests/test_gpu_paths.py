@@ -1,6 +1,7 @@
-"""Every specialised kernel gives the same bits as the general one-pixel-per-
-lane kernel on the same data (the general kernel is forced with a padded-
-stride view), for every transform, input type and transfer function."""
+"""Every specialised kernel gives the same bits as the general kernels on the
+same data (forced with padded-stride views: k_gather for inputs and output
+views, k_generic for outputs not aligned to their element), for every
+transform, input type and transfer function."""
 import numpy as np
 import pytest
 
@@ -203,3 +204,37 @@ def test_gather_equals_general(M, xform, dtype, src_kind, out_kind):
             xs = np.clip(x.astype(np.float64), 0, 1).reshape(-1, 3)
             got = packed if layout_out == "hwc" else packed.permute(0, 2, 3, 1)
             P.assert_parity_ties(xform, got.reshape(-1, 3).cpu().numpy(), xs, P.coeffs(p), gamma="none")
+
+
+OUT_VIEW_SHAPES = [(64, 96), (33, 32), (16, 36)]
+
+
+@pytest.mark.parametrize("out_dt", [torch.float32, torch.float16])
+@pytest.mark.parametrize("kind", ["hwc_u8", "hwc_u16", "hwc_f16", "hwc_f32", "chw_u8", "chw_f32"])
+@pytest.mark.parametrize("xform", [0, 1, 2, 3])
+def test_output_views_equal_packed(M, xform, kind, out_dt):
+    # inputs a 4-pixel kernel takes, into packed output; the same into output views that are not
+    # packed (HWC rows 3 pixels wider, CHW rows 2 wider): k_gather writes those from its lanes,
+    # same bits, and nothing outside the view.  2 images of 33 x 32: chunks that straddle them
+    layout, dt = kind.split("_")
+    p = M.default_params(xform)
+    gm = "bt709" if dt in ("u8", "u16") else "none"
+    odt = np.float32 if out_dt == torch.float32 else np.float16
+    for si, shape in enumerate(OUT_VIEW_SHAPES):
+        x = _src(dt, shape, 31 * xform + 7 * si + len(kind))
+        src = torch.from_numpy(np.ascontiguousarray(x.transpose(0, 3, 1, 2)) if layout == "chw" else x).cuda()
+        for out_layout in ("hwc", "chw"):
+            oshape = (2,) + shape + (3,) if out_layout == "hwc" else (2, 3) + shape
+            packed = torch.empty(oshape, dtype=out_dt, device="cuda")
+            if out_layout == "hwc":
+                big = torch.from_numpy(np.zeros((2,) + (shape[0], shape[1] + 3, 3), dtype=odt)).cuda()
+                view = big[:, :, :shape[1]]
+            else:
+                big = torch.from_numpy(np.zeros((2, 3) + (shape[0], shape[1] + 2), dtype=odt)).cuda()
+                view = big[..., :shape[1]]
+            M.transform(src, params=p, layout=layout, gamma=gm, out=packed, out_layout=out_layout)
+            M.transform(src, params=p, layout=layout, gamma=gm, out=view, out_layout=out_layout)
+            torch.cuda.synchronize()
+            assert torch.equal(packed, view), (shape, out_layout)
+            pad = big[:, :, shape[1]:] if out_layout == "hwc" else big[..., shape[1]:]
+            assert not pad.any(), (shape, out_layout)
