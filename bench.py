@@ -186,7 +186,10 @@ def bench_general(M, x, y, p, n_px, steps):
     pixels apart beyond their width; the row-strided kernel) into packed HWC,
     as CHW planes into HWC and into CHW, and packed HWC into CHW (the plane
     kernels); row-strided CHW planes into HWC and a row-padded float32 view
-    into HWC, float32 out."""
+    into HWC, float32 out; the packed batch into output views whose rows are
+    8 pixels wider (HWC float32 and float16, CHW float32); and shapes no
+    4-pixel kernel takes, 32 x 1081 x 1921: odd CHW planes into CHW and HWC,
+    and HWC rows of that odd width (a row-padded view) into HWC."""
     import torch
     out = {}
     n, h, w, _ = x.shape
@@ -225,6 +228,35 @@ def bench_general(M, x, y, p, n_px, steps):
     ms, _ = time_kernel(lambda: M.transform(fview, params=p, out=y), steps)
     rec("f32_row_padded_view", ms, 24.0)
     del fpad, fview
+    # output views: rows 8 pixels wider than the image
+    big = torch.empty((n, h, w + 8, 3), dtype=torch.float32, device="cuda")
+    ms, _ = time_kernel(lambda: M.transform(x, params=p, out=big[:, :, :w]), steps)
+    rec("u8_to_hwc_out_view", ms, 15.0)
+    big16 = big.view(-1).view(torch.float16)[: n * h * (w + 8) * 3].view(n, h, w + 8, 3)
+    ms, _ = time_kernel(lambda: M.transform(x, params=p, out=big16[:, :, :w]), steps)
+    rec("u8_to_hwc_out_view_f16", ms, 9.0)
+    del big16
+    bigc = big.view(-1)[: n * 3 * h * (w + 8)].view(n, 3, h, w + 8)
+    ms, _ = time_kernel(lambda: M.transform(x, params=p, out=bigc[..., :w], out_layout="chw"), steps)
+    rec("u8_to_chw_out_view", ms, 15.0)
+    del bigc, big
+    # odd shapes, 32 x 1081 x 1921 uniform bytes (their own pixel count)
+    on, oh, ow = 32, 1081, 1921
+    o_px = on * oh * ow
+    g = torch.Generator(device="cuda").manual_seed(11)
+    ochw = torch.randint(0, 256, (on, 3, oh, ow), dtype=torch.uint8, device="cuda", generator=g)
+    oy = y.view(-1)[: o_px * 3]
+    for name, fn in (("odd_chw_to_chw", lambda: M.transform(ochw, params=p, layout="chw", out=oy.view(on, 3, oh, ow),
+                                                           out_layout="chw")),
+                     ("odd_chw_to_hwc", lambda: M.transform(ochw, params=p, layout="chw", out=oy.view(on, oh, ow, 3),
+                                                           out_layout="hwc"))):
+        ms, _ = time_kernel(fn, steps)
+        out[name] = {"Mpx_s": o_px / ms / 1e3, "GBs": 15.0 * o_px / ms / 1e6, "ms": ms, "shape": [on, oh, ow]}
+    del ochw
+    opad = torch.randint(0, 256, (on, oh, ow + 7, 3), dtype=torch.uint8, device="cuda", generator=g)
+    ms, _ = time_kernel(lambda: M.transform(opad[:, :, :ow], params=p, out=oy.view(on, oh, ow, 3)), steps)
+    out["odd_hwc_rows_view"] = {"Mpx_s": o_px / ms / 1e3, "GBs": 15.0 * o_px / ms / 1e6, "ms": ms, "shape": [on, oh, ow]}
+    del opad
     return out
 
 
