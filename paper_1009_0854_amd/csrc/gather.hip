@@ -113,8 +113,8 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
   constexpr bool OCHW = OM == kGatherCHW;
   __shared__ float gtab[256];
   // per wave: 256 pixels of float32 HWC (3 KB; float16 1.5 KB), or 3 planes of 260 elements (CHW)
-  // (output views: the chunk's packed HWC input, up to 1.5 KB)
-  __shared__ g_f4 s_out[4][OM == kGatherCHW ? 195 : OM == kGatherHWC ? 192 : 96];
+  // (output views: the chunk's packed HWC input, up to 1.5 KB, then its float32 run of one row)
+  __shared__ g_f4 s_out[4][OM == kGatherCHW ? 195 : OM == kGatherHWC ? 192 : 193];
   if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
     gtab[threadIdx.x] = k_gamma_table[gamma][threadIdx.x];
     __syncthreads();
@@ -174,8 +174,44 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
       if (one) {
         constexpr int OES = OUT == MACT_F32 ? 4 : 2;
         void* ob = static_cast<char*>(dst.ptr) + (int64_t)n0 * dst.bs * OES;
+        const uint32_t y0 = dst.packed ? 0u : dst.div_w.div(r0), x0 = r0 - y0 * dst.W;
+        if (OUT == MACT_F32 && dst.layout == MACT_HWC && !dst.packed && x0 + 256u <= dst.W) {
+          // the chunk inside one row of an HWC float32 view: its 768 values are one run starting
+          // sh floats past a 16-byte boundary.  In the slice, value k of the run sits at sh + k,
+          // so that the run's aligned 4-value groups are aligned in LDS too: lanes store groups
+          // 0..191 whole (1..191 when sh != 0) with 16-byte stores, then lane 0 the run's first
+          // 4 - sh and last sh values one by one (the CHW path's scheme).
+          float* run = static_cast<float*>(ob) + (int64_t)y0 * dst.rs + 3 * (int64_t)x0;
+          const uint32_t sh = (uint32_t)((reinterpret_cast<uintptr_t>(run) >> 2) & 3u);
+          float* sf = reinterpret_cast<float*>(s_out[wv]);
+          __builtin_amdgcn_s_waitcnt(0xc07f);  // a staged input chunk has been read out of the slice
+          __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int j = 0; j < 4; ++j) put_in_image<OUT>(dst, ob, r0 + lane + 64u * j, o[j]);
+          for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) sf[sh + 3u * (lane + 64u * j) + ch] = o[j][ch];
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+          __builtin_amdgcn_wave_barrier();
+          float* a0 = run - sh;
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            const uint32_t g = 64u * q + lane;
+            if (g != 0u || sh == 0u)
+              __builtin_nontemporal_store(*reinterpret_cast<const g_f4*>(sf + 4u * g), reinterpret_cast<g_f4*>(a0 + 4u * g));
+          }
+          __builtin_amdgcn_sched_barrier(0);
+          if (lane == 0 && sh != 0) {
+#pragma unroll
+            for (uint32_t t = 0; t < 4u; ++t) {
+              const uint32_t i = t >= sh ? t : 768u + t;
+              __builtin_nontemporal_store(sf[i], a0 + i);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) put_in_image<OUT>(dst, ob, r0 + lane + 64u * j, o[j]);
+        }
       } else {
 #pragma unroll
         for (int j = 0; j < 4; ++j)

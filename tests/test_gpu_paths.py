@@ -206,7 +206,7 @@ def test_gather_equals_general(M, xform, dtype, src_kind, out_kind):
             P.assert_parity_ties(xform, got.reshape(-1, 3).cpu().numpy(), xs, P.coeffs(p), gamma="none")
 
 
-OUT_VIEW_SHAPES = [(64, 96), (33, 32), (16, 36)]
+OUT_VIEW_SHAPES = [(64, 96), (33, 32), (16, 36), (6, 520)]  # 520: chunks inside one row and across two
 
 
 @pytest.mark.parametrize("out_dt", [torch.float32, torch.float16])
@@ -215,7 +215,9 @@ OUT_VIEW_SHAPES = [(64, 96), (33, 32), (16, 36)]
 def test_output_views_equal_packed(M, xform, kind, out_dt):
     # inputs a 4-pixel kernel takes, into packed output; the same into output views that are not
     # packed (HWC rows 3 pixels wider, CHW rows 2 wider): k_gather writes those from its lanes,
-    # same bits, and nothing outside the view.  2 images of 33 x 32: chunks that straddle them
+    # or a chunk inside one HWC row as 16-byte groups, same bits, and nothing outside the view.
+    # 2 images of 33 x 32: chunks that straddle them; rows of 520: chunks inside one row, whose
+    # runs start at every offset from a 16-byte boundary (rows of 523 pixels, 3 floats a pixel)
     layout, dt = kind.split("_")
     p = M.default_params(xform)
     gm = "bt709" if dt in ("u8", "u16") else "none"
