@@ -105,6 +105,69 @@ __device__ __forceinline__ void put_in_image(const KImage& im, void* base, uint3
   }
 }
 
+// A wave's three plane runs of 256 outputs (pixel lane + 64 j of o[j]), run
+// ch starting at run[ch], any element alignment.  In the slice, value k of
+// run ch sits at 260 ch + sh + k (sh: the run's start in elements past a
+// 16-byte, float16 8-byte, boundary), so that the run's 4-element groups,
+// aligned in the output, are aligned in LDS too.  A run covers groups 0..63
+// whole when sh = 0, else groups 1..63 whole and sh elements of a 65th: lane
+// l stores group l with one 16-byte (8-byte) store, except lane 0 when sh !=
+// 0, which then stores the run's first 4 - sh and last sh elements one by
+// one, also non-temporal.  (Those element stores issued first, as plain
+// stores, cost the packed CHW path 25%; the groups taken in a loop of one or
+// two passes, both branches in each, 7%.)
+template <int OUT>
+__device__ __forceinline__ void store_plane_runs(g_f4* slice, uint32_t lane, const float o[4][3], void* const run[3]) {
+  constexpr uintptr_t ES = OUT == MACT_F32 ? 4 : 2;
+  uint32_t sh[3];
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) sh[ch] = (uint32_t)((reinterpret_cast<uintptr_t>(run[ch]) / ES) & 3u);
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // whatever the slice held before has been read
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const uint32_t i = 260u * ch + sh[ch] + lane + 64u * j;
+      if (OUT == MACT_F32) reinterpret_cast<float*>(slice)[i] = o[j][ch];
+      else reinterpret_cast<__half*>(slice)[i] = f2h_rn(o[j][ch]);
+    }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    const uint32_t lo = 260u * ch;  // group 0 in the slice
+    if (OUT == MACT_F32) {
+      float* a0 = static_cast<float*>(run[ch]) - sh[ch];  // group 0 in the output
+      const float* sl = reinterpret_cast<const float*>(slice) + lo;
+      if (lane != 0 || sh[ch] == 0)
+        __builtin_nontemporal_store(*reinterpret_cast<const g_f4*>(sl + 4 * lane), reinterpret_cast<g_f4*>(a0 + 4 * lane));
+      __builtin_amdgcn_sched_barrier(0);
+      if (lane == 0 && sh[ch] != 0) {
+#pragma unroll
+        for (uint32_t t = 0; t < 4u; ++t) {
+          const uint32_t i = t >= sh[ch] ? t : 256u + t;  // the head's elements of group 0, the tail's of group 64
+          __builtin_nontemporal_store(sl[i], a0 + i);
+        }
+      }
+    } else {
+      __half* a0 = static_cast<__half*>(run[ch]) - sh[ch];
+      const __half* sl = reinterpret_cast<const __half*>(slice) + lo;
+      if (lane != 0 || sh[ch] == 0)
+        __builtin_nontemporal_store(*reinterpret_cast<const g_f2*>(sl + 4 * lane), reinterpret_cast<g_f2*>(a0 + 4 * lane));
+      __builtin_amdgcn_sched_barrier(0);
+      if (lane == 0 && sh[ch] != 0) {
+#pragma unroll
+        for (uint32_t t = 0; t < 4u; ++t) {
+          const uint32_t i = t >= sh[ch] ? t : 256u + t;
+          __builtin_nontemporal_store(reinterpret_cast<const uint16_t*>(sl)[i], reinterpret_cast<uint16_t*>(a0) + i);
+        }
+      }
+    }
+  }
+}
+
 // OM: kGatherHWC and kGatherCHW write packed output at `out`; kGatherAny writes
 // the output view `dst` (float32 or float16, any layout and strides).
 template <int IN, int OUT, int XF, int DEG, int OM>
@@ -113,8 +176,9 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
   constexpr bool OCHW = OM == kGatherCHW;
   __shared__ float gtab[256];
   // per wave: 256 pixels of float32 HWC (3 KB; float16 1.5 KB), or 3 planes of 260 elements (CHW)
-  // (output views: the chunk's packed HWC input, up to 1.5 KB, then its float32 run of one row)
-  __shared__ g_f4 s_out[4][OM == kGatherCHW ? 195 : OM == kGatherHWC ? 192 : 193];
+  // (output views: the chunk's packed HWC input, up to 1.5 KB, then its run of one HWC row, 3 KB,
+  // or its three plane runs)
+  __shared__ g_f4 s_out[4][OM == kGatherHWC ? 192 : 195];
   if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
     gtab[threadIdx.x] = k_gamma_table[gamma][threadIdx.x];
     __syncthreads();
@@ -208,6 +272,15 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
               __builtin_nontemporal_store(sf[i], a0 + i);
             }
           }
+        } else if (dst.layout == MACT_CHW && (dst.packed || x0 + 256u <= dst.W)) {
+          // the chunk inside one row of a CHW view (or a packed one): each plane's 256 outputs
+          // are one run, stored as the packed CHW path stores them
+          const int64_t off = dst.packed ? (int64_t)r0 : (int64_t)y0 * dst.rs + x0;
+          void* run[3];
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch)
+            run[ch] = static_cast<char*>(ob) + (off + ch * dst.ps) * OES;
+          store_plane_runs<OUT>(s_out[wv], lane, o, run);
         } else {
 #pragma unroll
           for (int j = 0; j < 4; ++j) put_in_image<OUT>(dst, ob, r0 + lane + 64u * j, o[j]);
@@ -219,65 +292,15 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
           for (int ch = 0; ch < 3; ++ch) put<OUT>(dst.ptr, elem_off(dst, p0 + lane + 64u * j, ch), o[j][ch]);
       }
     } else if (OCHW && one) {
-      // the chunk inside one image: each plane's 256 outputs are one run starting at element e0.
-      // In the slice, element e0 + k of plane ch sits at ch 260 + e0 % 4 + k, so that the run's
-      // 4-element groups, aligned in the output, are aligned in LDS too.  A run starting at sh =
-      // e % 4 covers groups 0..63 whole when sh = 0, else groups 1..63 whole and sh elements of a
-      // 65th: lane l stores group l with one 16-byte (float16: 8-byte) store, except lane 0 when
-      // sh != 0, which then stores the run's first 4 - sh and last sh elements one by one, also
-      // non-temporal.  (Those element stores issued first, as plain stores, cost this path 25%;
-      // the groups taken in a loop of one or two passes, both branches in each, 7%.)
-      const size_t e0 = (size_t)3 * n0 * hw + (p0 - n0 * hw);
-      const uint32_t sh0 = (uint32_t)(e0 & 3u);
-      if (OUT == MACT_F32) {
-        float* sf = reinterpret_cast<float*>(s_out[wv]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int ch = 0; ch < 3; ++ch) sf[260 * ch + ((sh0 + (uint32_t)(hw & 3u) * ch) & 3u) + lane + 64 * j] = o[j][ch];
-      } else {
-        __half* sh = reinterpret_cast<__half*>(s_out[wv]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int ch = 0; ch < 3; ++ch) sh[260 * ch + ((sh0 + (uint32_t)(hw & 3u) * ch) & 3u) + lane + 64 * j] = f2h_rn(o[j][ch]);
-      }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-      __builtin_amdgcn_wave_barrier();
+      // the chunk inside one image: each plane's 256 outputs are one run
+      const size_t e0 = (size_t)3 * n0 * hw + r0;
+      void* run[3];
 #pragma unroll
       for (int ch = 0; ch < 3; ++ch) {
-        const size_t e = e0 + (size_t)ch * hw;  // the plane's run: elements [e, e + 256)
-        const uint32_t sh = (uint32_t)(e & 3u);
-        const uint32_t lo = 260u * ch;           // group 0 in the slice
-        if (OUT == MACT_F32) {
-          float* a0 = static_cast<float*>(out) + (e - sh);  // group 0 in the output
-          const float* sl = reinterpret_cast<const float*>(s_out[wv]) + lo;
-          if (lane != 0 || sh == 0)
-            __builtin_nontemporal_store(*reinterpret_cast<const g_f4*>(sl + 4 * lane), reinterpret_cast<g_f4*>(a0 + 4 * lane));
-          __builtin_amdgcn_sched_barrier(0);
-          if (lane == 0 && sh != 0) {
-#pragma unroll
-            for (uint32_t t = 0; t < 4u; ++t) {
-              const uint32_t i = t >= sh ? t : 256u + t;  // the head's elements of group 0, the tail's of group 64
-              __builtin_nontemporal_store(sl[i], a0 + i);
-            }
-          }
-        } else {
-          __half* a0 = static_cast<__half*>(out) + (e - sh);
-          const __half* sl = reinterpret_cast<const __half*>(s_out[wv]) + lo;
-          if (lane != 0 || sh == 0)
-            __builtin_nontemporal_store(*reinterpret_cast<const g_f2*>(sl + 4 * lane), reinterpret_cast<g_f2*>(a0 + 4 * lane));
-          __builtin_amdgcn_sched_barrier(0);
-          if (lane == 0 && sh != 0) {
-#pragma unroll
-            for (uint32_t t = 0; t < 4u; ++t) {
-              const uint32_t i = t >= sh ? t : 256u + t;
-              __builtin_nontemporal_store(reinterpret_cast<const uint16_t*>(sl)[i], reinterpret_cast<uint16_t*>(a0) + i);
-            }
-          }
-        }
+        const size_t e = e0 + (size_t)ch * hw;
+        run[ch] = OUT == MACT_F32 ? (void*)(static_cast<float*>(out) + e) : (void*)(static_cast<__half*>(out) + e);
       }
+      store_plane_runs<OUT>(s_out[wv], lane, o, run);
     } else if (OCHW) {
       // the chunk spans two images or more: element by element
 #pragma unroll
