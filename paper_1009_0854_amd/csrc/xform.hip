@@ -445,7 +445,7 @@ __device__ __forceinline__ void stage4(f4* slice, uint32_t lane, const float o[1
 // leaves as 16-byte stores (each instruction 1 KB of contiguous output, dst
 // 16-byte aligned), float16 as 8-byte stores (512 B per instruction; dst need
 // only be 8-byte aligned, which any run of a multiple of 4 pixels keeps).
-template <int OUT>
+template <int OUT, int HALVES = 1>
 __device__ __forceinline__ void store_staged(const f4* slice, void* dst, uint32_t cnt, uint32_t lane) {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): every lane's LDS writes have landed
@@ -454,7 +454,7 @@ __device__ __forceinline__ void store_staged(const f4* slice, void* dst, uint32_
   constexpr uint32_t WB = OUT == MACT_F32 ? 16 : 8;
   const StreamBuf b = wave_stream_buf(dst, n_valid * WB);
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < 3 * HALVES; ++q) {
     const uint32_t e = q * 64 + lane;
     if (e < n_valid) {
       if (OUT == MACT_F32) stream_store(b, e * WB, slice[e]);
@@ -477,11 +477,13 @@ __device__ __forceinline__ void store_plane4(void* out, size_t e, float a, float
 
 // Row-strided HWC (a view whose rows or images are not adjacent: a crop, a
 // pitched allocation) -> packed float32 or float16 HWC, W a multiple of 4.
-// Every row is cut into 256-pixel chunks, the last one partial, one chunk per
-// wave; each chunk takes k_hwc4's 12-byte loads (lanes past the row's end
-// idle; float32 pixels: three 16-byte loads per lane), its per-pixel code and
-// its LDS-transposed stores.  Requires the input pointer and both strides (in
+// Every row is cut into segments of kRowHalves 256-pixel chunks, the last one
+// partial, one segment per wave; each chunk takes k_hwc4's 12-byte loads
+// (lanes past the row's end idle; float32 pixels: three 16-byte loads per
+// lane), both chunks' loads issued first, then its per-pixel code and its
+// LDS-transposed stores.  Requires the input pointer and both strides (in
 // bytes) to be multiples of 4 (16 for float32) and `out` 16-byte aligned.
+constexpr int kRowHalves = 2;
 struct RowGeom {
   uint32_t W, cpr, H;      // pixels per row, chunks per row, rows per image
   FastDiv div_cpr, div_h;  // chunk -> row, row -> image
@@ -493,7 +495,8 @@ __global__ __launch_bounds__(kHotBlock) void k_rows4(const uint8_t* __restrict__
                                                      uint32_t n_chunks, RowGeom g, KCoef k, int gamma) {
   constexpr int WPC = IN == MACT_U8 ? 1 : IN == MACT_F32 ? 4 : 2;  // 12-byte words per lane
   constexpr uint32_t OSZ = OUT == MACT_F32 ? 4 : 2;
-  __shared__ f4 s_out[kHotWaves][3 * OSZ * 16];
+  constexpr uint32_t SLICE = 3 * OSZ * 16;                         // one half's output in 16-byte words
+  __shared__ f4 s_out[kHotWaves][kRowHalves * SLICE];
   __shared__ float gtab[256];
   if (IN == MACT_U8 && (XF == MACT_LAB || XF == MACT_LUV)) {
     for (uint32_t i = threadIdx.x; i < 256u; i += kHotBlock) gtab[i] = k_gamma_table[gamma][i];
@@ -505,32 +508,52 @@ __global__ __launch_bounds__(kHotBlock) void k_rows4(const uint8_t* __restrict__
   if (c >= n_chunks) return;  // no block-wide barrier follows
   const uint32_t r = g.div_cpr.div(c), j = c - r * g.cpr;
   const uint32_t n = g.div_h.div(r), y = r - n * g.H;
-  const uint32_t px0 = j * 256u, cnt = min(256u, g.W - px0);  // cnt: a multiple of 4
-  const uint3* row = reinterpret_cast<const uint3*>(in + n * g.bs_b + y * g.rs_b + (uint64_t)px0 * 3u * WPC);
-  float o[12];
-  if (4u * lane < cnt && IN == MACT_F32) {
-    const f4* rf = reinterpret_cast<const f4*>(row) + 3u * lane;  // 48 bytes per lane, 16-byte aligned
-    float v[12];
+  const uint32_t px0 = j * (256u * kRowHalves), cnt = min(256u * kRowHalves, g.W - px0);  // cnt: a multiple of 4
+  const uint8_t* row = in + n * g.bs_b + y * g.rs_b + (uint64_t)px0 * 3u * (IN == MACT_U8 ? 1u : IN == MACT_F32 ? 4u : 2u);
+  // both halves' loads first, then each half's pixels
+  uint3 w[kRowHalves][WPC];
+  f4 wf[kRowHalves][3];
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const f4 b = rf[t];
-      v[4 * t] = clamp01(b.x); v[4 * t + 1] = clamp01(b.y); v[4 * t + 2] = clamp01(b.z); v[4 * t + 3] = clamp01(b.w);
+  for (int h = 0; h < kRowHalves; ++h) {
+    if (256u * h + 4u * lane < cnt) {
+      if (IN == MACT_F32) {
+        const f4* rf = reinterpret_cast<const f4*>(row) + 192u * h + 3u * lane;  // 48 bytes per lane, 16-byte aligned
+#pragma unroll
+        for (int t = 0; t < 3; ++t) wf[h][t] = rf[t];
+      } else {
+        const uint3* rw = reinterpret_cast<const uint3*>(row) + (64u * h + lane) * WPC;
+#pragma unroll
+        for (int q = 0; q < WPC; ++q) w[h][q] = rw[q];
+      }
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) px1<MACT_F32, XF, DEG>(k, gamma, gtab, v + 3 * q, o + 3 * q);
-  } else if (4u * lane < cnt) {
-    uint3 w[WPC];
-#pragma unroll
-    for (int q = 0; q < WPC; ++q) w[q] = row[lane * WPC + q];
-    if (IN == MACT_U8) px4_u8<XF, DEG>(k, gtab, w[0], o);
-    else if (IN == MACT_U16) px4_u16<XF, DEG>(k, gamma, w[0], w[WPC - 1], o);
-    else px4_f16<XF, DEG>(k, gamma, w[0], w[WPC - 1], o);
-  } else {
-#pragma unroll
-    for (int q = 0; q < 12; ++q) o[q] = 0.0f;
   }
-  stage4<OUT>(s_out[wv], lane, o);
-  store_staged<OUT>(s_out[wv], static_cast<char*>(out) + ((uint64_t)r * g.W + px0) * 3u * OSZ, cnt, lane);
+#pragma unroll
+  for (int h = 0; h < kRowHalves; ++h) {
+    float o[12];
+    if (256u * h + 4u * lane < cnt) {
+      if (IN == MACT_F32) {
+        float v[12];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          v[4 * t] = clamp01(wf[h][t].x); v[4 * t + 1] = clamp01(wf[h][t].y);
+          v[4 * t + 2] = clamp01(wf[h][t].z); v[4 * t + 3] = clamp01(wf[h][t].w);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) px1<MACT_F32, XF, DEG>(k, gamma, gtab, v + 3 * q, o + 3 * q);
+      } else if (IN == MACT_U8) {
+        px4_u8<XF, DEG>(k, gtab, w[h][0], o);
+      } else if (IN == MACT_U16) {
+        px4_u16<XF, DEG>(k, gamma, w[h][0], w[h][WPC - 1], o);
+      } else {
+        px4_f16<XF, DEG>(k, gamma, w[h][0], w[h][WPC - 1], o);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 12; ++q) o[q] = 0.0f;
+    }
+    stage4<OUT>(s_out[wv] + SLICE * h, lane, o);
+  }
+  store_staged<OUT, kRowHalves>(s_out[wv], static_cast<char*>(out) + ((uint64_t)r * g.W + px0) * 3u * OSZ, cnt, lane);
 }
 
 // Blocks of k_hwc4 for n_px pixels: every full chunk covered once, and at
@@ -1119,7 +1142,7 @@ extern "C" mact_status mact_transform(const mact_params* params, const mact_imag
       RowGeom g;
       g.W = (uint32_t)hi.W;
       g.H = (uint32_t)hi.H;
-      g.cpr = (g.W + 255u) / 256u;
+      g.cpr = (g.W + 256u * kRowHalves - 1u) / (256u * kRowHalves);
       g.div_cpr = make_fastdiv(g.cpr);
       g.div_h = make_fastdiv(g.H);
       g.rs_b = (uint64_t)hi.rs * hi.esize;
