@@ -26,7 +26,9 @@ literature.  Readings used here:
                    + (c001 - c000) f_B + (c011 - c001 - c010 + c000) f_G f_B
                    for f_R smallest, and the same under axis permutation.
                    PARITY UNPINNED: no variant reproduces the paper's Table 12
-                   pyramidal row; held to invariants only.
+                   pyramidal row; held to invariants and to this reading's
+                   special cases (bilinear on the base face, linear on the
+                   edge from the base's far corner to the apex).
   * angular channels (H of HSI; angles A and B of SCT) are interpolated as
     circular data (Sec. 3.5.3): the weighted sum of unit vectors
     (cos theta_k, sin theta_k) with the method's own weights, then the angle

@@ -115,6 +115,50 @@ def test_prism_is_triangle_barycentric_times_lerp_along_r():
         np.testing.assert_allclose(out[0], want, atol=1e-11)
 
 
+def test_pyramidal_base_face_is_bilinear_and_apex_edge_is_linear():
+    # the reading of the pyramidal method: apex at corner 111, base the cell face through 000
+    # normal to the axis s of the smallest fraction.  On that face (f_s = 0) the value is the
+    # bilinear interpolation of the face's four corners (the library's 2-D grid interpolator);
+    # on the edge from the base's far corner (f_u = f_v = 1) to the apex it is the linear
+    # interpolation of the edge's two nodes (np.interp).  CIELAB nodes, which are not affine
+    N = 5
+    L = lut.build("lab", N)
+    g = synth.rng(8)
+    for s in range(3):
+        u, v = [j for j in range(3) if j != s]
+        for _ in range(100):
+            # base face: f_s = 0 in a random cell, the other two fractions in (0, 1)
+            i = g.integers(0, N - 1, 3)
+            f = np.zeros(3)
+            f[u], f[v] = g.uniform(0.01, 0.99, 2)
+            x = (i + f) / (N - 1)
+            face = np.empty((2, 2, 3))
+            for du in (0, 1):
+                for dv in (0, 1):
+                    c = i.copy()
+                    c[u] += du
+                    c[v] += dv
+                    face[du, dv] = L[tuple(c)]
+            want = scipy.interpolate.RegularGridInterpolator(([0.0, 1.0], [0.0, 1.0]), face)([[f[u], f[v]]])[0]
+            out, _ = lut.interp(L, "lab", "pyramidal", x=x[None])
+            np.testing.assert_allclose(out[0], want, atol=1e-11)
+            # apex edge: f_u = f_v = 1 (the last cell along u and v), f_s in [0, 1)
+            j = g.integers(0, N - 1, 3)
+            j[u] = j[v] = N - 2
+            fs = g.uniform(0.0, 0.99)
+            x = np.empty(3)
+            x[s] = (j[s] + fs) / (N - 1)
+            x[u] = x[v] = 1.0
+            a = j.copy()
+            a[u] += 1
+            a[v] += 1
+            b = a.copy()
+            b[s] += 1
+            want = np.array([np.interp(fs, [0.0, 1.0], [L[tuple(a)][ch], L[tuple(b)][ch]]) for ch in range(3)])
+            out, _ = lut.interp(L, "lab", "pyramidal", x=x[None])
+            np.testing.assert_allclose(out[0], want, atol=1e-11)
+
+
 @pytest.mark.parametrize("method", ["trilinear", "prism", "tetrahedral"])
 def test_continuity_across_cell_faces(method):
     # the pyramidal polynomial form is not continuous (neither across cell faces nor across
