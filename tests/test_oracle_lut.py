@@ -205,6 +205,29 @@ def test_angular_channels_wrap_and_constant():
     assert np.angle(np.exp(1j * out[0, 0])) == pytest.approx(0.0, abs=1e-12)
 
 
+def test_angular_channel_on_a_cell_edge_is_the_two_vector_resultant():
+    # on the R edge of a cell (f_G = f_B = 0) every method weighs the edge's two nodes by
+    # 1 - f and f.  The resultant of the unit vectors at angles t1 and t2 with those weights,
+    # in a frame rotated by t1: angle t1 + atan2(f sin d, 1 - f + f cos d) with d = t2 - t1
+    # wrapped into (-pi, pi], length sqrt((1 - f)^2 + f^2 + 2 f (1 - f) cos d) (law of cosines)
+    N = 4
+    g = synth.rng(10)
+    L = np.zeros((N, N, N, 3))
+    L[..., 0] = g.uniform(0.0, 2 * np.pi, (N, N, N))
+    for m in METHODS:
+        for _ in range(200):
+            i, j, k = g.integers(0, N - 1, 3)
+            f = g.uniform(0.0, 1.0)
+            x = np.array([[(i + f) / (N - 1), j / (N - 1), k / (N - 1)]])
+            t1, t2 = L[i, j, k, 0], L[i + 1, j, k, 0]
+            d = np.angle(np.exp(1j * (t2 - t1)))
+            want = t1 + np.arctan2(f * np.sin(d), 1 - f + f * np.cos(d))
+            length = np.sqrt((1 - f) ** 2 + f ** 2 + 2 * f * (1 - f) * np.cos(d))
+            out, r = lut.interp(L, "hsi", m, x=x)
+            assert abs(np.angle(np.exp(1j * (out[0, 0] - want)))) < 1e-9, (m, i, j, k, f)
+            assert r[0, 0] == pytest.approx(length, abs=1e-12), (m, i, j, k, f)
+
+
 def test_pyramidal_form_is_discontinuous_at_pyramid_boundary():
     # documents the reading: with only c010 = 1, the R-pyramid form gives f (1 - f_B) on
     # the plane f_R = f_G while the G-pyramid form gives 0
