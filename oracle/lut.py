@@ -33,7 +33,8 @@ literature.  Readings used here:
     circular data (Sec. 3.5.3): the weighted sum of unit vectors
     (cos theta_k, sin theta_k) with the method's own weights, then the angle
     of the resultant.  PARITY UNPINNED against the paper (its grid is not
-    stated); held to invariants only.
+    stated); held to invariants and, on cell edges, to the closed-form
+    resultant of two weighted unit vectors.
 """
 import numpy as np
 
