@@ -168,6 +168,67 @@ __device__ __forceinline__ void store_plane_runs(g_f4* slice, uint32_t lane, con
   }
 }
 
+// A wave's 256 pixels (pixel lane + 64 j of o[j]) as one run of 768 values
+// starting at `run` (any element alignment), HWC order.  In the slice, value
+// k sits at sh + k (sh: the run's start in elements past a 16-byte, float16
+// 8-byte, boundary), so that the run's aligned 4-value groups are aligned in
+// LDS too: lanes store groups 0..191 whole (1..191 when sh != 0) with 16-byte
+// (8-byte) stores, then lane 0 the run's first 4 - sh and last sh values one
+// by one (store_plane_runs' scheme).
+template <int OUT>
+__device__ __forceinline__ void store_row_run(g_f4* slice, uint32_t lane, const float o[4][3], void* run) {
+  constexpr uintptr_t ES = OUT == MACT_F32 ? 4 : 2;
+  const uint32_t sh = (uint32_t)((reinterpret_cast<uintptr_t>(run) / ES) & 3u);
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // whatever the slice held before has been read
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const uint32_t i = sh + 3u * (lane + 64u * j) + ch;
+      if (OUT == MACT_F32) reinterpret_cast<float*>(slice)[i] = o[j][ch];
+      else reinterpret_cast<__half*>(slice)[i] = f2h_rn(o[j][ch]);
+    }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  if (OUT == MACT_F32) {
+    float* a0 = static_cast<float*>(run) - sh;
+    const float* sf = reinterpret_cast<const float*>(slice);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const uint32_t g = 64u * q + lane;
+      if (g != 0u || sh == 0u)
+        __builtin_nontemporal_store(*reinterpret_cast<const g_f4*>(sf + 4u * g), reinterpret_cast<g_f4*>(a0 + 4u * g));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (lane == 0 && sh != 0) {
+#pragma unroll
+      for (uint32_t t = 0; t < 4u; ++t) {
+        const uint32_t i = t >= sh ? t : 768u + t;
+        __builtin_nontemporal_store(sf[i], a0 + i);
+      }
+    }
+  } else {
+    __half* a0 = static_cast<__half*>(run) - sh;
+    const __half* sf = reinterpret_cast<const __half*>(slice);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const uint32_t g = 64u * q + lane;
+      if (g != 0u || sh == 0u)
+        __builtin_nontemporal_store(*reinterpret_cast<const g_f2*>(sf + 4u * g), reinterpret_cast<g_f2*>(a0 + 4u * g));
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (lane == 0 && sh != 0) {
+#pragma unroll
+      for (uint32_t t = 0; t < 4u; ++t) {
+        const uint32_t i = t >= sh ? t : 768u + t;
+        __builtin_nontemporal_store(reinterpret_cast<const uint16_t*>(sf)[i], reinterpret_cast<uint16_t*>(a0) + i);
+      }
+    }
+  }
+}
+
 // OM: kGatherHWC and kGatherCHW write packed output at `out`; kGatherAny writes
 // the output view `dst` (float32 or float16, any layout and strides).
 template <int IN, int OUT, int XF, int DEG, int OM>
@@ -239,39 +300,9 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
         constexpr int OES = OUT == MACT_F32 ? 4 : 2;
         void* ob = static_cast<char*>(dst.ptr) + (int64_t)n0 * dst.bs * OES;
         const uint32_t y0 = dst.packed ? 0u : dst.div_w.div(r0), x0 = r0 - y0 * dst.W;
-        if (OUT == MACT_F32 && dst.layout == MACT_HWC && !dst.packed && x0 + 256u <= dst.W) {
-          // the chunk inside one row of an HWC float32 view: its 768 values are one run starting
-          // sh floats past a 16-byte boundary.  In the slice, value k of the run sits at sh + k,
-          // so that the run's aligned 4-value groups are aligned in LDS too: lanes store groups
-          // 0..191 whole (1..191 when sh != 0) with 16-byte stores, then lane 0 the run's first
-          // 4 - sh and last sh values one by one (the CHW path's scheme).
-          float* run = static_cast<float*>(ob) + (int64_t)y0 * dst.rs + 3 * (int64_t)x0;
-          const uint32_t sh = (uint32_t)((reinterpret_cast<uintptr_t>(run) >> 2) & 3u);
-          float* sf = reinterpret_cast<float*>(s_out[wv]);
-          __builtin_amdgcn_s_waitcnt(0xc07f);  // a staged input chunk has been read out of the slice
-          __builtin_amdgcn_wave_barrier();
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) sf[sh + 3u * (lane + 64u * j) + ch] = o[j][ch];
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-          __builtin_amdgcn_wave_barrier();
-          float* a0 = run - sh;
-#pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            const uint32_t g = 64u * q + lane;
-            if (g != 0u || sh == 0u)
-              __builtin_nontemporal_store(*reinterpret_cast<const g_f4*>(sf + 4u * g), reinterpret_cast<g_f4*>(a0 + 4u * g));
-          }
-          __builtin_amdgcn_sched_barrier(0);
-          if (lane == 0 && sh != 0) {
-#pragma unroll
-            for (uint32_t t = 0; t < 4u; ++t) {
-              const uint32_t i = t >= sh ? t : 768u + t;
-              __builtin_nontemporal_store(sf[i], a0 + i);
-            }
-          }
+        if (dst.layout == MACT_HWC && !dst.packed && x0 + 256u <= dst.W) {
+          // the chunk inside one row of an HWC view: its 768 values are one run
+          store_row_run<OUT>(s_out[wv], lane, o, static_cast<char*>(ob) + ((int64_t)y0 * dst.rs + 3 * (int64_t)x0) * OES);
         } else if (dst.layout == MACT_CHW && (dst.packed || x0 + 256u <= dst.W)) {
           // the chunk inside one row of a CHW view (or a packed one): each plane's 256 outputs
           // are one run, stored as the packed CHW path stores them
