@@ -188,7 +188,7 @@ def bench_general(M, x, y, p, n_px, steps):
     kernels); row-strided CHW planes into HWC and a row-padded float32 view
     into HWC, float32 out; the packed batch into output views whose rows are
     8 pixels wider (HWC float32 and float16, CHW float32); and shapes no
-    4-pixel kernel takes, 32 x 1081 x 1921: odd CHW planes into CHW and HWC,
+    4-pixel kernel takes, 64 x 1081 x 1921: odd CHW planes into CHW and HWC,
     and HWC rows of that odd width (a row-padded view) into HWC."""
     import torch
     out = {}
@@ -240,12 +240,13 @@ def bench_general(M, x, y, p, n_px, steps):
     ms, _ = time_kernel(lambda: M.transform(x, params=p, out=bigc[..., :w], out_layout="chw"), steps)
     rec("u8_to_chw_out_view", ms, 15.0)
     del bigc, big
-    # odd shapes, 32 x 1081 x 1921 uniform bytes (their own pixel count)
-    on, oh, ow = 32, 1081, 1921
+    # odd shapes, 64 x 1081 x 1921 uniform bytes (their own pixel count; 64 images, so that the input,
+    # 399 MB, does not stay in the 256 MB Infinity Cache from one step to the next)
+    on, oh, ow = 64, 1081, 1921
     o_px = on * oh * ow
     g = torch.Generator(device="cuda").manual_seed(11)
     ochw = torch.randint(0, 256, (on, 3, oh, ow), dtype=torch.uint8, device="cuda", generator=g)
-    oy = y.view(-1)[: o_px * 3]
+    oy = torch.empty(o_px * 3, dtype=torch.float32, device="cuda")
     for name, fn in (("odd_chw_to_chw", lambda: M.transform(ochw, params=p, layout="chw", out=oy.view(on, 3, oh, ow),
                                                            out_layout="chw")),
                      ("odd_chw_to_hwc", lambda: M.transform(ochw, params=p, layout="chw", out=oy.view(on, oh, ow, 3),
@@ -256,7 +257,8 @@ def bench_general(M, x, y, p, n_px, steps):
     opad = torch.randint(0, 256, (on, oh, ow + 7, 3), dtype=torch.uint8, device="cuda", generator=g)
     ms, _ = time_kernel(lambda: M.transform(opad[:, :, :ow], params=p, out=oy.view(on, oh, ow, 3)), steps)
     out["odd_hwc_rows_view"] = {"Mpx_s": o_px / ms / 1e3, "GBs": 15.0 * o_px / ms / 1e6, "ms": ms, "shape": [on, oh, ow]}
-    del opad
+    del opad, oy
+    torch.cuda.empty_cache()
     return out
 
 
