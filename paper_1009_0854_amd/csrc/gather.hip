@@ -46,6 +46,27 @@ __device__ __forceinline__ void load_px_t(const KImage& im, uint32_t p, float v[
   }
 }
 
+// Stages `bytes` bytes starting at `src` (any alignment) in LDS at `dst`, one
+// dword per lane and step (MAXQ steps at most); returns sh, the byte at src + i
+// then sitting at byte sh + i of dst.  Only whole aligned dwords are loaded,
+// each holding at least one byte of the run; an aligned dword never straddles a
+// page, so no load leaves the pages the run lies in.
+template <int MAXQ>
+__device__ __forceinline__ uint32_t stage_run(const void* src, uint32_t bytes, uint32_t* dst, uint32_t lane) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(src);
+  const uint32_t sh = (uint32_t)(a & 3u);
+  const uint32_t* d = reinterpret_cast<const uint32_t*>(a - sh);
+  const uint32_t n = (sh + bytes + 3u) >> 2;
+  uint32_t w[MAXQ];
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q)
+    if (lane + 64u * q < n) w[q] = d[lane + 64u * q];
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q)
+    if (lane + 64u * q < n) dst[lane + 64u * q] = w[q];
+  return sh;
+}
+
 // Pixel r of one image whose first element is `base` (the image's place in
 // `im`), as load_px_t returns it.  A chunk inside one image takes its base
 // once, uniform over the wave, so a lane's address is its pixel's offset in
@@ -253,11 +274,11 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
     const bool one = div_hw.div(p0 + 255u) == n0;  // the chunk inside one image
     const uint32_t r0 = p0 - n0 * hw;              // its first pixel in that image
     float o[4][3];
+    constexpr int ES = IN == MACT_U8 ? 1 : IN == MACT_F32 ? 4 : 2;
     if (OM == kGatherAny && IN != MACT_F32 && src.packed && src.layout == MACT_HWC &&
         (reinterpret_cast<uintptr_t>(src.ptr) & 3u) == 0) {
-      // packed 8- or 16-bit HWC input: the chunk's 768 or 1536 bytes come in as 12-byte words,
-      // lane-contiguous, through the wave's slice (a lane's own pixel is 3 or 6 bytes, so its
-      // element loads would cover a third or half of each line they touch)
+      // packed 8- or 16-bit HWC input into an output view: the chunk's 768 or 1536 bytes come in
+      // as 12-byte words, lane-contiguous, through the wave's slice
       constexpr int WPC = IN == MACT_U8 ? 1 : 2;
       const uint3* w = reinterpret_cast<const uint3*>(src.ptr) + (size_t)c * 64u * WPC;
       uint3* s3 = reinterpret_cast<uint3*>(s_out[wv]);
@@ -278,21 +299,66 @@ __global__ __launch_bounds__(256) void k_gather(KImage src, void* __restrict__ o
         }
         px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
       }
-    } else if (one) {
-      constexpr int ES = IN == MACT_U8 ? 1 : IN == MACT_F32 ? 4 : 2;
-      const void* base = static_cast<const char*>(src.ptr) + (int64_t)n0 * src.bs * ES;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float v[3];
-        load_in_image<IN>(src, base, r0 + lane + 64u * j, v);
-        px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
-      }
     } else {
+      // 8- and 16-bit inputs whose chunk is one contiguous run (HWC: packed, or inside one row;
+      // CHW: each plane, packed or inside one row): the runs come in through the wave's slice as
+      // lane-contiguous dwords (element loads of 1 or 2 bytes would issue 3 loads a pixel)
+      uint32_t y0s = 0, x0s = r0;
+      if (IN != MACT_F32 && one && !src.packed) {
+        y0s = src.div_w.div(r0);
+        x0s = r0 - y0s * src.W;
+      }
+      // (16-bit inputs: element-aligned, so that the staged halfwords are aligned in LDS)
+      const bool runs = IN != MACT_F32 && one && (src.packed || x0s + 256u <= src.W) &&
+                        (IN == MACT_U8 || (reinterpret_cast<uintptr_t>(src.ptr) & 1u) == 0);
+      if (runs) {
+        const char* ib = static_cast<const char*>(src.ptr) + (int64_t)n0 * src.bs * ES;
+        const int64_t off = src.packed ? (int64_t)r0 : (int64_t)y0s * src.rs + (src.layout == MACT_HWC ? 3 : 1) * (int64_t)x0s;
+        uint32_t* sd = reinterpret_cast<uint32_t*>(s_out[wv]);
+        uint32_t sh[3];
+        constexpr uint32_t PLANE = (256u * ES + 4u) / 4u;  // dwords per staged plane run
+        if (src.layout == MACT_HWC) {
+          sh[0] = stage_run<IN == MACT_U8 ? 4 : 7>(ib + (src.packed ? 3 * off : off) * ES, 768u * ES, sd, lane);
+        } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        float v[3];
-        load_px_t<IN>(src, p0 + lane + 64u * j, v);
-        px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
+          for (int ch = 0; ch < 3; ++ch)
+            sh[ch] = stage_run<IN == MACT_U8 ? 2 : 3>(ib + (off + ch * src.ps) * ES, 256u * ES, sd + PLANE * ch, lane);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the runs are in LDS
+        __builtin_amdgcn_wave_barrier();
+        const uint8_t* sb = reinterpret_cast<const uint8_t*>(sd);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t px = lane + 64u * j;
+          float v[3];
+#pragma unroll
+          for (int ch = 0; ch < 3; ++ch) {
+            const uint32_t b = src.layout == MACT_HWC ? sh[0] + (3u * px + ch) * ES : 4u * PLANE * ch + sh[ch] + px * ES;
+            if (IN == MACT_U8) v[ch] = (float)sb[b];
+            else if (IN == MACT_U16) v[ch] = (float)*reinterpret_cast<const uint16_t*>(sb + b);
+            else v[ch] = clamp01(__half2float(*reinterpret_cast<const __half*>(sb + b)));
+          }
+          px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
+        }
+        // every lane has read its bytes before any output is staged in the slice
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+      } else if (one) {
+        const void* base = static_cast<const char*>(src.ptr) + (int64_t)n0 * src.bs * ES;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float v[3];
+          load_in_image<IN>(src, base, r0 + lane + 64u * j, v);
+          px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float v[3];
+          load_px_t<IN>(src, p0 + lane + 64u * j, v);
+          px1<IN, XF, DEG>(k, gamma, gtab, v, o[j]);
+        }
       }
     }
     if (OM == kGatherAny) {
