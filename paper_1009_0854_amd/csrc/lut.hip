@@ -253,33 +253,29 @@ __device__ __forceinline__ void lut_px_cache(const float* __restrict__ cache, ui
     add(edge_r(1, 1), rg * fb);
   } else if (METHOD == MACT_PRISM) {
     // linear along R; the (G, B) triangle chosen by f_G >= f_B, its two edges blended along R
+    // (the triangle's edges and weights are selected, not branched on, so that a wave whose pixels
+    // fall in both triangles issues each load once)
     const float r0 = 1.0f - fr;
+    const bool gb = fg >= fb;
+    const float wu = gb ? fg : fb, wv = gb ? fb : fg;
     add(edge_r(0, 0), fr);
-    if (fg >= fb) {
-      add(edge_g(0, 0), fg * r0);
-      add(edge_g(1, 0), fg * fr);
-      add(edge_b(0, 1), fb * r0);
-      add(edge_b(1, 1), fb * fr);
-    } else {
-      add(edge_b(0, 0), fb * r0);
-      add(edge_b(1, 0), fb * fr);
-      add(edge_g(0, 1), fg * r0);
-      add(edge_g(1, 1), fg * fr);
-    }
+    add(gb ? edge_g(0, 0) : edge_b(0, 0), wu * r0);
+    add(gb ? edge_g(1, 0) : edge_b(1, 0), wu * fr);
+    add(gb ? edge_b(0, 1) : edge_g(0, 1), wv * r0);
+    add(gb ? edge_b(1, 1) : edge_g(1, 1), wv * fr);
   } else if (METHOD == MACT_TETRAHEDRAL) {
     // the path from c000 along the axes in decreasing order of the fractions (ties R, G, B):
     // each step's edge sits where the earlier steps have moved to
-    int e1, e2, e3;
-    float w1, w2, w3;
-    if (fr >= fg) {
-      if (fg >= fb) { e1 = edge_r(0, 0); w1 = fr; e2 = edge_g(1, 0); w2 = fg; e3 = edge_b(1, 1); w3 = fb; }
-      else if (fr >= fb) { e1 = edge_r(0, 0); w1 = fr; e2 = edge_b(1, 0); w2 = fb; e3 = edge_g(1, 1); w3 = fg; }
-      else { e1 = edge_b(0, 0); w1 = fb; e2 = edge_r(0, 1); w2 = fr; e3 = edge_g(1, 1); w3 = fg; }
-    } else {
-      if (fr >= fb) { e1 = edge_g(0, 0); w1 = fg; e2 = edge_r(1, 0); w2 = fr; e3 = edge_b(1, 1); w3 = fb; }
-      else if (fg >= fb) { e1 = edge_g(0, 0); w1 = fg; e2 = edge_b(0, 1); w2 = fb; e3 = edge_r(1, 1); w3 = fr; }
-      else { e1 = edge_b(0, 0); w1 = fb; e2 = edge_g(0, 1); w2 = fg; e3 = edge_r(1, 1); w3 = fr; }
-    }
+    // (selected, not branched on: rg, gb, rb are the three comparisons; with R >= G the first axis
+    // is R unless B beats R, the last B unless G is the smallest; with G > R, mirrored)
+    const bool rg = fr >= fg, gb = fg >= fb, rb = fr >= fb;
+    const int e1 = rg ? (rb ? edge_r(0, 0) : edge_b(0, 0)) : (gb ? edge_g(0, 0) : edge_b(0, 0));
+    const float w1 = rg ? (rb ? fr : fb) : (gb ? fg : fb);
+    const int e2 = rg ? (gb ? edge_g(1, 0) : rb ? edge_b(1, 0) : edge_r(0, 1))
+                      : (rb ? edge_r(1, 0) : gb ? edge_b(0, 1) : edge_g(0, 1));
+    const float w2 = rg ? (gb ? fg : rb ? fb : fr) : (rb ? fr : gb ? fb : fg);
+    const int e3 = rg ? (gb ? edge_b(1, 1) : edge_g(1, 1)) : (rb ? edge_b(1, 1) : edge_r(1, 1));
+    const float w3 = rg ? (gb ? fb : fg) : (rb ? fb : fr);
     add(e1, w1);
     add(e2, w2);
     add(e3, w3);
@@ -287,15 +283,13 @@ __device__ __forceinline__ void lut_px_cache(const float* __restrict__ cache, ui
     // pyramidal: s the axis of the smallest fraction (ties R, G, B), u, v the other two in order:
     // c000 + f_s (s edge at u = v = 1) + f_u (1 - f_v) (u edge at s = v = 0) + f_v (v edge at
     // s = u = 0) + f_u f_v (u edge at s = 0, v = 1)
-    int es, eu0, ev, eu1;
-    float fs, fu, fv;
-    if (fr <= fg && fr <= fb) {
-      es = edge_r(1, 1); eu0 = edge_g(0, 0); ev = edge_b(0, 0); eu1 = edge_g(0, 1); fs = fr; fu = fg; fv = fb;
-    } else if (fg <= fb) {
-      es = edge_g(1, 1); eu0 = edge_r(0, 0); ev = edge_b(0, 0); eu1 = edge_r(0, 1); fs = fg; fu = fr; fv = fb;
-    } else {
-      es = edge_b(1, 1); eu0 = edge_r(0, 0); ev = edge_g(0, 0); eu1 = edge_r(1, 0); fs = fb; fu = fr; fv = fg;
-    }
+    // (selected, not branched on)
+    const bool sr = fr <= fg && fr <= fb, sg = !sr && fg <= fb;
+    const int es = sr ? edge_r(1, 1) : sg ? edge_g(1, 1) : edge_b(1, 1);
+    const int eu0 = sr ? edge_g(0, 0) : edge_r(0, 0);
+    const int ev = sr || sg ? edge_b(0, 0) : edge_g(0, 0);
+    const int eu1 = sr ? edge_g(0, 1) : sg ? edge_r(0, 1) : edge_r(1, 0);
+    const float fs = sr ? fr : sg ? fg : fb, fu = sr ? fg : fr, fv = sr || sg ? fb : fg;
     const float uv = fu * fv;
     add(es, fs);
     add(eu0, fu - uv);
