@@ -396,6 +396,10 @@ __device__ __forceinline__ float swap1(float v) {
 // sort through 256 counters in `bins`).  The vector L1 looks up the lines of
 // each group of 4 neighbouring lanes: lanes on pixels of one cell share them,
 // and neighbouring pixels of a noisy image often sit in different cells.
+// CELLB (the caching records, 156 to 260 bytes each, so that neighbouring B
+// cells share no line): B cell mod 4 in place of B cell / 8, grouping the
+// pixels of one cell.
+template <bool CELLB = false>
 __device__ __forceinline__ void chunk_order(const uint8_t* s8, uint32_t N, uint32_t lane, uint32_t* bins,
                                             uint8_t* ord) {
 #pragma unroll
@@ -409,7 +413,7 @@ __device__ __forceinline__ void chunk_order(const uint8_t* s8, uint32_t N, uint3
     const uint32_t P = lane + 64u * j;
     const uint32_t i0 = min(s8[3 * P] * (N - 1) / 255u, N - 2), i1 = min(s8[3 * P + 1] * (N - 1) / 255u, N - 2),
                    i2 = min(s8[3 * P + 2] * (N - 1) / 255u, N - 2);
-    key[j] = ((i0 & 7u) << 5) | ((i1 & 7u) << 2) | ((i2 >> 3) & 3u);
+    key[j] = ((i0 & 7u) << 5) | ((i1 & 7u) << 2) | (CELLB ? (i2 & 3u) : ((i2 >> 3) & 3u));
     rank[j] = atomicAdd(&bins[key[j]], 1u);
   }
   __builtin_amdgcn_s_waitcnt(0xc07f);
@@ -687,7 +691,7 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
       constexpr bool SORT = !(FORM == kCells && (METHOD == MACT_PRISM || METHOD == MACT_PYRAMIDAL));
       uint32_t* bins = reinterpret_cast<uint32_t*>(tbuf + nw * 192) + wv * 320;
       uint8_t* ord = reinterpret_cast<uint8_t*>(bins + 256);
-      if (SORT) chunk_order(s8, N, lane, bins, ord);
+      if (SORT) chunk_order<FORM == kCache>(s8, N, lane, bins, ord);
       // two lanes per pixel: trilinear on the packed and cell-major grids; the other methods on
       // cell-major grids of more than 256 KB (17^3 and up: +2 to +38%; on 9^3, 64 KB, pyramidal
       // lost 19% and the others nothing)
