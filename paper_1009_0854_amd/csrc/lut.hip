@@ -733,8 +733,11 @@ __global__ __launch_bounds__(1024) void k_lut4(const f4* __restrict__ lut, uint3
           sf[3 * p + 1] = o[1];
           sf[3 * p + 2] = o[2];
           // one pixel's gathers in flight at a time: hoisting the next pixels' gathers costs
-          // occupancy and measured slower (the caching form's trilinear, 33^3: 59-92 vs 102 Gpx/s)
-          __builtin_amdgcn_sched_barrier(0);
+          // occupancy and measured slower (the caching form's trilinear, 33^3: 59-92 vs 102 Gpx/s).
+          // The caching form's tetrahedral, 4 entries a pixel, takes two pixels at a time, except
+          // for SCT's 20-byte entries (CIELAB 33^3 104 -> 109 Gpx/s, HSI 17^3 166 -> 181; SCT -3%)
+          constexpr bool kTwo = FORM == kCache && METHOD == MACT_TETRAHEDRAL && XF != MACT_SCT;
+          if (!kTwo || (j & 1)) __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
